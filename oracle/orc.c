@@ -1,0 +1,738 @@
+/*
+ * orc.c -- plain, slow, FP64 CPU oracle for the adaptive multi-NeRF rendering path.
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark load this library.  It shares no code, header, table or helper with
+ * the HIP library; both consume the same seeded float32 inputs.
+ *
+ * What it computes, and where the paper defines it:
+ *   - quantised guidance grid and density-median KD tree .......... Section 3.4
+ *     (BuildKDTree: sort, median of the cumulative density, split, recurse);
+ *     the distillation-based TestLeaf is replaced by max_leaves / max_depth.
+ *   - ray / KD-tree traversal producing leaf intervals ........... Section 3.5, Algorithm 1
+ *     (Traverse), taken near-side first so intervals come out front to back.
+ *   - equal sample count per leaf interval ........................ Section 3.5, Algorithm 1
+ *     (Sampling) and the figure on normalised intervals.
+ *   - per-leaf MLP F_theta_i(x, d) -> (c, sigma) .................. Section 3.1, with
+ *     frequency positional encoding (Section 3.2 figure caption).
+ *   - front-to-back volume rendering with early ray termination ... Section 3.1 (defers to
+ *     the NeRF quadrature), Section 4.1 (early termination).
+ *   - analytic gradient of that quadrature and of the MLPs, and Adam (training step;
+ *     not in the paper, so it follows the standard definitions).
+ *
+ * Everything is double precision; float inputs are promoted exactly.  No blocking,
+ * sorting, batching or fusion: every ray is processed on its own, sample by sample.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NODE_COLS 12
+#define IN_DIM 30
+#define OUT_DIM 4
+#define MAX_HIDDEN 256
+#define MAX_LAYERS 16
+
+/* ------------------------------------------------------------------------- */
+/* Guidance grid quantisation                                                 */
+/* ------------------------------------------------------------------------- */
+/* q = floor(g / g_max * 2^24 + 1/2); negative densities count as 0.  Integer masses make
+ * the median splits exact, so any two implementations build the same tree. */
+static void quantise(const float* g, int64_t ncell, uint32_t* q) {
+  double gmax = 0.0;
+  for (int64_t i = 0; i < ncell; ++i)
+    if ((double)g[i] > gmax) gmax = (double)g[i];
+  for (int64_t i = 0; i < ncell; ++i) {
+    double v = (double)g[i];
+    if (!(gmax > 0.0) || !(v > 0.0)) { q[i] = 0u; continue; }
+    q[i] = (uint32_t)floor(ldexp(v / gmax, 24) + 0.5);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* KD tree construction (Section 3.4)                                         */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int lo[3], hi[3];
+  uint32_t code;      /* binary node code: root 1, left child 2c, right child 2c+1 */
+  int depth;
+  int axis, plane;    /* split (inner nodes); plane is a cell index */
+  int child[2];
+  int slot;           /* leaf rank in left-first depth-first order */
+  uint64_t mass;
+  int leaf;
+} onode;
+
+static uint64_t mass_of_slab(const uint32_t* q, int n, const int lo[3], const int hi[3],
+                             int axis, int c) {
+  int a0 = lo[0], a1 = hi[0], b0 = lo[1], b1 = hi[1], e0 = lo[2], e1 = hi[2];
+  if (axis == 0) { a0 = c; a1 = c + 1; }
+  if (axis == 1) { b0 = c; b1 = c + 1; }
+  if (axis == 2) { e0 = c; e1 = c + 1; }
+  uint64_t s = 0;
+  for (int k = e0; k < e1; ++k)
+    for (int j = b0; j < b1; ++j)
+      for (int i = a0; i < a1; ++i) s += q[(int64_t)i + (int64_t)n * ((int64_t)j + (int64_t)n * k)];
+  return s;
+}
+
+static int longest_axis(const onode* nd) {
+  int a = 0;
+  for (int ax = 1; ax < 3; ++ax)
+    if (nd->hi[ax] - nd->lo[ax] > nd->hi[a] - nd->lo[a]) a = ax;
+  return a;
+}
+
+static int splittable(const onode* nd, int max_depth) {
+  int a = longest_axis(nd);
+  return nd->depth < max_depth && nd->hi[a] - nd->lo[a] >= 2;
+}
+
+static int slot_counter;
+static void assign_slots(onode* nodes, int i) {
+  if (nodes[i].leaf) { nodes[i].slot = slot_counter++; return; }
+  assign_slots(nodes, nodes[i].child[0]);
+  assign_slots(nodes, nodes[i].child[1]);
+}
+
+static const onode* sort_base;
+static int cmp_code(const void* a, const void* b) {
+  uint32_t ca = sort_base[*(const int*)a].code, cb = sort_base[*(const int*)b].code;
+  return ca < cb ? -1 : (ca > cb ? 1 : 0);
+}
+
+/* Builds the tree and exports it as rows of 12 int32, sorted by node code:
+ *   code, depth, lo[3], hi[3], axis (-1 leaf), plane (-1 leaf), slot (-1 inner), 0
+ * plus the integer mass of each node.  Returns 0, or -1 on bad arguments / capacity. */
+int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int cap,
+                   int32_t* rows, uint64_t* mass_out, int* n_nodes_out, int* n_leaves_out) {
+  if (!grid || n < 1 || max_depth < 0 || max_depth > 30 || max_leaves < 1 || !rows) return -1;
+  int64_t ncell = (int64_t)n * n * n;
+  uint32_t* q = (uint32_t*)malloc(sizeof(uint32_t) * ncell);
+  if (!q) return -1;
+  quantise(grid, ncell, q);
+  int maxn = 2 * max_leaves;
+  onode* nodes = (onode*)calloc(maxn, sizeof(onode));
+  uint64_t* slab = (uint64_t*)malloc(sizeof(uint64_t) * n);
+  int nn = 1, nleaves = 1;
+  onode* r = &nodes[0];
+  for (int a = 0; a < 3; ++a) { r->lo[a] = 0; r->hi[a] = n; }
+  r->code = 1; r->depth = 0; r->leaf = 1; r->axis = -1; r->plane = -1;
+  r->child[0] = r->child[1] = -1;
+  r->mass = 0;
+  for (int64_t i = 0; i < ncell; ++i) r->mass += q[i];
+
+  while (nleaves < max_leaves) {
+    /* best-first: the splittable leaf of largest mass, ties to the smallest code */
+    int best = -1;
+    for (int i = 0; i < nn; ++i) {
+      if (!nodes[i].leaf || !splittable(&nodes[i], max_depth)) continue;
+      if (best < 0 || nodes[i].mass > nodes[best].mass ||
+          (nodes[i].mass == nodes[best].mass && nodes[i].code < nodes[best].code))
+        best = i;
+    }
+    if (best < 0) break;
+    onode* p = &nodes[best];
+    int a = longest_axis(p);
+    int lo = p->lo[a], hi = p->hi[a];
+    for (int c = lo; c < hi; ++c) slab[c - lo] = mass_of_slab(q, n, p->lo, p->hi, a, c);
+    int plane;
+    if (p->mass == 0) {
+      plane = (lo + hi) / 2;
+    } else {
+      /* weighted median: smallest plane whose lower side holds at least half the mass */
+      plane = hi - 1;
+      uint64_t acc = 0;
+      for (int c = lo + 1; c <= hi - 1; ++c) {
+        acc += slab[c - 1 - lo];
+        if (2 * acc >= p->mass) { plane = c; break; }
+      }
+    }
+    uint64_t left_mass = 0;
+    for (int c = lo; c < plane; ++c) left_mass += slab[c - lo];
+    for (int side = 0; side < 2; ++side) {
+      onode* ch = &nodes[nn];
+      *ch = *p;
+      ch->code = 2u * p->code + (uint32_t)side;
+      ch->depth = p->depth + 1;
+      ch->leaf = 1; ch->axis = -1; ch->plane = -1; ch->child[0] = ch->child[1] = -1;
+      if (side == 0) { ch->hi[a] = plane; ch->mass = left_mass; }
+      else { ch->lo[a] = plane; ch->mass = p->mass - left_mass; }
+      p->child[side] = nn;
+      ++nn;
+    }
+    p->leaf = 0; p->axis = a; p->plane = plane;
+    ++nleaves;
+  }
+  free(slab);
+  free(q);
+  if (nn > cap) { free(nodes); return -1; }
+  slot_counter = 0;
+  for (int i = 0; i < nn; ++i) nodes[i].slot = -1;
+  assign_slots(nodes, 0);
+  int* order = (int*)malloc(sizeof(int) * nn);
+  for (int i = 0; i < nn; ++i) order[i] = i;
+  sort_base = nodes;
+  qsort(order, nn, sizeof(int), cmp_code);
+  for (int k = 0; k < nn; ++k) {
+    const onode* nd = &nodes[order[k]];
+    int32_t* row = rows + (int64_t)k * NODE_COLS;
+    row[0] = (int32_t)nd->code; row[1] = nd->depth;
+    for (int a = 0; a < 3; ++a) { row[2 + a] = nd->lo[a]; row[5 + a] = nd->hi[a]; }
+    row[8] = nd->leaf ? -1 : nd->axis;
+    row[9] = nd->leaf ? -1 : nd->plane;
+    row[10] = nd->leaf ? nd->slot : -1;
+    row[11] = 0;
+    if (mass_out) mass_out[k] = nd->mass;
+  }
+  free(order);
+  free(nodes);
+  *n_nodes_out = nn;
+  *n_leaves_out = nleaves;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Tree view over an exported node table                                      */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int nn, n_leaves, grid_n;
+  const int32_t* rows;
+  int* left;
+  int* right;
+  int root;
+} otree;
+
+static int find_code(const int32_t* rows, int nn, uint32_t code) {
+  int lo = 0, hi = nn - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) / 2;
+    uint32_t c = (uint32_t)rows[(int64_t)mid * NODE_COLS];
+    if (c == code) return mid;
+    if (c < code) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+static int otree_init(otree* T, const int32_t* rows, int nn, int grid_n) {
+  T->nn = nn; T->rows = rows; T->grid_n = grid_n; T->n_leaves = 0;
+  T->left = (int*)malloc(sizeof(int) * nn);
+  T->right = (int*)malloc(sizeof(int) * nn);
+  T->root = find_code(rows, nn, 1u);
+  if (T->root < 0) return -1;
+  for (int i = 0; i < nn; ++i) {
+    const int32_t* r = rows + (int64_t)i * NODE_COLS;
+    if (r[8] < 0) { T->left[i] = T->right[i] = -1; T->n_leaves++; continue; }
+    T->left[i] = find_code(rows, nn, 2u * (uint32_t)r[0]);
+    T->right[i] = find_code(rows, nn, 2u * (uint32_t)r[0] + 1u);
+    if (T->left[i] < 0 || T->right[i] < 0) return -1;
+  }
+  return 0;
+}
+
+static void otree_free(otree* T) { free(T->left); free(T->right); }
+
+/* ------------------------------------------------------------------------- */
+/* Traversal (Algorithm 1, Traverse)                                          */
+/* ------------------------------------------------------------------------- */
+typedef struct { double t0, t1; int slot; } oiv;
+
+typedef struct { oiv* iv; int m, cap; } ivlist;
+
+static void descend(const otree* T, int node, const double o[3], const double d[3],
+                    double t0, double t1, ivlist* L) {
+  const int32_t* r = T->rows + (int64_t)node * NODE_COLS;
+  if (r[8] < 0) {
+    if (t1 > t0 && L->m < L->cap) { L->iv[L->m].t0 = t0; L->iv[L->m].t1 = t1; L->iv[L->m].slot = r[10]; }
+    if (t1 > t0) L->m++;
+    return;
+  }
+  int a = r[8];
+  double s = (double)r[9] / (double)T->grid_n;
+  if (d[a] == 0.0) {
+    /* parallel to the plane: the whole segment lies on o's side (a point on the plane
+       belongs to the upper cell, matching half-open cells [lo, hi)) */
+    descend(T, o[a] >= s ? T->right[node] : T->left[node], o, d, t0, t1, L);
+    return;
+  }
+  double ts = (s - o[a]) / d[a];
+  int before = d[a] > 0.0 ? T->left[node] : T->right[node];
+  int after = d[a] > 0.0 ? T->right[node] : T->left[node];
+  if (ts >= t1) descend(T, before, o, d, t0, t1, L);
+  else if (ts <= t0) descend(T, after, o, d, t0, t1, L);
+  else { descend(T, before, o, d, t0, ts, L); descend(T, after, o, d, ts, t1, L); }
+}
+
+/* Root box [0,1]^3 slab test, then front-to-back descent; returns the interval count. */
+static int trace_ray(const otree* T, const double o[3], const double d[3], ivlist* L) {
+  L->m = 0;
+  double tin = 0.0, tout = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] == 0.0) {
+      if (o[a] < 0.0 || o[a] > 1.0) return 0;
+      continue;
+    }
+    double ta = (0.0 - o[a]) / d[a], tb = (1.0 - o[a]) / d[a];
+    if (ta > tb) { double t = ta; ta = tb; tb = t; }
+    if (ta > tin) tin = ta;
+    if (tb < tout) tout = tb;
+  }
+  if (!(tin < tout)) return 0;
+  descend(T, T->root, o, d, tin, tout, L);
+  return L->m;
+}
+
+static void load_ray(const float* o, const float* d, int64_t R, int64_t r, double oo[3], double dd[3]) {
+  for (int a = 0; a < 3; ++a) { oo[a] = (double)o[a * R + r]; dd[a] = (double)d[a * R + r]; }
+}
+
+int orc_trace_rays(const int32_t* rows, int nn, int grid_n, const float* o, const float* d,
+                   int64_t R, const int64_t* ray_idx, int64_t n_sel, int cap,
+                   double* t0, double* t1, int32_t* slot, int32_t* m_out) {
+  otree T;
+  if (otree_init(&T, rows, nn, grid_n)) { otree_free(&T); return -1; }
+  oiv* buf = (oiv*)malloc(sizeof(oiv) * (T.n_leaves + 1));
+  for (int64_t s = 0; s < n_sel; ++s) {
+    int64_t r = ray_idx ? ray_idx[s] : s;
+    double oo[3], dd[3];
+    load_ray(o, d, R, r, oo, dd);
+    ivlist L = {buf, 0, T.n_leaves + 1};
+    int m = trace_ray(&T, oo, dd, &L);
+    m_out[s] = m;
+    for (int k = 0; k < m && k < cap; ++k) {
+      t0[s * cap + k] = buf[k].t0; t1[s * cap + k] = buf[k].t1; slot[s * cap + k] = buf[k].slot;
+    }
+  }
+  free(buf);
+  otree_free(&T);
+  return 0;
+}
+
+/* A ray is robust when every interval is at least min_len long and its leaf sequence is
+   unchanged when o moves by +-eps along each axis.  Node ids are compared only there. */
+int orc_robust(const int32_t* rows, int nn, int grid_n, const float* o, const float* d,
+               int64_t R, const int64_t* ray_idx, int64_t n_sel, double min_len, double eps,
+               int32_t* robust) {
+  otree T;
+  if (otree_init(&T, rows, nn, grid_n)) { otree_free(&T); return -1; }
+  int cap = T.n_leaves + 1;
+  oiv* a = (oiv*)malloc(sizeof(oiv) * cap);
+  oiv* b = (oiv*)malloc(sizeof(oiv) * cap);
+  for (int64_t s = 0; s < n_sel; ++s) {
+    int64_t r = ray_idx ? ray_idx[s] : s;
+    double oo[3], dd[3];
+    load_ray(o, d, R, r, oo, dd);
+    ivlist La = {a, 0, cap};
+    int m = trace_ray(&T, oo, dd, &La);
+    int ok = 1;
+    for (int k = 0; k < m; ++k) if (a[k].t1 - a[k].t0 < min_len) ok = 0;
+    for (int ax = 0; ax < 3 && ok; ++ax)
+      for (int sg = -1; sg <= 1 && ok; sg += 2) {
+        double op[3] = {oo[0], oo[1], oo[2]};
+        op[ax] += sg * eps;
+        ivlist Lb = {b, 0, cap};
+        int mb = trace_ray(&T, op, dd, &Lb);
+        if (mb != m) { ok = 0; break; }
+        for (int k = 0; k < m; ++k) if (a[k].slot != b[k].slot) ok = 0;
+      }
+    robust[s] = ok;
+  }
+  free(a); free(b);
+  otree_free(&T);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sampling (Algorithm 1, Sampling)                                           */
+/* ------------------------------------------------------------------------- */
+/* splitmix64 (Steele, Lea, Flood 2014; constants as published by Vigna). */
+static uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* Offset u in [0,1) of the stratified samples of interval k of ray r: 1/2 (the centred
+   one-dimensional lattice) unless jittered, then a counter-based hash of (seed, r, k). */
+static double stratum_offset(int jitter, uint64_t seed, int64_t r, int k) {
+  if (!jitter) return 0.5;
+  uint64_t h = splitmix64(seed ^ ((uint64_t)r * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)k * 0xD1B54A32D192ED03ull));
+  return (double)(h >> 40) * (1.0 / 16777216.0);
+}
+
+/* Equal count per interval: n = max(1, floor(S_max/m)); when m > S_max only the first
+   S_max intervals receive one sample each. */
+static int samples_per_interval(int m, int s_max) { return m <= s_max ? s_max / m : 1; }
+
+typedef struct { int slot; double t, delta; } osample;
+
+static int make_samples(const oiv* iv, int m, int s_max, int jitter, uint64_t seed, int64_t r,
+                        osample* out) {
+  if (m == 0) return 0;
+  int n = samples_per_interval(m, s_max);
+  int meff = m <= s_max ? m : s_max;
+  int c = 0;
+  for (int k = 0; k < meff; ++k) {
+    double len = iv[k].t1 - iv[k].t0;
+    double u = stratum_offset(jitter, seed, r, k);
+    for (int j = 0; j < n; ++j) {
+      out[c].slot = iv[k].slot;
+      out[c].t = iv[k].t0 + ((double)j + u) / (double)n * len;
+      out[c].delta = len / (double)n;
+      ++c;
+    }
+  }
+  return c;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Per-leaf MLP (Section 3.1)                                                 */
+/* ------------------------------------------------------------------------- */
+typedef struct { int n_lin; int din[MAX_LAYERS], dout[MAX_LAYERS]; int off_w[MAX_LAYERS], off_b[MAX_LAYERS]; int P; } olayout;
+
+static int make_layout(int n_hidden, int hidden, olayout* L) {
+  if (n_hidden < 1 || n_hidden + 1 > MAX_LAYERS || hidden < 1 || hidden > MAX_HIDDEN) return -1;
+  L->n_lin = n_hidden + 1;
+  int off = 0;
+  for (int l = 0; l < L->n_lin; ++l) {
+    L->din[l] = l == 0 ? IN_DIM : hidden;
+    L->dout[l] = l == L->n_lin - 1 ? OUT_DIM : hidden;
+    L->off_w[l] = off; off += L->din[l] * L->dout[l];
+    L->off_b[l] = off; off += L->dout[l];
+  }
+  L->P = off;
+  return 0;
+}
+
+/* gamma(p) for p = 2x - 1: [p, sin(2^k pi p), cos(2^k pi p) for k = 0..3], then d. */
+static void features(const double x[3], const double dir[3], double u[IN_DIM]) {
+  double p[3];
+  for (int a = 0; a < 3; ++a) p[a] = 2.0 * x[a] - 1.0;
+  for (int a = 0; a < 3; ++a) u[a] = p[a];
+  for (int k = 0; k < 4; ++k) {
+    double f = ldexp(M_PI, k);
+    for (int a = 0; a < 3; ++a) {
+      u[3 + 6 * k + a] = sin(f * p[a]);
+      u[3 + 6 * k + 3 + a] = cos(f * p[a]);
+    }
+  }
+  for (int a = 0; a < 3; ++a) u[27 + a] = dir[a];
+}
+
+static double softplus(double z) { return (z > 0 ? z : 0.0) + log1p(exp(-fabs(z))); }
+static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
+
+/* Forward of one leaf MLP.  acts (optional) receives the input features followed by the
+   pre-activation of every layer (widths din[0], dout[0], ..., dout[last]). */
+static void mlp_forward(const olayout* L, const double* P, const double u[IN_DIM], double out[OUT_DIM],
+                        double* acts) {
+  double a[MAX_HIDDEN], z[MAX_HIDDEN];
+  int w = IN_DIM;
+  for (int i = 0; i < IN_DIM; ++i) a[i] = u[i];
+  double* rec = acts;
+  if (rec) { memcpy(rec, u, sizeof(double) * IN_DIM); rec += IN_DIM; }
+  for (int l = 0; l < L->n_lin; ++l) {
+    const double* W = P + L->off_w[l];
+    const double* b = P + L->off_b[l];
+    for (int o = 0; o < L->dout[l]; ++o) {
+      double s = b[o];
+      for (int i = 0; i < w; ++i) s += W[o * w + i] * a[i];
+      z[o] = s;
+    }
+    if (rec) { memcpy(rec, z, sizeof(double) * L->dout[l]); rec += L->dout[l]; }
+    w = L->dout[l];
+    if (l < L->n_lin - 1) for (int o = 0; o < w; ++o) a[o] = z[o] > 0.0 ? z[o] : 0.0;
+  }
+  out[0] = softplus(z[0]);
+  for (int c = 1; c < OUT_DIM; ++c) out[c] = sigmoid(z[c]);
+}
+
+int orc_mlp_eval(const float* params_leaf, int n_hidden, int hidden, const double* x,
+                 const double* dir, int64_t n, double* out, double* feat) {
+  olayout L;
+  if (make_layout(n_hidden, hidden, &L)) return -1;
+  double* P = (double*)malloc(sizeof(double) * L.P);
+  for (int i = 0; i < L.P; ++i) P[i] = (double)params_leaf[i];
+  for (int64_t s = 0; s < n; ++s) {
+    double u[IN_DIM];
+    features(x + 3 * s, dir + 3 * s, u);
+    if (feat) memcpy(feat + IN_DIM * s, u, sizeof(u));
+    mlp_forward(&L, P, u, out + OUT_DIM * s, NULL);
+  }
+  free(P);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Volume rendering (Section 3.1 -> NeRF quadrature) with early termination   */
+/* ------------------------------------------------------------------------- */
+#define FLAG_ERT_AMBIGUOUS 1
+#define FLAG_ERT_FIRED 2
+#define FLAG_CLIPPED 4
+
+typedef struct {
+  const otree* T;
+  const olayout* L;
+  const double* P;      /* [n_leaves][P] */
+  const float *o, *d;
+  int64_t R;
+  int s_max;
+  double eps;
+  int jitter;
+  uint64_t seed;
+} octx;
+
+/* Per-ray result plus optional per-sample record. */
+typedef struct {
+  double rgb[3], depth, opac;
+  int n_samples, n_used, flags, m;
+} oray;
+
+static void render_ray(const octx* C, int64_t r, oiv* ivbuf, osample* sbuf, oray* res,
+                       double* s_sigma, double* s_rgb, double* s_w) {
+  double oo[3], dd[3];
+  load_ray(C->o, C->d, C->R, r, oo, dd);
+  ivlist L = {ivbuf, 0, C->T->n_leaves + 1};
+  int m = trace_ray(C->T, oo, dd, &L);
+  int ns = make_samples(ivbuf, m, C->s_max, C->jitter, C->seed, r, sbuf);
+  memset(res, 0, sizeof(*res));
+  res->m = m;
+  res->n_samples = ns;
+  if (m > C->s_max) res->flags |= FLAG_CLIPPED;
+  double S = 0.0;
+  int used = 0;
+  for (int j = 0; j < ns; ++j) {
+    double x[3];
+    for (int a = 0; a < 3; ++a) x[a] = oo[a] + sbuf[j].t * dd[a];
+    double u[IN_DIM], out[OUT_DIM];
+    features(x, dd, u);
+    mlp_forward(C->L, C->P + (int64_t)sbuf[j].slot * C->L->P, u, out, NULL);
+    double tau = out[0] * sbuf[j].delta;
+    double T = exp(-S);
+    double alpha = -expm1(-tau);
+    double w = T * alpha;
+    for (int c = 0; c < 3; ++c) res->rgb[c] += w * out[1 + c];
+    res->depth += w * sbuf[j].t;
+    res->opac += w;
+    if (s_sigma) s_sigma[j] = out[0];
+    if (s_rgb) for (int c = 0; c < 3; ++c) s_rgb[3 * j + c] = out[1 + c];
+    if (s_w) s_w[j] = w;
+    S += tau;
+    used = j + 1;
+    if (C->eps > 0.0) {
+      double Tn = exp(-S);
+      if (fabs(Tn - C->eps) <= 1e-4 * C->eps) res->flags |= FLAG_ERT_AMBIGUOUS;
+      if (Tn < C->eps) { res->flags |= FLAG_ERT_FIRED; break; }
+    }
+  }
+  if (s_w) for (int j = used; j < ns; ++j) s_w[j] = 0.0;
+  res->n_used = used;
+}
+
+static int make_ctx(octx* C, otree* T, olayout* L, double** P, const int32_t* rows, int nn, int grid_n,
+                    const float* params, int n_leaves, int n_hidden, int hidden) {
+  if (otree_init(T, rows, nn, grid_n)) return -1;
+  if (make_layout(n_hidden, hidden, L)) return -1;
+  if (T->n_leaves != n_leaves) return -1;
+  *P = (double*)malloc(sizeof(double) * (int64_t)n_leaves * L->P);
+  for (int64_t i = 0; i < (int64_t)n_leaves * L->P; ++i) (*P)[i] = (double)params[i];
+  C->T = T; C->L = L; C->P = *P;
+  return 0;
+}
+
+/* Renders the selected rays (all rays when ray_idx is NULL). */
+int orc_render(const int32_t* rows, int nn, int grid_n, const float* params, int n_leaves,
+               int n_hidden, int hidden, const float* o, const float* d, int64_t R,
+               const int64_t* ray_idx, int64_t n_sel, int s_max, double eps, int jitter,
+               uint64_t seed, double* rgb, double* depth, double* opac, int32_t* n_samples,
+               int32_t* flags, int n_threads) {
+  if (s_max < 1) return -1;
+  otree T; olayout L; double* P = NULL; octx C;
+  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden)) {
+    free(P); otree_free(&T); return -1;
+  }
+  C.o = o; C.d = d; C.R = R; C.s_max = s_max; C.eps = eps; C.jitter = jitter; C.seed = seed;
+  int cap_iv = T.n_leaves + 1;
+#pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
+  {
+    oiv* ivbuf = (oiv*)malloc(sizeof(oiv) * cap_iv);
+    osample* sbuf = (osample*)malloc(sizeof(osample) * (s_max + 1));
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t s = 0; s < n_sel; ++s) {
+      int64_t r = ray_idx ? ray_idx[s] : s;
+      oray res;
+      render_ray(&C, r, ivbuf, sbuf, &res, NULL, NULL, NULL);
+      for (int c = 0; c < 3; ++c) rgb[3 * s + c] = res.rgb[c];
+      depth[s] = res.depth;
+      opac[s] = res.opac;
+      if (n_samples) n_samples[s] = res.n_samples;
+      if (flags) flags[s] = res.flags;
+    }
+    free(ivbuf);
+    free(sbuf);
+  }
+  free(P);
+  otree_free(&T);
+  return 0;
+}
+
+/* Per-sample record of one ray, front to back: leaf slot, t, delta, sigma, rgb, weight.
+   Returns the number of samples (<= cap) or -1. */
+int orc_ray_samples(const int32_t* rows, int nn, int grid_n, const float* params, int n_leaves,
+                    int n_hidden, int hidden, const float* o, const float* d, int64_t R,
+                    int64_t r, int s_max, double eps, int jitter, uint64_t seed, int cap,
+                    int32_t* slot, double* t, double* delta, double* sigma, double* rgb3,
+                    double* w, double* ray_out /* rgb3, depth, opac, flags, n_used */) {
+  otree T; olayout L; double* P = NULL; octx C;
+  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden)) {
+    free(P); otree_free(&T); return -1;
+  }
+  C.o = o; C.d = d; C.R = R; C.s_max = s_max; C.eps = eps; C.jitter = jitter; C.seed = seed;
+  oiv* ivbuf = (oiv*)malloc(sizeof(oiv) * (T.n_leaves + 1));
+  osample* sbuf = (osample*)malloc(sizeof(osample) * (s_max + 1));
+  double* sg = (double*)malloc(sizeof(double) * (s_max + 1));
+  double* sc = (double*)malloc(sizeof(double) * 3 * (s_max + 1));
+  double* sw = (double*)malloc(sizeof(double) * (s_max + 1));
+  oray res;
+  render_ray(&C, r, ivbuf, sbuf, &res, sg, sc, sw);
+  int ns = res.n_samples;
+  if (ns > cap) ns = -1;
+  for (int j = 0; j < ns; ++j) {
+    slot[j] = sbuf[j].slot; t[j] = sbuf[j].t; delta[j] = sbuf[j].delta;
+    sigma[j] = sg[j]; w[j] = sw[j];
+    for (int c = 0; c < 3; ++c) rgb3[3 * j + c] = sc[3 * j + c];
+  }
+  if (ray_out) {
+    for (int c = 0; c < 3; ++c) ray_out[c] = res.rgb[c];
+    ray_out[3] = res.depth; ray_out[4] = res.opac; ray_out[5] = res.flags; ray_out[6] = res.n_used;
+  }
+  free(ivbuf); free(sbuf); free(sg); free(sc); free(sw); free(P);
+  otree_free(&T);
+  return ns;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Gradient of the rendered outputs w.r.t. all leaf parameters                */
+/* ------------------------------------------------------------------------- */
+/* Given g = dL/d(rgb, depth, opacity) per ray, accumulates dL/dtheta into grad[L][P].
+   Along a ray with samples j <= J kept by early termination:
+     dC/dc_j = w_j,   dC/dtau_j = T_{j+1} c_j - (C - sum_{i<=j} w_i c_i)
+   (the same form for depth with c_j -> t_j and for opacity with c_j -> 1), then
+   dtau_j/dsigma_j = delta_j, softplus' = logistic, logistic' = c(1-c), and the chain
+   rule through the linear layers and ReLUs. */
+int orc_render_grad(const int32_t* rows, int nn, int grid_n, const float* params, int n_leaves,
+                    int n_hidden, int hidden, const float* o, const float* d, int64_t R,
+                    const int64_t* ray_idx, int64_t n_sel, int s_max, double eps, int jitter,
+                    uint64_t seed, const double* g_rgb, const double* g_depth,
+                    const double* g_opac, double* grad) {
+  otree T; olayout L; double* P = NULL; octx C;
+  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden)) {
+    free(P); otree_free(&T); return -1;
+  }
+  C.o = o; C.d = d; C.R = R; C.s_max = s_max; C.eps = eps; C.jitter = jitter; C.seed = seed;
+  int act_w = IN_DIM;
+  for (int l = 0; l < L.n_lin; ++l) act_w += L.dout[l];
+  int cap = s_max + 1;
+  oiv* ivbuf = (oiv*)malloc(sizeof(oiv) * (T.n_leaves + 1));
+  osample* sbuf = (osample*)malloc(sizeof(osample) * cap);
+  double* acts = (double*)malloc(sizeof(double) * (int64_t)act_w * cap);
+  double* outs = (double*)malloc(sizeof(double) * OUT_DIM * cap);
+  double* Tj = (double*)malloc(sizeof(double) * (cap + 1));
+  double* wj = (double*)malloc(sizeof(double) * cap);
+  for (int64_t s = 0; s < n_sel; ++s) {
+    int64_t r = ray_idx ? ray_idx[s] : s;
+    double oo[3], dd[3];
+    load_ray(o, d, R, r, oo, dd);
+    ivlist IL = {ivbuf, 0, T.n_leaves + 1};
+    int m = trace_ray(&T, oo, dd, &IL);
+    int ns = make_samples(ivbuf, m, s_max, jitter, seed, r, sbuf);
+    /* forward, keeping activations */
+    double S = 0.0, Cc[3] = {0, 0, 0}, D = 0.0, A = 0.0;
+    int J = ns;
+    Tj[0] = 1.0;
+    for (int j = 0; j < ns; ++j) {
+      double x[3], u[IN_DIM];
+      for (int a = 0; a < 3; ++a) x[a] = oo[a] + sbuf[j].t * dd[a];
+      features(x, dd, u);
+      mlp_forward(&L, P + (int64_t)sbuf[j].slot * L.P, u, outs + OUT_DIM * j, acts + (int64_t)act_w * j);
+      double tau = outs[OUT_DIM * j] * sbuf[j].delta;
+      double Tcur = exp(-S);
+      double w = Tcur * (-expm1(-tau));
+      wj[j] = w;
+      for (int c = 0; c < 3; ++c) Cc[c] += w * outs[OUT_DIM * j + 1 + c];
+      D += w * sbuf[j].t;
+      A += w;
+      S += tau;
+      Tj[j + 1] = exp(-S);
+      if (eps > 0.0 && Tj[j + 1] < eps) { J = j + 1; break; }
+    }
+    const double* gc = g_rgb + 3 * s;
+    double gd = g_depth ? g_depth[s] : 0.0, ga = g_opac ? g_opac[s] : 0.0;
+    double Cp[3] = {0, 0, 0}, Dp = 0.0, Ap = 0.0;
+    for (int j = 0; j < J; ++j) {
+      const double* out = outs + OUT_DIM * j;
+      for (int c = 0; c < 3; ++c) Cp[c] += wj[j] * out[1 + c];
+      Dp += wj[j] * sbuf[j].t;
+      Ap += wj[j];
+      double dtau = 0.0;
+      for (int c = 0; c < 3; ++c) dtau += gc[c] * (Tj[j + 1] * out[1 + c] - (Cc[c] - Cp[c]));
+      dtau += gd * (Tj[j + 1] * sbuf[j].t - (D - Dp));
+      dtau += ga * (Tj[j + 1] - (A - Ap));
+      double dsig = dtau * sbuf[j].delta;
+      /* output pre-activations */
+      const double* act = acts + (int64_t)act_w * j;
+      int zoff = act_w - OUT_DIM;
+      double dz[MAX_HIDDEN], dh[MAX_HIDDEN];
+      dz[0] = dsig * sigmoid(act[zoff + 0]);
+      for (int c = 0; c < 3; ++c) dz[1 + c] = gc[c] * wj[j] * out[1 + c] * (1.0 - out[1 + c]);
+      double* G = grad + (int64_t)sbuf[j].slot * L.P;
+      const double* Pl = P + (int64_t)sbuf[j].slot * L.P;
+      for (int l = L.n_lin - 1; l >= 0; --l) {
+        int din = L.din[l], dout = L.dout[l];
+        /* input of layer l: features for l == 0, else ReLU of layer l-1's pre-activation */
+        int in_off = IN_DIM;
+        for (int k = 0; k < l - 1; ++k) in_off += L.dout[k];
+        const double* zin = l == 0 ? act : act + in_off;
+        double xin[MAX_HIDDEN];
+        for (int i = 0; i < din; ++i) xin[i] = l == 0 ? zin[i] : (zin[i] > 0.0 ? zin[i] : 0.0);
+        const double* W = Pl + L.off_w[l];
+        for (int oi = 0; oi < dout; ++oi) {
+          G[L.off_b[l] + oi] += dz[oi];
+          for (int i = 0; i < din; ++i) G[L.off_w[l] + oi * din + i] += dz[oi] * xin[i];
+        }
+        if (l == 0) break;
+        for (int i = 0; i < din; ++i) {
+          double acc = 0.0;
+          for (int oi = 0; oi < dout; ++oi) acc += W[oi * din + i] * dz[oi];
+          dh[i] = zin[i] > 0.0 ? acc : 0.0;
+        }
+        for (int i = 0; i < din; ++i) dz[i] = dh[i];
+      }
+    }
+  }
+  free(ivbuf); free(sbuf); free(acts); free(outs); free(Tj); free(wj); free(P);
+  otree_free(&T);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Adam (Kingma & Ba 2015) with bias correction                               */
+/* ------------------------------------------------------------------------- */
+void orc_adam(double* p, double* m, double* v, const double* g, int64_t n, int step, double lr,
+              double b1, double b2, double eps) {
+  double c1 = 1.0 - pow(b1, step), c2 = 1.0 - pow(b2, step);
+  for (int64_t i = 0; i < n; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    double mh = m[i] / c1, vh = v[i] / c2;
+    p[i] -= lr * mh / (sqrt(vh) + eps);
+  }
+}
+
+/* Exposed for the published-vector check of the counter-based generator. */
+uint64_t orc_splitmix64(uint64_t x) { return splitmix64(x); }
+double orc_stratum_offset(int jitter, uint64_t seed, int64_t r, int k) {
+  return stratum_offset(jitter, seed, r, k);
+}
