@@ -1,0 +1,241 @@
+/*
+ * amnerf.h -- C ABI of the adaptive multi-NeRF rendering library for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The library renders a scene represented by many small same-shaped MLPs, one per leaf of
+ * a KD tree of axis-aligned boxes built from a guidance density grid (Section 3.2 and 3.4
+ * of the paper).  A render intersects every ray with the tree, places an equal number of
+ * samples in every leaf interval the ray crosses (Section 3.5, Algorithm 1), sorts the
+ * samples by leaf so that each leaf's MLP runs over one contiguous bucket (Section 3.5,
+ * parallel scheduling), and composites the samples front to back with early ray
+ * termination (Section 3.1, which defers to the NeRF volume-rendering quadrature, and
+ * Section 4.1).
+ *
+ * Conventions shared by every call
+ *   - Every call returns AMNERF_OK (0) or a negative status; amnerf_last_error() then gives
+ *     a message (thread-local; valid until the next failing call on the same thread).
+ *     No call aborts, throws or prints.
+ *   - Pointers documented as "device" address memory on the context's GPU; pointers
+ *     documented as "host" address CPU memory.  All such memory is owned by the caller;
+ *     the library only reads or writes it during the call (for device pointers: until the
+ *     work enqueued on the given stream has finished) and keeps no reference to it.
+ *   - Handles (amnerf_ctx, amnerf_tree) are created and destroyed by the library.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls that take
+ *     a stream only enqueue work on it and return without waiting, unless stated.
+ *   - Results are deterministic: the same inputs give bit-identical outputs run to run
+ *     (stable sorts, fixed-order reductions, no floating-point atomics).
+ *   - The scene box is [0,1]^3.  Rays are float32 SoA: o[3][R] then d[3][R] (x row, then
+ *     y, then z); d need not be exactly unit length.
+ */
+#ifndef AMNERF_H
+#define AMNERF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------ */
+#define AMNERF_OK 0
+#define AMNERF_EINVAL (-1)    /* bad argument (null pointer, size or value out of range) */
+#define AMNERF_ENOMEM (-2)    /* host allocation failed, or the workspace cap is too small */
+#define AMNERF_EDEVICE (-3)   /* a HIP runtime call failed */
+#define AMNERF_ECAPACITY (-4) /* a size exceeds a documented limit */
+#define AMNERF_ESTATE (-5)    /* the call is not valid in the current state */
+
+/* ---- arithmetic types of the per-leaf MLP -------------------------------------------- */
+#define AMNERF_F32 0          /* float32 weights and activations, float32 accumulate */
+#define AMNERF_BF16 1         /* bfloat16 weights and activations, float32 accumulate */
+
+/* ---- limits -------------------------------------------------------------------------- */
+#define AMNERF_MAX_GRID 512   /* guidance grid side */
+#define AMNERF_MAX_DEPTH 16
+#define AMNERF_MAX_LEAVES 4096
+#define AMNERF_MAX_SAMPLES 255 /* samples per ray (S_max) */
+
+typedef struct amnerf_ctx amnerf_ctx;
+typedef struct amnerf_tree amnerf_tree;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* amnerf_last_error(void);
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int amnerf_version(void);
+
+/* ---- context ------------------------------------------------------------------------- */
+/* Creates a context on HIP device `device`.  Device workspace is allocated lazily by the
+ * calls that need it and grows on demand up to `workspace_cap` bytes (0 = no cap); a call
+ * that would need more fails with AMNERF_ENOMEM and says how many bytes it needed.
+ * Growing the workspace synchronises the device.  A context must not be used by two host
+ * threads at once. */
+int amnerf_ctx_create(int device, size_t workspace_cap, amnerf_ctx** out);
+
+/* Synchronises the device, frees the workspace and the handle.  NULL is accepted. */
+int amnerf_ctx_destroy(amnerf_ctx* ctx);
+
+/* ---- tree (Section 3.4) -------------------------------------------------------------- */
+typedef struct {
+  int32_t max_depth;   /* 0 .. AMNERF_MAX_DEPTH */
+  int32_t max_leaves;  /* 1 .. AMNERF_MAX_LEAVES */
+} amnerf_tree_params;
+
+typedef struct {
+  int32_t n_nodes;     /* inner nodes + leaves = 2 * n_leaves - 1 */
+  int32_t n_leaves;
+  int32_t depth;       /* deepest leaf */
+  int32_t grid_n;
+} amnerf_tree_info;
+
+/* Builds the density-aware KD tree from a guidance density grid (Section 3.4, BuildKDTree).
+ *   grid_host: host float32[n^3], cell (i,j,k) at index i + n*(j + n*k), the density at the
+ *              cell centre ((i+1/2)/n, (j+1/2)/n, (k+1/2)/n).  Negative values count as 0;
+ *              NaN or infinity is AMNERF_EINVAL.  The grid is read during the call only.
+ *   n:         a power of two, 1 .. AMNERF_MAX_GRID.
+ * Densities are quantised to integers q = floor(g / max(g) * 2^24 + 1/2).  Starting from
+ * the root box (all cells), the splittable leaf of largest integer mass (ties: smallest
+ * node code) is split until there are max_leaves leaves or no leaf is splittable (a leaf
+ * is splittable when its depth < max_depth and its longest side is >= 2 cells).  A split
+ * cuts the longest side (ties: x, then y, then z) at the first cell plane whose lower side
+ * holds at least half of the node's mass (the last plane if none; the middle plane for a
+ * massless node).  Node codes are binary: root 1, children 2c (lower) and 2c+1 (upper).
+ * Leaves are numbered 0..L-1 ("slots") in left-first depth-first order; a leaf's slot is
+ * the node id samples are sorted by.  Runs synchronously on the host, then uploads the
+ * node table to the context's device. */
+int amnerf_build_tree(amnerf_ctx* ctx, const float* grid_host, int32_t n,
+                      const amnerf_tree_params* params, amnerf_tree** out);
+
+int amnerf_tree_info_get(const amnerf_tree* tree, amnerf_tree_info* out);
+
+/* Copies the tree into caller arrays, one row per node, sorted by node code.
+ *   rows_host: host int32[n_nodes][12]: code, depth, lo[3], hi[3] (integer cell box
+ *              [lo, hi)), split axis (-1 for a leaf), split plane (cell index, -1 for a
+ *              leaf), leaf slot (-1 for an inner node), 0.
+ *   mass_host: host uint64[n_nodes] integer masses, or NULL. */
+int amnerf_tree_export(const amnerf_tree* tree, int32_t* rows_host, uint64_t* mass_host);
+
+/* Frees the tree (host and device copies).  NULL is accepted. */
+int amnerf_tree_destroy(amnerf_tree* tree);
+
+/* ---- per-leaf MLPs (Section 3.1, Section 3.2) ----------------------------------------- */
+/* Every leaf holds the same MLP shape (the paper keeps one MLP size for all nodes):
+ *   input 30 = positional encoding of p = 2x - 1 (x the sample position):
+ *              [p, sin(2^k pi p), cos(2^k pi p) for k = 0..3] (27 values, each a 3-vector)
+ *              followed by the ray direction d (3);
+ *   n_hidden linear layers of width `hidden`, each followed by ReLU;
+ *   an output linear layer of width 4: sigma = softplus(o0), rgb = logistic(o1..o3).
+ * Master parameters of one leaf are float32, P floats: for each linear layer in order,
+ * W[out][in] row-major then b[out].  All leaves are stored back to back: [L][P]. */
+typedef struct {
+  int32_t n_hidden;    /* 1 .. 8 */
+  int32_t hidden;      /* 32 or 64 */
+} amnerf_mlp_shape;
+
+/* P, the float32 parameter count of one leaf, or -1 for an invalid shape. */
+int64_t amnerf_mlp_param_count(const amnerf_mlp_shape* shape);
+
+/* Bytes of the kernel-ready parameter block for `n_leaves` leaves in `dtype`. */
+int amnerf_mlp_packed_bytes(const amnerf_mlp_shape* shape, int32_t dtype, int32_t n_leaves,
+                            size_t* out);
+
+/* Converts device master parameters float32[n_leaves][P] into the kernel-ready block
+ * (matrix-core fragment order, weights in `dtype` rounded to nearest even, biases float32)
+ * in the caller's device buffer `packed_dev` of amnerf_mlp_packed_bytes bytes. */
+int amnerf_mlp_pack(amnerf_ctx* ctx, const amnerf_mlp_shape* shape, int32_t dtype,
+                    int32_t n_leaves, const float* master_dev, void* packed_dev, void* stream);
+
+typedef struct {
+  amnerf_mlp_shape shape;
+  int32_t dtype;          /* AMNERF_F32 or AMNERF_BF16 */
+  int32_t n_leaves;       /* must equal the tree's leaf count */
+  const void* packed_dev; /* device block written by amnerf_mlp_pack with the same
+                             shape, dtype and n_leaves */
+} amnerf_mlp;
+
+/* ---- rays ---------------------------------------------------------------------------- */
+typedef struct {
+  const float* o_dev;  /* device float32[3][n_rays] */
+  const float* d_dev;  /* device float32[3][n_rays] */
+  int64_t n_rays;      /* >= 0 */
+} amnerf_rays;
+
+/* ---- render (Section 3.5, Algorithm 1; Section 3.1) ----------------------------------- */
+#define AMNERF_JITTER 1u        /* stratified jitter instead of interval-centred samples */
+
+typedef struct {
+  int32_t s_max;          /* samples per ray budget, 1 .. AMNERF_MAX_SAMPLES */
+  float ert_eps;          /* stop after the sample where transmittance drops below this;
+                             0 disables early termination */
+  uint32_t flags;         /* AMNERF_JITTER */
+  uint64_t jitter_seed;   /* seed of the per-interval offsets when AMNERF_JITTER is set */
+} amnerf_render_params;
+
+typedef struct {
+  float* rgb_dev;         /* device float32[n_rays][3] (background 0) */
+  float* depth_dev;       /* device float32[n_rays]: sum of w_j t_j; may be NULL */
+  float* opacity_dev;     /* device float32[n_rays]: sum of w_j; may be NULL */
+  float* weights_dev;     /* device float32[n_samples] per-sample weights in ray-major
+                             sample order, or NULL; its size is only known after the
+                             render (amnerf_render_stats_get), so a caller passes a buffer
+                             of n_rays * s_max floats */
+} amnerf_render_out;
+
+/* Renders `rays`.  Per ray r: m intervals (t0_k, t1_k, leaf_k) of the leaves the ray
+ * crosses inside [0,1]^3 for t >= 0, front to back; n = s_max / m samples per interval
+ * (if m > s_max, one sample in each of the first s_max intervals); sample j of interval k
+ * at t = t0_k + (j + u) * (t1_k - t0_k) / n with u = 1/2 (or a hash of (seed, r, k) when
+ * jittered) and segment length delta = (t1_k - t0_k) / n.  Samples are then sorted by leaf
+ * slot (stably, so each bucket keeps ray-major order), each leaf's MLP evaluates its
+ * bucket, and per ray tau_j = sigma_j delta_j, T_j = exp(-sum_{i<j} tau_i),
+ * w_j = T_j (1 - exp(-tau_j)), rgb = sum w_j c_j, depth = sum w_j t_j,
+ * opacity = sum w_j, stopping after the first j with T_{j+1} < ert_eps.
+ * Asynchronous on `stream`.  Rays are processed in chunks when the sample budget of
+ * one pass would exceed the context's chunk limit. */
+int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
+                  const amnerf_rays* rays, const amnerf_render_params* params,
+                  amnerf_render_out* out, void* stream);
+
+typedef struct {
+  int64_t n_rays;
+  int64_t n_intervals;    /* leaf intervals that received samples */
+  int64_t n_samples;      /* samples evaluated by the MLPs */
+  int64_t n_tiles;        /* MLP work tiles of the last chunk */
+  int64_t n_chunks;
+  int64_t n_nonfinite;    /* rays whose rgb, depth or opacity is not finite */
+} amnerf_render_stats;
+
+/* Waits for the last render's stream and reports its totals. */
+int amnerf_render_stats_get(amnerf_ctx* ctx, amnerf_render_stats* out);
+
+/* Intermediate arrays of the last render (only if it ran as a single chunk), copied on
+ * `stream` into caller device buffers (any pointer may be NULL to skip that array):
+ *   ray_iv_off   uint32[n_rays+1]   first interval of each ray (ray-major), and the total
+ *   ray_smp_off  uint32[n_rays+1]   first sample of each ray (ray-major), and the total
+ *   iv_t0        float32[n_intervals]  interval start t
+ *   iv_dt        float32[n_intervals]  interval length
+ *   iv_slot      uint32[n_intervals]   leaf slot (the node id samples are sorted by)
+ *   iv_n         uint32[n_intervals]   samples in the interval
+ *   bucket_off   uint32[n_leaves+1]    first sorted sample of each leaf bucket, and total
+ *   perm         uint32[n_samples]     ray-major index of the sample at each sorted
+ *                                      position (the stable sort of samples by slot)
+ *   sample_out   float32[n_samples][4] MLP outputs (sigma, r, g, b) in ray-major order */
+typedef struct {
+  uint32_t* ray_iv_off;
+  uint32_t* ray_smp_off;
+  float* iv_t0;
+  float* iv_dt;
+  uint32_t* iv_slot;
+  uint32_t* iv_n;
+  uint32_t* bucket_off;
+  uint32_t* perm;
+  float* sample_out;
+} amnerf_inspect;
+
+int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMNERF_H */

@@ -1,0 +1,305 @@
+"""Python binding of libamnerf (adaptive multi-NeRF rendering on AMD MI355X).
+
+Every function here only marshals arguments for the C ABI in ``include/amnerf.h``; all
+steps of the rendering path run in the library's HIP kernels.  torch is used for device
+memory and streams: tensors are passed by ``data_ptr()``, streams by their handle.
+The library must have been built (``python -m paper_2310_01881_amd.build``); importing
+this module fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamnerf.so")
+
+AMNERF_OK = 0
+AMNERF_EINVAL = -1
+AMNERF_ENOMEM = -2
+AMNERF_EDEVICE = -3
+AMNERF_ECAPACITY = -4
+AMNERF_ESTATE = -5
+AMNERF_F32 = 0
+AMNERF_BF16 = 1
+AMNERF_JITTER = 1
+AMNERF_MAX_GRID = 512
+AMNERF_MAX_DEPTH = 16
+AMNERF_MAX_LEAVES = 4096
+AMNERF_MAX_SAMPLES = 255
+
+# symbols declared in include/amnerf.h
+EXPORTS = [
+    "amnerf_last_error", "amnerf_version", "amnerf_ctx_create", "amnerf_ctx_destroy",
+    "amnerf_build_tree", "amnerf_tree_info_get", "amnerf_tree_export", "amnerf_tree_destroy",
+    "amnerf_mlp_param_count", "amnerf_mlp_packed_bytes", "amnerf_mlp_pack", "amnerf_render",
+    "amnerf_render_stats_get", "amnerf_render_inspect",
+]
+
+
+class AmnerfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("amnerf error %d: %s" % (code, msg))
+        self.code = code
+
+
+class amnerf_tree_params(C.Structure):
+    _fields_ = [("max_depth", C.c_int32), ("max_leaves", C.c_int32)]
+
+
+class amnerf_tree_info(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_leaves", C.c_int32), ("depth", C.c_int32),
+                ("grid_n", C.c_int32)]
+
+
+class amnerf_mlp_shape(C.Structure):
+    _fields_ = [("n_hidden", C.c_int32), ("hidden", C.c_int32)]
+
+
+class amnerf_mlp(C.Structure):
+    _fields_ = [("shape", amnerf_mlp_shape), ("dtype", C.c_int32), ("n_leaves", C.c_int32),
+                ("packed_dev", C.c_void_p)]
+
+
+class amnerf_rays(C.Structure):
+    _fields_ = [("o_dev", C.c_void_p), ("d_dev", C.c_void_p), ("n_rays", C.c_int64)]
+
+
+class amnerf_render_params(C.Structure):
+    _fields_ = [("s_max", C.c_int32), ("ert_eps", C.c_float), ("flags", C.c_uint32),
+                ("jitter_seed", C.c_uint64)]
+
+
+class amnerf_render_out(C.Structure):
+    _fields_ = [("rgb_dev", C.c_void_p), ("depth_dev", C.c_void_p), ("opacity_dev", C.c_void_p),
+                ("weights_dev", C.c_void_p)]
+
+
+class amnerf_render_stats(C.Structure):
+    _fields_ = [("n_rays", C.c_int64), ("n_intervals", C.c_int64), ("n_samples", C.c_int64),
+                ("n_tiles", C.c_int64), ("n_chunks", C.c_int64), ("n_nonfinite", C.c_int64)]
+
+
+class amnerf_inspect(C.Structure):
+    _fields_ = [("ray_iv_off", C.c_void_p), ("ray_smp_off", C.c_void_p), ("iv_t0", C.c_void_p),
+                ("iv_dt", C.c_void_p), ("iv_slot", C.c_void_p), ("iv_n", C.c_void_p),
+                ("bucket_off", C.c_void_p), ("perm", C.c_void_p), ("sample_out", C.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libamnerf.so is not built: run `python -m paper_2310_01881_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    lib.amnerf_last_error.restype = C.c_char_p
+    lib.amnerf_version.restype = C.c_int
+    lib.amnerf_ctx_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(P)]
+    lib.amnerf_ctx_destroy.argtypes = [P]
+    lib.amnerf_build_tree.argtypes = [P, P, C.c_int32, C.POINTER(amnerf_tree_params), C.POINTER(P)]
+    lib.amnerf_tree_info_get.argtypes = [P, C.POINTER(amnerf_tree_info)]
+    lib.amnerf_tree_export.argtypes = [P, P, P]
+    lib.amnerf_tree_destroy.argtypes = [P]
+    lib.amnerf_mlp_param_count.argtypes = [C.POINTER(amnerf_mlp_shape)]
+    lib.amnerf_mlp_param_count.restype = C.c_int64
+    lib.amnerf_mlp_packed_bytes.argtypes = [C.POINTER(amnerf_mlp_shape), C.c_int32, C.c_int32,
+                                            C.POINTER(C.c_size_t)]
+    lib.amnerf_mlp_pack.argtypes = [P, C.POINTER(amnerf_mlp_shape), C.c_int32, C.c_int32, P, P, P]
+    lib.amnerf_render.argtypes = [P, P, C.POINTER(amnerf_mlp), C.POINTER(amnerf_rays),
+                                  C.POINTER(amnerf_render_params), C.POINTER(amnerf_render_out), P]
+    lib.amnerf_render_stats_get.argtypes = [P, C.POINTER(amnerf_render_stats)]
+    lib.amnerf_render_inspect.argtypes = [P, C.POINTER(amnerf_inspect), P]
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(rc):
+    if rc != AMNERF_OK:
+        raise AmnerfError(rc, _lib.amnerf_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------------------------------
+# C-ABI mirrors (same names, argument marshalling only)
+# ---------------------------------------------------------------------------------------
+def amnerf_last_error() -> str:
+    return _lib.amnerf_last_error().decode()
+
+
+def amnerf_version() -> int:
+    return _lib.amnerf_version()
+
+
+def amnerf_ctx_create(device: int = 0, workspace_cap: int = 0):
+    h = C.c_void_p()
+    _check(_lib.amnerf_ctx_create(device, workspace_cap, C.byref(h)))
+    return h
+
+
+def amnerf_ctx_destroy(ctx):
+    _check(_lib.amnerf_ctx_destroy(ctx))
+
+
+def amnerf_build_tree(ctx, grid: np.ndarray, n: int, max_depth: int, max_leaves: int):
+    g = np.ascontiguousarray(grid, dtype=np.float32)
+    if g.size != n ** 3:
+        raise ValueError("grid has %d cells, expected %d" % (g.size, n ** 3))
+    h = C.c_void_p()
+    prm = amnerf_tree_params(max_depth, max_leaves)
+    _check(_lib.amnerf_build_tree(ctx, g.ctypes.data_as(C.c_void_p), n, C.byref(prm), C.byref(h)))
+    return h
+
+
+def amnerf_tree_info_get(tree) -> amnerf_tree_info:
+    info = amnerf_tree_info()
+    _check(_lib.amnerf_tree_info_get(tree, C.byref(info)))
+    return info
+
+
+def amnerf_tree_export(tree):
+    info = amnerf_tree_info_get(tree)
+    rows = np.zeros((info.n_nodes, 12), np.int32)
+    mass = np.zeros(info.n_nodes, np.uint64)
+    _check(_lib.amnerf_tree_export(tree, rows.ctypes.data_as(C.c_void_p), mass.ctypes.data_as(C.c_void_p)))
+    return rows, mass
+
+
+def amnerf_tree_destroy(tree):
+    _check(_lib.amnerf_tree_destroy(tree))
+
+
+def amnerf_mlp_param_count(n_hidden: int, hidden: int) -> int:
+    s = amnerf_mlp_shape(n_hidden, hidden)
+    return int(_lib.amnerf_mlp_param_count(C.byref(s)))
+
+
+def amnerf_mlp_packed_bytes(n_hidden: int, hidden: int, dtype: int, n_leaves: int) -> int:
+    s = amnerf_mlp_shape(n_hidden, hidden)
+    out = C.c_size_t()
+    _check(_lib.amnerf_mlp_packed_bytes(C.byref(s), dtype, n_leaves, C.byref(out)))
+    return int(out.value)
+
+
+def amnerf_mlp_pack(ctx, n_hidden: int, hidden: int, dtype: int, n_leaves: int, master_dev, packed_dev,
+                    stream=None):
+    s = amnerf_mlp_shape(n_hidden, hidden)
+    _check(_lib.amnerf_mlp_pack(ctx, C.byref(s), dtype, n_leaves, _ptr(master_dev), _ptr(packed_dev),
+                                _stream(stream)))
+
+
+def amnerf_render(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, s_max: int, rgb_dev, depth_dev=None,
+                  opacity_dev=None, weights_dev=None, ert_eps: float = 1e-4, jitter: bool = False,
+                  seed: int = 0, stream=None):
+    rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]) if o_dev is not None else 0)
+    prm = amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed)
+    out = amnerf_render_out(_ptr(rgb_dev), _ptr(depth_dev), _ptr(opacity_dev), _ptr(weights_dev))
+    _check(_lib.amnerf_render(ctx, tree, C.byref(mlp), C.byref(rays), C.byref(prm), C.byref(out),
+                              _stream(stream)))
+
+
+def amnerf_render_stats_get(ctx) -> dict:
+    st = amnerf_render_stats()
+    _check(_lib.amnerf_render_stats_get(ctx, C.byref(st)))
+    return {k: getattr(st, k) for k, _ in st._fields_}
+
+
+def amnerf_render_inspect(ctx, stream=None, **bufs):
+    ins = amnerf_inspect(*[_ptr(bufs.get(k)) for k, _ in amnerf_inspect._fields_])
+    _check(_lib.amnerf_render_inspect(ctx, C.byref(ins), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------------------
+# Convenience objects (still marshalling only)
+# ---------------------------------------------------------------------------------------
+class Context:
+    """Owns an amnerf_ctx; closes it on ``close()`` or garbage collection."""
+
+    def __init__(self, device: int = 0, workspace_cap: int = 0):
+        self.device = device
+        self.h = amnerf_ctx_create(device, workspace_cap)
+
+    def close(self):
+        if self.h is not None:
+            amnerf_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    def __init__(self, ctx: Context, grid, n, max_depth, max_leaves):
+        self.ctx = ctx
+        self.h = amnerf_build_tree(ctx.h, grid, n, max_depth, max_leaves)
+        self.info = amnerf_tree_info_get(self.h)
+        self.rows, self.mass = amnerf_tree_export(self.h)
+
+    @property
+    def n_leaves(self):
+        return self.info.n_leaves
+
+    def leaf_boxes(self):
+        lv = self.rows[self.rows[:, 10] >= 0]
+        return lv[np.argsort(lv[:, 10])][:, 2:8].copy()
+
+    def close(self):
+        if self.h is not None:
+            amnerf_tree_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """Packed per-leaf parameters on the device (kept alive with the descriptor)."""
+
+    def __init__(self, ctx: Context, master_dev, n_hidden, hidden, dtype, n_leaves, stream=None):
+        import torch
+        nbytes = amnerf_mlp_packed_bytes(n_hidden, hidden, dtype, n_leaves)
+        self.packed = torch.empty(nbytes, dtype=torch.uint8, device=master_dev.device)
+        self.master = master_dev
+        amnerf_mlp_pack(ctx.h, n_hidden, hidden, dtype, n_leaves, master_dev, self.packed, stream)
+        self.desc = amnerf_mlp(amnerf_mlp_shape(n_hidden, hidden), dtype, n_leaves,
+                               C.c_void_p(self.packed.data_ptr()))
+        self.n_hidden, self.hidden, self.dtype, self.n_leaves = n_hidden, hidden, dtype, n_leaves
+
+
+def render(ctx: Context, tree: Tree, mlp: Mlp, o_dev, d_dev, s_max, ert_eps=1e-4, jitter=False, seed=0,
+           weights=False, stream=None):
+    """Allocates the outputs and renders; returns dict of device tensors."""
+    import torch
+    R = int(o_dev.shape[1])
+    dev = o_dev.device
+    out = {"rgb": torch.empty((R, 3), dtype=torch.float32, device=dev),
+           "depth": torch.empty(R, dtype=torch.float32, device=dev),
+           "opacity": torch.empty(R, dtype=torch.float32, device=dev)}
+    if weights:
+        out["weights"] = torch.zeros(R * s_max, dtype=torch.float32, device=dev)
+    amnerf_render(ctx.h, tree.h, mlp.desc, o_dev, d_dev, s_max, out["rgb"], out["depth"], out["opacity"],
+                  out.get("weights"), ert_eps, jitter, seed, stream)
+    return out

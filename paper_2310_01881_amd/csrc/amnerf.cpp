@@ -1,0 +1,601 @@
+// amnerf.cpp -- host side of the C ABI declared in include/amnerf.h: argument checks,
+// the integer KD-tree builder, the device workspace and the per-chunk launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "../../include/amnerf.h"
+#include "internal.hpp"
+
+using namespace amn;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(AMNERF_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr uint64_t kChunkSamples = 1ull << 28;   // worst-case samples of one render pass
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------------------
+struct amnerf_ctx {
+  int device = 0;
+  size_t cap = 0;
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  ChunkCounts* counts = nullptr;        // device
+  ChunkCounts* counts_host = nullptr;   // pinned
+  hipStream_t last_stream = nullptr;
+  bool have_render = false;
+  // last render, for stats and inspection
+  int64_t last_rays = 0;
+  int64_t last_chunks = 0;
+  uint32_t last_leaves = 0;
+  uint64_t last_niv_max = 0, last_ns_max = 0;
+  // workspace views of the last chunk
+  uint32_t *iv_off = nullptr, *smp_off = nullptr, *iv_key = nullptr, *bucket_off = nullptr,
+           *perm = nullptr;
+  float *iv_t0 = nullptr, *iv_dt = nullptr, *smp_out = nullptr;
+};
+
+struct amnerf_tree {
+  int device = 0;
+  int grid_n = 0;
+  int n_leaves = 0;
+  int depth = 0;
+  std::vector<int32_t> rows;     // [n][12] sorted by code
+  std::vector<uint64_t> mass;
+  DevNode* dev_nodes = nullptr;
+};
+
+// ---------------------------------------------------------------------------------------
+// misc
+// ---------------------------------------------------------------------------------------
+extern "C" const char* amnerf_last_error(void) { return g_err.c_str(); }
+extern "C" int amnerf_version(void) { return 100; }
+
+extern "C" int amnerf_ctx_create(int device, size_t workspace_cap, amnerf_ctx** out) {
+  if (!out) return fail(AMNERF_EINVAL, "amnerf_ctx_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(AMNERF_EINVAL, "amnerf_ctx_create: device %d of %d", device, ndev);
+  HIP_TRY(hipSetDevice(device));
+  amnerf_ctx* c = new (std::nothrow) amnerf_ctx();
+  if (!c) return fail(AMNERF_ENOMEM, "amnerf_ctx_create: host allocation");
+  c->device = device;
+  c->cap = workspace_cap;
+  hipError_t e = hipMalloc((void**)&c->counts, sizeof(ChunkCounts));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->counts_host, sizeof(ChunkCounts), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    if (c->counts) (void)hipFree(c->counts);
+    delete c;
+    return fail(AMNERF_EDEVICE, "amnerf_ctx_create: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_ctx_destroy(amnerf_ctx* ctx) {
+  if (!ctx) return AMNERF_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->arena) (void)hipFree(ctx->arena);
+  if (ctx->counts) (void)hipFree(ctx->counts);
+  if (ctx->counts_host) (void)hipHostFree(ctx->counts_host);
+  delete ctx;
+  return AMNERF_OK;
+}
+
+static int ensure_arena(amnerf_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->arena_bytes) return AMNERF_OK;
+  if (ctx->cap && bytes > ctx->cap)
+    return fail(AMNERF_ENOMEM, "workspace needs %zu bytes, cap is %zu", bytes, ctx->cap);
+  HIP_TRY(hipDeviceSynchronize());
+  if (ctx->arena) HIP_TRY(hipFree(ctx->arena));
+  ctx->arena = nullptr;
+  ctx->arena_bytes = 0;
+  ctx->have_render = false;
+  size_t grow = bytes + bytes / 8;
+  if (ctx->cap && grow > ctx->cap) grow = ctx->cap;
+  hipError_t e = hipMalloc(&ctx->arena, grow);
+  if (e != hipSuccess) return fail(AMNERF_ENOMEM, "workspace hipMalloc(%zu): %s", grow, hipGetErrorString(e));
+  ctx->arena_bytes = grow;
+  return AMNERF_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// tree (Section 3.4)
+// ---------------------------------------------------------------------------------------
+namespace {
+
+struct HNode {
+  int lo[3], hi[3];
+  uint32_t code;
+  int depth;
+  int axis = -1, plane = -1;
+  int left = -1;     // index of the lower child; the upper child follows it
+  int slot = -1;
+  uint64_t mass = 0;
+};
+
+// Summed-volume table of the quantised grid: V(i,j,k) = sum of q over [0,i)x[0,j)x[0,k).
+struct Svt {
+  int n;
+  std::vector<uint64_t> v;
+  uint64_t at(int i, int j, int k) const { return v[((size_t)k * (n + 1) + j) * (n + 1) + i]; }
+  uint64_t box(const int lo[3], const int hi[3]) const {
+    return at(hi[0], hi[1], hi[2]) - at(lo[0], hi[1], hi[2]) - at(hi[0], lo[1], hi[2]) -
+           at(hi[0], hi[1], lo[2]) + at(lo[0], lo[1], hi[2]) + at(lo[0], hi[1], lo[2]) +
+           at(hi[0], lo[1], lo[2]) - at(lo[0], lo[1], lo[2]);
+  }
+};
+
+int longest_axis(const HNode& nd) {
+  int a = 0;
+  for (int x = 1; x < 3; ++x)
+    if (nd.hi[x] - nd.lo[x] > nd.hi[a] - nd.lo[a]) a = x;
+  return a;
+}
+
+struct Cand {
+  uint64_t mass;
+  uint32_t code;
+  int idx;
+};
+struct CandLess {
+  bool operator()(const Cand& a, const Cand& b) const {
+    // priority_queue pops the largest: larger mass first, then the smaller code
+    if (a.mass != b.mass) return a.mass < b.mass;
+    return a.code > b.code;
+  }
+};
+
+}  // namespace
+
+extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
+                                 const amnerf_tree_params* p, amnerf_tree** out) {
+  if (!ctx || !grid || !p || !out) return fail(AMNERF_EINVAL, "amnerf_build_tree: null argument");
+  *out = nullptr;
+  if (n < 1 || n > 512 || (n & (n - 1)) != 0)
+    return fail(AMNERF_EINVAL, "amnerf_build_tree: grid side %d must be a power of two <= 512", n);
+  if (p->max_depth < 0 || p->max_depth > AMNERF_MAX_DEPTH)
+    return fail(AMNERF_EINVAL, "amnerf_build_tree: max_depth %d out of [0, %d]", p->max_depth, AMNERF_MAX_DEPTH);
+  if (p->max_leaves < 1 || p->max_leaves > AMNERF_MAX_LEAVES)
+    return fail(AMNERF_EINVAL, "amnerf_build_tree: max_leaves %d out of [1, %d]", p->max_leaves, AMNERF_MAX_LEAVES);
+  const size_t ncell = (size_t)n * n * n;
+  double gmax = 0.0;
+  for (size_t i = 0; i < ncell; ++i) {
+    float g = grid[i];
+    if (!std::isfinite(g)) return fail(AMNERF_EINVAL, "amnerf_build_tree: grid[%zu] is not finite", i);
+    if ((double)g > gmax) gmax = g;
+  }
+  Svt S;
+  S.n = n;
+  try {
+    S.v.assign((size_t)(n + 1) * (n + 1) * (n + 1), 0ull);
+  } catch (...) {
+    return fail(AMNERF_ENOMEM, "amnerf_build_tree: summed-volume table");
+  }
+  const size_t N1 = n + 1;
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        double g = grid[(size_t)i + (size_t)n * ((size_t)j + (size_t)n * k)];
+        uint64_t q = (gmax > 0.0 && g > 0.0) ? (uint64_t)std::floor(std::ldexp(g / gmax, 24) + 0.5) : 0ull;
+        size_t o = ((size_t)(k + 1) * N1 + (j + 1)) * N1 + (i + 1);
+        S.v[o] = q + S.v[o - 1] + S.v[o - N1] + S.v[o - N1 * N1] - S.v[o - 1 - N1] - S.v[o - 1 - N1 * N1] -
+                 S.v[o - N1 - N1 * N1] + S.v[o - 1 - N1 - N1 * N1];
+      }
+
+  std::vector<HNode> nodes;
+  nodes.reserve(2 * (size_t)p->max_leaves);
+  HNode root;
+  for (int a = 0; a < 3; ++a) { root.lo[a] = 0; root.hi[a] = n; }
+  root.code = 1;
+  root.depth = 0;
+  root.mass = S.box(root.lo, root.hi);
+  nodes.push_back(root);
+  auto splittable = [&](const HNode& nd) {
+    int a = longest_axis(nd);
+    return nd.depth < p->max_depth && nd.hi[a] - nd.lo[a] >= 2;
+  };
+  std::priority_queue<Cand, std::vector<Cand>, CandLess> pq;
+  if (splittable(nodes[0])) pq.push({nodes[0].mass, 1u, 0});
+  int leaves = 1;
+  while (leaves < p->max_leaves && !pq.empty()) {
+    Cand c = pq.top();
+    pq.pop();
+    HNode nd = nodes[c.idx];
+    const int a = longest_axis(nd);
+    const int lo = nd.lo[a], hi = nd.hi[a];
+    int plane;
+    auto lower_mass = [&](int pl) {
+      int h2[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
+      h2[a] = pl;
+      return S.box(nd.lo, h2);
+    };
+    if (nd.mass == 0) {
+      plane = (lo + hi) / 2;
+    } else {
+      // smallest plane in [lo+1, hi-1] with 2 * lower mass >= node mass (binary search on
+      // the monotone lower mass); the last plane when none qualifies
+      int L = lo + 1, R = hi - 1, ans = hi - 1;
+      while (L <= R) {
+        int mid = (L + R) / 2;
+        if (2 * lower_mass(mid) >= nd.mass) { ans = mid; R = mid - 1; }
+        else L = mid + 1;
+      }
+      plane = ans;
+    }
+    HNode lc = nd, rc = nd;
+    lc.hi[a] = plane;
+    rc.lo[a] = plane;
+    lc.code = 2 * nd.code;
+    rc.code = 2 * nd.code + 1;
+    lc.depth = rc.depth = nd.depth + 1;
+    lc.axis = rc.axis = lc.plane = rc.plane = lc.left = rc.left = -1;
+    lc.mass = S.box(lc.lo, lc.hi);
+    rc.mass = nd.mass - lc.mass;
+    int li = (int)nodes.size();
+    nodes[c.idx].axis = a;
+    nodes[c.idx].plane = plane;
+    nodes[c.idx].left = li;
+    nodes.push_back(lc);
+    nodes.push_back(rc);
+    ++leaves;
+    if (splittable(nodes[li])) pq.push({nodes[li].mass, nodes[li].code, li});
+    if (splittable(nodes[li + 1])) pq.push({nodes[li + 1].mass, nodes[li + 1].code, li + 1});
+  }
+  // slots: left-first depth-first order
+  int next_slot = 0, max_depth = 0;
+  std::vector<int> stack = {0};
+  while (!stack.empty()) {
+    int i = stack.back();
+    stack.pop_back();
+    if (nodes[i].left < 0) {
+      nodes[i].slot = next_slot++;
+      max_depth = std::max(max_depth, nodes[i].depth);
+    } else {
+      stack.push_back(nodes[i].left + 1);
+      stack.push_back(nodes[i].left);
+    }
+  }
+  amnerf_tree* t = new (std::nothrow) amnerf_tree();
+  if (!t) return fail(AMNERF_ENOMEM, "amnerf_build_tree: host allocation");
+  t->device = ctx->device;
+  t->grid_n = n;
+  t->n_leaves = leaves;
+  t->depth = max_depth;
+  std::vector<int> order(nodes.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return nodes[x].code < nodes[y].code; });
+  t->rows.resize(nodes.size() * 12);
+  t->mass.resize(nodes.size());
+  for (size_t k = 0; k < order.size(); ++k) {
+    const HNode& nd = nodes[order[k]];
+    int32_t* r = &t->rows[k * 12];
+    r[0] = (int32_t)nd.code;
+    r[1] = nd.depth;
+    for (int a = 0; a < 3; ++a) { r[2 + a] = nd.lo[a]; r[5 + a] = nd.hi[a]; }
+    r[8] = nd.left < 0 ? -1 : nd.axis;
+    r[9] = nd.left < 0 ? -1 : nd.plane;
+    r[10] = nd.slot;
+    r[11] = 0;
+    t->mass[k] = nd.mass;
+  }
+  // device table: breadth-first, siblings adjacent
+  std::vector<DevNode> dev(nodes.size());
+  std::vector<int> bfs = {0};
+  std::vector<int> at(nodes.size(), -1);
+  at[0] = 0;
+  int next = 1;
+  for (size_t q = 0; q < bfs.size(); ++q) {
+    int i = bfs[q];
+    DevNode& dn = dev[at[i]];
+    if (nodes[i].left < 0) {
+      dn.plane = 0.f;
+      dn.info = -(nodes[i].slot + 1);
+    } else {
+      int l = nodes[i].left;
+      at[l] = next;
+      at[l + 1] = next + 1;
+      dn.plane = (float)nodes[i].plane / (float)n;
+      dn.info = (next << 2) | nodes[i].axis;
+      next += 2;
+      bfs.push_back(l);
+      bfs.push_back(l + 1);
+    }
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&t->dev_nodes, sizeof(DevNode) * dev.size());
+  if (e == hipSuccess) e = hipMemcpy(t->dev_nodes, dev.data(), sizeof(DevNode) * dev.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (t->dev_nodes) (void)hipFree(t->dev_nodes);
+    delete t;
+    return fail(AMNERF_EDEVICE, "amnerf_build_tree: upload: %s", hipGetErrorString(e));
+  }
+  *out = t;
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_tree_info_get(const amnerf_tree* t, amnerf_tree_info* out) {
+  if (!t || !out) return fail(AMNERF_EINVAL, "amnerf_tree_info_get: null argument");
+  out->n_nodes = (int32_t)t->mass.size();
+  out->n_leaves = t->n_leaves;
+  out->depth = t->depth;
+  out->grid_n = t->grid_n;
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_tree_export(const amnerf_tree* t, int32_t* rows, uint64_t* mass) {
+  if (!t || !rows) return fail(AMNERF_EINVAL, "amnerf_tree_export: null argument");
+  std::memcpy(rows, t->rows.data(), sizeof(int32_t) * t->rows.size());
+  if (mass) std::memcpy(mass, t->mass.data(), sizeof(uint64_t) * t->mass.size());
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_tree_destroy(amnerf_tree* t) {
+  if (!t) return AMNERF_OK;
+  if (t->dev_nodes) {
+    (void)hipSetDevice(t->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(t->dev_nodes);
+  }
+  delete t;
+  return AMNERF_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// MLP parameters
+// ---------------------------------------------------------------------------------------
+extern "C" int64_t amnerf_mlp_param_count(const amnerf_mlp_shape* s) {
+  if (!s || s->n_hidden < 1 || s->n_hidden > 8 || (s->hidden != 32 && s->hidden != 64)) return -1;
+  int64_t P = 0;
+  for (int l = 0; l <= s->n_hidden; ++l) {
+    int64_t di = l == 0 ? 30 : s->hidden, dn = l == s->n_hidden ? 4 : s->hidden;
+    P += di * dn + dn;
+  }
+  return P;
+}
+
+static int check_geom(const amnerf_mlp_shape* s, int32_t dtype, MlpGeom* g, const char* who) {
+  if (!s) return fail(AMNERF_EINVAL, "%s: shape is NULL", who);
+  if (!mlp_geom(s->n_hidden, s->hidden, dtype, g))
+    return fail(AMNERF_EINVAL, "%s: unsupported MLP n_hidden=%d hidden=%d dtype=%d", who, s->n_hidden, s->hidden, dtype);
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_mlp_packed_bytes(const amnerf_mlp_shape* s, int32_t dtype, int32_t n_leaves, size_t* out) {
+  MlpGeom g;
+  int rc = check_geom(s, dtype, &g, "amnerf_mlp_packed_bytes");
+  if (rc) return rc;
+  if (!out || n_leaves < 1 || n_leaves > AMNERF_MAX_LEAVES) return fail(AMNERF_EINVAL, "amnerf_mlp_packed_bytes: bad argument");
+  *out = g.node_bytes * (size_t)n_leaves;
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_mlp_pack(amnerf_ctx* ctx, const amnerf_mlp_shape* s, int32_t dtype, int32_t n_leaves,
+                               const float* master, void* packed, void* stream) {
+  MlpGeom g;
+  int rc = check_geom(s, dtype, &g, "amnerf_mlp_pack");
+  if (rc) return rc;
+  if (!ctx || !master || !packed || n_leaves < 1 || n_leaves > AMNERF_MAX_LEAVES)
+    return fail(AMNERF_EINVAL, "amnerf_mlp_pack: bad argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(launch_mlp_pack(g, n_leaves, master, packed, (hipStream_t)stream));
+  return AMNERF_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// render
+// ---------------------------------------------------------------------------------------
+namespace {
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(uint64_t count) {
+    off = (off + 255) / 256 * 256;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * count;
+    return p;
+  }
+};
+
+struct Work {
+  uint32_t *cnt_iv, *cnt_smp, *iv_off, *smp_off, *scan_tmp;
+  float *iv_t0, *iv_dt;
+  uint32_t *iv_key, *iv_ray;
+  uint32_t *mat, *mat_scan, *sidx, *sn, *ssb, *bucket_off, *tile_off;
+  uint32_t *srec_ray, *perm;
+  float *srec_t, *smp_out;
+};
+
+size_t carve(char* base, uint64_t nr, uint64_t niv, uint64_t ns, const SortPlan& sp, Work& w) {
+  Carve c{base};
+  uint64_t scan_n = std::max<uint64_t>({nr, niv, (uint64_t)sp.n_leaves * sp.nseg_max});
+  w.cnt_iv = c.take<uint32_t>(nr);
+  w.cnt_smp = c.take<uint32_t>(nr);
+  w.iv_off = c.take<uint32_t>(nr + 1);
+  w.smp_off = c.take<uint32_t>(nr + 1);
+  w.scan_tmp = c.take<uint32_t>(scan_tmp_words(scan_n));
+  w.iv_t0 = c.take<float>(niv);
+  w.iv_dt = c.take<float>(niv);
+  w.iv_key = c.take<uint32_t>(niv);
+  w.iv_ray = c.take<uint32_t>(niv);
+  w.mat = c.take<uint32_t>((uint64_t)sp.n_leaves * sp.nseg_max);
+  w.mat_scan = c.take<uint32_t>((uint64_t)sp.n_leaves * sp.nseg_max + 1);
+  w.sidx = c.take<uint32_t>(niv);
+  w.sn = c.take<uint32_t>(niv);
+  w.ssb = c.take<uint32_t>(niv + 1);
+  w.bucket_off = c.take<uint32_t>(sp.n_leaves + 1);
+  w.tile_off = c.take<uint32_t>(sp.n_leaves + 1);
+  w.srec_ray = c.take<uint32_t>(ns);
+  w.srec_t = c.take<float>(ns);
+  w.perm = c.take<uint32_t>(ns);
+  w.smp_out = c.take<float>(4 * ns);
+  return c.off + 256;
+}
+
+}  // namespace
+
+extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
+                             const amnerf_rays* rays, const amnerf_render_params* p,
+                             amnerf_render_out* out, void* stream) {
+  if (!ctx || !tree || !mlp || !rays || !p || !out) return fail(AMNERF_EINVAL, "amnerf_render: null argument");
+  MlpGeom g;
+  int rc = check_geom(&mlp->shape, mlp->dtype, &g, "amnerf_render");
+  if (rc) return rc;
+  if (mlp->n_leaves != tree->n_leaves)
+    return fail(AMNERF_EINVAL, "amnerf_render: MLP has %d leaves, tree has %d", mlp->n_leaves, tree->n_leaves);
+  if (!mlp->packed_dev) return fail(AMNERF_EINVAL, "amnerf_render: packed parameters are NULL");
+  if (rays->n_rays < 0) return fail(AMNERF_EINVAL, "amnerf_render: n_rays < 0");
+  if (rays->n_rays > 0 && (!rays->o_dev || !rays->d_dev)) return fail(AMNERF_EINVAL, "amnerf_render: ray arrays are NULL");
+  if (rays->n_rays > 0 && !out->rgb_dev) return fail(AMNERF_EINVAL, "amnerf_render: rgb output is NULL");
+  if (p->s_max < 1 || p->s_max > AMNERF_MAX_SAMPLES)
+    return fail(AMNERF_EINVAL, "amnerf_render: s_max %d out of [1, %d]", p->s_max, AMNERF_MAX_SAMPLES);
+  if (!(p->ert_eps >= 0.f) || !(p->ert_eps < 1.f)) return fail(AMNERF_EINVAL, "amnerf_render: ert_eps must be in [0, 1)");
+  if (tree->device != ctx->device) return fail(AMNERF_EINVAL, "amnerf_render: tree lives on another device");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t R = rays->n_rays;
+  const uint32_t L = (uint32_t)tree->n_leaves;
+  const int jitter = (p->flags & AMNERF_JITTER) ? 1 : 0;
+  const uint64_t iv_per_ray = std::min<uint64_t>((uint64_t)p->s_max, L);
+  uint64_t chunk = std::max<uint64_t>(1, kChunkSamples / (uint64_t)p->s_max);
+  if (R > 0 && (uint64_t)R < chunk) chunk = (uint64_t)R;
+  const uint64_t niv_max = chunk * iv_per_ray, ns_max = chunk * (uint64_t)p->s_max;
+  SortPlan sp = make_sort_plan(niv_max, L);
+  Work w;
+  size_t need = carve(nullptr, chunk, niv_max, ns_max, sp, w);
+  rc = ensure_arena(ctx, need);
+  if (rc) return rc;
+  carve((char*)ctx->arena, chunk, niv_max, ns_max, sp, w);
+  HIP_TRY(launch_counts_reset(ctx->counts, st));
+  int64_t n_chunks = 0;
+  for (int64_t r0 = 0; r0 < R; r0 += (int64_t)chunk, ++n_chunks) {
+    const uint32_t nr = (uint32_t)std::min<int64_t>((int64_t)chunk, R - r0);
+    HIP_TRY(launch_trav_count(tree->dev_nodes, rays->o_dev, rays->d_dev, R, r0, nr, p->s_max, w.cnt_iv, w.cnt_smp, st));
+    HIP_TRY(launch_scan_u32(w.cnt_iv, w.iv_off, nr, nullptr, w.scan_tmp, st));
+    HIP_TRY(launch_scan_u32(w.cnt_smp, w.smp_off, nr, nullptr, w.scan_tmp, st));
+    const uint32_t* n_iv_dev = w.iv_off + nr;
+    HIP_TRY(launch_chunk_begin(ctx->counts, n_iv_dev, st));
+    HIP_TRY(launch_trav_emit(tree->dev_nodes, rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
+                             w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, st));
+    HIP_TRY(launch_sort_hist(sp, w.iv_key, n_iv_dev, w.mat, st));
+    HIP_TRY(launch_scan_u32(w.mat, w.mat_scan, (uint64_t)L * sp.nseg_max, nullptr, w.scan_tmp, st));
+    HIP_TRY(launch_sort_scatter(sp, w.iv_key, n_iv_dev, w.mat_scan, w.sidx, w.sn, st));
+    HIP_TRY(launch_scan_u32(w.sn, w.ssb, niv_max, n_iv_dev, w.scan_tmp, st));
+    HIP_TRY(launch_bucket_tiles(sp, w.mat_scan, w.ssb, w.bucket_off, w.tile_off, ctx->counts, st));
+    HIP_TRY(launch_expand(w.sidx, w.ssb, n_iv_dev, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_off, w.smp_off, r0,
+                          jitter, p->jitter_seed, w.srec_ray, w.srec_t, w.perm, st));
+    HIP_TRY(launch_mlp(g, mlp->packed_dev, L, w.bucket_off, w.tile_off, ctx->counts, w.srec_ray, w.srec_t, w.perm,
+                       rays->o_dev, rays->d_dev, R, r0, w.smp_out, st));
+    HIP_TRY(launch_composite(nr, w.iv_off, w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.smp_out, r0, jitter,
+                             p->jitter_seed, p->ert_eps, out->rgb_dev, out->depth_dev, out->opacity_dev,
+                             out->weights_dev, ctx->counts, st));
+    HIP_TRY(launch_chunk_finish(ctx->counts, w.smp_off + nr, n_iv_dev, st));
+  }
+  ctx->last_stream = st;
+  ctx->have_render = true;
+  ctx->last_rays = R;
+  ctx->last_chunks = n_chunks;
+  ctx->last_leaves = L;
+  ctx->last_niv_max = niv_max;
+  ctx->last_ns_max = ns_max;
+  ctx->iv_off = w.iv_off;
+  ctx->smp_off = w.smp_off;
+  ctx->iv_key = w.iv_key;
+  ctx->iv_t0 = w.iv_t0;
+  ctx->iv_dt = w.iv_dt;
+  ctx->bucket_off = w.bucket_off;
+  ctx->perm = w.perm;
+  ctx->smp_out = w.smp_out;
+  return AMNERF_OK;
+}
+
+static int read_counts(amnerf_ctx* ctx) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipMemcpyAsync(ctx->counts_host, ctx->counts, sizeof(ChunkCounts), hipMemcpyDeviceToHost, ctx->last_stream));
+  HIP_TRY(hipStreamSynchronize(ctx->last_stream));
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_render_stats_get(amnerf_ctx* ctx, amnerf_render_stats* out) {
+  if (!ctx || !out) return fail(AMNERF_EINVAL, "amnerf_render_stats_get: null argument");
+  if (!ctx->have_render) return fail(AMNERF_ESTATE, "amnerf_render_stats_get: no render yet");
+  int rc = read_counts(ctx);
+  if (rc) return rc;
+  const ChunkCounts& c = *ctx->counts_host;
+  out->n_rays = ctx->last_rays;
+  out->n_intervals = (int64_t)c.iv_global;
+  out->n_samples = (int64_t)c.smp_global;
+  out->n_tiles = c.n_tiles;
+  out->n_chunks = ctx->last_chunks;
+  out->n_nonfinite = (int64_t)c.nonfinite;
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* o, void* stream) {
+  if (!ctx || !o) return fail(AMNERF_EINVAL, "amnerf_render_inspect: null argument");
+  if (!ctx->have_render) return fail(AMNERF_ESTATE, "amnerf_render_inspect: no render yet");
+  if (ctx->last_chunks != 1) return fail(AMNERF_ESTATE, "amnerf_render_inspect: last render ran in %lld chunks", (long long)ctx->last_chunks);
+  int rc = read_counts(ctx);
+  if (rc) return rc;
+  const ChunkCounts& c = *ctx->counts_host;
+  const uint64_t nr = (uint64_t)ctx->last_rays, niv = c.n_iv, ns = c.n_smp, L = ctx->last_leaves;
+  hipStream_t st = (hipStream_t)stream;
+  auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!dst || bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+  };
+  HIP_TRY(cp(o->ray_iv_off, ctx->iv_off, 4 * (nr + 1)));
+  HIP_TRY(cp(o->ray_smp_off, ctx->smp_off, 4 * (nr + 1)));
+  HIP_TRY(cp(o->iv_t0, ctx->iv_t0, 4 * niv));
+  HIP_TRY(cp(o->iv_dt, ctx->iv_dt, 4 * niv));
+  HIP_TRY(cp(o->bucket_off, ctx->bucket_off, 4 * (L + 1)));
+  HIP_TRY(cp(o->perm, ctx->perm, 4 * ns));
+  HIP_TRY(cp(o->sample_out, ctx->smp_out, 16 * ns));
+  if (o->iv_slot || o->iv_n) {
+    // split the packed keys on the host (inspection only)
+    std::vector<uint32_t> keys(niv);
+    if (niv) {
+      HIP_TRY(hipMemcpyAsync(keys.data(), ctx->iv_key, 4 * niv, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+    std::vector<uint32_t> slot(niv), nn(niv);
+    for (uint64_t i = 0; i < niv; ++i) { slot[i] = keys[i] & 0xFFFFu; nn[i] = keys[i] >> 16; }
+    if (o->iv_slot && niv) HIP_TRY(hipMemcpy(o->iv_slot, slot.data(), 4 * niv, hipMemcpyHostToDevice));
+    if (o->iv_n && niv) HIP_TRY(hipMemcpy(o->iv_n, nn.data(), 4 * niv, hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return AMNERF_OK;
+}

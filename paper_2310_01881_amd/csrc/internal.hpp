@@ -1,0 +1,105 @@
+// internal.hpp -- declarations shared by the host orchestration and the HIP kernels of the
+// adaptive multi-NeRF library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace amn {
+
+// Device node table.  Children of an inner node are stored next to each other, so one
+// index reaches both.  info >= 0: inner node, (left_index << 2) | split_axis;
+// info < 0: leaf with slot -(info + 1).  plane is the split plane's coordinate in [0,1]
+// (a multiple of 1/grid_n, exact in float32).
+struct DevNode {
+  float plane;
+  int32_t info;
+};
+
+// Per-chunk totals produced on the device (the host never waits for them mid-render).
+struct ChunkCounts {
+  uint32_t n_iv;        // intervals that carry samples (this chunk)
+  uint32_t n_smp;       // samples (this chunk)
+  uint32_t n_tiles;     // MLP work tiles (this chunk)
+  uint32_t pad;
+  uint64_t smp_global;  // ray-major sample index of this chunk's first sample
+  uint64_t iv_global;   // intervals of the chunks before this one
+  uint64_t nonfinite;   // rays with a non-finite output (accumulated over chunks)
+};
+
+constexpr int kMlpTileRows = 256;       // rows of one MLP work tile (4 waves x 64)
+constexpr int kScanItems = 2048;        // elements per scan block (256 threads x 8)
+
+// ---- traversal (Algorithm 1: Traverse) -------------------------------------------------
+// Pass 1: per ray, the number of leaf intervals that receive samples (min(m, s_max)) and
+// the number of samples.  Pass 2: the intervals themselves, ray-major, at iv_off.
+hipError_t launch_trav_count(const DevNode* nodes, const float* o, const float* d,
+                             int64_t ray_stride, int64_t r0, uint32_t nr, int s_max,
+                             uint32_t* cnt_iv, uint32_t* cnt_smp, hipStream_t st);
+hipError_t launch_trav_emit(const DevNode* nodes, const float* o, const float* d,
+                            int64_t ray_stride, int64_t r0, uint32_t nr,
+                            const uint32_t* cnt_iv, const uint32_t* cnt_smp,
+                            const uint32_t* iv_off, float* iv_t0, float* iv_dt,
+                            uint32_t* iv_key, uint32_t* iv_ray, hipStream_t st);
+
+// ---- scans -----------------------------------------------------------------------------
+// Exclusive prefix sum of n uint32 values (n given on the host, or read from n_dev when
+// n_dev != nullptr, capped at n_cap); out[n] receives the total.  tmp needs
+// scan_tmp_words(n_cap) words.
+size_t scan_tmp_words(uint64_t n_cap);
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n_cap,
+                           const uint32_t* n_dev, uint32_t* tmp, hipStream_t st);
+
+// ---- sort by leaf slot (Section 3.5: sort, then infer per node) ------------------------
+struct SortPlan {
+  uint32_t seg;         // intervals per segment (multiple of 64)
+  uint32_t nseg_max;    // segments for the worst-case interval count
+  uint32_t key_bits;    // bits of the leaf slot
+  uint32_t n_leaves;
+};
+SortPlan make_sort_plan(uint64_t n_iv_max, uint32_t n_leaves);
+hipError_t launch_sort_hist(const SortPlan& p, const uint32_t* iv_key, const uint32_t* n_iv_dev,
+                            uint32_t* mat, hipStream_t st);
+hipError_t launch_sort_scatter(const SortPlan& p, const uint32_t* iv_key, const uint32_t* n_iv_dev,
+                               const uint32_t* mat_scan, uint32_t* sidx, uint32_t* sn,
+                               hipStream_t st);
+// bucket_off[b] = first sorted sample of leaf b; tile_off[b] = first MLP tile of leaf b;
+// also fills counts->n_smp and counts->n_tiles.
+hipError_t launch_bucket_tiles(const SortPlan& p, const uint32_t* mat_scan, const uint32_t* ssb,
+                               uint32_t* bucket_off, uint32_t* tile_off, ChunkCounts* counts,
+                               hipStream_t st);
+// One record per sorted sample: ray (chunk-local), t, ray-major sample index.
+hipError_t launch_expand(const uint32_t* sidx, const uint32_t* ssb, const uint32_t* n_iv_dev,
+                         const float* iv_t0, const float* iv_dt, const uint32_t* iv_key,
+                         const uint32_t* iv_ray, const uint32_t* iv_off, const uint32_t* smp_off,
+                         int64_t r0, int jitter, uint64_t seed, uint32_t* srec_ray,
+                         float* srec_t, uint32_t* perm, hipStream_t st);
+
+// ---- grouped per-leaf MLP ---------------------------------------------------------------
+struct MlpGeom {
+  int n_hidden, hidden, dtype;
+  size_t node_bytes;    // packed bytes of one leaf
+};
+bool mlp_geom(int n_hidden, int hidden, int dtype, MlpGeom* g);
+hipError_t launch_mlp_pack(const MlpGeom& g, int n_leaves, const float* master, void* packed,
+                           hipStream_t st);
+hipError_t launch_mlp(const MlpGeom& g, const void* packed, uint32_t n_leaves,
+                      const uint32_t* bucket_off, const uint32_t* tile_off,
+                      const ChunkCounts* counts, const uint32_t* srec_ray, const float* srec_t,
+                      const uint32_t* perm, const float* o, const float* d, int64_t ray_stride,
+                      int64_t r0, float* out, hipStream_t st);
+
+// ---- compositing (Section 3.1 -> NeRF quadrature, early ray termination) ---------------
+hipError_t launch_composite(uint32_t nr, const uint32_t* iv_off, const uint32_t* smp_off,
+                            const float* iv_t0, const float* iv_dt, const uint32_t* iv_key,
+                            const float* smp_out, int64_t r0, int jitter, uint64_t seed,
+                            float ert_eps, float* rgb, float* depth, float* opac,
+                            float* weights, ChunkCounts* counts, hipStream_t st);
+
+// ---- small helpers ----------------------------------------------------------------------
+hipError_t launch_counts_reset(ChunkCounts* counts, hipStream_t st);
+hipError_t launch_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total, hipStream_t st);
+hipError_t launch_chunk_finish(ChunkCounts* counts, const uint32_t* smp_off_total,
+                               const uint32_t* iv_off_total, hipStream_t st);
+
+}  // namespace amn

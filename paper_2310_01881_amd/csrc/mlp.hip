@@ -1,0 +1,398 @@
+// mlp.hip -- grouped per-leaf MLP inference on the matrix cores (Section 3.5: after the
+// sort, each node's small network runs over its bucket; Section 4.4: small MLPs are fast
+// when their weights stay on chip).
+//
+// Work: the sorted samples of leaf b form rows [bucket_off[b], bucket_off[b+1]); they are
+// cut into 256-row tiles that never straddle two leaves.  A persistent grid gives each
+// block a contiguous run of tiles, so consecutive tiles mostly share one leaf and the
+// leaf's packed parameters are staged into LDS only when the leaf changes.
+//
+// Data flow inside a wave (64 rows = 4 column blocks of 16 samples): every layer is
+// computed transposed, Y^T = W X^T, with the weights as the MFMA A operand (from LDS) and
+// the activations as the B operand (in registers).  An MFMA accumulator leaves lane
+// (g = lane/16, n = lane%16) holding rows 4g..4g+3 of its 16-row block for sample n; the
+// packer orders each layer's K index so that exactly those values are the next layer's B
+// operand for that lane.  Activations therefore never leave registers between layers.
+// Biases enter as the C operand of the first MFMA of each output block.
+//   F32  : v_mfma_f32_16x16x4_f32  (fp32 in, fp32 accumulate)
+//   BF16 : v_mfma_f32_16x16x32_bf16 (bf16 in, fp32 accumulate)
+#include "internal.hpp"
+#include "devcommon.hpp"
+
+#include "../../include/amnerf.h"
+
+namespace amn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kUnitBytes = 1024;   // one A fragment set: 64 lanes x 16 bytes
+
+struct Layout {
+  int H, nh, dtype, RB, KU0, KUh;
+  int bias_floats, bias_bytes, units;
+  uint32_t bytes;
+  __host__ __device__ int unit_index(int layer, int rb, int ku) const {
+    if (layer == 0) return rb * KU0 + ku;
+    int base = RB * KU0;
+    if (layer < nh) return base + (layer - 1) * RB * KUh + rb * KUh + ku;
+    return base + (nh - 1) * RB * KUh + ku;
+  }
+};
+
+Layout make_layout(int nh, int H, int dtype) {
+  Layout L;
+  L.H = H; L.nh = nh; L.dtype = dtype; L.RB = H / 16;
+  L.KU0 = dtype == AMNERF_BF16 ? 1 : 2;
+  L.KUh = dtype == AMNERF_BF16 ? H / 32 : H / 16;
+  L.bias_floats = nh * H + 16;
+  L.bias_bytes = (L.bias_floats * 4 + 15) / 16 * 16;
+  L.units = L.RB * L.KU0 + (nh - 1) * L.RB * L.KUh + L.KUh;
+  L.bytes = (uint32_t)(L.bias_bytes + L.units * kUnitBytes);
+  return L;
+}
+
+// Input feature held by lane group g in slot i (0..7) of the first layer's B operand, as a
+// column of the master W0[out][30]: sin(2^g pi p) xyz, cos(2^g pi p) xyz, then two of
+// (p_x, p_y, p_z, d_x, d_y, d_z, -, -).  -1 = zero feature.
+__host__ __device__ __forceinline__ int first_layer_col(int g, int i) {
+  if (i < 3) return 3 + 6 * g + i;
+  if (i < 6) return 3 + 6 * g + 3 + (i - 3);
+  int e = 2 * g + (i - 6);
+  return e < 3 ? e : (e < 6 ? 27 + (e - 3) : -1);
+}
+
+// Master offsets of layer l (din x dout weights then dout biases).
+__device__ __forceinline__ void master_offsets(int nh, int H, int l, int& din, int& dout, int& off_w,
+                                               int& off_b) {
+  int off = 0;
+  for (int k = 0; k < l; ++k) {
+    int di = k == 0 ? 30 : H, dn = k == nh ? 4 : H;
+    off += di * dn + dn;
+  }
+  din = l == 0 ? 30 : H;
+  dout = l == nh ? 4 : H;
+  off_w = off;
+  off_b = off + din * dout;
+}
+
+// One thread per (leaf, unit, lane): 16 bytes of A fragment.  Plus the bias block.
+__global__ void k_mlp_pack(Layout L, int n_leaves, int P, const float* __restrict__ master,
+                           uint8_t* __restrict__ packed) {
+  const uint64_t per_leaf = (uint64_t)L.units * 64;
+  const uint64_t total = per_leaf * n_leaves;
+  for (uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
+       id += (uint64_t)gridDim.x * blockDim.x) {
+    int leaf = (int)(id / per_leaf);
+    int rem = (int)(id % per_leaf);
+    int unit = rem / 64, lane = rem % 64;
+    int g = lane / 16, m = lane % 16;
+    // which layer / rb / ku is this unit
+    int layer, rb, ku;
+    int n0 = L.RB * L.KU0, nhid = (L.nh - 1) * L.RB * L.KUh;
+    if (unit < n0) { layer = 0; rb = unit / L.KU0; ku = unit % L.KU0; }
+    else if (unit < n0 + nhid) { int u = unit - n0; layer = 1 + u / (L.RB * L.KUh); u %= L.RB * L.KUh; rb = u / L.KUh; ku = u % L.KUh; }
+    else { layer = L.nh; rb = 0; ku = unit - n0 - nhid; }
+    int din, dout, off_w, off_b;
+    master_offsets(L.nh, L.H, layer, din, dout, off_w, off_b);
+    const float* W = master + (uint64_t)leaf * P + off_w;
+    int row = 16 * rb + m;
+    uint8_t* dst = packed + (uint64_t)leaf * L.bytes + L.bias_bytes + (uint64_t)unit * kUnitBytes + lane * 16;
+    int ne = L.dtype == AMNERF_BF16 ? 8 : 4;
+    float v[8];
+    for (int e = 0; e < ne; ++e) {
+      int col;
+      if (L.dtype == AMNERF_BF16) col = layer == 0 ? first_layer_col(g, e) : 16 * (2 * ku + e / 4) + 4 * g + (e % 4);
+      else { int kb = 4 * ku + e; col = layer == 0 ? first_layer_col(g, kb) : 16 * ku + 4 * g + e; }
+      v[e] = (row < dout && col >= 0) ? W[row * din + col] : 0.f;
+    }
+    if (L.dtype == AMNERF_BF16) {
+      bf16x8 h;
+      for (int e = 0; e < 8; ++e) h[e] = (__bf16)v[e];
+      *(bf16x8*)dst = h;
+    } else {
+      *(f32x4*)dst = f32x4{v[0], v[1], v[2], v[3]};
+    }
+  }
+  const uint64_t btotal = (uint64_t)(L.bias_bytes / 4) * n_leaves;
+  for (uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; id < btotal;
+       id += (uint64_t)gridDim.x * blockDim.x) {
+    int leaf = (int)(id / (L.bias_bytes / 4));
+    int j = (int)(id % (L.bias_bytes / 4));
+    float val = 0.f;
+    if (j < L.nh * L.H) {
+      int l = j / L.H, o = j % L.H, din, dout, off_w, off_b;
+      master_offsets(L.nh, L.H, l, din, dout, off_w, off_b);
+      val = master[(uint64_t)leaf * P + off_b + o];
+    } else if (j < L.nh * L.H + 4) {
+      int din, dout, off_w, off_b;
+      master_offsets(L.nh, L.H, L.nh, din, dout, off_w, off_b);
+      val = master[(uint64_t)leaf * P + off_b + (j - L.nh * L.H)];
+    }
+    ((float*)(packed + (uint64_t)leaf * L.bytes))[j] = val;
+  }
+}
+
+__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+__device__ __forceinline__ float logisticf(float z) { return 1.f / (1.f + expf(-z)); }
+
+template <bool BF16>
+__device__ __forceinline__ void sincos_pi(float x, float& s, float& c) {
+  if (BF16) {
+    // hardware sine/cosine take revolutions: sin(2 pi r); here r = x / 2 exactly
+    s = __builtin_amdgcn_sinf(0.5f * x);
+    c = __builtin_amdgcn_cosf(0.5f * x);
+  } else {
+    s = sinpif(x);
+    c = cospif(x);
+  }
+}
+
+template <int H, bool BF16>
+__global__ __launch_bounds__(kThreads) void k_mlp(
+    Layout L, const uint8_t* __restrict__ packed, uint32_t n_leaves,
+    const uint32_t* __restrict__ bucket_off, const uint32_t* __restrict__ tile_off,
+    const ChunkCounts* __restrict__ counts, const uint32_t* __restrict__ srec_ray,
+    const float* __restrict__ srec_t, const uint32_t* __restrict__ perm,
+    const float* __restrict__ o, const float* __restrict__ d, int64_t stride, int64_t r0,
+    float* __restrict__ out) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  constexpr int RB = H / 16;
+  constexpr int NCB = 4;                       // column blocks per wave
+  constexpr int KUh = BF16 ? H / 32 : H / 16;  // K units of a hidden-width input
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, m = lane & 15;
+  const float* bias = reinterpret_cast<const float*>(lds);
+  const uint8_t* units = lds + L.bias_bytes;
+
+  const uint32_t T = counts->n_tiles;
+  const uint32_t tb = (uint32_t)(((uint64_t)blockIdx.x * T) / gridDim.x);
+  const uint32_t te = (uint32_t)(((uint64_t)(blockIdx.x + 1) * T) / gridDim.x);
+  if (tb >= te) return;
+  // leaf of the first tile: largest b with tile_off[b] <= tb
+  uint32_t lo = 0, hi = n_leaves;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (tile_off[mid] <= tb) lo = mid; else hi = mid;
+  }
+  uint32_t b = lo;
+  int cur = -1;
+  for (uint32_t t = tb; t < te; ++t) {
+    while (tile_off[b + 1] <= t) ++b;
+    if ((int)b != cur) {
+      __syncthreads();
+      const f32x4* src = reinterpret_cast<const f32x4*>(packed + (uint64_t)b * L.bytes);
+      f32x4* dst = reinterpret_cast<f32x4*>(lds);
+      for (uint32_t i = tid; i < L.bytes / 16; i += kThreads) dst[i] = src[i];
+      __syncthreads();
+      cur = (int)b;
+    }
+    const uint32_t row0 = bucket_off[b] + (t - tile_off[b]) * kMlpTileRows + wave * 64;
+    const uint32_t row_end = bucket_off[b + 1];
+    if (row0 >= row_end) continue;
+
+    // ---- inputs: positional encoding of this lane's 8 features for 4 samples ----
+    float feat[NCB][8];
+    uint32_t dst_idx[NCB];
+    bool valid[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      uint32_t row = row0 + cb * 16 + m;
+      valid[cb] = row < row_end;
+      uint32_t ray = 0;
+      float ts = 0.f;
+      dst_idx[cb] = 0;
+      if (valid[cb]) {
+        ray = srec_ray[row];
+        ts = srec_t[row];
+        dst_idx[cb] = perm[row];
+      }
+      int64_t ri = r0 + ray;
+      float ox = o[ri], oy = o[stride + ri], oz = o[2 * stride + ri];
+      float dx = d[ri], dy = d[stride + ri], dz = d[2 * stride + ri];
+      float px = 2.f * fmaf(ts, dx, ox) - 1.f;
+      float py = 2.f * fmaf(ts, dy, oy) - 1.f;
+      float pz = 2.f * fmaf(ts, dz, oz) - 1.f;
+      float sc = (float)(1 << g);
+      float s0, c0, s1, c1, s2, c2;
+      sincos_pi<BF16>(px * sc, s0, c0);
+      sincos_pi<BF16>(py * sc, s1, c1);
+      sincos_pi<BF16>(pz * sc, s2, c2);
+      feat[cb][0] = s0; feat[cb][1] = s1; feat[cb][2] = s2;
+      feat[cb][3] = c0; feat[cb][4] = c1; feat[cb][5] = c2;
+      float e0 = g == 0 ? px : (g == 1 ? pz : (g == 2 ? dy : 0.f));
+      float e1 = g == 0 ? py : (g == 1 ? dx : (g == 2 ? dz : 0.f));
+      feat[cb][6] = valid[cb] ? e0 : 0.f;
+      feat[cb][7] = valid[cb] ? e1 : 0.f;
+    }
+
+    f32x4 acc[NCB][RB];
+    // ---- layer 0: 32 (padded) -> H ----
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
+      if (BF16) {
+        bf16x8 A = *reinterpret_cast<const bf16x8*>(units + L.unit_index(0, rb, 0) * kUnitBytes + lane * 16);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          bf16x8 Bv;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) Bv[e] = (__bf16)feat[cb][e];
+          acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv, bv, 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb][rb] = bv;
+#pragma unroll
+        for (int ku = 0; ku < 2; ++ku) {
+          f32x4 A = *reinterpret_cast<const f32x4*>(units + L.unit_index(0, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], feat[cb][4 * ku + e], acc[cb][rb], 0, 0, 0);
+        }
+      }
+    }
+
+    // ---- hidden layers H -> H, then the output layer H -> 4 (padded to 16) ----
+    for (int layer = 1; layer <= L.nh; ++layer) {
+      const bool last = layer == L.nh;
+      const int nrb = last ? 1 : RB;
+      // previous activations (ReLU) as B operands
+      f32x4 nacc[NCB][RB];
+      if (BF16) {
+        bf16x8 Bv[NCB][KUh];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int ku = 0; ku < KUh; ++ku)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) Bv[cb][ku][e] = (__bf16)fmaxf(acc[cb][2 * ku + e / 4][e % 4], 0.f);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= nrb) break;
+          f32x4 bv = *reinterpret_cast<const f32x4*>(bias + (layer * H) + 16 * rb + 4 * g);
+#pragma unroll
+          for (int ku = 0; ku < KUh; ++ku) {
+            bf16x8 A = *reinterpret_cast<const bf16x8*>(units + L.unit_index(layer, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              nacc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv[cb][ku], ku == 0 ? bv : nacc[cb][rb], 0, 0, 0);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[cb][rb][e] = fmaxf(acc[cb][rb][e], 0.f);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= nrb) break;
+          f32x4 bv = *reinterpret_cast<const f32x4*>(bias + (layer * H) + 16 * rb + 4 * g);
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) nacc[cb][rb] = bv;
+#pragma unroll
+          for (int ku = 0; ku < KUh; ++ku) {
+            f32x4 A = *reinterpret_cast<const f32x4*>(units + L.unit_index(layer, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb)
+                nacc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], acc[cb][ku][e], nacc[cb][rb], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          if (rb < nrb) acc[cb][rb] = nacc[cb][rb];
+    }
+
+    // ---- heads: lanes of group 0 hold (sigma^, r^, g^, b^) of their sample ----
+    if (g == 0) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        if (!valid[cb]) continue;
+        f32x4 z = acc[cb][0];
+        f32x4 r = {softplusf(z[0]), logisticf(z[1]), logisticf(z[2]), logisticf(z[3])};
+        *reinterpret_cast<f32x4*>(out + 4 * (uint64_t)dst_idx[cb]) = r;
+      }
+    }
+  }
+}
+
+template <int H, bool BF16>
+hipError_t launch_typed(const Layout& L, const void* packed, uint32_t n_leaves, const uint32_t* bucket_off,
+                        const uint32_t* tile_off, const ChunkCounts* counts, const uint32_t* srec_ray,
+                        const float* srec_t, const uint32_t* perm, const float* o, const float* d,
+                        int64_t stride, int64_t r0, float* out, hipStream_t st) {
+  static int grid = 0;
+  static uint32_t grid_bytes = 0;
+  auto kern = k_mlp<H, BF16>;
+  if (grid == 0 || grid_bytes != L.bytes) {
+    if (L.bytes > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.bytes);
+      if (e != hipSuccess) return e;
+    }
+    int dev = 0, ncu = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kThreads, L.bytes);
+    if (e != hipSuccess) return e;
+    if (per < 1) per = 1;
+    grid = ncu * per;
+    grid_bytes = L.bytes;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), L.bytes, st, L, (const uint8_t*)packed, n_leaves,
+                     bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d, stride, r0, out);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool mlp_geom(int n_hidden, int hidden, int dtype, MlpGeom* g) {
+  if (n_hidden < 1 || n_hidden > 8) return false;
+  if (hidden != 32 && hidden != 64) return false;
+  if (dtype != AMNERF_F32 && dtype != AMNERF_BF16) return false;
+  Layout L = make_layout(n_hidden, hidden, dtype);
+  if (L.bytes > 160 * 1024) return false;
+  g->n_hidden = n_hidden;
+  g->hidden = hidden;
+  g->dtype = dtype;
+  g->node_bytes = L.bytes;
+  return true;
+}
+
+hipError_t launch_mlp_pack(const MlpGeom& g, int n_leaves, const float* master, void* packed,
+                           hipStream_t st) {
+  Layout L = make_layout(g.n_hidden, g.hidden, g.dtype);
+  int P = 0;
+  for (int l = 0; l <= g.n_hidden; ++l) {
+    int di = l == 0 ? 30 : g.hidden, dn = l == g.n_hidden ? 4 : g.hidden;
+    P += di * dn + dn;
+  }
+  hipLaunchKernelGGL(k_mlp_pack, dim3(1024), dim3(256), 0, st, L, n_leaves, P, master, (uint8_t*)packed);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp(const MlpGeom& g, const void* packed, uint32_t n_leaves, const uint32_t* bucket_off,
+                      const uint32_t* tile_off, const ChunkCounts* counts, const uint32_t* srec_ray,
+                      const float* srec_t, const uint32_t* perm, const float* o, const float* d,
+                      int64_t ray_stride, int64_t r0, float* out, hipStream_t st) {
+  Layout L = make_layout(g.n_hidden, g.hidden, g.dtype);
+  if (g.dtype == AMNERF_BF16) {
+    if (g.hidden == 64) return launch_typed<64, true>(L, packed, n_leaves, bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d, ray_stride, r0, out, st);
+    return launch_typed<32, true>(L, packed, n_leaves, bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d, ray_stride, r0, out, st);
+  }
+  if (g.hidden == 64) return launch_typed<64, false>(L, packed, n_leaves, bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d, ray_stride, r0, out, st);
+  return launch_typed<32, false>(L, packed, n_leaves, bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d, ray_stride, r0, out, st);
+}
+
+}  // namespace amn

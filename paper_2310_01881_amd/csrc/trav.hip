@@ -1,0 +1,205 @@
+// trav.hip -- ray / KD-tree traversal producing front-to-back leaf intervals
+// (Section 3.5, Algorithm 1: Traverse), one lane per ray.
+//
+// Interval endpoints are carried as unevaluated float pairs (hi + lo): the plane
+// crossing t = (s - o) / d is formed with an exact TwoSum of the numerator and an
+// FMA-exact remainder of the division, so endpoints agree with a float64 evaluation to
+// about 2^-46 relative.  Descent decisions therefore match a float64 traversal except on
+// rays that graze a split edge, and interval lengths (which weight densities in the
+// quadrature) keep float32 relative accuracy even far along the ray.
+#include "internal.hpp"
+#include "devcommon.hpp"
+
+namespace amn {
+namespace {
+
+struct DF {
+  float hi, lo;
+};
+
+__device__ __forceinline__ DF two_sum(float a, float b) {
+  float s = a + b;
+  float bb = s - a;
+  float e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+
+// (s - o) / d as a normalised pair; d != 0.
+__device__ __forceinline__ DF plane_t(float s, float o, float d) {
+  DF num = two_sum(s, -o);
+  float q0 = num.hi / d;
+  float r = fmaf(-q0, d, num.hi);   // exact remainder of the float division
+  r += num.lo;
+  float q1 = r / d;
+  float h = q0 + q1;
+  float l = q1 - (h - q0);
+  return {h, l};
+}
+
+__device__ __forceinline__ bool df_lt(DF a, DF b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+
+constexpr int kStack = 17;       // AMNERF_MAX_DEPTH + 1
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ float axis_val(const float v[3], int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); }
+
+// Traverses one ray.  EMIT = false: returns the interval count, stopping once it exceeds
+// cap.  EMIT = true: writes the first `cap` intervals through the output pointers.
+template <bool EMIT>
+__device__ int traverse(const DevNode* __restrict__ nodes, const float o[3], const float dir[3],
+                        int cap, uint32_t n_per, uint32_t ray, int* st_node, float* st_hi,
+                        float* st_lo, float* iv_t0, float* iv_dt, uint32_t* iv_key,
+                        uint32_t* iv_ray) {
+  // root box [0,1]^3
+  DF tin = {0.f, 0.f}, tout = {__builtin_inff(), 0.f};
+  bool hit = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (dir[a] == 0.f) {
+      if (o[a] < 0.f || o[a] > 1.f) hit = false;
+      continue;
+    }
+    DF ta = plane_t(0.f, o[a], dir[a]);
+    DF tb = plane_t(1.f, o[a], dir[a]);
+    if (df_lt(tb, ta)) { DF t = ta; ta = tb; tb = t; }
+    if (df_lt(tin, ta)) tin = ta;
+    if (df_lt(tb, tout)) tout = tb;
+  }
+  hit = hit && df_lt(tin, tout);
+  if (!hit) return 0;
+  int m = 0, sp = 0, node = 0;
+  DF t0 = tin, t1 = tout;
+  while (true) {
+    int info = nodes[node].info;
+    while (info >= 0) {
+      int a = info & 3;
+      int left = info >> 2;
+      float s = nodes[node].plane;
+      float oa = axis_val(o, a), da = axis_val(dir, a);
+      if (da == 0.f) {
+        node = oa >= s ? left + 1 : left;
+      } else {
+        DF ts = plane_t(s, oa, da);
+        int before = da > 0.f ? left : left + 1;
+        int after = da > 0.f ? left + 1 : left;
+        if (!df_lt(ts, t1)) {
+          node = before;
+        } else if (!df_lt(t0, ts)) {
+          node = after;
+        } else {
+          st_node[sp * kBlock] = after;
+          st_hi[sp * kBlock] = t1.hi;
+          st_lo[sp * kBlock] = t1.lo;
+          ++sp;
+          node = before;
+          t1 = ts;
+        }
+      }
+      info = nodes[node].info;
+    }
+    // leaf interval [t0, t1], t1 > t0 by construction
+    if (EMIT) {
+      if (m < cap) {
+        float dh = t1.hi - t0.hi;
+        float dt = dh + (t1.lo - t0.lo);
+        iv_t0[m] = t0.hi;
+        iv_dt[m] = dt;
+        iv_key[m] = (uint32_t)(-(info + 1)) | (n_per << 16);
+        iv_ray[m] = ray;
+      }
+    }
+    ++m;
+    if (m >= cap + (EMIT ? 0 : 1) || sp == 0) break;
+    --sp;
+    node = st_node[sp * kBlock];
+    t0 = t1;
+    t1 = {st_hi[sp * kBlock], st_lo[sp * kBlock]};
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict__ nodes,
+                                                       const float* __restrict__ o,
+                                                       const float* __restrict__ d,
+                                                       int64_t stride, int64_t r0, uint32_t nr,
+                                                       int s_max, uint32_t* __restrict__ cnt_iv,
+                                                       uint32_t* __restrict__ cnt_smp) {
+  __shared__ int st_node[kStack * kBlock];
+  __shared__ float st_hi[kStack * kBlock];
+  __shared__ float st_lo[kStack * kBlock];
+  uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+  bool live = r < nr;
+  float oo[3] = {0.f, 0.f, 0.f}, dd[3] = {0.f, 0.f, 1.f};
+  if (live) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      oo[a] = o[a * stride + r0 + r];
+      dd[a] = d[a * stride + r0 + r];
+    }
+  }
+  int m = 0;
+  // skip the descent for a wave whose rays are all out of range
+  if (__ballot(live) != 0 && live)
+    m = traverse<false>(nodes, oo, dd, s_max, 0, 0, st_node + threadIdx.x, st_hi + threadIdx.x,
+                        st_lo + threadIdx.x, nullptr, nullptr, nullptr, nullptr);
+  if (live) {
+    uint32_t meff = m <= s_max ? (uint32_t)m : (uint32_t)s_max;
+    uint32_t nper = m == 0 ? 0u : (m <= s_max ? (uint32_t)(s_max / m) : 1u);
+    cnt_iv[r] = meff;
+    cnt_smp[r] = meff * nper;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict__ nodes,
+                                                      const float* __restrict__ o,
+                                                      const float* __restrict__ d, int64_t stride,
+                                                      int64_t r0, uint32_t nr,
+                                                      const uint32_t* __restrict__ cnt_iv,
+                                                      const uint32_t* __restrict__ cnt_smp,
+                                                      const uint32_t* __restrict__ iv_off,
+                                                      float* __restrict__ iv_t0,
+                                                      float* __restrict__ iv_dt,
+                                                      uint32_t* __restrict__ iv_key,
+                                                      uint32_t* __restrict__ iv_ray) {
+  __shared__ int st_node[kStack * kBlock];
+  __shared__ float st_hi[kStack * kBlock];
+  __shared__ float st_lo[kStack * kBlock];
+  uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+  uint32_t meff = r < nr ? cnt_iv[r] : 0u;
+  if (__ballot(meff != 0) == 0 || meff == 0) return;
+  float oo[3], dd[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    oo[a] = o[a * stride + r0 + r];
+    dd[a] = d[a * stride + r0 + r];
+  }
+  uint32_t nper = cnt_smp[r] / meff;
+  uint32_t base = iv_off[r];
+  traverse<true>(nodes, oo, dd, (int)meff, nper, r, st_node + threadIdx.x, st_hi + threadIdx.x,
+                 st_lo + threadIdx.x, iv_t0 + base, iv_dt + base, iv_key + base, iv_ray + base);
+}
+
+}  // namespace
+
+hipError_t launch_trav_count(const DevNode* nodes, const float* o, const float* d,
+                             int64_t ray_stride, int64_t r0, uint32_t nr, int s_max,
+                             uint32_t* cnt_iv, uint32_t* cnt_smp, hipStream_t st) {
+  if (nr == 0) return hipSuccess;
+  uint32_t grid = (nr + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_trav_count, dim3(grid), dim3(kBlock), 0, st, nodes, o, d, ray_stride, r0, nr,
+                     s_max, cnt_iv, cnt_smp);
+  return hipGetLastError();
+}
+
+hipError_t launch_trav_emit(const DevNode* nodes, const float* o, const float* d,
+                            int64_t ray_stride, int64_t r0, uint32_t nr, const uint32_t* cnt_iv,
+                            const uint32_t* cnt_smp, const uint32_t* iv_off, float* iv_t0,
+                            float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray, hipStream_t st) {
+  if (nr == 0) return hipSuccess;
+  uint32_t grid = (nr + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_trav_emit, dim3(grid), dim3(kBlock), 0, st, nodes, o, d, ray_stride, r0, nr,
+                     cnt_iv, cnt_smp, iv_off, iv_t0, iv_dt, iv_key, iv_ray);
+  return hipGetLastError();
+}
+
+}  // namespace amn

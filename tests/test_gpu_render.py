@@ -1,0 +1,246 @@
+"""Parity of the HIP rendering path (through the C ABI) with the FP64 oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from scene_util import Scene, gpu_setup, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2310_01881_amd as am  # noqa: E402
+
+# Tolerances (float32 path vs float64 oracle): rgb and opacity 1e-5 absolute; depth is a
+# weighted sum of t ~ 1.5..3.5, so its float32 rounding scales with t: 4e-5 absolute.
+TOL_RGB = 1e-5
+TOL_DEPTH = 4e-5
+
+
+def inspect(ctx, R):
+    st = am.amnerf_render_stats_get(ctx.h)
+    niv, ns = st["n_intervals"], st["n_samples"]
+    L = None
+    dev = "cuda:0"
+    b = {
+        "ray_iv_off": torch.empty(R + 1, dtype=torch.int32, device=dev),
+        "ray_smp_off": torch.empty(R + 1, dtype=torch.int32, device=dev),
+        "iv_t0": torch.empty(max(niv, 1), dtype=torch.float32, device=dev),
+        "iv_dt": torch.empty(max(niv, 1), dtype=torch.float32, device=dev),
+        "iv_slot": torch.empty(max(niv, 1), dtype=torch.int32, device=dev),
+        "iv_n": torch.empty(max(niv, 1), dtype=torch.int32, device=dev),
+        "perm": torch.empty(max(ns, 1), dtype=torch.int32, device=dev),
+        "sample_out": torch.empty((max(ns, 1), 4), dtype=torch.float32, device=dev),
+    }
+    return st, b
+
+
+def fetch_inspect(ctx, R, n_leaves):
+    st, b = inspect(ctx, R)
+    b["bucket_off"] = torch.empty(n_leaves + 1, dtype=torch.int32, device="cuda:0")
+    am.amnerf_render_inspect(ctx.h, **b)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in b.items()}
+    niv, ns = st["n_intervals"], st["n_samples"]
+    for k in ("iv_t0", "iv_dt", "iv_slot", "iv_n"):
+        out[k] = out[k][:niv]
+    out["perm"] = out["perm"][:ns].view(np.uint32)
+    out["sample_out"] = out["sample_out"][:ns]
+    return st, out
+
+
+def check_intervals_and_sort(scene, o, d, s_max, ins, rays_to_check):
+    """Node ids bit-exact on robust rays; perm and bucket offsets bit-exact everywhere."""
+    R = o.shape[1]
+    t0, t1, slot, m = oracle.trace(scene.otree, o, d, ray_idx=rays_to_check)
+    robust = oracle.robust(scene.otree, o, d, ray_idx=rays_to_check)
+    off = ins["ray_iv_off"].astype(np.int64)
+    n_nonrobust = 0
+    for q, r in enumerate(rays_to_check):
+        a, b = off[r], off[r + 1]
+        meff = min(m[q], s_max)
+        if not robust[q]:
+            n_nonrobust += 1
+            continue
+        assert b - a == meff, (r, b - a, meff)
+        np.testing.assert_array_equal(ins["iv_slot"][a:b], slot[q, :meff])
+        np.testing.assert_allclose(ins["iv_t0"][a:b], t0[q, :meff], rtol=0, atol=2e-6)
+        np.testing.assert_allclose(ins["iv_dt"][a:b], (t1 - t0)[q, :meff], rtol=1e-6, atol=1e-7)
+        if meff:
+            n = s_max // m[q] if m[q] <= s_max else 1
+            assert np.all(ins["iv_n"][a:b] == n)
+    assert n_nonrobust <= max(2, 0.01 * len(rays_to_check))
+    # the sort: ray-major sample keys expanded from intervals, stably sorted
+    keys = np.repeat(ins["iv_slot"], ins["iv_n"])
+    counts, offsets, perm = oracle.buckets(keys, scene.otree.n_leaves)
+    np.testing.assert_array_equal(ins["bucket_off"].view(np.uint32), offsets)
+    np.testing.assert_array_equal(ins["perm"], perm)
+    smp_off = ins["ray_smp_off"].astype(np.int64)
+    assert smp_off[R] == len(keys)
+    return robust
+
+
+def compare_render(scene, out, o, d, s_max, rays_to_check, robust, tol_rgb=TOL_RGB, tol_depth=TOL_DEPTH,
+                   jitter=False, seed=0):
+    cfg = scene.cfg
+    rgb, dep, op, ns, flags = oracle.render(scene.otree, scene.W, cfg.n_hidden, cfg.hidden, o, d, s_max,
+                                            eps=cfg.ert_eps, ray_idx=rays_to_check, jitter=jitter, seed=seed)
+    g_rgb = out["rgb"].cpu().numpy()[rays_to_check]
+    g_dep = out["depth"].cpu().numpy()[rays_to_check]
+    g_op = out["opacity"].cpu().numpy()[rays_to_check]
+    ok = robust & ((flags & oracle.FLAG_ERT_AMBIGUOUS) == 0)
+    assert ok.mean() > 0.98
+    e_rgb = np.abs(g_rgb - rgb)[ok].max()
+    e_op = np.abs(g_op - op)[ok].max()
+    e_dep = np.abs(g_dep - dep)[ok].max()
+    assert e_rgb <= tol_rgb, e_rgb
+    assert e_op <= tol_rgb, e_op
+    assert e_dep <= tol_depth, e_dep
+    return e_rgb, e_op, e_dep
+
+
+def render_all(scene, ctx, tree, mlp, o, d, s_max, **kw):
+    od, dd = to_dev(o), to_dev(d)
+    out = am.render(ctx, tree, mlp, od, dd, s_max, ert_eps=scene.cfg.ert_eps, **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_c1_fp32_parity_full_frame():
+    scene = Scene(synth.C1)
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = scene.camera_rays()
+    R = o.shape[1]
+    print("c1 fp32: rays", R, flush=True)
+    out = render_all(scene, ctx, tree, mlp, o, d, scene.cfg.s_max)
+    st, ins = fetch_inspect(ctx, R, tree.n_leaves)
+    assert st["n_nonfinite"] == 0
+    rays = np.arange(R)
+    robust = check_intervals_and_sort(scene, o, d, scene.cfg.s_max, ins, rays)
+    e = compare_render(scene, out, o, d, scene.cfg.s_max, rays, robust)
+    print("c1 fp32 max err rgb/opacity/depth", e)
+
+
+def test_c1_per_sample_mlp_outputs():
+    """sigma and rgb of every sample (ray-major) against the oracle's per-sample record."""
+    scene = Scene(synth.C1)
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = scene.camera_rays()
+    R = o.shape[1]
+    render_all(scene, ctx, tree, mlp, o, d, scene.cfg.s_max)
+    st, ins = fetch_inspect(ctx, R, tree.n_leaves)
+    smp_off = ins["ray_smp_off"].astype(np.int64)
+    rng = np.random.default_rng(0)
+    for r in rng.choice(R, 200, replace=False):
+        rec = oracle.ray_samples(scene.otree, scene.W, 2, 32, o, d, r, scene.cfg.s_max, eps=0.0)
+        g = ins["sample_out"][smp_off[r]:smp_off[r + 1]]
+        assert len(g) == len(rec["t"])
+        if len(g) == 0:
+            continue
+        # float32 sample positions are within ~1 ulp(t) ~ 2.4e-7 of the oracle's; the highest
+        # encoding frequency (8 pi on p = 2x - 1) turns that into ~1e-5 on pre-activations
+        np.testing.assert_allclose(g[:, 0], rec["sigma"], rtol=2e-5, atol=2e-5)
+        np.testing.assert_allclose(g[:, 1:], rec["rgb"], rtol=0, atol=1e-5)
+
+
+def test_determinism_bit_identical():
+    scene = Scene(synth.C1)
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = scene.camera_rays()
+    a = render_all(scene, ctx, tree, mlp, o, d, 64)
+    b = render_all(scene, ctx, tree, mlp, o, d, 64)
+    for k in ("rgb", "depth", "opacity"):
+        assert torch.equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("s_max", [1, 3, 17, 255])
+def test_sample_budgets_and_clipping(s_max):
+    scene = Scene(synth.scaled(synth.C1, max_depth=6, max_leaves=40))
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = synth.random_rays(3000, 11)
+    R = o.shape[1]
+    out = render_all(scene, ctx, tree, mlp, o, d, s_max)
+    st, ins = fetch_inspect(ctx, R, tree.n_leaves)
+    rays = np.arange(R)
+    robust = check_intervals_and_sort(scene, o, d, s_max, ins, rays)
+    compare_render(scene, out, o, d, s_max, rays, robust)
+
+
+def test_jittered_strata_match_oracle():
+    scene = Scene(synth.C1)
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = scene.camera_rays()
+    R = o.shape[1]
+    out = render_all(scene, ctx, tree, mlp, o, d, 64, jitter=True, seed=1234567)
+    st, ins = fetch_inspect(ctx, R, tree.n_leaves)
+    robust = oracle.robust(scene.otree, o, d)
+    compare_render(scene, out, o, d, 64, np.arange(R), robust, jitter=True, seed=1234567)
+
+
+def test_empty_and_missing_rays():
+    scene = Scene(synth.C1)
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    # zero rays
+    o = np.zeros((3, 0), np.float32)
+    out = render_all(scene, ctx, tree, mlp, o, o, 64)
+    assert out["rgb"].shape == (0, 3)
+    # rays that all miss the box: zero samples, zero outputs
+    o = np.tile(np.array([[3.0], [3.0], [3.0]], np.float32), (1, 300))
+    d = np.tile(np.array([[1.0], [0.0], [0.0]], np.float32), (1, 300))
+    out = render_all(scene, ctx, tree, mlp, o, d, 64)
+    assert am.amnerf_render_stats_get(ctx.h)["n_samples"] == 0
+    assert torch.count_nonzero(out["rgb"]) == 0 and torch.count_nonzero(out["opacity"]) == 0
+
+
+def test_single_leaf_and_max_leaves_trees():
+    for cfg in (synth.scaled(synth.C1, max_depth=0, max_leaves=1),
+                synth.scaled(synth.C2, grid_n=64, max_depth=12, max_leaves=4096, n_hidden=2, hidden=32,
+                             width=48, height=48, s_max=96)):
+        scene = Scene(cfg)
+        ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+        assert tree.n_leaves == cfg.max_leaves
+        o, d = scene.camera_rays()
+        R = o.shape[1]
+        out = render_all(scene, ctx, tree, mlp, o, d, cfg.s_max)
+        st, ins = fetch_inspect(ctx, R, tree.n_leaves)
+        rays = np.arange(R)
+        robust = check_intervals_and_sort(scene, o, d, cfg.s_max, ins, rays)
+        compare_render(scene, out, o, d, cfg.s_max, rays, robust)
+
+
+def test_c2_full_size_sampled_parity_fp32():
+    """800x800, 512 leaves, 4x64 MLPs, S_max 128: the bench workload, checked on sampled rays."""
+    scene = Scene(synth.C2)
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = scene.camera_rays()
+    R = o.shape[1]
+    print("c2 fp32: rays", R, flush=True)
+    out = render_all(scene, ctx, tree, mlp, o, d, 128)
+    st, ins = fetch_inspect(ctx, R, tree.n_leaves)
+    print("c2 stats", st, flush=True)
+    assert st["n_nonfinite"] == 0
+    rng = np.random.default_rng(2)
+    rays = np.sort(rng.choice(R, 1500, replace=False))
+    robust = check_intervals_and_sort(scene, o, d, 128, ins, rays)
+    e = compare_render(scene, out, o, d, 128, rays, robust)
+    print("c2 fp32 max err rgb/opacity/depth", e)
+
+
+def test_c2_bf16_error_report():
+    scene = Scene(synth.C2)
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_BF16)
+    o, d = scene.camera_rays()
+    R = o.shape[1]
+    out = render_all(scene, ctx, tree, mlp, o, d, 128)
+    rng = np.random.default_rng(3)
+    rays = np.sort(rng.choice(R, 1500, replace=False))
+    rgb, dep, op, ns, flags = oracle.render(scene.otree, scene.W, 4, 64, o, d, 128, eps=1e-4, ray_idx=rays)
+    g = out["rgb"].cpu().numpy()[rays]
+    psnr = oracle.psnr(g, rgb)
+    print("c2 bf16 psnr vs oracle %.2f dB, max abs %.3e" % (psnr, np.abs(g - rgb).max()))
+    assert psnr > 35.0
