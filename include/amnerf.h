@@ -234,6 +234,23 @@ typedef struct {
 
 int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* out, void* stream);
 
+/* ---- stage timing -------------------------------------------------------------------- */
+#define AMNERF_STAGE_TRAVERSE 0   /* both traversal passes and the per-ray offset scans */
+#define AMNERF_STAGE_SORT 1       /* slot histogram, scans, stable scatter, bucket/tile offsets */
+#define AMNERF_STAGE_EXPAND 2     /* sorted interval -> per-sample records */
+#define AMNERF_STAGE_MLP 3        /* grouped per-leaf MLP */
+#define AMNERF_STAGE_COMPOSITE 4  /* front-to-back compositing */
+#define AMNERF_N_STAGES 5
+
+/* Turns per-stage timing on or off.  When on, every render records HIP events between
+ * its stages on the render stream (no host synchronisation). */
+int amnerf_ctx_set_timing(amnerf_ctx* ctx, int enable);
+
+/* Waits for the events recorded since the last collection and returns, per stage, the
+ * summed GPU time in milliseconds (host double[AMNERF_N_STAGES]) and the number of
+ * render passes (chunks) timed; then restarts the sums. */
+int amnerf_timing_collect(amnerf_ctx* ctx, double* stage_ms_host, int64_t* n_passes);
+
 #ifdef __cplusplus
 }
 #endif

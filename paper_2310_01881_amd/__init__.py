@@ -3,7 +3,7 @@
 Every function here only marshals arguments for the C ABI in ``include/amnerf.h``; all
 steps of the rendering path run in the library's HIP kernels.  torch is used for device
 memory and streams: tensors are passed by ``data_ptr()``, streams by their handle.
-The library must have been built (``python -m paper_2310_01881_amd.build``); importing
+The library must have been built (``python paper_2310_01881_amd/build.py``); importing
 this module fails loudly if it is missing.
 """
 from __future__ import annotations
@@ -35,8 +35,10 @@ EXPORTS = [
     "amnerf_last_error", "amnerf_version", "amnerf_ctx_create", "amnerf_ctx_destroy",
     "amnerf_build_tree", "amnerf_tree_info_get", "amnerf_tree_export", "amnerf_tree_destroy",
     "amnerf_mlp_param_count", "amnerf_mlp_packed_bytes", "amnerf_mlp_pack", "amnerf_render",
-    "amnerf_render_stats_get", "amnerf_render_inspect",
+    "amnerf_render_stats_get", "amnerf_render_inspect", "amnerf_ctx_set_timing",
+    "amnerf_timing_collect",
 ]
+STAGES = ["traverse", "sort", "expand", "mlp", "composite"]
 
 
 class AmnerfError(RuntimeError):
@@ -90,7 +92,7 @@ class amnerf_inspect(C.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libamnerf.so is not built: run `python -m paper_2310_01881_amd.build` "
+        raise ImportError("libamnerf.so is not built: run `python paper_2310_01881_amd/build.py` "
                           "(there is no CPU fallback)")
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
@@ -111,6 +113,8 @@ def _load():
                                   C.POINTER(amnerf_render_params), C.POINTER(amnerf_render_out), P]
     lib.amnerf_render_stats_get.argtypes = [P, C.POINTER(amnerf_render_stats)]
     lib.amnerf_render_inspect.argtypes = [P, C.POINTER(amnerf_inspect), P]
+    lib.amnerf_ctx_set_timing.argtypes = [P, C.c_int]
+    lib.amnerf_timing_collect.argtypes = [P, P, C.POINTER(C.c_int64)]
     return lib
 
 
@@ -224,6 +228,18 @@ def amnerf_render_stats_get(ctx) -> dict:
 def amnerf_render_inspect(ctx, stream=None, **bufs):
     ins = amnerf_inspect(*[_ptr(bufs.get(k)) for k, _ in amnerf_inspect._fields_])
     _check(_lib.amnerf_render_inspect(ctx, C.byref(ins), _stream(stream)))
+
+
+def amnerf_ctx_set_timing(ctx, enable: bool):
+    _check(_lib.amnerf_ctx_set_timing(ctx, 1 if enable else 0))
+
+
+def amnerf_timing_collect(ctx):
+    """(dict stage -> summed ms, number of timed passes)."""
+    ms = np.zeros(len(STAGES), np.float64)
+    n = C.c_int64()
+    _check(_lib.amnerf_timing_collect(ctx, ms.ctypes.data_as(C.c_void_p), C.byref(n)))
+    return dict(zip(STAGES, ms.tolist())), int(n.value)
 
 
 # ---------------------------------------------------------------------------------------

@@ -1,6 +1,7 @@
 """Builds libamnerf.so (the HIP kernels and the host C ABI) for gfx950, in-tree.
 
-Usage: python -m paper_2310_01881_amd.build [-j N]
+Usage: python paper_2310_01881_amd/build.py [-j N]   (run as a file: importing the package
+loads the library this script builds)
 """
 from __future__ import annotations
 

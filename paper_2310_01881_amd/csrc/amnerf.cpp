@@ -44,8 +44,22 @@ constexpr uint64_t kChunkSamples = 1ull << 28;   // worst-case samples of one re
 // ---------------------------------------------------------------------------------------
 // handles
 // ---------------------------------------------------------------------------------------
+namespace {
+constexpr int kStages = AMNERF_N_STAGES;
+constexpr int kRing = 64;
+struct EvSet {
+  hipEvent_t ev[kStages + 1] = {};
+  bool pending = false;
+};
+}  // namespace
+
 struct amnerf_ctx {
   int device = 0;
+  bool timing = false;
+  std::vector<EvSet> ring;
+  int ring_next = 0;
+  double stage_ms[kStages] = {};
+  int64_t timed_passes = 0;
   size_t cap = 0;
   void* arena = nullptr;
   size_t arena_bytes = 0;
@@ -106,10 +120,65 @@ extern "C" int amnerf_ctx_destroy(amnerf_ctx* ctx) {
   if (!ctx) return AMNERF_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  for (EvSet& s : ctx->ring)
+    for (hipEvent_t e : s.ev)
+      if (e) (void)hipEventDestroy(e);
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->counts) (void)hipFree(ctx->counts);
   if (ctx->counts_host) (void)hipHostFree(ctx->counts_host);
   delete ctx;
+  return AMNERF_OK;
+}
+
+// Folds a completed event set into the stage sums.
+static int drain_set(amnerf_ctx* ctx, EvSet& s) {
+  if (!s.pending) return AMNERF_OK;
+  HIP_TRY(hipEventSynchronize(s.ev[kStages]));
+  for (int k = 0; k < kStages; ++k) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, s.ev[k], s.ev[k + 1]));
+    ctx->stage_ms[k] += ms;
+  }
+  ctx->timed_passes += 1;
+  s.pending = false;
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_ctx_set_timing(amnerf_ctx* ctx, int enable) {
+  if (!ctx) return fail(AMNERF_EINVAL, "amnerf_ctx_set_timing: ctx is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (enable && ctx->ring.empty()) {
+    ctx->ring.resize(kRing);
+    for (EvSet& s : ctx->ring)
+      for (hipEvent_t& e : s.ev) HIP_TRY(hipEventCreate(&e));
+  }
+  ctx->timing = enable != 0;
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_timing_collect(amnerf_ctx* ctx, double* stage_ms, int64_t* n_passes) {
+  if (!ctx || !stage_ms) return fail(AMNERF_EINVAL, "amnerf_timing_collect: null argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  for (EvSet& s : ctx->ring) {
+    int rc = drain_set(ctx, s);
+    if (rc) return rc;
+  }
+  for (int k = 0; k < kStages; ++k) {
+    stage_ms[k] = ctx->stage_ms[k];
+    ctx->stage_ms[k] = 0.0;
+  }
+  if (n_passes) *n_passes = ctx->timed_passes;
+  ctx->timed_passes = 0;
+  return AMNERF_OK;
+}
+
+// Event set for the next timed pass (drained first if it is still pending).
+static int next_set(amnerf_ctx* ctx, EvSet** out) {
+  EvSet& s = ctx->ring[ctx->ring_next];
+  ctx->ring_next = (ctx->ring_next + 1) % kRing;
+  int rc = drain_set(ctx, s);
+  if (rc) return rc;
+  *out = &s;
   return AMNERF_OK;
 }
 
@@ -503,6 +572,13 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   int64_t n_chunks = 0;
   for (int64_t r0 = 0; r0 < R; r0 += (int64_t)chunk, ++n_chunks) {
     const uint32_t nr = (uint32_t)std::min<int64_t>((int64_t)chunk, R - r0);
+    EvSet* ev = nullptr;
+    if (ctx->timing) {
+      rc = next_set(ctx, &ev);
+      if (rc) return rc;
+    }
+    auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev->ev[k], st) : hipSuccess; };
+    HIP_TRY(mark(0));
     HIP_TRY(launch_trav_count(tree->dev_nodes, rays->o_dev, rays->d_dev, R, r0, nr, p->s_max, w.cnt_iv, w.cnt_smp, st));
     HIP_TRY(launch_scan_u32(w.cnt_iv, w.iv_off, nr, nullptr, w.scan_tmp, st));
     HIP_TRY(launch_scan_u32(w.cnt_smp, w.smp_off, nr, nullptr, w.scan_tmp, st));
@@ -510,18 +586,24 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
     HIP_TRY(launch_chunk_begin(ctx->counts, n_iv_dev, st));
     HIP_TRY(launch_trav_emit(tree->dev_nodes, rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
                              w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, st));
+    HIP_TRY(mark(1));
     HIP_TRY(launch_sort_hist(sp, w.iv_key, n_iv_dev, w.mat, st));
     HIP_TRY(launch_scan_u32(w.mat, w.mat_scan, (uint64_t)L * sp.nseg_max, nullptr, w.scan_tmp, st));
     HIP_TRY(launch_sort_scatter(sp, w.iv_key, n_iv_dev, w.mat_scan, w.sidx, w.sn, st));
     HIP_TRY(launch_scan_u32(w.sn, w.ssb, niv_max, n_iv_dev, w.scan_tmp, st));
     HIP_TRY(launch_bucket_tiles(sp, w.mat_scan, w.ssb, w.bucket_off, w.tile_off, ctx->counts, st));
+    HIP_TRY(mark(2));
     HIP_TRY(launch_expand(w.sidx, w.ssb, n_iv_dev, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_off, w.smp_off, r0,
                           jitter, p->jitter_seed, w.srec_ray, w.srec_t, w.perm, st));
+    HIP_TRY(mark(3));
     HIP_TRY(launch_mlp(g, mlp->packed_dev, L, w.bucket_off, w.tile_off, ctx->counts, w.srec_ray, w.srec_t, w.perm,
                        rays->o_dev, rays->d_dev, R, r0, w.smp_out, st));
+    HIP_TRY(mark(4));
     HIP_TRY(launch_composite(nr, w.iv_off, w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.smp_out, r0, jitter,
                              p->jitter_seed, p->ert_eps, out->rgb_dev, out->depth_dev, out->opacity_dev,
                              out->weights_dev, ctx->counts, st));
+    HIP_TRY(mark(5));
+    if (ev) ev->pending = true;
     HIP_TRY(launch_chunk_finish(ctx->counts, w.smp_off + nr, n_iv_dev, st));
   }
   ctx->last_stream = st;
