@@ -219,7 +219,9 @@ int amnerf_render_stats_get(amnerf_ctx* ctx, amnerf_render_stats* out);
  *   bucket_off   uint32[n_leaves+1]    first sorted sample of each leaf bucket, and total
  *   perm         uint32[n_samples]     ray-major index of the sample at each sorted
  *                                      position (the stable sort of samples by slot)
- *   sample_out   float32[n_samples][4] MLP outputs (sigma, r, g, b) in ray-major order */
+ *   sample_out   float32[n_samples][4] MLP output pre-activations (sigma^, r^, g^, b^) in
+ *                                      ray-major order: sigma = softplus(sigma^),
+ *                                      rgb = logistic(r^, g^, b^) */
 typedef struct {
   uint32_t* ray_iv_off;
   uint32_t* ray_smp_off;

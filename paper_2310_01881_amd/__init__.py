@@ -91,6 +91,10 @@ class amnerf_inspect(C.Structure):
 
 
 def _load():
+    # torch bundles its own HIP runtime under the soname libamdhip64.so.7.  Loading torch
+    # first makes this library's dependency resolve to that same runtime, so one process
+    # never holds two HIP/HSA runtimes (device pointers and streams come from torch).
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("libamnerf.so is not built: run `python paper_2310_01881_amd/build.py` "
                           "(there is no CPU fallback)")

@@ -3,8 +3,8 @@
 // uses early termination).
 //
 // Per ray: tau_j = sigma_j delta_j, S_j = sum_{i<j} tau_i accumulated in float32 with
-// Kahan compensation (log-space transmittance), T_j = exp(-S_j),
-// w_j = T_j * (1 - exp(-tau_j)) via expm1, stop after the first j with T_{j+1} < eps.
+// compensation (log-space transmittance), T_j = exp(-S_j), w_j = T_j * (1 - exp(-tau_j))
+// via expm1, stop after the first j with T_{j+1} < eps.
 #include "internal.hpp"
 #include "devcommon.hpp"
 
@@ -13,55 +13,113 @@ namespace {
 
 constexpr int kThreads = 256;
 
+__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+__device__ __forceinline__ float logisticf(float z) { return 1.f / (1.f + expf(-z)); }
+
+// Unevaluated float pair hi + lo (compensated sums).
+struct DF {
+  float hi, lo;
+};
+
+__device__ __forceinline__ DF df_add(DF a, DF b) {
+  float s = a.hi + b.hi;
+  float bb = s - a.hi;
+  float e = (a.hi - (s - bb)) + (b.hi - bb);   // TwoSum error of the high parts
+  e += a.lo + b.lo;
+  float h = s + e;
+  return {h, e - (h - s)};
+}
+
+// exp(-(hi + lo)) for |lo| << 1: exp(-hi) * (1 - lo).
+__device__ __forceinline__ float df_exp_neg(DF a) { return expf(-a.hi) * (1.f - a.lo); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One wave per ray, 64 samples per step.  Lane j of a step handles sample base + j:
+// tau_j, then S_j = sum_{i<j} tau_i by a compensated (float pair) prefix scan across the
+// wave plus the running total of earlier steps; T_j = exp(-S_j), w_j = T_j (1 - e^-tau_j).
+// Early termination: the first lane whose T_{j+1} < eps keeps its sample and later lanes
+// (and steps) contribute nothing.  Samples of a ray have the same count n per interval, so
+// lane j's interval is j / n.
 __global__ __launch_bounds__(kThreads) void k_composite(
     uint32_t nr, const uint32_t* __restrict__ iv_off, const uint32_t* __restrict__ smp_off,
     const float* __restrict__ iv_t0, const float* __restrict__ iv_dt,
     const uint32_t* __restrict__ iv_key, const float* __restrict__ smp_out, int64_t r0, int jitter,
     uint64_t seed, float eps, float* __restrict__ rgb, float* __restrict__ depth,
     float* __restrict__ opac, float* __restrict__ weights, ChunkCounts* __restrict__ counts) {
-  uint32_t r = blockIdx.x * kThreads + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const uint32_t r = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (r >= nr) return;
-  const uint32_t i0 = iv_off[r], i1 = iv_off[r + 1];
-  uint32_t s = smp_off[r];
-  const uint64_t wbase = counts->smp_global;
-  float S = 0.f, comp = 0.f;
+  const uint32_t i0 = iv_off[r], m = iv_off[r + 1] - i0;
+  const uint32_t s0 = smp_off[r], ns = smp_off[r + 1] - s0;
+  const uint64_t wbase = counts->smp_global + s0;
   float cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f, acc = 0.f;
-  bool done = false;
-  for (uint32_t i = i0; i < i1; ++i) {
-    const uint32_t n = key_n(iv_key[i]);
-    const float t0 = iv_t0[i];
-    const float delta = iv_dt[i] / (float)n;
-    const float u = stratum_u(jitter, seed, (uint64_t)(r0 + r), i - i0);
-    for (uint32_t j = 0; j < n; ++j, ++s) {
-      if (done) {
-        if (weights) weights[wbase + s] = 0.f;
-        continue;
+  if (ns > 0) {
+    const uint32_t n = ns / m;
+    DF carry = {0.f, 0.f};
+    bool done = false;
+    for (uint32_t base = 0; base < ns; base += 64) {
+      const uint32_t j = base + lane;
+      const bool valid = !done && j < ns;
+      float tau = 0.f, sig_c[3] = {0.f, 0.f, 0.f}, t = 0.f;
+      if (valid) {
+        const uint32_t k = j / n, jj = j - k * n;
+        const float4 z = *reinterpret_cast<const float4*>(smp_out + 4 * (uint64_t)(s0 + j));
+        const float delta = iv_dt[i0 + k] / (float)n;
+        const float u = stratum_u(jitter, seed, (uint64_t)(r0 + r), k);
+        t = sample_t(iv_t0[i0 + k], delta, jj, u);
+        tau = softplusf(z.x) * delta;       // sigma = softplus, rgb = logistic
+        sig_c[0] = logisticf(z.y);
+        sig_c[1] = logisticf(z.z);
+        sig_c[2] = logisticf(z.w);
       }
-      const float4 v = *reinterpret_cast<const float4*>(smp_out + 4 * (uint64_t)s);
-      const float tau = v.x * delta;
-      const float T = expf(-S);
-      const float w = T * -expm1f(-tau);
-      cr = fmaf(w, v.y, cr);
-      cg = fmaf(w, v.z, cg);
-      cb = fmaf(w, v.w, cb);
-      dep = fmaf(w, sample_t(t0, delta, j, u), dep);
+      // inclusive compensated scan of tau across the wave
+      DF inc = {tau, 0.f};
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        DF y = {__shfl_up(inc.hi, off, 64), __shfl_up(inc.lo, off, 64)};
+        if (lane >= off) inc = df_add(inc, y);
+      }
+      DF exc = {__shfl_up(inc.hi, 1, 64), __shfl_up(inc.lo, 1, 64)};
+      if (lane == 0) exc = {0.f, 0.f};
+      const DF S = df_add(carry, exc);
+      const DF Sn = df_add(carry, inc);
+      float w = valid ? df_exp_neg(S) * -expm1f(-tau) : 0.f;
+      const bool stop = valid && eps > 0.f && df_exp_neg(Sn) < eps;
+      const uint64_t stops = __ballot(stop);
+      if (stops) {
+        const int first = __ffsll((unsigned long long)stops) - 1;
+        if (lane > first) w = 0.f;
+        done = true;
+      }
+      cr = fmaf(w, sig_c[0], cr);
+      cg = fmaf(w, sig_c[1], cg);
+      cb = fmaf(w, sig_c[2], cb);
+      dep = fmaf(w, t, dep);
       acc += w;
-      if (weights) weights[wbase + s] = w;
-      // Kahan-compensated S += tau
-      const float y = tau - comp;
-      const float tsum = S + y;
-      comp = (tsum - S) - y;
-      S = tsum;
-      if (eps > 0.f && expf(-S) < eps) done = true;
+      if (weights && j < ns) weights[wbase + j] = w;
+      carry = {__shfl(Sn.hi, 63, 64), __shfl(Sn.lo, 63, 64)};
+      if (done && !weights) break;
     }
+    cr = wave_sum(cr);
+    cg = wave_sum(cg);
+    cb = wave_sum(cb);
+    dep = wave_sum(dep);
+    acc = wave_sum(acc);
   }
-  rgb[3 * (uint64_t)(r0 + r) + 0] = cr;
-  rgb[3 * (uint64_t)(r0 + r) + 1] = cg;
-  rgb[3 * (uint64_t)(r0 + r) + 2] = cb;
-  if (depth) depth[r0 + r] = dep;
-  if (opac) opac[r0 + r] = acc;
-  if (!isfinite(cr) || !isfinite(cg) || !isfinite(cb) || !isfinite(dep) || !isfinite(acc))
-    atomicAdd(reinterpret_cast<unsigned long long*>(&counts->nonfinite), 1ull);
+  if (lane == 0) {
+    rgb[3 * (uint64_t)(r0 + r) + 0] = cr;
+    rgb[3 * (uint64_t)(r0 + r) + 1] = cg;
+    rgb[3 * (uint64_t)(r0 + r) + 2] = cb;
+    if (depth) depth[r0 + r] = dep;
+    if (opac) opac[r0 + r] = acc;
+    if (!isfinite(cr) || !isfinite(cg) || !isfinite(cb) || !isfinite(dep) || !isfinite(acc))
+      atomicAdd(reinterpret_cast<unsigned long long*>(&counts->nonfinite), 1ull);
+  }
 }
 
 // Records the chunk's totals for the host and advances the global sample base.
@@ -90,7 +148,8 @@ hipError_t launch_composite(uint32_t nr, const uint32_t* iv_off, const uint32_t*
                             float ert_eps, float* rgb, float* depth, float* opac, float* weights,
                             ChunkCounts* counts, hipStream_t st) {
   if (nr == 0) return hipSuccess;
-  uint32_t grid = (nr + kThreads - 1) / kThreads;
+  const uint32_t rays_per_block = kThreads / 64;
+  uint32_t grid = (nr + rays_per_block - 1) / rays_per_block;
   hipLaunchKernelGGL(k_composite, dim3(grid), dim3(kThreads), 0, st, nr, iv_off, smp_off, iv_t0, iv_dt,
                      iv_key, smp_out, r0, jitter, seed, ert_eps, rgb, depth, opac, weights, counts);
   return hipGetLastError();

@@ -56,13 +56,20 @@ Layout make_layout(int nh, int H, int dtype) {
 }
 
 // Input feature held by lane group g in slot i (0..7) of the first layer's B operand, as a
-// column of the master W0[out][30]: sin(2^g pi p) xyz, cos(2^g pi p) xyz, then two of
-// (p_x, p_y, p_z, d_x, d_y, d_z, -, -).  -1 = zero feature.
+// column of the master W0[out][30] (-1 = zero feature).
+// float32: group g holds frequency 2^g: sin(2^g pi p) xyz, cos(2^g pi p) xyz, then two of
+//          (p_x, p_y, p_z, d_x, d_y, d_z, -, -).
+// bfloat16: group g < 3 holds coordinate g at all four frequencies (sin, cos for k = 0..3),
+//          obtained from k = 0 by double-angle steps; group 3 holds p and d.
 __host__ __device__ __forceinline__ int first_layer_col(int g, int i) {
   if (i < 3) return 3 + 6 * g + i;
   if (i < 6) return 3 + 6 * g + 3 + (i - 3);
   int e = 2 * g + (i - 6);
   return e < 3 ? e : (e < 6 ? 27 + (e - 3) : -1);
+}
+__host__ __device__ __forceinline__ int first_layer_col_bf16(int g, int i) {
+  if (g < 3) return 3 + 6 * (i / 2) + 3 * (i % 2) + g;
+  return i < 3 ? i : (i < 6 ? 27 + (i - 3) : -1);
 }
 
 // Master offsets of layer l (din x dout weights then dout biases).
@@ -105,7 +112,7 @@ __global__ void k_mlp_pack(Layout L, int n_leaves, int P, const float* __restric
     float v[8];
     for (int e = 0; e < ne; ++e) {
       int col;
-      if (L.dtype == AMNERF_BF16) col = layer == 0 ? first_layer_col(g, e) : 16 * (2 * ku + e / 4) + 4 * g + (e % 4);
+      if (L.dtype == AMNERF_BF16) col = layer == 0 ? first_layer_col_bf16(g, e) : 16 * (2 * ku + e / 4) + 4 * g + (e % 4);
       else { int kb = 4 * ku + e; col = layer == 0 ? first_layer_col(g, kb) : 16 * ku + 4 * g + e; }
       v[e] = (row < dout && col >= 0) ? W[row * din + col] : 0.f;
     }
@@ -136,19 +143,17 @@ __global__ void k_mlp_pack(Layout L, int n_leaves, int P, const float* __restric
   }
 }
 
-__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
-__device__ __forceinline__ float logisticf(float z) { return 1.f / (1.f + expf(-z)); }
+typedef short s16x8 __attribute__((ext_vector_type(8)));
 
-template <bool BF16>
-__device__ __forceinline__ void sincos_pi(float x, float& s, float& c) {
-  if (BF16) {
-    // hardware sine/cosine take revolutions: sin(2 pi r); here r = x / 2 exactly
-    s = __builtin_amdgcn_sinf(0.5f * x);
-    c = __builtin_amdgcn_cosf(0.5f * x);
-  } else {
-    s = sinpif(x);
-    c = cospif(x);
-  }
+// ReLU of eight values rounded to bfloat16: after the conversion the sign is the top bit,
+// so a packed signed 16-bit max with 0 clears every negative value (and -0).
+__device__ __forceinline__ bf16x8 relu_bf16x8(const float v[8]) {
+  bf16x8 h;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) h[e] = (__bf16)v[e];
+  s16x8 s = __builtin_bit_cast(s16x8, h);
+  s = __builtin_elementwise_max(s, (s16x8)0);
+  return __builtin_bit_cast(bf16x8, s);
 }
 
 template <int H, bool BF16>
@@ -216,17 +221,39 @@ __global__ __launch_bounds__(kThreads) void k_mlp(
       float px = 2.f * fmaf(ts, dx, ox) - 1.f;
       float py = 2.f * fmaf(ts, dy, oy) - 1.f;
       float pz = 2.f * fmaf(ts, dz, oz) - 1.f;
-      float sc = (float)(1 << g);
-      float s0, c0, s1, c1, s2, c2;
-      sincos_pi<BF16>(px * sc, s0, c0);
-      sincos_pi<BF16>(py * sc, s1, c1);
-      sincos_pi<BF16>(pz * sc, s2, c2);
-      feat[cb][0] = s0; feat[cb][1] = s1; feat[cb][2] = s2;
-      feat[cb][3] = c0; feat[cb][4] = c1; feat[cb][5] = c2;
-      float e0 = g == 0 ? px : (g == 1 ? pz : (g == 2 ? dy : 0.f));
-      float e1 = g == 0 ? py : (g == 1 ? dx : (g == 2 ? dz : 0.f));
-      feat[cb][6] = valid[cb] ? e0 : 0.f;
-      feat[cb][7] = valid[cb] ? e1 : 0.f;
+      if (BF16) {
+        // this lane group's coordinate at frequencies 1, 2, 4, 8 (times pi): the hardware
+        // sine takes revolutions, sin(2 pi r) with r = v / 2 exactly; higher frequencies by
+        // sin 2a = 2 sin a cos a, cos 2a = 1 - 2 sin^2 a
+        float v = g == 1 ? py : (g == 2 ? pz : px);
+        float sn = __builtin_amdgcn_sinf(0.5f * v);
+        float cs = __builtin_amdgcn_cosf(0.5f * v);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          feat[cb][2 * k] = sn;
+          feat[cb][2 * k + 1] = cs;
+          float t2 = sn + sn;
+          float s2 = t2 * cs;
+          cs = fmaf(-t2, sn, 1.f);
+          sn = s2;
+        }
+        if (g == 3) {
+          feat[cb][0] = px; feat[cb][1] = py; feat[cb][2] = pz;
+          feat[cb][3] = dx; feat[cb][4] = dy; feat[cb][5] = dz;
+          feat[cb][6] = 0.f; feat[cb][7] = 0.f;
+        }
+      } else {
+        float sc = (float)(1 << g);
+        float s0 = sinpif(px * sc), c0 = cospif(px * sc);
+        float s1 = sinpif(py * sc), c1 = cospif(py * sc);
+        float s2 = sinpif(pz * sc), c2 = cospif(pz * sc);
+        feat[cb][0] = s0; feat[cb][1] = s1; feat[cb][2] = s2;
+        feat[cb][3] = c0; feat[cb][4] = c1; feat[cb][5] = c2;
+        float e0 = g == 0 ? px : (g == 1 ? pz : (g == 2 ? dy : 0.f));
+        float e1 = g == 0 ? py : (g == 1 ? dx : (g == 2 ? dz : 0.f));
+        feat[cb][6] = e0;
+        feat[cb][7] = e1;
+      }
     }
 
     f32x4 acc[NCB][RB];
@@ -269,9 +296,12 @@ __global__ __launch_bounds__(kThreads) void k_mlp(
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-          for (int ku = 0; ku < KUh; ++ku)
+          for (int ku = 0; ku < KUh; ++ku) {
+            float v[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) Bv[cb][ku][e] = (__bf16)fmaxf(acc[cb][2 * ku + e / 4][e % 4], 0.f);
+            for (int e = 0; e < 8; ++e) v[e] = acc[cb][2 * ku + e / 4][e % 4];
+            Bv[cb][ku] = relu_bf16x8(v);
+          }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           if (rb >= nrb) break;
@@ -315,15 +345,12 @@ __global__ __launch_bounds__(kThreads) void k_mlp(
           if (rb < nrb) acc[cb][rb] = nacc[cb][rb];
     }
 
-    // ---- heads: lanes of group 0 hold (sigma^, r^, g^, b^) of their sample ----
+    // ---- lanes of group 0 hold the pre-activations (sigma^, r^, g^, b^) of their sample;
+    //      the compositing kernel applies softplus / logistic ----
     if (g == 0) {
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        if (!valid[cb]) continue;
-        f32x4 z = acc[cb][0];
-        f32x4 r = {softplusf(z[0]), logisticf(z[1]), logisticf(z[2]), logisticf(z[3])};
-        *reinterpret_cast<f32x4*>(out + 4 * (uint64_t)dst_idx[cb]) = r;
-      }
+      for (int cb = 0; cb < NCB; ++cb)
+        if (valid[cb]) *reinterpret_cast<f32x4*>(out + 4 * (uint64_t)dst_idx[cb]) = acc[cb][0];
     }
   }
 }

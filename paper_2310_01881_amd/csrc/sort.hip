@@ -143,6 +143,9 @@ __global__ __launch_bounds__(1024) void k_bucket_tiles(const uint32_t* __restric
   }
 }
 
+// One block per 256 consecutive sorted intervals: their records go to LDS, then the block
+// writes all of their samples with consecutive threads on consecutive sorted positions
+// (each thread finds its interval by binary search over the staged sample bases).
 __global__ __launch_bounds__(kThreads) void k_expand(
     const uint32_t* __restrict__ sidx, const uint32_t* __restrict__ ssb,
     const uint32_t* __restrict__ n_iv_dev, const float* __restrict__ iv_t0,
@@ -150,23 +153,43 @@ __global__ __launch_bounds__(kThreads) void k_expand(
     const uint32_t* __restrict__ iv_ray, const uint32_t* __restrict__ iv_off,
     const uint32_t* __restrict__ smp_off, int64_t r0, int jitter, uint64_t seed,
     uint32_t* __restrict__ srec_ray, float* __restrict__ srec_t, uint32_t* __restrict__ perm) {
+  __shared__ uint32_t sh_base[kThreads + 1];
+  __shared__ uint32_t sh_ray[kThreads], sh_rm[kThreads];
+  __shared__ float sh_t0[kThreads], sh_delta[kThreads], sh_u[kThreads];
   const uint32_t n_iv = *n_iv_dev;
-  for (uint32_t p = blockIdx.x * kThreads + threadIdx.x; p < n_iv; p += gridDim.x * kThreads) {
-    uint32_t i = sidx[p];
-    uint32_t ray = iv_ray[i];
-    uint32_t key = iv_key[i];
-    uint32_t n = key_n(key);
-    uint32_t k = i - iv_off[ray];
-    uint32_t rm = smp_off[ray] + k * n;      // ray-major index of the first sample
-    uint32_t dst = ssb[p];
-    float t0 = iv_t0[i];
-    float delta = iv_dt[i] / (float)n;
-    float u = stratum_u(jitter, seed, (uint64_t)(r0 + ray), k);
-    for (uint32_t j = 0; j < n; ++j) {
-      srec_ray[dst + j] = ray;
-      srec_t[dst + j] = sample_t(t0, delta, j, u);
-      perm[dst + j] = rm + j;
+  const uint32_t n_groups = (n_iv + kThreads - 1) / kThreads;
+  for (uint32_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+    const uint32_t p0 = grp * kThreads;
+    const uint32_t cnt = n_iv - p0 < (uint32_t)kThreads ? n_iv - p0 : (uint32_t)kThreads;
+    const uint32_t p = p0 + threadIdx.x;
+    if (threadIdx.x < cnt) {
+      uint32_t i = sidx[p];
+      uint32_t ray = iv_ray[i];
+      uint32_t n = key_n(iv_key[i]);
+      uint32_t k = i - iv_off[ray];
+      sh_base[threadIdx.x] = ssb[p];
+      sh_ray[threadIdx.x] = ray;
+      sh_rm[threadIdx.x] = smp_off[ray] + k * n;   // ray-major index of the first sample
+      sh_t0[threadIdx.x] = iv_t0[i];
+      sh_delta[threadIdx.x] = iv_dt[i] / (float)n;
+      sh_u[threadIdx.x] = stratum_u(jitter, seed, (uint64_t)(r0 + ray), k);
     }
+    if (threadIdx.x == 0) sh_base[cnt] = ssb[p0 + cnt];
+    __syncthreads();
+    const uint32_t q0 = sh_base[0], q1 = sh_base[cnt];
+    for (uint32_t q = q0 + threadIdx.x; q < q1; q += kThreads) {
+      // largest a with sh_base[a] <= q
+      uint32_t lo = 0, hi = cnt;
+      while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (sh_base[mid] <= q) lo = mid; else hi = mid;
+      }
+      const uint32_t j = q - sh_base[lo];
+      srec_ray[q] = sh_ray[lo];
+      srec_t[q] = sample_t(sh_t0[lo], sh_delta[lo], j, sh_u[lo]);
+      perm[q] = sh_rm[lo] + j;
+    }
+    __syncthreads();
   }
 }
 

@@ -138,7 +138,8 @@ def test_c1_per_sample_mlp_outputs():
     rng = np.random.default_rng(0)
     for r in rng.choice(R, 200, replace=False):
         rec = oracle.ray_samples(scene.otree, scene.W, 2, 32, o, d, r, scene.cfg.s_max, eps=0.0)
-        g = ins["sample_out"][smp_off[r]:smp_off[r + 1]]
+        z = ins["sample_out"][smp_off[r]:smp_off[r + 1]].astype(np.float64)
+        g = np.concatenate([np.logaddexp(0, z[:, :1]), 1 / (1 + np.exp(-z[:, 1:]))], axis=1)
         assert len(g) == len(rec["t"])
         if len(g) == 0:
             continue
