@@ -140,8 +140,9 @@ int amnerf_mlp_packed_bytes(const amnerf_mlp_shape* shape, int32_t dtype, int32_
                             size_t* out);
 
 /* Converts device master parameters float32[n_leaves][P] into the kernel-ready block
- * (matrix-core fragment order, weights in `dtype` rounded to nearest even, biases float32)
- * in the caller's device buffer `packed_dev` of amnerf_mlp_packed_bytes bytes. */
+ * (matrix-core fragment order, weights in `dtype` rounded to nearest even, biases float32;
+ * for AMNERF_BF16 it also holds the transposed weights the backward pass uses) in the
+ * caller's device buffer `packed_dev` of amnerf_mlp_packed_bytes bytes. */
 int amnerf_mlp_pack(amnerf_ctx* ctx, const amnerf_mlp_shape* shape, int32_t dtype,
                     int32_t n_leaves, const float* master_dev, void* packed_dev, void* stream);
 
@@ -252,6 +253,64 @@ int amnerf_ctx_set_timing(amnerf_ctx* ctx, int enable);
  * summed GPU time in milliseconds (host double[AMNERF_N_STAGES]) and the number of
  * render passes (chunks) timed; then restarts the sums. */
 int amnerf_timing_collect(amnerf_ctx* ctx, double* stage_ms_host, int64_t* n_passes);
+
+/* ---- training (not in the paper, which distils its leaf MLPs offline: differentiable
+ *      rendering so the leaf MLPs can be fitted to images) --------------------------------- */
+
+/* Gradient of a scalar loss L with respect to every leaf parameter, given dL/d(outputs) of
+ * the rays of the most recent amnerf_render on this context.  That render must have used
+ * the same tree, MLP (dtype AMNERF_BF16), rays and params and run as a single chunk; its
+ * intermediate arrays are reused, and per-sample activations are recomputed (none are kept
+ * from the forward pass).  Backward through the quadrature: dL/dc_j = w_j g,
+ * dL/dtau_j = T_{j+1} c_j g - g . sum_{i>j} w_i c_i (likewise for depth with t_j and for
+ * opacity with 1), zero after the early-termination sample; then softplus' = logistic,
+ * logistic' = c (1 - c), and the chain rule through the ReLU MLP (bfloat16 operands,
+ * float32 accumulation).
+ *   g_rgb_dev     device float32[n_rays][3]
+ *   g_depth_dev   device float32[n_rays] or NULL (zero)
+ *   g_opacity_dev device float32[n_rays] or NULL (zero)
+ *   grad_dev      device float32[n_leaves][P], overwritten (master parameter layout)
+ * Supported shapes: n_hidden 2 or 4, hidden 32 or 64. */
+int amnerf_render_backward(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
+                           const amnerf_rays* rays, const float* g_rgb_dev,
+                           const float* g_depth_dev, const float* g_opacity_dev,
+                           float* grad_dev, void* stream);
+
+typedef struct {
+  float lr, beta1, beta2, eps;  /* Adam (Kingma & Ba) with bias correction */
+  int32_t step;                 /* 1-based step number */
+} amnerf_adam_params;
+
+/* param -= lr * mhat / (sqrt(vhat) + eps) elementwise on n float32 values, updating the
+ * moments m and v in place (all device arrays of n floats). */
+int amnerf_adam_step(amnerf_ctx* ctx, int64_t n, float* param_dev, float* m_dev, float* v_dev,
+                     const float* grad_dev, const amnerf_adam_params* p, void* stream);
+
+typedef struct {
+  amnerf_mlp_shape shape;
+  int32_t n_leaves;
+  float* master_dev;   /* float32[n_leaves][P] parameters, updated in place */
+  float* grad_dev;     /* float32[n_leaves][P] gradient of the last step (written) */
+  float* m_dev;        /* float32[n_leaves][P] Adam first moments */
+  float* v_dev;        /* float32[n_leaves][P] Adam second moments */
+  void* packed_dev;    /* AMNERF_BF16 packed block (amnerf_mlp_packed_bytes), re-packed */
+} amnerf_mlp_train;
+
+#define AMNERF_GRAD_ONLY 1u   /* compute loss and gradient, skip the Adam update */
+
+typedef struct {
+  amnerf_render_params render;
+  amnerf_adam_params adam;
+  uint32_t flags;           /* AMNERF_GRAD_ONLY */
+} amnerf_train_params;
+
+/* One training step on a batch of rays: bfloat16 render, loss
+ * L = mean over rays and channels of (rgb - target)^2, backward, Adam on the float32
+ * masters, and re-packing of the bfloat16 block.  target_rgb_dev: device float32
+ * [n_rays][3]; loss_dev: device float32[1] receives L. */
+int amnerf_train_step(amnerf_ctx* ctx, const amnerf_tree* tree, amnerf_mlp_train* m,
+                      const amnerf_rays* rays, const float* target_rgb_dev,
+                      const amnerf_train_params* p, float* loss_dev, void* stream);
 
 #ifdef __cplusplus
 }

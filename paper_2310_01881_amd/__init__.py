@@ -36,8 +36,9 @@ EXPORTS = [
     "amnerf_build_tree", "amnerf_tree_info_get", "amnerf_tree_export", "amnerf_tree_destroy",
     "amnerf_mlp_param_count", "amnerf_mlp_packed_bytes", "amnerf_mlp_pack", "amnerf_render",
     "amnerf_render_stats_get", "amnerf_render_inspect", "amnerf_ctx_set_timing",
-    "amnerf_timing_collect",
+    "amnerf_timing_collect", "amnerf_render_backward", "amnerf_adam_step", "amnerf_train_step",
 ]
+AMNERF_GRAD_ONLY = 1
 STAGES = ["traverse", "sort", "expand", "mlp", "composite"]
 
 
@@ -90,6 +91,21 @@ class amnerf_inspect(C.Structure):
                 ("bucket_off", C.c_void_p), ("perm", C.c_void_p), ("sample_out", C.c_void_p)]
 
 
+class amnerf_adam_params(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int32)]
+
+
+class amnerf_mlp_train(C.Structure):
+    _fields_ = [("shape", amnerf_mlp_shape), ("n_leaves", C.c_int32), ("master_dev", C.c_void_p),
+                ("grad_dev", C.c_void_p), ("m_dev", C.c_void_p), ("v_dev", C.c_void_p),
+                ("packed_dev", C.c_void_p)]
+
+
+class amnerf_train_params(C.Structure):
+    _fields_ = [("render", amnerf_render_params), ("adam", amnerf_adam_params), ("flags", C.c_uint32)]
+
+
 def _load():
     # torch bundles its own HIP runtime under the soname libamdhip64.so.7.  Loading torch
     # first makes this library's dependency resolve to that same runtime, so one process
@@ -119,6 +135,10 @@ def _load():
     lib.amnerf_render_inspect.argtypes = [P, C.POINTER(amnerf_inspect), P]
     lib.amnerf_ctx_set_timing.argtypes = [P, C.c_int]
     lib.amnerf_timing_collect.argtypes = [P, P, C.POINTER(C.c_int64)]
+    lib.amnerf_render_backward.argtypes = [P, P, C.POINTER(amnerf_mlp), C.POINTER(amnerf_rays), P, P, P, P, P]
+    lib.amnerf_adam_step.argtypes = [P, C.c_int64, P, P, P, P, C.POINTER(amnerf_adam_params), P]
+    lib.amnerf_train_step.argtypes = [P, P, C.POINTER(amnerf_mlp_train), C.POINTER(amnerf_rays), P,
+                                      C.POINTER(amnerf_train_params), P, P]
     return lib
 
 
@@ -246,6 +266,32 @@ def amnerf_timing_collect(ctx):
     return dict(zip(STAGES, ms.tolist())), int(n.value)
 
 
+def amnerf_render_backward(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, g_rgb_dev, grad_dev, g_depth_dev=None,
+                           g_opacity_dev=None, stream=None):
+    rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]))
+    _check(_lib.amnerf_render_backward(ctx, tree, C.byref(mlp), C.byref(rays), _ptr(g_rgb_dev),
+                                       _ptr(g_depth_dev), _ptr(g_opacity_dev), _ptr(grad_dev),
+                                       _stream(stream)))
+
+
+def amnerf_adam_step(ctx, param_dev, m_dev, v_dev, grad_dev, step, lr=1e-3, beta1=0.9, beta2=0.999,
+                     eps=1e-8, stream=None):
+    prm = amnerf_adam_params(lr, beta1, beta2, eps, step)
+    _check(_lib.amnerf_adam_step(ctx, param_dev.numel(), _ptr(param_dev), _ptr(m_dev), _ptr(v_dev),
+                                 _ptr(grad_dev), C.byref(prm), _stream(stream)))
+
+
+def amnerf_train_step(ctx, tree, train: amnerf_mlp_train, o_dev, d_dev, target_dev, loss_dev, s_max, step,
+                      lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, ert_eps=1e-4, jitter=False, seed=0,
+                      grad_only=False, stream=None):
+    rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]))
+    prm = amnerf_train_params(amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed),
+                              amnerf_adam_params(lr, beta1, beta2, eps, step),
+                              AMNERF_GRAD_ONLY if grad_only else 0)
+    _check(_lib.amnerf_train_step(ctx, tree, C.byref(train), C.byref(rays), _ptr(target_dev), C.byref(prm),
+                                  _ptr(loss_dev), _stream(stream)))
+
+
 # ---------------------------------------------------------------------------------------
 # Convenience objects (still marshalling only)
 # ---------------------------------------------------------------------------------------
@@ -323,3 +369,81 @@ def render(ctx: Context, tree: Tree, mlp: Mlp, o_dev, d_dev, s_max, ert_eps=1e-4
     amnerf_render(ctx.h, tree.h, mlp.desc, o_dev, d_dev, s_max, out["rgb"], out["depth"], out["opacity"],
                   out.get("weights"), ert_eps, jitter, seed, stream)
     return out
+
+
+class Trainer:
+    """Float32 masters, gradient and Adam moments of a leaf-MLP set, plus its bf16 packed block."""
+
+    def __init__(self, ctx: Context, tree: Tree, master_dev, n_hidden, hidden):
+        import torch
+        self.ctx, self.tree = ctx, tree
+        self.master = master_dev.contiguous()
+        self.grad = torch.zeros_like(self.master)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        L = tree.n_leaves
+        nbytes = amnerf_mlp_packed_bytes(n_hidden, hidden, AMNERF_BF16, L)
+        self.packed = torch.empty(nbytes, dtype=torch.uint8, device=self.master.device)
+        amnerf_mlp_pack(ctx.h, n_hidden, hidden, AMNERF_BF16, L, self.master, self.packed)
+        self.desc = amnerf_mlp_train(amnerf_mlp_shape(n_hidden, hidden), L, C.c_void_p(self.master.data_ptr()),
+                                     C.c_void_p(self.grad.data_ptr()), C.c_void_p(self.m.data_ptr()),
+                                     C.c_void_p(self.v.data_ptr()), C.c_void_p(self.packed.data_ptr()))
+        self.mlp = amnerf_mlp(amnerf_mlp_shape(n_hidden, hidden), AMNERF_BF16, L, C.c_void_p(self.packed.data_ptr()))
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.master.device)
+        self.step_no = 0
+
+    def step(self, o_dev, d_dev, target_dev, s_max, lr=1e-3, grad_only=False, **kw):
+        if not grad_only:
+            self.step_no += 1
+        amnerf_train_step(self.ctx.h, self.tree.h, self.desc, o_dev, d_dev, target_dev, self.loss, s_max,
+                          max(self.step_no, 1), lr=lr, grad_only=grad_only, **kw)
+        return self.loss
+
+
+def _render_fn():
+    import torch
+
+    class RenderFn(torch.autograd.Function):
+        """rgb, depth, opacity = RenderFn.apply(master, ctx, tree, o, d, s_max, ert_eps, n_hidden, hidden).
+
+        Forward packs the float32 master parameters to bfloat16 and renders; backward
+        returns dL/dmaster from the library's hand-written backward pass."""
+
+        @staticmethod
+        def forward(fctx, master, ctx, tree, o_dev, d_dev, s_max, ert_eps, n_hidden, hidden):
+            L = tree.n_leaves
+            nbytes = amnerf_mlp_packed_bytes(n_hidden, hidden, AMNERF_BF16, L)
+            packed = torch.empty(nbytes, dtype=torch.uint8, device=master.device)
+            master_c = master.detach().contiguous()
+            amnerf_mlp_pack(ctx.h, n_hidden, hidden, AMNERF_BF16, L, master_c, packed)
+            desc = amnerf_mlp(amnerf_mlp_shape(n_hidden, hidden), AMNERF_BF16, L, C.c_void_p(packed.data_ptr()))
+            R = int(o_dev.shape[1])
+            rgb = torch.empty((R, 3), dtype=torch.float32, device=master.device)
+            depth = torch.empty(R, dtype=torch.float32, device=master.device)
+            opac = torch.empty(R, dtype=torch.float32, device=master.device)
+            amnerf_render(ctx.h, tree.h, desc, o_dev, d_dev, s_max, rgb, depth, opac, None, ert_eps)
+            fctx.keep = (ctx, tree, desc, packed, o_dev, d_dev, master_c)
+            return rgb, depth, opac
+
+        @staticmethod
+        def backward(fctx, g_rgb, g_depth, g_opac):
+            ctx, tree, desc, packed, o_dev, d_dev, master_c = fctx.keep
+            grad = torch.empty_like(master_c)
+            amnerf_render_backward(ctx.h, tree.h, desc, o_dev, d_dev, g_rgb.contiguous(), grad,
+                                   None if g_depth is None else g_depth.contiguous(),
+                                   None if g_opac is None else g_opac.contiguous())
+            return grad, None, None, None, None, None, None, None, None
+
+    return RenderFn
+
+
+class _LazyRenderFn:
+    _fn = None
+
+    def __getattr__(self, name):
+        if _LazyRenderFn._fn is None:
+            _LazyRenderFn._fn = _render_fn()
+        return getattr(_LazyRenderFn._fn, name)
+
+
+RenderFn = _LazyRenderFn()

@@ -74,8 +74,16 @@ struct amnerf_ctx {
   uint64_t last_niv_max = 0, last_ns_max = 0;
   // workspace views of the last chunk
   uint32_t *iv_off = nullptr, *smp_off = nullptr, *iv_key = nullptr, *bucket_off = nullptr,
-           *perm = nullptr;
-  float *iv_t0 = nullptr, *iv_dt = nullptr, *smp_out = nullptr;
+           *perm = nullptr, *tile_off = nullptr, *srec_ray = nullptr;
+  float *iv_t0 = nullptr, *iv_dt = nullptr, *smp_out = nullptr, *srec_t = nullptr;
+  const amnerf_tree* last_tree = nullptr;
+  const void* last_packed = nullptr;
+  int32_t last_dtype = -1;
+  amnerf_render_params last_params = {};
+  const float* last_o = nullptr;
+  // second arena: backward and training buffers
+  void* arena2 = nullptr;
+  size_t arena2_bytes = 0;
 };
 
 struct amnerf_tree {
@@ -124,6 +132,7 @@ extern "C" int amnerf_ctx_destroy(amnerf_ctx* ctx) {
     for (hipEvent_t e : s.ev)
       if (e) (void)hipEventDestroy(e);
   if (ctx->arena) (void)hipFree(ctx->arena);
+  if (ctx->arena2) (void)hipFree(ctx->arena2);
   if (ctx->counts) (void)hipFree(ctx->counts);
   if (ctx->counts_host) (void)hipHostFree(ctx->counts_host);
   delete ctx;
@@ -182,9 +191,23 @@ static int next_set(amnerf_ctx* ctx, EvSet** out) {
   return AMNERF_OK;
 }
 
+static int ensure_arena2(amnerf_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->arena2_bytes) return AMNERF_OK;
+  if (ctx->cap && bytes + ctx->arena_bytes > ctx->cap)
+    return fail(AMNERF_ENOMEM, "workspace needs %zu more bytes, cap is %zu", bytes, ctx->cap);
+  HIP_TRY(hipDeviceSynchronize());
+  if (ctx->arena2) HIP_TRY(hipFree(ctx->arena2));
+  ctx->arena2 = nullptr;
+  ctx->arena2_bytes = 0;
+  hipError_t e = hipMalloc(&ctx->arena2, bytes);
+  if (e != hipSuccess) return fail(AMNERF_ENOMEM, "workspace hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  ctx->arena2_bytes = bytes;
+  return AMNERF_OK;
+}
+
 static int ensure_arena(amnerf_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->arena_bytes) return AMNERF_OK;
-  if (ctx->cap && bytes > ctx->cap)
+  if (ctx->cap && bytes + ctx->arena2_bytes > ctx->cap)
     return fail(AMNERF_ENOMEM, "workspace needs %zu bytes, cap is %zu", bytes, ctx->cap);
   HIP_TRY(hipDeviceSynchronize());
   if (ctx->arena) HIP_TRY(hipFree(ctx->arena));
@@ -466,7 +489,7 @@ extern "C" int amnerf_mlp_packed_bytes(const amnerf_mlp_shape* s, int32_t dtype,
   int rc = check_geom(s, dtype, &g, "amnerf_mlp_packed_bytes");
   if (rc) return rc;
   if (!out || n_leaves < 1 || n_leaves > AMNERF_MAX_LEAVES) return fail(AMNERF_EINVAL, "amnerf_mlp_packed_bytes: bad argument");
-  *out = g.node_bytes * (size_t)n_leaves;
+  *out = (g.node_bytes + g.bwd_node_bytes) * (size_t)n_leaves;
   return AMNERF_OK;
 }
 
@@ -621,6 +644,14 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   ctx->bucket_off = w.bucket_off;
   ctx->perm = w.perm;
   ctx->smp_out = w.smp_out;
+  ctx->tile_off = w.tile_off;
+  ctx->srec_ray = w.srec_ray;
+  ctx->srec_t = w.srec_t;
+  ctx->last_tree = tree;
+  ctx->last_packed = mlp->packed_dev;
+  ctx->last_dtype = mlp->dtype;
+  ctx->last_params = *p;
+  ctx->last_o = rays->o_dev;
   return AMNERF_OK;
 }
 
@@ -679,5 +710,135 @@ extern "C" int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* o, v
     if (o->iv_n && niv) HIP_TRY(hipMemcpy(o->iv_n, nn.data(), 4 * niv, hipMemcpyHostToDevice));
   }
   HIP_TRY(hipStreamSynchronize(st));
+  return AMNERF_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// training
+// ---------------------------------------------------------------------------------------
+namespace {
+
+struct BwdWork {
+  float* gpre;
+  uint32_t* seg_off;
+  float* part;
+  float* rgb;
+  float* g_rgb;
+  float* loss_partial;
+};
+
+size_t carve_bwd(char* base, uint64_t ns, uint64_t L, uint64_t nseg, uint64_t P, uint64_t R, BwdWork& w) {
+  Carve c{base};
+  w.gpre = c.take<float>(4 * ns);
+  w.seg_off = c.take<uint32_t>(L + 1);
+  w.part = c.take<float>(nseg * P);
+  w.rgb = c.take<float>(3 * R);
+  w.g_rgb = c.take<float>(3 * R);
+  w.loss_partial = c.take<float>(loss_partial_words(R));
+  return c.off + 256;
+}
+
+int backward_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp, const amnerf_rays* rays,
+                  const float* g_rgb, const float* g_depth, const float* g_opac, float* grad, hipStream_t st,
+                  BwdWork* w_out) {
+  MlpGeom g;
+  int rc = check_geom(&mlp->shape, mlp->dtype, &g, "amnerf_render_backward");
+  if (rc) return rc;
+  if (mlp->dtype != AMNERF_BF16) return fail(AMNERF_EINVAL, "amnerf_render_backward: the backward pass runs in bfloat16");
+  if (!mlp_bwd_supported(mlp->shape.n_hidden, mlp->shape.hidden))
+    return fail(AMNERF_EINVAL, "amnerf_render_backward: n_hidden must be 2 or 4 (got %d)", mlp->shape.n_hidden);
+  if (!ctx->have_render || ctx->last_tree != tree || ctx->last_packed != mlp->packed_dev ||
+      ctx->last_dtype != mlp->dtype || ctx->last_rays != rays->n_rays || ctx->last_o != rays->o_dev)
+    return fail(AMNERF_ESTATE, "amnerf_render_backward: the last render on this context used other inputs");
+  if (ctx->last_chunks != 1) return fail(AMNERF_ESTATE, "amnerf_render_backward: the last render ran in %lld chunks",
+                                         (long long)ctx->last_chunks);
+  if (!grad || (rays->n_rays > 0 && !g_rgb)) return fail(AMNERF_EINVAL, "amnerf_render_backward: null gradient pointer");
+  const uint64_t L = (uint64_t)tree->n_leaves;
+  const uint64_t P = (uint64_t)amnerf_mlp_param_count(&mlp->shape);
+  const uint64_t ns = ctx->last_ns_max, R = (uint64_t)rays->n_rays;
+  const uint64_t tiles = ns / kMlpTileRows + L;
+  const uint64_t nseg = tiles / kSegTiles + L;
+  BwdWork w;
+  size_t need = carve_bwd(nullptr, ns, L, nseg, P, R, w);
+  rc = ensure_arena2(ctx, need);
+  if (rc) return rc;
+  carve_bwd((char*)ctx->arena2, ns, L, nseg, P, R, w);
+  if (w_out) *w_out = w;
+  const amnerf_render_params& p = ctx->last_params;
+  const int jitter = (p.flags & AMNERF_JITTER) ? 1 : 0;
+  const uint32_t nr = (uint32_t)R;
+  HIP_TRY(launch_comp_bwd(nr, ctx->iv_off, ctx->smp_off, ctx->iv_t0, ctx->iv_dt, ctx->iv_key, ctx->smp_out, 0,
+                          jitter, p.jitter_seed, p.ert_eps, g_rgb, g_depth, g_opac, w.gpre, st));
+  HIP_TRY(launch_seg_offsets(ctx->tile_off, (uint32_t)L, w.seg_off, st));
+  HIP_TRY(launch_mlp_bwd(g, mlp->packed_dev, (uint32_t)L, ctx->bucket_off, ctx->tile_off, w.seg_off, ctx->srec_ray,
+                         ctx->srec_t, ctx->perm, rays->o_dev, rays->d_dev, rays->n_rays, 0, w.gpre, w.part, st));
+  HIP_TRY(launch_grad_reduce(w.part, w.seg_off, (uint32_t)L, (uint32_t)P, grad, st));
+  return AMNERF_OK;
+}
+
+}  // namespace
+
+extern "C" int amnerf_render_backward(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
+                                      const amnerf_rays* rays, const float* g_rgb, const float* g_depth,
+                                      const float* g_opac, float* grad, void* stream) {
+  if (!ctx || !tree || !mlp || !rays) return fail(AMNERF_EINVAL, "amnerf_render_backward: null argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  return backward_impl(ctx, tree, mlp, rays, g_rgb, g_depth, g_opac, grad, (hipStream_t)stream, nullptr);
+}
+
+extern "C" int amnerf_adam_step(amnerf_ctx* ctx, int64_t n, float* param, float* m, float* v, const float* grad,
+                                const amnerf_adam_params* p, void* stream) {
+  if (!ctx || !p || n < 0 || (n > 0 && (!param || !m || !v || !grad)))
+    return fail(AMNERF_EINVAL, "amnerf_adam_step: bad argument");
+  if (p->step < 1 || !(p->lr >= 0.f) || !(p->beta1 >= 0.f && p->beta1 < 1.f) || !(p->beta2 >= 0.f && p->beta2 < 1.f) ||
+      !(p->eps > 0.f))
+    return fail(AMNERF_EINVAL, "amnerf_adam_step: bad hyper-parameters");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(launch_adam(n, param, m, v, grad, p->lr, p->beta1, p->beta2, p->eps, p->step, (hipStream_t)stream));
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_train_step(amnerf_ctx* ctx, const amnerf_tree* tree, amnerf_mlp_train* m,
+                                 const amnerf_rays* rays, const float* target, const amnerf_train_params* p,
+                                 float* loss, void* stream) {
+  if (!ctx || !tree || !m || !rays || !p || !loss || (rays->n_rays > 0 && !target))
+    return fail(AMNERF_EINVAL, "amnerf_train_step: null argument");
+  if (!m->master_dev || !m->grad_dev || !m->m_dev || !m->v_dev || !m->packed_dev)
+    return fail(AMNERF_EINVAL, "amnerf_train_step: null parameter buffer");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  amnerf_mlp mlp;
+  mlp.shape = m->shape;
+  mlp.dtype = AMNERF_BF16;
+  mlp.n_leaves = m->n_leaves;
+  mlp.packed_dev = m->packed_dev;
+  const uint64_t R = (uint64_t)rays->n_rays;
+  // outputs of the forward pass live in the second arena: size it before rendering
+  BwdWork w;
+  {
+    const uint64_t L = (uint64_t)tree->n_leaves;
+    const uint64_t P = (uint64_t)amnerf_mlp_param_count(&m->shape);
+    uint64_t chunk = std::max<uint64_t>(1, kChunkSamples / (uint64_t)std::max(1, p->render.s_max));
+    if (R > chunk) return fail(AMNERF_ECAPACITY, "amnerf_train_step: %llu rays exceed one pass (%llu)",
+                               (unsigned long long)R, (unsigned long long)chunk);
+    const uint64_t ns = std::max<uint64_t>(R, 1) * (uint64_t)std::max(1, p->render.s_max);
+    const uint64_t nseg = (ns / kMlpTileRows + L) / kSegTiles + L;
+    int rc = ensure_arena2(ctx, carve_bwd(nullptr, ns, L, nseg, P, R, w));
+    if (rc) return rc;
+    carve_bwd((char*)ctx->arena2, ns, L, nseg, P, R, w);
+  }
+  amnerf_render_out out = {w.rgb, nullptr, nullptr, nullptr};
+  int rc = amnerf_render(ctx, tree, &mlp, rays, &p->render, &out, stream);
+  if (rc) return rc;
+  HIP_TRY(launch_loss_grad((uint32_t)R, w.rgb, target, w.g_rgb, w.loss_partial, loss, st));
+  rc = backward_impl(ctx, tree, &mlp, rays, w.g_rgb, nullptr, nullptr, m->grad_dev, st, nullptr);
+  if (rc) return rc;
+  if (!(p->flags & AMNERF_GRAD_ONLY)) {
+    const int64_t n = (int64_t)m->n_leaves * amnerf_mlp_param_count(&m->shape);
+    rc = amnerf_adam_step(ctx, n, m->master_dev, m->m_dev, m->v_dev, m->grad_dev, &p->adam, stream);
+    if (rc) return rc;
+    rc = amnerf_mlp_pack(ctx, &m->shape, AMNERF_BF16, m->n_leaves, m->master_dev, m->packed_dev, stream);
+    if (rc) return rc;
+  }
   return AMNERF_OK;
 }

@@ -28,6 +28,7 @@ struct ChunkCounts {
 };
 
 constexpr int kMlpTileRows = 256;       // rows of one MLP work tile (4 waves x 64)
+constexpr int kSegTiles = 16;           // tiles per backward work segment (one leaf)
 constexpr int kScanItems = 2048;        // elements per scan block (256 threads x 8)
 
 // ---- traversal (Algorithm 1: Traverse) -------------------------------------------------
@@ -78,7 +79,8 @@ hipError_t launch_expand(const uint32_t* sidx, const uint32_t* ssb, const uint32
 // ---- grouped per-leaf MLP ---------------------------------------------------------------
 struct MlpGeom {
   int n_hidden, hidden, dtype;
-  size_t node_bytes;    // packed bytes of one leaf
+  size_t node_bytes;      // packed forward bytes of one leaf
+  size_t bwd_node_bytes;  // packed backward bytes of one leaf (bfloat16 only)
 };
 bool mlp_geom(int n_hidden, int hidden, int dtype, MlpGeom* g);
 hipError_t launch_mlp_pack(const MlpGeom& g, int n_leaves, const float* master, void* packed,
@@ -95,6 +97,25 @@ hipError_t launch_composite(uint32_t nr, const uint32_t* iv_off, const uint32_t*
                             const float* smp_out, int64_t r0, int jitter, uint64_t seed,
                             float ert_eps, float* rgb, float* depth, float* opac,
                             float* weights, ChunkCounts* counts, hipStream_t st);
+
+// ---- training ----------------------------------------------------------------------------
+bool mlp_bwd_supported(int n_hidden, int hidden);
+hipError_t launch_comp_bwd(uint32_t nr, const uint32_t* iv_off, const uint32_t* smp_off, const float* iv_t0,
+                           const float* iv_dt, const uint32_t* iv_key, const float* smp_out, int64_t r0,
+                           int jitter, uint64_t seed, float eps, const float* g_rgb, const float* g_depth,
+                           const float* g_opac, float* gpre, hipStream_t st);
+hipError_t launch_seg_offsets(const uint32_t* tile_off, uint32_t n_leaves, uint32_t* seg_off, hipStream_t st);
+hipError_t launch_mlp_bwd(const MlpGeom& g, const void* packed, uint32_t n_leaves, const uint32_t* bucket_off,
+                          const uint32_t* tile_off, const uint32_t* seg_off, const uint32_t* srec_ray,
+                          const float* srec_t, const uint32_t* perm, const float* o, const float* d,
+                          int64_t ray_stride, int64_t r0, const float* gpre, float* part, hipStream_t st);
+hipError_t launch_grad_reduce(const float* part, const uint32_t* seg_off, uint32_t n_leaves, uint32_t P,
+                              float* grad, hipStream_t st);
+size_t loss_partial_words(uint64_t R);
+hipError_t launch_loss_grad(uint32_t R, const float* rgb, const float* target, float* g_rgb, float* partial,
+                            float* loss, hipStream_t st);
+hipError_t launch_adam(int64_t n, float* p, float* m, float* v, const float* g, float lr, float b1, float b2,
+                       float eps, int step, hipStream_t st);
 
 // ---- small helpers ----------------------------------------------------------------------
 hipError_t launch_counts_reset(ChunkCounts* counts, hipStream_t st);

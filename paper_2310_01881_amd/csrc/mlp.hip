@@ -18,73 +18,15 @@
 //   BF16 : v_mfma_f32_16x16x32_bf16 (bf16 in, fp32 accumulate)
 #include "internal.hpp"
 #include "devcommon.hpp"
+#include "mlp_layout.hpp"
 
 #include "../../include/amnerf.h"
 
 namespace amn {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kUnitBytes = 1024;   // one A fragment set: 64 lanes x 16 bytes
-
-struct Layout {
-  int H, nh, dtype, RB, KU0, KUh;
-  int bias_floats, bias_bytes, units;
-  uint32_t bytes;
-  __host__ __device__ int unit_index(int layer, int rb, int ku) const {
-    if (layer == 0) return rb * KU0 + ku;
-    int base = RB * KU0;
-    if (layer < nh) return base + (layer - 1) * RB * KUh + rb * KUh + ku;
-    return base + (nh - 1) * RB * KUh + ku;
-  }
-};
-
-Layout make_layout(int nh, int H, int dtype) {
-  Layout L;
-  L.H = H; L.nh = nh; L.dtype = dtype; L.RB = H / 16;
-  L.KU0 = dtype == AMNERF_BF16 ? 1 : 2;
-  L.KUh = dtype == AMNERF_BF16 ? H / 32 : H / 16;
-  L.bias_floats = nh * H + 16;
-  L.bias_bytes = (L.bias_floats * 4 + 15) / 16 * 16;
-  L.units = L.RB * L.KU0 + (nh - 1) * L.RB * L.KUh + L.KUh;
-  L.bytes = (uint32_t)(L.bias_bytes + L.units * kUnitBytes);
-  return L;
-}
-
-// Input feature held by lane group g in slot i (0..7) of the first layer's B operand, as a
-// column of the master W0[out][30] (-1 = zero feature).
-// float32: group g holds frequency 2^g: sin(2^g pi p) xyz, cos(2^g pi p) xyz, then two of
-//          (p_x, p_y, p_z, d_x, d_y, d_z, -, -).
-// bfloat16: group g < 3 holds coordinate g at all four frequencies (sin, cos for k = 0..3),
-//          obtained from k = 0 by double-angle steps; group 3 holds p and d.
-__host__ __device__ __forceinline__ int first_layer_col(int g, int i) {
-  if (i < 3) return 3 + 6 * g + i;
-  if (i < 6) return 3 + 6 * g + 3 + (i - 3);
-  int e = 2 * g + (i - 6);
-  return e < 3 ? e : (e < 6 ? 27 + (e - 3) : -1);
-}
-__host__ __device__ __forceinline__ int first_layer_col_bf16(int g, int i) {
-  if (g < 3) return 3 + 6 * (i / 2) + 3 * (i % 2) + g;
-  return i < 3 ? i : (i < 6 ? 27 + (i - 3) : -1);
-}
-
-// Master offsets of layer l (din x dout weights then dout biases).
-__device__ __forceinline__ void master_offsets(int nh, int H, int l, int& din, int& dout, int& off_w,
-                                               int& off_b) {
-  int off = 0;
-  for (int k = 0; k < l; ++k) {
-    int di = k == 0 ? 30 : H, dn = k == nh ? 4 : H;
-    off += di * dn + dn;
-  }
-  din = l == 0 ? 30 : H;
-  dout = l == nh ? 4 : H;
-  off_w = off;
-  off_b = off + din * dout;
-}
 
 // One thread per (leaf, unit, lane): 16 bytes of A fragment.  Plus the bias block.
 __global__ void k_mlp_pack(Layout L, int n_leaves, int P, const float* __restrict__ master,
@@ -141,19 +83,32 @@ __global__ void k_mlp_pack(Layout L, int n_leaves, int P, const float* __restric
     }
     ((float*)(packed + (uint64_t)leaf * L.bytes))[j] = val;
   }
-}
-
-typedef short s16x8 __attribute__((ext_vector_type(8)));
-
-// ReLU of eight values rounded to bfloat16: after the conversion the sign is the top bit,
-// so a packed signed 16-bit max with 0 clears every negative value (and -0).
-__device__ __forceinline__ bf16x8 relu_bf16x8(const float v[8]) {
-  bf16x8 h;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) h[e] = (__bf16)v[e];
-  s16x8 s = __builtin_bit_cast(s16x8, h);
-  s = __builtin_elementwise_max(s, (s16x8)0);
-  return __builtin_bit_cast(bf16x8, s);
+  // transposed weights for the backward pass: unit (layer l >= 1, rb, ku), lane (g, m)
+  // holds W_l^T[in = 16 rb + m][out = hidden_col_bf16(ku, g, e)], e = 0..7
+  const uint64_t bper = (uint64_t)L.bwd_units * 64;
+  const uint64_t bt = bper * n_leaves;
+  uint8_t* bwd = packed + (uint64_t)n_leaves * L.bytes;
+  for (uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; id < bt;
+       id += (uint64_t)gridDim.x * blockDim.x) {
+    int leaf = (int)(id / bper);
+    int rem = (int)(id % bper);
+    int unit = rem / 64, lane = rem % 64;
+    int g = lane / 16, m = lane % 16;
+    int per_hidden = L.RB * L.KUh;
+    int layer, rb, ku;
+    if (unit < (L.nh - 1) * per_hidden) { layer = 1 + unit / per_hidden; rb = (unit % per_hidden) / L.KUh; ku = unit % L.KUh; }
+    else { layer = L.nh; rb = unit - (L.nh - 1) * per_hidden; ku = 0; }
+    int din, dout, off_w, off_b;
+    master_offsets(L.nh, L.H, layer, din, dout, off_w, off_b);
+    const float* W = master + (uint64_t)leaf * P + off_w;
+    int in = 16 * rb + m;
+    bf16x8 h;
+    for (int e = 0; e < 8; ++e) {
+      int out = hidden_col_bf16(ku, g, e);
+      h[e] = (__bf16)((out < dout && in < din) ? W[out * din + in] : 0.f);
+    }
+    *(bf16x8*)(bwd + (uint64_t)leaf * L.bwd_bytes + (uint64_t)unit * kUnitBytes + lane * 16) = h;
+  }
 }
 
 template <int H, bool BF16>
@@ -394,17 +349,14 @@ bool mlp_geom(int n_hidden, int hidden, int dtype, MlpGeom* g) {
   g->hidden = hidden;
   g->dtype = dtype;
   g->node_bytes = L.bytes;
+  g->bwd_node_bytes = L.bwd_bytes;
   return true;
 }
 
 hipError_t launch_mlp_pack(const MlpGeom& g, int n_leaves, const float* master, void* packed,
                            hipStream_t st) {
   Layout L = make_layout(g.n_hidden, g.hidden, g.dtype);
-  int P = 0;
-  for (int l = 0; l <= g.n_hidden; ++l) {
-    int di = l == 0 ? 30 : g.hidden, dn = l == g.n_hidden ? 4 : g.hidden;
-    P += di * dn + dn;
-  }
+  int P = master_param_count(g.n_hidden, g.hidden);
   hipLaunchKernelGGL(k_mlp_pack, dim3(1024), dim3(256), 0, st, L, n_leaves, P, master, (uint8_t*)packed);
   return hipGetLastError();
 }

@@ -1,0 +1,337 @@
+// mlp_bwd.hip -- backward pass of the grouped per-leaf MLP (bfloat16 operands, float32
+// accumulation), the differentiable counterpart of the grouped forward in mlp.hip.
+//
+// Work item: a segment of at most kSegTiles consecutive 256-row tiles of one leaf, each
+// processed as two 128-row sub-tiles.  Every wave (32 rows) recomputes its forward
+// activations (none are stored
+// between the forward and backward passes) and keeps each layer's bfloat16 input in
+// registers in B-operand order.  Then, from the output layer down:
+//   * dZ_l (gradient at layer l's pre-activation) and the layer's input H_{l-1} are staged
+//     feature-major in LDS ([feature][128 samples], rows padded by 16 bytes), and the four
+//     waves accumulate dW_l = sum_samples dZ_l H_{l-1}^T on MFMA with K = samples (and
+//     db_l = sum_samples dZ_l against a ones operand);
+//   * dH_{l-1} = W_l^T dZ_l runs on MFMA in registers (transposed weights packed in the
+//     same register-chained order as the forward), then dZ_{l-1} = dH_{l-1} where the
+//     forward activation was positive.
+// Each segment writes its partial dW, db (master layout) to its own slot; a separate
+// kernel sums the slots of each leaf in order, so the gradient is deterministic.
+#include "internal.hpp"
+#include "devcommon.hpp"
+#include "mlp_layout.hpp"
+
+namespace amn {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kNCB = 2;                          // 16-sample column blocks per wave
+constexpr int kTileRows = kMlpTileRows;          // 256-row tiles of the forward pass ...
+constexpr int kSubRows = 4 * 16 * kNCB;          // ... processed as 128-row sub-tiles
+constexpr int kRowBytes = kSubRows * 2 + 16;     // staged feature row (bf16) + padding
+
+__device__ __forceinline__ void stage(uint8_t* base, int row, int col, __bf16 v) {
+  *reinterpret_cast<__bf16*>(base + row * kRowBytes + col * 2) = v;
+}
+__device__ __forceinline__ bf16x8 ld_frag(const uint8_t* base, int row, int col) {
+  return *reinterpret_cast<const bf16x8*>(base + row * kRowBytes + col * 2);
+}
+__device__ __forceinline__ bool pos_bf16(__bf16 v) {
+  return __builtin_bit_cast(short, v) > 0;
+}
+
+template <int H, int NH>
+__global__ __launch_bounds__(kThreads) void k_mlp_bwd(
+    Layout L, const uint8_t* __restrict__ packed_fwd, const uint8_t* __restrict__ packed_bwd,
+    uint32_t n_leaves, const uint32_t* __restrict__ bucket_off,
+    const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ seg_off,
+    const uint32_t* __restrict__ srec_ray, const float* __restrict__ srec_t,
+    const uint32_t* __restrict__ perm, const float* __restrict__ o, const float* __restrict__ d,
+    int64_t stride, int64_t r0, const float* __restrict__ gpre, float* __restrict__ part, int P) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  constexpr int RB = H / 16;
+  constexpr int KUh = H / 32;
+  uint8_t* w_fwd = lds;
+  uint8_t* w_bwd = lds + L.bytes;
+  uint8_t* s_dz = w_bwd + L.bwd_bytes;
+  uint8_t* s_h = s_dz + H * kRowBytes;
+  const float* bias = reinterpret_cast<const float*>(w_fwd);
+  const uint8_t* units = w_fwd + L.bias_bytes;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, m = lane & 15;
+  bf16x8 ones;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.f;
+
+  const uint32_t n_seg = seg_off[n_leaves];
+  int cur = -1;
+  for (uint32_t seg = blockIdx.x; seg < n_seg; seg += gridDim.x) {
+    uint32_t lo = 0, hi = n_leaves;
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (seg_off[mid] <= seg) lo = mid; else hi = mid;
+    }
+    const uint32_t b = lo;
+    const uint32_t t_first = tile_off[b] + (seg - seg_off[b]) * kSegTiles;
+    const uint32_t t_last = t_first + kSegTiles < tile_off[b + 1] ? t_first + kSegTiles : tile_off[b + 1];
+    if ((int)b != cur) {
+      __syncthreads();
+      const f32x4* s1 = reinterpret_cast<const f32x4*>(packed_fwd + (uint64_t)b * L.bytes);
+      for (uint32_t i = tid; i < L.bytes / 16; i += kThreads) reinterpret_cast<f32x4*>(w_fwd)[i] = s1[i];
+      const f32x4* s2 = reinterpret_cast<const f32x4*>(packed_bwd + (uint64_t)b * L.bwd_bytes);
+      for (uint32_t i = tid; i < L.bwd_bytes / 16; i += kThreads) reinterpret_cast<f32x4*>(w_bwd)[i] = s2[i];
+      __syncthreads();
+      cur = (int)b;
+    }
+    f32x4 accW[NH + 1][4];
+    f32x4 accB[NH + 1];
+#pragma unroll
+    for (int l = 0; l <= NH; ++l) {
+      accB[l] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) accW[l][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+
+    for (uint32_t sub = 2 * t_first; sub < 2 * t_last; ++sub) {
+      const uint32_t row0 = bucket_off[b] + (sub - 2 * tile_off[b]) * kSubRows + wave * (16 * kNCB);
+      const uint32_t row_end = bucket_off[b + 1];
+      // ---- forward recompute: layer inputs in B-operand order ----
+      bf16x8 X0[kNCB];
+      bf16x8 Hs[NH + 1][kNCB][KUh];    // Hs[l] = input of layer l (l >= 1), after ReLU
+      f32x4 dz[kNCB][RB];
+#pragma unroll
+      for (int cb = 0; cb < kNCB; ++cb) {
+        const uint32_t row = row0 + cb * 16 + m;
+        const bool valid = row < row_end;
+        uint32_t ray = 0;
+        float ts = 0.f;
+        uint32_t dst = 0;
+        if (valid) {
+          ray = srec_ray[row];
+          ts = srec_t[row];
+          dst = perm[row];
+        }
+        const int64_t ri = r0 + ray;
+        const float ox = o[ri], oy = o[stride + ri], oz = o[2 * stride + ri];
+        const float dx = d[ri], dy = d[stride + ri], dzz = d[2 * stride + ri];
+        const float px = 2.f * fmaf(ts, dx, ox) - 1.f;
+        const float py = 2.f * fmaf(ts, dy, oy) - 1.f;
+        const float pz = 2.f * fmaf(ts, dzz, oz) - 1.f;
+        float feat[8];
+        const float v = g == 1 ? py : (g == 2 ? pz : px);
+        float sn = __builtin_amdgcn_sinf(0.5f * v);
+        float cs = __builtin_amdgcn_cosf(0.5f * v);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          feat[2 * k] = sn;
+          feat[2 * k + 1] = cs;
+          const float t2 = sn + sn;
+          const float s2 = t2 * cs;
+          cs = fmaf(-t2, sn, 1.f);
+          sn = s2;
+        }
+        if (g == 3) {
+          feat[0] = px; feat[1] = py; feat[2] = pz;
+          feat[3] = dx; feat[4] = dy; feat[5] = dzz;
+          feat[6] = 0.f; feat[7] = 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) X0[cb][e] = (__bf16)feat[e];
+        // output-layer gradient: lanes of group 0 hold (dsigma^, dr^, dg^, db^)
+        f32x4 gz = {0.f, 0.f, 0.f, 0.f};
+        if (g == 0 && valid) gz = *reinterpret_cast<const f32x4*>(gpre + 4 * (uint64_t)dst);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) dz[cb][rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        dz[cb][0] = gz;
+      }
+#pragma unroll
+      for (int l = 0; l < NH; ++l) {
+        f32x4 acc[kNCB][RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + l * H + 16 * rb + 4 * g);
+          if (l == 0) {
+            const bf16x8 A = *reinterpret_cast<const bf16x8*>(units + L.unit_index(0, rb, 0) * kUnitBytes + lane * 16);
+#pragma unroll
+            for (int cb = 0; cb < kNCB; ++cb) acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, X0[cb], bv, 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int ku = 0; ku < KUh; ++ku) {
+              const bf16x8 A = *reinterpret_cast<const bf16x8*>(units + L.unit_index(l, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+              for (int cb = 0; cb < kNCB; ++cb)
+                acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Hs[l][cb][ku], ku == 0 ? bv : acc[cb][rb], 0, 0, 0);
+            }
+          }
+        }
+#pragma unroll
+        for (int cb = 0; cb < kNCB; ++cb)
+#pragma unroll
+          for (int ku = 0; ku < KUh; ++ku) {
+            float vv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) vv[e] = acc[cb][2 * ku + e / 4][e % 4];
+            Hs[l + 1][cb][ku] = relu_bf16x8(vv);
+          }
+      }
+
+      // ---- backward, output layer first ----
+#pragma unroll
+      for (int l = NH; l >= 0; --l) {
+        const int rbo = l == NH ? 1 : RB;          // row blocks of this layer's outputs
+        const int cbi = l == 0 ? 2 : RB;           // 16-column blocks of its inputs
+        const int n_items = rbo * cbi;
+        const int per = (n_items + 3) / 4;
+        // stage dZ_l and the layer input, feature-major
+        __syncthreads();
+#pragma unroll
+        for (int cb = 0; cb < kNCB; ++cb) {
+          const int col = wave * (16 * kNCB) + cb * 16 + m;
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            if (rb >= rbo) break;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) stage(s_dz, 16 * rb + 4 * g + i, col, (__bf16)dz[cb][rb][i]);
+          }
+          if (l == 0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) stage(s_h, 8 * g + e, col, X0[cb][e]);
+          } else {
+#pragma unroll
+            for (int ku = 0; ku < KUh; ++ku)
+#pragma unroll
+              for (int e = 0; e < 8; ++e) stage(s_h, hidden_col_bf16(ku, g, e), col, Hs[l][cb][ku][e]);
+          }
+        }
+        __syncthreads();
+        // dW_l += dZ_l H^T, db_l += dZ_l 1 over the sub-tile's 128 samples
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int item = wave * per + q;
+          if (q >= per || item >= n_items) break;
+          const int rb = item / cbi, ci = item % cbi;
+#pragma unroll
+          for (int kb = 0; kb < kSubRows / 32; ++kb) {
+            const bf16x8 A = ld_frag(s_dz, 16 * rb + m, kb * 32 + 8 * g);
+            const bf16x8 Bm = ld_frag(s_h, 16 * ci + m, kb * 32 + 8 * g);
+            accW[l][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bm, accW[l][q], 0, 0, 0);
+            if (ci == 0) accB[l] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, ones, accB[l], 0, 0, 0);
+          }
+        }
+        if (l == 0) break;
+        // dH = W_l^T dZ_l, then the ReLU mask of the forward activation
+        const int ku_n = l == NH ? 1 : KUh;
+        bf16x8 Bz[kNCB][KUh];
+#pragma unroll
+        for (int cb = 0; cb < kNCB; ++cb)
+#pragma unroll
+          for (int ku = 0; ku < KUh; ++ku) {
+            if (ku >= ku_n) break;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int rbs = 2 * ku + e / 4;
+              const float v = (rbs < rbo) ? dz[cb][rbs][e % 4] : 0.f;
+              Bz[cb][ku][e] = (__bf16)v;
+            }
+          }
+        f32x4 dh[kNCB][RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+          for (int ku = 0; ku < KUh; ++ku) {
+            if (ku >= ku_n) break;
+            const bf16x8 A = *reinterpret_cast<const bf16x8*>(w_bwd + L.bwd_unit_index(l, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+            for (int cb = 0; cb < kNCB; ++cb)
+              dh[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  A, Bz[cb][ku], ku == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : dh[cb][rb], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int cb = 0; cb < kNCB; ++cb)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              dz[cb][rb][i] = pos_bf16(Hs[l][cb][rb / 2][4 * (rb % 2) + i]) ? dh[cb][rb][i] : 0.f;
+      }
+    }
+
+    // ---- this segment's partial gradient, master layout ----
+    float* dst = part + (uint64_t)seg * P;
+#pragma unroll
+    for (int l = 0; l <= NH; ++l) {
+      const int rbo = l == NH ? 1 : RB;
+      const int cbi = l == 0 ? 2 : RB;
+      const int n_items = rbo * cbi;
+      const int per = (n_items + 3) / 4;
+      int din, dout, off_w, off_b;
+      master_offsets(NH, H, l, din, dout, off_w, off_b);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int item = wave * per + q;
+        if (q >= per || item >= n_items) break;
+        const int rb = item / cbi, ci = item % cbi;
+        const int c = 16 * ci + m;
+        const int col = l == 0 ? first_layer_col_bf16(c / 8, c % 8) : c;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int out = 16 * rb + 4 * g + i;
+          if (out < dout && col >= 0) dst[off_w + out * din + col] = accW[l][q][i];
+          if (ci == 0 && m == 0 && out < dout) dst[off_b + out] = accB[l][i];
+        }
+      }
+    }
+  }
+}
+
+template <int H, int NH>
+hipError_t launch_bwd_typed(const Layout& L, const void* packed, uint32_t n_leaves,
+                            const uint32_t* bucket_off, const uint32_t* tile_off,
+                            const uint32_t* seg_off, const uint32_t* srec_ray, const float* srec_t,
+                            const uint32_t* perm, const float* o, const float* d, int64_t stride,
+                            int64_t r0, const float* gpre, float* part, hipStream_t st) {
+  auto kern = k_mlp_bwd<H, NH>;
+  const uint32_t lds = L.bytes + L.bwd_bytes + 2u * H * kRowBytes;
+  static int grid = 0;
+  if (grid == 0) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    int dev = 0, ncu = 0, per = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kThreads, lds);
+    if (e != hipSuccess) return e;
+    grid = ncu * (per > 0 ? per : 1);
+  }
+  const uint8_t* pf = (const uint8_t*)packed;
+  const uint8_t* pb = pf + (uint64_t)n_leaves * L.bytes;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, L, pf, pb, n_leaves, bucket_off, tile_off,
+                     seg_off, srec_ray, srec_t, perm, o, d, stride, r0, gpre, part,
+                     master_param_count(NH, H));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool mlp_bwd_supported(int n_hidden, int hidden) {
+  return (n_hidden == 2 || n_hidden == 4) && (hidden == 32 || hidden == 64);
+}
+
+hipError_t launch_mlp_bwd(const MlpGeom& g, const void* packed, uint32_t n_leaves,
+                          const uint32_t* bucket_off, const uint32_t* tile_off, const uint32_t* seg_off,
+                          const uint32_t* srec_ray, const float* srec_t, const uint32_t* perm,
+                          const float* o, const float* d, int64_t ray_stride, int64_t r0,
+                          const float* gpre, float* part, hipStream_t st) {
+  Layout L = make_layout(g.n_hidden, g.hidden, AMNERF_BF16);
+#define AMN_BWD(HH, NN)                                                                          \
+  if (g.hidden == HH && g.n_hidden == NN)                                                        \
+    return launch_bwd_typed<HH, NN>(L, packed, n_leaves, bucket_off, tile_off, seg_off, srec_ray, \
+                                    srec_t, perm, o, d, ray_stride, r0, gpre, part, st);
+  AMN_BWD(64, 4)
+  AMN_BWD(64, 2)
+  AMN_BWD(32, 4)
+  AMN_BWD(32, 2)
+#undef AMN_BWD
+  return hipErrorInvalidValue;
+}
+
+}  // namespace amn
