@@ -63,6 +63,15 @@ def lib():
         _lib.orc_splitmix64.restype = u64
         _lib.orc_stratum_offset.argtypes = [i32, u64, i64, i32]
         _lib.orc_stratum_offset.restype = dbl
+        _lib.orc_render_proposal.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, P, i64, P, i64, i32, dbl,
+                                             dbl, i32, P, P, P, P, P, P, P, i32]
+        _lib.orc_prop_eval.argtypes = [P, i32, i32, P, P, P, i64, P, i64, i32, i64, P, P]
+        _lib.orc_prop_eval.restype = i64
+        _lib.orc_prop_targets.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, P, i64, i32, i64, P]
+        _lib.orc_prop_targets.restype = i64
+        _lib.orc_prop_loss_grad.argtypes = [P, P, P, i64, P]
+        _lib.orc_prop_loss_grad.restype = dbl
+        _lib.orc_prop_param_count.restype = i32
     return _lib
 
 
@@ -227,3 +236,71 @@ def buckets(keys, n_buckets):
 def psnr(a, b, peak=1.0):
     mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
     return float("inf") if mse == 0 else 10.0 * np.log10(peak * peak / mse)
+
+
+# ---------------------------------------------------------------------------------------
+# learned proposal
+# ---------------------------------------------------------------------------------------
+PROP_IN, PROP_H, PROP_BINS = 43, 64, 32
+
+
+def prop_param_count():
+    return int(lib().orc_prop_param_count())
+
+
+def render_proposal(tree: Tree, params, n_hidden, hidden, prop, o, d, s_max, eps=1e-4, mass_thresh=0.99,
+                    cap=48, ray_idx=None, threads=None):
+    """Per ray: rgb, depth, opacity, samples used, plan size (-1 = fallback), plan slots [n][cap], M^."""
+    params = _c(params, np.float32)
+    prop = _c(prop, np.float32)
+    o = _c(o, np.float32); d = _c(d, np.float32)
+    R = o.shape[1]
+    ri, n = _sel(ray_idx, R)
+    rgb = np.zeros((n, 3)); depth = np.zeros(n); opac = np.zeros(n)
+    ns = np.zeros(n, np.int32); pn = np.zeros(n, np.int32); psel = np.zeros((n, cap), np.int32)
+    mass = np.zeros(n)
+    threads = threads or min(16, os.cpu_count() or 1)
+    rc = lib().orc_render_proposal(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(params), params.shape[0],
+                                   n_hidden, hidden, _p(prop), _p(o), _p(d), R, _p(ri), n, s_max, eps,
+                                   mass_thresh, cap, _p(rgb), _p(depth), _p(opac), _p(ns), _p(pn), _p(psel),
+                                   _p(mass), threads)
+    if rc != 0:
+        raise ValueError("orc_render_proposal failed")
+    return rgb, depth, opac, ns, pn, psel, mass
+
+
+def prop_eval(tree: Tree, prop, o, d, s_max, ray_idx=None, cap=1 << 22):
+    """Features [N][43] and predicted bin thicknesses [N][32] of every sampled interval."""
+    prop = _c(prop, np.float32)
+    o = _c(o, np.float32); d = _c(d, np.float32)
+    R = o.shape[1]
+    ri, n = _sel(ray_idx, R)
+    N = int(lib().orc_prop_eval(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(prop), _p(o), _p(d), R, _p(ri), n,
+                                s_max, 0, None, None))
+    feat = np.zeros((N, PROP_IN)); tau = np.zeros((N, PROP_BINS))
+    lib().orc_prop_eval(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(prop), _p(o), _p(d), R, _p(ri), n, s_max,
+                        N, _p(feat), _p(tau))
+    return feat, tau
+
+
+def prop_targets(tree: Tree, params, n_hidden, hidden, o, d, s_max, ray_idx=None):
+    """Bin opacities 1 - exp(-tau_b) of the plain quadrature, [N][32], intervals ray by ray."""
+    params = _c(params, np.float32)
+    o = _c(o, np.float32); d = _c(d, np.float32)
+    R = o.shape[1]
+    ri, n = _sel(ray_idx, R)
+    N = int(lib().orc_prop_targets(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(params), params.shape[0],
+                                   n_hidden, hidden, _p(o), _p(d), R, _p(ri), n, s_max, 0, None))
+    alpha = np.zeros((N, PROP_BINS))
+    lib().orc_prop_targets(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(params), params.shape[0], n_hidden,
+                           hidden, _p(o), _p(d), R, _p(ri), n, s_max, N, _p(alpha))
+    return alpha
+
+
+def prop_loss_grad(prop, feat, alpha):
+    """(loss, gradient[P]) of mean((1 - exp(-tau^) - alpha)^2) over items and bins."""
+    prop = _c(prop, np.float32)
+    feat = _c(feat, np.float64); alpha = _c(alpha, np.float64)
+    grad = np.zeros(prop_param_count())
+    loss = lib().orc_prop_loss_grad(_p(prop), _p(feat), _p(alpha), len(feat), _p(grad))
+    return float(loss), grad

@@ -736,3 +736,350 @@ uint64_t orc_splitmix64(uint64_t x) { return splitmix64(x); }
 double orc_stratum_offset(int jitter, uint64_t seed, int64_t r, int k) {
   return stratum_offset(jitter, seed, r, k);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Learned proposal (not in the paper; it only cites sample-predicting        */
+/* networks as prior art).  Per (ray, leaf interval): 43 features ->          */
+/* 64 -> 64 (ReLU) -> 32 bin optical thicknesses tau^ = softplus(.), bins     */
+/* uniform over the interval.  Compositing the bins front to back along the   */
+/* ray gives the predicted weight histogram over the ray's leaf intervals.    */
+/* ------------------------------------------------------------------------- */
+#define PROP_IN 43
+#define PROP_H 64
+#define PROP_BINS 32
+#define PROP_P (PROP_H * PROP_IN + PROP_H + PROP_H * PROP_H + PROP_H + PROP_BINS * PROP_H + PROP_BINS)
+
+/* [q, d, sin/cos(2^k pi q) k=0,1, sin/cos(2^k pi d) k=0,1, k/S_max, 2*centre-1, size,
+    2*entry-1, 2*exit-1] with q = (o - 1/2)/2; sin block before cos block per k. */
+static void prop_features(const double o[3], const double d[3], double t0, double t1, int k, int s_max,
+                          const int32_t* row, int grid_n, double f[PROP_IN]) {
+  double q[3];
+  int c = 0;
+  for (int a = 0; a < 3; ++a) q[a] = (o[a] - 0.5) * 0.5;
+  for (int a = 0; a < 3; ++a) f[c++] = q[a];
+  for (int a = 0; a < 3; ++a) f[c++] = d[a];
+  for (int src = 0; src < 2; ++src) {
+    const double* v = src == 0 ? q : d;
+    for (int kk = 0; kk < 2; ++kk) {
+      double fr = ldexp(M_PI, kk);
+      for (int a = 0; a < 3; ++a) f[c++] = sin(fr * v[a]);
+      for (int a = 0; a < 3; ++a) f[c++] = cos(fr * v[a]);
+    }
+  }
+  f[c++] = (double)k / (double)s_max;
+  for (int a = 0; a < 3; ++a) f[c++] = (double)(row[2 + a] + row[5 + a]) / (double)grid_n - 1.0;
+  for (int a = 0; a < 3; ++a) f[c++] = (double)(row[5 + a] - row[2 + a]) / (double)grid_n;
+  for (int a = 0; a < 3; ++a) f[c++] = 2.0 * (o[a] + t0 * d[a]) - 1.0;
+  for (int a = 0; a < 3; ++a) f[c++] = 2.0 * (o[a] + t1 * d[a]) - 1.0;
+}
+
+/* acts (optional): z0[64], z1[64], zo[32] pre-activations. */
+static void prop_forward(const double* P, const double f[PROP_IN], double tau[PROP_BINS], double* acts) {
+  const double* W0 = P;
+  const double* b0 = W0 + PROP_H * PROP_IN;
+  const double* W1 = b0 + PROP_H;
+  const double* b1 = W1 + PROP_H * PROP_H;
+  const double* W2 = b1 + PROP_H;
+  const double* b2 = W2 + PROP_BINS * PROP_H;
+  double z0[PROP_H], h0[PROP_H], z1[PROP_H], h1[PROP_H], zo[PROP_BINS];
+  for (int o = 0; o < PROP_H; ++o) {
+    double s = b0[o];
+    for (int i = 0; i < PROP_IN; ++i) s += W0[o * PROP_IN + i] * f[i];
+    z0[o] = s;
+    h0[o] = s > 0.0 ? s : 0.0;
+  }
+  for (int o = 0; o < PROP_H; ++o) {
+    double s = b1[o];
+    for (int i = 0; i < PROP_H; ++i) s += W1[o * PROP_H + i] * h0[i];
+    z1[o] = s;
+    h1[o] = s > 0.0 ? s : 0.0;
+  }
+  for (int o = 0; o < PROP_BINS; ++o) {
+    double s = b2[o];
+    for (int i = 0; i < PROP_H; ++i) s += W2[o * PROP_H + i] * h1[i];
+    zo[o] = s;
+    tau[o] = softplus(s);
+  }
+  if (acts) {
+    memcpy(acts, z0, sizeof(z0));
+    memcpy(acts + PROP_H, z1, sizeof(z1));
+    memcpy(acts + 2 * PROP_H, zo, sizeof(zo));
+  }
+}
+
+/* Length of [a0, a1) intersected with [b0, b1). */
+static double overlap(double a0, double a1, double b0, double b1) {
+  double lo = a0 > b0 ? a0 : b0, hi = a1 < b1 ? a1 : b1;
+  return hi > lo ? hi - lo : 0.0;
+}
+
+typedef struct {
+  int n_sel;          /* selected plain slots (-1: fallback to all plain slots) */
+  int n_plain;        /* plain slots of the ray */
+  double mass;        /* predicted mass M^ = 1 - T^_end */
+} oplan;
+
+/* Slot indices ordered by decreasing p, equal p in increasing index (stable insertion). */
+static void order_desc(const double* p, int n, int* order) {
+  for (int j = 0; j < n; ++j) {
+    int q = j;
+    while (q > 0 && p[order[q - 1]] < p[j]) { order[q] = order[q - 1]; --q; }
+    order[q] = j;
+  }
+}
+
+/* Plan of one ray: predicted slot masses p_j of the plain slots, then the fewest slots of
+   largest p (ties: earlier slot) whose sum reaches mass_thresh * M^, if M^ >= mass_thresh and
+   that set has at most cap slots; otherwise fallback.  sel[] receives the chosen plain slot
+   indices in increasing order. */
+static void plan_ray(const otree* T, const double* PP, const double o[3], const double d[3], const oiv* iv,
+                     int m, int s_max, double mass_thresh, int cap, oplan* pl, int* sel, double* p_out) {
+  pl->n_sel = -1;
+  pl->mass = 0.0;
+  pl->n_plain = 0;
+  if (m == 0) { pl->n_sel = 0; return; }
+  int n = samples_per_interval(m, s_max);
+  int meff = m <= s_max ? m : s_max;
+  pl->n_plain = n * meff;
+  double S = 0.0;
+  double* p = p_out;
+  for (int j = 0; j < pl->n_plain; ++j) p[j] = 0.0;
+  for (int k = 0; k < meff; ++k) {
+    int node = -1;
+    for (int i = 0; i < T->nn; ++i) if (T->rows[(int64_t)i * NODE_COLS + 10] == iv[k].slot) { node = i; break; }
+    double f[PROP_IN], tau[PROP_BINS];
+    prop_features(o, d, iv[k].t0, iv[k].t1, k, s_max, T->rows + (int64_t)node * NODE_COLS, T->grid_n, f);
+    prop_forward(PP, f, tau, NULL);
+    for (int b = 0; b < PROP_BINS; ++b) {
+      double w = exp(-S) * (-expm1(-tau[b]));
+      S += tau[b];
+      /* spread the bin's weight over the plain slots it overlaps */
+      for (int j = 0; j < n; ++j) {
+        double ov = overlap((double)j / n, (double)(j + 1) / n, (double)b / PROP_BINS, (double)(b + 1) / PROP_BINS);
+        p[k * n + j] += w * ov * PROP_BINS;
+      }
+    }
+  }
+  pl->mass = -expm1(-S);
+  if (pl->mass < mass_thresh) return;
+  int* order = (int*)malloc(sizeof(int) * pl->n_plain);
+  order_desc(p, pl->n_plain, order);
+  double target = mass_thresh * pl->mass, acc = 0.0;
+  int cnt = 0;
+  while (cnt < pl->n_plain && acc < target) acc += p[order[cnt++]];
+  if (cnt <= cap && acc >= target) {
+    pl->n_sel = cnt;
+    /* increasing slot order */
+    char* mark = (char*)calloc(pl->n_plain, 1);
+    for (int i = 0; i < cnt; ++i) mark[order[i]] = 1;
+    int c = 0;
+    for (int j = 0; j < pl->n_plain; ++j) if (mark[j]) sel[c++] = j;
+    free(mark);
+  }
+  free(order);
+}
+
+/* Renders rays with the proposal: per ray the plan's slots (plain positions and segment
+   lengths, centred strata) are composited front to back and the other slots are skipped;
+   fallback rays use every plain slot.  Also returns the plan (n_sel per ray, -1 =
+   fallback; sel[ray][cap] slot lists) and the predicted mass. */
+int orc_render_proposal(const int32_t* rows, int nn, int grid_n, const float* params, int n_leaves, int n_hidden,
+                        int hidden, const float* prop_params, const float* o, const float* d, int64_t R,
+                        const int64_t* ray_idx, int64_t n_sel, int s_max, double eps, double mass_thresh, int cap,
+                        double* rgb, double* depth, double* opac, int32_t* n_samples, int32_t* plan_n,
+                        int32_t* plan_sel, double* mass, int n_threads) {
+  if (s_max < 1 || cap < 1) return -1;
+  otree T; olayout L; double* P = NULL; octx C;
+  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden)) {
+    free(P); otree_free(&T); return -1;
+  }
+  double* PP = (double*)malloc(sizeof(double) * PROP_P);
+  for (int i = 0; i < PROP_P; ++i) PP[i] = (double)prop_params[i];
+#pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
+  {
+    oiv* ivbuf = (oiv*)malloc(sizeof(oiv) * (T.n_leaves + 1));
+    osample* sbuf = (osample*)malloc(sizeof(osample) * (s_max + 1));
+    double* p = (double*)malloc(sizeof(double) * (s_max + 1));
+    int* sel = (int*)malloc(sizeof(int) * (s_max + 1));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t s = 0; s < n_sel; ++s) {
+      int64_t r = ray_idx ? ray_idx[s] : s;
+      double oo[3], dd[3];
+      load_ray(o, d, R, r, oo, dd);
+      ivlist IL = {ivbuf, 0, T.n_leaves + 1};
+      int m = trace_ray(&T, oo, dd, &IL);
+      int ns = make_samples(ivbuf, m, s_max, 0, 0, r, sbuf);
+      oplan pl;
+      plan_ray(&T, PP, oo, dd, ivbuf, m, s_max, mass_thresh, cap, &pl, sel, p);
+      int use = pl.n_sel < 0 ? ns : pl.n_sel;
+      double Sacc = 0.0, cr[3] = {0, 0, 0}, dep = 0.0, op = 0.0;
+      for (int q = 0; q < use; ++q) {
+        int j = pl.n_sel < 0 ? q : sel[q];
+        double x[3], u[IN_DIM], out[OUT_DIM];
+        for (int a = 0; a < 3; ++a) x[a] = oo[a] + sbuf[j].t * dd[a];
+        features(x, dd, u);
+        mlp_forward(&L, P + (int64_t)sbuf[j].slot * L.P, u, out, NULL);
+        double tau = out[0] * sbuf[j].delta;
+        double w = exp(-Sacc) * (-expm1(-tau));
+        for (int c = 0; c < 3; ++c) cr[c] += w * out[1 + c];
+        dep += w * sbuf[j].t;
+        op += w;
+        Sacc += tau;
+        if (eps > 0.0 && exp(-Sacc) < eps) break;
+      }
+      for (int c = 0; c < 3; ++c) rgb[3 * s + c] = cr[c];
+      depth[s] = dep;
+      opac[s] = op;
+      if (n_samples) n_samples[s] = use;
+      if (plan_n) plan_n[s] = pl.n_sel;
+      if (plan_sel) for (int q = 0; q < cap; ++q) plan_sel[s * cap + q] = (pl.n_sel >= 0 && q < pl.n_sel) ? sel[q] : -1;
+      if (mass) mass[s] = pl.mass;
+    }
+    free(ivbuf); free(sbuf); free(p); free(sel);
+  }
+  free(PP); free(P);
+  otree_free(&T);
+  return 0;
+}
+
+/* Proposal features and predicted bin thicknesses of every interval of the given rays
+   (front to back, ray by ray): feat[N][43], tau[N][32]; returns N. */
+int64_t orc_prop_eval(const int32_t* rows, int nn, int grid_n, const float* prop_params, const float* o,
+                      const float* d, int64_t R, const int64_t* ray_idx, int64_t n_sel, int s_max, int64_t cap,
+                      double* feat, double* tau) {
+  otree T;
+  if (otree_init(&T, rows, nn, grid_n)) { otree_free(&T); return -1; }
+  double* PP = (double*)malloc(sizeof(double) * PROP_P);
+  for (int i = 0; i < PROP_P; ++i) PP[i] = (double)prop_params[i];
+  oiv* ivbuf = (oiv*)malloc(sizeof(oiv) * (T.n_leaves + 1));
+  int64_t c = 0;
+  for (int64_t s = 0; s < n_sel; ++s) {
+    int64_t r = ray_idx ? ray_idx[s] : s;
+    double oo[3], dd[3];
+    load_ray(o, d, R, r, oo, dd);
+    ivlist IL = {ivbuf, 0, T.n_leaves + 1};
+    int m = trace_ray(&T, oo, dd, &IL);
+    int meff = m <= s_max ? m : s_max;
+    for (int k = 0; k < meff; ++k, ++c) {
+      if (c >= cap) continue;
+      int node = -1;
+      for (int i = 0; i < T.nn; ++i) if (T.rows[(int64_t)i * NODE_COLS + 10] == ivbuf[k].slot) { node = i; break; }
+      double f[PROP_IN], tt[PROP_BINS];
+      prop_features(oo, dd, ivbuf[k].t0, ivbuf[k].t1, k, s_max, T.rows + (int64_t)node * NODE_COLS, grid_n, f);
+      prop_forward(PP, f, tt, NULL);
+      if (feat) memcpy(feat + c * PROP_IN, f, sizeof(f));
+      if (tau) memcpy(tau + c * PROP_BINS, tt, sizeof(tt));
+    }
+  }
+  free(ivbuf); free(PP);
+  otree_free(&T);
+  return c;
+}
+
+/* Training targets of the proposal from the plain render: per interval and bin b, the
+   plain quadrature's optical thickness over the bin, tau_b = sum_j sigma_j |slot_j n bin_b|
+   (lengths in t), as the bin opacity alpha_b = 1 - exp(-tau_b).  Every plain sample counts
+   (targets describe the field, not one ray's early termination).  Returns the count. */
+int64_t orc_prop_targets(const int32_t* rows, int nn, int grid_n, const float* params, int n_leaves, int n_hidden,
+                         int hidden, const float* o, const float* d, int64_t R, const int64_t* ray_idx,
+                         int64_t n_sel, int s_max, int64_t cap, double* alpha) {
+  otree T; olayout L; double* P = NULL; octx C;
+  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden)) {
+    free(P); otree_free(&T); return -1;
+  }
+  oiv* ivbuf = (oiv*)malloc(sizeof(oiv) * (T.n_leaves + 1));
+  osample* sbuf = (osample*)malloc(sizeof(osample) * (s_max + 1));
+  int64_t c = 0;
+  for (int64_t s = 0; s < n_sel; ++s) {
+    int64_t r = ray_idx ? ray_idx[s] : s;
+    double oo[3], dd[3];
+    load_ray(o, d, R, r, oo, dd);
+    ivlist IL = {ivbuf, 0, T.n_leaves + 1};
+    int m = trace_ray(&T, oo, dd, &IL);
+    make_samples(ivbuf, m, s_max, 0, 0, r, sbuf);
+    int n = m == 0 ? 0 : samples_per_interval(m, s_max);
+    int meff = m <= s_max ? m : s_max;
+    for (int k = 0; k < meff; ++k, ++c) {
+      double len = ivbuf[k].t1 - ivbuf[k].t0;
+      double tb[PROP_BINS];
+      for (int b = 0; b < PROP_BINS; ++b) tb[b] = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const osample* sm = &sbuf[k * n + j];
+        double x[3], u[IN_DIM], out[OUT_DIM];
+        for (int a = 0; a < 3; ++a) x[a] = oo[a] + sm->t * dd[a];
+        features(x, dd, u);
+        mlp_forward(&L, P + (int64_t)sm->slot * L.P, u, out, NULL);
+        for (int b = 0; b < PROP_BINS; ++b)
+          tb[b] += out[0] * len * overlap((double)j / n, (double)(j + 1) / n, (double)b / PROP_BINS,
+                                          (double)(b + 1) / PROP_BINS);
+      }
+      if (c < cap) for (int b = 0; b < PROP_BINS; ++b) alpha[c * PROP_BINS + b] = -expm1(-tb[b]);
+    }
+  }
+  free(ivbuf); free(sbuf); free(P);
+  otree_free(&T);
+  return c;
+}
+
+/* Loss L = mean over items and bins of (alpha^ - alpha)^2 with alpha^ = 1 - exp(-tau^), and
+   its gradient w.r.t. the proposal parameters (analytic, float64).  Returns L. */
+double orc_prop_loss_grad(const float* prop_params, const double* feat, const double* alpha, int64_t N,
+                          double* grad) {
+  double* PP = (double*)malloc(sizeof(double) * PROP_P);
+  for (int i = 0; i < PROP_P; ++i) PP[i] = (double)prop_params[i];
+  const double* W1 = PP + PROP_H * PROP_IN + PROP_H;
+  const double* W2 = W1 + PROP_H * PROP_H + PROP_H;
+  double* G0 = grad;
+  double* gb0 = G0 + PROP_H * PROP_IN;
+  double* G1 = gb0 + PROP_H;
+  double* gb1 = G1 + PROP_H * PROP_H;
+  double* G2 = gb1 + PROP_H;
+  double* gb2 = G2 + PROP_BINS * PROP_H;
+  double loss = 0.0;
+  const double scale = 1.0 / ((double)N * PROP_BINS);
+  for (int64_t s = 0; s < N; ++s) {
+    const double* f = feat + s * PROP_IN;
+    double tau[PROP_BINS], acts[2 * PROP_H + PROP_BINS];
+    prop_forward(PP, f, tau, acts);
+    const double* z0 = acts;
+    const double* z1 = acts + PROP_H;
+    const double* zo = acts + 2 * PROP_H;
+    double dzo[PROP_BINS], dh1[PROP_H], dz1[PROP_H], dh0[PROP_H], dz0[PROP_H];
+    for (int b = 0; b < PROP_BINS; ++b) {
+      double ah = -expm1(-tau[b]);
+      double e = ah - alpha[s * PROP_BINS + b];
+      loss += e * e * scale;
+      /* d/dtau (1 - e^-tau) = e^-tau; d tau/d zo = logistic(zo) */
+      dzo[b] = 2.0 * e * scale * exp(-tau[b]) * sigmoid(zo[b]);
+    }
+    for (int b = 0; b < PROP_BINS; ++b) {
+      gb2[b] += dzo[b];
+      for (int i = 0; i < PROP_H; ++i) G2[b * PROP_H + i] += dzo[b] * (z1[i] > 0.0 ? z1[i] : 0.0);
+    }
+    for (int i = 0; i < PROP_H; ++i) {
+      double acc = 0.0;
+      for (int b = 0; b < PROP_BINS; ++b) acc += W2[b * PROP_H + i] * dzo[b];
+      dh1[i] = acc;
+      dz1[i] = z1[i] > 0.0 ? acc : 0.0;
+    }
+    for (int o = 0; o < PROP_H; ++o) {
+      gb1[o] += dz1[o];
+      for (int i = 0; i < PROP_H; ++i) G1[o * PROP_H + i] += dz1[o] * (z0[i] > 0.0 ? z0[i] : 0.0);
+    }
+    for (int i = 0; i < PROP_H; ++i) {
+      double acc = 0.0;
+      for (int o = 0; o < PROP_H; ++o) acc += W1[o * PROP_H + i] * dz1[o];
+      dh0[i] = acc;
+      dz0[i] = z0[i] > 0.0 ? acc : 0.0;
+    }
+    for (int o = 0; o < PROP_H; ++o) {
+      gb0[o] += dz0[o];
+      for (int i = 0; i < PROP_IN; ++i) G0[o * PROP_IN + i] += dz0[o] * f[i];
+    }
+    (void)dh1; (void)dh0;
+  }
+  free(PP);
+  return loss;
+}
+
+int orc_prop_param_count(void) { return PROP_P; }

@@ -305,3 +305,21 @@ def leaf_boxes_from_nodes(nodes: np.ndarray) -> np.ndarray:
     leaves = nodes[nodes[:, 10] >= 0]
     leaves = leaves[np.argsort(leaves[:, 10])]
     return np.ascontiguousarray(leaves[:, 2:8])
+
+
+# ----------------------------------------------------------------------------
+# Proposal network parameters
+# ----------------------------------------------------------------------------
+PROP_DIMS = [(43, 64), (64, 64), (64, 32)]
+
+
+def make_prop_weights(seed: int) -> np.ndarray:
+    """He-normal float32 parameters of the 43 -> 64 -> 64 -> 32 proposal MLP, biases 0.
+
+    Layout as the leaf MLPs: per layer W[out][in] row-major, then b[out]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fi, fo in PROP_DIMS:
+        parts.append((rng.standard_normal((fo, fi)) * math.sqrt(2.0 / fi)).reshape(-1))
+        parts.append(np.zeros(fo))
+    return np.ascontiguousarray(np.concatenate(parts).astype(np.float32))
