@@ -164,12 +164,23 @@ typedef struct {
 /* ---- render (Section 3.5, Algorithm 1; Section 3.1) ----------------------------------- */
 #define AMNERF_JITTER 1u        /* stratified jitter instead of interval-centred samples */
 
+/* Learned proposal used by a render (see amnerf_propose below). */
+typedef struct {
+  int32_t dtype;          /* AMNERF_F32 or AMNERF_BF16 inference */
+  const void* packed_dev; /* block written by amnerf_prop_pack with the same dtype */
+  float mass_thresh;      /* keep slots holding this fraction of the predicted mass; fall
+                             back to all plain slots when the predicted mass is below it */
+  int32_t cap;            /* at most this many kept samples per ray, 1 .. s_max */
+} amnerf_proposal;
+
 typedef struct {
   int32_t s_max;          /* samples per ray budget, 1 .. AMNERF_MAX_SAMPLES */
   float ert_eps;          /* stop after the sample where transmittance drops below this;
                              0 disables early termination */
   uint32_t flags;         /* AMNERF_JITTER */
   uint64_t jitter_seed;   /* seed of the per-interval offsets when AMNERF_JITTER is set */
+  const amnerf_proposal* proposal;  /* NULL: plain sampling; else proposal sampling (the
+                             strata are then centred: AMNERF_JITTER is rejected) */
 } amnerf_render_params;
 
 typedef struct {
@@ -204,6 +215,8 @@ typedef struct {
   int64_t n_tiles;        /* MLP work tiles of the last chunk */
   int64_t n_chunks;
   int64_t n_nonfinite;    /* rays whose rgb, depth or opacity is not finite */
+  int64_t n_fallback;     /* rays rendered with every plain slot under a proposal */
+  int64_t n_plain_samples;/* samples the plain sampler would have taken */
 } amnerf_render_stats;
 
 /* Waits for the last render's stream and reports its totals. */
@@ -311,6 +324,55 @@ typedef struct {
 int amnerf_train_step(amnerf_ctx* ctx, const amnerf_tree* tree, amnerf_mlp_train* m,
                       const amnerf_rays* rays, const float* target_rgb_dev,
                       const amnerf_train_params* p, float* loss_dev, void* stream);
+
+/* ---- learned proposal (not in the paper; it cites sample-predicting networks as prior
+ *      art).  A 43 -> 64 -> 64 -> 32 ReLU MLP maps features of a (ray, leaf interval) --
+ *      (o - 1/2)/2, d, sin/cos(2^k pi .) of both for k = 0, 1, k/S_max, the leaf box centre
+ *      (2c - 1) and size, entry and exit points (2x - 1) -- to the optical thickness
+ *      softplus(.) of 32 equal bins of the interval.  Compositing the bins front to back over
+ *      the ray's intervals gives its predicted weight histogram; plain slot j of an interval
+ *      with n slots receives the weight of the bins it overlaps.  A render keeps the fewest
+ *      slots of largest predicted weight (ties: earlier slot) holding mass_thresh of the
+ *      predicted mass M^ = 1 - T^_end, and skips the others (a subset of the plain
+ *      quadrature); it falls back to every plain slot when M^ < mass_thresh or more than cap
+ *      slots would be needed.  Parameters: float32, per layer W[out][in] then b[out]. ----- */
+#define AMNERF_PROP_BINS 32
+
+int64_t amnerf_prop_param_count(void);
+int amnerf_prop_packed_bytes(int32_t dtype, size_t* out);
+/* Converts the float32 parameters into the kernel-ready block (dtype AMNERF_F32 also holds
+ * the transposed weights the training step uses). */
+int amnerf_prop_pack(amnerf_ctx* ctx, int32_t dtype, const float* master_dev, void* packed_dev,
+                     void* stream);
+
+#define AMNERF_PROPOSE_INFER 0
+#define AMNERF_PROPOSE_TRAIN 1
+
+typedef struct {
+  int32_t mode;             /* AMNERF_PROPOSE_INFER or AMNERF_PROPOSE_TRAIN */
+  int32_t s_max;            /* plain sampling budget the proposal is used with */
+  /* INFER: predicted thicknesses of every sampled interval of the rays, ray-major */
+  int32_t infer_dtype;      /* AMNERF_F32 or AMNERF_BF16 */
+  const void* infer_packed_dev;
+  float* tau_dev;           /* device float32[tau_cap][32] */
+  int64_t tau_cap;
+  /* TRAIN: one Adam step on the loss mean over intervals and bins of
+   * (1 - exp(-tau^_b) - alpha_b)^2, alpha_b = 1 - exp(-sum_j sigma_j |slot_j n bin_b|) from
+   * a plain render of the rays with the scene's leaf MLPs (float32 forward and backward) */
+  float* master_dev;        /* float32[P], updated */
+  float* grad_dev;          /* float32[P], written */
+  float* m_dev;             /* float32[P] Adam moments */
+  float* v_dev;
+  void* packed_dev;         /* AMNERF_F32 block of master_dev, re-packed after the step */
+  amnerf_adam_params adam;
+  float* loss_dev;          /* device float32[1] */
+} amnerf_propose_params;
+
+/* INFER or TRAIN as above.  scene_mlp renders the plain targets (TRAIN only, any dtype).
+ * Asynchronous on the stream except that TRAIN and INFER wait once for the interval count. */
+int amnerf_propose(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* scene_mlp,
+                   const amnerf_rays* rays, const amnerf_propose_params* p, int64_t* n_intervals,
+                   void* stream);
 
 #ifdef __cplusplus
 }

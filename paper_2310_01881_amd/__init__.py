@@ -37,7 +37,10 @@ EXPORTS = [
     "amnerf_mlp_param_count", "amnerf_mlp_packed_bytes", "amnerf_mlp_pack", "amnerf_render",
     "amnerf_render_stats_get", "amnerf_render_inspect", "amnerf_ctx_set_timing",
     "amnerf_timing_collect", "amnerf_render_backward", "amnerf_adam_step", "amnerf_train_step",
+    "amnerf_prop_param_count", "amnerf_prop_packed_bytes", "amnerf_prop_pack", "amnerf_propose",
 ]
+AMNERF_PROPOSE_INFER = 0
+AMNERF_PROPOSE_TRAIN = 1
 AMNERF_GRAD_ONLY = 1
 STAGES = ["traverse", "sort", "expand", "mlp", "composite"]
 
@@ -70,9 +73,13 @@ class amnerf_rays(C.Structure):
     _fields_ = [("o_dev", C.c_void_p), ("d_dev", C.c_void_p), ("n_rays", C.c_int64)]
 
 
+class amnerf_proposal(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("packed_dev", C.c_void_p), ("mass_thresh", C.c_float), ("cap", C.c_int32)]
+
+
 class amnerf_render_params(C.Structure):
     _fields_ = [("s_max", C.c_int32), ("ert_eps", C.c_float), ("flags", C.c_uint32),
-                ("jitter_seed", C.c_uint64)]
+                ("jitter_seed", C.c_uint64), ("proposal", C.POINTER(amnerf_proposal))]
 
 
 class amnerf_render_out(C.Structure):
@@ -82,7 +89,8 @@ class amnerf_render_out(C.Structure):
 
 class amnerf_render_stats(C.Structure):
     _fields_ = [("n_rays", C.c_int64), ("n_intervals", C.c_int64), ("n_samples", C.c_int64),
-                ("n_tiles", C.c_int64), ("n_chunks", C.c_int64), ("n_nonfinite", C.c_int64)]
+                ("n_tiles", C.c_int64), ("n_chunks", C.c_int64), ("n_nonfinite", C.c_int64),
+                ("n_fallback", C.c_int64), ("n_plain_samples", C.c_int64)]
 
 
 class amnerf_inspect(C.Structure):
@@ -104,6 +112,13 @@ class amnerf_mlp_train(C.Structure):
 
 class amnerf_train_params(C.Structure):
     _fields_ = [("render", amnerf_render_params), ("adam", amnerf_adam_params), ("flags", C.c_uint32)]
+
+
+class amnerf_propose_params(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("s_max", C.c_int32), ("infer_dtype", C.c_int32),
+                ("infer_packed_dev", C.c_void_p), ("tau_dev", C.c_void_p), ("tau_cap", C.c_int64),
+                ("master_dev", C.c_void_p), ("grad_dev", C.c_void_p), ("m_dev", C.c_void_p), ("v_dev", C.c_void_p),
+                ("packed_dev", C.c_void_p), ("adam", amnerf_adam_params), ("loss_dev", C.c_void_p)]
 
 
 def _load():
@@ -139,6 +154,11 @@ def _load():
     lib.amnerf_adam_step.argtypes = [P, C.c_int64, P, P, P, P, C.POINTER(amnerf_adam_params), P]
     lib.amnerf_train_step.argtypes = [P, P, C.POINTER(amnerf_mlp_train), C.POINTER(amnerf_rays), P,
                                       C.POINTER(amnerf_train_params), P, P]
+    lib.amnerf_prop_param_count.restype = C.c_int64
+    lib.amnerf_prop_packed_bytes.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+    lib.amnerf_prop_pack.argtypes = [P, C.c_int32, P, P, P]
+    lib.amnerf_propose.argtypes = [P, P, C.POINTER(amnerf_mlp), C.POINTER(amnerf_rays),
+                                   C.POINTER(amnerf_propose_params), C.POINTER(C.c_int64), P]
     return lib
 
 
@@ -235,9 +255,10 @@ def amnerf_mlp_pack(ctx, n_hidden: int, hidden: int, dtype: int, n_leaves: int, 
 
 def amnerf_render(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, s_max: int, rgb_dev, depth_dev=None,
                   opacity_dev=None, weights_dev=None, ert_eps: float = 1e-4, jitter: bool = False,
-                  seed: int = 0, stream=None):
+                  seed: int = 0, stream=None, proposal: "amnerf_proposal" = None):
     rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]) if o_dev is not None else 0)
-    prm = amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed)
+    prm = amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed,
+                               C.pointer(proposal) if proposal is not None else None)
     out = amnerf_render_out(_ptr(rgb_dev), _ptr(depth_dev), _ptr(opacity_dev), _ptr(weights_dev))
     _check(_lib.amnerf_render(ctx, tree, C.byref(mlp), C.byref(rays), C.byref(prm), C.byref(out),
                               _stream(stream)))
@@ -285,11 +306,33 @@ def amnerf_train_step(ctx, tree, train: amnerf_mlp_train, o_dev, d_dev, target_d
                       lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, ert_eps=1e-4, jitter=False, seed=0,
                       grad_only=False, stream=None):
     rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]))
-    prm = amnerf_train_params(amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed),
+    prm = amnerf_train_params(amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed, None),
                               amnerf_adam_params(lr, beta1, beta2, eps, step),
                               AMNERF_GRAD_ONLY if grad_only else 0)
     _check(_lib.amnerf_train_step(ctx, tree, C.byref(train), C.byref(rays), _ptr(target_dev), C.byref(prm),
                                   _ptr(loss_dev), _stream(stream)))
+
+
+def amnerf_prop_param_count() -> int:
+    return int(_lib.amnerf_prop_param_count())
+
+
+def amnerf_prop_packed_bytes(dtype: int) -> int:
+    out = C.c_size_t()
+    _check(_lib.amnerf_prop_packed_bytes(dtype, C.byref(out)))
+    return int(out.value)
+
+
+def amnerf_prop_pack(ctx, dtype, master_dev, packed_dev, stream=None):
+    _check(_lib.amnerf_prop_pack(ctx, dtype, _ptr(master_dev), _ptr(packed_dev), _stream(stream)))
+
+
+def amnerf_propose(ctx, tree, scene_mlp: amnerf_mlp, o_dev, d_dev, params: "amnerf_propose_params", stream=None):
+    rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]))
+    n = C.c_int64()
+    _check(_lib.amnerf_propose(ctx, tree, C.byref(scene_mlp), C.byref(rays), C.byref(params), C.byref(n),
+                               _stream(stream)))
+    return int(n.value)
 
 
 # ---------------------------------------------------------------------------------------
@@ -447,3 +490,49 @@ class _LazyRenderFn:
 
 
 RenderFn = _LazyRenderFn()
+
+
+class Proposal:
+    """Float32 proposal parameters with Adam state, float32 (training) and bf16 packed blocks."""
+
+    def __init__(self, ctx: Context, master_dev):
+        import torch
+        self.ctx = ctx
+        self.master = master_dev.contiguous()
+        self.grad = torch.zeros_like(self.master)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        dev = self.master.device
+        self.packed = {AMNERF_F32: torch.empty(amnerf_prop_packed_bytes(AMNERF_F32), dtype=torch.uint8, device=dev),
+                       AMNERF_BF16: torch.empty(amnerf_prop_packed_bytes(AMNERF_BF16), dtype=torch.uint8, device=dev)}
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.step_no = 0
+        self.repack()
+
+    def repack(self):
+        for dt, buf in self.packed.items():
+            amnerf_prop_pack(self.ctx.h, dt, self.master, buf)
+
+    def descriptor(self, dtype=AMNERF_BF16, mass_thresh=0.99, cap=48):
+        self._desc = amnerf_proposal(dtype, C.c_void_p(self.packed[dtype].data_ptr()), mass_thresh, cap)
+        return self._desc
+
+    def train_step(self, tree: "Tree", scene_mlp: amnerf_mlp, o_dev, d_dev, s_max, lr=1e-3):
+        self.step_no += 1
+        prm = amnerf_propose_params(AMNERF_PROPOSE_TRAIN, s_max, 0, None, None, 0,
+                                    C.c_void_p(self.master.data_ptr()), C.c_void_p(self.grad.data_ptr()),
+                                    C.c_void_p(self.m.data_ptr()), C.c_void_p(self.v.data_ptr()),
+                                    C.c_void_p(self.packed[AMNERF_F32].data_ptr()),
+                                    amnerf_adam_params(lr, 0.9, 0.999, 1e-8, self.step_no),
+                                    C.c_void_p(self.loss.data_ptr()))
+        amnerf_propose(self.ctx.h, tree.h, scene_mlp, o_dev, d_dev, prm)
+        return self.loss
+
+    def infer(self, tree: "Tree", scene_mlp: amnerf_mlp, o_dev, d_dev, s_max, dtype=AMNERF_F32, cap=1 << 22):
+        import torch
+        tau = torch.empty((cap, 32), dtype=torch.float32, device=self.master.device)
+        prm = amnerf_propose_params(AMNERF_PROPOSE_INFER, s_max, dtype, C.c_void_p(self.packed[dtype].data_ptr()),
+                                    C.c_void_p(tau.data_ptr()), cap, None, None, None, None, None,
+                                    amnerf_adam_params(0, 0, 0, 0, 1), None)
+        n = amnerf_propose(self.ctx.h, tree.h, scene_mlp, o_dev, d_dev, prm)
+        return tau[:n]

@@ -72,10 +72,14 @@ struct amnerf_ctx {
   int64_t last_chunks = 0;
   uint32_t last_leaves = 0;
   uint64_t last_niv_max = 0, last_ns_max = 0;
-  // workspace views of the last chunk
-  uint32_t *iv_off = nullptr, *smp_off = nullptr, *iv_key = nullptr, *bucket_off = nullptr,
-           *perm = nullptr, *tile_off = nullptr, *srec_ray = nullptr;
-  float *iv_t0 = nullptr, *iv_dt = nullptr, *smp_out = nullptr, *srec_t = nullptr;
+  // workspace views of the last chunk: the intervals the samples came from (plain or
+  // planned by the proposal) and the sorted sample arrays
+  IvSet use = {};
+  uint32_t *bucket_off = nullptr, *perm = nullptr, *tile_off = nullptr, *srec_ray = nullptr;
+  float *smp_out = nullptr, *srec_t = nullptr;
+  // third arena: proposal stage buffers, sized from the measured interval count
+  void* arena3 = nullptr;
+  size_t arena3_bytes = 0;
   const amnerf_tree* last_tree = nullptr;
   const void* last_packed = nullptr;
   int32_t last_dtype = -1;
@@ -94,6 +98,7 @@ struct amnerf_tree {
   std::vector<int32_t> rows;     // [n][12] sorted by code
   std::vector<uint64_t> mass;
   DevNode* dev_nodes = nullptr;
+  float* dev_leafbox = nullptr;   // per leaf slot: 2*centre-1 (3), size (3), in [0,1] units
 };
 
 // ---------------------------------------------------------------------------------------
@@ -133,6 +138,7 @@ extern "C" int amnerf_ctx_destroy(amnerf_ctx* ctx) {
       if (e) (void)hipEventDestroy(e);
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->arena2) (void)hipFree(ctx->arena2);
+  if (ctx->arena3) (void)hipFree(ctx->arena3);
   if (ctx->counts) (void)hipFree(ctx->counts);
   if (ctx->counts_host) (void)hipHostFree(ctx->counts_host);
   delete ctx;
@@ -202,6 +208,21 @@ static int ensure_arena2(amnerf_ctx* ctx, size_t bytes) {
   hipError_t e = hipMalloc(&ctx->arena2, bytes);
   if (e != hipSuccess) return fail(AMNERF_ENOMEM, "workspace hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
   ctx->arena2_bytes = bytes;
+  return AMNERF_OK;
+}
+
+static int ensure_arena3(amnerf_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->arena3_bytes) return AMNERF_OK;
+  if (ctx->cap && bytes + ctx->arena_bytes + ctx->arena2_bytes > ctx->cap)
+    return fail(AMNERF_ENOMEM, "workspace needs %zu more bytes, cap is %zu", bytes, ctx->cap);
+  HIP_TRY(hipDeviceSynchronize());
+  if (ctx->arena3) HIP_TRY(hipFree(ctx->arena3));
+  ctx->arena3 = nullptr;
+  ctx->arena3_bytes = 0;
+  size_t grow = bytes + bytes / 4;
+  hipError_t e = hipMalloc(&ctx->arena3, grow);
+  if (e != hipSuccess) return fail(AMNERF_ENOMEM, "workspace hipMalloc(%zu): %s", grow, hipGetErrorString(e));
+  ctx->arena3_bytes = grow;
   return AMNERF_OK;
 }
 
@@ -425,11 +446,22 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
       bfs.push_back(l + 1);
     }
   }
+  std::vector<float> box(6 * (size_t)leaves);
+  for (const HNode& nd : nodes) {
+    if (nd.left >= 0) continue;
+    for (int a = 0; a < 3; ++a) {
+      box[6 * nd.slot + a] = (float)(nd.lo[a] + nd.hi[a]) / (float)n - 1.f;
+      box[6 * nd.slot + 3 + a] = (float)(nd.hi[a] - nd.lo[a]) / (float)n;
+    }
+  }
   hipError_t e = hipSetDevice(ctx->device);
   if (e == hipSuccess) e = hipMalloc((void**)&t->dev_nodes, sizeof(DevNode) * dev.size());
   if (e == hipSuccess) e = hipMemcpy(t->dev_nodes, dev.data(), sizeof(DevNode) * dev.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&t->dev_leafbox, sizeof(float) * box.size());
+  if (e == hipSuccess) e = hipMemcpy(t->dev_leafbox, box.data(), sizeof(float) * box.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     if (t->dev_nodes) (void)hipFree(t->dev_nodes);
+    if (t->dev_leafbox) (void)hipFree(t->dev_leafbox);
     delete t;
     return fail(AMNERF_EDEVICE, "amnerf_build_tree: upload: %s", hipGetErrorString(e));
   }
@@ -459,6 +491,7 @@ extern "C" int amnerf_tree_destroy(amnerf_tree* t) {
     (void)hipSetDevice(t->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(t->dev_nodes);
+    if (t->dev_leafbox) (void)hipFree(t->dev_leafbox);
   }
   delete t;
   return AMNERF_OK;
@@ -525,7 +558,7 @@ struct Carve {
 struct Work {
   uint32_t *cnt_iv, *cnt_smp, *iv_off, *smp_off, *scan_tmp;
   float *iv_t0, *iv_dt;
-  uint32_t *iv_key, *iv_ray;
+  uint32_t *iv_key, *iv_ray, *iv_base;
   uint32_t *mat, *mat_scan, *sidx, *sn, *ssb, *bucket_off, *tile_off;
   uint32_t *srec_ray, *perm;
   float *srec_t, *smp_out;
@@ -543,6 +576,7 @@ size_t carve(char* base, uint64_t nr, uint64_t niv, uint64_t ns, const SortPlan&
   w.iv_dt = c.take<float>(niv);
   w.iv_key = c.take<uint32_t>(niv);
   w.iv_ray = c.take<uint32_t>(niv);
+  w.iv_base = c.take<uint32_t>(niv);
   w.mat = c.take<uint32_t>((uint64_t)sp.n_leaves * sp.nseg_max);
   w.mat_scan = c.take<uint32_t>((uint64_t)sp.n_leaves * sp.nseg_max + 1);
   w.sidx = c.take<uint32_t>(niv);
@@ -557,7 +591,50 @@ size_t carve(char* base, uint64_t nr, uint64_t niv, uint64_t ns, const SortPlan&
   return c.off + 256;
 }
 
+// Proposal-stage buffers of one chunk (sized from the measured plain interval count).
+struct PropWork {
+  float* tau;
+  uint32_t *runs, *nsel, *pv_off, *ps_off;
+  uint64_t* mask;
+  float *pt0, *pdt;
+  uint32_t *pkey, *pray, *pbase;
+  uint32_t *mat, *mat_scan, *sidx, *sn, *ssb, *scan_tmp;
+};
+
+size_t carve_prop(char* base, uint64_t nr, uint64_t niv_plain, uint64_t niv_plan, const SortPlan& sp, PropWork& w) {
+  Carve c{base};
+  w.tau = c.take<float>(32 * std::max<uint64_t>(niv_plain, 1));
+  w.runs = c.take<uint32_t>(nr);
+  w.nsel = c.take<uint32_t>(nr);
+  w.pv_off = c.take<uint32_t>(nr + 1);
+  w.ps_off = c.take<uint32_t>(nr + 1);
+  w.mask = c.take<uint64_t>(4 * nr);
+  w.pt0 = c.take<float>(niv_plan);
+  w.pdt = c.take<float>(niv_plan);
+  w.pkey = c.take<uint32_t>(niv_plan);
+  w.pray = c.take<uint32_t>(niv_plan);
+  w.pbase = c.take<uint32_t>(niv_plan);
+  w.mat = c.take<uint32_t>((uint64_t)sp.n_leaves * sp.nseg_max);
+  w.mat_scan = c.take<uint32_t>((uint64_t)sp.n_leaves * sp.nseg_max + 1);
+  w.sidx = c.take<uint32_t>(niv_plan);
+  w.sn = c.take<uint32_t>(niv_plan);
+  w.ssb = c.take<uint32_t>(niv_plan + 1);
+  w.scan_tmp = c.take<uint32_t>(scan_tmp_words(std::max<uint64_t>({nr, niv_plan, (uint64_t)sp.n_leaves * sp.nseg_max})));
+  return c.off + 256;
+}
+
 }  // namespace
+
+static int check_proposal(const amnerf_render_params* p) {
+  if (!p->proposal) return AMNERF_OK;
+  const amnerf_proposal* q = p->proposal;
+  if (!q->packed_dev) return fail(AMNERF_EINVAL, "proposal: packed parameters are NULL");
+  if (q->dtype != AMNERF_F32 && q->dtype != AMNERF_BF16) return fail(AMNERF_EINVAL, "proposal: bad dtype %d", q->dtype);
+  if (!(q->mass_thresh > 0.f)) return fail(AMNERF_EINVAL, "proposal: mass_thresh must be > 0");
+  if (q->cap < 1 || q->cap > p->s_max) return fail(AMNERF_EINVAL, "proposal: cap %d out of [1, s_max]", q->cap);
+  if (p->flags & AMNERF_JITTER) return fail(AMNERF_EINVAL, "proposal sampling uses centred strata (no jitter)");
+  return AMNERF_OK;
+}
 
 extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
                              const amnerf_rays* rays, const amnerf_render_params* p,
@@ -576,6 +653,8 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
     return fail(AMNERF_EINVAL, "amnerf_render: s_max %d out of [1, %d]", p->s_max, AMNERF_MAX_SAMPLES);
   if (!(p->ert_eps >= 0.f) || !(p->ert_eps < 1.f)) return fail(AMNERF_EINVAL, "amnerf_render: ert_eps must be in [0, 1)");
   if (tree->device != ctx->device) return fail(AMNERF_EINVAL, "amnerf_render: tree lives on another device");
+  rc = check_proposal(p);
+  if (rc) return rc;
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const int64_t R = rays->n_rays;
@@ -593,6 +672,8 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   carve((char*)ctx->arena, chunk, niv_max, ns_max, sp, w);
   HIP_TRY(launch_counts_reset(ctx->counts, st));
   int64_t n_chunks = 0;
+  IvSet use = {};
+  uint32_t *mat = w.mat, *mat_scan = w.mat_scan, *sidx = w.sidx, *sn = w.sn, *ssb = w.ssb, *scan_tmp = w.scan_tmp;
   for (int64_t r0 = 0; r0 < R; r0 += (int64_t)chunk, ++n_chunks) {
     const uint32_t nr = (uint32_t)std::min<int64_t>((int64_t)chunk, R - r0);
     EvSet* ev = nullptr;
@@ -605,29 +686,56 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
     HIP_TRY(launch_trav_count(tree->dev_nodes, rays->o_dev, rays->d_dev, R, r0, nr, p->s_max, w.cnt_iv, w.cnt_smp, st));
     HIP_TRY(launch_scan_u32(w.cnt_iv, w.iv_off, nr, nullptr, w.scan_tmp, st));
     HIP_TRY(launch_scan_u32(w.cnt_smp, w.smp_off, nr, nullptr, w.scan_tmp, st));
-    const uint32_t* n_iv_dev = w.iv_off + nr;
-    HIP_TRY(launch_chunk_begin(ctx->counts, n_iv_dev, st));
     HIP_TRY(launch_trav_emit(tree->dev_nodes, rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
-                             w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, st));
+                             w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, st));
+    const IvSet plain = {w.iv_off, w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, w.iv_off + nr};
+    use = plain;
+    SortPlan spu = sp;
+    mat = w.mat; mat_scan = w.mat_scan; sidx = w.sidx; sn = w.sn; ssb = w.ssb; scan_tmp = w.scan_tmp;
+    uint64_t niv_use_max = niv_max;
+    if (p->proposal) {
+      // the proposal buffers are sized from the plain interval count: wait for it once
+      uint32_t niv_plain = 0;
+      HIP_TRY(hipMemcpyAsync(&ctx->counts_host->n_iv, w.iv_off + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      niv_plain = ctx->counts_host->n_iv;
+      const amnerf_proposal* q = p->proposal;
+      const uint64_t niv_plan = (uint64_t)niv_plain + (uint64_t)nr * (uint64_t)std::min(q->cap, p->s_max);
+      SortPlan spp = make_sort_plan(niv_plan, L);
+      PropWork pw;
+      rc = ensure_arena3(ctx, carve_prop(nullptr, nr, niv_plain, niv_plan, spp, pw));
+      if (rc) return rc;
+      carve_prop((char*)ctx->arena3, nr, niv_plain, niv_plan, spp, pw);
+      HIP_TRY(launch_prop_fwd(q->dtype, q->packed_dev, plain, rays->o_dev, rays->d_dev, R, r0, tree->dev_leafbox,
+                              p->s_max, niv_plain, pw.tau, st));
+      HIP_TRY(launch_prop_select(nr, plain, pw.tau, q->mass_thresh, q->cap, pw.runs, pw.nsel, pw.mask, nullptr,
+                                 ctx->counts, st));
+      HIP_TRY(launch_scan_u32(pw.runs, pw.pv_off, nr, nullptr, pw.scan_tmp, st));
+      HIP_TRY(launch_scan_u32(pw.nsel, pw.ps_off, nr, nullptr, pw.scan_tmp, st));
+      HIP_TRY(launch_prop_emit(nr, plain, pw.mask, pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, st));
+      use = {pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, pw.pv_off + nr};
+      spu = spp;
+      mat = pw.mat; mat_scan = pw.mat_scan; sidx = pw.sidx; sn = pw.sn; ssb = pw.ssb; scan_tmp = pw.scan_tmp;
+      niv_use_max = niv_plan;
+    }
+    HIP_TRY(launch_chunk_begin(ctx->counts, use.n_iv_dev, st));
     HIP_TRY(mark(1));
-    HIP_TRY(launch_sort_hist(sp, w.iv_key, n_iv_dev, w.mat, st));
-    HIP_TRY(launch_scan_u32(w.mat, w.mat_scan, (uint64_t)L * sp.nseg_max, nullptr, w.scan_tmp, st));
-    HIP_TRY(launch_sort_scatter(sp, w.iv_key, n_iv_dev, w.mat_scan, w.sidx, w.sn, st));
-    HIP_TRY(launch_scan_u32(w.sn, w.ssb, niv_max, n_iv_dev, w.scan_tmp, st));
-    HIP_TRY(launch_bucket_tiles(sp, w.mat_scan, w.ssb, w.bucket_off, w.tile_off, ctx->counts, st));
+    HIP_TRY(launch_sort_hist(spu, use.key, use.n_iv_dev, mat, st));
+    HIP_TRY(launch_scan_u32(mat, mat_scan, (uint64_t)L * spu.nseg_max, nullptr, scan_tmp, st));
+    HIP_TRY(launch_sort_scatter(spu, use.key, use.n_iv_dev, mat_scan, sidx, sn, st));
+    HIP_TRY(launch_scan_u32(sn, ssb, niv_use_max, use.n_iv_dev, scan_tmp, st));
+    HIP_TRY(launch_bucket_tiles(spu, mat_scan, ssb, w.bucket_off, w.tile_off, ctx->counts, st));
     HIP_TRY(mark(2));
-    HIP_TRY(launch_expand(w.sidx, w.ssb, n_iv_dev, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_off, w.smp_off, r0,
-                          jitter, p->jitter_seed, w.srec_ray, w.srec_t, w.perm, st));
+    HIP_TRY(launch_expand(sidx, ssb, use, r0, jitter, p->jitter_seed, w.srec_ray, w.srec_t, w.perm, st));
     HIP_TRY(mark(3));
     HIP_TRY(launch_mlp(g, mlp->packed_dev, L, w.bucket_off, w.tile_off, ctx->counts, w.srec_ray, w.srec_t, w.perm,
                        rays->o_dev, rays->d_dev, R, r0, w.smp_out, st));
     HIP_TRY(mark(4));
-    HIP_TRY(launch_composite(nr, w.iv_off, w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.smp_out, r0, jitter,
-                             p->jitter_seed, p->ert_eps, out->rgb_dev, out->depth_dev, out->opacity_dev,
-                             out->weights_dev, ctx->counts, st));
+    HIP_TRY(launch_composite(nr, use, w.smp_out, r0, jitter, p->jitter_seed, p->ert_eps, out->rgb_dev, out->depth_dev,
+                             out->opacity_dev, out->weights_dev, ctx->counts, st));
     HIP_TRY(mark(5));
     if (ev) ev->pending = true;
-    HIP_TRY(launch_chunk_finish(ctx->counts, w.smp_off + nr, n_iv_dev, st));
+    HIP_TRY(launch_chunk_finish(ctx->counts, use.smp_off + nr, use.n_iv_dev, w.smp_off + nr, st));
   }
   ctx->last_stream = st;
   ctx->have_render = true;
@@ -636,11 +744,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   ctx->last_leaves = L;
   ctx->last_niv_max = niv_max;
   ctx->last_ns_max = ns_max;
-  ctx->iv_off = w.iv_off;
-  ctx->smp_off = w.smp_off;
-  ctx->iv_key = w.iv_key;
-  ctx->iv_t0 = w.iv_t0;
-  ctx->iv_dt = w.iv_dt;
+  ctx->use = use;
   ctx->bucket_off = w.bucket_off;
   ctx->perm = w.perm;
   ctx->smp_out = w.smp_out;
@@ -651,6 +755,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   ctx->last_packed = mlp->packed_dev;
   ctx->last_dtype = mlp->dtype;
   ctx->last_params = *p;
+  ctx->last_params.proposal = nullptr;
   ctx->last_o = rays->o_dev;
   return AMNERF_OK;
 }
@@ -674,6 +779,8 @@ extern "C" int amnerf_render_stats_get(amnerf_ctx* ctx, amnerf_render_stats* out
   out->n_tiles = c.n_tiles;
   out->n_chunks = ctx->last_chunks;
   out->n_nonfinite = (int64_t)c.nonfinite;
+  out->n_fallback = (int64_t)c.fallback;
+  out->n_plain_samples = (int64_t)c.plain_smp;
   return AMNERF_OK;
 }
 
@@ -690,10 +797,11 @@ extern "C" int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* o, v
     if (!dst || bytes == 0) return hipSuccess;
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
   };
-  HIP_TRY(cp(o->ray_iv_off, ctx->iv_off, 4 * (nr + 1)));
-  HIP_TRY(cp(o->ray_smp_off, ctx->smp_off, 4 * (nr + 1)));
-  HIP_TRY(cp(o->iv_t0, ctx->iv_t0, 4 * niv));
-  HIP_TRY(cp(o->iv_dt, ctx->iv_dt, 4 * niv));
+  const IvSet& u = ctx->use;
+  HIP_TRY(cp(o->ray_iv_off, u.iv_off, 4 * (nr + 1)));
+  HIP_TRY(cp(o->ray_smp_off, u.smp_off, 4 * (nr + 1)));
+  HIP_TRY(cp(o->iv_t0, u.t0, 4 * niv));
+  HIP_TRY(cp(o->iv_dt, u.dt, 4 * niv));
   HIP_TRY(cp(o->bucket_off, ctx->bucket_off, 4 * (L + 1)));
   HIP_TRY(cp(o->perm, ctx->perm, 4 * ns));
   HIP_TRY(cp(o->sample_out, ctx->smp_out, 16 * ns));
@@ -701,7 +809,7 @@ extern "C" int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* o, v
     // split the packed keys on the host (inspection only)
     std::vector<uint32_t> keys(niv);
     if (niv) {
-      HIP_TRY(hipMemcpyAsync(keys.data(), ctx->iv_key, 4 * niv, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(keys.data(), u.key, 4 * niv, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
     }
     std::vector<uint32_t> slot(niv), nn(niv);
@@ -767,8 +875,8 @@ int backward_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* ml
   const amnerf_render_params& p = ctx->last_params;
   const int jitter = (p.flags & AMNERF_JITTER) ? 1 : 0;
   const uint32_t nr = (uint32_t)R;
-  HIP_TRY(launch_comp_bwd(nr, ctx->iv_off, ctx->smp_off, ctx->iv_t0, ctx->iv_dt, ctx->iv_key, ctx->smp_out, 0,
-                          jitter, p.jitter_seed, p.ert_eps, g_rgb, g_depth, g_opac, w.gpre, st));
+  HIP_TRY(launch_comp_bwd(nr, ctx->use, ctx->smp_out, 0, jitter, p.jitter_seed, p.ert_eps, g_rgb, g_depth, g_opac,
+                          w.gpre, st));
   HIP_TRY(launch_seg_offsets(ctx->tile_off, (uint32_t)L, w.seg_off, st));
   HIP_TRY(launch_mlp_bwd(g, mlp->packed_dev, (uint32_t)L, ctx->bucket_off, ctx->tile_off, w.seg_off, ctx->srec_ray,
                          ctx->srec_t, ctx->perm, rays->o_dev, rays->d_dev, rays->n_rays, 0, w.gpre, w.part, st));
@@ -840,5 +948,97 @@ extern "C" int amnerf_train_step(amnerf_ctx* ctx, const amnerf_tree* tree, amner
     rc = amnerf_mlp_pack(ctx, &m->shape, AMNERF_BF16, m->n_leaves, m->master_dev, m->packed_dev, stream);
     if (rc) return rc;
   }
+  return AMNERF_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// learned proposal
+// ---------------------------------------------------------------------------------------
+extern "C" int64_t amnerf_prop_param_count(void) { return prop_param_count(); }
+
+extern "C" int amnerf_prop_packed_bytes(int32_t dtype, size_t* out) {
+  if (!out || (dtype != AMNERF_F32 && dtype != AMNERF_BF16)) return fail(AMNERF_EINVAL, "amnerf_prop_packed_bytes: bad argument");
+  *out = prop_packed_bytes(dtype);
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_prop_pack(amnerf_ctx* ctx, int32_t dtype, const float* master, void* packed, void* stream) {
+  if (!ctx || !master || !packed || (dtype != AMNERF_F32 && dtype != AMNERF_BF16))
+    return fail(AMNERF_EINVAL, "amnerf_prop_pack: bad argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(launch_prop_pack(dtype, master, packed, (hipStream_t)stream));
+  return AMNERF_OK;
+}
+
+namespace {
+struct PropTrainWork {
+  float *rgb, *tau, *alpha, *part, *loss_part;
+};
+size_t carve_prop_train(char* base, uint64_t R, uint64_t niv, uint64_t nb, PropTrainWork& w) {
+  Carve c{base};
+  w.rgb = c.take<float>(3 * std::max<uint64_t>(R, 1));
+  w.tau = c.take<float>(32 * std::max<uint64_t>(niv, 1));
+  w.alpha = c.take<float>(32 * std::max<uint64_t>(niv, 1));
+  w.part = c.take<float>(nb * (uint64_t)prop_param_count());
+  w.loss_part = c.take<float>(nb);
+  return c.off + 256;
+}
+}  // namespace
+
+extern "C" int amnerf_propose(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* scene_mlp,
+                              const amnerf_rays* rays, const amnerf_propose_params* p, int64_t* n_intervals,
+                              void* stream) {
+  if (!ctx || !tree || !scene_mlp || !rays || !p) return fail(AMNERF_EINVAL, "amnerf_propose: null argument");
+  if (p->mode != AMNERF_PROPOSE_INFER && p->mode != AMNERF_PROPOSE_TRAIN)
+    return fail(AMNERF_EINVAL, "amnerf_propose: bad mode %d", p->mode);
+  if (p->mode == AMNERF_PROPOSE_TRAIN &&
+      (!p->master_dev || !p->grad_dev || !p->m_dev || !p->v_dev || !p->packed_dev || !p->loss_dev))
+    return fail(AMNERF_EINVAL, "amnerf_propose: null training buffer");
+  if (p->mode == AMNERF_PROPOSE_INFER && (!p->infer_packed_dev || !p->tau_dev ||
+                                          (p->infer_dtype != AMNERF_F32 && p->infer_dtype != AMNERF_BF16)))
+    return fail(AMNERF_EINVAL, "amnerf_propose: bad inference arguments");
+  const uint64_t R = (uint64_t)rays->n_rays;
+  if (R * (uint64_t)std::max(1, p->s_max) > kChunkSamples)
+    return fail(AMNERF_ECAPACITY, "amnerf_propose: %llu rays x %d samples exceed one pass", (unsigned long long)R, p->s_max);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  // a plain render of the rays provides the intervals (and, for training, the samples' sigma)
+  uint32_t niv_guess = 0;
+  {
+    PropTrainWork tw;
+    int rc = ensure_arena3(ctx, carve_prop_train(nullptr, R, 0, prop_train_blocks(), tw));
+    if (rc) return rc;
+    carve_prop_train((char*)ctx->arena3, R, 0, prop_train_blocks(), tw);
+    amnerf_render_params rp = {};
+    rp.s_max = p->s_max;
+    rp.ert_eps = 0.f;
+    amnerf_render_out out = {tw.rgb, nullptr, nullptr, nullptr};
+    rc = amnerf_render(ctx, tree, scene_mlp, rays, &rp, &out, stream);
+    if (rc) return rc;
+    rc = read_counts(ctx);
+    if (rc) return rc;
+    niv_guess = ctx->counts_host->n_iv;
+  }
+  if (n_intervals) *n_intervals = niv_guess;
+  PropTrainWork tw;
+  const uint32_t nb = prop_train_blocks();
+  // the render used the main arena only, so the third arena can be re-carved freely
+  int rc = ensure_arena3(ctx, carve_prop_train(nullptr, R, niv_guess, nb, tw));
+  if (rc) return rc;
+  carve_prop_train((char*)ctx->arena3, R, niv_guess, nb, tw);
+  const IvSet& iv = ctx->use;
+  if (p->mode == AMNERF_PROPOSE_INFER) {
+    if ((int64_t)niv_guess > p->tau_cap)
+      return fail(AMNERF_ECAPACITY, "amnerf_propose: %u intervals exceed tau_cap %lld", niv_guess, (long long)p->tau_cap);
+    HIP_TRY(launch_prop_fwd(p->infer_dtype, p->infer_packed_dev, iv, rays->o_dev, rays->d_dev, rays->n_rays, 0,
+                            tree->dev_leafbox, p->s_max, niv_guess, p->tau_dev, st));
+    return AMNERF_OK;
+  }
+  HIP_TRY(launch_prop_targets(iv, ctx->smp_out, tw.alpha, st));
+  HIP_TRY(launch_prop_train(p->packed_dev, iv, rays->o_dev, rays->d_dev, rays->n_rays, 0, tree->dev_leafbox, p->s_max,
+                            tw.alpha, tw.part, tw.loss_part, p->grad_dev, p->loss_dev, st));
+  rc = amnerf_adam_step(ctx, prop_param_count(), p->master_dev, p->m_dev, p->v_dev, p->grad_dev, &p->adam, stream);
+  if (rc) return rc;
+  HIP_TRY(launch_prop_pack(AMNERF_F32, p->master_dev, p->packed_dev, st));
   return AMNERF_OK;
 }

@@ -43,23 +43,20 @@ __device__ __forceinline__ float wave_sum(float v) {
 // tau_j, then S_j = sum_{i<j} tau_i by a compensated (float pair) prefix scan across the
 // wave plus the running total of earlier steps; T_j = exp(-S_j), w_j = T_j (1 - e^-tau_j).
 // Early termination: the first lane whose T_{j+1} < eps keeps its sample and later lanes
-// (and steps) contribute nothing.  Samples of a ray have the same count n per interval, so
-// lane j's interval is j / n.
+// (and steps) contribute nothing.  Lane j finds its interval by binary search over the
+// intervals' first-sample indices.
 __global__ __launch_bounds__(kThreads) void k_composite(
-    uint32_t nr, const uint32_t* __restrict__ iv_off, const uint32_t* __restrict__ smp_off,
-    const float* __restrict__ iv_t0, const float* __restrict__ iv_dt,
-    const uint32_t* __restrict__ iv_key, const float* __restrict__ smp_out, int64_t r0, int jitter,
+    uint32_t nr, IvSet iv, const float* __restrict__ smp_out, int64_t r0, int jitter,
     uint64_t seed, float eps, float* __restrict__ rgb, float* __restrict__ depth,
     float* __restrict__ opac, float* __restrict__ weights, ChunkCounts* __restrict__ counts) {
   const int lane = threadIdx.x & 63;
   const uint32_t r = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (r >= nr) return;
-  const uint32_t i0 = iv_off[r], m = iv_off[r + 1] - i0;
-  const uint32_t s0 = smp_off[r], ns = smp_off[r + 1] - s0;
+  const uint32_t i0 = iv.iv_off[r], i1 = iv.iv_off[r + 1];
+  const uint32_t s0 = iv.smp_off[r], ns = iv.smp_off[r + 1] - s0;
   const uint64_t wbase = counts->smp_global + s0;
   float cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f, acc = 0.f;
   if (ns > 0) {
-    const uint32_t n = ns / m;
     DF carry = {0.f, 0.f};
     bool done = false;
     for (uint32_t base = 0; base < ns; base += 64) {
@@ -67,11 +64,12 @@ __global__ __launch_bounds__(kThreads) void k_composite(
       const bool valid = !done && j < ns;
       float tau = 0.f, sig_c[3] = {0.f, 0.f, 0.f}, t = 0.f;
       if (valid) {
-        const uint32_t k = j / n, jj = j - k * n;
+        const uint32_t i = find_interval(iv.base, i0, i1, s0 + j);
+        const uint32_t jj = s0 + j - iv.base[i];
         const float4 z = *reinterpret_cast<const float4*>(smp_out + 4 * (uint64_t)(s0 + j));
-        const float delta = iv_dt[i0 + k] / (float)n;
-        const float u = stratum_u(jitter, seed, (uint64_t)(r0 + r), k);
-        t = sample_t(iv_t0[i0 + k], delta, jj, u);
+        const float delta = iv.dt[i] / (float)key_n(iv.key[i]);
+        const float u = stratum_u(jitter, seed, (uint64_t)(r0 + r), i - i0);
+        t = sample_t(iv.t0[i], delta, jj, u);
         tau = softplusf(z.x) * delta;       // sigma = softplus, rgb = logistic
         sig_c[0] = logisticf(z.y);
         sig_c[1] = logisticf(z.z);
@@ -123,10 +121,12 @@ __global__ __launch_bounds__(kThreads) void k_composite(
 }
 
 // Records the chunk's totals for the host and advances the global sample base.
-__global__ void k_chunk_finish(ChunkCounts* counts, const uint32_t* smp_total, const uint32_t* iv_total) {
+__global__ void k_chunk_finish(ChunkCounts* counts, const uint32_t* smp_total, const uint32_t* iv_total,
+                               const uint32_t* plain_total) {
   if (threadIdx.x != 0) return;
   counts->smp_global += *smp_total;
   counts->iv_global += *iv_total;
+  counts->plain_smp += *plain_total;
 }
 
 __global__ void k_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total) {
@@ -142,22 +142,22 @@ __global__ void k_counts_reset(ChunkCounts* counts) {
 
 }  // namespace
 
-hipError_t launch_composite(uint32_t nr, const uint32_t* iv_off, const uint32_t* smp_off,
-                            const float* iv_t0, const float* iv_dt, const uint32_t* iv_key,
-                            const float* smp_out, int64_t r0, int jitter, uint64_t seed,
-                            float ert_eps, float* rgb, float* depth, float* opac, float* weights,
-                            ChunkCounts* counts, hipStream_t st) {
+hipError_t launch_composite(uint32_t nr, const IvSet& iv, const float* smp_out, int64_t r0,
+                            int jitter, uint64_t seed, float ert_eps, float* rgb, float* depth,
+                            float* opac, float* weights, ChunkCounts* counts, hipStream_t st) {
   if (nr == 0) return hipSuccess;
   const uint32_t rays_per_block = kThreads / 64;
   uint32_t grid = (nr + rays_per_block - 1) / rays_per_block;
-  hipLaunchKernelGGL(k_composite, dim3(grid), dim3(kThreads), 0, st, nr, iv_off, smp_off, iv_t0, iv_dt,
-                     iv_key, smp_out, r0, jitter, seed, ert_eps, rgb, depth, opac, weights, counts);
+  hipLaunchKernelGGL(k_composite, dim3(grid), dim3(kThreads), 0, st, nr, iv, smp_out, r0, jitter, seed,
+                     ert_eps, rgb, depth, opac, weights, counts);
   return hipGetLastError();
 }
 
 hipError_t launch_chunk_finish(ChunkCounts* counts, const uint32_t* smp_off_total,
-                               const uint32_t* iv_off_total, hipStream_t st) {
-  hipLaunchKernelGGL(k_chunk_finish, dim3(1), dim3(64), 0, st, counts, smp_off_total, iv_off_total);
+                               const uint32_t* iv_off_total, const uint32_t* plain_smp_total,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_chunk_finish, dim3(1), dim3(64), 0, st, counts, smp_off_total, iv_off_total,
+                     plain_smp_total);
   return hipGetLastError();
 }
 

@@ -25,6 +25,8 @@ struct ChunkCounts {
   uint64_t smp_global;  // ray-major sample index of this chunk's first sample
   uint64_t iv_global;   // intervals of the chunks before this one
   uint64_t nonfinite;   // rays with a non-finite output (accumulated over chunks)
+  uint64_t fallback;    // rays that fell back to plain sampling under a proposal
+  uint64_t plain_smp;   // samples of the plain sampler (before any proposal)
 };
 
 constexpr int kMlpTileRows = 256;       // rows of one MLP work tile (4 waves x 64)
@@ -40,8 +42,34 @@ hipError_t launch_trav_count(const DevNode* nodes, const float* o, const float* 
 hipError_t launch_trav_emit(const DevNode* nodes, const float* o, const float* d,
                             int64_t ray_stride, int64_t r0, uint32_t nr,
                             const uint32_t* cnt_iv, const uint32_t* cnt_smp,
-                            const uint32_t* iv_off, float* iv_t0, float* iv_dt,
-                            uint32_t* iv_key, uint32_t* iv_ray, hipStream_t st);
+                            const uint32_t* iv_off, const uint32_t* smp_off, float* iv_t0,
+                            float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray, uint32_t* iv_base,
+                            hipStream_t st);
+
+// Intervals of one chunk, ray-major: per ray the interval range [iv_off[r], iv_off[r+1]) and
+// sample range [smp_off[r], smp_off[r+1]); per interval t0, length dt, key (slot | n << 16),
+// chunk-local ray, and base = ray-major index of its first sample.
+struct IvSet {
+  const uint32_t* iv_off;
+  const uint32_t* smp_off;
+  const float* t0;
+  const float* dt;
+  const uint32_t* key;
+  const uint32_t* ray;
+  const uint32_t* base;
+  const uint32_t* n_iv_dev;   // total intervals (device)
+};
+
+// Interval holding ray-major sample s among intervals [i0, i1) (largest i with base[i] <= s).
+__device__ __forceinline__ uint32_t find_interval(const uint32_t* __restrict__ base, uint32_t i0,
+                                                  uint32_t i1, uint32_t s) {
+  uint32_t lo = i0, hi = i1;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (base[mid] <= s) lo = mid; else hi = mid;
+  }
+  return lo;
+}
 
 // ---- scans -----------------------------------------------------------------------------
 // Exclusive prefix sum of n uint32 values (n given on the host, or read from n_dev when
@@ -70,9 +98,7 @@ hipError_t launch_bucket_tiles(const SortPlan& p, const uint32_t* mat_scan, cons
                                uint32_t* bucket_off, uint32_t* tile_off, ChunkCounts* counts,
                                hipStream_t st);
 // One record per sorted sample: ray (chunk-local), t, ray-major sample index.
-hipError_t launch_expand(const uint32_t* sidx, const uint32_t* ssb, const uint32_t* n_iv_dev,
-                         const float* iv_t0, const float* iv_dt, const uint32_t* iv_key,
-                         const uint32_t* iv_ray, const uint32_t* iv_off, const uint32_t* smp_off,
+hipError_t launch_expand(const uint32_t* sidx, const uint32_t* ssb, const IvSet& iv,
                          int64_t r0, int jitter, uint64_t seed, uint32_t* srec_ray,
                          float* srec_t, uint32_t* perm, hipStream_t st);
 
@@ -92,17 +118,14 @@ hipError_t launch_mlp(const MlpGeom& g, const void* packed, uint32_t n_leaves,
                       int64_t r0, float* out, hipStream_t st);
 
 // ---- compositing (Section 3.1 -> NeRF quadrature, early ray termination) ---------------
-hipError_t launch_composite(uint32_t nr, const uint32_t* iv_off, const uint32_t* smp_off,
-                            const float* iv_t0, const float* iv_dt, const uint32_t* iv_key,
-                            const float* smp_out, int64_t r0, int jitter, uint64_t seed,
-                            float ert_eps, float* rgb, float* depth, float* opac,
-                            float* weights, ChunkCounts* counts, hipStream_t st);
+hipError_t launch_composite(uint32_t nr, const IvSet& iv, const float* smp_out, int64_t r0,
+                            int jitter, uint64_t seed, float ert_eps, float* rgb, float* depth,
+                            float* opac, float* weights, ChunkCounts* counts, hipStream_t st);
 
 // ---- training ----------------------------------------------------------------------------
 bool mlp_bwd_supported(int n_hidden, int hidden);
-hipError_t launch_comp_bwd(uint32_t nr, const uint32_t* iv_off, const uint32_t* smp_off, const float* iv_t0,
-                           const float* iv_dt, const uint32_t* iv_key, const float* smp_out, int64_t r0,
-                           int jitter, uint64_t seed, float eps, const float* g_rgb, const float* g_depth,
+hipError_t launch_comp_bwd(uint32_t nr, const IvSet& iv, const float* smp_out, int64_t r0, int jitter,
+                           uint64_t seed, float eps, const float* g_rgb, const float* g_depth,
                            const float* g_opac, float* gpre, hipStream_t st);
 hipError_t launch_seg_offsets(const uint32_t* tile_off, uint32_t n_leaves, uint32_t* seg_off, hipStream_t st);
 hipError_t launch_mlp_bwd(const MlpGeom& g, const void* packed, uint32_t n_leaves, const uint32_t* bucket_off,
@@ -117,10 +140,30 @@ hipError_t launch_loss_grad(uint32_t R, const float* rgb, const float* target, f
 hipError_t launch_adam(int64_t n, float* p, float* m, float* v, const float* g, float lr, float b1, float b2,
                        float eps, int step, hipStream_t st);
 
+// ---- learned proposal ----------------------------------------------------------------------
+int prop_param_count();
+size_t prop_packed_bytes(int dtype);
+uint32_t prop_train_blocks();
+hipError_t launch_prop_pack(int dtype, const float* master, void* packed, hipStream_t st);
+hipError_t launch_prop_fwd(int dtype, const void* packed, const IvSet& iv, const float* o, const float* d,
+                           int64_t stride, int64_t r0, const float* leafbox, int s_max, uint32_t n_iv_max,
+                           float* tau, hipStream_t st);
+hipError_t launch_prop_select(uint32_t nr, const IvSet& iv, const float* tau, float mass_thresh, int cap,
+                              uint32_t* runs, uint32_t* nsel, uint64_t* mask, float* mass, ChunkCounts* counts,
+                              hipStream_t st);
+hipError_t launch_prop_emit(uint32_t nr, const IvSet& iv, const uint64_t* mask, const uint32_t* pv_off,
+                            const uint32_t* ps_off, float* pt0, float* pdt, uint32_t* pkey, uint32_t* pray,
+                            uint32_t* pbase, hipStream_t st);
+hipError_t launch_prop_targets(const IvSet& iv, const float* smp_out, float* alpha, hipStream_t st);
+hipError_t launch_prop_train(const void* packed, const IvSet& iv, const float* o, const float* d, int64_t stride,
+                             int64_t r0, const float* leafbox, int s_max, const float* alpha, float* part,
+                             float* loss_part, float* grad, float* loss, hipStream_t st);
+
 // ---- small helpers ----------------------------------------------------------------------
 hipError_t launch_counts_reset(ChunkCounts* counts, hipStream_t st);
 hipError_t launch_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total, hipStream_t st);
 hipError_t launch_chunk_finish(ChunkCounts* counts, const uint32_t* smp_off_total,
-                               const uint32_t* iv_off_total, hipStream_t st);
+                               const uint32_t* iv_off_total, const uint32_t* plain_smp_total,
+                               hipStream_t st);
 
 }  // namespace amn

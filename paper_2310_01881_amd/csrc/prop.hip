@@ -1,0 +1,879 @@
+// prop.hip -- the learned proposal: a 43 -> 64 -> 64 -> 32 MLP evaluated per (ray, leaf
+// interval) that predicts the optical thickness of 32 equal bins of the interval.
+// Compositing the bins along the ray gives the ray's predicted weight histogram over its
+// leaf intervals; the plain sampler's slots are ranked by the predicted weight they cover,
+// the fewest slots holding mass_thresh of the predicted mass are kept (at most cap), and the
+// ray falls back to every plain slot when the predicted mass is below mass_thresh or the cap
+// is exceeded.  The kept slots become new intervals (runs of consecutive slots), so the
+// rest of the path (sort by leaf, grouped MLP, compositing) runs unchanged on fewer samples.
+//
+// Training targets come from the plain render: bin opacity 1 - exp(-sum_j sigma_j |slot_j n
+// bin|).  Training runs in float32 on the matrix cores (forward, backward chain and dW with
+// K = items staged through LDS), with per-block partial gradients reduced in a fixed order.
+#include "internal.hpp"
+#include "devcommon.hpp"
+#include "mlp_layout.hpp"
+
+#include <algorithm>
+
+namespace amn {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kIn = 43, kH = 64, kBins = 32;
+constexpr int kP = kH * kIn + kH + kH * kH + kH + kBins * kH + kBins;   // 9056
+// master offsets
+constexpr int kW0 = 0, kB0 = kW0 + kH * kIn, kW1 = kB0 + kH, kB1 = kW1 + kH * kH, kW2 = kB1 + kH,
+              kB2 = kW2 + kBins * kH;
+// packed: biases (160 floats) then 1 KiB units.
+// f32 forward units: layer 0: rb 0..3 x ku 0..2 (12 k-blocks of 4 inputs); layer 1: 4 x 4;
+//   layer 2: rb 0..1 x 4.  Backward (transposed) units: layer 1: rb_in 0..3 x ku 0..3;
+//   layer 2: rb_in 0..3 x ku 0..1.
+// bf16 forward units: layer 0: rb 0..3 x ku 0..1 (K = 64 padded from 43); layer 1: 4 x 2;
+//   layer 2: 2 x 2.
+constexpr int kBiasBytes = (kH + kH + kBins) * 4;
+constexpr int kF32Units = 12 + 16 + 8, kF32BwdUnits = 16 + 8, kBf16Units = 8 + 8 + 4;
+constexpr uint32_t kF32Bytes = kBiasBytes + (kF32Units + kF32BwdUnits) * kUnitBytes;
+constexpr uint32_t kBf16Bytes = kBiasBytes + kBf16Units * kUnitBytes;
+
+__host__ __device__ __forceinline__ int f32_unit(int layer, int rb, int ku) {
+  return layer == 0 ? rb * 3 + ku : (layer == 1 ? 12 + rb * 4 + ku : 28 + rb * 4 + ku);
+}
+__host__ __device__ __forceinline__ int f32_bwd_unit(int layer, int rb, int ku) {
+  return kF32Units + (layer == 1 ? rb * 4 + ku : 16 + rb * 2 + ku);
+}
+__host__ __device__ __forceinline__ int bf16_unit(int layer, int rb, int ku) {
+  return layer == 0 ? rb * 2 + ku : (layer == 1 ? 8 + rb * 2 + ku : 16 + rb * 2 + ku);
+}
+
+__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+__device__ __forceinline__ float logisticf(float z) { return 1.f / (1.f + expf(-z)); }
+
+__global__ void k_prop_pack(int dtype, const float* __restrict__ master, uint8_t* __restrict__ packed) {
+  const int n_units = dtype == AMNERF_BF16 ? kBf16Units : kF32Units + kF32BwdUnits;
+  for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < n_units * 64 + kBiasBytes / 4;
+       id += gridDim.x * blockDim.x) {
+    if (id >= n_units * 64) {
+      const int j = id - n_units * 64;
+      const float v = j < kH ? master[kB0 + j] : (j < 2 * kH ? master[kB1 + j - kH] : master[kB2 + j - 2 * kH]);
+      reinterpret_cast<float*>(packed)[j] = v;
+      continue;
+    }
+    const int unit = id / 64, lane = id % 64, g = lane / 16, m = lane % 16;
+    uint8_t* dst = packed + kBiasBytes + unit * kUnitBytes + lane * 16;
+    if (dtype == AMNERF_BF16) {
+      int layer, rb, ku;
+      if (unit < 8) { layer = 0; rb = unit / 2; ku = unit % 2; }
+      else if (unit < 16) { layer = 1; rb = (unit - 8) / 2; ku = unit % 2; }
+      else { layer = 2; rb = (unit - 16) / 2; ku = unit % 2; }
+      const int row = 16 * rb + m;
+      bf16x8 h;
+      for (int e = 0; e < 8; ++e) {
+        float v;
+        if (layer == 0) { const int f = 32 * ku + 8 * g + e; v = f < kIn ? master[kW0 + row * kIn + f] : 0.f; }
+        else if (layer == 1) v = master[kW1 + row * kH + hidden_col_bf16(ku, g, e)];
+        else v = master[kW2 + row * kH + hidden_col_bf16(ku, g, e)];
+        h[e] = (__bf16)v;
+      }
+      *reinterpret_cast<bf16x8*>(dst) = h;
+    } else if (unit < kF32Units) {
+      int layer, rb, ku;
+      if (unit < 12) { layer = 0; rb = unit / 3; ku = unit % 3; }
+      else if (unit < 28) { layer = 1; rb = (unit - 12) / 4; ku = (unit - 12) % 4; }
+      else { layer = 2; rb = (unit - 28) / 4; ku = (unit - 28) % 4; }
+      const int row = 16 * rb + m;
+      f32x4 v;
+      for (int e = 0; e < 4; ++e) {
+        const int kb = 4 * ku + e;
+        if (layer == 0) { const int f = 4 * kb + g; v[e] = f < kIn ? master[kW0 + row * kIn + f] : 0.f; }
+        else if (layer == 1) v[e] = master[kW1 + row * kH + 16 * ku + 4 * g + e];
+        else v[e] = master[kW2 + row * kH + 16 * ku + 4 * g + e];
+      }
+      *reinterpret_cast<f32x4*>(dst) = v;
+    } else {
+      // transposed: lane (g, m) of unit (rb_in, ku) holds W^T[in = 16 rb_in + m][out], out =
+      // 16 ku + 4 g + e (the accumulator rows of the gradient's row block ku)
+      const int u = unit - kF32Units;
+      const int layer = u < 16 ? 1 : 2;
+      const int rb = layer == 1 ? u / 4 : (u - 16) / 2, ku = layer == 1 ? u % 4 : (u - 16) % 2;
+      const int in = 16 * rb + m;
+      f32x4 v;
+      for (int e = 0; e < 4; ++e) {
+        const int out = 16 * ku + 4 * g + e;
+        v[e] = layer == 1 ? master[kW1 + out * kH + in] : master[kW2 + out * kH + in];
+      }
+      *reinterpret_cast<f32x4*>(dst) = v;
+    }
+  }
+}
+
+// The 43 features of an interval (the oracle's order).
+__device__ __forceinline__ void prop_features(const float o[3], const float d[3], float t0, float t1, uint32_t k,
+                                              int s_max, const float* box, float F[kIn]) {
+  float q[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) q[a] = (o[a] - 0.5f) * 0.5f;
+  int c = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[c++] = q[a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[c++] = d[a];
+#pragma unroll
+  for (int src = 0; src < 2; ++src) {
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const float fr = (float)(1 << kk);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[c++] = sinpif(fr * (src == 0 ? q[a] : d[a]));
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[c++] = cospif(fr * (src == 0 ? q[a] : d[a]));
+    }
+  }
+  F[c++] = (float)k / (float)s_max;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) F[c++] = box[a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[c++] = 2.f * fmaf(t0, d[a], o[a]) - 1.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[c++] = 2.f * fmaf(t1, d[a], o[a]) - 1.f;
+}
+
+__device__ __forceinline__ float pick4(const float* F, int base, int g, int limit) {
+  const float v0 = base < limit ? F[base < limit ? base : 0] : 0.f;
+  const float v1 = base + 1 < limit ? F[base + 1 < limit ? base + 1 : 0] : 0.f;
+  const float v2 = base + 2 < limit ? F[base + 2 < limit ? base + 2 : 0] : 0.f;
+  const float v3 = base + 3 < limit ? F[base + 3 < limit ? base + 3 : 0] : 0.f;
+  return g == 0 ? v0 : (g == 1 ? v1 : (g == 2 ? v2 : v3));
+}
+
+// Inputs of one item (interval i of the chunk).
+__device__ __forceinline__ void item_features(const IvSet& iv, uint32_t i, const float* __restrict__ o,
+                                              const float* __restrict__ d, int64_t stride, int64_t r0,
+                                              const float* __restrict__ leafbox, int s_max, float F[kIn]) {
+  const uint32_t ray = iv.ray[i];
+  const uint32_t k = i - iv.iv_off[ray];
+  const int64_t ri = r0 + ray;
+  const float oo[3] = {o[ri], o[stride + ri], o[2 * stride + ri]};
+  const float dd[3] = {d[ri], d[stride + ri], d[2 * stride + ri]};
+  const float t0 = iv.t0[i];
+  const float t1 = t0 + iv.dt[i];
+  prop_features(oo, dd, t0, t1, k, s_max, leafbox + 6 * key_slot(iv.key[i]), F);
+}
+
+// ---- inference: tau^[item][32] --------------------------------------------------------
+template <bool BF16>
+__global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict__ packed, IvSet iv,
+                                                       const float* __restrict__ o, const float* __restrict__ d,
+                                                       int64_t stride, int64_t r0,
+                                                       const float* __restrict__ leafbox, int s_max,
+                                                       float* __restrict__ tau) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const uint32_t bytes = BF16 ? kBf16Bytes : kBiasBytes + kF32Units * kUnitBytes;
+  for (uint32_t i = threadIdx.x; i < bytes / 16; i += kThreads)
+    reinterpret_cast<f32x4*>(lds)[i] = reinterpret_cast<const f32x4*>(packed)[i];
+  __syncthreads();
+  const float* bias = reinterpret_cast<const float*>(lds);
+  const uint8_t* units = lds + kBiasBytes;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, m = lane & 15;
+  constexpr int NCB = 4;
+  const uint32_t n_items = *iv.n_iv_dev;
+  for (uint32_t tile = blockIdx.x; tile * 256u < n_items; tile += gridDim.x) {
+    const uint32_t base = tile * 256u + wave * 64u;
+    if (base >= n_items) continue;
+    f32x4 acc[NCB][4];
+    if (BF16) {
+      bf16x8 X[NCB][2];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const uint32_t it = base + cb * 16 + m;
+        float F[kIn];
+        item_features(iv, it < n_items ? it : n_items - 1, o, d, stride, r0, leafbox, s_max, F);
+#pragma unroll
+        for (int ku = 0; ku < 2; ++ku)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int b0 = 32 * ku + e;   // feature 32 ku + 8 g + e
+            const float v0 = b0 < kIn ? F[b0 < kIn ? b0 : 0] : 0.f;
+            const float v1 = b0 + 8 < kIn ? F[b0 + 8 < kIn ? b0 + 8 : 0] : 0.f;
+            const float v2 = b0 + 16 < kIn ? F[b0 + 16 < kIn ? b0 + 16 : 0] : 0.f;
+            const float v3 = b0 + 24 < kIn ? F[b0 + 24 < kIn ? b0 + 24 : 0] : 0.f;
+            X[cb][ku][e] = (__bf16)(g == 0 ? v0 : (g == 1 ? v1 : (g == 2 ? v2 : v3)));
+          }
+      }
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
+#pragma unroll
+        for (int ku = 0; ku < 2; ++ku) {
+          const bf16x8 A = *reinterpret_cast<const bf16x8*>(units + bf16_unit(0, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, X[cb][ku], ku == 0 ? bv : acc[cb][rb], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int layer = 1; layer <= 2; ++layer) {
+        bf16x8 Bv[NCB][2];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int ku = 0; ku < 2; ++ku) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = acc[cb][2 * ku + e / 4][e % 4];
+            Bv[cb][ku] = relu_bf16x8(v);
+          }
+        const int nrb = layer == 1 ? 4 : 2;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          if (rb >= nrb) break;
+          const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + layer * kH + 16 * rb + 4 * g);
+#pragma unroll
+          for (int ku = 0; ku < 2; ++ku) {
+            const bf16x8 A = *reinterpret_cast<const bf16x8*>(units + bf16_unit(layer, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv[cb][ku], ku == 0 ? bv : acc[cb][rb], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      float X[NCB][12];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const uint32_t it = base + cb * 16 + m;
+        float F[kIn];
+        item_features(iv, it < n_items ? it : n_items - 1, o, d, stride, r0, leafbox, s_max, F);
+#pragma unroll
+        for (int kb = 0; kb < 12; ++kb) X[cb][kb] = pick4(F, 4 * kb, g, kIn);
+      }
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb][rb] = bv;
+#pragma unroll
+        for (int ku = 0; ku < 3; ++ku) {
+          const f32x4 A = *reinterpret_cast<const f32x4*>(units + f32_unit(0, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], X[cb][4 * ku + e], acc[cb][rb], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int layer = 1; layer <= 2; ++layer) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[cb][rb][e] = fmaxf(acc[cb][rb][e], 0.f);
+        const int nrb = layer == 1 ? 4 : 2;
+        f32x4 nacc[NCB][4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          if (rb >= nrb) break;
+          const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + layer * kH + 16 * rb + 4 * g);
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) nacc[cb][rb] = bv;
+#pragma unroll
+          for (int ku = 0; ku < 4; ++ku) {
+            const f32x4 A = *reinterpret_cast<const f32x4*>(units + f32_unit(layer, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb)
+                nacc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], acc[cb][ku][e], nacc[cb][rb], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+            if (rb < nrb) acc[cb][rb] = nacc[cb][rb];
+      }
+    }
+    // outputs: rows 16 rb + 4 g + e of the 32 bins
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const uint32_t it = base + cb * 16 + m;
+      if (it >= n_items) continue;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        f32x4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = softplusf(acc[cb][rb][e]);
+        *reinterpret_cast<f32x4*>(tau + (uint64_t)it * kBins + 16 * rb + 4 * g) = v;
+      }
+    }
+  }
+}
+
+// ---- selection: one wave per ray ----------------------------------------------------
+// Per ray: the bins of the ray's intervals are composited two intervals (64 bins) per step;
+// slot j of interval k (n slots) receives the predicted weight of the bins it overlaps.
+// The threshold theta* = the largest value with sum_{p_j >= theta} p_j >= mass_thresh * M^ is
+// found by binary search over the bit patterns of non-negative floats; slots above it are
+// kept, and among slots equal to it the earliest ones until the sum is reached.
+constexpr int kMaxSlots = 256;   // >= AMNERF_MAX_SAMPLES + 1
+
+__global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv, const float* __restrict__ tau,
+                                                          float mass_thresh, int cap, uint32_t* __restrict__ runs,
+                                                          uint32_t* __restrict__ nsel, uint64_t* __restrict__ mask,
+                                                          float* __restrict__ mass_out,
+                                                          ChunkCounts* __restrict__ counts) {
+  __shared__ float wbuf[kThreads / 64][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t r = blockIdx.x * (kThreads / 64) + wave;
+  if (r >= nr) return;
+  const uint32_t i0 = iv.iv_off[r], meff = iv.iv_off[r + 1] - i0;
+  const uint32_t ns = iv.smp_off[r + 1] - iv.smp_off[r];
+  if (meff == 0) {
+    if (lane == 0) { runs[r] = 0; nsel[r] = 0; if (mass_out) mass_out[r] = 0.f; }
+    return;
+  }
+  const uint32_t n = ns / meff;
+  float p[4] = {0.f, 0.f, 0.f, 0.f};
+  float carry = 0.f;
+  for (uint32_t k = 0; k < meff; k += 2) {
+    const uint32_t kk = k + (uint32_t)(lane >> 5);
+    const float t = kk < meff ? tau[(uint64_t)(i0 + kk) * kBins + (lane & 31)] : 0.f;
+    float inc = t;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const float y = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += y;
+    }
+    const float S = carry + inc - t;
+    wbuf[wave][lane] = expf(-S) * -expm1f(-t);
+    carry += __shfl(inc, 63, 64);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t s = (uint32_t)lane + 64u * q;
+      if (s >= ns) continue;
+      const uint32_t sk = s / n, j = s - sk * n;
+      if (sk != k && sk != k + 1) continue;
+      const float a0 = (float)j / (float)n, a1 = (float)(j + 1) / (float)n;
+      const int b_lo = (int)((32u * j) / n);
+      const int b_hi = min(31, (int)((32u * (j + 1) + n - 1) / n) - 1);
+      float acc = 0.f;
+      for (int b = b_lo; b <= b_hi; ++b) {
+        const float ov = fminf(a1, (float)(b + 1) * (1.f / 32.f)) - fmaxf(a0, (float)b * (1.f / 32.f));
+        if (ov > 0.f) acc += wbuf[wave][(sk - k) * 32 + b] * ov * 32.f;
+      }
+      p[q] = acc;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  const float M = -expm1f(-carry);
+  if (mass_out && lane == 0) mass_out[r] = M;
+  bool fallback = !(M >= mass_thresh);
+  uint64_t sel[4] = {0, 0, 0, 0};
+  uint32_t count = 0;
+  if (!fallback) {
+    const float target = mass_thresh * M;
+    auto mass_at_least = [&](uint32_t bits) {
+      const float th = __uint_as_float(bits);
+      float s = 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if ((uint32_t)lane + 64u * q < ns && p[q] >= th) s += p[q];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+      return s;
+    };
+    float pmax = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if ((uint32_t)lane + 64u * q < ns) pmax = fmaxf(pmax, p[q]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) pmax = fmaxf(pmax, __shfl_xor(pmax, off, 64));
+    uint32_t lo = 0u, hi = __float_as_uint(pmax) + 1u;   // f(lo) >= target > f(hi)
+    while (hi - lo > 1u) {
+      const uint32_t mid = lo + (hi - lo) / 2u;
+      if (mass_at_least(mid) >= target) lo = mid; else hi = mid;
+    }
+    const float th = __uint_as_float(lo);
+    const float above = mass_at_least(lo + 1u);
+    // earliest slots equal to th until the target is reached
+    uint32_t rank_base = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t s = (uint32_t)lane + 64u * q;
+      const bool valid = s < ns;
+      const bool gt = valid && p[q] > th;
+      const bool eq = valid && p[q] == th;
+      const uint64_t eqm = __ballot(eq);
+      const uint32_t rank = rank_base + (uint32_t)__popcll(eqm & ((1ull << lane) - 1ull));
+      const bool take_eq = eq && (above + (float)rank * th < target);
+      sel[q] = __ballot(gt || take_eq);
+      rank_base += (uint32_t)__popcll(eqm);
+      count += (uint32_t)__popcll(sel[q]);
+    }
+    if (count > (uint32_t)cap || count == 0) fallback = true;
+  }
+  if (fallback) {
+    if (lane == 0) {
+      runs[r] = meff;
+      nsel[r] = ns;
+      atomicAdd(reinterpret_cast<unsigned long long*>(&counts->fallback), 1ull);
+    }
+    if (lane < 4) mask[4 * (uint64_t)r + lane] = ~0ull;
+    return;
+  }
+  // runs: a kept slot starts a run unless the previous slot is kept in the same interval
+  uint32_t nruns = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t s = (uint32_t)lane + 64u * q;
+    const bool mine = (sel[q] >> lane) & 1ull;
+    bool start = false;
+    if (mine) {
+      if (s == 0 || s % n == 0) start = true;
+      else {
+        const uint32_t ps = s - 1;
+        start = !((sel[ps / 64] >> (ps % 64)) & 1ull);
+      }
+    }
+    nruns += (uint32_t)__popcll(__ballot(start));
+  }
+  if (lane == 0) { runs[r] = nruns; nsel[r] = count; }
+  if (lane < 4) mask[4 * (uint64_t)r + lane] = lane == 0 ? sel[0] : (lane == 1 ? sel[1] : (lane == 2 ? sel[2] : sel[3]));
+}
+
+// ---- emission of the planned intervals: one lane per ray ------------------------------
+__global__ __launch_bounds__(kThreads) void k_prop_emit(uint32_t nr, IvSet iv, const uint64_t* __restrict__ mask,
+                                                        const uint32_t* __restrict__ pv_off,
+                                                        const uint32_t* __restrict__ ps_off,
+                                                        float* __restrict__ pt0, float* __restrict__ pdt,
+                                                        uint32_t* __restrict__ pkey, uint32_t* __restrict__ pray,
+                                                        uint32_t* __restrict__ pbase) {
+  const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
+  if (r >= nr) return;
+  const uint32_t i0 = iv.iv_off[r], meff = iv.iv_off[r + 1] - i0;
+  if (meff == 0) return;
+  const uint32_t ns = iv.smp_off[r + 1] - iv.smp_off[r];
+  const uint32_t n = ns / meff;
+  uint32_t out = pv_off[r], smp = ps_off[r];
+  const uint64_t m0 = mask[4 * (uint64_t)r], m1 = mask[4 * (uint64_t)r + 1], m2 = mask[4 * (uint64_t)r + 2],
+                 m3 = mask[4 * (uint64_t)r + 3];
+  auto kept = [&](uint32_t s) {
+    const uint64_t w = s < 64 ? m0 : (s < 128 ? m1 : (s < 192 ? m2 : m3));
+    return ((w >> (s % 64)) & 1ull) != 0;
+  };
+  uint32_t s = 0;
+  while (s < ns) {
+    if (!kept(s)) { ++s; continue; }
+    const uint32_t k = s / n, j0 = s - k * n;
+    uint32_t len = 1;
+    while (j0 + len < n && kept(s + len)) ++len;
+    const uint32_t i = i0 + k;
+    const float delta = iv.dt[i] / (float)n;
+    if (j0 == 0 && len == n) {          // the whole interval: keep it exactly
+      pt0[out] = iv.t0[i];
+      pdt[out] = iv.dt[i];
+    } else {
+      pt0[out] = fmaf((float)j0, delta, iv.t0[i]);
+      pdt[out] = (float)len * delta;
+    }
+    pkey[out] = key_slot(iv.key[i]) | (len << 16);
+    pray[out] = r;
+    pbase[out] = smp;
+    ++out;
+    smp += len;
+    s += len;
+  }
+}
+
+// ---- training --------------------------------------------------------------------------
+// Targets: per interval, bin opacity 1 - exp(-tau_b), tau_b = sum_j sigma_j len |slot_j n bin_b|.
+__global__ __launch_bounds__(kThreads) void k_prop_targets(IvSet iv, const float* __restrict__ smp_out,
+                                                           float* __restrict__ alpha) {
+  const uint32_t n_iv = *iv.n_iv_dev;
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n_iv; i += gridDim.x * kThreads) {
+    const uint32_t n = key_n(iv.key[i]);
+    const uint32_t base = iv.base[i];
+    const float len = iv.dt[i];
+    float tb[kBins];
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) tb[b] = 0.f;
+    for (uint32_t j = 0; j < n; ++j) {
+      const float sig = softplusf(smp_out[4 * (uint64_t)(base + j)]);
+      const float a0 = (float)j / (float)n, a1 = (float)(j + 1) / (float)n;
+#pragma unroll
+      for (int b = 0; b < kBins; ++b) {
+        const float ov = fminf(a1, (float)(b + 1) * (1.f / 32.f)) - fmaxf(a0, (float)b * (1.f / 32.f));
+        if (ov > 0.f) tb[b] = fmaf(sig * len, ov, tb[b]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBins; b += 4)
+      *reinterpret_cast<f32x4*>(alpha + (uint64_t)i * kBins + b) =
+          f32x4{-expm1f(-tb[b]), -expm1f(-tb[b + 1]), -expm1f(-tb[b + 2]), -expm1f(-tb[b + 3])};
+  }
+}
+
+constexpr int kTrNCB = 2;                       // 32 items per wave
+constexpr int kTrItems = 4 * 16 * kTrNCB;       // 128 items per block step
+constexpr int kTrRow = kTrItems * 4 + 16;       // staged float row + padding
+
+__device__ __forceinline__ void stf(uint8_t* base, int row, int col, float v) {
+  *reinterpret_cast<float*>(base + row * kTrRow + col * 4) = v;
+}
+__device__ __forceinline__ float ldf(const uint8_t* base, int row, int col) {
+  return *reinterpret_cast<const float*>(base + row * kTrRow + col * 4);
+}
+
+// Forward + backward of the proposal over a contiguous range of 128-item steps per block:
+// loss partial and dW/db partial per block (master layout).
+__global__ __launch_bounds__(kThreads) void k_prop_train(const uint8_t* __restrict__ packed, IvSet iv,
+                                                         const float* __restrict__ o, const float* __restrict__ d,
+                                                         int64_t stride, int64_t r0,
+                                                         const float* __restrict__ leafbox, int s_max,
+                                                         const float* __restrict__ alpha, float* __restrict__ part,
+                                                         float* __restrict__ loss_part) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const uint32_t wbytes = kF32Bytes;
+  uint8_t* s_dz = lds + wbytes;
+  uint8_t* s_h = s_dz + kH * kTrRow;
+  for (uint32_t i = threadIdx.x; i < wbytes / 16; i += kThreads)
+    reinterpret_cast<f32x4*>(lds)[i] = reinterpret_cast<const f32x4*>(packed)[i];
+  __syncthreads();
+  const float* bias = reinterpret_cast<const float*>(lds);
+  const uint8_t* units = lds + kBiasBytes;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, m = lane & 15;
+  const uint32_t n_items = *iv.n_iv_dev;
+  const uint32_t steps = (n_items + kTrItems - 1) / kTrItems;
+  const uint32_t sb = (uint32_t)(((uint64_t)blockIdx.x * steps) / gridDim.x);
+  const uint32_t se = (uint32_t)(((uint64_t)(blockIdx.x + 1) * steps) / gridDim.x);
+  const float scale = 1.f / ((float)n_items * (float)kBins);
+  // dW items: layer 0: rb 0..3 x ci 0..2 (48 input slots) -> 3 per wave; layer 1: 4 x 4 -> 4;
+  // layer 2: 2 x 4 -> 2.  Wave w owns rows of one output row block for each layer.
+  f32x4 aW0[3], aW1[4], aW2[2], aB0, aB1, aB2;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) { if (q < 3) aW0[q] = f32x4{0, 0, 0, 0}; aW1[q] = f32x4{0, 0, 0, 0}; if (q < 2) aW2[q] = f32x4{0, 0, 0, 0}; }
+  aB0 = aB1 = aB2 = f32x4{0, 0, 0, 0};
+  float lsum = 0.f;
+  for (uint32_t st = sb; st < se; ++st) {
+    const uint32_t base = st * kTrItems + wave * 16 * kTrNCB;
+    float X[kTrNCB][12];
+    bool valid[kTrNCB];
+#pragma unroll
+    for (int cb = 0; cb < kTrNCB; ++cb) {
+      const uint32_t it = base + cb * 16 + m;
+      valid[cb] = it < n_items;
+      float F[kIn];
+      item_features(iv, valid[cb] ? it : 0u, o, d, stride, r0, leafbox, s_max, F);
+#pragma unroll
+      for (int kb = 0; kb < 12; ++kb) X[cb][kb] = pick4(F, 4 * kb, g, kIn);
+    }
+    // forward
+    f32x4 H1[kTrNCB][4], H2[kTrNCB][4], Z3[kTrNCB][2];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
+#pragma unroll
+      for (int cb = 0; cb < kTrNCB; ++cb) H1[cb][rb] = bv;
+#pragma unroll
+      for (int ku = 0; ku < 3; ++ku) {
+        const f32x4 A = *reinterpret_cast<const f32x4*>(units + f32_unit(0, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int cb = 0; cb < kTrNCB; ++cb)
+            H1[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], X[cb][4 * ku + e], H1[cb][rb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < kTrNCB; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) H1[cb][rb][e] = fmaxf(H1[cb][rb][e], 0.f);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + kH + 16 * rb + 4 * g);
+#pragma unroll
+      for (int cb = 0; cb < kTrNCB; ++cb) H2[cb][rb] = bv;
+#pragma unroll
+      for (int ku = 0; ku < 4; ++ku) {
+        const f32x4 A = *reinterpret_cast<const f32x4*>(units + f32_unit(1, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int cb = 0; cb < kTrNCB; ++cb)
+            H2[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], H1[cb][ku][e], H2[cb][rb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < kTrNCB; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) H2[cb][rb][e] = fmaxf(H2[cb][rb][e], 0.f);
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 2 * kH + 16 * rb + 4 * g);
+#pragma unroll
+      for (int cb = 0; cb < kTrNCB; ++cb) Z3[cb][rb] = bv;
+#pragma unroll
+      for (int ku = 0; ku < 4; ++ku) {
+        const f32x4 A = *reinterpret_cast<const f32x4*>(units + f32_unit(2, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int cb = 0; cb < kTrNCB; ++cb)
+            Z3[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], H2[cb][ku][e], Z3[cb][rb], 0, 0, 0);
+      }
+    }
+    // loss and output gradient: alpha^ = 1 - exp(-softplus(z))
+    f32x4 dZ3[kTrNCB][2];
+#pragma unroll
+    for (int cb = 0; cb < kTrNCB; ++cb) {
+      const uint32_t it = base + cb * 16 + m;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        f32x4 tg = {0.f, 0.f, 0.f, 0.f};
+        if (valid[cb]) tg = *reinterpret_cast<const f32x4*>(alpha + (uint64_t)it * kBins + 16 * rb + 4 * g);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float z = Z3[cb][rb][e];
+          const float tau = softplusf(z);
+          const float et = expf(-tau);
+          const float err = (1.f - et) - tg[e];
+          lsum += valid[cb] ? err * err : 0.f;
+          dZ3[cb][rb][e] = valid[cb] ? 2.f * err * scale * et * logisticf(z) : 0.f;
+        }
+      }
+    }
+    // backward, layer 2 -> 0; stage dZ and inputs feature-major, then dW on MFMA (K = items)
+#pragma unroll
+    for (int layer = 2; layer >= 0; --layer) {
+      const int rbo = layer == 2 ? 2 : 4;
+      const int cbi = layer == 0 ? 3 : 4;
+      __syncthreads();
+#pragma unroll
+      for (int cb = 0; cb < kTrNCB; ++cb) {
+        const int col = wave * 16 * kTrNCB + cb * 16 + m;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          if (rb >= rbo) break;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float v = layer == 2 ? dZ3[cb][rb < 2 ? rb : 0][e] : (layer == 1 ? H2[cb][rb][e] : H1[cb][rb][e]);
+            stf(s_dz, 16 * rb + 4 * g + e, col, v);
+          }
+        }
+        if (layer == 0) {
+#pragma unroll
+          for (int kb = 0; kb < 12; ++kb) stf(s_h, 4 * kb + g, col, X[cb][kb]);
+        } else {
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) stf(s_h, 16 * rb + 4 * g + e, col, layer == 2 ? H2[cb][rb][e] : H1[cb][rb][e]);
+        }
+      }
+      __syncthreads();
+      // H2/H1 staged into s_dz above hold dZ for layers 1 and 0 (see the chain below)
+      const int n_items_l = rbo * cbi;
+      const int per = (n_items_l + 3) / 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int item = wave * per + q;
+        if (q >= per || item >= n_items_l) break;
+        const int rb = item / cbi, ci = item % cbi;
+        f32x4 acc = layer == 2 ? aW2[q < 2 ? q : 0] : (layer == 1 ? aW1[q] : aW0[q < 3 ? q : 0]);
+        f32x4 accb = layer == 2 ? aB2 : (layer == 1 ? aB1 : aB0);
+        for (int kb = 0; kb < kTrItems / 4; ++kb) {
+          const float a = ldf(s_dz, 16 * rb + m, 4 * kb + g);
+          const float bm = ldf(s_h, 16 * ci + m, 4 * kb + g);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bm, acc, 0, 0, 0);
+          if (ci == 0) accb = __builtin_amdgcn_mfma_f32_16x16x4f32(a, 1.f, accb, 0, 0, 0);
+        }
+        if (layer == 2) { aW2[q < 2 ? q : 0] = acc; if (ci == 0) aB2 = accb; }
+        else if (layer == 1) { aW1[q] = acc; if (ci == 0) aB1 = accb; }
+        else { aW0[q < 3 ? q : 0] = acc; if (ci == 0) aB0 = accb; }
+      }
+      if (layer == 0) break;
+      // chain: dH = W^T dZ, masked by the forward activation, becomes dZ of the layer below
+      if (layer == 2) {
+#pragma unroll
+        for (int cb = 0; cb < kTrNCB; ++cb)
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ku = 0; ku < 2; ++ku) {
+              const f32x4 A = *reinterpret_cast<const f32x4*>(units + (f32_bwd_unit(2, rb, ku) - kF32Units + kF32Units) * kUnitBytes + lane * 16);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], dZ3[cb][ku][e], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) H2[cb][rb][e] = H2[cb][rb][e] > 0.f ? acc[e] : 0.f;
+          }
+      } else {
+#pragma unroll
+        for (int cb = 0; cb < kTrNCB; ++cb) {
+          f32x4 nd[4];
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ku = 0; ku < 4; ++ku) {
+              const f32x4 A = *reinterpret_cast<const f32x4*>(units + f32_bwd_unit(1, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], H2[cb][ku][e], acc, 0, 0, 0);
+            }
+            nd[rb] = acc;
+          }
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) H1[cb][rb][e] = H1[cb][rb][e] > 0.f ? nd[rb][e] : 0.f;
+        }
+      }
+    }
+  }
+  // partial gradient of this block, master layout
+  float* dst = part + (uint64_t)blockIdx.x * kP;
+#pragma unroll
+  for (int layer = 0; layer <= 2; ++layer) {
+    const int rbo = layer == 2 ? 2 : 4;
+    const int cbi = layer == 0 ? 3 : 4;
+    const int n_items_l = rbo * cbi;
+    const int per = (n_items_l + 3) / 4;
+    const int din = layer == 0 ? kIn : kH;
+    const int offw = layer == 0 ? kW0 : (layer == 1 ? kW1 : kW2);
+    const int offb = layer == 0 ? kB0 : (layer == 1 ? kB1 : kB2);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int item = wave * per + q;
+      if (q >= per || item >= n_items_l) break;
+      const int rb = item / cbi, ci = item % cbi;
+      const f32x4 acc = layer == 2 ? aW2[q < 2 ? q : 0] : (layer == 1 ? aW1[q] : aW0[q < 3 ? q : 0]);
+      const f32x4 accb = layer == 2 ? aB2 : (layer == 1 ? aB1 : aB0);
+      const int col = 16 * ci + m;   // staged input row: feature index (layer 0: slot 4 kb + g == feature)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int out = 16 * rb + 4 * g + e;
+        if (col < din) dst[offw + out * din + col] = acc[e];
+        if (ci == 0 && m == 0) dst[offb + out] = accb[e];
+      }
+    }
+  }
+  // loss partial
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+  __shared__ float lsh[4];
+  if (lane == 0) lsh[wave] = lsum;
+  __syncthreads();
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = (lsh[0] + lsh[1]) + (lsh[2] + lsh[3]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_prop_reduce(const float* __restrict__ part, uint32_t nb,
+                                                          const float* __restrict__ loss_part,
+                                                          uint32_t n_items_unused, float* __restrict__ grad,
+                                                          float* __restrict__ loss, const uint32_t* __restrict__ n_iv) {
+  for (uint32_t p = blockIdx.x * kThreads + threadIdx.x; p < (uint32_t)kP; p += gridDim.x * kThreads) {
+    float s = 0.f;
+    for (uint32_t b = 0; b < nb; ++b) s += part[(uint64_t)b * kP + p];
+    grad[p] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    float s = 0.f;
+    for (uint32_t b = 0; b < nb; ++b) s += loss_part[b];
+    loss[0] = s / ((float)(*n_iv) * (float)kBins);
+  }
+}
+
+int g_ncu = 0;
+hipError_t ncu(int* out) {
+  if (g_ncu == 0) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&g_ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+  }
+  *out = g_ncu;
+  return hipSuccess;
+}
+
+}  // namespace
+
+int prop_param_count() { return kP; }
+size_t prop_packed_bytes(int dtype) { return dtype == AMNERF_BF16 ? kBf16Bytes : kF32Bytes; }
+uint32_t prop_train_blocks() {
+  int n = 0;
+  ncu(&n);
+  return (uint32_t)(n > 0 ? n : 256);
+}
+
+hipError_t launch_prop_pack(int dtype, const float* master, void* packed, hipStream_t st) {
+  hipLaunchKernelGGL(k_prop_pack, dim3(64), dim3(256), 0, st, dtype, master, (uint8_t*)packed);
+  return hipGetLastError();
+}
+
+hipError_t launch_prop_fwd(int dtype, const void* packed, const IvSet& iv, const float* o, const float* d,
+                           int64_t stride, int64_t r0, const float* leafbox, int s_max, uint32_t n_iv_max,
+                           float* tau, hipStream_t st) {
+  int n = 0;
+  hipError_t e = ncu(&n);
+  if (e != hipSuccess) return e;
+  uint32_t tiles = (n_iv_max + 255) / 256;
+  uint32_t grid = std::min<uint32_t>(tiles > 0 ? tiles : 1, (uint32_t)n * 4);
+  if (dtype == AMNERF_BF16)
+    hipLaunchKernelGGL(k_prop_fwd<true>, dim3(grid), dim3(kThreads), kBf16Bytes, st, (const uint8_t*)packed, iv, o,
+                       d, stride, r0, leafbox, s_max, tau);
+  else
+    hipLaunchKernelGGL(k_prop_fwd<false>, dim3(grid), dim3(kThreads), kBiasBytes + kF32Units * kUnitBytes, st,
+                       (const uint8_t*)packed, iv, o, d, stride, r0, leafbox, s_max, tau);
+  return hipGetLastError();
+}
+
+hipError_t launch_prop_select(uint32_t nr, const IvSet& iv, const float* tau, float mass_thresh, int cap,
+                              uint32_t* runs, uint32_t* nsel, uint64_t* mask, float* mass, ChunkCounts* counts,
+                              hipStream_t st) {
+  if (nr == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prop_select, dim3((nr + 3) / 4), dim3(kThreads), 0, st, nr, iv, tau, mass_thresh, cap, runs,
+                     nsel, mask, mass, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_prop_emit(uint32_t nr, const IvSet& iv, const uint64_t* mask, const uint32_t* pv_off,
+                            const uint32_t* ps_off, float* pt0, float* pdt, uint32_t* pkey, uint32_t* pray,
+                            uint32_t* pbase, hipStream_t st) {
+  if (nr == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prop_emit, dim3((nr + kThreads - 1) / kThreads), dim3(kThreads), 0, st, nr, iv, mask, pv_off,
+                     ps_off, pt0, pdt, pkey, pray, pbase);
+  return hipGetLastError();
+}
+
+hipError_t launch_prop_targets(const IvSet& iv, const float* smp_out, float* alpha, hipStream_t st) {
+  hipLaunchKernelGGL(k_prop_targets, dim3(2048), dim3(kThreads), 0, st, iv, smp_out, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_prop_train(const void* packed, const IvSet& iv, const float* o, const float* d, int64_t stride,
+                             int64_t r0, const float* leafbox, int s_max, const float* alpha, float* part,
+                             float* loss_part, float* grad, float* loss, hipStream_t st) {
+  const uint32_t nb = prop_train_blocks();
+  const uint32_t lds = kF32Bytes + 2u * kH * kTrRow;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_prop_train, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_prop_train, dim3(nb), dim3(kThreads), lds, st, (const uint8_t*)packed, iv, o, d, stride, r0,
+                     leafbox, s_max, alpha, part, loss_part);
+  hipLaunchKernelGGL(k_prop_reduce, dim3(36), dim3(kThreads), 0, st, part, nb, loss_part, 0u, grad, loss, iv.n_iv_dev);
+  return hipGetLastError();
+}
+
+}  // namespace amn

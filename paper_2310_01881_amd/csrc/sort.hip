@@ -147,16 +147,13 @@ __global__ __launch_bounds__(1024) void k_bucket_tiles(const uint32_t* __restric
 // writes all of their samples with consecutive threads on consecutive sorted positions
 // (each thread finds its interval by binary search over the staged sample bases).
 __global__ __launch_bounds__(kThreads) void k_expand(
-    const uint32_t* __restrict__ sidx, const uint32_t* __restrict__ ssb,
-    const uint32_t* __restrict__ n_iv_dev, const float* __restrict__ iv_t0,
-    const float* __restrict__ iv_dt, const uint32_t* __restrict__ iv_key,
-    const uint32_t* __restrict__ iv_ray, const uint32_t* __restrict__ iv_off,
-    const uint32_t* __restrict__ smp_off, int64_t r0, int jitter, uint64_t seed,
-    uint32_t* __restrict__ srec_ray, float* __restrict__ srec_t, uint32_t* __restrict__ perm) {
+    const uint32_t* __restrict__ sidx, const uint32_t* __restrict__ ssb, IvSet iv, int64_t r0,
+    int jitter, uint64_t seed, uint32_t* __restrict__ srec_ray, float* __restrict__ srec_t,
+    uint32_t* __restrict__ perm) {
   __shared__ uint32_t sh_base[kThreads + 1];
   __shared__ uint32_t sh_ray[kThreads], sh_rm[kThreads];
   __shared__ float sh_t0[kThreads], sh_delta[kThreads], sh_u[kThreads];
-  const uint32_t n_iv = *n_iv_dev;
+  const uint32_t n_iv = *iv.n_iv_dev;
   const uint32_t n_groups = (n_iv + kThreads - 1) / kThreads;
   for (uint32_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
     const uint32_t p0 = grp * kThreads;
@@ -164,14 +161,14 @@ __global__ __launch_bounds__(kThreads) void k_expand(
     const uint32_t p = p0 + threadIdx.x;
     if (threadIdx.x < cnt) {
       uint32_t i = sidx[p];
-      uint32_t ray = iv_ray[i];
-      uint32_t n = key_n(iv_key[i]);
-      uint32_t k = i - iv_off[ray];
+      uint32_t ray = iv.ray[i];
+      uint32_t n = key_n(iv.key[i]);
+      uint32_t k = i - iv.iv_off[ray];
       sh_base[threadIdx.x] = ssb[p];
       sh_ray[threadIdx.x] = ray;
-      sh_rm[threadIdx.x] = smp_off[ray] + k * n;   // ray-major index of the first sample
-      sh_t0[threadIdx.x] = iv_t0[i];
-      sh_delta[threadIdx.x] = iv_dt[i] / (float)n;
+      sh_rm[threadIdx.x] = iv.base[i];   // ray-major index of the first sample
+      sh_t0[threadIdx.x] = iv.t0[i];
+      sh_delta[threadIdx.x] = iv.dt[i] / (float)n;
       sh_u[threadIdx.x] = stratum_u(jitter, seed, (uint64_t)(r0 + ray), k);
     }
     if (threadIdx.x == 0) sh_base[cnt] = ssb[p0 + cnt];
@@ -240,13 +237,11 @@ hipError_t launch_bucket_tiles(const SortPlan& p, const uint32_t* mat_scan, cons
   return hipGetLastError();
 }
 
-hipError_t launch_expand(const uint32_t* sidx, const uint32_t* ssb, const uint32_t* n_iv_dev,
-                         const float* iv_t0, const float* iv_dt, const uint32_t* iv_key,
-                         const uint32_t* iv_ray, const uint32_t* iv_off, const uint32_t* smp_off,
-                         int64_t r0, int jitter, uint64_t seed, uint32_t* srec_ray, float* srec_t,
-                         uint32_t* perm, hipStream_t st) {
-  hipLaunchKernelGGL(k_expand, dim3(4096), dim3(kThreads), 0, st, sidx, ssb, n_iv_dev, iv_t0, iv_dt,
-                     iv_key, iv_ray, iv_off, smp_off, r0, jitter, seed, srec_ray, srec_t, perm);
+hipError_t launch_expand(const uint32_t* sidx, const uint32_t* ssb, const IvSet& iv, int64_t r0,
+                         int jitter, uint64_t seed, uint32_t* srec_ray, float* srec_t, uint32_t* perm,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_expand, dim3(4096), dim3(kThreads), 0, st, sidx, ssb, iv, r0, jitter, seed,
+                     srec_ray, srec_t, perm);
   return hipGetLastError();
 }
 

@@ -66,18 +66,15 @@ __device__ __forceinline__ float suffix_excl(float v, int lane) {
 //             + g_A (T_{j+1} - sum_{i>j} w_i),
 // dL/dsigma^_j = dL/dtau_j delta_j logistic(sigma^_j), dL/dc^_j = g w_j c_j (1 - c_j).
 __global__ __launch_bounds__(kThreads) void k_comp_bwd(
-    uint32_t nr, const uint32_t* __restrict__ iv_off, const uint32_t* __restrict__ smp_off,
-    const float* __restrict__ iv_t0, const float* __restrict__ iv_dt,
-    const uint32_t* __restrict__ iv_key, const float* __restrict__ smp_out, int64_t r0, int jitter,
+    uint32_t nr, IvSet iv, const float* __restrict__ smp_out, int64_t r0, int jitter,
     uint64_t seed, float eps, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
     const float* __restrict__ g_opac, float* __restrict__ gpre) {
   const int lane = threadIdx.x & 63;
   const uint32_t r = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (r >= nr) return;
-  const uint32_t i0 = iv_off[r], m = iv_off[r + 1] - i0;
-  const uint32_t s0 = smp_off[r], ns = smp_off[r + 1] - s0;
+  const uint32_t i0 = iv.iv_off[r], i1 = iv.iv_off[r + 1];
+  const uint32_t s0 = iv.smp_off[r], ns = iv.smp_off[r + 1] - s0;
   if (ns == 0) return;
-  const uint32_t n = ns / m;
   const float gr = g_rgb[3 * (uint64_t)(r0 + r)], gg = g_rgb[3 * (uint64_t)(r0 + r) + 1],
               gb = g_rgb[3 * (uint64_t)(r0 + r) + 2];
   const float gd = g_depth ? g_depth[r0 + r] : 0.f;
@@ -85,11 +82,12 @@ __global__ __launch_bounds__(kThreads) void k_comp_bwd(
   constexpr int kMaxSteps = (AMNERF_MAX_SAMPLES + 63) / 64;
   DF carry_at[kMaxSteps];
   auto sample = [&](uint32_t j, float& tau, float& delta, float& t, float4& z) {
-    const uint32_t k = j / n, jj = j - k * n;
+    const uint32_t i = find_interval(iv.base, i0, i1, s0 + j);
+    const uint32_t jj = s0 + j - iv.base[i];
     z = *reinterpret_cast<const float4*>(smp_out + 4 * (uint64_t)(s0 + j));
-    delta = iv_dt[i0 + k] / (float)n;
-    const float u = stratum_u(jitter, seed, (uint64_t)(r0 + r), k);
-    t = sample_t(iv_t0[i0 + k], delta, jj, u);
+    delta = iv.dt[i] / (float)key_n(iv.key[i]);
+    const float u = stratum_u(jitter, seed, (uint64_t)(r0 + r), i - i0);
+    t = sample_t(iv.t0[i], delta, jj, u);
     tau = softplusf(z.x) * delta;
   };
   // pass 1: forward scan, termination sample
@@ -252,15 +250,13 @@ __global__ __launch_bounds__(kThreads) void k_adam(int64_t n, float* __restrict_
 
 }  // namespace
 
-hipError_t launch_comp_bwd(uint32_t nr, const uint32_t* iv_off, const uint32_t* smp_off, const float* iv_t0,
-                           const float* iv_dt, const uint32_t* iv_key, const float* smp_out, int64_t r0,
-                           int jitter, uint64_t seed, float eps, const float* g_rgb, const float* g_depth,
+hipError_t launch_comp_bwd(uint32_t nr, const IvSet& iv, const float* smp_out, int64_t r0, int jitter,
+                           uint64_t seed, float eps, const float* g_rgb, const float* g_depth,
                            const float* g_opac, float* gpre, hipStream_t st) {
   if (nr == 0) return hipSuccess;
   const uint32_t rays_per_block = kThreads / 64;
   hipLaunchKernelGGL(k_comp_bwd, dim3((nr + rays_per_block - 1) / rays_per_block), dim3(kThreads), 0, st, nr,
-                     iv_off, smp_off, iv_t0, iv_dt, iv_key, smp_out, r0, jitter, seed, eps, g_rgb, g_depth,
-                     g_opac, gpre);
+                     iv, smp_out, r0, jitter, seed, eps, g_rgb, g_depth, g_opac, gpre);
   return hipGetLastError();
 }
 

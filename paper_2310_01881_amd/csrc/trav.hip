@@ -49,7 +49,7 @@ template <bool EMIT>
 __device__ int traverse(const DevNode* __restrict__ nodes, const float o[3], const float dir[3],
                         int cap, uint32_t n_per, uint32_t ray, int* st_node, float* st_hi,
                         float* st_lo, float* iv_t0, float* iv_dt, uint32_t* iv_key,
-                        uint32_t* iv_ray) {
+                        uint32_t* iv_ray, uint32_t* iv_base, uint32_t smp_base) {
   // root box [0,1]^3
   DF tin = {0.f, 0.f}, tout = {__builtin_inff(), 0.f};
   bool hit = true;
@@ -106,6 +106,7 @@ __device__ int traverse(const DevNode* __restrict__ nodes, const float o[3], con
         iv_dt[m] = dt;
         iv_key[m] = (uint32_t)(-(info + 1)) | (n_per << 16);
         iv_ray[m] = ray;
+        iv_base[m] = smp_base + (uint32_t)m * n_per;
       }
     }
     ++m;
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict
   // skip the descent for a wave whose rays are all out of range
   if (__ballot(live) != 0 && live)
     m = traverse<false>(nodes, oo, dd, s_max, 0, 0, st_node + threadIdx.x, st_hi + threadIdx.x,
-                        st_lo + threadIdx.x, nullptr, nullptr, nullptr, nullptr);
+                        st_lo + threadIdx.x, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
   if (live) {
     uint32_t meff = m <= s_max ? (uint32_t)m : (uint32_t)s_max;
     uint32_t nper = m == 0 ? 0u : (m <= s_max ? (uint32_t)(s_max / m) : 1u);
@@ -157,10 +158,12 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
                                                       const uint32_t* __restrict__ cnt_iv,
                                                       const uint32_t* __restrict__ cnt_smp,
                                                       const uint32_t* __restrict__ iv_off,
+                                                      const uint32_t* __restrict__ smp_off,
                                                       float* __restrict__ iv_t0,
                                                       float* __restrict__ iv_dt,
                                                       uint32_t* __restrict__ iv_key,
-                                                      uint32_t* __restrict__ iv_ray) {
+                                                      uint32_t* __restrict__ iv_ray,
+                                                      uint32_t* __restrict__ iv_base) {
   __shared__ int st_node[kStack * kBlock];
   __shared__ float st_hi[kStack * kBlock];
   __shared__ float st_lo[kStack * kBlock];
@@ -176,7 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
   uint32_t nper = cnt_smp[r] / meff;
   uint32_t base = iv_off[r];
   traverse<true>(nodes, oo, dd, (int)meff, nper, r, st_node + threadIdx.x, st_hi + threadIdx.x,
-                 st_lo + threadIdx.x, iv_t0 + base, iv_dt + base, iv_key + base, iv_ray + base);
+                 st_lo + threadIdx.x, iv_t0 + base, iv_dt + base, iv_key + base, iv_ray + base,
+                 iv_base + base, smp_off[r]);
 }
 
 }  // namespace
@@ -193,12 +197,13 @@ hipError_t launch_trav_count(const DevNode* nodes, const float* o, const float* 
 
 hipError_t launch_trav_emit(const DevNode* nodes, const float* o, const float* d,
                             int64_t ray_stride, int64_t r0, uint32_t nr, const uint32_t* cnt_iv,
-                            const uint32_t* cnt_smp, const uint32_t* iv_off, float* iv_t0,
-                            float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray, hipStream_t st) {
+                            const uint32_t* cnt_smp, const uint32_t* iv_off, const uint32_t* smp_off,
+                            float* iv_t0, float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray,
+                            uint32_t* iv_base, hipStream_t st) {
   if (nr == 0) return hipSuccess;
   uint32_t grid = (nr + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_trav_emit, dim3(grid), dim3(kBlock), 0, st, nodes, o, d, ray_stride, r0, nr,
-                     cnt_iv, cnt_smp, iv_off, iv_t0, iv_dt, iv_key, iv_ray);
+                     cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base);
   return hipGetLastError();
 }
 
