@@ -3,12 +3,15 @@
 
 One step renders one 800x800 frame (640 000 rays) of the seeded 128^3-grid scene with a
 512-leaf KD tree and 4x64 per-leaf MLPs, at most 128 samples per ray, through the whole
-path: traversal -> per-leaf samples -> sort by leaf -> grouped MLP -> compositing.
-Rays of 8 cameras are resident in HBM before the timed region; step k renders camera
-k mod 8.  The float32 path and the bfloat16 path are both timed; the JSON line's `value`
-is the bfloat16 path's samples/s (samples evaluated by the MLPs), `ms_per_step` its
+path: traversal -> (learned proposal) -> per-leaf samples -> sort by leaf -> grouped MLP
+-> compositing.  Rays of 8 held-out cameras are resident in HBM before the timed region;
+step k renders camera k mod 8.  Three paths are timed: plain float32, plain bfloat16, and
+bfloat16 with the learned proposal (bfloat16 inference, <= 48 samples per ray, fallback
+below 0.99 predicted mass).  The proposal is first trained (untimed) by the library's own
+kernels on plain-render targets from 200 seeded training cameras.  `value` is the
+proposal path's samples/s (samples evaluated by the leaf MLPs) and `ms_per_step` its
 ms/frame.  The oracle (float64, CPU) renders a bounded random subset of camera 0's rays:
-that gives the CPU baseline and the PSNR of both GPU paths against the oracle.
+that gives the CPU baseline and the PSNR of each GPU path against the oracle.
 """
 from __future__ import annotations
 
@@ -24,7 +27,6 @@ sys.path.insert(0, ROOT)
 
 FLOP_PER_SAMPLE_4x64 = 2 * (30 * 64 + 3 * 64 * 64 + 64 * 4)   # 28 928, unpadded
 PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
-HBM_PEAK_GBS = 8000.0
 
 
 def log(msg):
@@ -44,7 +46,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time")
+    ap.add_argument("--prop-steps", type=int, default=1500, help="proposal training steps (untimed)")
+    ap.add_argument("--prop-batch", type=int, default=32768)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -77,26 +81,56 @@ def main():
         o, d = synth.camera_rays(c)
         rays.append((torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)))
     R = cfg.width * cfg.height
+
+    # ---- learned proposal, trained by the library (untimed) ----
+    t0 = time.perf_counter()
+    prop = am.Proposal(ctx, torch.from_numpy(synth.make_prop_weights(cfg.seed_proposal)).to(dev))
+    train_cams = synth.make_cameras(200, cfg.seed_batches, cfg.width, cfg.height)
+    pool_o, pool_d = synth.random_pixel_rays(train_cams, 2_000_000, cfg.seed_batches + 1)
+    pool_o, pool_d = torch.from_numpy(pool_o).to(dev), torch.from_numpy(pool_d).to(dev)
+    gen = torch.Generator(device=dev).manual_seed(cfg.seed_batches + 2)
+    losses = []
+    for it in range(args.prop_steps):
+        lr = 3e-3 if it < 0.7 * args.prop_steps else 1e-3
+        idx = torch.randint(0, pool_o.shape[1], (args.prop_batch,), device=dev, generator=gen)
+        loss = prop.train_step(tree, mlps["f32"].desc, pool_o[:, idx].contiguous(), pool_d[:, idx].contiguous(),
+                               cfg.s_max, lr=lr)
+        if it % 100 == 0 or it == args.prop_steps - 1:
+            losses.append(float(loss.item()))
+    prop.repack()
+    torch.cuda.synchronize()
+    t_prop = time.perf_counter() - t0
+    log("proposal: %d steps of %d rays in %.1f s, loss %s" % (args.prop_steps, args.prop_batch, t_prop,
+                                                             ["%.2e" % v for v in losses]))
+    desc = prop.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
+
+    paths = {"f32": ("f32", None), "bf16": ("bf16", None), "bf16_prop": ("bf16", desc)}
     outs = {k: {"rgb": torch.empty((R, 3), device=dev), "depth": torch.empty(R, device=dev),
-                "opacity": torch.empty(R, device=dev)} for k in mlps}
+                "opacity": torch.empty(R, device=dev)} for k in paths}
 
     def render(kind, cam):
         o, d = rays[cam]
         ob = outs[kind]
-        am.amnerf_render(ctx.h, tree.h, mlps[kind].desc, o, d, cfg.s_max, ob["rgb"], ob["depth"],
-                         ob["opacity"], None, cfg.ert_eps)
+        mk, pd = paths[kind]
+        am.amnerf_render(ctx.h, tree.h, mlps[mk].desc, o, d, cfg.s_max, ob["rgb"], ob["depth"], ob["opacity"],
+                         None, cfg.ert_eps, proposal=pd)
 
     # samples per camera (untimed)
-    samples = []
-    for cam in range(n_cams):
-        render("f32", cam)
-        samples.append(am.amnerf_render_stats_get(ctx.h)["n_samples"])
+    samples = {k: [] for k in paths}
+    fallback = []
+    for kind in paths:
+        for cam in range(n_cams):
+            render(kind, cam)
+            st = am.amnerf_render_stats_get(ctx.h)
+            samples[kind].append(st["n_samples"])
+            if kind == "bf16_prop":
+                fallback.append(st["n_fallback"])
     torch.cuda.synchronize()
-    log("samples per frame: %s" % samples)
+    log("samples per frame: plain %s, proposal %s, fallback rays %s" % (samples["f32"], samples["bf16_prop"], fallback))
 
     results = {}
     am.amnerf_ctx_set_timing(ctx.h, True)
-    for kind in ("f32", "bf16"):
+    for kind in paths:
         for w in range(args.warmup):
             render(kind, w % n_cams)
         torch.cuda.synchronize()
@@ -107,13 +141,15 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         stage_ms, npass = am.amnerf_timing_collect(ctx.h)
-        n_s = sum(samples[k % n_cams] for k in range(args.steps))
+        n_s = sum(samples[kind][k % n_cams] for k in range(args.steps))
         mlp_ms = stage_ms["mlp"] / max(npass, 1)
         flops = FLOP_PER_SAMPLE_4x64 * n_s / args.steps
         results[kind] = {
             "ms_per_frame": 1e3 * dt / args.steps,
             "samples_per_s": n_s / dt,
+            "samples_per_frame": n_s / args.steps,
             "stage_ms_per_frame": {k: v / max(npass, 1) for k, v in stage_ms.items()},
+            "mlp_ms": mlp_ms,
             "mlp_tflops": flops / (mlp_ms * 1e-3) / 1e12,
         }
         log("%s: %.3f ms/frame, %.3e samples/s, stages %s" % (
@@ -123,13 +159,13 @@ def main():
 
     # outputs of camera 0 for the accuracy report
     imgs = {}
-    for kind in mlps:
+    for kind in paths:
         render(kind, 0)
         torch.cuda.synchronize()
         imgs[kind] = outs[kind]["rgb"].cpu().numpy().astype(np.float64)
 
     cpu = None
-    psnr = {k: None for k in mlps}
+    psnr = {k: None for k in paths}
     if not args.no_cpu:
         import oracle
         otree = oracle.build_tree(grid, cfg.grid_n, cfg.max_depth, cfg.max_leaves)
@@ -137,27 +173,28 @@ def main():
         o0, d0 = synth.camera_rays(cams[0])
         threads = cpu_threads()
         rng = np.random.default_rng(12345)
-        probe = np.sort(rng.choice(R, 2000, replace=False))
+        probe = np.sort(rng.choice(R, 4000, replace=False))
+        oracle.render(otree, W, cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max, eps=cfg.ert_eps, ray_idx=probe,
+                      threads=threads)
         t0 = time.perf_counter()
-        oracle.render(otree, W, cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max, eps=cfg.ert_eps,
-                      ray_idx=probe, threads=threads)
+        oracle.render(otree, W, cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max, eps=cfg.ert_eps, ray_idx=probe,
+                      threads=threads)
         per_ray = (time.perf_counter() - t0) / len(probe)
-        n_sample = int(min(R, max(2000, args.cpu_seconds / max(per_ray, 1e-9))))
+        n_sample = int(min(R, max(4000, args.cpu_seconds / max(per_ray, 1e-9))))
         sel = np.sort(rng.choice(R, n_sample, replace=False))
         t0 = time.perf_counter()
         rgb, dep, op, ns, flags = oracle.render(otree, W, cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max,
                                                 eps=cfg.ert_eps, ray_idx=sel, threads=threads)
         t_cpu = time.perf_counter() - t0
         cpu = {"value": float(ns.sum()) / t_cpu, "unit": "samples/s", "cores": threads, "kind": "oracle",
-               "sample": "%d random rays of camera 0 (%.1f%% of one 800x800 frame, %d samples), "
-                         "float64, %.1f s" % (n_sample, 100.0 * n_sample / R, int(ns.sum()), t_cpu)}
-        for kind in mlps:
+               "sample": "%d random rays of held-out camera 0 (%.1f%% of one 800x800 frame, %d samples), "
+                         "float64 plain render, %.1f s" % (n_sample, 100.0 * n_sample / R, int(ns.sum()), t_cpu)}
+        for kind in paths:
             psnr[kind] = oracle.psnr(imgs[kind][sel], rgb)
-        log("oracle: %.3e samples/s on %d threads; psnr f32 %.2f dB, bf16 %.2f dB" % (
-            cpu["value"], threads, psnr["f32"], psnr["bf16"]))
+        log("oracle: %.3e samples/s on %d threads; psnr %s" % (cpu["value"], threads,
+                                                              {k: round(v, 2) for k, v in psnr.items()}))
 
-    head = results["bf16"]
-    mlp_ms = head["stage_ms_per_frame"]["mlp"]
+    head = results["bf16_prop"]
     achieved = head["mlp_tflops"]
     traffic = None
     prof = os.path.join(ROOT, "profiles", "mlp_bf16_c2_traffic.json")
@@ -181,20 +218,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": "800x800 frame, 128^3 guidance grid (200 anisotropic blobs + ground slab), "
                                "512-leaf KD tree (max depth 12), 4x64 per-leaf MLPs, <=128 samples/ray, "
-                               "ERT at T<1e-4; 8 cameras",
-                   "rays_per_step": R, "samples_per_step": sum(samples) / n_cams, "n_leaves": L,
-                   "path": "bf16 plain (no proposal)"},
+                               "ERT at T<1e-4; 8 held-out cameras",
+                   "rays_per_step": R, "n_leaves": L, "path": "bf16 leaf MLPs + learned proposal (bf16 inference, "
+                   "<=48 samples/ray, fallback below 0.99 predicted mass)",
+                   "plain_samples_per_step": sum(samples["f32"]) / n_cams,
+                   "proposal_samples_per_step": sum(samples["bf16_prop"]) / n_cams,
+                   "fallback_rays_per_step": sum(fallback) / n_cams,
+                   "proposal_training": {"steps": args.prop_steps, "rays_per_step": args.prop_batch,
+                                         "cameras": 200, "seconds": t_prop, "loss_first_last": [losses[0], losses[-1]]}},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS["bf16"], "traffic": traffic,
-                     "kernel": "k_mlp<64,bf16>", "kernel_ms": mlp_ms},
+                     "kernel": "k_mlp<64,bf16>", "kernel_ms": head["mlp_ms"]},
         "cpu_baseline": cpu,
-        "plain_fp32": {"ms_per_frame": results["f32"]["ms_per_frame"],
-                       "samples_per_s": results["f32"]["samples_per_s"],
-                       "mlp_tflops": results["f32"]["mlp_tflops"],
-                       "mlp_frac_of_fp32_peak": results["f32"]["mlp_tflops"] / PEAK_TFLOPS["f32"],
-                       "stage_ms_per_frame": results["f32"]["stage_ms_per_frame"],
-                       "psnr_vs_oracle_db": psnr["f32"]},
-        "bf16": {"stage_ms_per_frame": head["stage_ms_per_frame"], "psnr_vs_oracle_db": psnr["bf16"]},
+        "psnr_vs_oracle_db": psnr,
+        "speedup_vs_plain_fp32": results["f32"]["ms_per_frame"] / head["ms_per_frame"],
+        "paths": results,
     }
     print(json.dumps(line), flush=True)
 

@@ -252,11 +252,12 @@ int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* out, void* stre
 
 /* ---- stage timing -------------------------------------------------------------------- */
 #define AMNERF_STAGE_TRAVERSE 0   /* both traversal passes and the per-ray offset scans */
-#define AMNERF_STAGE_SORT 1       /* slot histogram, scans, stable scatter, bucket/tile offsets */
-#define AMNERF_STAGE_EXPAND 2     /* sorted interval -> per-sample records */
-#define AMNERF_STAGE_MLP 3        /* grouped per-leaf MLP */
-#define AMNERF_STAGE_COMPOSITE 4  /* front-to-back compositing */
-#define AMNERF_N_STAGES 5
+#define AMNERF_STAGE_PROPOSAL 1   /* proposal inference, selection and planned intervals */
+#define AMNERF_STAGE_SORT 2       /* slot histogram, scans, stable scatter, bucket/tile offsets */
+#define AMNERF_STAGE_EXPAND 3     /* sorted interval -> per-sample records */
+#define AMNERF_STAGE_MLP 4        /* grouped per-leaf MLP */
+#define AMNERF_STAGE_COMPOSITE 5  /* front-to-back compositing */
+#define AMNERF_N_STAGES 6
 
 /* Turns per-stage timing on or off.  When on, every render records HIP events between
  * its stages on the render stream (no host synchronisation). */

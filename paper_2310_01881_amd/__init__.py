@@ -42,7 +42,7 @@ EXPORTS = [
 AMNERF_PROPOSE_INFER = 0
 AMNERF_PROPOSE_TRAIN = 1
 AMNERF_GRAD_ONLY = 1
-STAGES = ["traverse", "sort", "expand", "mlp", "composite"]
+STAGES = ["traverse", "proposal", "sort", "expand", "mlp", "composite"]
 
 
 class AmnerfError(RuntimeError):

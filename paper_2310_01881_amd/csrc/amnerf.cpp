@@ -688,6 +688,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
     HIP_TRY(launch_scan_u32(w.cnt_smp, w.smp_off, nr, nullptr, w.scan_tmp, st));
     HIP_TRY(launch_trav_emit(tree->dev_nodes, rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
                              w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, st));
+    HIP_TRY(mark(1));
     const IvSet plain = {w.iv_off, w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, w.iv_off + nr};
     use = plain;
     SortPlan spu = sp;
@@ -719,21 +720,21 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
       niv_use_max = niv_plan;
     }
     HIP_TRY(launch_chunk_begin(ctx->counts, use.n_iv_dev, st));
-    HIP_TRY(mark(1));
+    HIP_TRY(mark(2));
     HIP_TRY(launch_sort_hist(spu, use.key, use.n_iv_dev, mat, st));
     HIP_TRY(launch_scan_u32(mat, mat_scan, (uint64_t)L * spu.nseg_max, nullptr, scan_tmp, st));
     HIP_TRY(launch_sort_scatter(spu, use.key, use.n_iv_dev, mat_scan, sidx, sn, st));
     HIP_TRY(launch_scan_u32(sn, ssb, niv_use_max, use.n_iv_dev, scan_tmp, st));
     HIP_TRY(launch_bucket_tiles(spu, mat_scan, ssb, w.bucket_off, w.tile_off, ctx->counts, st));
-    HIP_TRY(mark(2));
-    HIP_TRY(launch_expand(sidx, ssb, use, r0, jitter, p->jitter_seed, w.srec_ray, w.srec_t, w.perm, st));
     HIP_TRY(mark(3));
+    HIP_TRY(launch_expand(sidx, ssb, use, r0, jitter, p->jitter_seed, w.srec_ray, w.srec_t, w.perm, st));
+    HIP_TRY(mark(4));
     HIP_TRY(launch_mlp(g, mlp->packed_dev, L, w.bucket_off, w.tile_off, ctx->counts, w.srec_ray, w.srec_t, w.perm,
                        rays->o_dev, rays->d_dev, R, r0, w.smp_out, st));
-    HIP_TRY(mark(4));
+    HIP_TRY(mark(5));
     HIP_TRY(launch_composite(nr, use, w.smp_out, r0, jitter, p->jitter_seed, p->ert_eps, out->rgb_dev, out->depth_dev,
                              out->opacity_dev, out->weights_dev, ctx->counts, st));
-    HIP_TRY(mark(5));
+    HIP_TRY(mark(6));
     if (ev) ev->pending = true;
     HIP_TRY(launch_chunk_finish(ctx->counts, use.smp_off + nr, use.n_iv_dev, w.smp_off + nr, st));
   }

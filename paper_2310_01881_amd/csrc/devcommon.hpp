@@ -32,4 +32,28 @@ __device__ __forceinline__ float sample_t(float t0, float delta, uint32_t j, flo
 __device__ __forceinline__ uint32_t key_slot(uint32_t key) { return key & 0xFFFFu; }
 __device__ __forceinline__ uint32_t key_n(uint32_t key) { return key >> 16; }
 
+// Lane shift within the wave's data-parallel-primitive network: lanes whose source is
+// outside the selected rows (or whose row is masked off) read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_or_zero(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4, 8 within rows of
+// 16 lanes, then the last lane of row 0 (2) is added to row 1 (3) and the last lane of
+// row 1 to rows 2 and 3.  The association order is fixed, so results are reproducible.
+__device__ __forceinline__ float wave_scan_incl(float v) {
+  v += dpp_or_zero<0x111, 0xF>(v);   // row_shr:1
+  v += dpp_or_zero<0x112, 0xF>(v);   // row_shr:2
+  v += dpp_or_zero<0x114, 0xF>(v);   // row_shr:4
+  v += dpp_or_zero<0x118, 0xF>(v);   // row_shr:8
+  v += dpp_or_zero<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_or_zero<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 }  // namespace amn

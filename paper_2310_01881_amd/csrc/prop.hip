@@ -47,6 +47,30 @@ __host__ __device__ __forceinline__ int bf16_unit(int layer, int rb, int ku) {
 }
 
 __device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+// softplus with the hardware base-2 exponential and logarithm: log1p(e) is taken as
+// e (1 - e/2) below e = 2^-12, where that is exact to float rounding.
+__device__ __forceinline__ float softplus_fast(float z) {
+  const float e = __builtin_amdgcn_exp2f(-fabsf(z) * 1.44269504f);
+  const float l = e < 2.44140625e-4f ? e * fmaf(-0.5f, e, 1.f) : __builtin_amdgcn_logf(1.f + e) * 0.693147181f;
+  return fmaxf(z, 0.f) + l;
+}
+
+// Feature (index into the 43 of an interval) held by element e of lane group g in K step
+// ku of the BF16 first layer, or -1 for a zero column.  The order lets every lane compute
+// only its own 16 inputs with the same operations in all four lane groups: in step 0,
+// group g holds sin and cos of pi f v with v = position (g < 2) or direction (g >= 2) and
+// f = 1 (g even) or 2 (g odd), plus k / S_max in group 0; in step 1, group g holds the
+// position, the direction, the entry point or the exit point (g = 0..3), and the leaf
+// box's lower (g = 0) or upper (g = 1) corner.
+__host__ __device__ __forceinline__ int bf16_in_feature(int ku, int g, int e) {
+  if (ku == 0) {
+    if (e < 6) return 6 + 12 * (g >> 1) + 6 * (g & 1) + e;
+    return (e == 6 && g == 0) ? 30 : -1;
+  }
+  if (e < 3) return g == 0 ? e : (g == 1 ? 3 + e : (g == 2 ? 37 + e : 40 + e));
+  if (e < 6 && g < 2) return 31 + 3 * g + (e - 3);
+  return -1;
+}
 __device__ __forceinline__ float logisticf(float z) { return 1.f / (1.f + expf(-z)); }
 
 __global__ void k_prop_pack(int dtype, const float* __restrict__ master, uint8_t* __restrict__ packed) {
@@ -70,7 +94,7 @@ __global__ void k_prop_pack(int dtype, const float* __restrict__ master, uint8_t
       bf16x8 h;
       for (int e = 0; e < 8; ++e) {
         float v;
-        if (layer == 0) { const int f = 32 * ku + 8 * g + e; v = f < kIn ? master[kW0 + row * kIn + f] : 0.f; }
+        if (layer == 0) { const int f = bf16_in_feature(ku, g, e); v = f >= 0 ? master[kW0 + row * kIn + f] : 0.f; }
         else if (layer == 1) v = master[kW1 + row * kH + hidden_col_bf16(ku, g, e)];
         else v = master[kW2 + row * kH + hidden_col_bf16(ku, g, e)];
         h[e] = (__bf16)v;
@@ -175,30 +199,44 @@ __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict
   const float* bias = reinterpret_cast<const float*>(lds);
   const uint8_t* units = lds + kBiasBytes;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, m = lane & 15;
-  constexpr int NCB = 4;
+  // items per wave and pass: 16 NCB (BF16 keeps fewer accumulators live for occupancy)
+  constexpr int NCB = BF16 ? 2 : 4;
+  constexpr uint32_t kTile = 4u * 16u * NCB;
   const uint32_t n_items = *iv.n_iv_dev;
-  for (uint32_t tile = blockIdx.x; tile * 256u < n_items; tile += gridDim.x) {
-    const uint32_t base = tile * 256u + wave * 64u;
+  for (uint32_t tile = blockIdx.x; tile * kTile < n_items; tile += gridDim.x) {
+    const uint32_t base = tile * kTile + wave * 16u * NCB;
     if (base >= n_items) continue;
     f32x4 acc[NCB][4];
     if (BF16) {
       bf16x8 X[NCB][2];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
-        const uint32_t it = base + cb * 16 + m;
-        float F[kIn];
-        item_features(iv, it < n_items ? it : n_items - 1, o, d, stride, r0, leafbox, s_max, F);
+        uint32_t it = base + cb * 16 + m;
+        it = it < n_items ? it : n_items - 1;
+        const uint32_t ray = iv.ray[it];
+        const uint32_t k = it - iv.iv_off[ray];
+        const int64_t ri = r0 + ray;
+        const float oo[3] = {o[ri], o[stride + ri], o[2 * stride + ri]};
+        const float dd[3] = {d[ri], d[stride + ri], d[2 * stride + ri]};
+        const float t0 = iv.t0[it];
+        const float t1 = t0 + iv.dt[it];
+        const float* box = leafbox + 6 * key_slot(iv.key[it]) + 3 * (g & 1);
+        const float tt = g == 2 ? t0 : t1;
+        const float half_f = (g & 1) ? 1.f : 0.5f;   // revolutions per unit of v
 #pragma unroll
-        for (int ku = 0; ku < 2; ++ku)
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int b0 = 32 * ku + e;   // feature 32 ku + 8 g + e
-            const float v0 = b0 < kIn ? F[b0 < kIn ? b0 : 0] : 0.f;
-            const float v1 = b0 + 8 < kIn ? F[b0 + 8 < kIn ? b0 + 8 : 0] : 0.f;
-            const float v2 = b0 + 16 < kIn ? F[b0 + 16 < kIn ? b0 + 16 : 0] : 0.f;
-            const float v3 = b0 + 24 < kIn ? F[b0 + 24 < kIn ? b0 + 24 : 0] : 0.f;
-            X[cb][ku][e] = (__bf16)(g == 0 ? v0 : (g == 1 ? v1 : (g == 2 ? v2 : v3)));
-          }
+        for (int a = 0; a < 3; ++a) {
+          const float q = (oo[a] - 0.5f) * 0.5f;
+          const float v = g < 2 ? q : dd[a];
+          const float x = 2.f * fmaf(tt, dd[a], oo[a]) - 1.f;
+          X[cb][0][a] = (__bf16)__builtin_amdgcn_sinf(half_f * v);
+          X[cb][0][3 + a] = (__bf16)__builtin_amdgcn_cosf(half_f * v);
+          X[cb][1][a] = (__bf16)(g == 0 ? q : (g == 1 ? dd[a] : x));
+          X[cb][1][3 + a] = (__bf16)(g < 2 ? box[a] : 0.f);
+        }
+        X[cb][0][6] = (__bf16)(g == 0 ? (float)k / (float)s_max : 0.f);
+        X[cb][0][7] = (__bf16)0.f;
+        X[cb][1][6] = (__bf16)0.f;
+        X[cb][1][7] = (__bf16)0.f;
       }
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) {
@@ -304,7 +342,7 @@ __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict
       for (int rb = 0; rb < 2; ++rb) {
         f32x4 v;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = softplusf(acc[cb][rb][e]);
+        for (int e = 0; e < 4; ++e) v[e] = BF16 ? softplus_fast(acc[cb][rb][e]) : softplusf(acc[cb][rb][e]);
         *reinterpret_cast<f32x4*>(tau + (uint64_t)it * kBins + 16 * rb + 4 * g) = v;
       }
     }
@@ -312,12 +350,87 @@ __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict
 }
 
 // ---- selection: one wave per ray ----------------------------------------------------
-// Per ray: the bins of the ray's intervals are composited two intervals (64 bins) per step;
-// slot j of interval k (n slots) receives the predicted weight of the bins it overlaps.
-// The threshold theta* = the largest value with sum_{p_j >= theta} p_j >= mass_thresh * M^ is
-// found by binary search over the bit patterns of non-negative floats; slots above it are
-// kept, and among slots equal to it the earliest ones until the sum is reached.
+// Per ray: the bins of the ray's intervals are composited two intervals (64 bins, one per
+// lane) per step.  Slot j of an interval with n slots covers bins [32 j / n, 32 (j+1) / n);
+// its predicted weight is the bin weights it covers, each scaled by the covered fraction:
+// the partial first and last bins directly and the whole bins in between as a difference
+// of the step's running sum of bin weights.  The slots are then sorted by (weight
+// descending, slot ascending) with a bitonic network across the wave (E keys per lane), a
+// prefix sum over the sorted weights finds the shortest prefix holding mass_thresh * M^,
+// and the chosen slots' bits are set in the mask.
 constexpr int kMaxSlots = 256;   // >= AMNERF_MAX_SAMPLES + 1
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor((uint32_t)v, m, 64), hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Sorts 64*E keys (element e = q*64 + lane held in key[q] of that lane) in descending order.
+template <int E>
+__device__ __forceinline__ void bitonic_desc(uint64_t key[E], int lane) {
+#pragma unroll
+  for (int k = 2; k <= 64 * E; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int e = q * 64 + lane;
+        const bool desc_block = (e & k) == 0;   // this k-block sorts descending
+        if (j < 64) {
+          const uint64_t other = shfl_xor_u64(key[q], j);
+          const bool lower = (e & j) == 0;
+          const bool keep_max = lower == desc_block;
+          const uint64_t mx = key[q] > other ? key[q] : other;
+          const uint64_t mn = key[q] > other ? other : key[q];
+          key[q] = keep_max ? mx : mn;
+        } else if (((q * 64) & j) == 0) {
+          const int q2 = q + j / 64;
+          const uint64_t a = key[q], b = key[q2];
+          const bool swap = desc_block ? (a < b) : (a > b);
+          key[q] = swap ? b : a;
+          key[q2] = swap ? a : b;
+        }
+      }
+    }
+  }
+}
+
+// Returns the number of slots kept; *reached is false when all ns slots together stay
+// below the target (the ray then falls back to plain sampling).
+template <int E>
+__device__ __forceinline__ uint32_t select_sorted(const float p[4], uint32_t ns, float target, int lane,
+                                                  uint64_t* mask_lds, bool* reached) {
+  uint64_t key[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const uint32_t s = (uint32_t)lane + 64u * q;
+    key[q] = s < ns ? ((uint64_t)__float_as_uint(p[q]) << 32) | (uint64_t)(0xFFFFFFFFu - s) : 0ull;
+  }
+  bitonic_desc<E>(key, lane);
+  // exclusive prefix sums over the sorted weights; sorted position = q * 64 + lane
+  float carry = 0.f;
+  uint32_t count = 0;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const float v = __uint_as_float((uint32_t)(key[q] >> 32));
+    float inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const float y = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += y;
+    }
+    const uint32_t pos = (uint32_t)q * 64u + (uint32_t)lane;
+    const bool take = pos < ns && carry + (inc - v) < target;
+    if (take) {
+      const uint32_t s = 0xFFFFFFFFu - (uint32_t)(key[q] & 0xFFFFFFFFull);
+      atomicOr(reinterpret_cast<unsigned long long*>(&mask_lds[s >> 6]), 1ull << (s & 63));
+    }
+    count += (uint32_t)__popcll(__ballot(take));
+    carry += __shfl(inc, 63, 64);
+  }
+  *reached = count < ns || carry >= target;
+  return count;
+}
 
 __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv, const float* __restrict__ tau,
                                                           float mass_thresh, int cap, uint32_t* __restrict__ runs,
@@ -325,47 +438,62 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
                                                           float* __restrict__ mass_out,
                                                           ChunkCounts* __restrict__ counts) {
   __shared__ float wbuf[kThreads / 64][64];
+  __shared__ float cbuf[kThreads / 64][64];
+  __shared__ uint64_t mlds[kThreads / 64][4];
+  __shared__ uint32_t fb_lds[kThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t r = blockIdx.x * (kThreads / 64) + wave;
-  if (r >= nr) return;
+  // fallback rays are counted per wave and added once per block: one global atomic per
+  // fallback ray serialises on the counter's cache line
+  uint32_t n_fb = 0;
+  for (uint32_t r = blockIdx.x * (kThreads / 64) + wave; r < nr; r += gridDim.x * (kThreads / 64)) {
   const uint32_t i0 = iv.iv_off[r], meff = iv.iv_off[r + 1] - i0;
   const uint32_t ns = iv.smp_off[r + 1] - iv.smp_off[r];
   if (meff == 0) {
     if (lane == 0) { runs[r] = 0; nsel[r] = 0; if (mass_out) mass_out[r] = 0.f; }
-    return;
+    continue;
   }
   const uint32_t n = ns / meff;
+  // floor(x / n) = (x * magic) >> 32 for x < 2^16 (the error x (magic - 2^32/n) / 2^32 stays
+  // below 1/n, so it never carries into the integer part)
+  const uint64_t magic = ((1ull << 32) + n - 1) / n;
+  auto div_n = [&](uint32_t x) { return (uint32_t)(((uint64_t)x * magic) >> 32); };
+  const float inv_n = 1.f / (float)n;
+  // slot geometry: interval sk, first and last bin, covered fractions (in bins)
+  uint32_t sk[4], blo[4], bhi[4];
+  float clo[4], chi[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t s = (uint32_t)lane + 64u * q;
+    sk[q] = s < ns ? div_n(s) : 0xFFFFu;
+    const uint32_t j = s < ns ? s - sk[q] * n : 0u;
+    blo[q] = div_n(32u * j);
+    bhi[q] = div_n(32u * (j + 1) + n - 1) - 1u;
+    const float u0 = (float)(32u * j) * inv_n, u1 = (float)(32u * (j + 1)) * inv_n;
+    clo[q] = bhi[q] == blo[q] ? 32.f * inv_n : (float)(blo[q] + 1) - u0;
+    chi[q] = u1 - (float)bhi[q];
+  }
   float p[4] = {0.f, 0.f, 0.f, 0.f};
   float carry = 0.f;
   for (uint32_t k = 0; k < meff; k += 2) {
     const uint32_t kk = k + (uint32_t)(lane >> 5);
     const float t = kk < meff ? tau[(uint64_t)(i0 + kk) * kBins + (lane & 31)] : 0.f;
-    float inc = t;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const float y = __shfl_up(inc, off, 64);
-      if (lane >= off) inc += y;
-    }
-    const float S = carry + inc - t;
-    wbuf[wave][lane] = expf(-S) * -expm1f(-t);
-    carry += __shfl(inc, 63, 64);
+    const float inc = wave_scan_incl(t);
+    const float S = carry + (inc - t);
+    const float w = expf(-S) * -expm1f(-t);
+    wbuf[wave][lane] = w;
+    cbuf[wave][lane] = wave_scan_incl(w);
+    carry += lane_value(inc, 63);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const uint32_t s = (uint32_t)lane + 64u * q;
-      if (s >= ns) continue;
-      const uint32_t sk = s / n, j = s - sk * n;
-      if (sk != k && sk != k + 1) continue;
-      const float a0 = (float)j / (float)n, a1 = (float)(j + 1) / (float)n;
-      const int b_lo = (int)((32u * j) / n);
-      const int b_hi = min(31, (int)((32u * (j + 1) + n - 1) / n) - 1);
-      float acc = 0.f;
-      for (int b = b_lo; b <= b_hi; ++b) {
-        const float ov = fminf(a1, (float)(b + 1) * (1.f / 32.f)) - fmaxf(a0, (float)b * (1.f / 32.f));
-        if (ov > 0.f) acc += wbuf[wave][(sk - k) * 32 + b] * ov * 32.f;
+      const uint32_t rel = sk[q] - k;
+      if (rel < 2u) {
+        const uint32_t lo = rel * 32u + blo[q], hi = rel * 32u + bhi[q];
+        float v = clo[q] * wbuf[wave][lo];
+        if (hi > lo) v += (cbuf[wave][hi - 1] - cbuf[wave][lo]) + chi[q] * wbuf[wave][hi];
+        p[q] = v;
       }
-      p[q] = acc;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -373,59 +501,28 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
   const float M = -expm1f(-carry);
   if (mass_out && lane == 0) mass_out[r] = M;
   bool fallback = !(M >= mass_thresh);
-  uint64_t sel[4] = {0, 0, 0, 0};
   uint32_t count = 0;
   if (!fallback) {
+    if (lane < 4) mlds[wave][lane] = 0ull;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     const float target = mass_thresh * M;
-    auto mass_at_least = [&](uint32_t bits) {
-      const float th = __uint_as_float(bits);
-      float s = 0.f;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if ((uint32_t)lane + 64u * q < ns && p[q] >= th) s += p[q];
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-      return s;
-    };
-    float pmax = 0.f;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if ((uint32_t)lane + 64u * q < ns) pmax = fmaxf(pmax, p[q]);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) pmax = fmaxf(pmax, __shfl_xor(pmax, off, 64));
-    uint32_t lo = 0u, hi = __float_as_uint(pmax) + 1u;   // f(lo) >= target > f(hi)
-    while (hi - lo > 1u) {
-      const uint32_t mid = lo + (hi - lo) / 2u;
-      if (mass_at_least(mid) >= target) lo = mid; else hi = mid;
-    }
-    const float th = __uint_as_float(lo);
-    const float above = mass_at_least(lo + 1u);
-    // earliest slots equal to th until the target is reached
-    uint32_t rank_base = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t s = (uint32_t)lane + 64u * q;
-      const bool valid = s < ns;
-      const bool gt = valid && p[q] > th;
-      const bool eq = valid && p[q] == th;
-      const uint64_t eqm = __ballot(eq);
-      const uint32_t rank = rank_base + (uint32_t)__popcll(eqm & ((1ull << lane) - 1ull));
-      const bool take_eq = eq && (above + (float)rank * th < target);
-      sel[q] = __ballot(gt || take_eq);
-      rank_base += (uint32_t)__popcll(eqm);
-      count += (uint32_t)__popcll(sel[q]);
-    }
-    if (count > (uint32_t)cap || count == 0) fallback = true;
+    bool reached = true;
+    count = ns <= 128 ? select_sorted<2>(p, ns, target, lane, mlds[wave], &reached)
+                      : select_sorted<4>(p, ns, target, lane, mlds[wave], &reached);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (count > (uint32_t)cap || count == 0 || !reached) fallback = true;
   }
   if (fallback) {
-    if (lane == 0) {
-      runs[r] = meff;
-      nsel[r] = ns;
-      atomicAdd(reinterpret_cast<unsigned long long*>(&counts->fallback), 1ull);
-    }
+    if (lane == 0) { runs[r] = meff; nsel[r] = ns; }
     if (lane < 4) mask[4 * (uint64_t)r + lane] = ~0ull;
-    return;
+    ++n_fb;
+    continue;
   }
+  uint64_t sel[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sel[q] = mlds[wave][q];
   // runs: a kept slot starts a run unless the previous slot is kept in the same interval
   uint32_t nruns = 0;
 #pragma unroll
@@ -434,7 +531,7 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
     const bool mine = (sel[q] >> lane) & 1ull;
     bool start = false;
     if (mine) {
-      if (s == 0 || s % n == 0) start = true;
+      if (s % n == 0) start = true;
       else {
         const uint32_t ps = s - 1;
         start = !((sel[ps / 64] >> (ps % 64)) & 1ull);
@@ -443,7 +540,15 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
     nruns += (uint32_t)__popcll(__ballot(start));
   }
   if (lane == 0) { runs[r] = nruns; nsel[r] = count; }
-  if (lane < 4) mask[4 * (uint64_t)r + lane] = lane == 0 ? sel[0] : (lane == 1 ? sel[1] : (lane == 2 ? sel[2] : sel[3]));
+  if (lane < 4) mask[4 * (uint64_t)r + lane] = sel[lane];
+  }
+  if (lane == 0) fb_lds[wave] = n_fb;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kThreads / 64; ++w) t += fb_lds[w];
+    if (t) atomicAdd(reinterpret_cast<unsigned long long*>(&counts->fallback), (unsigned long long)t);
+  }
 }
 
 // ---- emission of the planned intervals: one lane per ray ------------------------------
@@ -825,8 +930,9 @@ hipError_t launch_prop_fwd(int dtype, const void* packed, const IvSet& iv, const
   int n = 0;
   hipError_t e = ncu(&n);
   if (e != hipSuccess) return e;
-  uint32_t tiles = (n_iv_max + 255) / 256;
-  uint32_t grid = std::min<uint32_t>(tiles > 0 ? tiles : 1, (uint32_t)n * 4);
+  const uint32_t tile = dtype == AMNERF_BF16 ? 128u : 256u;
+  uint32_t tiles = (n_iv_max + tile - 1) / tile;
+  uint32_t grid = std::min<uint32_t>(tiles > 0 ? tiles : 1, (uint32_t)n * 8);
   if (dtype == AMNERF_BF16)
     hipLaunchKernelGGL(k_prop_fwd<true>, dim3(grid), dim3(kThreads), kBf16Bytes, st, (const uint8_t*)packed, iv, o,
                        d, stride, r0, leafbox, s_max, tau);
@@ -840,8 +946,12 @@ hipError_t launch_prop_select(uint32_t nr, const IvSet& iv, const float* tau, fl
                               uint32_t* runs, uint32_t* nsel, uint64_t* mask, float* mass, ChunkCounts* counts,
                               hipStream_t st) {
   if (nr == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prop_select, dim3((nr + 3) / 4), dim3(kThreads), 0, st, nr, iv, tau, mass_thresh, cap, runs,
-                     nsel, mask, mass, counts);
+  int n = 0;
+  hipError_t e = ncu(&n);
+  if (e != hipSuccess) return e;
+  const uint32_t grid = std::min<uint32_t>((nr + 3) / 4, (uint32_t)n * 16);
+  hipLaunchKernelGGL(k_prop_select, dim3(grid), dim3(kThreads), 0, st, nr, iv, tau, mass_thresh, cap, runs, nsel,
+                     mask, mass, counts);
   return hipGetLastError();
 }
 

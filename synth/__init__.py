@@ -220,6 +220,37 @@ def camera_rays(cam: Camera) -> tuple:
             np.ascontiguousarray(d.astype(np.float32)))
 
 
+def random_pixel_rays(cams: list, n: int, seed: int) -> tuple:
+    """Rays through n seeded random pixel centres of random cameras (all cameras share W, H)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ci = rng.integers(0, len(cams), n)
+    W, H = cams[0].width, cams[0].height
+    px = rng.integers(0, W * H, n)
+    o = np.empty((3, n), np.float64)
+    d = np.empty((3, n), np.float64)
+    up = np.array([0.0, 0.0, 1.0])
+    centre = np.array([0.5, 0.5, 0.5])
+    for c in np.unique(ci):
+        sel = np.where(ci == c)[0]
+        cam = cams[c]
+        pos = np.array(cam.position, dtype=np.float64)
+        f = centre - pos
+        f /= np.linalg.norm(f)
+        r = np.cross(f, up)
+        r /= np.linalg.norm(r)
+        u = np.cross(r, f)
+        th = math.tan(math.radians(cam.fov_y_deg) / 2.0)
+        i = px[sel] % W
+        j = px[sel] // W
+        x = ((i + 0.5) / W * 2.0 - 1.0) * th * (W / H)
+        y = (1.0 - (j + 0.5) / H * 2.0) * th
+        dd = f[:, None] + x[None, :] * r[:, None] + y[None, :] * u[:, None]
+        dd /= np.linalg.norm(dd, axis=0, keepdims=True)
+        d[:, sel] = dd
+        o[:, sel] = pos[:, None]
+    return np.ascontiguousarray(o.astype(np.float32)), np.ascontiguousarray(d.astype(np.float32))
+
+
 def rays_for_cameras(cams: list) -> tuple:
     """Concatenated rays of several cameras (camera-major)."""
     os_, ds_ = zip(*(camera_rays(c) for c in cams))
