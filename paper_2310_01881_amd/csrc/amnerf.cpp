@@ -708,7 +708,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
       if (rc) return rc;
       carve_prop((char*)ctx->arena3, nr, niv_plain, niv_plan, spp, pw);
       HIP_TRY(launch_prop_fwd(q->dtype, q->packed_dev, plain, rays->o_dev, rays->d_dev, R, r0, tree->dev_leafbox,
-                              p->s_max, niv_plain, pw.tau, st));
+                              p->s_max, niv_plain, true, pw.tau, st));
       HIP_TRY(launch_prop_select(nr, plain, pw.tau, q->mass_thresh, q->cap, pw.runs, pw.nsel, pw.mask, nullptr,
                                  ctx->counts, st));
       HIP_TRY(launch_scan_u32(pw.runs, pw.pv_off, nr, nullptr, pw.scan_tmp, st));
@@ -1032,7 +1032,7 @@ extern "C" int amnerf_propose(amnerf_ctx* ctx, const amnerf_tree* tree, const am
     if ((int64_t)niv_guess > p->tau_cap)
       return fail(AMNERF_ECAPACITY, "amnerf_propose: %u intervals exceed tau_cap %lld", niv_guess, (long long)p->tau_cap);
     HIP_TRY(launch_prop_fwd(p->infer_dtype, p->infer_packed_dev, iv, rays->o_dev, rays->d_dev, rays->n_rays, 0,
-                            tree->dev_leafbox, p->s_max, niv_guess, p->tau_dev, st));
+                            tree->dev_leafbox, p->s_max, niv_guess, false, p->tau_dev, st));
     return AMNERF_OK;
   }
   HIP_TRY(launch_prop_targets(iv, ctx->smp_out, tw.alpha, st));

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict
                                                        const float* __restrict__ o, const float* __restrict__ d,
                                                        int64_t stride, int64_t r0,
                                                        const float* __restrict__ leafbox, int s_max,
-                                                       float* __restrict__ tau) {
+                                                       int cum, float* __restrict__ tau) {
   extern __shared__ __align__(16) uint8_t lds[];
   const uint32_t bytes = BF16 ? kBf16Bytes : kBiasBytes + kF32Units * kUnitBytes;
   for (uint32_t i = threadIdx.x; i < bytes / 16; i += kThreads)
@@ -333,214 +333,288 @@ __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict
             if (rb < nrb) acc[cb][rb] = nacc[cb][rb];
       }
     }
-    // outputs: rows 16 rb + 4 g + e of the 32 bins
+    // outputs: rows 16 rb + 4 g + e of the 32 bins.  With cum set, the inclusive prefix sum
+    // of the interval's bins is stored instead (bin b holds tau_0 + ... + tau_b): lane group
+    // g holds bins 4g..4g+3 and 16+4g..16+4g+3 of its column, so the offsets of its two runs
+    // are sums over the lower groups, gathered 16 and 32 lanes down the wave.
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
       const uint32_t it = base + cb * 16 + m;
+      f32x4 v[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[rb][e] = BF16 ? softplus_fast(acc[cb][rb][e]) : softplusf(acc[cb][rb][e]);
+      if (cum) {
+        float run[2], off[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          v[rb][1] += v[rb][0];
+          v[rb][2] += v[rb][1];
+          v[rb][3] += v[rb][2];
+          float x = v[rb][3];
+          float y = __shfl_up(x, 16, 64);
+          x += g >= 1 ? y : 0.f;
+          y = __shfl_up(x, 32, 64);
+          x += g >= 2 ? y : 0.f;
+          run[rb] = x;                       // inclusive over groups 0..g
+          off[rb] = x - v[rb][3];
+        }
+        const float tot0 = __shfl(run[0], 48 + m, 64);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          v[0][e] += off[0];
+          v[1][e] += tot0 + off[1];
+        }
+      }
       if (it >= n_items) continue;
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        f32x4 v;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = BF16 ? softplus_fast(acc[cb][rb][e]) : softplusf(acc[cb][rb][e]);
-        *reinterpret_cast<f32x4*>(tau + (uint64_t)it * kBins + 16 * rb + 4 * g) = v;
-      }
+      for (int rb = 0; rb < 2; ++rb)
+        *reinterpret_cast<f32x4*>(tau + (uint64_t)it * kBins + 16 * rb + 4 * g) = v[rb];
     }
   }
 }
 
 // ---- selection: one wave per ray ----------------------------------------------------
-// Per ray: the bins of the ray's intervals are composited two intervals (64 bins, one per
-// lane) per step.  Slot j of an interval with n slots covers bins [32 j / n, 32 (j+1) / n);
-// its predicted weight is the bin weights it covers, each scaled by the covered fraction:
-// the partial first and last bins directly and the whole bins in between as a difference
-// of the step's running sum of bin weights.  The slots are then sorted by (weight
-// descending, slot ascending) with a bitonic network across the wave (E keys per lane), a
-// prefix sum over the sorted weights finds the shortest prefix holding mass_thresh * M^,
-// and the chosen slots' bits are set in the mask.
+// Input: per interval, the inclusive prefix sums P_b = tau_0 + ... + tau_b of its 32 bins.
+// The ray's optical depth before interval k, S_k, is a wave scan of the interval totals
+// P_31; the predicted mass is 1 - exp(-S_total), and rays below mass_thresh fall back.
+// Slot j of an interval with n slots covers bins [32 j / n, 32 (j+1) / n).  Its weight is
+// the bins' composited weights T_b (1 - exp(-tau_b)) scaled by the covered fraction of each
+// bin; over the fully covered bins in the middle the sum telescopes, so with
+// E(x) = exp(-(S_k + x)) and D(a, b) = 1 - exp(-(b - a)):
+//   partial first bin lo:  c_lo E(P_lo-1) D(P_lo-1, P_lo)
+//   whole bins lo+1..hi-1: E(P_lo) D(P_lo, P_hi-1)
+//   partial last bin hi:   c_hi E(P_hi-1) D(P_hi-1, P_hi)
+// The weights are then sorted (descending) across the wave, a prefix sum over them gives
+// the number c of slots needed to reach mass_thresh * M^, and the slots kept are those with
+// weight above the c-th largest value w* plus, among those equal to w*, the lowest-indexed
+// ones (so ties go to the earlier slot).
 constexpr int kMaxSlots = 256;   // >= AMNERF_MAX_SAMPLES + 1
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-  const uint32_t lo = __shfl_xor((uint32_t)v, m, 64), hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
-  return ((uint64_t)hi << 32) | lo;
+// Value of lane (lane ^ J): lane permutations within rows (J <= 8, two steps for 4 and
+// 8: a mirror of 8 or 16 lanes followed by a mirror of 4 or 8), a swizzle within 32 lanes
+// (J = 16), or a general permute (J = 32).
+template <int J>
+__device__ __forceinline__ float xor_lane(float v) {
+  const int x = __float_as_int(v);
+  int r;
+  if constexpr (J == 1) r = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);        // quad_perm 1,0,3,2
+  else if constexpr (J == 2) r = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  else if constexpr (J == 4)                                                           // i^7 then i^3
+    r = __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false), 0x1B, 0xF, 0xF, false);
+  else if constexpr (J == 8)                                                           // i^15 then i^7
+    r = __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false), 0x141, 0xF, 0xF, false);
+  else if constexpr (J == 16) r = __builtin_amdgcn_ds_swizzle(x, 0x401F);             // xor 16 within 32
+  else r = __shfl_xor(x, J, 64);
+  return __int_as_float(r);
 }
 
-// Sorts 64*E keys (element e = q*64 + lane held in key[q] of that lane) in descending order.
+// One compare-exchange at lane distance J < 64 for element e of a bitonic k-block: the
+// lower element of a descending block keeps the maximum.
+template <int J>
+__device__ __forceinline__ float bitonic_lane_step(float key, int e, int k) {
+  const float other = xor_lane<J>(key);
+  const bool keep_max = ((e & J) == 0) == ((e & k) == 0);
+  return keep_max ? fmaxf(key, other) : fminf(key, other);
+}
+
+// Sorts 64*E values (element e = q*64 + lane held in key[q] of that lane), descending.
 template <int E>
-__device__ __forceinline__ void bitonic_desc(uint64_t key[E], int lane) {
+__device__ __forceinline__ void bitonic_desc(float key[E], int lane) {
 #pragma unroll
   for (int k = 2; k <= 64 * E; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+          if (((q * 64) & j) != 0) continue;
+          const int q2 = q + j / 64;
+          const bool desc_block = ((q * 64) & k) == 0;
+          const float a = key[q], b = key[q2];
+          key[q] = desc_block ? fmaxf(a, b) : fminf(a, b);
+          key[q2] = desc_block ? fminf(a, b) : fmaxf(a, b);
+        }
+        continue;
+      }
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         const int e = q * 64 + lane;
-        const bool desc_block = (e & k) == 0;   // this k-block sorts descending
-        if (j < 64) {
-          const uint64_t other = shfl_xor_u64(key[q], j);
-          const bool lower = (e & j) == 0;
-          const bool keep_max = lower == desc_block;
-          const uint64_t mx = key[q] > other ? key[q] : other;
-          const uint64_t mn = key[q] > other ? other : key[q];
-          key[q] = keep_max ? mx : mn;
-        } else if (((q * 64) & j) == 0) {
-          const int q2 = q + j / 64;
-          const uint64_t a = key[q], b = key[q2];
-          const bool swap = desc_block ? (a < b) : (a > b);
-          key[q] = swap ? b : a;
-          key[q2] = swap ? a : b;
+        switch (j) {
+          case 32: key[q] = bitonic_lane_step<32>(key[q], e, k); break;
+          case 16: key[q] = bitonic_lane_step<16>(key[q], e, k); break;
+          case 8: key[q] = bitonic_lane_step<8>(key[q], e, k); break;
+          case 4: key[q] = bitonic_lane_step<4>(key[q], e, k); break;
+          case 2: key[q] = bitonic_lane_step<2>(key[q], e, k); break;
+          default: key[q] = bitonic_lane_step<1>(key[q], e, k); break;
         }
       }
     }
   }
 }
 
-// Returns the number of slots kept; *reached is false when all ns slots together stay
-// below the target (the ray then falls back to plain sampling).
+// exp(-x) with the hardware base-2 exponential
+__device__ __forceinline__ float exp_neg(float x) { return __builtin_amdgcn_exp2f(-1.44269504f * x); }
+// 1 - exp(-d) for d >= 0: a cubic Taylor polynomial below 1/16 (relative error under 2^-23
+// there), else from the hardware exponential
+__device__ __forceinline__ float one_minus_exp_neg(float d) {
+  d = fmaxf(d, 0.f);   // prefix differences can dip an ulp below zero
+  if (d < 0.0625f) return d * fmaf(d, fmaf(d, fmaf(d, -1.f / 24.f, 1.f / 6.f), -0.5f), 1.f);
+  return 1.f - exp_neg(d);
+}
+
+// Number of slots kept: the shortest prefix of the descending weights whose sum reaches
+// target.  *reached is false when all ns slots together stay below it.  *wcut = weight of
+// the last kept slot.
 template <int E>
-__device__ __forceinline__ uint32_t select_sorted(const float p[4], uint32_t ns, float target, int lane,
-                                                  uint64_t* mask_lds, bool* reached) {
-  uint64_t key[E];
+__device__ __forceinline__ uint32_t count_sorted(const float p[4], uint32_t ns, float target, int lane, bool* reached,
+                                                 float* wcut) {
+  float key[E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const uint32_t s = (uint32_t)lane + 64u * q;
-    key[q] = s < ns ? ((uint64_t)__float_as_uint(p[q]) << 32) | (uint64_t)(0xFFFFFFFFu - s) : 0ull;
-  }
+  for (int q = 0; q < E; ++q) key[q] = (uint32_t)lane + 64u * q < ns ? p[q] : -1.f;
   bitonic_desc<E>(key, lane);
-  // exclusive prefix sums over the sorted weights; sorted position = q * 64 + lane
-  float carry = 0.f;
+  float carry = 0.f, cut = 0.f;
   uint32_t count = 0;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
-    const float v = __uint_as_float((uint32_t)(key[q] >> 32));
-    float inc = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const float y = __shfl_up(inc, off, 64);
-      if (lane >= off) inc += y;
-    }
+    const float v = fmaxf(key[q], 0.f);
+    const float inc = wave_scan_incl(v);
     const uint32_t pos = (uint32_t)q * 64u + (uint32_t)lane;
     const bool take = pos < ns && carry + (inc - v) < target;
-    if (take) {
-      const uint32_t s = 0xFFFFFFFFu - (uint32_t)(key[q] & 0xFFFFFFFFull);
-      atomicOr(reinterpret_cast<unsigned long long*>(&mask_lds[s >> 6]), 1ull << (s & 63));
-    }
-    count += (uint32_t)__popcll(__ballot(take));
-    carry += __shfl(inc, 63, 64);
+    const uint64_t b = __ballot(take);
+    if (b) cut = lane_value(v, 63 - __builtin_clzll(b));
+    count += (uint32_t)__popcll(b);
+    carry += lane_value(inc, 63);
   }
   *reached = count < ns || carry >= target;
+  *wcut = cut;
   return count;
 }
 
-__global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv, const float* __restrict__ tau,
+__global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv, const float* __restrict__ cum,
                                                           float mass_thresh, int cap, uint32_t* __restrict__ runs,
                                                           uint32_t* __restrict__ nsel, uint64_t* __restrict__ mask,
                                                           float* __restrict__ mass_out,
                                                           ChunkCounts* __restrict__ counts) {
-  __shared__ float wbuf[kThreads / 64][64];
-  __shared__ float cbuf[kThreads / 64][64];
-  __shared__ uint64_t mlds[kThreads / 64][4];
+  __shared__ float sbuf[kThreads / 64][kMaxSlots];
   __shared__ uint32_t fb_lds[kThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // fallback rays are counted per wave and added once per block: one global atomic per
   // fallback ray serialises on the counter's cache line
   uint32_t n_fb = 0;
   for (uint32_t r = blockIdx.x * (kThreads / 64) + wave; r < nr; r += gridDim.x * (kThreads / 64)) {
-  const uint32_t i0 = iv.iv_off[r], meff = iv.iv_off[r + 1] - i0;
-  const uint32_t ns = iv.smp_off[r + 1] - iv.smp_off[r];
-  if (meff == 0) {
-    if (lane == 0) { runs[r] = 0; nsel[r] = 0; if (mass_out) mass_out[r] = 0.f; }
-    continue;
-  }
-  const uint32_t n = ns / meff;
-  // floor(x / n) = (x * magic) >> 32 for x < 2^16 (the error x (magic - 2^32/n) / 2^32 stays
-  // below 1/n, so it never carries into the integer part)
-  const uint64_t magic = ((1ull << 32) + n - 1) / n;
-  auto div_n = [&](uint32_t x) { return (uint32_t)(((uint64_t)x * magic) >> 32); };
-  const float inv_n = 1.f / (float)n;
-  // slot geometry: interval sk, first and last bin, covered fractions (in bins)
-  uint32_t sk[4], blo[4], bhi[4];
-  float clo[4], chi[4];
+    const uint32_t i0 = iv.iv_off[r], meff = iv.iv_off[r + 1] - i0;
+    const uint32_t ns = iv.smp_off[r + 1] - iv.smp_off[r];
+    if (meff == 0) {
+      if (lane == 0) { runs[r] = 0; nsel[r] = 0; if (mass_out) mass_out[r] = 0.f; }
+      continue;
+    }
+    // optical depth before each interval
+    float carry = 0.f;
+    for (uint32_t k0 = 0; k0 < meff; k0 += 64) {
+      const uint32_t k = k0 + (uint32_t)lane;
+      const float tot = k < meff ? cum[(uint64_t)(i0 + k) * kBins + (kBins - 1)] : 0.f;
+      const float inc = wave_scan_incl(tot);
+      if (k < meff) sbuf[wave][k] = carry + (inc - tot);
+      carry += lane_value(inc, 63);
+    }
+    const float M = -expm1f(-carry);
+    if (mass_out && lane == 0) mass_out[r] = M;
+    bool fallback = !(M >= mass_thresh);
+    uint32_t count = 0;
+    uint64_t sel[4] = {0ull, 0ull, 0ull, 0ull};
+    const uint32_t n = ns / meff;
+    if (!fallback) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // floor(x / n) = (x * magic) >> 32 for x < 2^16 (the error x (magic - 2^32/n) / 2^32
+      // stays below 1/n, so it never carries into the integer part)
+      const uint64_t magic = ((1ull << 32) + n - 1) / n;
+      const float inv_n = 1.f / (float)n;
+      const uint32_t nq = (ns + 63u) / 64u;
+      float p[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t s = (uint32_t)lane + 64u * q;
-    sk[q] = s < ns ? div_n(s) : 0xFFFFu;
-    const uint32_t j = s < ns ? s - sk[q] * n : 0u;
-    blo[q] = div_n(32u * j);
-    bhi[q] = div_n(32u * (j + 1) + n - 1) - 1u;
-    const float u0 = (float)(32u * j) * inv_n, u1 = (float)(32u * (j + 1)) * inv_n;
-    clo[q] = bhi[q] == blo[q] ? 32.f * inv_n : (float)(blo[q] + 1) - u0;
-    chi[q] = u1 - (float)bhi[q];
-  }
-  float p[4] = {0.f, 0.f, 0.f, 0.f};
-  float carry = 0.f;
-  for (uint32_t k = 0; k < meff; k += 2) {
-    const uint32_t kk = k + (uint32_t)(lane >> 5);
-    const float t = kk < meff ? tau[(uint64_t)(i0 + kk) * kBins + (lane & 31)] : 0.f;
-    const float inc = wave_scan_incl(t);
-    const float S = carry + (inc - t);
-    const float w = expf(-S) * -expm1f(-t);
-    wbuf[wave][lane] = w;
-    cbuf[wave][lane] = wave_scan_incl(w);
-    carry += lane_value(inc, 63);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+      for (int q = 0; q < 4; ++q) {
+        if ((uint32_t)q >= nq) break;
+        const uint32_t s = (uint32_t)lane + 64u * q;
+        if (s >= ns) continue;
+        const uint32_t sk = (uint32_t)(((uint64_t)s * magic) >> 32);
+        const uint32_t j = s - sk * n;
+        const uint32_t blo = (uint32_t)(((uint64_t)(32u * j) * magic) >> 32);
+        const uint32_t bhi = (uint32_t)(((uint64_t)(32u * (j + 1) + n - 1) * magic) >> 32) - 1u;
+        const float u0 = (float)(32u * j) * inv_n, u1 = (float)(32u * (j + 1)) * inv_n;
+        const float* row = cum + (uint64_t)(i0 + sk) * kBins;
+        const float S = sbuf[wave][sk];
+        const float Plo0 = blo ? row[blo - 1] : 0.f, Plo = row[blo];
+        if (bhi == blo) {
+          p[q] = 32.f * inv_n * exp_neg(S + Plo0) * one_minus_exp_neg(Plo - Plo0);
+        } else {
+          const float Phi0 = row[bhi - 1], Phi = row[bhi];
+          const float clo = (float)(blo + 1) - u0, chi = u1 - (float)bhi;
+          float v = clo * exp_neg(S + Plo0) * one_minus_exp_neg(Plo - Plo0);
+          if (bhi > blo + 1) v += exp_neg(S + Plo) * one_minus_exp_neg(Phi0 - Plo);
+          v += chi * exp_neg(S + Phi0) * one_minus_exp_neg(Phi - Phi0);
+          p[q] = fmaxf(v, 0.f);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const float target = mass_thresh * M;
+      bool reached = true;
+      float wcut = 0.f;
+      count = nq <= 2 ? count_sorted<2>(p, ns, target, lane, &reached, &wcut)
+                      : count_sorted<4>(p, ns, target, lane, &reached, &wcut);
+      if (count > (uint32_t)cap || count == 0 || !reached) {
+        fallback = true;
+      } else {
+        // above the cut, then the earliest slots equal to it
+        uint32_t n_gt = 0;
+        uint64_t eqm[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool valid = (uint32_t)lane + 64u * q < ns;
+          sel[q] = __ballot(valid && p[q] > wcut);
+          eqm[q] = __ballot(valid && p[q] == wcut);
+          n_gt += (uint32_t)__popcll(sel[q]);
+        }
+        uint32_t need = count - n_gt;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          uint64_t e = eqm[q];
+          while (need && e) {
+            const uint64_t low = e & (~e + 1ull);
+            sel[q] |= low;
+            e ^= low;
+            --need;
+          }
+        }
+      }
+    }
+    if (fallback) {
+      if (lane == 0) { runs[r] = meff; nsel[r] = ns; }
+      if (lane < 4) mask[4 * (uint64_t)r + lane] = ~0ull;
+      ++n_fb;
+      continue;
+    }
+    // runs: a kept slot starts a run unless the previous slot is kept in the same interval
+    uint32_t nruns = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const uint32_t rel = sk[q] - k;
-      if (rel < 2u) {
-        const uint32_t lo = rel * 32u + blo[q], hi = rel * 32u + bhi[q];
-        float v = clo[q] * wbuf[wave][lo];
-        if (hi > lo) v += (cbuf[wave][hi - 1] - cbuf[wave][lo]) + chi[q] * wbuf[wave][hi];
-        p[q] = v;
+      const uint32_t s = (uint32_t)lane + 64u * q;
+      const bool mine = (sel[q] >> lane) & 1ull;
+      bool start = false;
+      if (mine) {
+        if (s % n == 0) start = true;
+        else {
+          const uint32_t ps = s - 1;
+          start = !((sel[ps / 64] >> (ps % 64)) & 1ull);
+        }
       }
+      nruns += (uint32_t)__popcll(__ballot(start));
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  }
-  const float M = -expm1f(-carry);
-  if (mass_out && lane == 0) mass_out[r] = M;
-  bool fallback = !(M >= mass_thresh);
-  uint32_t count = 0;
-  if (!fallback) {
-    if (lane < 4) mlds[wave][lane] = 0ull;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const float target = mass_thresh * M;
-    bool reached = true;
-    count = ns <= 128 ? select_sorted<2>(p, ns, target, lane, mlds[wave], &reached)
-                      : select_sorted<4>(p, ns, target, lane, mlds[wave], &reached);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if (count > (uint32_t)cap || count == 0 || !reached) fallback = true;
-  }
-  if (fallback) {
-    if (lane == 0) { runs[r] = meff; nsel[r] = ns; }
-    if (lane < 4) mask[4 * (uint64_t)r + lane] = ~0ull;
-    ++n_fb;
-    continue;
-  }
-  uint64_t sel[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) sel[q] = mlds[wave][q];
-  // runs: a kept slot starts a run unless the previous slot is kept in the same interval
-  uint32_t nruns = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t s = (uint32_t)lane + 64u * q;
-    const bool mine = (sel[q] >> lane) & 1ull;
-    bool start = false;
-    if (mine) {
-      if (s % n == 0) start = true;
-      else {
-        const uint32_t ps = s - 1;
-        start = !((sel[ps / 64] >> (ps % 64)) & 1ull);
-      }
-    }
-    nruns += (uint32_t)__popcll(__ballot(start));
-  }
-  if (lane == 0) { runs[r] = nruns; nsel[r] = count; }
-  if (lane < 4) mask[4 * (uint64_t)r + lane] = sel[lane];
+    if (lane == 0) { runs[r] = nruns; nsel[r] = count; }
+    if (lane < 4) mask[4 * (uint64_t)r + lane] = sel[lane];
   }
   if (lane == 0) fb_lds[wave] = n_fb;
   __syncthreads();
@@ -926,7 +1000,7 @@ hipError_t launch_prop_pack(int dtype, const float* master, void* packed, hipStr
 
 hipError_t launch_prop_fwd(int dtype, const void* packed, const IvSet& iv, const float* o, const float* d,
                            int64_t stride, int64_t r0, const float* leafbox, int s_max, uint32_t n_iv_max,
-                           float* tau, hipStream_t st) {
+                           bool cum, float* tau, hipStream_t st) {
   int n = 0;
   hipError_t e = ncu(&n);
   if (e != hipSuccess) return e;
@@ -935,10 +1009,10 @@ hipError_t launch_prop_fwd(int dtype, const void* packed, const IvSet& iv, const
   uint32_t grid = std::min<uint32_t>(tiles > 0 ? tiles : 1, (uint32_t)n * 8);
   if (dtype == AMNERF_BF16)
     hipLaunchKernelGGL(k_prop_fwd<true>, dim3(grid), dim3(kThreads), kBf16Bytes, st, (const uint8_t*)packed, iv, o,
-                       d, stride, r0, leafbox, s_max, tau);
+                       d, stride, r0, leafbox, s_max, cum ? 1 : 0, tau);
   else
     hipLaunchKernelGGL(k_prop_fwd<false>, dim3(grid), dim3(kThreads), kBiasBytes + kF32Units * kUnitBytes, st,
-                       (const uint8_t*)packed, iv, o, d, stride, r0, leafbox, s_max, tau);
+                       (const uint8_t*)packed, iv, o, d, stride, r0, leafbox, s_max, cum ? 1 : 0, tau);
   return hipGetLastError();
 }
 
