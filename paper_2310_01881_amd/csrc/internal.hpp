@@ -109,6 +109,11 @@ struct MlpGeom {
   size_t bwd_node_bytes;  // packed backward bytes of one leaf (bfloat16 only)
 };
 bool mlp_geom(int n_hidden, int hidden, int dtype, MlpGeom* g);
+// Blocks of `kern` (threads per block, dynamic LDS bytes) resident per compute unit on the
+// current device: the register/wave limit from the runtime, the LDS limit from the
+// device's LDS size per compute unit.
+hipError_t resident_blocks(const void* kern, int threads, uint32_t lds, int* per_cu);
+
 hipError_t launch_mlp_pack(const MlpGeom& g, int n_leaves, const float* master, void* packed,
                            hipStream_t st);
 hipError_t launch_mlp(const MlpGeom& g, const void* packed, uint32_t n_leaves,

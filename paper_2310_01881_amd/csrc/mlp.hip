@@ -16,6 +16,8 @@
 // Biases enter as the C operand of the first MFMA of each output block.
 //   F32  : v_mfma_f32_16x16x4_f32  (fp32 in, fp32 accumulate)
 //   BF16 : v_mfma_f32_16x16x32_bf16 (bf16 in, fp32 accumulate)
+#include <algorithm>
+
 #include "internal.hpp"
 #include "devcommon.hpp"
 #include "mlp_layout.hpp"
@@ -112,7 +114,7 @@ __global__ void k_mlp_pack(Layout L, int n_leaves, int P, const float* __restric
 }
 
 template <int H, bool BF16>
-__global__ __launch_bounds__(kThreads) void k_mlp(
+__global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
     Layout L, const uint8_t* __restrict__ packed, uint32_t n_leaves,
     const uint32_t* __restrict__ bucket_off, const uint32_t* __restrict__ tile_off,
     const ChunkCounts* __restrict__ counts, const uint32_t* __restrict__ srec_ray,
@@ -155,7 +157,8 @@ __global__ __launch_bounds__(kThreads) void k_mlp(
     if (row0 >= row_end) continue;
 
     // ---- inputs: positional encoding of this lane's 8 features for 4 samples ----
-    float feat[NCB][8];
+    float feat[NCB][8];   // float32 inputs (the BF16 path packs them at once into X0)
+    bf16x8 X0[NCB];
     uint32_t dst_idx[NCB];
     bool valid[NCB];
 #pragma unroll
@@ -183,20 +186,22 @@ __global__ __launch_bounds__(kThreads) void k_mlp(
         float v = g == 1 ? py : (g == 2 ? pz : px);
         float sn = __builtin_amdgcn_sinf(0.5f * v);
         float cs = __builtin_amdgcn_cosf(0.5f * v);
+        float f[8];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          feat[cb][2 * k] = sn;
-          feat[cb][2 * k + 1] = cs;
+          f[2 * k] = sn;
+          f[2 * k + 1] = cs;
           float t2 = sn + sn;
           float s2 = t2 * cs;
           cs = fmaf(-t2, sn, 1.f);
           sn = s2;
         }
         if (g == 3) {
-          feat[cb][0] = px; feat[cb][1] = py; feat[cb][2] = pz;
-          feat[cb][3] = dx; feat[cb][4] = dy; feat[cb][5] = dz;
-          feat[cb][6] = 0.f; feat[cb][7] = 0.f;
+          f[0] = px; f[1] = py; f[2] = pz;
+          f[3] = dx; f[4] = dy; f[5] = dz;
+          f[6] = 0.f; f[7] = 0.f;
         }
+        X0[cb] = cvt_bf16x8(f);
       } else {
         float sc = (float)(1 << g);
         float s0 = sinpif(px * sc), c0 = cospif(px * sc);
@@ -212,41 +217,26 @@ __global__ __launch_bounds__(kThreads) void k_mlp(
     }
 
     f32x4 acc[NCB][RB];
-    // ---- layer 0: 32 (padded) -> H ----
+    if (BF16) {
+      // ---- layer 0: 32 (padded) -> H ----
+      {
+        bf16x8 A0[RB];
+        f32x4 bv[RB];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
-      if (BF16) {
-        bf16x8 A = *reinterpret_cast<const bf16x8*>(units + L.unit_index(0, rb, 0) * kUnitBytes + lane * 16);
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          bf16x8 Bv;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) Bv[e] = (__bf16)feat[cb][e];
-          acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv, bv, 0, 0, 0);
+        for (int rb = 0; rb < RB; ++rb) {
+          A0[rb] = *reinterpret_cast<const bf16x8*>(units + L.unit_index(0, rb, 0) * kUnitBytes + lane * 16);
+          bv[rb] = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
         }
-      } else {
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[cb][rb] = bv;
+        for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-        for (int ku = 0; ku < 2; ++ku) {
-          f32x4 A = *reinterpret_cast<const f32x4*>(units + L.unit_index(0, rb, ku) * kUnitBytes + lane * 16);
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb)
-              acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], feat[cb][4 * ku + e], acc[cb][rb], 0, 0, 0);
-        }
+          for (int rb = 0; rb < RB; ++rb) acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[rb], X0[cb], bv[rb], 0, 0, 0);
       }
-    }
-
-    // ---- hidden layers H -> H, then the output layer H -> 4 (padded to 16) ----
-    for (int layer = 1; layer <= L.nh; ++layer) {
-      const bool last = layer == L.nh;
-      const int nrb = last ? 1 : RB;
-      // previous activations (ReLU) as B operands
-      f32x4 nacc[NCB][RB];
-      if (BF16) {
+      // ---- hidden layers H -> H, then the output layer H -> 4 (padded to 16): the previous
+      //      activations of all column blocks are rounded to bf16 (with ReLU) first, so the
+      //      accumulators can be replaced in place one output row block at a time ----
+      for (int layer = 1; layer <= L.nh; ++layer) {
+        const int nrb = layer == L.nh ? 1 : RB;
         bf16x8 Bv[NCB][KUh];
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
@@ -260,37 +250,63 @@ __global__ __launch_bounds__(kThreads) void k_mlp(
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           if (rb >= nrb) break;
-          f32x4 bv = *reinterpret_cast<const f32x4*>(bias + (layer * H) + 16 * rb + 4 * g);
+          bf16x8 A[KUh];
 #pragma unroll
-          for (int ku = 0; ku < KUh; ++ku) {
-            bf16x8 A = *reinterpret_cast<const bf16x8*>(units + L.unit_index(layer, rb, ku) * kUnitBytes + lane * 16);
+          for (int ku = 0; ku < KUh; ++ku)
+            A[ku] = *reinterpret_cast<const bf16x8*>(units + L.unit_index(layer, rb, ku) * kUnitBytes + lane * 16);
+          const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + layer * H + 16 * rb + 4 * g);
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb)
-              nacc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv[cb][ku], ku == 0 ? bv : nacc[cb][rb], 0, 0, 0);
+          for (int cb = 0; cb < NCB; ++cb) {
+            f32x4 c = bv;
+#pragma unroll
+            for (int ku = 0; ku < KUh; ++ku) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ku], Bv[cb][ku], c, 0, 0, 0);
+            acc[cb][rb] = c;
           }
         }
-      } else {
+      }
+    } else {
+    // ---- layer 0: 32 (padded) -> H ----
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
+    for (int rb = 0; rb < RB; ++rb) {
+      f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
 #pragma unroll
-          for (int rb = 0; rb < RB; ++rb)
+      for (int cb = 0; cb < NCB; ++cb) acc[cb][rb] = bv;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[cb][rb][e] = fmaxf(acc[cb][rb][e], 0.f);
+      for (int ku = 0; ku < 2; ++ku) {
+        f32x4 A = *reinterpret_cast<const f32x4*>(units + L.unit_index(0, rb, ku) * kUnitBytes + lane * 16);
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          if (rb >= nrb) break;
-          f32x4 bv = *reinterpret_cast<const f32x4*>(bias + (layer * H) + 16 * rb + 4 * g);
+        for (int e = 0; e < 4; ++e)
 #pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) nacc[cb][rb] = bv;
+          for (int cb = 0; cb < NCB; ++cb)
+            acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], feat[cb][4 * ku + e], acc[cb][rb], 0, 0, 0);
+      }
+    }
+
+    // ---- hidden layers H -> H, then the output layer H -> 4 (padded to 16) ----
+    for (int layer = 1; layer <= L.nh; ++layer) {
+      const bool last = layer == L.nh;
+      const int nrb = last ? 1 : RB;
+      f32x4 nacc[NCB][RB];
 #pragma unroll
-          for (int ku = 0; ku < KUh; ++ku) {
-            f32x4 A = *reinterpret_cast<const f32x4*>(units + L.unit_index(layer, rb, ku) * kUnitBytes + lane * 16);
+      for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-              for (int cb = 0; cb < NCB; ++cb)
-                nacc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], acc[cb][ku][e], nacc[cb][rb], 0, 0, 0);
-          }
+          for (int e = 0; e < 4; ++e) acc[cb][rb][e] = fmaxf(acc[cb][rb][e], 0.f);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        if (rb >= nrb) break;
+        f32x4 bv = *reinterpret_cast<const f32x4*>(bias + (layer * H) + 16 * rb + 4 * g);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) nacc[cb][rb] = bv;
+#pragma unroll
+        for (int ku = 0; ku < KUh; ++ku) {
+          f32x4 A = *reinterpret_cast<const f32x4*>(units + L.unit_index(layer, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              nacc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], acc[cb][ku][e], nacc[cb][rb], 0, 0, 0);
         }
       }
 #pragma unroll
@@ -298,6 +314,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp(
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
           if (rb < nrb) acc[cb][rb] = nacc[cb][rb];
+    }
     }
 
     // ---- lanes of group 0 hold the pre-activations (sigma^, r^, g^, b^) of their sample;
@@ -326,9 +343,8 @@ hipError_t launch_typed(const Layout& L, const void* packed, uint32_t n_leaves, 
     int dev = 0, ncu = 0, per = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kThreads, L.bytes);
+    if (e == hipSuccess) e = resident_blocks((const void*)kern, kThreads, L.bytes, &per);
     if (e != hipSuccess) return e;
-    if (per < 1) per = 1;
     grid = ncu * per;
     grid_bytes = L.bytes;
   }
@@ -338,6 +354,18 @@ hipError_t launch_typed(const Layout& L, const void* packed, uint32_t n_leaves, 
 }
 
 }  // namespace
+
+hipError_t resident_blocks(const void* kern, int threads, uint32_t lds, int* per_cu) {
+  int dev = 0, lds_cu = 0, per_regs = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_regs, kern, threads, 0);
+  if (e != hipSuccess) return e;
+  int per = per_regs;
+  if (lds > 0 && lds_cu > 0) per = std::min(per, (int)((uint32_t)lds_cu / lds));
+  *per_cu = per > 0 ? per : 1;
+  return hipSuccess;
+}
 
 bool mlp_geom(int n_hidden, int hidden, int dtype, MlpGeom* g) {
   if (n_hidden < 1 || n_hidden > 8) return false;

@@ -298,9 +298,9 @@ hipError_t launch_bwd_typed(const Layout& L, const void* packed, uint32_t n_leav
     int dev = 0, ncu = 0, per = 0;
     e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kThreads, lds);
+    if (e == hipSuccess) e = resident_blocks((const void*)kern, kThreads, lds, &per);
     if (e != hipSuccess) return e;
-    grid = ncu * (per > 0 ? per : 1);
+    grid = ncu * per;
   }
   const uint8_t* pf = (const uint8_t*)packed;
   const uint8_t* pb = pf + (uint64_t)n_leaves * L.bytes;

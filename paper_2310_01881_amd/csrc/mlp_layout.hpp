@@ -96,13 +96,31 @@ __host__ __device__ __forceinline__ int master_param_count(int nh, int H) {
 
 // ReLU of eight values rounded to bfloat16: after the conversion the sign is the top bit,
 // so a packed signed 16-bit max with 0 clears every negative value (and -0).
-__device__ __forceinline__ bf16x8 relu_bf16x8(const float v[8]) {
-  bf16x8 h;
+// Pairs are converted with one packed conversion each.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+
+__device__ __forceinline__ bf16x8 cvt_bf16x8(const float v[8]) {
+  uint32_t w[4];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) h[e] = (__bf16)v[e];
-  s16x8 s = __builtin_bit_cast(s16x8, h);
-  s = __builtin_elementwise_max(s, (s16x8)0);
-  return __builtin_bit_cast(bf16x8, s);
+  for (int i = 0; i < 4; ++i) w[i] = bf16_pair(v[2 * i], v[2 * i + 1]);
+  return __builtin_bit_cast(bf16x8, w);
+}
+
+__device__ __forceinline__ bf16x8 relu_bf16x8(const float v[8]) {
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    s16x2 s = __builtin_bit_cast(s16x2, bf16_pair(v[2 * i], v[2 * i + 1]));
+    s = __builtin_elementwise_max(s, (s16x2)0);
+    w[i] = __builtin_bit_cast(uint32_t, s);
+  }
+  return __builtin_bit_cast(bf16x8, w);
 }
 
 }  // namespace amn
