@@ -142,6 +142,34 @@ __global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
   }
   uint32_t b = lo;
   int cur = -1;
+  // Inputs of the wave's 64 rows of the next tile, one row per lane: the sample record is
+  // loaded a tile ahead and the ray's origin and direction are gathered during the current
+  // tile's first layer, so neither load is waited for at the start of a tile.
+  uint32_t qb = lo, q_row0 = 0, q_end = 0;
+  uint32_t n_ray = 0, n_perm = 0;
+  float n_t = 0.f, n_o[3] = {0.f, 0.f, 0.f}, n_d[3] = {0.f, 0.f, 0.f};
+  auto next_rows = [&](uint32_t tt) {
+    while (tile_off[qb + 1] <= tt) ++qb;
+    q_row0 = bucket_off[qb] + (tt - tile_off[qb]) * kMlpTileRows + wave * 64;
+    q_end = bucket_off[qb + 1];
+    const uint32_t row = q_row0 + lane;
+    n_ray = 0u; n_perm = 0u; n_t = 0.f;
+    if (row < q_end) {
+      n_ray = srec_ray[row];
+      n_t = srec_t[row];
+      n_perm = perm[row];
+    }
+  };
+  auto gather = [&]() {
+    const int64_t ri = r0 + n_ray;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      n_o[a] = o[a * stride + ri];
+      n_d[a] = d[a * stride + ri];
+    }
+  };
+  next_rows(tb);
+  gather();
   for (uint32_t t = tb; t < te; ++t) {
     while (tile_off[b + 1] <= t) ++b;
     if ((int)b != cur) {
@@ -152,9 +180,21 @@ __global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
       __syncthreads();
       cur = (int)b;
     }
-    const uint32_t row0 = bucket_off[b] + (t - tile_off[b]) * kMlpTileRows + wave * 64;
-    const uint32_t row_end = bucket_off[b + 1];
-    if (row0 >= row_end) continue;
+    const uint32_t row0 = q_row0, row_end = q_end;
+    const uint32_t c_perm = n_perm;
+    // this lane's row: sample position mapped to [-1, 1]^3, and the direction
+    float c_p[3], c_d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      c_d[a] = n_d[a];
+      c_p[a] = 2.f * fmaf(n_t, n_d[a], n_o[a]) - 1.f;
+    }
+    const bool more = t + 1 < te;
+    if (more) next_rows(t + 1);
+    if (row0 >= row_end) {
+      if (more) gather();
+      continue;
+    }
 
     // ---- inputs: positional encoding of this lane's 8 features for 4 samples ----
     float feat[NCB][8];   // float32 inputs (the BF16 path packs them at once into X0)
@@ -163,22 +203,11 @@ __global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
     bool valid[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
-      uint32_t row = row0 + cb * 16 + m;
-      valid[cb] = row < row_end;
-      uint32_t ray = 0;
-      float ts = 0.f;
-      dst_idx[cb] = 0;
-      if (valid[cb]) {
-        ray = srec_ray[row];
-        ts = srec_t[row];
-        dst_idx[cb] = perm[row];
-      }
-      int64_t ri = r0 + ray;
-      float ox = o[ri], oy = o[stride + ri], oz = o[2 * stride + ri];
-      float dx = d[ri], dy = d[stride + ri], dz = d[2 * stride + ri];
-      float px = 2.f * fmaf(ts, dx, ox) - 1.f;
-      float py = 2.f * fmaf(ts, dy, oy) - 1.f;
-      float pz = 2.f * fmaf(ts, dz, oz) - 1.f;
+      const int src = cb * 16 + m;   // lane holding row cb * 16 + m
+      valid[cb] = row0 + (uint32_t)src < row_end;
+      dst_idx[cb] = (uint32_t)__shfl((int)c_perm, src, 64);
+      float px = __shfl(c_p[0], src, 64), py = __shfl(c_p[1], src, 64), pz = __shfl(c_p[2], src, 64);
+      float dx = __shfl(c_d[0], src, 64), dy = __shfl(c_d[1], src, 64), dz = __shfl(c_d[2], src, 64);
       if (BF16) {
         // this lane group's coordinate at frequencies 1, 2, 4, 8 (times pi): the hardware
         // sine takes revolutions, sin(2 pi r) with r = v / 2 exactly; higher frequencies by
@@ -218,38 +247,31 @@ __global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
 
     f32x4 acc[NCB][RB];
     if (BF16) {
+      // Activations between layers are held as ReLU'd bf16 B operands: H[cb][ku] packs
+      // accumulator rows 2ku (elements 0..3) and 2ku+1 (elements 4..7) of column block cb,
+      // two values per register.  Each output row block is converted as soon as its MFMAs
+      // finish, so only one row block of float accumulators is live at a time.
+      uint32_t Hc[NCB][KUh][4];
       // ---- layer 0: 32 (padded) -> H ----
-      {
-        bf16x8 A0[RB];
-        f32x4 bv[RB];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          A0[rb] = *reinterpret_cast<const bf16x8*>(units + L.unit_index(0, rb, 0) * kUnitBytes + lane * 16);
-          bv[rb] = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
+      for (int rb = 0; rb < RB; ++rb) {
+        const bf16x8 A0 = *reinterpret_cast<const bf16x8*>(units + L.unit_index(0, rb, 0) * kUnitBytes + lane * 16);
+        const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, X0[cb], bv, 0, 0, 0);
+          Hc[cb][rb >> 1][2 * (rb & 1)] = relu_bf16_pair(c[0], c[1]);
+          Hc[cb][rb >> 1][2 * (rb & 1) + 1] = relu_bf16_pair(c[2], c[3]);
         }
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[rb], X0[cb], bv[rb], 0, 0, 0);
       }
-      // ---- hidden layers H -> H, then the output layer H -> 4 (padded to 16): the previous
-      //      activations of all column blocks are rounded to bf16 (with ReLU) first, so the
-      //      accumulators can be replaced in place one output row block at a time ----
-      for (int layer = 1; layer <= L.nh; ++layer) {
-        const int nrb = layer == L.nh ? 1 : RB;
-        bf16x8 Bv[NCB][KUh];
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-          for (int ku = 0; ku < KUh; ++ku) {
-            float v[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = acc[cb][2 * ku + e / 4][e % 4];
-            Bv[cb][ku] = relu_bf16x8(v);
-          }
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) gather();
+      __builtin_amdgcn_sched_barrier(0);
+      // ---- hidden layers H -> H ----
+      for (int layer = 1; layer < L.nh; ++layer) {
+        uint32_t Hn[NCB][KUh][4];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-          if (rb >= nrb) break;
           bf16x8 A[KUh];
 #pragma unroll
           for (int ku = 0; ku < KUh; ++ku)
@@ -259,9 +281,33 @@ __global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
           for (int cb = 0; cb < NCB; ++cb) {
             f32x4 c = bv;
 #pragma unroll
-            for (int ku = 0; ku < KUh; ++ku) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ku], Bv[cb][ku], c, 0, 0, 0);
-            acc[cb][rb] = c;
+            for (int ku = 0; ku < KUh; ++ku)
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ku], __builtin_bit_cast(bf16x8, Hc[cb][ku]), c, 0, 0, 0);
+            Hn[cb][rb >> 1][2 * (rb & 1)] = relu_bf16_pair(c[0], c[1]);
+            Hn[cb][rb >> 1][2 * (rb & 1) + 1] = relu_bf16_pair(c[2], c[3]);
           }
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int ku = 0; ku < KUh; ++ku)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Hc[cb][ku][i] = Hn[cb][ku][i];
+      }
+      // ---- output layer H -> 4 (padded to 16) ----
+      {
+        bf16x8 A[KUh];
+#pragma unroll
+        for (int ku = 0; ku < KUh; ++ku)
+          A[ku] = *reinterpret_cast<const bf16x8*>(units + L.unit_index(L.nh, 0, ku) * kUnitBytes + lane * 16);
+        const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + L.nh * H + 4 * g);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          f32x4 c = bv;
+#pragma unroll
+          for (int ku = 0; ku < KUh; ++ku)
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ku], __builtin_bit_cast(bf16x8, Hc[cb][ku]), c, 0, 0, 0);
+          acc[cb][0] = c;
         }
       }
     } else {
@@ -282,6 +328,9 @@ __global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
       }
     }
 
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) gather();
+    __builtin_amdgcn_sched_barrier(0);
     // ---- hidden layers H -> H, then the output layer H -> 4 (padded to 16) ----
     for (int layer = 1; layer <= L.nh; ++layer) {
       const bool last = layer == L.nh;

@@ -112,6 +112,13 @@ __device__ __forceinline__ bf16x8 cvt_bf16x8(const float v[8]) {
   return __builtin_bit_cast(bf16x8, w);
 }
 
+// ReLU of a pair rounded to bfloat16, packed low (a) and high (b).
+__device__ __forceinline__ uint32_t relu_bf16_pair(float a, float b) {
+  s16x2 s = __builtin_bit_cast(s16x2, bf16_pair(a, b));
+  s = __builtin_elementwise_max(s, (s16x2)0);
+  return __builtin_bit_cast(uint32_t, s);
+}
+
 __device__ __forceinline__ bf16x8 relu_bf16x8(const float v[8]) {
   uint32_t w[4];
 #pragma unroll
