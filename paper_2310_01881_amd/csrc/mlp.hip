@@ -113,6 +113,67 @@ __global__ void k_mlp_pack(Layout L, int n_leaves, int P, const float* __restric
   }
 }
 
+// ---- BF16 layer steps.  Activations between layers are ReLU'd bf16 B operands: H[cb][ku]
+// packs accumulator rows 2ku (elements 0..3) and 2ku+1 (elements 4..7) of column block
+// cb, two values per register.  A layer walks its output row blocks and converts the
+// previous block's results while the current block's MFMAs run, so the MFMA result
+// latency is not waited for in line.
+template <int H, int NCB, int KIN>
+__device__ __forceinline__ void bf16_layer(const Layout& L, const uint8_t* units, const float* bias, int layer, int lane,
+                                           int g, const uint32_t (&Hin)[NCB][KIN][4], uint32_t (&Hout)[NCB][H / 32][4]) {
+  constexpr int RB = H / 16;
+  f32x4 c[2][NCB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int cur = rb & 1, prv = cur ^ 1;
+    bf16x8 A[KIN];
+#pragma unroll
+    for (int ku = 0; ku < KIN; ++ku)
+      A[ku] = *reinterpret_cast<const bf16x8*>(units + L.unit_index(layer, rb, ku) * kUnitBytes + lane * 16);
+    const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + layer * H + 16 * rb + 4 * g);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) c[cur][cb] = bv;
+#pragma unroll
+    for (int ku = 0; ku < KIN; ++ku)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        c[cur][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ku], __builtin_bit_cast(bf16x8, Hin[cb][ku]),
+                                                             c[cur][cb], 0, 0, 0);
+    if (rb > 0) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        Hout[cb][(rb - 1) >> 1][2 * ((rb - 1) & 1)] = relu_bf16_pair(c[prv][cb][0], c[prv][cb][1]);
+        Hout[cb][(rb - 1) >> 1][2 * ((rb - 1) & 1) + 1] = relu_bf16_pair(c[prv][cb][2], c[prv][cb][3]);
+      }
+    }
+  }
+  constexpr int last = (RB - 1) & 1;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    Hout[cb][(RB - 1) >> 1][2 * ((RB - 1) & 1)] = relu_bf16_pair(c[last][cb][0], c[last][cb][1]);
+    Hout[cb][(RB - 1) >> 1][2 * ((RB - 1) & 1) + 1] = relu_bf16_pair(c[last][cb][2], c[last][cb][3]);
+  }
+}
+
+// Output layer H -> 4 (padded to 16): float pre-activations of column block cb.
+template <int H, int NCB>
+__device__ __forceinline__ void bf16_out(const Layout& L, const uint8_t* units, const float* bias, int lane, int g,
+                                         const uint32_t (&Hin)[NCB][H / 32][4], f32x4 (&out)[NCB]) {
+  constexpr int KUh = H / 32;
+  bf16x8 A[KUh];
+#pragma unroll
+  for (int ku = 0; ku < KUh; ++ku)
+    A[ku] = *reinterpret_cast<const bf16x8*>(units + L.unit_index(L.nh, 0, ku) * kUnitBytes + lane * 16);
+  const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + L.nh * H + 4 * g);
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) out[cb] = bv;
+#pragma unroll
+  for (int ku = 0; ku < KUh; ++ku)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      out[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ku], __builtin_bit_cast(bf16x8, Hin[cb][ku]), out[cb], 0, 0, 0);
+}
+
 template <int H, bool BF16>
 __global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
     Layout L, const uint8_t* __restrict__ packed, uint32_t n_leaves,
@@ -246,70 +307,35 @@ __global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
     }
 
     f32x4 acc[NCB][RB];
-    if (BF16) {
-      // Activations between layers are held as ReLU'd bf16 B operands: H[cb][ku] packs
-      // accumulator rows 2ku (elements 0..3) and 2ku+1 (elements 4..7) of column block cb,
-      // two values per register.  Each output row block is converted as soon as its MFMAs
-      // finish, so only one row block of float accumulators is live at a time.
-      uint32_t Hc[NCB][KUh][4];
-      // ---- layer 0: 32 (padded) -> H ----
+    if constexpr (BF16) {
+      // layer 0 reads the packed inputs (one K unit), then the hidden layers alternate
+      // between two activation buffers, two layers per step
+      uint32_t X0u[NCB][1][4];
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const bf16x8 A0 = *reinterpret_cast<const bf16x8*>(units + L.unit_index(0, rb, 0) * kUnitBytes + lane * 16);
-        const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
+      for (int cb = 0; cb < NCB; ++cb) {
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(&X0[cb]);
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, X0[cb], bv, 0, 0, 0);
-          Hc[cb][rb >> 1][2 * (rb & 1)] = relu_bf16_pair(c[0], c[1]);
-          Hc[cb][rb >> 1][2 * (rb & 1) + 1] = relu_bf16_pair(c[2], c[3]);
-        }
+        for (int i = 0; i < 4; ++i) X0u[cb][0][i] = w[i];
       }
+      uint32_t Ha[NCB][KUh][4], Hb[NCB][KUh][4];
+      bf16_layer<H, NCB, 1>(L, units, bias, 0, lane, g, X0u, Ha);
       __builtin_amdgcn_sched_barrier(0);
       if (more) gather();
       __builtin_amdgcn_sched_barrier(0);
-      // ---- hidden layers H -> H ----
-      for (int layer = 1; layer < L.nh; ++layer) {
-        uint32_t Hn[NCB][KUh][4];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          bf16x8 A[KUh];
-#pragma unroll
-          for (int ku = 0; ku < KUh; ++ku)
-            A[ku] = *reinterpret_cast<const bf16x8*>(units + L.unit_index(layer, rb, ku) * kUnitBytes + lane * 16);
-          const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + layer * H + 16 * rb + 4 * g);
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) {
-            f32x4 c = bv;
-#pragma unroll
-            for (int ku = 0; ku < KUh; ++ku)
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ku], __builtin_bit_cast(bf16x8, Hc[cb][ku]), c, 0, 0, 0);
-            Hn[cb][rb >> 1][2 * (rb & 1)] = relu_bf16_pair(c[0], c[1]);
-            Hn[cb][rb >> 1][2 * (rb & 1) + 1] = relu_bf16_pair(c[2], c[3]);
-          }
-        }
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-          for (int ku = 0; ku < KUh; ++ku)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) Hc[cb][ku][i] = Hn[cb][ku][i];
+      int layer = 1;
+      for (; layer + 1 < L.nh; layer += 2) {
+        bf16_layer<H, NCB, KUh>(L, units, bias, layer, lane, g, Ha, Hb);
+        bf16_layer<H, NCB, KUh>(L, units, bias, layer + 1, lane, g, Hb, Ha);
       }
-      // ---- output layer H -> 4 (padded to 16) ----
-      {
-        bf16x8 A[KUh];
-#pragma unroll
-        for (int ku = 0; ku < KUh; ++ku)
-          A[ku] = *reinterpret_cast<const bf16x8*>(units + L.unit_index(L.nh, 0, ku) * kUnitBytes + lane * 16);
-        const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + L.nh * H + 4 * g);
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          f32x4 c = bv;
-#pragma unroll
-          for (int ku = 0; ku < KUh; ++ku)
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ku], __builtin_bit_cast(bf16x8, Hc[cb][ku]), c, 0, 0, 0);
-          acc[cb][0] = c;
-        }
+      f32x4 res[NCB];
+      if (layer < L.nh) {
+        bf16_layer<H, NCB, KUh>(L, units, bias, layer, lane, g, Ha, Hb);
+        bf16_out<H, NCB>(L, units, bias, lane, g, Hb, res);
+      } else {
+        bf16_out<H, NCB>(L, units, bias, lane, g, Ha, res);
       }
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb][0] = res[cb];
     } else {
     // ---- layer 0: 32 (padded) -> H ----
 #pragma unroll
