@@ -396,8 +396,8 @@ constexpr int kMaxSlots = 256;   // >= AMNERF_MAX_SAMPLES + 1
 // 8: a mirror of 8 or 16 lanes followed by a mirror of 4 or 8), a swizzle within 32 lanes
 // (J = 16), or a general permute (J = 32).
 template <int J>
-__device__ __forceinline__ float xor_lane(float v) {
-  const int x = __float_as_int(v);
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+  const int x = (int)v;
   int r;
   if constexpr (J == 1) r = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);        // quad_perm 1,0,3,2
   else if constexpr (J == 2) r = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
@@ -407,47 +407,57 @@ __device__ __forceinline__ float xor_lane(float v) {
     r = __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false), 0x141, 0xF, 0xF, false);
   else if constexpr (J == 16) r = __builtin_amdgcn_ds_swizzle(x, 0x401F);             // xor 16 within 32
   else r = __shfl_xor(x, J, 64);
-  return __int_as_float(r);
+  return (uint32_t)r;
 }
 
-// One compare-exchange at lane distance J < 64 for element e of a bitonic k-block: the
-// lower element of a descending block keeps the maximum.
+// Bitonic sort, descending, of 64*E keys (element e = q*64 + lane held in key[q]).  The
+// keys are the bit patterns of non-negative floats, whose unsigned order is their value
+// order.  A compare-exchange at lane distance J keeps the maximum in the lower element of
+// a descending block; with dir = all ones (keep maximum) or 0 (keep minimum) per lane,
+// median3(key, other, dir) is that result in one instruction.  bit[j] holds all ones in
+// lanes whose bit j is clear.
 template <int J>
-__device__ __forceinline__ float bitonic_lane_step(float key, int e, int k) {
-  const float other = xor_lane<J>(key);
-  const bool keep_max = ((e & J) == 0) == ((e & k) == 0);
-  return keep_max ? fmaxf(key, other) : fminf(key, other);
+__device__ __forceinline__ uint32_t bitonic_lane_step(uint32_t key, uint32_t dir) {
+  const uint32_t other = xor_lane<J>(key);
+  return max(min(key, other), min(max(key, other), dir));   // median of (key, other, dir)
 }
 
-// Sorts 64*E values (element e = q*64 + lane held in key[q] of that lane), descending.
 template <int E>
-__device__ __forceinline__ void bitonic_desc(float key[E], int lane) {
+__device__ __forceinline__ void bitonic_desc(uint32_t key[E], int lane) {
+  uint32_t bit[6];
 #pragma unroll
-  for (int k = 2; k <= 64 * E; k <<= 1) {
+  for (int j = 0; j < 6; ++j) bit[j] = ((lane >> j) & 1) ? 0u : 0xFFFFFFFFu;
 #pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
+  for (int lk = 1; (1 << lk) <= 64 * E; ++lk) {
+    const int k = 1 << lk;
+#pragma unroll
+    for (int lj = lk - 1; lj >= 0; --lj) {
+      const int j = 1 << lj;
       if (j >= 64) {
 #pragma unroll
         for (int q = 0; q < E; ++q) {
           if (((q * 64) & j) != 0) continue;
           const int q2 = q + j / 64;
           const bool desc_block = ((q * 64) & k) == 0;
-          const float a = key[q], b = key[q2];
-          key[q] = desc_block ? fmaxf(a, b) : fminf(a, b);
-          key[q2] = desc_block ? fminf(a, b) : fmaxf(a, b);
+          const uint32_t a = key[q], b = key[q2];
+          key[q] = desc_block ? max(a, b) : min(a, b);
+          key[q2] = desc_block ? min(a, b) : max(a, b);
         }
         continue;
       }
 #pragma unroll
       for (int q = 0; q < E; ++q) {
-        const int e = q * 64 + lane;
+        // keep the maximum where (e & j) == 0 equals (e & k) == 0, e = q * 64 + lane
+        uint32_t dir;
+        if (k >= 64) dir = (((q * 64) & k) == 0) ? bit[lj] : ~bit[lj];
+        else dir = ~(bit[lj] ^ bit[lk]);
         switch (j) {
-          case 32: key[q] = bitonic_lane_step<32>(key[q], e, k); break;
-          case 16: key[q] = bitonic_lane_step<16>(key[q], e, k); break;
-          case 8: key[q] = bitonic_lane_step<8>(key[q], e, k); break;
-          case 4: key[q] = bitonic_lane_step<4>(key[q], e, k); break;
-          case 2: key[q] = bitonic_lane_step<2>(key[q], e, k); break;
-          default: key[q] = bitonic_lane_step<1>(key[q], e, k); break;
+          case 32: key[q] = bitonic_lane_step<32>(key[q], dir); break;
+          case 16: key[q] = bitonic_lane_step<16>(key[q], dir); break;
+          case 8: key[q] = bitonic_lane_step<8>(key[q], dir); break;
+          case 4: key[q] = bitonic_lane_step<4>(key[q], dir); break;
+          case 2: key[q] = bitonic_lane_step<2>(key[q], dir); break;
+          default: key[q] = bitonic_lane_step<1>(key[q], dir); break;
         }
       }
     }
@@ -470,15 +480,17 @@ __device__ __forceinline__ float one_minus_exp_neg(float d) {
 template <int E>
 __device__ __forceinline__ uint32_t count_sorted(const float p[4], uint32_t ns, float target, int lane, bool* reached,
                                                  float* wcut) {
-  float key[E];
+  // slots past ns sort last as +0 (a valid zero weight never decides the cut: adding it
+  // cannot reach a positive target)
+  uint32_t key[E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) key[q] = (uint32_t)lane + 64u * q < ns ? p[q] : -1.f;
+  for (int q = 0; q < E; ++q) key[q] = (uint32_t)lane + 64u * q < ns ? __float_as_uint(p[q]) : 0u;
   bitonic_desc<E>(key, lane);
   float carry = 0.f, cut = 0.f;
   uint32_t count = 0;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
-    const float v = fmaxf(key[q], 0.f);
+    const float v = __uint_as_float(key[q]);
     const float inc = wave_scan_incl(v);
     const uint32_t pos = (uint32_t)q * 64u + (uint32_t)lane;
     const bool take = pos < ns && carry + (inc - v) < target;
@@ -524,13 +536,15 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
     bool fallback = !(M >= mass_thresh);
     uint32_t count = 0;
     uint64_t sel[4] = {0ull, 0ull, 0ull, 0ull};
+    uint64_t first[4] = {0ull, 0ull, 0ull, 0ull};   // slots that start an interval
     const uint32_t n = ns / meff;
     if (!fallback) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      // floor(x / n) = (x * magic) >> 32 for x < 2^16 (the error x (magic - 2^32/n) / 2^32
-      // stays below 1/n, so it never carries into the integer part)
-      const uint64_t magic = ((1ull << 32) + n - 1) / n;
+      // floor(x / n) = umulhi(x, m) with m = ceil(2^32 / n) for x < 2^16 and n >= 2 (the
+      // error x (m - 2^32/n) / 2^32 stays below 1/n, so it never carries into the integer part)
+      const uint32_t m32 = n > 1u ? 0xFFFFFFFFu / n + 1u : 0u;
+      auto div_n = [&](uint32_t x) { return n > 1u ? __umulhi(x, m32) : x; };
       const float inv_n = 1.f / (float)n;
       const uint32_t nq = (ns + 63u) / 64u;
       float p[4] = {0.f, 0.f, 0.f, 0.f};
@@ -538,11 +552,12 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
       for (int q = 0; q < 4; ++q) {
         if ((uint32_t)q >= nq) break;
         const uint32_t s = (uint32_t)lane + 64u * q;
-        if (s >= ns) continue;
-        const uint32_t sk = (uint32_t)(((uint64_t)s * magic) >> 32);
+        const uint32_t sk = div_n(s);
         const uint32_t j = s - sk * n;
-        const uint32_t blo = (uint32_t)(((uint64_t)(32u * j) * magic) >> 32);
-        const uint32_t bhi = (uint32_t)(((uint64_t)(32u * (j + 1) + n - 1) * magic) >> 32) - 1u;
+        first[q] = __ballot(j == 0u);
+        if (s >= ns) continue;
+        const uint32_t blo = div_n(32u * j);
+        const uint32_t bhi = div_n(32u * (j + 1) + n - 1) - 1u;
         const float u0 = (float)(32u * j) * inv_n, u1 = (float)(32u * (j + 1)) * inv_n;
         const float* row = cum + (uint64_t)(i0 + sk) * kBins;
         const float S = sbuf[wave][sk];
@@ -601,17 +616,8 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
     uint32_t nruns = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const uint32_t s = (uint32_t)lane + 64u * q;
-      const bool mine = (sel[q] >> lane) & 1ull;
-      bool start = false;
-      if (mine) {
-        if (s % n == 0) start = true;
-        else {
-          const uint32_t ps = s - 1;
-          start = !((sel[ps / 64] >> (ps % 64)) & 1ull);
-        }
-      }
-      nruns += (uint32_t)__popcll(__ballot(start));
+      const uint64_t prev_kept = (sel[q] << 1) | (q > 0 ? sel[q - 1] >> 63 : 0ull);
+      nruns += (uint32_t)__popcll(sel[q] & ~(prev_kept & ~first[q]));
     }
     if (lane == 0) { runs[r] = nruns; nsel[r] = count; }
     if (lane < 4) mask[4 * (uint64_t)r + lane] = sel[lane];
