@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--prop-batch", type=int, default=32768)
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=20, help="timed training steps (0: skip)")
+    ap.add_argument("--train-batch", type=int, default=262144)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -157,15 +159,55 @@ def main():
             {k: round(v, 4) for k, v in results[kind]["stage_ms_per_frame"].items()}))
     am.amnerf_ctx_set_timing(ctx.h, False)
 
+    # ---- training step on the same scene (teacher-student, bf16 forward, float32 gradients,
+    #      Adam), timed apart from the frame ----
+    train = None
+    if args.train_steps > 0:
+        B = args.train_batch
+        tcams = synth.make_cameras(100, cfg.seed_batches + 3, cfg.width, cfg.height)
+        po, pd = synth.random_pixel_rays(tcams, 4 * B, cfg.seed_batches + 4)
+        po, pd = torch.from_numpy(po).to(dev), torch.from_numpy(pd).to(dev)
+        ptarget = torch.empty((4 * B, 3), device=dev)
+        am.amnerf_render(ctx.h, tree.h, mlps["f32"].desc, po, pd, cfg.s_max, ptarget, None, None, None, cfg.ert_eps)
+        batches = [(po[:, i * B:(i + 1) * B].contiguous(), pd[:, i * B:(i + 1) * B].contiguous(),
+                    ptarget[i * B:(i + 1) * B].contiguous()) for i in range(4)]
+        W_s = synth.make_weights(L, cfg.n_hidden, cfg.hidden, cfg.seed_student, dens)
+        trainer = am.Trainer(ctx, tree, torch.from_numpy(W_s).to(dev), cfg.n_hidden, cfg.hidden)
+        tlosses, tsamples = [], 0
+        for it in range(2):
+            ob, db_, tb = batches[it % 4]
+            tlosses.append(float(trainer.step(ob, db_, tb, cfg.s_max, lr=1e-3).item()))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for it in range(args.train_steps):
+            ob, db_, tb = batches[it % 4]
+            trainer.step(ob, db_, tb, cfg.s_max, lr=1e-3)
+        e1.record()
+        torch.cuda.synchronize()
+        t_ms = e0.elapsed_time(e1) / args.train_steps
+        for it in range(4):
+            ob, db_, tb = batches[it]
+            tlosses.append(float(trainer.step(ob, db_, tb, cfg.s_max, lr=1e-3).item()))
+            tsamples += am.amnerf_render_stats_get(ctx.h)["n_samples"]
+        train = {"ms_per_step": t_ms, "rays_per_step": B, "samples_per_step": tsamples / 4,
+                 "samples_per_s": tsamples / 4 / (t_ms * 1e-3), "steps": args.train_steps,
+                 "loss_first_last": [tlosses[0], tlosses[-1]],
+                 "workload": "teacher = the scene's leaf MLPs (float32 renders as targets), student re-seeded; "
+                             "%d-ray batches drawn from 100 cameras at 800x800" % B}
+        log("train: %.3f ms/step, %.3e samples/s, loss %.3e -> %.3e" % (
+            t_ms, train["samples_per_s"], tlosses[0], tlosses[-1]))
+
     # outputs of camera 0 for the accuracy report
     imgs = {}
     for kind in paths:
         render(kind, 0)
         torch.cuda.synchronize()
-        imgs[kind] = outs[kind]["rgb"].cpu().numpy().astype(np.float64)
+        imgs[kind] = outs[kind]["rgb"].clone()
 
     cpu = None
     psnr = {k: None for k in paths}
+    max_abs = {k: None for k in paths}
     if not args.no_cpu:
         import oracle
         otree = oracle.build_tree(grid, cfg.grid_n, cfg.max_depth, cfg.max_leaves)
@@ -189,10 +231,16 @@ def main():
         cpu = {"value": float(ns.sum()) / t_cpu, "unit": "samples/s", "cores": threads, "kind": "oracle",
                "sample": "%d random rays of held-out camera 0 (%.1f%% of one 800x800 frame, %d samples), "
                          "float64 plain render, %.1f s" % (n_sample, 100.0 * n_sample / R, int(ns.sum()), t_cpu)}
+        # float64 error report on the GPU over the sampled rays
+        sel_dev = torch.from_numpy(sel).to(dev)
+        ref_dev = torch.from_numpy(np.ascontiguousarray(rgb, dtype=np.float64)).to(dev).view(-1)
         for kind in paths:
-            psnr[kind] = oracle.psnr(imgs[kind][sel], rgb)
-        log("oracle: %.3e samples/s on %d threads; psnr %s" % (cpu["value"], threads,
-                                                              {k: round(v, 2) for k, v in psnr.items()}))
+            rep = am.amnerf_error_stats(ctx.h, imgs[kind][sel_dev].contiguous().view(-1), ref_dev)
+            psnr[kind] = rep["psnr"]
+            max_abs[kind] = rep["max_abs"]
+        log("oracle: %.3e samples/s on %d threads; psnr %s; max |rgb - oracle| %s" % (
+            cpu["value"], threads, {k: round(v, 2) for k, v in psnr.items()},
+            {k: float("%.3g" % v) for k, v in max_abs.items()}))
 
     head = results["bf16_prop"]
     achieved = head["mlp_tflops"]
@@ -231,7 +279,9 @@ def main():
                      "kernel": "k_mlp<64,bf16>", "kernel_ms": head["mlp_ms"]},
         "cpu_baseline": cpu,
         "psnr_vs_oracle_db": psnr,
+        "max_abs_rgb_vs_oracle": max_abs,
         "speedup_vs_plain_fp32": results["f32"]["ms_per_frame"] / head["ms_per_frame"],
+        "training": train,
         "paths": results,
     }
     print(json.dumps(line), flush=True)

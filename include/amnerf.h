@@ -375,6 +375,19 @@ int amnerf_propose(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* s
                    const amnerf_rays* rays, const amnerf_propose_params* p, int64_t* n_intervals,
                    void* stream);
 
+/* ---- error report (Section 4 reports rendering quality as PSNR) ---------------------- */
+/* Compares a device float32 result x_dev[n] with device float64 reference values
+ * ref_dev[n] (for instance reference outputs uploaded to the device) over the elements
+ * with sel_dev[i] != 0 (sel_dev may be NULL: all elements).  Writes to the host array
+ * out[4]: max |x - ref| (infinite if a difference is NaN), the sum of (x - ref)^2, the
+ * number of elements compared, and the sum of |x - ref|, accumulated in float64 on the
+ * device in a fixed order (bit-identical from run to run).  PSNR with peak 1 is
+ * 10 log10(out[2] / out[1]).  Synchronous: returns once out[] is written.  Uses 32 KiB of
+ * device memory held by the context.  EINVAL for a null ctx/out or n < 0, or null arrays
+ * with n > 0. */
+int amnerf_error_stats(amnerf_ctx* ctx, const float* x_dev, const double* ref_dev, const uint8_t* sel_dev,
+                       int64_t n, double out[4], void* stream);
+
 #ifdef __cplusplus
 }
 #endif

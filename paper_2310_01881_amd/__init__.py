@@ -9,6 +9,7 @@ this module fails loudly if it is missing.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -38,6 +39,7 @@ EXPORTS = [
     "amnerf_render_stats_get", "amnerf_render_inspect", "amnerf_ctx_set_timing",
     "amnerf_timing_collect", "amnerf_render_backward", "amnerf_adam_step", "amnerf_train_step",
     "amnerf_prop_param_count", "amnerf_prop_packed_bytes", "amnerf_prop_pack", "amnerf_propose",
+    "amnerf_error_stats",
 ]
 AMNERF_PROPOSE_INFER = 0
 AMNERF_PROPOSE_TRAIN = 1
@@ -152,6 +154,7 @@ def _load():
     lib.amnerf_timing_collect.argtypes = [P, P, C.POINTER(C.c_int64)]
     lib.amnerf_render_backward.argtypes = [P, P, C.POINTER(amnerf_mlp), C.POINTER(amnerf_rays), P, P, P, P, P]
     lib.amnerf_adam_step.argtypes = [P, C.c_int64, P, P, P, P, C.POINTER(amnerf_adam_params), P]
+    lib.amnerf_error_stats.argtypes = [P, P, P, P, C.c_int64, C.POINTER(C.c_double * 4), P]
     lib.amnerf_train_step.argtypes = [P, P, C.POINTER(amnerf_mlp_train), C.POINTER(amnerf_rays), P,
                                       C.POINTER(amnerf_train_params), P, P]
     lib.amnerf_prop_param_count.restype = C.c_int64
@@ -300,6 +303,21 @@ def amnerf_adam_step(ctx, param_dev, m_dev, v_dev, grad_dev, step, lr=1e-3, beta
     prm = amnerf_adam_params(lr, beta1, beta2, eps, step)
     _check(_lib.amnerf_adam_step(ctx, param_dev.numel(), _ptr(param_dev), _ptr(m_dev), _ptr(v_dev),
                                  _ptr(grad_dev), C.byref(prm), _stream(stream)))
+
+
+def amnerf_error_stats(ctx, x_dev, ref_dev, sel_dev=None, stream=None):
+    """float64 error report of a float32 device tensor against float64 device reference values
+    (same number of elements; sel_dev an optional uint8 mask): dict with max_abs, sum_sq, count,
+    sum_abs, and psnr (peak 1) and mse derived from them."""
+    n = x_dev.numel()
+    if ref_dev.numel() != n or (sel_dev is not None and sel_dev.numel() != n):
+        raise ValueError("amnerf_error_stats: size mismatch")
+    out = (C.c_double * 4)()
+    _check(_lib.amnerf_error_stats(ctx, _ptr(x_dev), _ptr(ref_dev), _ptr(sel_dev), n, C.byref(out), _stream(stream)))
+    mx, sq, cnt, ab = out[0], out[1], out[2], out[3]
+    mse = sq / cnt if cnt > 0 else 0.0
+    psnr = float("inf") if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
+    return {"max_abs": mx, "sum_sq": sq, "count": int(cnt), "sum_abs": ab, "mse": mse, "psnr": psnr}
 
 
 def amnerf_train_step(ctx, tree, train: amnerf_mlp_train, o_dev, d_dev, target_dev, loss_dev, s_max, step,

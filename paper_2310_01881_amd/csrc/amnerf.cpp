@@ -88,6 +88,9 @@ struct amnerf_ctx {
   // second arena: backward and training buffers
   void* arena2 = nullptr;
   size_t arena2_bytes = 0;
+  // error report: block partials and totals (device), totals (pinned host)
+  double* err_dev = nullptr;
+  double* err_host = nullptr;
 };
 
 struct amnerf_tree {
@@ -141,6 +144,8 @@ extern "C" int amnerf_ctx_destroy(amnerf_ctx* ctx) {
   if (ctx->arena3) (void)hipFree(ctx->arena3);
   if (ctx->counts) (void)hipFree(ctx->counts);
   if (ctx->counts_host) (void)hipHostFree(ctx->counts_host);
+  if (ctx->err_dev) (void)hipFree(ctx->err_dev);
+  if (ctx->err_host) (void)hipHostFree(ctx->err_host);
   delete ctx;
   return AMNERF_OK;
 }
@@ -893,6 +898,22 @@ extern "C" int amnerf_render_backward(amnerf_ctx* ctx, const amnerf_tree* tree, 
   if (!ctx || !tree || !mlp || !rays) return fail(AMNERF_EINVAL, "amnerf_render_backward: null argument");
   HIP_TRY(hipSetDevice(ctx->device));
   return backward_impl(ctx, tree, mlp, rays, g_rgb, g_depth, g_opac, grad, (hipStream_t)stream, nullptr);
+}
+
+extern "C" int amnerf_error_stats(amnerf_ctx* ctx, const float* x, const double* ref, const uint8_t* sel, int64_t n,
+                                  double out[4], void* stream) {
+  if (!ctx || !out || n < 0 || (n > 0 && (!x || !ref))) return fail(AMNERF_EINVAL, "amnerf_error_stats: bad argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (!ctx->err_dev) {
+    HIP_TRY(hipMalloc((void**)&ctx->err_dev, sizeof(double) * (4 * kErrBlocks + 4)));
+    HIP_TRY(hipHostMalloc((void**)&ctx->err_host, sizeof(double) * 4, 0));
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_error_stats(x, ref, sel, n, ctx->err_dev, ctx->err_dev + 4 * kErrBlocks, st));
+  HIP_TRY(hipMemcpyAsync(ctx->err_host, ctx->err_dev + 4 * kErrBlocks, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int i = 0; i < 4; ++i) out[i] = ctx->err_host[i];
+  return AMNERF_OK;
 }
 
 extern "C" int amnerf_adam_step(amnerf_ctx* ctx, int64_t n, float* param, float* m, float* v, const float* grad,

@@ -109,6 +109,12 @@ struct MlpGeom {
   size_t bwd_node_bytes;  // packed backward bytes of one leaf (bfloat16 only)
 };
 bool mlp_geom(int n_hidden, int hidden, int dtype, MlpGeom* g);
+// Error report: partial sums of kErrBlocks blocks (4 doubles each), then the totals
+// {max |x - ref|, sum (x - ref)^2, count, sum |x - ref|} in out[4] (device).
+constexpr int kErrBlocks = 1024;
+hipError_t launch_error_stats(const float* x, const double* ref, const uint8_t* sel, int64_t n, double* part,
+                              double* out, hipStream_t st);
+
 // Blocks of `kern` (threads per block, dynamic LDS bytes) resident per compute unit on the
 // current device: the register/wave limit from the runtime, the LDS limit from the
 // device's LDS size per compute unit.
