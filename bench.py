@@ -51,6 +51,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-steps", type=int, default=20, help="timed training steps (0: skip)")
+    ap.add_argument("--paths", default="f32,bf16,bf16_prop",
+                    help="comma-separated render paths to time (the headline bf16_prop is always timed)")
     ap.add_argument("--train-batch", type=int, default=262144)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -106,7 +108,9 @@ def main():
                                                              ["%.2e" % v for v in losses]))
     desc = prop.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
 
-    paths = {"f32": ("f32", None), "bf16": ("bf16", None), "bf16_prop": ("bf16", desc)}
+    all_paths = {"f32": ("f32", None), "bf16": ("bf16", None), "bf16_prop": ("bf16", desc)}
+    wanted = set(args.paths.split(",")) | {"bf16_prop"}
+    paths = {k: v for k, v in all_paths.items() if k in wanted}
     outs = {k: {"rgb": torch.empty((R, 3), device=dev), "depth": torch.empty(R, device=dev),
                 "opacity": torch.empty(R, device=dev)} for k in paths}
 
@@ -119,7 +123,7 @@ def main():
 
     # samples per camera (untimed)
     samples = {k: [] for k in paths}
-    fallback = []
+    fallback, plain = [], []
     for kind in paths:
         for cam in range(n_cams):
             render(kind, cam)
@@ -127,8 +131,9 @@ def main():
             samples[kind].append(st["n_samples"])
             if kind == "bf16_prop":
                 fallback.append(st["n_fallback"])
+                plain.append(st["n_plain_samples"])
     torch.cuda.synchronize()
-    log("samples per frame: plain %s, proposal %s, fallback rays %s" % (samples["f32"], samples["bf16_prop"], fallback))
+    log("samples per frame: plain %s, proposal %s, fallback rays %s" % (plain, samples["bf16_prop"], fallback))
 
     results = {}
     am.amnerf_ctx_set_timing(ctx.h, True)
@@ -269,7 +274,7 @@ def main():
                                "ERT at T<1e-4; 8 held-out cameras",
                    "rays_per_step": R, "n_leaves": L, "path": "bf16 leaf MLPs + learned proposal (bf16 inference, "
                    "<=48 samples/ray, fallback below 0.99 predicted mass)",
-                   "plain_samples_per_step": sum(samples["f32"]) / n_cams,
+                   "plain_samples_per_step": sum(plain) / n_cams,
                    "proposal_samples_per_step": sum(samples["bf16_prop"]) / n_cams,
                    "fallback_rays_per_step": sum(fallback) / n_cams,
                    "proposal_training": {"steps": args.prop_steps, "rays_per_step": args.prop_batch,
@@ -280,7 +285,7 @@ def main():
         "cpu_baseline": cpu,
         "psnr_vs_oracle_db": psnr,
         "max_abs_rgb_vs_oracle": max_abs,
-        "speedup_vs_plain_fp32": results["f32"]["ms_per_frame"] / head["ms_per_frame"],
+        "speedup_vs_plain_fp32": results["f32"]["ms_per_frame"] / head["ms_per_frame"] if "f32" in results else None,
         "training": train,
         "paths": results,
     }
