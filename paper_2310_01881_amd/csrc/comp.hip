@@ -13,8 +13,23 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
-__device__ __forceinline__ float logisticf(float z) { return 1.f / (1.f + expf(-z)); }
+// Output heads and exponentials from the hardware base-2 exponential, logarithm and
+// reciprocal (about 1 ulp each; the float32 result stays far inside the 1e-5 parity
+// tolerance).
+constexpr float kLog2e = 1.44269504f, kLn2 = 0.693147181f;
+__device__ __forceinline__ float exp_neg(float x) { return __builtin_amdgcn_exp2f(-kLog2e * x); }
+// softplus z = max(z, 0) + log(1 + e^-|z|), with log1p(e) = e (1 - e/2) below 2^-12
+__device__ __forceinline__ float softplusf(float z) {
+  const float e = exp_neg(fabsf(z));
+  const float l = e < 2.44140625e-4f ? e * fmaf(-0.5f, e, 1.f) : __builtin_amdgcn_logf(1.f + e) * kLn2;
+  return fmaxf(z, 0.f) + l;
+}
+__device__ __forceinline__ float logisticf(float z) { return __builtin_amdgcn_rcpf(1.f + exp_neg(z)); }
+// 1 - e^-t for t >= 0: a quartic Taylor polynomial below 1/16, else from the exponential
+__device__ __forceinline__ float one_minus_exp_neg(float t) {
+  if (t < 0.0625f) return t * fmaf(t, fmaf(t, fmaf(t, -1.f / 24.f, 1.f / 6.f), -0.5f), 1.f);
+  return 1.f - exp_neg(t);
+}
 
 // Unevaluated float pair hi + lo (compensated sums).
 struct DF {
@@ -31,7 +46,7 @@ __device__ __forceinline__ DF df_add(DF a, DF b) {
 }
 
 // exp(-(hi + lo)) for |lo| << 1: exp(-hi) * (1 - lo).
-__device__ __forceinline__ float df_exp_neg(DF a) { return expf(-a.hi) * (1.f - a.lo); }
+__device__ __forceinline__ float df_exp_neg(DF a) { return exp_neg(a.hi) * (1.f - a.lo); }
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -45,15 +60,27 @@ __device__ __forceinline__ float wave_sum(float v) {
 // Early termination: the first lane whose T_{j+1} < eps keeps its sample and later lanes
 // (and steps) contribute nothing.  Lane j finds its interval by binary search over the
 // intervals' first-sample indices.
+constexpr uint32_t kStage = 256;   // intervals of a ray searched in LDS (more: in memory)
+
 __global__ __launch_bounds__(kThreads) void k_composite(
     uint32_t nr, IvSet iv, const float* __restrict__ smp_out, int64_t r0, int jitter,
     uint64_t seed, float eps, float* __restrict__ rgb, float* __restrict__ depth,
     float* __restrict__ opac, float* __restrict__ weights, ChunkCounts* __restrict__ counts) {
-  const int lane = threadIdx.x & 63;
-  const uint32_t r = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  __shared__ uint32_t sbase[kThreads / 64][kStage];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t r = blockIdx.x * (kThreads / 64) + wave;
   if (r >= nr) return;
   const uint32_t i0 = iv.iv_off[r], i1 = iv.iv_off[r + 1];
   const uint32_t s0 = iv.smp_off[r], ns = iv.smp_off[r + 1] - s0;
+  // the ray's interval start samples (relative to s0), searched in LDS
+  const uint32_t m = i1 - i0;
+  const bool staged = m <= kStage;
+  if (staged) {
+    for (uint32_t k = lane; k < m; k += 64) sbase[wave][k] = iv.base[i0 + k] - s0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
   const uint64_t wbase = counts->smp_global + s0;
   float cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f, acc = 0.f;
   if (ns > 0) {
@@ -64,7 +91,17 @@ __global__ __launch_bounds__(kThreads) void k_composite(
       const bool valid = !done && j < ns;
       float tau = 0.f, sig_c[3] = {0.f, 0.f, 0.f}, t = 0.f;
       if (valid) {
-        const uint32_t i = find_interval(iv.base, i0, i1, s0 + j);
+        uint32_t i;
+        if (staged) {
+          uint32_t lo = 0, hi = m;
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (sbase[wave][mid] <= j) lo = mid; else hi = mid;
+          }
+          i = i0 + lo;
+        } else {
+          i = find_interval(iv.base, i0, i1, s0 + j);
+        }
         const uint32_t jj = s0 + j - iv.base[i];
         const float4 z = *reinterpret_cast<const float4*>(smp_out + 4 * (uint64_t)(s0 + j));
         const float delta = iv.dt[i] / (float)key_n(iv.key[i]);
@@ -86,7 +123,7 @@ __global__ __launch_bounds__(kThreads) void k_composite(
       if (lane == 0) exc = {0.f, 0.f};
       const DF S = df_add(carry, exc);
       const DF Sn = df_add(carry, inc);
-      float w = valid ? df_exp_neg(S) * -expm1f(-tau) : 0.f;
+      float w = valid ? df_exp_neg(S) * one_minus_exp_neg(tau) : 0.f;
       const bool stop = valid && eps > 0.f && df_exp_neg(Sn) < eps;
       const uint64_t stops = __ballot(stop);
       if (stops) {
