@@ -48,11 +48,26 @@ __device__ __forceinline__ DF df_add(DF a, DF b) {
 // exp(-(hi + lo)) for |lo| << 1: exp(-hi) * (1 - lo).
 __device__ __forceinline__ float df_exp_neg(DF a) { return exp_neg(a.hi) * (1.f - a.lo); }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// Inclusive compensated prefix sum over the wave: the float-pair add of wave_scan_incl's
+// shift pattern (within rows of 16 by 1, 2, 4, 8, then the last lane of row 0 (2) into
+// row 1 (3) and the last lane of row 1 into rows 2 and 3).  Lanes whose source is outside
+// the pattern add (0, 0), which leaves a normalised pair unchanged.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ DF df_shift(DF a) {
+  return {dpp_or_zero<CTRL, ROW_MASK>(a.hi), dpp_or_zero<CTRL, ROW_MASK>(a.lo)};
+}
+
+__device__ __forceinline__ DF df_scan_incl(DF v) {
+  v = df_add(v, df_shift<0x111, 0xF>(v));
+  v = df_add(v, df_shift<0x112, 0xF>(v));
+  v = df_add(v, df_shift<0x114, 0xF>(v));
+  v = df_add(v, df_shift<0x118, 0xF>(v));
+  v = df_add(v, df_shift<0x142, 0xA>(v));
+  v = df_add(v, df_shift<0x143, 0xC>(v));
   return v;
 }
+
+__device__ __forceinline__ float wave_sum(float v) { return lane_value(wave_scan_incl(v), 63); }
 
 // One wave per ray, 64 samples per step.  Lane j of a step handles sample base + j:
 // tau_j, then S_j = sum_{i<j} tau_i by a compensated (float pair) prefix scan across the
@@ -112,15 +127,9 @@ __global__ __launch_bounds__(kThreads) void k_composite(
         sig_c[1] = logisticf(z.z);
         sig_c[2] = logisticf(z.w);
       }
-      // inclusive compensated scan of tau across the wave
-      DF inc = {tau, 0.f};
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        DF y = {__shfl_up(inc.hi, off, 64), __shfl_up(inc.lo, off, 64)};
-        if (lane >= off) inc = df_add(inc, y);
-      }
-      DF exc = {__shfl_up(inc.hi, 1, 64), __shfl_up(inc.lo, 1, 64)};
-      if (lane == 0) exc = {0.f, 0.f};
+      // inclusive compensated scan of tau across the wave; exclusive = shifted by one lane
+      const DF inc = df_scan_incl({tau, 0.f});
+      const DF exc = df_shift<0x138, 0xF>(inc);   // wave_shr:1, lane 0 reads (0, 0)
       const DF S = df_add(carry, exc);
       const DF Sn = df_add(carry, inc);
       float w = valid ? df_exp_neg(S) * one_minus_exp_neg(tau) : 0.f;
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_composite(
       dep = fmaf(w, t, dep);
       acc += w;
       if (weights && j < ns) weights[wbase + j] = w;
-      carry = {__shfl(Sn.hi, 63, 64), __shfl(Sn.lo, 63, 64)};
+      carry = {lane_value(Sn.hi, 63), lane_value(Sn.lo, 63)};
       if (done && !weights) break;
     }
     cr = wave_sum(cr);
