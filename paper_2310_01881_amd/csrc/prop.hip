@@ -631,7 +631,10 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
   }
 }
 
-// ---- emission of the planned intervals: one lane per ray ------------------------------
+// ---- emission of the planned intervals: one lane per ray -------------------------------
+// The lane walks its ray's slot mask run by run: trailing zeros skip slots that are not
+// kept, trailing ones give the run's length, cut at the interval's end.  A run that is a
+// whole interval keeps its endpoints exactly.
 __global__ __launch_bounds__(kThreads) void k_prop_emit(uint32_t nr, IvSet iv, const uint64_t* __restrict__ mask,
                                                         const uint32_t* __restrict__ pv_off,
                                                         const uint32_t* __restrict__ ps_off,
@@ -644,19 +647,34 @@ __global__ __launch_bounds__(kThreads) void k_prop_emit(uint32_t nr, IvSet iv, c
   if (meff == 0) return;
   const uint32_t ns = iv.smp_off[r + 1] - iv.smp_off[r];
   const uint32_t n = ns / meff;
+  const uint32_t m32 = n > 1u ? 0xFFFFFFFFu / n + 1u : 0u;   // floor(x / n) = umulhi(x, m32), x < 2^16
   uint32_t out = pv_off[r], smp = ps_off[r];
-  const uint64_t m0 = mask[4 * (uint64_t)r], m1 = mask[4 * (uint64_t)r + 1], m2 = mask[4 * (uint64_t)r + 2],
-                 m3 = mask[4 * (uint64_t)r + 3];
-  auto kept = [&](uint32_t s) {
-    const uint64_t w = s < 64 ? m0 : (s < 128 ? m1 : (s < 192 ? m2 : m3));
-    return ((w >> (s % 64)) & 1ull) != 0;
-  };
+  const uint64_t w[4] = {mask[4 * (uint64_t)r], mask[4 * (uint64_t)r + 1], mask[4 * (uint64_t)r + 2],
+                         mask[4 * (uint64_t)r + 3]};
+  auto word = [&](uint32_t q) { return q == 0 ? w[0] : (q == 1 ? w[1] : (q == 2 ? w[2] : w[3])); };
   uint32_t s = 0;
   while (s < ns) {
-    if (!kept(s)) { ++s; continue; }
-    const uint32_t k = s / n, j0 = s - k * n;
-    uint32_t len = 1;
-    while (j0 + len < n && kept(s + len)) ++len;
+    // next kept slot at or after s
+    const uint64_t x = word(s >> 6) >> (s & 63u);
+    if (x == 0ull) {
+      s = (s | 63u) + 1u;
+      continue;
+    }
+    s += (uint32_t)__builtin_ctzll(x);
+    if (s >= ns) break;
+    const uint32_t k = n > 1u ? __umulhi(s, m32) : s;
+    const uint32_t j0 = s - k * n;
+    // consecutive kept slots from s, word by word, cut at the interval's end
+    uint32_t len = 0, pos = s;
+    while (pos < ns) {
+      const uint32_t b = pos & 63u;
+      const uint64_t y = ~(word(pos >> 6) >> b);
+      const uint32_t c = y ? (uint32_t)__builtin_ctzll(y) : 64u - b;
+      len += c;
+      pos += c;
+      if (c < 64u - b) break;
+    }
+    len = min(len, min(n - j0, ns - s));
     const uint32_t i = i0 + k;
     const float delta = iv.dt[i] / (float)n;
     if (j0 == 0 && len == n) {          // the whole interval: keep it exactly
