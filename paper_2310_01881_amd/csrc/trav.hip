@@ -40,13 +40,14 @@ __device__ __forceinline__ bool df_lt(DF a, DF b) { return a.hi < b.hi || (a.hi 
 
 constexpr int kStack = 17;       // AMNERF_MAX_DEPTH + 1
 constexpr int kBlock = 256;
+constexpr int kLdsNodes = 2048;  // node tables up to this size are staged in LDS per block
 
 __device__ __forceinline__ float axis_val(const float v[3], int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); }
 
 // Traverses one ray.  EMIT = false: returns the interval count, stopping once it exceeds
 // cap.  EMIT = true: writes the first `cap` intervals through the output pointers.
-template <bool EMIT>
-__device__ int traverse(const DevNode* __restrict__ nodes, const float o[3], const float dir[3],
+template <bool EMIT, typename NodePtr>
+__device__ int traverse(NodePtr nodes, const float o[3], const float dir[3],
                         int cap, uint32_t n_per, uint32_t ray, int* st_node, float* st_hi,
                         float* st_lo, float* iv_t0, float* iv_dt, uint32_t* iv_key,
                         uint32_t* iv_ray, uint32_t* iv_base, uint32_t smp_base) {
@@ -119,7 +120,18 @@ __device__ int traverse(const DevNode* __restrict__ nodes, const float o[3], con
   return m;
 }
 
-__global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict__ nodes,
+// The block's copy of the node table (LDS = true) or the table in memory.
+template <bool LDS>
+__device__ __forceinline__ const DevNode* stage_nodes(const DevNode* __restrict__ nodes, uint32_t n_nodes,
+                                                      DevNode* lds) {
+  if (!LDS) return nodes;
+  for (uint32_t i = threadIdx.x; i < n_nodes; i += kBlock) lds[i] = nodes[i];
+  __syncthreads();
+  return lds;
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict__ nodes, uint32_t n_nodes,
                                                        const float* __restrict__ o,
                                                        const float* __restrict__ d,
                                                        int64_t stride, int64_t r0, uint32_t nr,
@@ -128,6 +140,8 @@ __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict
   __shared__ int st_node[kStack * kBlock];
   __shared__ float st_hi[kStack * kBlock];
   __shared__ float st_lo[kStack * kBlock];
+  extern __shared__ DevNode s_nodes[];
+  const DevNode* tn = stage_nodes<LDS>(nodes, n_nodes, s_nodes);
   uint32_t r = blockIdx.x * kBlock + threadIdx.x;
   bool live = r < nr;
   float oo[3] = {0.f, 0.f, 0.f}, dd[3] = {0.f, 0.f, 1.f};
@@ -141,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict
   int m = 0;
   // skip the descent for a wave whose rays are all out of range
   if (__ballot(live) != 0 && live)
-    m = traverse<false>(nodes, oo, dd, s_max, 0, 0, st_node + threadIdx.x, st_hi + threadIdx.x,
+    m = traverse<false>(tn, oo, dd, s_max, 0, 0, st_node + threadIdx.x, st_hi + threadIdx.x,
                         st_lo + threadIdx.x, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
   if (live) {
     uint32_t meff = m <= s_max ? (uint32_t)m : (uint32_t)s_max;
@@ -151,7 +165,8 @@ __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict__ nodes,
+template <bool LDS>
+__global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict__ nodes, uint32_t n_nodes,
                                                       const float* __restrict__ o,
                                                       const float* __restrict__ d, int64_t stride,
                                                       int64_t r0, uint32_t nr,
@@ -167,6 +182,8 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
   __shared__ int st_node[kStack * kBlock];
   __shared__ float st_hi[kStack * kBlock];
   __shared__ float st_lo[kStack * kBlock];
+  extern __shared__ DevNode s_nodes[];
+  const DevNode* tn = stage_nodes<LDS>(nodes, n_nodes, s_nodes);
   uint32_t r = blockIdx.x * kBlock + threadIdx.x;
   uint32_t meff = r < nr ? cnt_iv[r] : 0u;
   if (__ballot(meff != 0) == 0 || meff == 0) return;
@@ -178,32 +195,40 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
   }
   uint32_t nper = cnt_smp[r] / meff;
   uint32_t base = iv_off[r];
-  traverse<true>(nodes, oo, dd, (int)meff, nper, r, st_node + threadIdx.x, st_hi + threadIdx.x,
+  traverse<true>(tn, oo, dd, (int)meff, nper, r, st_node + threadIdx.x, st_hi + threadIdx.x,
                  st_lo + threadIdx.x, iv_t0 + base, iv_dt + base, iv_key + base, iv_ray + base,
                  iv_base + base, smp_off[r]);
 }
 
 }  // namespace
 
-hipError_t launch_trav_count(const DevNode* nodes, const float* o, const float* d,
+hipError_t launch_trav_count(const DevNode* nodes, uint32_t n_nodes, const float* o, const float* d,
                              int64_t ray_stride, int64_t r0, uint32_t nr, int s_max,
                              uint32_t* cnt_iv, uint32_t* cnt_smp, hipStream_t st) {
   if (nr == 0) return hipSuccess;
   uint32_t grid = (nr + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_trav_count, dim3(grid), dim3(kBlock), 0, st, nodes, o, d, ray_stride, r0, nr,
-                     s_max, cnt_iv, cnt_smp);
+  if (n_nodes <= (uint32_t)kLdsNodes)
+    hipLaunchKernelGGL(k_trav_count<true>, dim3(grid), dim3(kBlock), sizeof(DevNode) * n_nodes, st, nodes, n_nodes, o,
+                       d, ray_stride, r0, nr, s_max, cnt_iv, cnt_smp);
+  else
+    hipLaunchKernelGGL(k_trav_count<false>, dim3(grid), dim3(kBlock), 0, st, nodes, n_nodes, o, d, ray_stride, r0,
+                       nr, s_max, cnt_iv, cnt_smp);
   return hipGetLastError();
 }
 
-hipError_t launch_trav_emit(const DevNode* nodes, const float* o, const float* d,
+hipError_t launch_trav_emit(const DevNode* nodes, uint32_t n_nodes, const float* o, const float* d,
                             int64_t ray_stride, int64_t r0, uint32_t nr, const uint32_t* cnt_iv,
                             const uint32_t* cnt_smp, const uint32_t* iv_off, const uint32_t* smp_off,
                             float* iv_t0, float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray,
                             uint32_t* iv_base, hipStream_t st) {
   if (nr == 0) return hipSuccess;
   uint32_t grid = (nr + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_trav_emit, dim3(grid), dim3(kBlock), 0, st, nodes, o, d, ray_stride, r0, nr,
-                     cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base);
+  if (n_nodes <= (uint32_t)kLdsNodes)
+    hipLaunchKernelGGL(k_trav_emit<true>, dim3(grid), dim3(kBlock), sizeof(DevNode) * n_nodes, st, nodes, n_nodes, o,
+                       d, ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base);
+  else
+    hipLaunchKernelGGL(k_trav_emit<false>, dim3(grid), dim3(kBlock), 0, st, nodes, n_nodes, o, d, ray_stride, r0,
+                       nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base);
   return hipGetLastError();
 }
 
