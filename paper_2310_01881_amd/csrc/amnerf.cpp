@@ -688,10 +688,10 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
     }
     auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev->ev[k], st) : hipSuccess; };
     HIP_TRY(mark(0));
-    HIP_TRY(launch_trav_count(tree->dev_nodes, (uint32_t)tree->mass.size(), rays->o_dev, rays->d_dev, R, r0, nr, p->s_max, w.cnt_iv, w.cnt_smp, st));
+    HIP_TRY(launch_trav_count(tree->dev_nodes, (uint32_t)tree->mass.size(), tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, p->s_max, w.cnt_iv, w.cnt_smp, st));
     HIP_TRY(launch_scan_u32(w.cnt_iv, w.iv_off, nr, nullptr, w.scan_tmp, st));
     HIP_TRY(launch_scan_u32(w.cnt_smp, w.smp_off, nr, nullptr, w.scan_tmp, st));
-    HIP_TRY(launch_trav_emit(tree->dev_nodes, (uint32_t)tree->mass.size(), rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
+    HIP_TRY(launch_trav_emit(tree->dev_nodes, (uint32_t)tree->mass.size(), tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
                              w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, st));
     HIP_TRY(mark(1));
     const IvSet plain = {w.iv_off, w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, w.iv_off + nr};

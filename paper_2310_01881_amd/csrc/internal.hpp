@@ -36,10 +36,10 @@ constexpr int kScanItems = 2048;        // elements per scan block (256 threads 
 // ---- traversal (Algorithm 1: Traverse) -------------------------------------------------
 // Pass 1: per ray, the number of leaf intervals that receive samples (min(m, s_max)) and
 // the number of samples.  Pass 2: the intervals themselves, ray-major, at iv_off.
-hipError_t launch_trav_count(const DevNode* nodes, uint32_t n_nodes, const float* o, const float* d,
+hipError_t launch_trav_count(const DevNode* nodes, uint32_t n_nodes, int depth, const float* o, const float* d,
                              int64_t ray_stride, int64_t r0, uint32_t nr, int s_max,
                              uint32_t* cnt_iv, uint32_t* cnt_smp, hipStream_t st);
-hipError_t launch_trav_emit(const DevNode* nodes, uint32_t n_nodes, const float* o, const float* d,
+hipError_t launch_trav_emit(const DevNode* nodes, uint32_t n_nodes, int depth, const float* o, const float* d,
                             int64_t ray_stride, int64_t r0, uint32_t nr,
                             const uint32_t* cnt_iv, const uint32_t* cnt_smp,
                             const uint32_t* iv_off, const uint32_t* smp_off, float* iv_t0,

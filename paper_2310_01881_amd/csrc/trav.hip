@@ -38,8 +38,10 @@ __device__ __forceinline__ DF plane_t(float s, float o, float d) {
 
 __device__ __forceinline__ bool df_lt(DF a, DF b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
 
-constexpr int kStack = 17;       // AMNERF_MAX_DEPTH + 1
 constexpr int kBlock = 256;
+// LDS per block: the node table (when staged), then the traversal stack of `stack_n` =
+// tree depth + 1 entries per thread as three arrays (node, exit hi, exit lo), strided by
+// kBlock so that a wave's accesses fall in distinct banks.
 constexpr int kLdsNodes = 2048;  // node tables up to this size are staged in LDS per block
 
 __device__ __forceinline__ float axis_val(const float v[3], int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); }
@@ -120,28 +122,46 @@ __device__ int traverse(NodePtr nodes, const float o[3], const float dir[3],
   return m;
 }
 
-// The block's copy of the node table (LDS = true) or the table in memory.
+// The block's copy of the node table (LDS = true) or the table in memory, and the stack.
+struct TravLds {
+  const DevNode* nodes;
+  int* st_node;
+  float *st_hi, *st_lo;
+};
+
 template <bool LDS>
-__device__ __forceinline__ const DevNode* stage_nodes(const DevNode* __restrict__ nodes, uint32_t n_nodes,
-                                                      DevNode* lds) {
-  if (!LDS) return nodes;
-  for (uint32_t i = threadIdx.x; i < n_nodes; i += kBlock) lds[i] = nodes[i];
-  __syncthreads();
-  return lds;
+__device__ __forceinline__ TravLds stage(const DevNode* __restrict__ nodes, uint32_t n_nodes, int stack_n,
+                                         uint8_t* dyn) {
+  TravLds t;
+  uint8_t* p = dyn;
+  if (LDS) {
+    DevNode* s = reinterpret_cast<DevNode*>(p);
+    for (uint32_t i = threadIdx.x; i < n_nodes; i += kBlock) s[i] = nodes[i];
+    p += sizeof(DevNode) * n_nodes;
+    t.nodes = s;
+  } else {
+    t.nodes = nodes;
+  }
+  t.st_node = reinterpret_cast<int*>(p) + threadIdx.x;
+  t.st_hi = reinterpret_cast<float*>(p + 4u * stack_n * kBlock) + threadIdx.x;
+  t.st_lo = reinterpret_cast<float*>(p + 8u * stack_n * kBlock) + threadIdx.x;
+  if (LDS) __syncthreads();
+  return t;
+}
+
+__host__ __device__ constexpr uint32_t trav_lds_bytes(bool lds, uint32_t n_nodes, int stack_n) {
+  return (lds ? (uint32_t)sizeof(DevNode) * n_nodes : 0u) + 12u * (uint32_t)stack_n * kBlock;
 }
 
 template <bool LDS>
 __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict__ nodes, uint32_t n_nodes,
-                                                       const float* __restrict__ o,
+                                                       int stack_n, const float* __restrict__ o,
                                                        const float* __restrict__ d,
                                                        int64_t stride, int64_t r0, uint32_t nr,
                                                        int s_max, uint32_t* __restrict__ cnt_iv,
                                                        uint32_t* __restrict__ cnt_smp) {
-  __shared__ int st_node[kStack * kBlock];
-  __shared__ float st_hi[kStack * kBlock];
-  __shared__ float st_lo[kStack * kBlock];
-  extern __shared__ DevNode s_nodes[];
-  const DevNode* tn = stage_nodes<LDS>(nodes, n_nodes, s_nodes);
+  extern __shared__ __align__(16) uint8_t dyn[];
+  const TravLds tl = stage<LDS>(nodes, n_nodes, stack_n, dyn);
   uint32_t r = blockIdx.x * kBlock + threadIdx.x;
   bool live = r < nr;
   float oo[3] = {0.f, 0.f, 0.f}, dd[3] = {0.f, 0.f, 1.f};
@@ -155,8 +175,8 @@ __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict
   int m = 0;
   // skip the descent for a wave whose rays are all out of range
   if (__ballot(live) != 0 && live)
-    m = traverse<false>(tn, oo, dd, s_max, 0, 0, st_node + threadIdx.x, st_hi + threadIdx.x,
-                        st_lo + threadIdx.x, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+    m = traverse<false>(tl.nodes, oo, dd, s_max, 0, 0, tl.st_node, tl.st_hi, tl.st_lo, nullptr, nullptr, nullptr,
+                        nullptr, nullptr, 0);
   if (live) {
     uint32_t meff = m <= s_max ? (uint32_t)m : (uint32_t)s_max;
     uint32_t nper = m == 0 ? 0u : (m <= s_max ? (uint32_t)(s_max / m) : 1u);
@@ -167,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict
 
 template <bool LDS>
 __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict__ nodes, uint32_t n_nodes,
-                                                      const float* __restrict__ o,
+                                                      int stack_n, const float* __restrict__ o,
                                                       const float* __restrict__ d, int64_t stride,
                                                       int64_t r0, uint32_t nr,
                                                       const uint32_t* __restrict__ cnt_iv,
@@ -179,11 +199,8 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
                                                       uint32_t* __restrict__ iv_key,
                                                       uint32_t* __restrict__ iv_ray,
                                                       uint32_t* __restrict__ iv_base) {
-  __shared__ int st_node[kStack * kBlock];
-  __shared__ float st_hi[kStack * kBlock];
-  __shared__ float st_lo[kStack * kBlock];
-  extern __shared__ DevNode s_nodes[];
-  const DevNode* tn = stage_nodes<LDS>(nodes, n_nodes, s_nodes);
+  extern __shared__ __align__(16) uint8_t dyn[];
+  const TravLds tl = stage<LDS>(nodes, n_nodes, stack_n, dyn);
   uint32_t r = blockIdx.x * kBlock + threadIdx.x;
   uint32_t meff = r < nr ? cnt_iv[r] : 0u;
   if (__ballot(meff != 0) == 0 || meff == 0) return;
@@ -195,40 +212,62 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
   }
   uint32_t nper = cnt_smp[r] / meff;
   uint32_t base = iv_off[r];
-  traverse<true>(tn, oo, dd, (int)meff, nper, r, st_node + threadIdx.x, st_hi + threadIdx.x,
-                 st_lo + threadIdx.x, iv_t0 + base, iv_dt + base, iv_key + base, iv_ray + base,
-                 iv_base + base, smp_off[r]);
+  traverse<true>(tl.nodes, oo, dd, (int)meff, nper, r, tl.st_node, tl.st_hi, tl.st_lo, iv_t0 + base, iv_dt + base,
+                 iv_key + base, iv_ray + base, iv_base + base, smp_off[r]);
 }
 
 }  // namespace
 
-hipError_t launch_trav_count(const DevNode* nodes, uint32_t n_nodes, const float* o, const float* d,
+static hipError_t allow_lds(const void* kern) {
+  return hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+}
+
+static hipError_t trav_setup() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipError_t e = allow_lds((const void*)k_trav_count<true>);
+  if (e == hipSuccess) e = allow_lds((const void*)k_trav_count<false>);
+  if (e == hipSuccess) e = allow_lds((const void*)k_trav_emit<true>);
+  if (e == hipSuccess) e = allow_lds((const void*)k_trav_emit<false>);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+hipError_t launch_trav_count(const DevNode* nodes, uint32_t n_nodes, int depth, const float* o, const float* d,
                              int64_t ray_stride, int64_t r0, uint32_t nr, int s_max,
                              uint32_t* cnt_iv, uint32_t* cnt_smp, hipStream_t st) {
   if (nr == 0) return hipSuccess;
-  uint32_t grid = (nr + kBlock - 1) / kBlock;
+  hipError_t e = trav_setup();
+  if (e != hipSuccess) return e;
+  const int stack_n = depth + 1;
+  const uint32_t grid = (nr + kBlock - 1) / kBlock;
   if (n_nodes <= (uint32_t)kLdsNodes)
-    hipLaunchKernelGGL(k_trav_count<true>, dim3(grid), dim3(kBlock), sizeof(DevNode) * n_nodes, st, nodes, n_nodes, o,
-                       d, ray_stride, r0, nr, s_max, cnt_iv, cnt_smp);
+    hipLaunchKernelGGL(k_trav_count<true>, dim3(grid), dim3(kBlock), trav_lds_bytes(true, n_nodes, stack_n), st, nodes,
+                       n_nodes, stack_n, o, d, ray_stride, r0, nr, s_max, cnt_iv, cnt_smp);
   else
-    hipLaunchKernelGGL(k_trav_count<false>, dim3(grid), dim3(kBlock), 0, st, nodes, n_nodes, o, d, ray_stride, r0,
-                       nr, s_max, cnt_iv, cnt_smp);
+    hipLaunchKernelGGL(k_trav_count<false>, dim3(grid), dim3(kBlock), trav_lds_bytes(false, n_nodes, stack_n), st,
+                       nodes, n_nodes, stack_n, o, d, ray_stride, r0, nr, s_max, cnt_iv, cnt_smp);
   return hipGetLastError();
 }
 
-hipError_t launch_trav_emit(const DevNode* nodes, uint32_t n_nodes, const float* o, const float* d,
+hipError_t launch_trav_emit(const DevNode* nodes, uint32_t n_nodes, int depth, const float* o, const float* d,
                             int64_t ray_stride, int64_t r0, uint32_t nr, const uint32_t* cnt_iv,
                             const uint32_t* cnt_smp, const uint32_t* iv_off, const uint32_t* smp_off,
                             float* iv_t0, float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray,
                             uint32_t* iv_base, hipStream_t st) {
   if (nr == 0) return hipSuccess;
-  uint32_t grid = (nr + kBlock - 1) / kBlock;
+  hipError_t e = trav_setup();
+  if (e != hipSuccess) return e;
+  const int stack_n = depth + 1;
+  const uint32_t grid = (nr + kBlock - 1) / kBlock;
   if (n_nodes <= (uint32_t)kLdsNodes)
-    hipLaunchKernelGGL(k_trav_emit<true>, dim3(grid), dim3(kBlock), sizeof(DevNode) * n_nodes, st, nodes, n_nodes, o,
-                       d, ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base);
+    hipLaunchKernelGGL(k_trav_emit<true>, dim3(grid), dim3(kBlock), trav_lds_bytes(true, n_nodes, stack_n), st, nodes,
+                       n_nodes, stack_n, o, d, ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt,
+                       iv_key, iv_ray, iv_base);
   else
-    hipLaunchKernelGGL(k_trav_emit<false>, dim3(grid), dim3(kBlock), 0, st, nodes, n_nodes, o, d, ray_stride, r0,
-                       nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base);
+    hipLaunchKernelGGL(k_trav_emit<false>, dim3(grid), dim3(kBlock), trav_lds_bytes(false, n_nodes, stack_n), st,
+                       nodes, n_nodes, stack_n, o, d, ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0,
+                       iv_dt, iv_key, iv_ray, iv_base);
   return hipGetLastError();
 }
 
