@@ -724,10 +724,10 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
       mat = pw.mat; mat_scan = pw.mat_scan; sidx = pw.sidx; sn = pw.sn; ssb = pw.ssb; scan_tmp = pw.scan_tmp;
       niv_use_max = niv_plan;
     }
-    HIP_TRY(launch_chunk_begin(ctx->counts, use.n_iv_dev, st));
+    HIP_TRY(launch_chunk_begin(ctx->counts, use.n_iv_dev, spu.seg, L, st));
     HIP_TRY(mark(2));
     HIP_TRY(launch_sort_hist(spu, use.key, use.n_iv_dev, mat, st));
-    HIP_TRY(launch_scan_u32(mat, mat_scan, (uint64_t)L * spu.nseg_max, nullptr, scan_tmp, st));
+    HIP_TRY(launch_scan_u32(mat, mat_scan, (uint64_t)L * spu.nseg_max, &ctx->counts->mat_n, scan_tmp, st));
     HIP_TRY(launch_sort_scatter(spu, use.key, use.n_iv_dev, mat_scan, sidx, sn, st));
     HIP_TRY(launch_scan_u32(sn, ssb, niv_use_max, use.n_iv_dev, scan_tmp, st));
     HIP_TRY(launch_bucket_tiles(spu, mat_scan, ssb, w.bucket_off, w.tile_off, ctx->counts, st));

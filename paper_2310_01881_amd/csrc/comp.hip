@@ -175,9 +175,11 @@ __global__ void k_chunk_finish(ChunkCounts* counts, const uint32_t* smp_total, c
   counts->plain_smp += *plain_total;
 }
 
-__global__ void k_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total) {
+__global__ void k_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total, uint32_t seg, uint32_t n_leaves) {
   if (threadIdx.x != 0) return;
-  counts->n_iv = *iv_total;
+  const uint32_t n = *iv_total;
+  counts->n_iv = n;
+  counts->mat_n = n_leaves * ((n + seg - 1) / seg);
 }
 
 __global__ void k_counts_reset(ChunkCounts* counts) {
@@ -212,8 +214,9 @@ hipError_t launch_counts_reset(ChunkCounts* counts, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total, hipStream_t st) {
-  hipLaunchKernelGGL(k_chunk_begin, dim3(1), dim3(64), 0, st, counts, iv_total);
+hipError_t launch_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total, uint32_t seg, uint32_t n_leaves,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_chunk_begin, dim3(1), dim3(64), 0, st, counts, iv_total, seg, n_leaves);
   return hipGetLastError();
 }
 

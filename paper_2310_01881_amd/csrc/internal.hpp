@@ -21,7 +21,7 @@ struct ChunkCounts {
   uint32_t n_iv;        // intervals that carry samples (this chunk)
   uint32_t n_smp;       // samples (this chunk)
   uint32_t n_tiles;     // MLP work tiles (this chunk)
-  uint32_t pad;
+  uint32_t mat_n;       // entries of the sort's slot x segment count matrix (this chunk)
   uint64_t smp_global;  // ray-major sample index of this chunk's first sample
   uint64_t iv_global;   // intervals of the chunks before this one
   uint64_t nonfinite;   // rays with a non-finite output (accumulated over chunks)
@@ -82,7 +82,8 @@ hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n_cap,
 // ---- sort by leaf slot (Section 3.5: sort, then infer per node) ------------------------
 struct SortPlan {
   uint32_t seg;         // intervals per segment (multiple of 64)
-  uint32_t nseg_max;    // segments for the worst-case interval count
+  uint32_t nseg_max;    // segments for the worst-case interval count (the kernels use the
+                        // actual count, ceil(n_iv / seg), as the matrix's row length)
   uint32_t key_bits;    // bits of the leaf slot
   uint32_t n_leaves;
 };
@@ -172,7 +173,8 @@ hipError_t launch_prop_train(const void* packed, const IvSet& iv, const float* o
 
 // ---- small helpers ----------------------------------------------------------------------
 hipError_t launch_counts_reset(ChunkCounts* counts, hipStream_t st);
-hipError_t launch_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total, hipStream_t st);
+hipError_t launch_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total, uint32_t seg, uint32_t n_leaves,
+                              hipStream_t st);
 hipError_t launch_chunk_finish(ChunkCounts* counts, const uint32_t* smp_off_total,
                                const uint32_t* iv_off_total, const uint32_t* plain_smp_total,
                                hipStream_t st);

@@ -6,7 +6,9 @@
 // its samples in place.  The sort therefore runs on intervals (about S_max / n fewer keys
 // than samples):
 //   hist    one wave per segment of `seg` consecutive intervals: LDS histogram of slots,
-//           written column-wise into a [slot][segment] count matrix;
+//           written column-wise into a [slot][segment] count matrix (row length = the
+//           chunk's actual segment count, so the matrix and its scan scale with the
+//           intervals present, and there is a segment per wave across the machine);
 //   scan    exclusive scan of that matrix in slot-major order = the first sorted position
 //           of (slot, segment);
 //   scatter one wave per segment again, 64 intervals at a time: lanes holding the same
@@ -34,7 +36,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t* __restri
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* hist = sh + wave * n_leaves;
   const uint32_t n_iv = *n_iv_dev;
-  for (uint32_t s = blockIdx.x * kWaves + wave; s < nseg_max; s += gridDim.x * kWaves) {
+  const uint32_t nseg = (n_iv + seg - 1) / seg;
+  for (uint32_t s = blockIdx.x * kWaves + wave; s < nseg; s += gridDim.x * kWaves) {
     for (uint32_t b = lane; b < n_leaves; b += 64) hist[b] = 0u;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -43,7 +46,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t* __restri
     for (uint64_t i = begin + lane; i < end; i += 64) atomicAdd(&hist[key_slot(iv_key[i])], 1u);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t b = lane; b < n_leaves; b += 64) mat[(uint64_t)b * nseg_max + s] = hist[b];
+    for (uint32_t b = lane; b < n_leaves; b += 64) mat[(uint64_t)b * nseg + s] = hist[b];
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
@@ -62,7 +65,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint32_t* __res
   const uint32_t n_iv = *n_iv_dev;
   const uint32_t nseg = (n_iv + seg - 1) / seg;
   for (uint32_t s = blockIdx.x * kWaves + wave; s < nseg; s += gridDim.x * kWaves) {
-    for (uint32_t b = lane; b < n_leaves; b += 64) base[b] = mat_scan[(uint64_t)b * nseg_max + s];
+    for (uint32_t b = lane; b < n_leaves; b += 64) base[b] = mat_scan[(uint64_t)b * nseg + s];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     uint64_t begin = (uint64_t)s * seg;
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint32_t* __res
 
 // One block: leaf bucket offsets in sorted samples and MLP tile offsets.
 __global__ __launch_bounds__(1024) void k_bucket_tiles(const uint32_t* __restrict__ mat_scan,
-                                                       uint32_t nseg_max, uint32_t n_leaves,
+                                                       uint32_t seg, uint32_t n_leaves,
                                                        const uint32_t* __restrict__ ssb,
                                                        uint32_t* __restrict__ bucket_off,
                                                        uint32_t* __restrict__ tile_off,
@@ -106,14 +109,15 @@ __global__ __launch_bounds__(1024) void k_bucket_tiles(const uint32_t* __restric
   __shared__ uint32_t sh[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t n_iv = counts->n_iv;
+  const uint32_t nseg = (n_iv + seg - 1) / seg;
   const uint32_t n_smp = ssb[n_iv];
   uint32_t carry = 0;
   for (uint32_t c = 0; c < n_leaves; c += 1024) {
     uint32_t b = c + threadIdx.x;
     uint32_t lo = 0, hi = 0;
     if (b < n_leaves) {
-      lo = ssb[mat_scan[(uint64_t)b * nseg_max]];
-      hi = b + 1 < n_leaves ? ssb[mat_scan[(uint64_t)(b + 1) * nseg_max]] : n_smp;
+      lo = ssb[mat_scan[(uint64_t)b * nseg]];
+      hi = b + 1 < n_leaves ? ssb[mat_scan[(uint64_t)(b + 1) * nseg]] : n_smp;
       bucket_off[b] = lo;
     }
     uint32_t nt = (hi - lo + kMlpTileRows - 1) / kMlpTileRows;
@@ -198,10 +202,10 @@ SortPlan make_sort_plan(uint64_t n_iv_max, uint32_t n_leaves) {
   uint32_t bits = 0;
   while ((1u << bits) < n_leaves) ++bits;
   p.key_bits = bits;
-  uint64_t seg = 16ull * n_leaves;
-  if (seg < 4096) seg = 4096;
-  // keep the count matrix (n_leaves x segments) no larger than about 4M words
-  while ((uint64_t)n_leaves * ((n_iv_max + seg - 1) / seg) > (4ull << 20)) seg *= 2;
+  // a segment per wave; at least as many intervals per segment as slots, so the count
+  // matrix (n_leaves x segments) has no more entries than there are intervals
+  uint64_t seg = ((uint64_t)n_leaves + 63) / 64 * 64;
+  if (seg < 512) seg = 512;
   p.seg = (uint32_t)seg;
   p.nseg_max = (uint32_t)((n_iv_max + seg - 1) / seg);
   if (p.nseg_max == 0) p.nseg_max = 1;
@@ -232,7 +236,7 @@ hipError_t launch_sort_scatter(const SortPlan& p, const uint32_t* iv_key, const 
 hipError_t launch_bucket_tiles(const SortPlan& p, const uint32_t* mat_scan, const uint32_t* ssb,
                                uint32_t* bucket_off, uint32_t* tile_off, ChunkCounts* counts,
                                hipStream_t st) {
-  hipLaunchKernelGGL(k_bucket_tiles, dim3(1), dim3(1024), 0, st, mat_scan, p.nseg_max, p.n_leaves,
+  hipLaunchKernelGGL(k_bucket_tiles, dim3(1), dim3(1024), 0, st, mat_scan, p.seg, p.n_leaves,
                      ssb, bucket_off, tile_off, counts);
   return hipGetLastError();
 }
