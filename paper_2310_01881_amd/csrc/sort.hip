@@ -147,9 +147,28 @@ __global__ __launch_bounds__(1024) void k_bucket_tiles(const uint32_t* __restric
   }
 }
 
-// One block per 256 consecutive sorted intervals: their records go to LDS, then the block
-// writes all of their samples with consecutive threads on consecutive sorted positions
-// (each thread finds its interval by binary search over the staged sample bases).
+// Prefix maximum over the 64 lanes of a wave (signed), on the same lane-shift pattern as
+// wave_scan_incl; lanes outside the pattern contribute INT32_MIN.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_or_min(int v) {
+  return __builtin_amdgcn_update_dpp((int)0x80000000, v, CTRL, ROW_MASK, 0xF, false);
+}
+__device__ __forceinline__ int wave_max_incl(int v) {
+  v = max(v, dpp_or_min<0x111, 0xF>(v));
+  v = max(v, dpp_or_min<0x112, 0xF>(v));
+  v = max(v, dpp_or_min<0x114, 0xF>(v));
+  v = max(v, dpp_or_min<0x118, 0xF>(v));
+  v = max(v, dpp_or_min<0x142, 0xA>(v));
+  v = max(v, dpp_or_min<0x143, 0xC>(v));
+  return v;
+}
+
+// One block per 256 consecutive sorted intervals: their records go to LDS, then each wave
+// writes windows of 64 consecutive sorted samples (coalesced).  A sample's interval is
+// found without a search: the intervals starting inside the window mark their first
+// lane in a per-wave LDS row, and a prefix maximum over the row (seeded with the last
+// interval of the previous window) gives every lane the latest interval started at or
+// before it.
 __global__ __launch_bounds__(kThreads) void k_expand(
     const uint32_t* __restrict__ sidx, const uint32_t* __restrict__ ssb, IvSet iv, int64_t r0,
     int jitter, uint64_t seed, uint32_t* __restrict__ srec_ray, float* __restrict__ srec_t,
@@ -157,6 +176,8 @@ __global__ __launch_bounds__(kThreads) void k_expand(
   __shared__ uint32_t sh_base[kThreads + 1];
   __shared__ uint32_t sh_ray[kThreads], sh_rm[kThreads];
   __shared__ float sh_t0[kThreads], sh_delta[kThreads], sh_u[kThreads];
+  __shared__ int sh_mark[kWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t n_iv = *iv.n_iv_dev;
   const uint32_t n_groups = (n_iv + kThreads - 1) / kThreads;
   for (uint32_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
@@ -178,17 +199,40 @@ __global__ __launch_bounds__(kThreads) void k_expand(
     if (threadIdx.x == 0) sh_base[cnt] = ssb[p0 + cnt];
     __syncthreads();
     const uint32_t q0 = sh_base[0], q1 = sh_base[cnt];
-    for (uint32_t q = q0 + threadIdx.x; q < q1; q += kThreads) {
-      // largest a with sh_base[a] <= q
-      uint32_t lo = 0, hi = cnt;
-      while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (sh_base[mid] <= q) lo = mid; else hi = mid;
+    // this lane's view of the staged intervals' first samples (intervals lane + 64 c)
+    uint32_t st[kWaves];
+#pragma unroll
+    for (int c = 0; c < kWaves; ++c) {
+      const uint32_t a = (uint32_t)lane + 64u * c;
+      st[c] = a < cnt ? sh_base[a] : 0xFFFFFFFFu;
+    }
+    // windows of 64 samples: wave w takes windows w, w + 4, ...; the interval covering a
+    // window's first sample is the last one starting at or before it
+    for (uint32_t qw = q0 + 64u * wave; qw < q1; qw += 64u * kWaves) {
+      sh_mark[wave][lane] = -1;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      int before = 0;   // intervals starting at or before qw (at least interval 0 does)
+#pragma unroll
+      for (int c = 0; c < kWaves; ++c) {
+        const uint32_t a = (uint32_t)lane + 64u * c;
+        if (st[c] != 0xFFFFFFFFu && st[c] >= qw && st[c] < qw + 64u) sh_mark[wave][st[c] - qw] = (int)a;
+        if (st[c] <= qw) before = max(before, (int)a);
       }
-      const uint32_t j = q - sh_base[lo];
-      srec_ray[q] = sh_ray[lo];
-      srec_t[q] = sample_t(sh_t0[lo], sh_delta[lo], j, sh_u[lo]);
-      perm[q] = sh_rm[lo] + j;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const int first = wave_max_incl(before);                       // lane 63 holds the maximum
+      const int seed_iv = __builtin_amdgcn_readlane(first, 63);
+      const int lo = max(wave_max_incl(sh_mark[wave][lane]), seed_iv);
+      const uint32_t q = qw + (uint32_t)lane;
+      if (q < q1) {
+        const uint32_t j = q - sh_base[lo];
+        srec_ray[q] = sh_ray[lo];
+        srec_t[q] = sample_t(sh_t0[lo], sh_delta[lo], j, sh_u[lo]);
+        perm[q] = sh_rm[lo] + j;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
   }
