@@ -5,9 +5,9 @@ One step renders one 800x800 frame (640 000 rays) of the seeded 128^3-grid scene
 512-leaf KD tree and 4x64 per-leaf MLPs, at most 128 samples per ray, through the whole
 path: traversal -> (learned proposal) -> per-leaf samples -> sort by leaf -> grouped MLP
 -> compositing.  Rays of 8 held-out cameras are resident in HBM before the timed region;
-step k renders camera k mod 8.  Three paths are timed: plain float32, plain bfloat16, and
+step k renders camera k mod 8.  Five paths are timed: plain float32, plain bfloat16,
 bfloat16 with the learned proposal (bfloat16 inference, <= 48 samples per ray, fallback
-below 0.99 predicted mass).  The proposal is first trained (untimed) by the library's own
+below 0.99 predicted mass), and float8 (e4m3) leaf weights without and with the proposal.  The proposal is first trained (untimed) by the library's own
 kernels on plain-render targets from 200 seeded training cameras.  `value` is the
 proposal path's samples/s (samples evaluated by the leaf MLPs) and `ms_per_step` its
 ms/frame.  The oracle (float64, CPU) renders a bounded random subset of camera 0's rays:
@@ -51,7 +51,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-steps", type=int, default=20, help="timed training steps (0: skip)")
-    ap.add_argument("--paths", default="f32,bf16,bf16_prop",
+    ap.add_argument("--paths", default="f32,bf16,bf16_prop,fp8,fp8_prop",
                     help="comma-separated render paths to time (the headline bf16_prop is always timed)")
     ap.add_argument("--train-batch", type=int, default=262144)
     args = ap.parse_args()
@@ -77,7 +77,8 @@ def main():
     W = synth.make_weights(L, cfg.n_hidden, cfg.hidden, cfg.seed_weights, dens)
     master = torch.from_numpy(W).to(dev)
     mlps = {"f32": am.Mlp(ctx, master, cfg.n_hidden, cfg.hidden, am.AMNERF_F32, L),
-            "bf16": am.Mlp(ctx, master, cfg.n_hidden, cfg.hidden, am.AMNERF_BF16, L)}
+            "bf16": am.Mlp(ctx, master, cfg.n_hidden, cfg.hidden, am.AMNERF_BF16, L),
+            "fp8": am.Mlp(ctx, master, cfg.n_hidden, cfg.hidden, am.AMNERF_FP8, L)}
     n_cams = 8
     cams = synth.make_cameras(n_cams, cfg.seed_cameras, cfg.width, cfg.height)
     rays = []
@@ -108,7 +109,8 @@ def main():
                                                              ["%.2e" % v for v in losses]))
     desc = prop.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
 
-    all_paths = {"f32": ("f32", None), "bf16": ("bf16", None), "bf16_prop": ("bf16", desc)}
+    all_paths = {"f32": ("f32", None), "bf16": ("bf16", None), "bf16_prop": ("bf16", desc),
+                 "fp8": ("fp8", None), "fp8_prop": ("fp8", desc)}
     wanted = set(args.paths.split(",")) | {"bf16_prop"}
     paths = {k: v for k, v in all_paths.items() if k in wanted}
     outs = {k: {"rgb": torch.empty((R, 3), device=dev), "depth": torch.empty(R, device=dev),

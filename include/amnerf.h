@@ -48,6 +48,11 @@ extern "C" {
 /* ---- arithmetic types of the per-leaf MLP -------------------------------------------- */
 #define AMNERF_F32 0          /* float32 weights and activations, float32 accumulate */
 #define AMNERF_BF16 1         /* bfloat16 weights and activations, float32 accumulate */
+#define AMNERF_FP8 2          /* float8 e4m3 weights (OCP encoding: bias 7, 3 mantissa bits, max 448,
+                                 no infinities) with a float32 scale per leaf and layer
+                                 (max |W| / 448), widened to bfloat16 when a leaf's block is
+                                 staged on chip; bfloat16 activations, float32 accumulate.
+                                 Render only (no backward). */
 
 /* ---- limits -------------------------------------------------------------------------- */
 #define AMNERF_MAX_GRID 512   /* guidance grid side */
@@ -141,14 +146,24 @@ int amnerf_mlp_packed_bytes(const amnerf_mlp_shape* shape, int32_t dtype, int32_
 
 /* Converts device master parameters float32[n_leaves][P] into the kernel-ready block
  * (matrix-core fragment order, weights in `dtype` rounded to nearest even, biases float32;
- * for AMNERF_BF16 it also holds the transposed weights the backward pass uses) in the
- * caller's device buffer `packed_dev` of amnerf_mlp_packed_bytes bytes. */
+ * for AMNERF_BF16 it also holds the transposed weights the backward pass uses; for
+ * AMNERF_FP8 each leaf and layer gets the scale max |W| / 448 (1 for an all-zero layer)
+ * and the weights W / scale are rounded to the nearest e4m3 value, saturating at 448) in the
+ * caller's device buffer `packed_dev` of amnerf_mlp_packed_bytes bytes.
+ * An AMNERF_FP8 block is n_leaves equal leaf blocks, each: the float32 biases (the hidden
+ * layers' n_hidden * hidden, then the output layer's 4, zero-padded to n_hidden * hidden + 16
+ * floats and then to a multiple of 16 bytes), 16 float32 scale slots (slot l = layer l, the
+ * rest unused), then the e4m3 codes of the weights, layer after layer, each layer's codes in
+ * fragment order, in which every weight appears once and zero codes fill the padding (layer
+ * 0's 30 inputs are padded to 32 and the output layer's 4 rows to 16, so the layers hold
+ * 32 * hidden, hidden * hidden and 16 * hidden codes).  The pack launches on `stream`; errors come back as
+ * AMNERF_EINVAL (bad shape, dtype, count or NULL pointer) or AMNERF_EDEVICE. */
 int amnerf_mlp_pack(amnerf_ctx* ctx, const amnerf_mlp_shape* shape, int32_t dtype,
                     int32_t n_leaves, const float* master_dev, void* packed_dev, void* stream);
 
 typedef struct {
   amnerf_mlp_shape shape;
-  int32_t dtype;          /* AMNERF_F32 or AMNERF_BF16 */
+  int32_t dtype;          /* AMNERF_F32, AMNERF_BF16 or AMNERF_FP8 */
   int32_t n_leaves;       /* must equal the tree's leaf count */
   const void* packed_dev; /* device block written by amnerf_mlp_pack with the same
                              shape, dtype and n_leaves */

@@ -5,6 +5,9 @@ this package.  The product (``paper_2310_01881_amd``) never imports it and share
 code with it.  ``orc.c`` holds the arithmetic (plain loops in double precision); this
 module only loads the shared object and marshals numpy arrays.
 
+``fp8.py`` (numpy) states the float8 e4m3 weight storage of the quantised leaf MLPs;
+the float8 checks render with its dequantised weights.
+
 Two steps use library routines as permitted building blocks:
 ``buckets`` (the stable sort of sample indices by leaf slot is ``numpy.argsort`` with
 ``kind="stable"``) and ``psnr``.

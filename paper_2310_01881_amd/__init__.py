@@ -25,6 +25,7 @@ AMNERF_ECAPACITY = -4
 AMNERF_ESTATE = -5
 AMNERF_F32 = 0
 AMNERF_BF16 = 1
+AMNERF_FP8 = 2
 AMNERF_JITTER = 1
 AMNERF_MAX_GRID = 512
 AMNERF_MAX_DEPTH = 16

@@ -16,6 +16,8 @@
 // Biases enter as the C operand of the first MFMA of each output block.
 //   F32  : v_mfma_f32_16x16x4_f32  (fp32 in, fp32 accumulate)
 //   BF16 : v_mfma_f32_16x16x32_bf16 (bf16 in, fp32 accumulate)
+//   FP8  : the BF16 kernel; the leaf's e4m3 weights are widened to bf16 (times the layer's
+//          scale) while they are staged into LDS, so the block in memory is half the size.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -30,7 +32,52 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// One thread per (leaf, unit, lane): 16 bytes of A fragment.  Plus the bias block.
+// float8 e4m3 in the OCP encoding (sign, 4 exponent bits with bias 7, 3 mantissa bits; no
+// infinities, 0x7F is NaN, largest finite 448): round to nearest, ties to even, saturating.
+__device__ __forceinline__ uint32_t e4m3_encode(float x) {
+  const uint32_t sign = x < 0.f ? 0x80u : 0u;
+  const float a = fabsf(x);
+  if (!(a < 464.f)) return sign | 0x7Eu;            // at or beyond the midpoint above 448
+  if (a < 0.015625f) return sign | (uint32_t)rintf(a * 512.f);   // subnormals, step 2^-9 (8 = 2^-6)
+  int e2;
+  frexpf(a, &e2);                                    // a in [2^(e2-1), 2^e2)
+  int E = e2 - 1;
+  uint32_t m = (uint32_t)rintf((ldexpf(a, -E) - 1.f) * 8.f);
+  if (m == 8u) { m = 0u; ++E; }
+  if (E > 8 || (E == 8 && m > 6u)) return sign | 0x7Eu;
+  return sign | ((uint32_t)(E + 7) << 3) | m;
+}
+
+__device__ __forceinline__ float e4m3_decode(uint32_t b) {
+  const uint32_t e = (b >> 3) & 15u, m = b & 7u;
+  const float v = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
+  return (b & 0x80u) ? -v : v;
+}
+
+// float8 scales: one block per (leaf, layer), max |W| / 448 (1 for an all-zero layer).
+__global__ __launch_bounds__(kThreads) void k_fp8_scales(Layout L, int P, const float* __restrict__ master,
+                                                          uint8_t* __restrict__ packed) {
+  __shared__ float red[kThreads];
+  const int leaf = blockIdx.x / (L.nh + 1), layer = blockIdx.x % (L.nh + 1);
+  int din, dout, off_w, off_b;
+  master_offsets(L.nh, L.H, layer, din, dout, off_w, off_b);
+  const float* W = master + (uint64_t)leaf * P + off_w;
+  float mx = 0.f;
+  for (int i = threadIdx.x; i < din * dout; i += kThreads) mx = fmaxf(mx, fabsf(W[i]));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    float* sc = reinterpret_cast<float*>(packed + (uint64_t)leaf * L.bytes8 + L.bias_bytes);
+    sc[layer] = red[0] > 0.f ? red[0] / 448.f : 1.f;
+  }
+}
+
+// One thread per (leaf, unit, lane): 16 bytes of A fragment (8 for float8).  Plus the bias
+// block.
 __global__ void k_mlp_pack(Layout L, int n_leaves, int P, const float* __restrict__ master,
                            uint8_t* __restrict__ packed) {
   const uint64_t per_leaf = (uint64_t)L.units * 64;
@@ -52,15 +99,24 @@ __global__ void k_mlp_pack(Layout L, int n_leaves, int P, const float* __restric
     const float* W = master + (uint64_t)leaf * P + off_w;
     int row = 16 * rb + m;
     uint8_t* dst = packed + (uint64_t)leaf * L.bytes + L.bias_bytes + (uint64_t)unit * kUnitBytes + lane * 16;
-    int ne = L.dtype == AMNERF_BF16 ? 8 : 4;
+    const bool b16 = L.dtype == AMNERF_BF16 || L.dtype == AMNERF_FP8;
+    int ne = b16 ? 8 : 4;
     float v[8];
     for (int e = 0; e < ne; ++e) {
       int col;
-      if (L.dtype == AMNERF_BF16) col = layer == 0 ? first_layer_col_bf16(g, e) : 16 * (2 * ku + e / 4) + 4 * g + (e % 4);
+      if (b16) col = layer == 0 ? first_layer_col_bf16(g, e) : 16 * (2 * ku + e / 4) + 4 * g + (e % 4);
       else { int kb = 4 * ku + e; col = layer == 0 ? first_layer_col(g, kb) : 16 * ku + 4 * g + e; }
       v[e] = (row < dout && col >= 0) ? W[row * din + col] : 0.f;
     }
-    if (L.dtype == AMNERF_BF16) {
+    if (L.dtype == AMNERF_FP8) {
+      uint8_t* blk = packed + (uint64_t)leaf * L.bytes8;
+      const float sc = reinterpret_cast<const float*>(blk + L.bias_bytes)[layer];
+      uint32_t lo = 0, hi = 0;
+      for (int e = 0; e < 4; ++e) lo |= e4m3_encode(v[e] / sc) << (8 * e);
+      for (int e = 0; e < 4; ++e) hi |= e4m3_encode(v[4 + e] / sc) << (8 * e);
+      *reinterpret_cast<uint2*>(blk + L.bias_bytes + kFp8ScaleBytes + (uint64_t)unit * kUnit8Bytes + lane * 8) =
+          make_uint2(lo, hi);
+    } else if (L.dtype == AMNERF_BF16) {
       bf16x8 h;
       for (int e = 0; e < 8; ++e) h[e] = (__bf16)v[e];
       *(bf16x8*)dst = h;
@@ -83,7 +139,7 @@ __global__ void k_mlp_pack(Layout L, int n_leaves, int P, const float* __restric
       master_offsets(L.nh, L.H, L.nh, din, dout, off_w, off_b);
       val = master[(uint64_t)leaf * P + off_b + (j - L.nh * L.H)];
     }
-    ((float*)(packed + (uint64_t)leaf * L.bytes))[j] = val;
+    ((float*)(packed + (uint64_t)leaf * (L.dtype == AMNERF_FP8 ? L.bytes8 : L.bytes)))[j] = val;
   }
   // transposed weights for the backward pass: unit (layer l >= 1, rb, ku), lane (g, m)
   // holds W_l^T[in = 16 rb + m][out = hidden_col_bf16(ku, g, e)], e = 0..7
@@ -174,7 +230,37 @@ __device__ __forceinline__ void bf16_out(const Layout& L, const uint8_t* units, 
       out[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ku], __builtin_bit_cast(bf16x8, Hin[cb][ku]), out[cb], 0, 0, 0);
 }
 
-template <int H, bool BF16>
+// Stages leaf b's parameters into LDS in the on-chip bfloat16 (or float32) layout.  A
+// float8 block is expanded on the way: each 8-byte lane fragment becomes the 16-byte
+// bfloat16 fragment of the same unit and lane, every weight times its layer's scale.
+template <bool FP8>
+__device__ __forceinline__ void stage_leaf(const Layout& L, const uint8_t* __restrict__ packed, uint32_t b,
+                                           uint8_t* lds, int tid) {
+  if constexpr (FP8) {
+    const uint8_t* blk = packed + (uint64_t)b * L.bytes8;
+    const f32x4* bsrc = reinterpret_cast<const f32x4*>(blk);
+    for (int i = tid; i < L.bias_bytes / 16; i += kThreads) reinterpret_cast<f32x4*>(lds)[i] = bsrc[i];
+    const float* scale = reinterpret_cast<const float*>(blk + L.bias_bytes);
+    const uint2* wsrc = reinterpret_cast<const uint2*>(blk + L.bias_bytes + kFp8ScaleBytes);
+    for (int i = tid; i < L.units * 64; i += kThreads) {
+      const uint2 q = wsrc[i];
+      const float s = scale[L.layer_of_unit(i >> 6)];
+      float f[8];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        f[e] = e4m3_decode((q.x >> (8 * e)) & 255u) * s;
+        f[4 + e] = e4m3_decode((q.y >> (8 * e)) & 255u) * s;
+      }
+      *reinterpret_cast<bf16x8*>(lds + L.bias_bytes + (uint32_t)i * 16) = cvt_bf16x8(f);
+    }
+  } else {
+    const f32x4* src = reinterpret_cast<const f32x4*>(packed + (uint64_t)b * L.bytes);
+    f32x4* dst = reinterpret_cast<f32x4*>(lds);
+    for (uint32_t i = tid; i < L.bytes / 16; i += kThreads) dst[i] = src[i];
+  }
+}
+
+template <int H, bool BF16, bool FP8 = false>
 __global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
     Layout L, const uint8_t* __restrict__ packed, uint32_t n_leaves,
     const uint32_t* __restrict__ bucket_off, const uint32_t* __restrict__ tile_off,
@@ -235,9 +321,7 @@ __global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
     while (tile_off[b + 1] <= t) ++b;
     if ((int)b != cur) {
       __syncthreads();
-      const f32x4* src = reinterpret_cast<const f32x4*>(packed + (uint64_t)b * L.bytes);
-      f32x4* dst = reinterpret_cast<f32x4*>(lds);
-      for (uint32_t i = tid; i < L.bytes / 16; i += kThreads) dst[i] = src[i];
+      stage_leaf<FP8>(L, packed, b, lds, tid);
       __syncthreads();
       cur = (int)b;
     }
@@ -402,14 +486,14 @@ __global__ __launch_bounds__(kThreads, BF16 ? 4 : 2) void k_mlp(
   }
 }
 
-template <int H, bool BF16>
+template <int H, bool BF16, bool FP8 = false>
 hipError_t launch_typed(const Layout& L, const void* packed, uint32_t n_leaves, const uint32_t* bucket_off,
                         const uint32_t* tile_off, const ChunkCounts* counts, const uint32_t* srec_ray,
                         const float* srec_t, const uint32_t* perm, const float* o, const float* d,
                         int64_t stride, int64_t r0, float* out, hipStream_t st) {
   static int grid = 0;
   static uint32_t grid_bytes = 0;
-  auto kern = k_mlp<H, BF16>;
+  auto kern = k_mlp<H, BF16, FP8>;
   if (grid == 0 || grid_bytes != L.bytes) {
     if (L.bytes > 64 * 1024) {
       hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.bytes);
@@ -445,13 +529,13 @@ hipError_t resident_blocks(const void* kern, int threads, uint32_t lds, int* per
 bool mlp_geom(int n_hidden, int hidden, int dtype, MlpGeom* g) {
   if (n_hidden < 1 || n_hidden > 8) return false;
   if (hidden != 32 && hidden != 64) return false;
-  if (dtype != AMNERF_F32 && dtype != AMNERF_BF16) return false;
+  if (dtype != AMNERF_F32 && dtype != AMNERF_BF16 && dtype != AMNERF_FP8) return false;
   Layout L = make_layout(n_hidden, hidden, dtype);
   if (L.bytes > 160 * 1024) return false;
   g->n_hidden = n_hidden;
   g->hidden = hidden;
   g->dtype = dtype;
-  g->node_bytes = L.bytes;
+  g->node_bytes = dtype == AMNERF_FP8 ? L.bytes8 : L.bytes;
   g->bwd_node_bytes = L.bwd_bytes;
   return true;
 }
@@ -460,6 +544,9 @@ hipError_t launch_mlp_pack(const MlpGeom& g, int n_leaves, const float* master, 
                            hipStream_t st) {
   Layout L = make_layout(g.n_hidden, g.hidden, g.dtype);
   int P = master_param_count(g.n_hidden, g.hidden);
+  if (g.dtype == AMNERF_FP8)
+    hipLaunchKernelGGL(k_fp8_scales, dim3(n_leaves * (g.n_hidden + 1)), dim3(kThreads), 0, st, L, P, master,
+                       (uint8_t*)packed);
   hipLaunchKernelGGL(k_mlp_pack, dim3(1024), dim3(256), 0, st, L, n_leaves, P, master, (uint8_t*)packed);
   return hipGetLastError();
 }
@@ -469,6 +556,10 @@ hipError_t launch_mlp(const MlpGeom& g, const void* packed, uint32_t n_leaves, c
                       const float* srec_t, const uint32_t* perm, const float* o, const float* d,
                       int64_t ray_stride, int64_t r0, float* out, hipStream_t st) {
   Layout L = make_layout(g.n_hidden, g.hidden, g.dtype);
+  if (g.dtype == AMNERF_FP8) {
+    if (g.hidden == 64) return launch_typed<64, true, true>(L, packed, n_leaves, bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d, ray_stride, r0, out, st);
+    return launch_typed<32, true, true>(L, packed, n_leaves, bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d, ray_stride, r0, out, st);
+  }
   if (g.dtype == AMNERF_BF16) {
     if (g.hidden == 64) return launch_typed<64, true>(L, packed, n_leaves, bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d, ray_stride, r0, out, st);
     return launch_typed<32, true>(L, packed, n_leaves, bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d, ray_stride, r0, out, st);

@@ -14,6 +14,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kUnitBytes = 1024;   // one A fragment set: 64 lanes x 16 bytes
+constexpr int kUnit8Bytes = 512;   // the same fragments as float8: 64 lanes x 8 bytes
+constexpr int kFp8ScaleBytes = 64; // one float32 scale per layer (at most 9 layers), padded
 
 // Per leaf: float32 biases (n_hidden * H + 16, padded to 16 bytes), then 1 KiB units of
 // A fragments.  Forward units: layer 0 (RB x KU0), hidden layers (RB x KUh each), output
@@ -24,6 +26,14 @@ struct Layout {
   int H, nh, dtype, RB, KU0, KUh;
   int bias_floats, bias_bytes, units, bwd_units;
   uint32_t bytes, bwd_bytes;
+  uint32_t bytes8;   // float8 blocks in memory: biases, kFp8ScaleBytes of scales, 512-byte units
+  // layer of forward unit u
+  __host__ __device__ int layer_of_unit(int u) const {
+    const int n0 = RB * KU0;
+    if (u < n0) return 0;
+    if (u < n0 + (nh - 1) * RB * KUh) return 1 + (u - n0) / (RB * KUh);
+    return nh;
+  }
   __host__ __device__ int unit_index(int layer, int rb, int ku) const {
     if (layer == 0) return rb * KU0 + ku;
     int base = RB * KU0;
@@ -37,17 +47,21 @@ struct Layout {
   }
 };
 
+// float8 weights are staged on chip as bfloat16, so the bfloat16 layout applies on chip;
+// `bytes8` is the float8 block in memory.
 inline Layout make_layout(int nh, int H, int dtype) {
   Layout L;
+  const bool b16 = dtype == AMNERF_BF16 || dtype == AMNERF_FP8;
   L.H = H; L.nh = nh; L.dtype = dtype; L.RB = H / 16;
-  L.KU0 = dtype == AMNERF_BF16 ? 1 : 2;
-  L.KUh = dtype == AMNERF_BF16 ? H / 32 : H / 16;
+  L.KU0 = b16 ? 1 : 2;
+  L.KUh = b16 ? H / 32 : H / 16;
   L.bias_floats = nh * H + 16;
   L.bias_bytes = (L.bias_floats * 4 + 15) / 16 * 16;
   L.units = L.RB * L.KU0 + (nh - 1) * L.RB * L.KUh + L.KUh;
   L.bytes = (uint32_t)(L.bias_bytes + L.units * kUnitBytes);
   L.bwd_units = dtype == AMNERF_BF16 ? (nh - 1) * L.RB * L.KUh + L.RB : 0;
   L.bwd_bytes = (uint32_t)(L.bwd_units * kUnitBytes);
+  L.bytes8 = dtype == AMNERF_FP8 ? (uint32_t)(L.bias_bytes + kFp8ScaleBytes + L.units * kUnit8Bytes) : 0u;
   return L;
 }
 

@@ -34,3 +34,12 @@ def test_calls_that_need_no_device():
         raise AssertionError("hidden=48 accepted")
     except am.AmnerfError as e:
         assert e.code == am.AMNERF_EINVAL and "unsupported" in am.amnerf_last_error()
+
+
+def test_fp8_block_size():
+    # float8 leaf block: float32 biases (n_hidden * hidden + 16, padded to 16 bytes), 16 scale
+    # slots, then 32H + (n_hidden - 1) H^2 + 16H one-byte codes
+    for nh, H in ((1, 32), (2, 32), (4, 64), (8, 64)):
+        per = ((nh * H + 16) * 4 + 15) // 16 * 16 + 64 + 32 * H + (nh - 1) * H * H + 16 * H
+        assert am.amnerf_mlp_packed_bytes(nh, H, am.AMNERF_FP8, 512) == per * 512
+    assert am.amnerf_mlp_packed_bytes(4, 64, am.AMNERF_FP8, 1) < am.amnerf_mlp_packed_bytes(4, 64, am.AMNERF_BF16, 1) // 2
