@@ -12,6 +12,11 @@ kernels on plain-render targets from 200 seeded training cameras.  `value` is th
 proposal path's samples/s (samples evaluated by the leaf MLPs) and `ms_per_step` its
 ms/frame.  The oracle (float64, CPU) renders a bounded random subset of camera 0's rays:
 that gives the CPU baseline and the PSNR of each GPU path against the oracle.
+
+A second, larger workload follows in the same run and is reported under `large_scene`
+(skip it with --no-large): 1920x1080 frames of a 256^3-grid scene with a 100:1 blob-density
+skew, a 4096-leaf tree, float8 (and bfloat16) leaf weights and S_max 192; one call renders
+30 held-out cameras, with and without a proposal trained on 200 other cameras.
 """
 from __future__ import annotations
 
@@ -41,6 +46,156 @@ def cpu_threads():
     return max(1, min(16, n))
 
 
+def large_scene(args, am, torch, np, synth, ctx):
+    """The 1920x1080 scene: 256^3 grid with a 100:1 blob-density skew, 4096-leaf tree,
+    4x64 leaf MLPs with float8 weights, S_max 192.  30 held-out cameras are rendered by one
+    call (62.2 M rays, processed in chunks of at most 2^28 / S_max rays); a proposal is
+    trained on 200 other cameras.  Accuracy against the oracle on a seeded 1/64 pixel
+    subset of camera 0; the proposal's error against the plain float8 render on every pixel
+    of the 30 cameras (the plain renderer judges it)."""
+    cfg = synth.C3
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    grid = synth.make_grid(cfg)
+    tree = am.Tree(ctx, grid, cfg.grid_n, cfg.max_depth, cfg.max_leaves)
+    L = tree.n_leaves
+    dens = synth.leaf_mean_density(grid, cfg.grid_n, tree.leaf_boxes())
+    W = synth.make_weights(L, cfg.n_hidden, cfg.hidden, cfg.seed_weights, dens)
+    master = torch.from_numpy(W).to(dev)
+    mlps = {k: am.Mlp(ctx, master, cfg.n_hidden, cfg.hidden, dt, L)
+            for k, dt in (("fp8", am.AMNERF_FP8), ("bf16", am.AMNERF_BF16), ("f32", am.AMNERF_F32))}
+    n_cams = cfg.n_cameras
+    cams = synth.make_cameras(n_cams, cfg.seed_cameras, cfg.width, cfg.height)
+    R1 = cfg.width * cfg.height
+    R = R1 * n_cams
+    o_all = torch.empty((3, R), dtype=torch.float32, device=dev)
+    d_all = torch.empty((3, R), dtype=torch.float32, device=dev)
+    for i, c in enumerate(cams):
+        o, d = synth.camera_rays(c)
+        o_all[:, i * R1:(i + 1) * R1] = torch.from_numpy(o).to(dev)
+        d_all[:, i * R1:(i + 1) * R1] = torch.from_numpy(d).to(dev)
+    log("large scene %s: %d leaves, %d rays per call, set-up %.1f s" % (cfg.name, L, R, time.perf_counter() - t0))
+
+    # proposal trained on 200 other cameras (untimed)
+    t0 = time.perf_counter()
+    prop = am.Proposal(ctx, torch.from_numpy(synth.make_prop_weights(cfg.seed_proposal)).to(dev))
+    untrained = am.Proposal(ctx, torch.from_numpy(synth.make_prop_weights(cfg.seed_proposal)).to(dev))
+    untrained.repack()
+    train_cams = synth.make_cameras(200, cfg.seed_batches, cfg.width, cfg.height)
+    pool_o, pool_d = synth.random_pixel_rays(train_cams, 2_000_000, cfg.seed_batches + 1)
+    pool_o, pool_d = torch.from_numpy(pool_o).to(dev), torch.from_numpy(pool_d).to(dev)
+    gen = torch.Generator(device=dev).manual_seed(cfg.seed_batches + 2)
+    losses = []
+    for it in range(args.large_prop_steps):
+        lr = 3e-3 if it < 0.7 * args.large_prop_steps else 1e-3
+        idx = torch.randint(0, pool_o.shape[1], (args.prop_batch,), device=dev, generator=gen)
+        loss = prop.train_step(tree, mlps["f32"].desc, pool_o[:, idx].contiguous(), pool_d[:, idx].contiguous(),
+                               cfg.s_max, lr=lr)
+        if it % 1000 == 0 or it == args.large_prop_steps - 1:
+            losses.append(float(loss.item()))
+    prop.repack()
+    torch.cuda.synchronize()
+    t_prop = time.perf_counter() - t0
+    del pool_o, pool_d
+    log("large proposal: %d steps in %.1f s, loss %s" % (args.large_prop_steps, t_prop, ["%.2e" % v for v in losses]))
+    desc = prop.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
+    desc_untrained = untrained.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
+
+    paths = {"fp8": ("fp8", None), "fp8_prop": ("fp8", desc), "bf16": ("bf16", None), "bf16_prop": ("bf16", desc),
+             "fp8_untrained_prop": ("fp8", desc_untrained)}
+    outs = {k: torch.empty((R, 3), dtype=torch.float32, device=dev) for k in paths}
+
+    def render(kind, rgb):
+        mk, pd = paths[kind]
+        am.amnerf_render(ctx.h, tree.h, mlps[mk].desc, o_all, d_all, cfg.s_max, rgb, None, None, None, cfg.ert_eps,
+                         proposal=pd)
+
+    res = {}
+    am.amnerf_ctx_set_timing(ctx.h, True)
+    for kind in paths:
+        rgb = outs[kind]
+        render(kind, rgb)                                    # warm-up, and the sample counts
+        st = am.amnerf_render_stats_get(ctx.h)
+        am.amnerf_timing_collect(ctx.h)
+        calls = args.large_calls if kind != "fp8_untrained_prop" else 1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            render(kind, rgb)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / calls
+        stage_ms, npass = am.amnerf_timing_collect(ctx.h)
+        mlp_ms = stage_ms["mlp"] / calls
+        res[kind] = {"ms_per_frame": 1e3 * dt / n_cams, "ms_per_call": 1e3 * dt,
+                     "samples_per_s": st["n_samples"] / dt, "samples_per_frame": st["n_samples"] / n_cams,
+                     "samples_per_ray": st["n_samples"] / R, "fallback_fraction": st["n_fallback"] / R,
+                     "chunks_per_call": st["n_chunks"],
+                     "stage_ms_per_frame": {k: v / calls / n_cams for k, v in stage_ms.items()},
+                     "mlp_tflops": FLOP_PER_SAMPLE_4x64 * st["n_samples"] / (mlp_ms * 1e-3) / 1e12}
+        log("large %s: %.3f ms/frame, %.3e samples/s, %.1f samples/ray, fallback %.3f, stages %s" % (
+            kind, res[kind]["ms_per_frame"], res[kind]["samples_per_s"], res[kind]["samples_per_ray"],
+            res[kind]["fallback_fraction"], {k: round(v, 4) for k, v in res[kind]["stage_ms_per_frame"].items()}))
+    am.amnerf_ctx_set_timing(ctx.h, False)
+
+    # each proposal render judged by the plain render with the same leaf weights, every pixel
+    # of the 30 cameras (the outputs of the last timed call)
+    psnr_prop_vs_plain = {}
+    for kind, ref in (("fp8_prop", "fp8"), ("bf16_prop", "bf16"), ("fp8_untrained_prop", "fp8")):
+        rep = am.amnerf_error_stats(ctx.h, outs[kind].view(-1), outs[ref].view(-1).double())
+        psnr_prop_vs_plain[kind] = rep["psnr"]
+    log("large proposal psnr vs plain: %s" % {k: round(v, 2) for k, v in psnr_prop_vs_plain.items()})
+
+    # bucket sizes of one single-chunk pass: the first 2^20 rays of camera 0
+    n_sub = 1 << 20
+    o_sub, d_sub = o_all[:, :n_sub].contiguous(), d_all[:, :n_sub].contiguous()
+    sub_rgb = torch.empty((n_sub, 3), dtype=torch.float32, device=dev)
+    am.amnerf_render(ctx.h, tree.h, mlps["fp8"].desc, o_sub, d_sub, cfg.s_max, sub_rgb, None, None, None, cfg.ert_eps)
+    st = am.amnerf_render_stats_get(ctx.h)
+    ns = st["n_samples"]
+    bo = torch.empty(L + 1, dtype=torch.int32, device=dev)
+    am.amnerf_render_inspect(ctx.h, bucket_off=bo)
+    sizes = np.diff(bo.cpu().numpy().astype(np.int64))
+    nz = sizes[sizes > 0]
+    spread = {"rays": n_sub, "samples": int(ns), "leaves_nonempty": int(nz.size),
+              "min": int(nz.min()), "p1": float(np.percentile(nz, 1)), "median": float(np.median(nz)),
+              "p99": float(np.percentile(nz, 99)), "max": int(nz.max()),
+              "max_over_min_nonempty": float(nz.max() / nz.min()),
+              "p99_over_p1": float(np.percentile(nz, 99) / max(np.percentile(nz, 1), 1))}
+    log("large bucket sizes: %s" % spread)
+
+    acc = None
+    if not args.no_cpu:
+        import oracle
+        from oracle import fp8 as ofp8
+        otree = oracle.build_tree(grid, cfg.grid_n, cfg.max_depth, cfg.max_leaves)
+        assert np.array_equal(otree.rows, tree.rows)
+        o0, d0 = synth.camera_rays(cams[0])
+        sel = np.sort(np.random.default_rng(64).choice(R1, R1 // 64, replace=False))
+        threads = cpu_threads()
+        rgb_o, _, _, ns_o, _ = oracle.render(otree, W, cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max, eps=cfg.ert_eps,
+                                             ray_idx=sel, threads=threads)
+        _, _, deq = ofp8.quantise(W, cfg.n_hidden, cfg.hidden)
+        rgb_q, _, _, _, _ = oracle.render(otree, deq.astype(np.float32), cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max,
+                                          eps=cfg.ert_eps, ray_idx=sel, threads=threads)
+        sel_dev = torch.from_numpy(sel).to(dev)
+        acc = {"rays": int(sel.size), "sample": "seeded 1/64 pixel subset of camera 0"}
+        for kind in ("fp8", "fp8_prop"):
+            x = outs[kind][:R1][sel_dev].contiguous().view(-1)
+            acc["psnr_%s_vs_oracle_db" % kind] = am.amnerf_error_stats(
+                ctx.h, x, torch.from_numpy(np.ascontiguousarray(rgb_o)).to(dev).view(-1))["psnr"]
+            acc["psnr_%s_vs_oracle_fp8_weights_db" % kind] = am.amnerf_error_stats(
+                ctx.h, x, torch.from_numpy(np.ascontiguousarray(rgb_q)).to(dev).view(-1))["psnr"]
+        log("large accuracy: %s" % acc)
+
+    return {"workload": "1920x1080 frames, 256^3 guidance grid (2000 anisotropic blobs, 100:1 density skew), "
+                        "%d-leaf KD tree (max depth 12), 4x64 leaf MLPs, <=192 samples/ray, ERT at T<1e-4; "
+                        "%d held-out cameras rendered by one call" % (L, n_cams),
+            "n_leaves": L, "rays_per_call": R, "cameras_per_call": n_cams, "paths": res,
+            "psnr_vs_plain_db": psnr_prop_vs_plain, "bucket_sizes": spread, "accuracy": acc,
+            "proposal_training": {"steps": args.large_prop_steps, "rays_per_step": args.prop_batch, "cameras": 200,
+                                  "seconds": t_prop, "loss_first_last": [losses[0], losses[-1]]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,6 +209,9 @@ def main():
     ap.add_argument("--paths", default="f32,bf16,bf16_prop,fp8,fp8_prop",
                     help="comma-separated render paths to time (the headline bf16_prop is always timed)")
     ap.add_argument("--train-batch", type=int, default=262144)
+    ap.add_argument("--no-large", action="store_true", help="skip the 1920x1080 4096-leaf scene")
+    ap.add_argument("--large-calls", type=int, default=3, help="timed 30-camera calls of the large scene")
+    ap.add_argument("--large-prop-steps", type=int, default=6000, help="proposal training steps, large scene")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -249,6 +407,14 @@ def main():
             cpu["value"], threads, {k: round(v, 2) for k, v in psnr.items()},
             {k: float("%.3g" % v) for k, v in max_abs.items()}))
 
+    large = None
+    if not args.no_large:
+        del mlps, outs, imgs
+        if args.train_steps > 0:
+            del trainer, batches, po, pd, ptarget
+        torch.cuda.empty_cache()
+        large = large_scene(args, am, torch, np, synth, ctx)
+
     head = results["bf16_prop"]
     achieved = head["mlp_tflops"]
     traffic = None
@@ -290,6 +456,7 @@ def main():
         "speedup_vs_plain_fp32": results["f32"]["ms_per_frame"] / head["ms_per_frame"] if "f32" in results else None,
         "training": train,
         "paths": results,
+        "large_scene": large,
     }
     print(json.dumps(line), flush=True)
 

@@ -25,6 +25,8 @@ Conventions
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -126,6 +128,9 @@ def make_grid(cfg: SceneConfig) -> np.ndarray:
         regions = [0] * n_oct + [1] * n_rest
     else:
         regions = [2] * cfg.n_blobs
+    # blob parameters are drawn in order; the boxes are evaluated on a thread pool (numpy
+    # releases the interpreter lock inside its array kernels) and summed in blob order
+    blobs = []
     for reg in regions:
         if reg == 0:
             mu = rng.uniform(0.0, 0.5, 3)
@@ -144,12 +149,16 @@ def make_grid(cfg: SceneConfig) -> np.ndarray:
         else:
             s1 = rng.uniform(*cfg.s_range)
             cov = np.eye(3) * s1 * s1
+        blobs.append((mu, amp, cov))
+
+    def box(blob):
+        mu, amp, cov = blob
         prec = np.linalg.inv(cov)
         half = 4.0 * np.sqrt(np.diag(cov))
         lo = np.clip(np.floor((mu - half) * n).astype(int), 0, n)
         hi = np.clip(np.ceil((mu + half) * n).astype(int) + 1, 0, n)
         if np.any(hi <= lo):
-            continue
+            return None
         xs = centres[lo[0]:hi[0]] - mu[0]
         ys = centres[lo[1]:hi[1]] - mu[1]
         zs = centres[lo[2]:hi[2]] - mu[2]
@@ -158,7 +167,20 @@ def make_grid(cfg: SceneConfig) -> np.ndarray:
               + 2.0 * (prec[0, 1] * X * Y + prec[0, 2] * X * Z + prec[1, 2] * Y * Z))
         val = amp * np.exp(-0.5 * m2)
         val[m2 > 16.0] = 0.0
-        g[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] += val
+        return lo, hi, val
+
+    workers = max(1, min(8, os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as pool:
+        window = 2 * workers
+        futs = [pool.submit(box, b) for b in blobs[:window]]
+        for i in range(len(blobs)):
+            r = futs[i].result()
+            futs[i] = None
+            if i + window < len(blobs):
+                futs.append(pool.submit(box, blobs[i + window]))
+            if r is not None:
+                lo, hi, val = r
+                g[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] += val
     if cfg.ground_cells > 0:
         g[:cfg.ground_cells, :, :] += cfg.ground_amp
     return np.ascontiguousarray(g.astype(np.float32).reshape(-1))

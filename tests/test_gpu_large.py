@@ -1,0 +1,84 @@
+"""The large uneven scene on the GPU: 256^3 grid with a 100:1 blob-density skew, 4096-leaf
+tree, 4x64 leaf MLPs, S_max 192, 1920x1080 cameras -- parity on sampled rays."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import fp8
+from scene_util import Scene, gpu_setup, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2310_01881_amd as am  # noqa: E402
+from test_gpu_render import check_intervals_and_sort, compare_render, fetch_inspect  # noqa: E402
+
+S_MAX = synth.C3.s_max
+
+
+@pytest.fixture(scope="module")
+def scene():
+    print("c3 scene set-up", flush=True)
+    return Scene(synth.C3)
+
+
+def test_c3_fp32_one_pass_subset(scene):
+    """200 000 random pixels of camera 0 in one pass: node ids and intervals on robust rays,
+    bucket offsets and the permutation bit-exact, float32 render within the float32 bar."""
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    assert tree.n_leaves == 4096
+    o, d = scene.camera_rays()
+    pick = np.sort(np.random.default_rng(5).choice(o.shape[1], 200_000, replace=False))
+    o, d = np.ascontiguousarray(o[:, pick]), np.ascontiguousarray(d[:, pick])
+    R = o.shape[1]
+    print("c3 fp32 subset: rays", R, flush=True)
+    out = am.render(ctx, tree, mlp, to_dev(o), to_dev(d), S_MAX, ert_eps=scene.cfg.ert_eps)
+    torch.cuda.synchronize()
+    st, ins = fetch_inspect(ctx, R, tree.n_leaves)
+    print("c3 stats", st, flush=True)
+    assert st["n_chunks"] == 1 and st["n_nonfinite"] == 0
+    rays = np.sort(np.random.default_rng(6).choice(R, 1500, replace=False))
+    robust = check_intervals_and_sort(scene, o, d, S_MAX, ins, rays)
+    e = compare_render(scene, out, o, d, S_MAX, rays, robust)
+    print("c3 fp32 max err rgb/opacity/depth", e, flush=True)
+    sizes = np.diff(ins["bucket_off"].astype(np.int64))
+    nz = sizes[sizes > 0]
+    print("c3 bucket sizes: %d non-empty of %d, min %d, median %d, max %d" % (
+        nz.size, sizes.size, nz.min(), np.median(nz), nz.max()), flush=True)
+    # the skewed scene gives buckets over at least two orders of magnitude
+    assert nz.max() >= 100 * nz.min()
+
+
+def test_c3_fp8_full_camera_in_two_passes(scene):
+    """Camera 0 whole (2 073 600 rays, two passes at S_max 192) with float8 weights, checked
+    on sampled rays of both passes against the oracle on the dequantised weights."""
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_FP8)
+    o, d = scene.camera_rays()
+    R = o.shape[1]
+    print("c3 fp8: rays", R, flush=True)
+    out = am.render(ctx, tree, mlp, to_dev(o), to_dev(d), S_MAX, ert_eps=cfg.ert_eps)
+    torch.cuda.synchronize()
+    st = am.amnerf_render_stats_get(ctx.h)
+    print("c3 fp8 stats", st, flush=True)
+    assert st["n_chunks"] == 2 and st["n_nonfinite"] == 0
+    rays = np.sort(np.random.default_rng(7).choice(R, 1500, replace=False))
+    chunk = (1 << 28) // S_MAX
+    assert rays.min() < chunk <= rays.max()
+    _, _, deq = fp8.quantise(scene.W, cfg.n_hidden, cfg.hidden)
+    rgb_q, _, _, _, _ = oracle.render(scene.otree, deq.astype(np.float32), cfg.n_hidden, cfg.hidden, o, d, S_MAX,
+                                      eps=cfg.ert_eps, ray_idx=rays)
+    rgb, _, _, _, _ = oracle.render(scene.otree, scene.W, cfg.n_hidden, cfg.hidden, o, d, S_MAX,
+                                    eps=cfg.ert_eps, ray_idx=rays)
+    g = out["rgb"].cpu().numpy()[rays]
+    p_q, p_full, p_oq = oracle.psnr(g, rgb_q), oracle.psnr(g, rgb), oracle.psnr(rgb_q, rgb)
+    print("c3 fp8: psnr vs oracle(dequantised) %.2f dB, vs oracle(float32 weights) %.2f dB, "
+          "quantisation alone %.2f dB" % (p_q, p_full, p_oq), flush=True)
+    assert p_q > 45.0
+    assert p_full > p_oq - 1.0
