@@ -23,11 +23,16 @@ SOURCES = ["amnerf.cpp", "trav.hip", "scan.hip", "sort.hip", "mlp.hip", "mlp_bwd
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include")]
+# Kernels that post-process every matrix-core result with vector instructions keep their
+# accumulators in ordinary VGPRs: in the accumulation registers each result would first be
+# copied out (one v_accvgpr_read per value).
+PER_FILE = {"prop.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+            "mlp_bwd.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + PER_FILE.get(src, []) + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
