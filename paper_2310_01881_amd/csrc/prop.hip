@@ -203,24 +203,56 @@ __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict
   constexpr int NCB = BF16 ? 2 : 4;
   constexpr uint32_t kTile = 4u * 16u * NCB;
   const uint32_t n_items = *iv.n_iv_dev;
+  // The interval records (ray, t0, dt, key) of a wave's next tile are loaded one tile ahead;
+  // the loads that depend on them (the ray's origin, direction and first interval, the leaf
+  // box) are issued at the start of the tile, before that prefetch, so waiting for them
+  // never waits for it.
+  uint32_t p_ray[NCB], p_key[NCB];
+  float p_t0[NCB], p_dt[NCB];
+  auto load_records = [&](uint32_t tl) {
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      uint32_t it = tl * kTile + wave * 16u * NCB + cb * 16 + m;
+      it = it < n_items ? it : n_items - 1;
+      p_ray[cb] = iv.ray[it];
+      p_t0[cb] = iv.t0[it];
+      p_dt[cb] = iv.dt[it];
+      p_key[cb] = iv.key[it];
+    }
+  };
+  if (BF16 && blockIdx.x * kTile < n_items) load_records(blockIdx.x);
   for (uint32_t tile = blockIdx.x; tile * kTile < n_items; tile += gridDim.x) {
     const uint32_t base = tile * kTile + wave * 16u * NCB;
-    if (base >= n_items) continue;
+    if (base >= n_items) continue;   // so are this wave's later tiles
     f32x4 acc[NCB][4];
     if (BF16) {
       bf16x8 X[NCB][2];
+      uint32_t c_ray[NCB], c_k[NCB];
+      float c_t0[NCB], c_t1[NCB], c_o[NCB][3], c_d[NCB][3], c_box[NCB][3];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         uint32_t it = base + cb * 16 + m;
         it = it < n_items ? it : n_items - 1;
-        const uint32_t ray = iv.ray[it];
-        const uint32_t k = it - iv.iv_off[ray];
-        const int64_t ri = r0 + ray;
-        const float oo[3] = {o[ri], o[stride + ri], o[2 * stride + ri]};
-        const float dd[3] = {d[ri], d[stride + ri], d[2 * stride + ri]};
-        const float t0 = iv.t0[it];
-        const float t1 = t0 + iv.dt[it];
-        const float* box = leafbox + 6 * key_slot(iv.key[it]) + 3 * (g & 1);
+        c_ray[cb] = p_ray[cb];
+        c_k[cb] = it - iv.iv_off[c_ray[cb]];
+        const int64_t ri = r0 + c_ray[cb];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          c_o[cb][a] = o[a * stride + ri];
+          c_d[cb][a] = d[a * stride + ri];
+          c_box[cb][a] = leafbox[6 * key_slot(p_key[cb]) + 3 * (g & 1) + a];
+        }
+        c_t0[cb] = p_t0[cb];
+        c_t1[cb] = p_t0[cb] + p_dt[cb];
+      }
+      if ((tile + gridDim.x) * kTile < n_items) load_records(tile + gridDim.x);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const uint32_t k = c_k[cb];
+        const float* oo = c_o[cb];
+        const float* dd = c_d[cb];
+        const float t0 = c_t0[cb], t1 = c_t1[cb];
+        const float* box = c_box[cb];
         const float tt = g == 2 ? t0 : t1;
         const float half_f = (g & 1) ? 1.f : 0.5f;   // revolutions per unit of v
 #pragma unroll
