@@ -598,7 +598,7 @@ size_t carve(char* base, uint64_t nr, uint64_t niv, uint64_t ns, const SortPlan&
 
 // Proposal-stage buffers of one chunk (sized from the measured plain interval count).
 struct PropWork {
-  float* tau;
+  float *wts, *tot;
   uint32_t *runs, *nsel, *pv_off, *ps_off;
   uint64_t* mask;
   float *pt0, *pdt;
@@ -608,7 +608,8 @@ struct PropWork {
 
 size_t carve_prop(char* base, uint64_t nr, uint64_t niv_plain, uint64_t niv_plan, const SortPlan& sp, PropWork& w) {
   Carve c{base};
-  w.tau = c.take<float>(32 * std::max<uint64_t>(niv_plain, 1));
+  w.wts = c.take<float>(32 * std::max<uint64_t>(niv_plain, 1));
+  w.tot = c.take<float>(std::max<uint64_t>(niv_plain, 1));
   w.runs = c.take<uint32_t>(nr);
   w.nsel = c.take<uint32_t>(nr);
   w.pv_off = c.take<uint32_t>(nr + 1);
@@ -713,8 +714,8 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
       if (rc) return rc;
       carve_prop((char*)ctx->arena3, nr, niv_plain, niv_plan, spp, pw);
       HIP_TRY(launch_prop_fwd(q->dtype, q->packed_dev, plain, rays->o_dev, rays->d_dev, R, r0, tree->dev_leafbox,
-                              p->s_max, niv_plain, true, pw.tau, st));
-      HIP_TRY(launch_prop_select(nr, plain, pw.tau, q->mass_thresh, q->cap, pw.runs, pw.nsel, pw.mask, nullptr,
+                              p->s_max, niv_plain, true, pw.wts, pw.tot, st));
+      HIP_TRY(launch_prop_select(nr, plain, pw.wts, pw.tot, q->mass_thresh, q->cap, pw.runs, pw.nsel, pw.mask, nullptr,
                                  ctx->counts, st));
       HIP_TRY(launch_scan_u32(pw.runs, pw.pv_off, nr, nullptr, pw.scan_tmp, st));
       HIP_TRY(launch_scan_u32(pw.nsel, pw.ps_off, nr, nullptr, pw.scan_tmp, st));
@@ -1053,7 +1054,7 @@ extern "C" int amnerf_propose(amnerf_ctx* ctx, const amnerf_tree* tree, const am
     if ((int64_t)niv_guess > p->tau_cap)
       return fail(AMNERF_ECAPACITY, "amnerf_propose: %u intervals exceed tau_cap %lld", niv_guess, (long long)p->tau_cap);
     HIP_TRY(launch_prop_fwd(p->infer_dtype, p->infer_packed_dev, iv, rays->o_dev, rays->d_dev, rays->n_rays, 0,
-                            tree->dev_leafbox, p->s_max, niv_guess, false, p->tau_dev, st));
+                            tree->dev_leafbox, p->s_max, niv_guess, false, p->tau_dev, nullptr, st));
     return AMNERF_OK;
   }
   HIP_TRY(launch_prop_targets(iv, ctx->smp_out, tw.alpha, st));

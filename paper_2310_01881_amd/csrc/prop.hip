@@ -47,6 +47,13 @@ __host__ __device__ __forceinline__ int bf16_unit(int layer, int rb, int ku) {
 }
 
 __device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+// exp(-x) with the hardware base-2 exponential
+__device__ __forceinline__ float exp_neg(float x) { return __builtin_amdgcn_exp2f(-1.44269504f * x); }
+// 1 - exp(-d) for d >= 0 given e = exp(-d): a quartic Taylor polynomial below 1/16
+// (relative error under 2^-23 there), else 1 - e
+__device__ __forceinline__ float one_minus_exp_neg(float d, float e) {
+  return d < 0.0625f ? d * fmaf(d, fmaf(d, fmaf(d, -1.f / 24.f, 1.f / 6.f), -0.5f), 1.f) : 1.f - e;
+}
 // softplus with the hardware base-2 exponential and logarithm: log1p(e) is taken as
 // e (1 - e/2) below e = 2^-12, where that is exact to float rounding.
 __device__ __forceinline__ float softplus_fast(float z) {
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict
                                                        const float* __restrict__ o, const float* __restrict__ d,
                                                        int64_t stride, int64_t r0,
                                                        const float* __restrict__ leafbox, int s_max,
-                                                       int cum, float* __restrict__ tau) {
+                                                       int cum, float* __restrict__ tau, float* __restrict__ tot) {
   extern __shared__ __align__(16) uint8_t lds[];
   const uint32_t bytes = BF16 ? kBf16Bytes : kBiasBytes + kF32Units * kUnitBytes;
   for (uint32_t i = threadIdx.x; i < bytes / 16; i += kThreads)
@@ -365,10 +372,12 @@ __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict
             if (rb < nrb) acc[cb][rb] = nacc[cb][rb];
       }
     }
-    // outputs: rows 16 rb + 4 g + e of the 32 bins.  With cum set, the inclusive prefix sum
-    // of the interval's bins is stored instead (bin b holds tau_0 + ... + tau_b): lane group
-    // g holds bins 4g..4g+3 and 16+4g..16+4g+3 of its column, so the offsets of its two runs
-    // are sums over the lower groups, gathered 16 and 32 lanes down the wave.
+    // outputs: rows 16 rb + 4 g + e of the 32 bins.  With cum set (rendering), the bins'
+    // local composited weights are stored instead, w_b = exp(-P_(b-1)) (1 - exp(-tau_b)) with
+    // P_b = tau_0 + ... + tau_b, and the interval's total P_31 goes to tot.  Lane group g
+    // holds bins 4g..4g+3 and 16+4g..16+4g+3 of its column, so the offsets of its two runs
+    // are sums over the lower groups, gathered 16 and 32 lanes down the wave; within a run
+    // the transmittance steps by exp(-tau_b).
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
       const uint32_t it = base + cb * 16 + m;
@@ -377,47 +386,54 @@ __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict
       for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) v[rb][e] = BF16 ? softplus_fast(acc[cb][rb][e]) : softplusf(acc[cb][rb][e]);
+      float total = 0.f;
       if (cum) {
-        float run[2], off[2];
+        float run[2], off[2], last[2];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
-          v[rb][1] += v[rb][0];
-          v[rb][2] += v[rb][1];
-          v[rb][3] += v[rb][2];
-          float x = v[rb][3];
+          float x = v[rb][0] + v[rb][1];
+          x += v[rb][2];
+          x += v[rb][3];
+          last[rb] = x;                      // this lane's run total
           float y = __shfl_up(x, 16, 64);
           x += g >= 1 ? y : 0.f;
           y = __shfl_up(x, 32, 64);
           x += g >= 2 ? y : 0.f;
           run[rb] = x;                       // inclusive over groups 0..g
-          off[rb] = x - v[rb][3];
+          off[rb] = x - last[rb];
         }
         const float tot0 = __shfl(run[0], 48 + m, 64);
+        const float start[2] = {off[0], tot0 + off[1]};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          v[0][e] += off[0];
-          v[1][e] += tot0 + off[1];
+        for (int rb = 0; rb < 2; ++rb) {
+          float T = exp_neg(start[rb]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float tb = v[rb][e];
+            const float eb = exp_neg(tb);
+            v[rb][e] = T * one_minus_exp_neg(tb, eb);
+            T *= eb;
+          }
         }
+        total = last[1] + (tot0 + off[1]);   // P_31 in lane group 3
       }
       if (it >= n_items) continue;
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
         *reinterpret_cast<f32x4*>(tau + (uint64_t)it * kBins + 16 * rb + 4 * g) = v[rb];
+      if (cum && g == 3) tot[it] = total;
     }
   }
 }
 
 // ---- selection: one wave per ray ----------------------------------------------------
-// Input: per interval, the inclusive prefix sums P_b = tau_0 + ... + tau_b of its 32 bins.
-// The ray's optical depth before interval k, S_k, is a wave scan of the interval totals
-// P_31; the predicted mass is 1 - exp(-S_total), and rays below mass_thresh fall back.
-// Slot j of an interval with n slots covers bins [32 j / n, 32 (j+1) / n).  Its weight is
-// the bins' composited weights T_b (1 - exp(-tau_b)) scaled by the covered fraction of each
-// bin; over the fully covered bins in the middle the sum telescopes, so with
-// E(x) = exp(-(S_k + x)) and D(a, b) = 1 - exp(-(b - a)):
-//   partial first bin lo:  c_lo E(P_lo-1) D(P_lo-1, P_lo)
-//   whole bins lo+1..hi-1: E(P_lo) D(P_lo, P_hi-1)
-//   partial last bin hi:   c_hi E(P_hi-1) D(P_hi-1, P_hi)
+// Input: per interval, its total optical thickness P_31 and the local composited weights
+// w_b of its 32 bins (the weights the bins would have if the ray entered the interval
+// unattenuated).  The ray's optical depth before interval k, S_k, is a wave scan of the
+// totals; the predicted mass is 1 - exp(-S_total), and rays below mass_thresh fall back.
+// Slot j of an interval with n slots covers bins [32 j / n, 32 (j+1) / n); its weight is
+// exp(-S_k) times the covered fraction of each bin's weight: c_lo w_lo + w_(lo+1) + ... +
+// w_(hi-1) + c_hi w_hi, or (32 / n) w_lo when the slot lies inside one bin.
 // The weights are then sorted (descending) across the wave, a prefix sum over them gives
 // the number c of slots needed to reach mass_thresh * M^, and the slots kept are those with
 // weight above the c-th largest value w* plus, among those equal to w*, the lowest-indexed
@@ -496,16 +512,6 @@ __device__ __forceinline__ void bitonic_desc(uint32_t key[E], int lane) {
   }
 }
 
-// exp(-x) with the hardware base-2 exponential
-__device__ __forceinline__ float exp_neg(float x) { return __builtin_amdgcn_exp2f(-1.44269504f * x); }
-// 1 - exp(-d) for d >= 0: a cubic Taylor polynomial below 1/16 (relative error under 2^-23
-// there), else from the hardware exponential
-__device__ __forceinline__ float one_minus_exp_neg(float d) {
-  d = fmaxf(d, 0.f);   // prefix differences can dip an ulp below zero
-  if (d < 0.0625f) return d * fmaf(d, fmaf(d, fmaf(d, -1.f / 24.f, 1.f / 6.f), -0.5f), 1.f);
-  return 1.f - exp_neg(d);
-}
-
 // Number of slots kept: the shortest prefix of the descending weights whose sum reaches
 // target.  *reached is false when all ns slots together stay below it.  *wcut = weight of
 // the last kept slot.
@@ -536,7 +542,8 @@ __device__ __forceinline__ uint32_t count_sorted(const float p[4], uint32_t ns, 
   return count;
 }
 
-__global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv, const float* __restrict__ cum,
+__global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv, const float* __restrict__ wts,
+                                                          const float* __restrict__ tot,
                                                           float mass_thresh, int cap, uint32_t* __restrict__ runs,
                                                           uint32_t* __restrict__ nsel, uint64_t* __restrict__ mask,
                                                           float* __restrict__ mass_out,
@@ -547,20 +554,63 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
   // fallback rays are counted per wave and added once per block: one global atomic per
   // fallback ray serialises on the counter's cache line
   uint32_t n_fb = 0;
-  for (uint32_t r = blockIdx.x * (kThreads / 64) + wave; r < nr; r += gridDim.x * (kThreads / 64)) {
-    const uint32_t i0 = iv.iv_off[r], meff = iv.iv_off[r + 1] - i0;
-    const uint32_t ns = iv.smp_off[r + 1] - iv.smp_off[r];
+  const uint32_t step = gridDim.x * (kThreads / 64);
+  uint32_t r = blockIdx.x * (kThreads / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(wave);
+  // the ray's interval and sample offsets are loaded one ray ahead
+  uint32_t nx_i0 = 0, nx_i1 = 0, nx_s0 = 0, nx_s1 = 0;
+  if (r < nr) { nx_i0 = iv.iv_off[r]; nx_i1 = iv.iv_off[r + 1]; nx_s0 = iv.smp_off[r]; nx_s1 = iv.smp_off[r + 1]; }
+  for (; r < nr; r += step) {
+    const uint32_t i0 = nx_i0, meff = nx_i1 - nx_i0;
+    const uint32_t ns = nx_s1 - nx_s0;
+    const uint32_t rn = r + step;
     if (meff == 0) {
       if (lane == 0) { runs[r] = 0; nsel[r] = 0; if (mass_out) mass_out[r] = 0.f; }
+      if (rn < nr) { nx_i0 = iv.iv_off[rn]; nx_i1 = iv.iv_off[rn + 1]; nx_s0 = iv.smp_off[rn]; nx_s1 = iv.smp_off[rn + 1]; }
       continue;
     }
-    // optical depth before each interval
+    const uint32_t n = ns / meff;
+    // floor(x / n) = umulhi(x, m) with m = ceil(2^32 / n) for x < 2^16 and n >= 2 (the
+    // error x (m - 2^32/n) / 2^32 stays below 1/n, so it never carries into the integer part)
+    const uint32_t m32 = n > 1u ? 0xFFFFFFFFu / n + 1u : 0u;
+    auto div_n = [&](uint32_t x) { return n > 1u ? __umulhi(x, m32) : x; };
+    const uint32_t nq = (ns + 63u) / 64u;
+    // Every load of the ray is issued before the first wait: the bin weights each slot
+    // covers (its first and last bin and up to 4 whole bins between them), then the
+    // interval totals, then the next ray's offsets.
+    // The slot geometry is kept packed: interval k (8 bits), slot j in it (8 bits), first and
+    // last bin (5 bits each).
+    constexpr int kMid = 4;
+    float wlo[4], whi[4], wmid[4][kMid];
+    uint32_t geo[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      wlo[q] = 0.f; whi[q] = 0.f; geo[q] = 0u;
+#pragma unroll
+      for (int t = 0; t < kMid; ++t) wmid[q][t] = 0.f;
+      if ((uint32_t)q >= nq) continue;
+      const uint32_t s = (uint32_t)lane + 64u * q;
+      const uint32_t sk = div_n(s);
+      const uint32_t j = s - sk * n;
+      const uint32_t blo = div_n(32u * j);
+      const uint32_t bhi = div_n(32u * (j + 1) + n - 1) - 1u;
+      geo[q] = (sk & 255u) | ((j & 255u) << 8) | (blo << 16) | ((bhi & 31u) << 24);
+      if (s >= ns) continue;
+      const float* row = wts + (uint64_t)(i0 + sk) * kBins;
+      wlo[q] = row[blo];
+      whi[q] = row[bhi];
+#pragma unroll
+      for (int t = 0; t < kMid; ++t)
+        if (blo + 1u + (uint32_t)t < bhi) wmid[q][t] = row[blo + 1u + t];
+    }
+    float tk0 = (uint32_t)lane < meff ? tot[i0 + lane] : 0.f;
+    if (rn < nr) { nx_i0 = iv.iv_off[rn]; nx_i1 = iv.iv_off[rn + 1]; nx_s0 = iv.smp_off[rn]; nx_s1 = iv.smp_off[rn + 1]; }
+    // transmittance at the entry of each interval, exp(-S_k)
     float carry = 0.f;
     for (uint32_t k0 = 0; k0 < meff; k0 += 64) {
       const uint32_t k = k0 + (uint32_t)lane;
-      const float tot = k < meff ? cum[(uint64_t)(i0 + k) * kBins + (kBins - 1)] : 0.f;
-      const float inc = wave_scan_incl(tot);
-      if (k < meff) sbuf[wave][k] = carry + (inc - tot);
+      const float tk = k0 == 0 ? tk0 : (k < meff ? tot[i0 + k] : 0.f);
+      const float inc = wave_scan_incl(tk);
+      if (k < meff) sbuf[wave][k] = exp_neg(carry + (inc - tk));
       carry += lane_value(inc, 63);
     }
     const float M = -expm1f(-carry);
@@ -569,41 +619,32 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
     uint32_t count = 0;
     uint64_t sel[4] = {0ull, 0ull, 0ull, 0ull};
     uint64_t first[4] = {0ull, 0ull, 0ull, 0ull};   // slots that start an interval
-    const uint32_t n = ns / meff;
     if (!fallback) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      // floor(x / n) = umulhi(x, m) with m = ceil(2^32 / n) for x < 2^16 and n >= 2 (the
-      // error x (m - 2^32/n) / 2^32 stays below 1/n, so it never carries into the integer part)
-      const uint32_t m32 = n > 1u ? 0xFFFFFFFFu / n + 1u : 0u;
-      auto div_n = [&](uint32_t x) { return n > 1u ? __umulhi(x, m32) : x; };
       const float inv_n = 1.f / (float)n;
-      const uint32_t nq = (ns + 63u) / 64u;
       float p[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if ((uint32_t)q >= nq) break;
         const uint32_t s = (uint32_t)lane + 64u * q;
-        const uint32_t sk = div_n(s);
-        const uint32_t j = s - sk * n;
+        const uint32_t sk = geo[q] & 255u, j = (geo[q] >> 8) & 255u;
         first[q] = __ballot(j == 0u);
         if (s >= ns) continue;
-        const uint32_t blo = div_n(32u * j);
-        const uint32_t bhi = div_n(32u * (j + 1) + n - 1) - 1u;
+        const uint32_t blo = (geo[q] >> 16) & 31u, bhi = geo[q] >> 24;
         const float u0 = (float)(32u * j) * inv_n, u1 = (float)(32u * (j + 1)) * inv_n;
-        const float* row = cum + (uint64_t)(i0 + sk) * kBins;
-        const float S = sbuf[wave][sk];
-        const float Plo0 = blo ? row[blo - 1] : 0.f, Plo = row[blo];
+        float v;
         if (bhi == blo) {
-          p[q] = 32.f * inv_n * exp_neg(S + Plo0) * one_minus_exp_neg(Plo - Plo0);
+          v = 32.f * inv_n * wlo[q];
         } else {
-          const float Phi0 = row[bhi - 1], Phi = row[bhi];
-          const float clo = (float)(blo + 1) - u0, chi = u1 - (float)bhi;
-          float v = clo * exp_neg(S + Plo0) * one_minus_exp_neg(Plo - Plo0);
-          if (bhi > blo + 1) v += exp_neg(S + Plo) * one_minus_exp_neg(Phi0 - Plo);
-          v += chi * exp_neg(S + Phi0) * one_minus_exp_neg(Phi - Phi0);
-          p[q] = fmaxf(v, 0.f);
+          v = ((float)(blo + 1) - u0) * wlo[q];
+#pragma unroll
+          for (int t = 0; t < kMid; ++t) v += wmid[q][t];
+          const float* row = wts + (uint64_t)(i0 + sk) * kBins;
+          for (uint32_t b = blo + 1u + kMid; b < bhi; ++b) v += row[b];   // slots wider than 5 bins
+          v += (u1 - (float)bhi) * whi[q];
         }
+        p[q] = sbuf[wave][sk] * v;
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -1056,7 +1097,7 @@ hipError_t launch_prop_pack(int dtype, const float* master, void* packed, hipStr
 
 hipError_t launch_prop_fwd(int dtype, const void* packed, const IvSet& iv, const float* o, const float* d,
                            int64_t stride, int64_t r0, const float* leafbox, int s_max, uint32_t n_iv_max,
-                           bool cum, float* tau, hipStream_t st) {
+                           bool cum, float* tau, float* tot, hipStream_t st) {
   int n = 0;
   hipError_t e = ncu(&n);
   if (e != hipSuccess) return e;
@@ -1065,14 +1106,15 @@ hipError_t launch_prop_fwd(int dtype, const void* packed, const IvSet& iv, const
   uint32_t grid = std::min<uint32_t>(tiles > 0 ? tiles : 1, (uint32_t)n * 8);
   if (dtype == AMNERF_BF16)
     hipLaunchKernelGGL(k_prop_fwd<true>, dim3(grid), dim3(kThreads), kBf16Bytes, st, (const uint8_t*)packed, iv, o,
-                       d, stride, r0, leafbox, s_max, cum ? 1 : 0, tau);
+                       d, stride, r0, leafbox, s_max, cum ? 1 : 0, tau, tot);
   else
     hipLaunchKernelGGL(k_prop_fwd<false>, dim3(grid), dim3(kThreads), kBiasBytes + kF32Units * kUnitBytes, st,
-                       (const uint8_t*)packed, iv, o, d, stride, r0, leafbox, s_max, cum ? 1 : 0, tau);
+                       (const uint8_t*)packed, iv, o, d, stride, r0, leafbox, s_max, cum ? 1 : 0, tau, tot);
   return hipGetLastError();
 }
 
-hipError_t launch_prop_select(uint32_t nr, const IvSet& iv, const float* tau, float mass_thresh, int cap,
+hipError_t launch_prop_select(uint32_t nr, const IvSet& iv, const float* wts, const float* tot, float mass_thresh,
+                              int cap,
                               uint32_t* runs, uint32_t* nsel, uint64_t* mask, float* mass, ChunkCounts* counts,
                               hipStream_t st) {
   if (nr == 0) return hipSuccess;
@@ -1080,7 +1122,7 @@ hipError_t launch_prop_select(uint32_t nr, const IvSet& iv, const float* tau, fl
   hipError_t e = ncu(&n);
   if (e != hipSuccess) return e;
   const uint32_t grid = std::min<uint32_t>((nr + 3) / 4, (uint32_t)n * 16);
-  hipLaunchKernelGGL(k_prop_select, dim3(grid), dim3(kThreads), 0, st, nr, iv, tau, mass_thresh, cap, runs, nsel,
+  hipLaunchKernelGGL(k_prop_select, dim3(grid), dim3(kThreads), 0, st, nr, iv, wts, tot, mass_thresh, cap, runs, nsel,
                      mask, mass, counts);
   return hipGetLastError();
 }
