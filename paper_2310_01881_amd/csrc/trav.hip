@@ -7,6 +7,8 @@
 // about 2^-46 relative.  Descent decisions therefore match a float64 traversal except on
 // rays that graze a split edge, and interval lengths (which weight densities in the
 // quadrature) keep float32 relative accuracy even far along the ray.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "devcommon.hpp"
 
@@ -48,11 +50,9 @@ __device__ __forceinline__ float axis_val(const float v[3], int a) { return a ==
 
 // Traverses one ray.  EMIT = false: returns the interval count, stopping once it exceeds
 // cap.  EMIT = true: writes the first `cap` intervals through the output pointers.
-template <bool EMIT, typename NodePtr>
-__device__ int traverse(NodePtr nodes, const float o[3], const float dir[3],
-                        int cap, uint32_t n_per, uint32_t ray, int* st_node, float* st_hi,
-                        float* st_lo, float* iv_t0, float* iv_dt, uint32_t* iv_key,
-                        uint32_t* iv_ray, uint32_t* iv_base, uint32_t smp_base) {
+template <bool EMIT, typename NodePtr, typename Put>
+__device__ int traverse(NodePtr nodes, const float o[3], const float dir[3], int cap, uint32_t n_per,
+                        int* st_node, float* st_hi, float* st_lo, Put put) {
   // root box [0,1]^3
   DF tin = {0.f, 0.f}, tout = {__builtin_inff(), 0.f};
   bool hit = true;
@@ -105,11 +105,7 @@ __device__ int traverse(NodePtr nodes, const float o[3], const float dir[3],
       if (m < cap) {
         float dh = t1.hi - t0.hi;
         float dt = dh + (t1.lo - t0.lo);
-        iv_t0[m] = t0.hi;
-        iv_dt[m] = dt;
-        iv_key[m] = (uint32_t)(-(info + 1)) | (n_per << 16);
-        iv_ray[m] = ray;
-        iv_base[m] = smp_base + (uint32_t)m * n_per;
+        put(m, t0.hi, dt, (uint32_t)(-(info + 1)) | (n_per << 16));
       }
     }
     ++m;
@@ -175,8 +171,8 @@ __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict
   int m = 0;
   // skip the descent for a wave whose rays are all out of range
   if (__ballot(live) != 0 && live)
-    m = traverse<false>(tl.nodes, oo, dd, s_max, 0, 0, tl.st_node, tl.st_hi, tl.st_lo, nullptr, nullptr, nullptr,
-                        nullptr, nullptr, 0);
+    m = traverse<false>(tl.nodes, oo, dd, s_max, 0, tl.st_node, tl.st_hi, tl.st_lo,
+                        [](int, float, float, uint32_t) {});
   if (live) {
     uint32_t meff = m <= s_max ? (uint32_t)m : (uint32_t)s_max;
     uint32_t nper = m == 0 ? 0u : (m <= s_max ? (uint32_t)(s_max / m) : 1u);
@@ -185,9 +181,14 @@ __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict
   }
 }
 
+// Emission: the block's rays are consecutive, so its intervals fill one contiguous range of
+// the output.  Each lane puts its intervals into an LDS copy of the first `stage_n` entries
+// of that range (entries past it go straight to memory), and the block then writes the
+// staged entries out with consecutive threads on consecutive entries, so every cache line
+// is written whole at once instead of piecewise by lanes that finish at different times.
 template <bool LDS>
 __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict__ nodes, uint32_t n_nodes,
-                                                      int stack_n, const float* __restrict__ o,
+                                                      int stack_n, uint32_t stage_n, const float* __restrict__ o,
                                                       const float* __restrict__ d, int64_t stride,
                                                       int64_t r0, uint32_t nr,
                                                       const uint32_t* __restrict__ cnt_iv,
@@ -201,19 +202,48 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
                                                       uint32_t* __restrict__ iv_base) {
   extern __shared__ __align__(16) uint8_t dyn[];
   const TravLds tl = stage<LDS>(nodes, n_nodes, stack_n, dyn);
-  uint32_t r = blockIdx.x * kBlock + threadIdx.x;
-  uint32_t meff = r < nr ? cnt_iv[r] : 0u;
-  if (__ballot(meff != 0) == 0 || meff == 0) return;
-  float oo[3], dd[3];
+  uint8_t* sp = dyn + trav_lds_bytes(LDS, n_nodes, stack_n);
+  float* s_t0 = reinterpret_cast<float*>(sp);
+  float* s_dt = s_t0 + stage_n;
+  uint32_t* s_key = reinterpret_cast<uint32_t*>(s_dt + stage_n);
+  uint32_t* s_ray = s_key + stage_n;
+  uint32_t* s_base = s_ray + stage_n;
+  const uint32_t rb = blockIdx.x * kBlock;                      // first ray of the block
+  const uint32_t re = rb + kBlock < nr ? rb + kBlock : nr;      // one past its last ray
+  const uint32_t b0 = iv_off[rb], b1 = iv_off[re];              // the block's output range
+  const uint32_t r = rb + threadIdx.x;
+  const uint32_t meff = r < nr ? cnt_iv[r] : 0u;
+  if (__ballot(meff != 0) != 0 && meff != 0) {
+    float oo[3], dd[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    oo[a] = o[a * stride + r0 + r];
-    dd[a] = d[a * stride + r0 + r];
+    for (int a = 0; a < 3; ++a) {
+      oo[a] = o[a * stride + r0 + r];
+      dd[a] = d[a * stride + r0 + r];
+    }
+    const uint32_t nper = cnt_smp[r] / meff;
+    const uint32_t pos0 = iv_off[r] - b0;
+    const uint32_t base = smp_off[r];
+    traverse<true>(tl.nodes, oo, dd, (int)meff, nper, tl.st_node, tl.st_hi, tl.st_lo,
+                   [&](int m, float t0, float dt, uint32_t key) {
+                     const uint32_t q = pos0 + (uint32_t)m;
+                     const uint32_t smp = base + (uint32_t)m * nper;
+                     if (q < stage_n) {
+                       s_t0[q] = t0; s_dt[q] = dt; s_key[q] = key; s_ray[q] = r; s_base[q] = smp;
+                     } else {
+                       iv_t0[b0 + q] = t0; iv_dt[b0 + q] = dt; iv_key[b0 + q] = key; iv_ray[b0 + q] = r;
+                       iv_base[b0 + q] = smp;
+                     }
+                   });
   }
-  uint32_t nper = cnt_smp[r] / meff;
-  uint32_t base = iv_off[r];
-  traverse<true>(tl.nodes, oo, dd, (int)meff, nper, r, tl.st_node, tl.st_hi, tl.st_lo, iv_t0 + base, iv_dt + base,
-                 iv_key + base, iv_ray + base, iv_base + base, smp_off[r]);
+  __syncthreads();
+  const uint32_t n = b1 - b0 < stage_n ? b1 - b0 : stage_n;
+  for (uint32_t q = threadIdx.x; q < n; q += kBlock) {
+    iv_t0[b0 + q] = s_t0[q];
+    iv_dt[b0 + q] = s_dt[q];
+    iv_key[b0 + q] = s_key[q];
+    iv_ray[b0 + q] = s_ray[q];
+    iv_base[b0 + q] = s_base[q];
+  }
 }
 
 }  // namespace
@@ -260,14 +290,20 @@ hipError_t launch_trav_emit(const DevNode* nodes, uint32_t n_nodes, int depth, c
   if (e != hipSuccess) return e;
   const int stack_n = depth + 1;
   const uint32_t grid = (nr + kBlock - 1) / kBlock;
-  if (n_nodes <= (uint32_t)kLdsNodes)
-    hipLaunchKernelGGL(k_trav_emit<true>, dim3(grid), dim3(kBlock), trav_lds_bytes(true, n_nodes, stack_n), st, nodes,
-                       n_nodes, stack_n, o, d, ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt,
-                       iv_key, iv_ray, iv_base);
+  const bool lds = n_nodes <= (uint32_t)kLdsNodes;
+  // staging sized so that two blocks still fit in a CU's 160 KiB of LDS (the traversal
+  // needs the occupancy), at most 2048 entries of 20 bytes
+  const uint32_t fixed = trav_lds_bytes(lds, n_nodes, stack_n);
+  const uint32_t budget = 80u * 1024u;
+  uint32_t stage_n = fixed + 20u * 256u <= budget ? (budget - fixed) / 20u : 256u;
+  stage_n = std::min<uint32_t>(stage_n, 2048u) & ~63u;
+  const uint32_t bytes = fixed + 20u * stage_n;
+  if (lds)
+    hipLaunchKernelGGL(k_trav_emit<true>, dim3(grid), dim3(kBlock), bytes, st, nodes, n_nodes, stack_n, stage_n, o, d,
+                       ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base);
   else
-    hipLaunchKernelGGL(k_trav_emit<false>, dim3(grid), dim3(kBlock), trav_lds_bytes(false, n_nodes, stack_n), st,
-                       nodes, n_nodes, stack_n, o, d, ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0,
-                       iv_dt, iv_key, iv_ray, iv_base);
+    hipLaunchKernelGGL(k_trav_emit<false>, dim3(grid), dim3(kBlock), bytes, st, nodes, n_nodes, stack_n, stage_n, o,
+                       d, ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base);
   return hipGetLastError();
 }
 
