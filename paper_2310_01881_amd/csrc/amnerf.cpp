@@ -690,8 +690,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
     auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev->ev[k], st) : hipSuccess; };
     HIP_TRY(mark(0));
     HIP_TRY(launch_trav_count(tree->dev_nodes, (uint32_t)tree->mass.size(), tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, p->s_max, w.cnt_iv, w.cnt_smp, st));
-    HIP_TRY(launch_scan_u32(w.cnt_iv, w.iv_off, nr, nullptr, w.scan_tmp, st));
-    HIP_TRY(launch_scan_u32(w.cnt_smp, w.smp_off, nr, nullptr, w.scan_tmp, st));
+    HIP_TRY(launch_scan_u32_pair(w.cnt_iv, w.iv_off, w.cnt_smp, w.smp_off, nr, w.scan_tmp, st));
     HIP_TRY(launch_trav_emit(tree->dev_nodes, (uint32_t)tree->mass.size(), tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
                              w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, st));
     HIP_TRY(mark(1));
@@ -717,8 +716,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
                               p->s_max, niv_plain, true, pw.wts, pw.tot, st));
       HIP_TRY(launch_prop_select(nr, plain, pw.wts, pw.tot, q->mass_thresh, q->cap, pw.runs, pw.nsel, pw.mask, nullptr,
                                  ctx->counts, st));
-      HIP_TRY(launch_scan_u32(pw.runs, pw.pv_off, nr, nullptr, pw.scan_tmp, st));
-      HIP_TRY(launch_scan_u32(pw.nsel, pw.ps_off, nr, nullptr, pw.scan_tmp, st));
+      HIP_TRY(launch_scan_u32_pair(pw.runs, pw.pv_off, pw.nsel, pw.ps_off, nr, pw.scan_tmp, st));
       HIP_TRY(launch_prop_emit(nr, plain, pw.mask, pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, st));
       use = {pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, pw.pv_off + nr};
       spu = spp;

@@ -78,6 +78,10 @@ __device__ __forceinline__ uint32_t find_interval(const uint32_t* __restrict__ b
 size_t scan_tmp_words(uint64_t n_cap);
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n_cap,
                            const uint32_t* n_dev, uint32_t* tmp, hipStream_t st);
+// Exclusive scans of two uint32 arrays of the same length n_cap at once (out_x[n_cap] = the
+// totals), each total below 2^32; tmp as above, 8-byte aligned.
+hipError_t launch_scan_u32_pair(const uint32_t* in_a, uint32_t* out_a, const uint32_t* in_b, uint32_t* out_b,
+                                uint64_t n_cap, uint32_t* tmp, hipStream_t st);
 
 // ---- sort by leaf slot (Section 3.5: sort, then infer per node) ------------------------
 struct SortPlan {

@@ -15,20 +15,42 @@ __device__ __forceinline__ uint64_t scan_n(uint64_t n_cap, const uint32_t* n_dev
   return n < n_cap ? n : n_cap;
 }
 
+// Elements are uint32 (one array) or, for a pair of arrays scanned together, uint64 with
+// the first array in the high and the second in the low half: the sums of both stay below
+// 2^32 (a pass holds at most 2^28 samples), so the halves never carry into each other.
+template <bool PAIR>
+struct Elem {
+  typedef uint32_t T;
+  __device__ static T load(const uint32_t* a, const uint32_t*, uint64_t i) { return a[i]; }
+  __device__ static void store(uint32_t* a, uint32_t*, uint64_t i, T v) { a[i] = v; }
+};
+template <>
+struct Elem<true> {
+  typedef uint64_t T;
+  __device__ static T load(const uint32_t* a, const uint32_t* b, uint64_t i) {
+    return ((uint64_t)a[i] << 32) | b[i];
+  }
+  __device__ static void store(uint32_t* a, uint32_t* b, uint64_t i, T v) {
+    a[i] = (uint32_t)(v >> 32);
+    b[i] = (uint32_t)v;
+  }
+};
+
 // Inclusive scan of one value per thread across a 256-thread block; returns the block total.
-__device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* sh_wave, uint32_t& incl) {
+template <typename T>
+__device__ __forceinline__ T block_incl_scan(T v, T* sh_wave, T& incl) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
-    uint32_t y = __shfl_up(v, off, 64);
+    T y = __shfl_up(v, off, 64);
     if (lane >= off) v += y;
   }
   if (lane == 63) sh_wave[wave] = v;
   __syncthreads();
-  uint32_t pre = 0, tot = 0;
+  T pre = 0, tot = 0;
 #pragma unroll
   for (int w = 0; w < kThreads / 64; ++w) {
-    uint32_t s = sh_wave[w];
+    T s = sh_wave[w];
     if (w < wave) pre += s;
     tot += s;
   }
@@ -37,48 +59,52 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* sh_wav
   return tot;
 }
 
+template <bool PAIR>
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                          const uint32_t* __restrict__ in2,
                                                           uint64_t n_cap, const uint32_t* n_dev,
-                                                          uint32_t* __restrict__ bsum) {
-  __shared__ uint32_t sh[kThreads / 64];
+                                                          typename Elem<PAIR>::T* __restrict__ bsum) {
+  typedef typename Elem<PAIR>::T T;
+  __shared__ T sh[kThreads / 64];
   const uint64_t n = scan_n(n_cap, n_dev);
   const uint64_t nb = (n + kScanItems - 1) / kScanItems;
   for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     uint64_t base = b * kScanItems + (uint64_t)threadIdx.x * kPer;
-    uint32_t s = 0;
+    T s = 0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i)
-      if (base + i < n) s += in[base + i];
-    uint32_t incl;
-    uint32_t tot = block_incl_scan(s, sh, incl);
+      if (base + i < n) s += Elem<PAIR>::load(in, in2, base + i);
+    T incl;
+    T tot = block_incl_scan<T>(s, sh, incl);
     if (threadIdx.x == 0) bsum[b] = tot;
   }
 }
 
 // Single block: exclusive scan of the block sums in place; writes the grand total to out[n].
-__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* __restrict__ bsum, uint64_t n_cap,
-                                                      const uint32_t* n_dev,
-                                                      uint32_t* __restrict__ out) {
-  __shared__ uint32_t sh[1024 / 64];
-  __shared__ uint32_t carry_sh;
+template <bool PAIR>
+__global__ __launch_bounds__(1024) void k_scan_blocks(typename Elem<PAIR>::T* __restrict__ bsum, uint64_t n_cap,
+                                                      const uint32_t* n_dev, uint32_t* __restrict__ out,
+                                                      uint32_t* __restrict__ out2) {
+  typedef typename Elem<PAIR>::T T;
+  __shared__ T sh[1024 / 64];
   const uint64_t n = scan_n(n_cap, n_dev);
   const uint64_t nb = (n + kScanItems - 1) / kScanItems;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t carry = 0;
+  T carry = 0;
   for (uint64_t c = 0; c < nb; c += 1024) {
     uint64_t i = c + threadIdx.x;
-    uint32_t v = i < nb ? bsum[i] : 0u;
-    uint32_t x = v;
+    T v = i < nb ? bsum[i] : (T)0;
+    T x = v;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      uint32_t y = __shfl_up(x, off, 64);
+      T y = __shfl_up(x, off, 64);
       if (lane >= off) x += y;
     }
     if (lane == 63) sh[wave] = x;
     __syncthreads();
-    uint32_t pre = 0, tot = 0;
+    T pre = 0, tot = 0;
     for (int w = 0; w < 16; ++w) {
-      uint32_t s = sh[w];
+      T s = sh[w];
       if (w < wave) pre += s;
       tot += s;
     }
@@ -86,34 +112,34 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* __restrict__ bsu
     carry += tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    out[n] = carry;
-    carry_sh = carry;
-  }
+  if (threadIdx.x == 0) Elem<PAIR>::store(out, out2, n, carry);
 }
 
+template <bool PAIR>
 __global__ __launch_bounds__(kThreads) void k_scan_final(const uint32_t* __restrict__ in,
-                                                         uint32_t* __restrict__ out, uint64_t n_cap,
-                                                         const uint32_t* n_dev,
-                                                         const uint32_t* __restrict__ bsum) {
-  __shared__ uint32_t sh[kThreads / 64];
+                                                         const uint32_t* __restrict__ in2,
+                                                         uint32_t* __restrict__ out, uint32_t* __restrict__ out2,
+                                                         uint64_t n_cap, const uint32_t* n_dev,
+                                                         const typename Elem<PAIR>::T* __restrict__ bsum) {
+  typedef typename Elem<PAIR>::T T;
+  __shared__ T sh[kThreads / 64];
   const uint64_t n = scan_n(n_cap, n_dev);
   const uint64_t nb = (n + kScanItems - 1) / kScanItems;
   for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     uint64_t base = b * kScanItems + (uint64_t)threadIdx.x * kPer;
-    uint32_t v[kPer];
-    uint32_t s = 0;
+    T v[kPer];
+    T s = 0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-      v[i] = base + i < n ? in[base + i] : 0u;
+      v[i] = base + i < n ? Elem<PAIR>::load(in, in2, base + i) : (T)0;
       s += v[i];
     }
-    uint32_t incl;
-    block_incl_scan(s, sh, incl);
-    uint32_t run = bsum[b] + incl - s;
+    T incl;
+    block_incl_scan<T>(s, sh, incl);
+    T run = bsum[b] + incl - s;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-      if (base + i < n) out[base + i] = run;
+      if (base + i < n) Elem<PAIR>::store(out, out2, base + i, run);
       run += v[i];
     }
   }
@@ -121,15 +147,29 @@ __global__ __launch_bounds__(kThreads) void k_scan_final(const uint32_t* __restr
 
 }  // namespace
 
-size_t scan_tmp_words(uint64_t n_cap) { return (n_cap + kScanItems - 1) / kScanItems + 1; }
+// Block sums of up to 64 bits each, plus the total.
+size_t scan_tmp_words(uint64_t n_cap) { return 2 * ((n_cap + kScanItems - 1) / kScanItems + 1); }
 
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n_cap, const uint32_t* n_dev,
                            uint32_t* tmp, hipStream_t st) {
   uint64_t nb = (n_cap + kScanItems - 1) / kScanItems;
   uint32_t grid = (uint32_t)(nb < kMaxGrid ? (nb > 0 ? nb : 1) : kMaxGrid);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(kThreads), 0, st, in, n_cap, n_dev, tmp);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, tmp, n_cap, n_dev, out);
-  hipLaunchKernelGGL(k_scan_final, dim3(grid), dim3(kThreads), 0, st, in, out, n_cap, n_dev, tmp);
+  hipLaunchKernelGGL(k_scan_reduce<false>, dim3(grid), dim3(kThreads), 0, st, in, nullptr, n_cap, n_dev, tmp);
+  hipLaunchKernelGGL(k_scan_blocks<false>, dim3(1), dim3(1024), 0, st, tmp, n_cap, n_dev, out, nullptr);
+  hipLaunchKernelGGL(k_scan_final<false>, dim3(grid), dim3(kThreads), 0, st, in, nullptr, out, nullptr, n_cap, n_dev,
+                     tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_u32_pair(const uint32_t* in_a, uint32_t* out_a, const uint32_t* in_b, uint32_t* out_b,
+                                uint64_t n_cap, uint32_t* tmp, hipStream_t st) {
+  uint64_t nb = (n_cap + kScanItems - 1) / kScanItems;
+  uint32_t grid = (uint32_t)(nb < kMaxGrid ? (nb > 0 ? nb : 1) : kMaxGrid);
+  uint64_t* t64 = reinterpret_cast<uint64_t*>(tmp);
+  hipLaunchKernelGGL(k_scan_reduce<true>, dim3(grid), dim3(kThreads), 0, st, in_a, in_b, n_cap, nullptr, t64);
+  hipLaunchKernelGGL(k_scan_blocks<true>, dim3(1), dim3(1024), 0, st, t64, n_cap, nullptr, out_a, out_b);
+  hipLaunchKernelGGL(k_scan_final<true>, dim3(grid), dim3(kThreads), 0, st, in_a, in_b, out_a, out_b, n_cap, nullptr,
+                     t64);
   return hipGetLastError();
 }
 
