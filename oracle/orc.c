@@ -853,10 +853,14 @@ static void plan_ray(const otree* T, const double* PP, const double o[3], const 
     for (int b = 0; b < PROP_BINS; ++b) {
       double w = exp(-S) * (-expm1(-tau[b]));
       S += tau[b];
-      /* spread the bin's weight over the plain slots it overlaps */
+      /* spread the bin's weight over the plain slots it overlaps: in units of 1/(32 n) of
+         the interval, slot j is [32 j, 32 (j+1)) and bin b is [b n, (b+1) n), so the covered
+         fraction of the bin is an integer over n (slots inside one bin get exactly equal
+         weights, which the selection must see as ties) */
       for (int j = 0; j < n; ++j) {
-        double ov = overlap((double)j / n, (double)(j + 1) / n, (double)b / PROP_BINS, (double)(b + 1) / PROP_BINS);
-        p[k * n + j] += w * ov * PROP_BINS;
+        int lo = PROP_BINS * j > b * n ? PROP_BINS * j : b * n;
+        int hi = PROP_BINS * (j + 1) < (b + 1) * n ? PROP_BINS * (j + 1) : (b + 1) * n;
+        if (hi > lo) p[k * n + j] += w * ((double)(hi - lo) / n);
       }
     }
   }

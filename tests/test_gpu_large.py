@@ -82,3 +82,41 @@ def test_c3_fp8_full_camera_in_two_passes(scene):
           "quantisation alone %.2f dB" % (p_q, p_full, p_oq), flush=True)
     assert p_q > 45.0
     assert p_full > p_oq - 1.0
+
+
+def test_c3_thirty_cameras_in_one_call(scene):
+    """The benchmark's launch: 30 cameras (62.2 M rays) in one call with float8 weights, 45
+    passes of at most 2^28 / S_max rays; 1 500 rays sampled across all cameras and passes
+    against the oracle on the dequantised weights."""
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_FP8)
+    cams = synth.make_cameras(cfg.n_cameras, cfg.seed_cameras, cfg.width, cfg.height)
+    R1 = cfg.width * cfg.height
+    R = R1 * len(cams)
+    o_all = torch.empty((3, R), dtype=torch.float32, device="cuda:0")
+    d_all = torch.empty((3, R), dtype=torch.float32, device="cuda:0")
+    rng = np.random.default_rng(8)
+    pick = np.sort(rng.choice(R, 1500, replace=False))
+    o_pick = np.zeros((3, pick.size), np.float32)
+    d_pick = np.zeros((3, pick.size), np.float32)
+    for i, c in enumerate(cams):
+        o, d = synth.camera_rays(c)
+        o_all[:, i * R1:(i + 1) * R1] = torch.from_numpy(o).to("cuda:0")
+        d_all[:, i * R1:(i + 1) * R1] = torch.from_numpy(d).to("cuda:0")
+        sel = (pick >= i * R1) & (pick < (i + 1) * R1)
+        o_pick[:, sel] = o[:, pick[sel] - i * R1]
+        d_pick[:, sel] = d[:, pick[sel] - i * R1]
+    print("c3 30 cameras: rays", R, flush=True)
+    out = am.render(ctx, tree, mlp, o_all, d_all, S_MAX, ert_eps=cfg.ert_eps)
+    torch.cuda.synchronize()
+    st = am.amnerf_render_stats_get(ctx.h)
+    print("c3 30 cameras stats", st, flush=True)
+    assert st["n_chunks"] == -(-R // ((1 << 28) // S_MAX)) and st["n_nonfinite"] == 0
+    g = out["rgb"][torch.from_numpy(pick).to("cuda:0")].cpu().numpy()
+    _, _, deq = fp8.quantise(scene.W, cfg.n_hidden, cfg.hidden)
+    rgb_q, _, _, _, _ = oracle.render(scene.otree, deq.astype(np.float32), cfg.n_hidden, cfg.hidden, o_pick, d_pick,
+                                      S_MAX, eps=cfg.ert_eps)
+    p_q = oracle.psnr(g, rgb_q)
+    print("c3 30 cameras fp8: psnr vs oracle(dequantised) %.2f dB on %d rays of %d cameras" % (
+        p_q, pick.size, len(np.unique(pick // R1))), flush=True)
+    assert p_q > 45.0

@@ -73,23 +73,34 @@ def test_all_fallback_is_bit_identical_to_plain():
     assert fb[3]["n_fallback"] == int((ray_sample_counts(ctx, o.shape[1]) > 0).sum())
 
 
-def test_planned_render_matches_oracle():
+@pytest.mark.parametrize("case", ["small_s64", "small_s160", "small_s255", "large_subset"])
+def test_planned_render_matches_oracle(case):
     """An untrained proposal with a low mass threshold plans for many rays: compare per-ray
-    sample counts with the oracle's plans and the rendered colours where the plans agree."""
-    cfg = synth.C1
+    sample counts with the oracle's plans and the rendered colours where the plans agree.
+    S_max 160 and 255 give rays of up to 192 and 256 slots (three and four registers of the
+    selection's sort); the large scene is checked on 20 000 random pixels of one camera."""
+    if case == "large_subset":
+        cfg, s_max, thresh, cap = synth.C3, synth.C3.s_max, 0.5, 48
+    else:
+        cfg, s_max = synth.C1, int(case.split("_s")[1])
+        thresh, cap = (0.5, 40) if s_max == 64 else (0.6, 48)
+    print("planned render case", case, flush=True)
     scene, ctx, tree, mlp, prop, prop_w = setup(cfg)
     o, d = scene.camera_rays()
+    if case == "large_subset":
+        pick = np.sort(np.random.default_rng(11).choice(o.shape[1], 20_000, replace=False))
+        o, d = np.ascontiguousarray(o[:, pick]), np.ascontiguousarray(d[:, pick])
     R = o.shape[1]
-    thresh, cap = 0.5, 40
     desc = prop.descriptor(am.AMNERF_F32, mass_thresh=thresh, cap=cap)
-    rgb, dep, op, st = render(ctx, tree, mlp, o, d, cfg.s_max, proposal=desc)
+    rgb, dep, op, st = render(ctx, tree, mlp, o, d, s_max, proposal=desc)
     counts = ray_sample_counts(ctx, R)
-    orgb, odep, oop, ons, opn, opsel, omass = oracle.render_proposal(scene.otree, scene.W, 2, 32, prop_w, o, d,
-                                                                     cfg.s_max, eps=1e-4, mass_thresh=thresh, cap=cap)
+    orgb, odep, oop, ons, opn, opsel, omass = oracle.render_proposal(scene.otree, scene.W, cfg.n_hidden, cfg.hidden,
+                                                                     prop_w, o, d, s_max, eps=1e-4,
+                                                                     mass_thresh=thresh, cap=cap)
     same = counts == ons
     planned = opn > 0
-    print("plans: %d planned rays, %d fallback (gpu %d), counts agree on %.4f of rays" % (
-        planned.sum(), (opn < 0).sum(), st["n_fallback"], same.mean()))
+    print("plans: %d planned rays, %d fallback (gpu %d), counts agree on %.4f of rays, max plan %d slots" % (
+        planned.sum(), (opn < 0).sum(), st["n_fallback"], same.mean(), opn.max()))
     assert planned.sum() > 0.2 * R
     assert same.mean() >= 0.97
     ok = same & ~np.isin(np.arange(R), np.where(np.abs(omass - thresh) < 1e-4)[0])
@@ -97,6 +108,12 @@ def test_planned_render_matches_oracle():
     print("planned render: max |rgb - oracle| on agreeing rays %.3e" % err)
     assert err <= 1e-4
     assert st["n_samples"] < st["n_plain_samples"]
+    if s_max > 128:
+        # some planned rays chose from more than 128 slots (the sort's wider forms ran)
+        m = oracle.trace(scene.otree, o, d, cap=s_max + 1)[3]
+        slots = np.where(m > 0, np.minimum(m, s_max) * np.maximum(s_max // np.maximum(m, 1), 1), 0)
+        print("planned rays with more than 128 slots: %d" % int((planned & (slots > 128)).sum()))
+        assert (planned & (slots > 128)).sum() > 0
 
 
 def test_training_step_gradient_matches_oracle():
