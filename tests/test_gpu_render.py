@@ -245,3 +245,41 @@ def test_c2_bf16_error_report():
     psnr = oracle.psnr(g, rgb)
     print("c2 bf16 psnr vs oracle %.2f dB, max abs %.3e" % (psnr, np.abs(g - rgb).max()))
     assert psnr > 35.0
+
+
+@pytest.mark.parametrize("n_hidden,hidden", [(1, 32), (3, 64), (5, 32), (8, 64)])
+def test_mlp_shapes(n_hidden, hidden):
+    """Every hidden-layer count the kernels unroll differently (none, odd, even, the maximum):
+    float32 per-sample outputs against the oracle's per-sample record, and the bf16 and e4m3
+    renders against the oracle (the latter on its dequantised weights)."""
+    from oracle import fp8
+    cfg = synth.scaled(synth.C1, n_hidden=n_hidden, hidden=hidden)
+    scene = Scene(cfg)
+    o, d = scene.camera_rays()
+    R = o.shape[1]
+    print("mlp shape %dx%d" % (n_hidden, hidden), flush=True)
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    render_all(scene, ctx, tree, mlp, o, d, cfg.s_max)
+    st, ins = fetch_inspect(ctx, R, tree.n_leaves)
+    smp_off = ins["ray_smp_off"].astype(np.int64)
+    rng = np.random.default_rng(n_hidden)
+    for r in rng.choice(R, 60, replace=False):
+        rec = oracle.ray_samples(scene.otree, scene.W, n_hidden, hidden, o, d, r, cfg.s_max, eps=0.0)
+        z = ins["sample_out"][smp_off[r]:smp_off[r + 1]].astype(np.float64)
+        assert len(z) == len(rec["t"])
+        if len(z) == 0:
+            continue
+        g = np.concatenate([np.logaddexp(0, z[:, :1]), 1 / (1 + np.exp(-z[:, 1:]))], axis=1)
+        np.testing.assert_allclose(g[:, 0], rec["sigma"], rtol=2e-5, atol=2e-5)
+        np.testing.assert_allclose(g[:, 1:], rec["rgb"], rtol=0, atol=1e-5)
+    rays = np.sort(rng.choice(R, 800, replace=False))
+    ref, _, _, _, _ = oracle.render(scene.otree, scene.W, n_hidden, hidden, o, d, cfg.s_max, eps=1e-4, ray_idx=rays)
+    _, _, deq = fp8.quantise(scene.W, n_hidden, hidden)
+    ref8, _, _, _, _ = oracle.render(scene.otree, deq.astype(np.float32), n_hidden, hidden, o, d, cfg.s_max,
+                                     eps=1e-4, ray_idx=rays)
+    for dtype, want in ((am.AMNERF_BF16, ref), (am.AMNERF_FP8, ref8)):
+        m2 = am.Mlp(ctx, mlp.master, n_hidden, hidden, dtype, tree.n_leaves)
+        out = render_all(scene, ctx, tree, m2, o, d, cfg.s_max)
+        psnr = oracle.psnr(out["rgb"].cpu().numpy()[rays], want)
+        print("  dtype %d: psnr %.2f dB" % (dtype, psnr), flush=True)
+        assert psnr > 50.0   # measured 62-69 dB
