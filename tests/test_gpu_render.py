@@ -54,7 +54,7 @@ def fetch_inspect(ctx, R, n_leaves):
     return st, out
 
 
-def check_intervals_and_sort(scene, o, d, s_max, ins, rays_to_check):
+def check_intervals_and_sort(scene, o, d, s_max, ins, rays_to_check, max_nonrobust=0.01):
     """Node ids bit-exact on robust rays; perm and bucket offsets bit-exact everywhere."""
     R = o.shape[1]
     t0, t1, slot, m = oracle.trace(scene.otree, o, d, ray_idx=rays_to_check)
@@ -74,7 +74,7 @@ def check_intervals_and_sort(scene, o, d, s_max, ins, rays_to_check):
         if meff:
             n = s_max // m[q] if m[q] <= s_max else 1
             assert np.all(ins["iv_n"][a:b] == n)
-    assert n_nonrobust <= max(2, 0.01 * len(rays_to_check))
+    assert n_nonrobust <= max(2, max_nonrobust * len(rays_to_check))
     # the sort: ray-major sample keys expanded from intervals, stably sorted
     keys = np.repeat(ins["iv_slot"], ins["iv_n"])
     counts, offsets, perm = oracle.buckets(keys, scene.otree.n_leaves)
@@ -86,7 +86,7 @@ def check_intervals_and_sort(scene, o, d, s_max, ins, rays_to_check):
 
 
 def compare_render(scene, out, o, d, s_max, rays_to_check, robust, tol_rgb=TOL_RGB, tol_depth=TOL_DEPTH,
-                   jitter=False, seed=0):
+                   jitter=False, seed=0, min_ok=0.98):
     cfg = scene.cfg
     rgb, dep, op, ns, flags = oracle.render(scene.otree, scene.W, cfg.n_hidden, cfg.hidden, o, d, s_max,
                                             eps=cfg.ert_eps, ray_idx=rays_to_check, jitter=jitter, seed=seed)
@@ -94,7 +94,7 @@ def compare_render(scene, out, o, d, s_max, rays_to_check, robust, tol_rgb=TOL_R
     g_dep = out["depth"].cpu().numpy()[rays_to_check]
     g_op = out["opacity"].cpu().numpy()[rays_to_check]
     ok = robust & ((flags & oracle.FLAG_ERT_AMBIGUOUS) == 0)
-    assert ok.mean() > 0.98
+    assert ok.mean() > min_ok
     e_rgb = np.abs(g_rgb - rgb)[ok].max()
     e_op = np.abs(g_op - op)[ok].max()
     e_dep = np.abs(g_dep - dep)[ok].max()
@@ -283,3 +283,36 @@ def test_mlp_shapes(n_hidden, hidden):
         psnr = oracle.psnr(out["rgb"].cpu().numpy()[rays], want)
         print("  dtype %d: psnr %.2f dB" % (dtype, psnr), flush=True)
         assert psnr > 50.0   # measured 62-69 dB
+
+
+def test_axis_parallel_and_inside_rays():
+    """Rays along the axes (zero direction components), from outside and from inside the box,
+    some on cell planes: intervals, sort and float32 render against the oracle."""
+    scene = Scene(synth.scaled(synth.C1, max_depth=6, max_leaves=40))
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    rng = np.random.default_rng(21)
+    os_, ds_ = [], []
+    for a in range(3):
+        for sgn in (1.0, -1.0):
+            for inside in (False, True):
+                n = 200
+                o = rng.uniform(0.02, 0.98, (3, n))
+                if not inside:
+                    o[a] = -0.5 if sgn > 0 else 1.5
+                if inside:
+                    o[:, :20] = np.round(o[:, :20] * 32) / 32      # on cell planes
+                d = np.zeros((3, n))
+                d[a] = sgn
+                os_.append(o)
+                ds_.append(d)
+    o = np.ascontiguousarray(np.concatenate(os_, axis=1).astype(np.float32))
+    d = np.ascontiguousarray(np.concatenate(ds_, axis=1).astype(np.float32))
+    R = o.shape[1]
+    out = render_all(scene, ctx, tree, mlp, o, d, 64)
+    st, ins = fetch_inspect(ctx, R, tree.n_leaves)
+    rays = np.arange(R)
+    # a tenth of the rays start on cell planes, so a few percent graze a split
+    robust = check_intervals_and_sort(scene, o, d, 64, ins, rays, max_nonrobust=0.05)
+    print("axis-parallel rays: %d, robust %d, samples %d" % (R, robust.sum(), st["n_samples"]))
+    assert st["n_samples"] > 0
+    compare_render(scene, out, o, d, 64, rays, robust, min_ok=0.9)
