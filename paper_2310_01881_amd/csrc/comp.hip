@@ -73,8 +73,10 @@ __device__ __forceinline__ float wave_sum(float v) { return lane_value(wave_scan
 // tau_j, then S_j = sum_{i<j} tau_i by a compensated (float pair) prefix scan across the
 // wave plus the running total of earlier steps; T_j = exp(-S_j), w_j = T_j (1 - e^-tau_j).
 // Early termination: the first lane whose T_{j+1} < eps keeps its sample and later lanes
-// (and steps) contribute nothing.  Lane j finds its interval by binary search over the
-// intervals' first-sample indices.
+// (and steps) contribute nothing.  T_j is the neighbouring lane's T_{j+1} (the exclusive
+// sum of lane j is the inclusive sum of lane j - 1), so one exponential per sample serves
+// both.  Lane j finds its interval by binary search over the intervals' first-sample
+// indices.
 constexpr uint32_t kStage = 256;   // intervals of a ray searched in LDS (more: in memory)
 
 __global__ __launch_bounds__(kThreads) void k_composite(
@@ -129,11 +131,12 @@ __global__ __launch_bounds__(kThreads) void k_composite(
       }
       // inclusive compensated scan of tau across the wave; exclusive = shifted by one lane
       const DF inc = df_scan_incl({tau, 0.f});
-      const DF exc = df_shift<0x138, 0xF>(inc);   // wave_shr:1, lane 0 reads (0, 0)
-      const DF S = df_add(carry, exc);
       const DF Sn = df_add(carry, inc);
-      float w = valid ? df_exp_neg(S) * one_minus_exp_neg(tau) : 0.f;
-      const bool stop = valid && eps > 0.f && df_exp_neg(Sn) < eps;
+      const float Tn = df_exp_neg(Sn);                        // T_{j+1}
+      const float Tsh = dpp_or_zero<0x138, 0xF>(Tn);          // wave_shr:1: lane j - 1's T_j
+      const float T = lane == 0 ? df_exp_neg(carry) : Tsh;
+      float w = valid ? T * one_minus_exp_neg(tau) : 0.f;
+      const bool stop = valid && eps > 0.f && Tn < eps;
       const uint64_t stops = __ballot(stop);
       if (stops) {
         const int first = __ffsll((unsigned long long)stops) - 1;

@@ -52,6 +52,22 @@ __device__ __forceinline__ float wave_scan_incl(float v) {
   return v;
 }
 
+// Prefix maximum over the 64 lanes of a wave (signed), on the same lane-shift pattern as
+// wave_scan_incl; lanes outside the pattern contribute INT32_MIN.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_or_min(int v) {
+  return __builtin_amdgcn_update_dpp((int)0x80000000, v, CTRL, ROW_MASK, 0xF, false);
+}
+__device__ __forceinline__ int wave_max_incl(int v) {
+  v = max(v, dpp_or_min<0x111, 0xF>(v));
+  v = max(v, dpp_or_min<0x112, 0xF>(v));
+  v = max(v, dpp_or_min<0x114, 0xF>(v));
+  v = max(v, dpp_or_min<0x118, 0xF>(v));
+  v = max(v, dpp_or_min<0x142, 0xA>(v));
+  v = max(v, dpp_or_min<0x143, 0xC>(v));
+  return v;
+}
+
 __device__ __forceinline__ float lane_value(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }

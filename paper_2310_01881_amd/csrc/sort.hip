@@ -147,22 +147,6 @@ __global__ __launch_bounds__(1024) void k_bucket_tiles(const uint32_t* __restric
   }
 }
 
-// Prefix maximum over the 64 lanes of a wave (signed), on the same lane-shift pattern as
-// wave_scan_incl; lanes outside the pattern contribute INT32_MIN.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ int dpp_or_min(int v) {
-  return __builtin_amdgcn_update_dpp((int)0x80000000, v, CTRL, ROW_MASK, 0xF, false);
-}
-__device__ __forceinline__ int wave_max_incl(int v) {
-  v = max(v, dpp_or_min<0x111, 0xF>(v));
-  v = max(v, dpp_or_min<0x112, 0xF>(v));
-  v = max(v, dpp_or_min<0x114, 0xF>(v));
-  v = max(v, dpp_or_min<0x118, 0xF>(v));
-  v = max(v, dpp_or_min<0x142, 0xA>(v));
-  v = max(v, dpp_or_min<0x143, 0xC>(v));
-  return v;
-}
-
 // One block per 256 consecutive sorted intervals: their records go to LDS, then each wave
 // writes windows of 64 consecutive sorted samples (coalesced).  A sample's interval is
 // found without a search: the intervals starting inside the window mark their first
