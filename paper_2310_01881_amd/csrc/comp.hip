@@ -48,23 +48,31 @@ __device__ __forceinline__ DF df_add(DF a, DF b) {
 // exp(-(hi + lo)) for |lo| << 1: exp(-hi) * (1 - lo).
 __device__ __forceinline__ float df_exp_neg(DF a) { return exp_neg(a.hi) * (1.f - a.lo); }
 
-// Inclusive compensated prefix sum over the wave: the float-pair add of wave_scan_incl's
-// shift pattern (within rows of 16 by 1, 2, 4, 8, then the last lane of row 0 (2) into
-// row 1 (3) and the last lane of row 1 into rows 2 and 3).  Lanes whose source is outside
-// the pattern add (0, 0), which leaves a normalised pair unchanged.
+// Inclusive compensated prefix sum over the wave on wave_scan_incl's shift pattern (within
+// rows of 16 by 1, 2, 4, 8, then the last lane of row 0 (2) into row 1 (3) and the last
+// lane of row 1 into rows 2 and 3; lanes whose source is outside the pattern add 0).  The
+// high parts are added with an exact TwoSum; the low parts, and each TwoSum's rounding
+// error, go into a plain running sum of low parts, normalised once at the end.
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ DF df_shift(DF a) {
-  return {dpp_or_zero<CTRL, ROW_MASK>(a.hi), dpp_or_zero<CTRL, ROW_MASK>(a.lo)};
+__device__ __forceinline__ void df_scan_step(float& hi, float& lo) {
+  const float b = dpp_or_zero<CTRL, ROW_MASK>(hi);
+  const float s = hi + b;
+  const float bb = s - hi;
+  const float e = (hi - (s - bb)) + (b - bb);
+  lo = lo + dpp_or_zero<CTRL, ROW_MASK>(lo) + e;
+  hi = s;
 }
 
 __device__ __forceinline__ DF df_scan_incl(DF v) {
-  v = df_add(v, df_shift<0x111, 0xF>(v));
-  v = df_add(v, df_shift<0x112, 0xF>(v));
-  v = df_add(v, df_shift<0x114, 0xF>(v));
-  v = df_add(v, df_shift<0x118, 0xF>(v));
-  v = df_add(v, df_shift<0x142, 0xA>(v));
-  v = df_add(v, df_shift<0x143, 0xC>(v));
-  return v;
+  float hi = v.hi, lo = v.lo;
+  df_scan_step<0x111, 0xF>(hi, lo);
+  df_scan_step<0x112, 0xF>(hi, lo);
+  df_scan_step<0x114, 0xF>(hi, lo);
+  df_scan_step<0x118, 0xF>(hi, lo);
+  df_scan_step<0x142, 0xA>(hi, lo);
+  df_scan_step<0x143, 0xC>(hi, lo);
+  const float h = hi + lo;
+  return {h, lo - (h - hi)};
 }
 
 __device__ __forceinline__ float wave_sum(float v) { return lane_value(wave_scan_incl(v), 63); }
