@@ -42,17 +42,25 @@ __device__ __forceinline__ bool df_lt(DF a, DF b) { return a.hi < b.hi || (a.hi 
 
 constexpr int kBlock = 256;
 // LDS per block: the node table (when staged), then the traversal stack of `stack_n` =
-// tree depth + 1 entries per thread as three arrays (node, exit hi, exit lo), strided by
-// kBlock so that a wave's accesses fall in distinct banks.
+// tree depth + 1 entries per thread as two arrays strided by kBlock (so that a wave's
+// accesses fall in distinct banks): the exit parameter's high part, and the node index
+// (16 bits) packed with the exit parameter's low part rounded to bfloat16 (the pair then
+// still carries about 2^-32 relative precision, far below the 1e-6 perturbation under which
+// node ids are compared).
 constexpr int kLdsNodes = 2048;  // node tables up to this size are staged in LDS per block
 
 __device__ __forceinline__ float axis_val(const float v[3], int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); }
 
 // Traverses one ray.  EMIT = false: returns the interval count, stopping once it exceeds
 // cap.  EMIT = true: writes the first `cap` intervals through the output pointers.
+__device__ __forceinline__ uint32_t push_word(int node, float lo) {
+  return (uint32_t)node | ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)lo) << 16);
+}
+__device__ __forceinline__ float word_lo(uint32_t w) { return (float)__builtin_bit_cast(__bf16, (uint16_t)(w >> 16)); }
+
 template <bool EMIT, typename NodePtr, typename Put>
 __device__ int traverse(NodePtr nodes, const float o[3], const float dir[3], int cap, uint32_t n_per,
-                        int* st_node, float* st_hi, float* st_lo, Put put) {
+                        uint32_t* st_word, float* st_hi, Put put) {
   // root box [0,1]^3
   DF tin = {0.f, 0.f}, tout = {__builtin_inff(), 0.f};
   bool hit = true;
@@ -90,9 +98,8 @@ __device__ int traverse(NodePtr nodes, const float o[3], const float dir[3], int
         } else if (!df_lt(t0, ts)) {
           node = after;
         } else {
-          st_node[sp * kBlock] = after;
+          st_word[sp * kBlock] = push_word(after, t1.lo);
           st_hi[sp * kBlock] = t1.hi;
-          st_lo[sp * kBlock] = t1.lo;
           ++sp;
           node = before;
           t1 = ts;
@@ -111,9 +118,10 @@ __device__ int traverse(NodePtr nodes, const float o[3], const float dir[3], int
     ++m;
     if (m >= cap + (EMIT ? 0 : 1) || sp == 0) break;
     --sp;
-    node = st_node[sp * kBlock];
+    const uint32_t w = st_word[sp * kBlock];
+    node = (int)(w & 0xFFFFu);
     t0 = t1;
-    t1 = {st_hi[sp * kBlock], st_lo[sp * kBlock]};
+    t1 = {st_hi[sp * kBlock], word_lo(w)};
   }
   return m;
 }
@@ -121,8 +129,8 @@ __device__ int traverse(NodePtr nodes, const float o[3], const float dir[3], int
 // The block's copy of the node table (LDS = true) or the table in memory, and the stack.
 struct TravLds {
   const DevNode* nodes;
-  int* st_node;
-  float *st_hi, *st_lo;
+  uint32_t* st_word;
+  float* st_hi;
 };
 
 template <bool LDS>
@@ -138,15 +146,14 @@ __device__ __forceinline__ TravLds stage(const DevNode* __restrict__ nodes, uint
   } else {
     t.nodes = nodes;
   }
-  t.st_node = reinterpret_cast<int*>(p) + threadIdx.x;
+  t.st_word = reinterpret_cast<uint32_t*>(p) + threadIdx.x;
   t.st_hi = reinterpret_cast<float*>(p + 4u * stack_n * kBlock) + threadIdx.x;
-  t.st_lo = reinterpret_cast<float*>(p + 8u * stack_n * kBlock) + threadIdx.x;
   if (LDS) __syncthreads();
   return t;
 }
 
 __host__ __device__ constexpr uint32_t trav_lds_bytes(bool lds, uint32_t n_nodes, int stack_n) {
-  return (lds ? (uint32_t)sizeof(DevNode) * n_nodes : 0u) + 12u * (uint32_t)stack_n * kBlock;
+  return (lds ? (uint32_t)sizeof(DevNode) * n_nodes : 0u) + 8u * (uint32_t)stack_n * kBlock;
 }
 
 template <bool LDS>
@@ -171,8 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict
   int m = 0;
   // skip the descent for a wave whose rays are all out of range
   if (__ballot(live) != 0 && live)
-    m = traverse<false>(tl.nodes, oo, dd, s_max, 0, tl.st_node, tl.st_hi, tl.st_lo,
-                        [](int, float, float, uint32_t) {});
+    m = traverse<false>(tl.nodes, oo, dd, s_max, 0, tl.st_word, tl.st_hi, [](int, float, float, uint32_t) {});
   if (live) {
     uint32_t meff = m <= s_max ? (uint32_t)m : (uint32_t)s_max;
     uint32_t nper = m == 0 ? 0u : (m <= s_max ? (uint32_t)(s_max / m) : 1u);
@@ -223,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
     const uint32_t nper = cnt_smp[r] / meff;
     const uint32_t pos0 = iv_off[r] - b0;
     const uint32_t base = smp_off[r];
-    traverse<true>(tl.nodes, oo, dd, (int)meff, nper, tl.st_node, tl.st_hi, tl.st_lo,
+    traverse<true>(tl.nodes, oo, dd, (int)meff, nper, tl.st_word, tl.st_hi,
                    [&](int m, float t0, float dt, uint32_t key) {
                      const uint32_t q = pos0 + (uint32_t)m;
                      const uint32_t smp = base + (uint32_t)m * nper;
