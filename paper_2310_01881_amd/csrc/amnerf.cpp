@@ -714,7 +714,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
       carve_prop((char*)ctx->arena3, nr, niv_plain, niv_plan, spp, pw);
       HIP_TRY(launch_prop_fwd(q->dtype, q->packed_dev, plain, rays->o_dev, rays->d_dev, R, r0, tree->dev_leafbox,
                               p->s_max, niv_plain, true, pw.wts, pw.tot, st));
-      HIP_TRY(launch_prop_select(nr, plain, pw.wts, pw.tot, q->mass_thresh, q->cap, pw.runs, pw.nsel, pw.mask, nullptr,
+      HIP_TRY(launch_prop_select(nr, plain, pw.wts, pw.tot, q->mass_thresh, q->cap, p->s_max, pw.runs, pw.nsel, pw.mask, nullptr,
                                  ctx->counts, st));
       HIP_TRY(launch_scan_u32_pair(pw.runs, pw.pv_off, pw.nsel, pw.ps_off, nr, pw.scan_tmp, st));
       HIP_TRY(launch_prop_emit(nr, plain, pw.mask, pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, st));

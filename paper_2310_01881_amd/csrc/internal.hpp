@@ -165,7 +165,7 @@ hipError_t launch_prop_fwd(int dtype, const void* packed, const IvSet& iv, const
                            int64_t stride, int64_t r0, const float* leafbox, int s_max, uint32_t n_iv_max,
                            bool cum, float* tau, float* tot, hipStream_t st);
 hipError_t launch_prop_select(uint32_t nr, const IvSet& iv, const float* wts, const float* tot, float mass_thresh,
-                              int cap,
+                              int cap, int s_max,
                               uint32_t* runs, uint32_t* nsel, uint64_t* mask, float* mass, ChunkCounts* counts,
                               hipStream_t st);
 hipError_t launch_prop_emit(uint32_t nr, const IvSet& iv, const uint64_t* mask, const uint32_t* pv_off,

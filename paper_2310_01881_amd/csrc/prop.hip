@@ -542,7 +542,10 @@ __device__ __forceinline__ uint32_t count_sorted(const float p[4], uint32_t ns, 
   return count;
 }
 
-__global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv, const float* __restrict__ wts,
+// QM: registers of 64 slots a ray may need (2 when S_max <= 128, else 4); fewer live
+// registers in the common case keep more waves resident.
+template <int QM>
+__global__ __launch_bounds__(kThreads, QM == 2 ? 8 : 1) void k_prop_select(uint32_t nr, IvSet iv, const float* __restrict__ wts,
                                                           const float* __restrict__ tot,
                                                           float mass_thresh, int cap, uint32_t* __restrict__ runs,
                                                           uint32_t* __restrict__ nsel, uint64_t* __restrict__ mask,
@@ -575,15 +578,15 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
     auto div_n = [&](uint32_t x) { return n > 1u ? __umulhi(x, m32) : x; };
     const uint32_t nq = (ns + 63u) / 64u;
     // Every load of the ray is issued before the first wait: the bin weights each slot
-    // covers (its first and last bin and up to 4 whole bins between them), then the
+    // covers (its first and last bin and up to kMid whole bins between them), then the
     // interval totals, then the next ray's offsets.
     // The slot geometry is kept packed: interval k (8 bits), slot j in it (8 bits), first and
     // last bin (5 bits each).
-    constexpr int kMid = 4;
-    float wlo[4], whi[4], wmid[4][kMid];
-    uint32_t geo[4];
+    constexpr int kMid = QM == 2 ? 3 : 4;
+    float wlo[QM], whi[QM], wmid[QM][kMid];
+    uint32_t geo[QM];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QM; ++q) {
       wlo[q] = 0.f; whi[q] = 0.f; geo[q] = 0u;
 #pragma unroll
       for (int t = 0; t < kMid; ++t) wmid[q][t] = 0.f;
@@ -625,7 +628,7 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
       const float inv_n = 1.f / (float)n;
       float p[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < QM; ++q) {
         if ((uint32_t)q >= nq) break;
         const uint32_t s = (uint32_t)lane + 64u * q;
         const uint32_t sk = geo[q] & 255u, j = (geo[q] >> 8) & 255u;
@@ -641,7 +644,7 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
 #pragma unroll
           for (int t = 0; t < kMid; ++t) v += wmid[q][t];
           const float* row = wts + (uint64_t)(i0 + sk) * kBins;
-          for (uint32_t b = blo + 1u + kMid; b < bhi; ++b) v += row[b];   // slots wider than 5 bins
+          for (uint32_t b = blo + 1u + kMid; b < bhi; ++b) v += row[b];   // slots wider than kMid + 1 bins
           v += (u1 - (float)bhi) * whi[q];
         }
         p[q] = sbuf[wave][sk] * v;
@@ -651,8 +654,9 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
       const float target = mass_thresh * M;
       bool reached = true;
       float wcut = 0.f;
-      count = nq <= 2 ? count_sorted<2>(p, ns, target, lane, &reached, &wcut)
-                      : count_sorted<4>(p, ns, target, lane, &reached, &wcut);
+      if constexpr (QM == 2) count = count_sorted<2>(p, ns, target, lane, &reached, &wcut);
+      else count = nq <= 2 ? count_sorted<2>(p, ns, target, lane, &reached, &wcut)
+                           : count_sorted<4>(p, ns, target, lane, &reached, &wcut);
       if (count > (uint32_t)cap || count == 0 || !reached) {
         fallback = true;
       } else {
@@ -660,7 +664,7 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
         uint32_t n_gt = 0;
         uint64_t eqm[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < QM; ++q) {
           const bool valid = (uint32_t)lane + 64u * q < ns;
           sel[q] = __ballot(valid && p[q] > wcut);
           eqm[q] = __ballot(valid && p[q] == wcut);
@@ -668,7 +672,7 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
         }
         uint32_t need = count - n_gt;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < QM; ++q) {
           uint64_t e = eqm[q];
           while (need && e) {
             const uint64_t low = e & (~e + 1ull);
@@ -688,7 +692,7 @@ __global__ __launch_bounds__(kThreads) void k_prop_select(uint32_t nr, IvSet iv,
     // runs: a kept slot starts a run unless the previous slot is kept in the same interval
     uint32_t nruns = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QM; ++q) {
       const uint64_t prev_kept = (sel[q] << 1) | (q > 0 ? sel[q - 1] >> 63 : 0ull);
       nruns += (uint32_t)__popcll(sel[q] & ~(prev_kept & ~first[q]));
     }
@@ -1114,7 +1118,7 @@ hipError_t launch_prop_fwd(int dtype, const void* packed, const IvSet& iv, const
 }
 
 hipError_t launch_prop_select(uint32_t nr, const IvSet& iv, const float* wts, const float* tot, float mass_thresh,
-                              int cap,
+                              int cap, int s_max,
                               uint32_t* runs, uint32_t* nsel, uint64_t* mask, float* mass, ChunkCounts* counts,
                               hipStream_t st) {
   if (nr == 0) return hipSuccess;
@@ -1122,7 +1126,8 @@ hipError_t launch_prop_select(uint32_t nr, const IvSet& iv, const float* wts, co
   hipError_t e = ncu(&n);
   if (e != hipSuccess) return e;
   const uint32_t grid = std::min<uint32_t>((nr + 3) / 4, (uint32_t)n * 16);
-  hipLaunchKernelGGL(k_prop_select, dim3(grid), dim3(kThreads), 0, st, nr, iv, wts, tot, mass_thresh, cap, runs, nsel,
+  hipLaunchKernelGGL(s_max <= 128 ? k_prop_select<2> : k_prop_select<4>, dim3(grid), dim3(kThreads), 0, st, nr, iv, wts,
+                     tot, mass_thresh, cap, runs, nsel,
                      mask, mass, counts);
   return hipGetLastError();
 }
