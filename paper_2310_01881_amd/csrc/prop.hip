@@ -542,10 +542,10 @@ __device__ __forceinline__ uint32_t count_sorted(const float p[4], uint32_t ns, 
   return count;
 }
 
-// QM: registers of 64 slots a ray may need (2 when S_max <= 128, else 4); fewer live
-// registers in the common case keep more waves resident.
+// QM: registers of 64 slots a ray may need (2 when S_max <= 128, 3 up to 192, else 4);
+// fewer live registers keep more waves resident.
 template <int QM>
-__global__ __launch_bounds__(kThreads, QM == 2 ? 8 : 1) void k_prop_select(uint32_t nr, IvSet iv, const float* __restrict__ wts,
+__global__ __launch_bounds__(kThreads, QM == 2 ? 8 : (QM == 3 ? 7 : 1)) void k_prop_select(uint32_t nr, IvSet iv, const float* __restrict__ wts,
                                                           const float* __restrict__ tot,
                                                           float mass_thresh, int cap, uint32_t* __restrict__ runs,
                                                           uint32_t* __restrict__ nsel, uint64_t* __restrict__ mask,
@@ -655,6 +655,8 @@ __global__ __launch_bounds__(kThreads, QM == 2 ? 8 : 1) void k_prop_select(uint3
       bool reached = true;
       float wcut = 0.f;
       if constexpr (QM == 2) count = count_sorted<2>(p, ns, target, lane, &reached, &wcut);
+      else if constexpr (QM == 3) count = nq <= 2 ? count_sorted<2>(p, ns, target, lane, &reached, &wcut)
+                                                  : count_sorted<4>(p, ns, target, lane, &reached, &wcut);
       else count = nq <= 2 ? count_sorted<2>(p, ns, target, lane, &reached, &wcut)
                            : count_sorted<4>(p, ns, target, lane, &reached, &wcut);
       if (count > (uint32_t)cap || count == 0 || !reached) {
@@ -1126,7 +1128,8 @@ hipError_t launch_prop_select(uint32_t nr, const IvSet& iv, const float* wts, co
   hipError_t e = ncu(&n);
   if (e != hipSuccess) return e;
   const uint32_t grid = std::min<uint32_t>((nr + 3) / 4, (uint32_t)n * 16);
-  hipLaunchKernelGGL(s_max <= 128 ? k_prop_select<2> : k_prop_select<4>, dim3(grid), dim3(kThreads), 0, st, nr, iv, wts,
+  hipLaunchKernelGGL(s_max <= 128 ? k_prop_select<2> : (s_max <= 192 ? k_prop_select<3> : k_prop_select<4>), dim3(grid),
+                     dim3(kThreads), 0, st, nr, iv, wts,
                      tot, mass_thresh, cap, runs, nsel,
                      mask, mass, counts);
   return hipGetLastError();
