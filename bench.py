@@ -324,6 +324,49 @@ def main():
             {k: round(v, 4) for k, v in results[kind]["stage_ms_per_frame"].items()}))
     am.amnerf_ctx_set_timing(ctx.h, False)
 
+    # ---- ablation without the adaptive subdivision: the same grid under a regular tree of as
+    #      many leaves (middle planes, breadth-first), plain bf16 render, same cameras ----
+    ablation = None
+    if "bf16" in paths:
+        rtree = am.Tree(ctx, grid, cfg.grid_n, cfg.max_depth, cfg.max_leaves, am.AMNERF_SPLIT_MIDDLE)
+        rdens = synth.leaf_mean_density(grid, cfg.grid_n, rtree.leaf_boxes())
+        rW = synth.make_weights(rtree.n_leaves, cfg.n_hidden, cfg.hidden, cfg.seed_weights, rdens)
+        rmlp = am.Mlp(ctx, torch.from_numpy(rW).to(dev), cfg.n_hidden, cfg.hidden, am.AMNERF_BF16, rtree.n_leaves)
+        ob = outs["bf16"]
+
+        def rrender(cam):
+            o, d = rays[cam]
+            am.amnerf_render(ctx.h, rtree.h, rmlp.desc, o, d, cfg.s_max, ob["rgb"], ob["depth"], ob["opacity"],
+                             None, cfg.ert_eps)
+        rs = []
+        for cam in range(n_cams):
+            rrender(cam)
+            rs.append(am.amnerf_render_stats_get(ctx.h)["n_samples"])
+        for w in range(args.warmup):
+            rrender(w % n_cams)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            rrender(k % n_cams)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+
+        def mass_spread(t):
+            lv = t.mass[t.rows[:, 10] >= 0].astype(np.float64)
+            return float(lv.max() / max(np.median(lv), 1.0))
+        ablation = {"tree": "regular subdivision, %d leaves" % rtree.n_leaves, "path": "bf16, no proposal",
+                    "ms_per_frame": 1e3 * dt / args.steps,
+                    "samples_per_frame": float(np.mean(rs)),
+                    "adaptive_ms_per_frame": results["bf16"]["ms_per_frame"],
+                    "adaptive_samples_per_frame": results["bf16"]["samples_per_frame"],
+                    "leaf_mass_max_over_median": mass_spread(rtree),
+                    "adaptive_leaf_mass_max_over_median": mass_spread(tree)}
+        log("ablation (regular tree): %.3f ms/frame, %.3e samples/frame; adaptive %.3f ms, %.3e samples" % (
+            ablation["ms_per_frame"], ablation["samples_per_frame"], ablation["adaptive_ms_per_frame"],
+            ablation["adaptive_samples_per_frame"]))
+        rtree.close()
+        del rmlp
+
     # ---- training step on the same scene (teacher-student, bf16 forward, float32 gradients,
     #      Adam), timed apart from the frame ----
     train = None
@@ -457,6 +500,7 @@ def main():
         "training": train,
         "paths": results,
         "large_scene": large,
+        "ablation_regular_tree": ablation,
     }
     print(json.dumps(line), flush=True)
 

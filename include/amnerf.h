@@ -81,9 +81,13 @@ int amnerf_ctx_create(int device, size_t workspace_cap, amnerf_ctx** out);
 int amnerf_ctx_destroy(amnerf_ctx* ctx);
 
 /* ---- tree (Section 3.4) -------------------------------------------------------------- */
+#define AMNERF_SPLIT_MEDIAN 0  /* density-median subdivision (the method) */
+#define AMNERF_SPLIT_MIDDLE 1  /* regular subdivision, for the ablation without it */
+
 typedef struct {
   int32_t max_depth;   /* 0 .. AMNERF_MAX_DEPTH */
   int32_t max_leaves;  /* 1 .. AMNERF_MAX_LEAVES */
+  int32_t split;       /* AMNERF_SPLIT_MEDIAN or AMNERF_SPLIT_MIDDLE */
 } amnerf_tree_params;
 
 typedef struct {
@@ -107,7 +111,12 @@ typedef struct {
  * massless node).  Node codes are binary: root 1, children 2c (lower) and 2c+1 (upper).
  * Leaves are numbered 0..L-1 ("slots") in left-first depth-first order; a leaf's slot is
  * the node id samples are sorted by.  Runs synchronously on the host, then uploads the
- * node table to the context's device. */
+ * node table to the context's device.
+ * With split = AMNERF_SPLIT_MIDDLE the subdivision ignores the density (the regular-grid
+ * subdivision that Section 4.2's ablation removes the adaptive split against): the
+ * splittable leaf of smallest depth (ties: smallest node code) is split, at the middle
+ * cell plane (lo + hi) / 2 of its longest side.  A power-of-two leaf count on a
+ * power-of-two grid then gives equal boxes.  Masses are recorded as in the median mode. */
 int amnerf_build_tree(amnerf_ctx* ctx, const float* grid_host, int32_t n,
                       const amnerf_tree_params* params, amnerf_tree** out);
 

@@ -49,7 +49,7 @@ def lib():
         _lib = C.CDLL(_SO)
         P = C.c_void_p
         i32, i64, dbl, u64 = C.c_int32, C.c_int64, C.c_double, C.c_uint64
-        _lib.orc_build_tree.argtypes = [P, i32, i32, i32, i32, P, P, P, P]
+        _lib.orc_build_tree.argtypes = [P, i32, i32, i32, i32, i32, P, P, P, P]
         _lib.orc_trace_rays.argtypes = [P, i32, i32, P, P, i64, P, i64, i32, P, P, P, P]
         _lib.orc_robust.argtypes = [P, i32, i32, P, P, i64, P, i64, dbl, dbl, P]
         _lib.orc_mlp_eval.argtypes = [P, i32, i32, P, P, i64, P, P]
@@ -107,14 +107,16 @@ class Tree:
         return lv[np.argsort(lv[:, 10])][:, 2:8].copy()
 
 
-def build_tree(grid, n, max_depth, max_leaves) -> Tree:
+def build_tree(grid, n, max_depth, max_leaves, split=0) -> Tree:
+    """KD tree of the guidance grid: split 0 = density-median subdivision (best-first by
+    mass), 1 = regular subdivision (breadth-first, middle planes)."""
     grid = _c(grid, np.float32)
     cap = 2 * max_leaves
     rows = np.zeros((cap, NODE_COLS), np.int32)
     mass = np.zeros(cap, np.uint64)
     nn = np.zeros(1, np.int32)
     nl = np.zeros(1, np.int32)
-    rc = lib().orc_build_tree(_p(grid), n, max_depth, max_leaves, cap, _p(rows), _p(mass), _p(nn), _p(nl))
+    rc = lib().orc_build_tree(_p(grid), n, max_depth, max_leaves, int(split), cap, _p(rows), _p(mass), _p(nn), _p(nl))
     if rc != 0:
         raise ValueError("orc_build_tree failed")
     k = int(nn[0])

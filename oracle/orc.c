@@ -105,9 +105,10 @@ static int cmp_code(const void* a, const void* b) {
 /* Builds the tree and exports it as rows of 12 int32, sorted by node code:
  *   code, depth, lo[3], hi[3], axis (-1 leaf), plane (-1 leaf), slot (-1 inner), 0
  * plus the integer mass of each node.  Returns 0, or -1 on bad arguments / capacity. */
-int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int cap,
+int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int split, int cap,
                    int32_t* rows, uint64_t* mass_out, int* n_nodes_out, int* n_leaves_out) {
   if (!grid || n < 1 || max_depth < 0 || max_depth > 30 || max_leaves < 1 || !rows) return -1;
+  if (split != 0 && split != 1) return -1;
   int64_t ncell = (int64_t)n * n * n;
   uint32_t* q = (uint32_t*)malloc(sizeof(uint32_t) * ncell);
   if (!q) return -1;
@@ -124,13 +125,19 @@ int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int 
   for (int64_t i = 0; i < ncell; ++i) r->mass += q[i];
 
   while (nleaves < max_leaves) {
-    /* best-first: the splittable leaf of largest mass, ties to the smallest code */
+    /* median split (split = 0): best-first, the splittable leaf of largest mass; middle
+       split (split = 1): breadth-first, the splittable leaf of smallest depth; ties to the
+       smallest code */
     int best = -1;
     for (int i = 0; i < nn; ++i) {
       if (!nodes[i].leaf || !splittable(&nodes[i], max_depth)) continue;
-      if (best < 0 || nodes[i].mass > nodes[best].mass ||
-          (nodes[i].mass == nodes[best].mass && nodes[i].code < nodes[best].code))
-        best = i;
+      int better;
+      if (best < 0) better = 1;
+      else if (split == 0) better = nodes[i].mass > nodes[best].mass ||
+                                    (nodes[i].mass == nodes[best].mass && nodes[i].code < nodes[best].code);
+      else better = nodes[i].depth < nodes[best].depth ||
+                    (nodes[i].depth == nodes[best].depth && nodes[i].code < nodes[best].code);
+      if (better) best = i;
     }
     if (best < 0) break;
     onode* p = &nodes[best];
@@ -138,7 +145,7 @@ int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int 
     int lo = p->lo[a], hi = p->hi[a];
     for (int c = lo; c < hi; ++c) slab[c - lo] = mass_of_slab(q, n, p->lo, p->hi, a, c);
     int plane;
-    if (p->mass == 0) {
+    if (split == 1 || p->mass == 0) {
       plane = (lo + hi) / 2;
     } else {
       /* weighted median: smallest plane whose lower side holds at least half the mass */

@@ -26,6 +26,8 @@ AMNERF_ESTATE = -5
 AMNERF_F32 = 0
 AMNERF_BF16 = 1
 AMNERF_FP8 = 2
+AMNERF_SPLIT_MEDIAN = 0
+AMNERF_SPLIT_MIDDLE = 1
 AMNERF_JITTER = 1
 AMNERF_MAX_GRID = 512
 AMNERF_MAX_DEPTH = 16
@@ -55,7 +57,7 @@ class AmnerfError(RuntimeError):
 
 
 class amnerf_tree_params(C.Structure):
-    _fields_ = [("max_depth", C.c_int32), ("max_leaves", C.c_int32)]
+    _fields_ = [("max_depth", C.c_int32), ("max_leaves", C.c_int32), ("split", C.c_int32)]
 
 
 class amnerf_tree_info(C.Structure):
@@ -210,12 +212,12 @@ def amnerf_ctx_destroy(ctx):
     _check(_lib.amnerf_ctx_destroy(ctx))
 
 
-def amnerf_build_tree(ctx, grid: np.ndarray, n: int, max_depth: int, max_leaves: int):
+def amnerf_build_tree(ctx, grid: np.ndarray, n: int, max_depth: int, max_leaves: int, split: int = 0):
     g = np.ascontiguousarray(grid, dtype=np.float32)
     if g.size != n ** 3:
         raise ValueError("grid has %d cells, expected %d" % (g.size, n ** 3))
     h = C.c_void_p()
-    prm = amnerf_tree_params(max_depth, max_leaves)
+    prm = amnerf_tree_params(max_depth, max_leaves, split)
     _check(_lib.amnerf_build_tree(ctx, g.ctypes.data_as(C.c_void_p), n, C.byref(prm), C.byref(h)))
     return h
 
@@ -377,9 +379,9 @@ class Context:
 
 
 class Tree:
-    def __init__(self, ctx: Context, grid, n, max_depth, max_leaves):
+    def __init__(self, ctx: Context, grid, n, max_depth, max_leaves, split=0):
         self.ctx = ctx
-        self.h = amnerf_build_tree(ctx.h, grid, n, max_depth, max_leaves)
+        self.h = amnerf_build_tree(ctx.h, grid, n, max_depth, max_leaves, split)
         self.info = amnerf_tree_info_get(self.h)
         self.rows, self.mass = amnerf_tree_export(self.h)
 

@@ -283,14 +283,14 @@ int longest_axis(const HNode& nd) {
 }
 
 struct Cand {
-  uint64_t mass;
+  uint64_t prio;   // the mass (median split) or 64 - depth (middle split)
   uint32_t code;
   int idx;
 };
 struct CandLess {
   bool operator()(const Cand& a, const Cand& b) const {
-    // priority_queue pops the largest: larger mass first, then the smaller code
-    if (a.mass != b.mass) return a.mass < b.mass;
+    // priority_queue pops the largest: larger priority first, then the smaller code
+    if (a.prio != b.prio) return a.prio < b.prio;
     return a.code > b.code;
   }
 };
@@ -305,6 +305,8 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
     return fail(AMNERF_EINVAL, "amnerf_build_tree: grid side %d must be a power of two <= 512", n);
   if (p->max_depth < 0 || p->max_depth > AMNERF_MAX_DEPTH)
     return fail(AMNERF_EINVAL, "amnerf_build_tree: max_depth %d out of [0, %d]", p->max_depth, AMNERF_MAX_DEPTH);
+  if (p->split != AMNERF_SPLIT_MEDIAN && p->split != AMNERF_SPLIT_MIDDLE)
+    return fail(AMNERF_EINVAL, "amnerf_build_tree: bad split mode %d", p->split);
   if (p->max_leaves < 1 || p->max_leaves > AMNERF_MAX_LEAVES)
     return fail(AMNERF_EINVAL, "amnerf_build_tree: max_leaves %d out of [1, %d]", p->max_leaves, AMNERF_MAX_LEAVES);
   const size_t ncell = (size_t)n * n * n;
@@ -344,8 +346,10 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
     int a = longest_axis(nd);
     return nd.depth < p->max_depth && nd.hi[a] - nd.lo[a] >= 2;
   };
+  const bool middle = p->split == AMNERF_SPLIT_MIDDLE;
+  auto prio = [&](const HNode& nd) { return middle ? (uint64_t)(64 - nd.depth) : nd.mass; };
   std::priority_queue<Cand, std::vector<Cand>, CandLess> pq;
-  if (splittable(nodes[0])) pq.push({nodes[0].mass, 1u, 0});
+  if (splittable(nodes[0])) pq.push({prio(nodes[0]), 1u, 0});
   int leaves = 1;
   while (leaves < p->max_leaves && !pq.empty()) {
     Cand c = pq.top();
@@ -359,7 +363,7 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
       h2[a] = pl;
       return S.box(nd.lo, h2);
     };
-    if (nd.mass == 0) {
+    if (middle || nd.mass == 0) {
       plane = (lo + hi) / 2;
     } else {
       // smallest plane in [lo+1, hi-1] with 2 * lower mass >= node mass (binary search on
@@ -388,8 +392,8 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
     nodes.push_back(lc);
     nodes.push_back(rc);
     ++leaves;
-    if (splittable(nodes[li])) pq.push({nodes[li].mass, nodes[li].code, li});
-    if (splittable(nodes[li + 1])) pq.push({nodes[li + 1].mass, nodes[li + 1].code, li + 1});
+    if (splittable(nodes[li])) pq.push({prio(nodes[li]), nodes[li].code, li});
+    if (splittable(nodes[li + 1])) pq.push({prio(nodes[li + 1]), nodes[li + 1].code, li + 1});
   }
   // slots: left-first depth-first order
   int next_slot = 0, max_depth = 0;

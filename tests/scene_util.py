@@ -13,10 +13,11 @@ import synth
 
 
 class Scene:
-    def __init__(self, cfg: synth.SceneConfig, grid=None):
+    def __init__(self, cfg: synth.SceneConfig, grid=None, split=0):
         self.cfg = cfg
+        self.split = split
         self.grid = synth.make_grid(cfg) if grid is None else grid
-        self.otree = oracle.build_tree(self.grid, cfg.grid_n, cfg.max_depth, cfg.max_leaves)
+        self.otree = oracle.build_tree(self.grid, cfg.grid_n, cfg.max_depth, cfg.max_leaves, split)
         dens = synth.leaf_mean_density(self.grid, cfg.grid_n, self.otree.leaf_boxes())
         self.W = synth.make_weights(self.otree.n_leaves, cfg.n_hidden, cfg.hidden, cfg.seed_weights, dens)
 
@@ -31,7 +32,7 @@ def gpu_setup(scene: Scene, dtype, device="cuda:0"):
     import torch
     import paper_2310_01881_amd as am
     ctx = am.Context(0)
-    tree = am.Tree(ctx, scene.grid, scene.cfg.grid_n, scene.cfg.max_depth, scene.cfg.max_leaves)
+    tree = am.Tree(ctx, scene.grid, scene.cfg.grid_n, scene.cfg.max_depth, scene.cfg.max_leaves, scene.split)
     assert np.array_equal(tree.rows, scene.otree.rows)
     assert np.array_equal(tree.mass, scene.otree.mass)
     master = torch.from_numpy(scene.W).to(device)

@@ -437,3 +437,41 @@ def test_buckets_are_contiguous_stable_and_counted():
         seg = perm[offsets[b]:offsets[b + 1]]
         assert len(seg) == counts[b] == (keys == b).sum()
         assert np.all(keys[seg] == b) and np.all(np.diff(seg.astype(np.int64)) > 0)
+
+
+@pytest.mark.parametrize("n,max_depth,max_leaves", [(32, 6, 64), (32, 12, 40), (64, 12, 512)])
+def test_middle_split_is_regular_subdivision(n, max_depth, max_leaves):
+    """The regular subdivision of the ablation: breadth-first, middle planes, independent of
+    the density; with 2^k leaves on a 2^m grid the leaves are equal boxes tiling the grid."""
+    g1 = synth.make_grid(synth.scaled(synth.C1, grid_n=n))
+    g2 = np.random.default_rng(3).uniform(0, 10, n ** 3).astype(np.float32)
+    t1 = oracle.build_tree(g1, n, max_depth, max_leaves, split=1)
+    t2 = oracle.build_tree(g2, n, max_depth, max_leaves, split=1)
+    assert t1.n_leaves == max_leaves
+    np.testing.assert_array_equal(t1.rows, t2.rows)          # the structure ignores the density
+    rows = t1.rows
+    q = quantised(g1).reshape(n, n, n)
+    for r, m in zip(rows, t1.mass):
+        lx, ly, lz, hx, hy, hz = r[2:8]
+        assert int(q[lz:hz, ly:hy, lx:hx].sum()) == int(m)
+    inner = rows[rows[:, 8] >= 0]
+    for r in inner:
+        a, p = int(r[8]), int(r[9])
+        ext = r[5:8] - r[2:5]
+        assert a == int(np.argmax(ext))
+        assert p == (int(r[2 + a]) + int(r[5 + a])) // 2
+    leaves = rows[rows[:, 10] >= 0]
+    depths = leaves[:, 1]
+    assert depths.max() - depths.min() <= 1                   # breadth-first
+    # the leaves split at the deepest level are those of smallest code at the level above
+    shallow = leaves[depths == depths.min()]
+    deep_parents = sorted({int(c) >> 1 for c in leaves[depths == depths.max()][:, 0]})
+    if depths.max() != depths.min():
+        assert max(deep_parents) < shallow[:, 0].min()
+    if max_leaves & (max_leaves - 1) == 0:
+        k = max_leaves.bit_length() - 1
+        side = n >> (k // 3)
+        ext = leaves[:, 5:8] - leaves[:, 2:5]
+        assert np.all(depths == k)
+        assert np.all(ext.max(axis=1) <= side) and np.all(ext.min(axis=1) >= side // 2)
+        assert np.all(np.prod(ext, axis=1) == n ** 3 // max_leaves)
