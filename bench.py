@@ -367,6 +367,45 @@ def main():
         rtree.close()
         del rmlp
 
+    # ---- hierarchical sampling (HCheck): every node gets an MLP, plain bf16 render, same
+    #      cameras; the footprint (sample spacing per unit distance) is a free parameter ----
+    hier = None
+    if "bf16" in paths:
+        rows = tree.rows
+        nboxes = rows[np.argsort(rows[:, 11])][:, 2:8].copy()
+        ndens = synth.leaf_mean_density(grid, cfg.grid_n, nboxes)
+        nW = synth.make_weights(len(nboxes), cfg.n_hidden, cfg.hidden, cfg.seed_weights, ndens)
+        nmlp = am.Mlp(ctx, torch.from_numpy(nW).to(dev), cfg.n_hidden, cfg.hidden, am.AMNERF_BF16, len(nboxes))
+        ob = outs["bf16"]
+        hier = {"path": "bf16, no proposal, %d node MLPs" % len(nboxes),
+                "adaptive_leaves_ms_per_frame": results["bf16"]["ms_per_frame"],
+                "adaptive_leaves_samples_per_frame": results["bf16"]["samples_per_frame"], "footprints": {}}
+        for fp in (0.05, 0.1, 0.25):
+            def hrender(cam):
+                o, d = rays[cam]
+                am.amnerf_render(ctx.h, tree.h, nmlp.desc, o, d, cfg.s_max, ob["rgb"], ob["depth"], ob["opacity"],
+                                 None, cfg.ert_eps, hcheck_footprint=fp)
+            hs, hiv = [], []
+            for cam in range(n_cams):
+                hrender(cam)
+                st = am.amnerf_render_stats_get(ctx.h)
+                hs.append(st["n_samples"])
+                hiv.append(st["n_intervals"])
+            for w in range(args.warmup):
+                hrender(w % n_cams)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                hrender(k % n_cams)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            hier["footprints"][str(fp)] = {"ms_per_frame": 1e3 * dt / args.steps,
+                                           "samples_per_frame": float(np.mean(hs)),
+                                           "intervals_per_frame": float(np.mean(hiv))}
+            log("hierarchical sampling, footprint %g: %.3f ms/frame, %.3e samples/frame, %.3e intervals/frame" % (
+                fp, 1e3 * dt / args.steps, np.mean(hs), np.mean(hiv)))
+        del nmlp
+
     # ---- training step on the same scene (teacher-student, bf16 forward, float32 gradients,
     #      Adam), timed apart from the frame ----
     train = None
@@ -501,6 +540,7 @@ def main():
         "paths": results,
         "large_scene": large,
         "ablation_regular_tree": ablation,
+        "hierarchical_sampling": hier,
     }
     print(json.dumps(line), flush=True)
 

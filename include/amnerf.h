@@ -125,7 +125,9 @@ int amnerf_tree_info_get(const amnerf_tree* tree, amnerf_tree_info* out);
 /* Copies the tree into caller arrays, one row per node, sorted by node code.
  *   rows_host: host int32[n_nodes][12]: code, depth, lo[3], hi[3] (integer cell box
  *              [lo, hi)), split axis (-1 for a leaf), split plane (cell index, -1 for a
- *              leaf), leaf slot (-1 for an inner node), 0.
+ *              leaf), leaf slot (-1 for an inner node), node slot (the node's rank among
+              all nodes in left-first depth-first preorder: root 0, a node's lower child
+              right after it, its upper child after the lower child's subtree).
  *   mass_host: host uint64[n_nodes] integer masses, or NULL. */
 int amnerf_tree_export(const amnerf_tree* tree, int32_t* rows_host, uint64_t* mass_host);
 
@@ -173,7 +175,8 @@ int amnerf_mlp_pack(amnerf_ctx* ctx, const amnerf_mlp_shape* shape, int32_t dtyp
 typedef struct {
   amnerf_mlp_shape shape;
   int32_t dtype;          /* AMNERF_F32, AMNERF_BF16 or AMNERF_FP8 */
-  int32_t n_leaves;       /* must equal the tree's leaf count */
+  int32_t n_leaves;       /* parameter sets: the tree's leaf count (its node count for a
+                             render with hierarchical sampling) */
   const void* packed_dev; /* device block written by amnerf_mlp_pack with the same
                              shape, dtype and n_leaves */
 } amnerf_mlp;
@@ -205,6 +208,20 @@ typedef struct {
   uint64_t jitter_seed;   /* seed of the per-interval offsets when AMNERF_JITTER is set */
   const amnerf_proposal* proposal;  /* NULL: plain sampling; else proposal sampling (the
                              strata are then centred: AMNERF_JITTER is rejected) */
+  float hcheck_footprint; /* 0: samples in leaf intervals only.  > 0: hierarchical sampling
+                             (Section 3.5, HCheck): the descent stops at an inner node when
+                             the ray enters it at t > size / hcheck_footprint (size = the
+                             node's longest side in [0,1] units; the quotient rounded once
+                             to float32, compared with the float32 entry parameter), and that
+                             node's MLP takes the ray's whole segment inside it.  The MLP then
+                             holds one parameter set per node, indexed by the node's preorder
+                             slot (amnerf_tree_export column 11), so n_nodes <=
+                             AMNERF_MAX_LEAVES (else AMNERF_ECAPACITY).  Samples per interval
+                             stay those of the leaf intervals (s_max / m with m the ray's
+                             leaf-interval count), so a node that stops the descent gets one
+                             interval's share.  Not combined with a proposal (AMNERF_EINVAL).
+                             The footprint is a sample spacing per unit distance, e.g.
+                             kappa times the pixel angle */
 } amnerf_render_params;
 
 typedef struct {

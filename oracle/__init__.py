@@ -48,18 +48,18 @@ def lib():
         build()
         _lib = C.CDLL(_SO)
         P = C.c_void_p
-        i32, i64, dbl, u64 = C.c_int32, C.c_int64, C.c_double, C.c_uint64
+        i32, i64, dbl, u64, f32 = C.c_int32, C.c_int64, C.c_double, C.c_uint64, C.c_float
         _lib.orc_build_tree.argtypes = [P, i32, i32, i32, i32, i32, P, P, P, P]
-        _lib.orc_trace_rays.argtypes = [P, i32, i32, P, P, i64, P, i64, i32, P, P, P, P]
-        _lib.orc_robust.argtypes = [P, i32, i32, P, P, i64, P, i64, dbl, dbl, P]
+        _lib.orc_trace_rays.argtypes = [P, i32, i32, P, P, i64, P, i64, i32, P, P, P, P, f32]
+        _lib.orc_robust.argtypes = [P, i32, i32, P, P, i64, P, i64, dbl, dbl, P, f32]
         _lib.orc_mlp_eval.argtypes = [P, i32, i32, P, P, i64, P, P]
         _lib.orc_render.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, P, i64, i32, dbl,
-                                    i32, u64, P, P, P, P, P, i32]
+                                    i32, u64, P, P, P, P, P, i32, f32]
         _lib.orc_ray_samples.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, i64, i32, dbl,
-                                         i32, u64, i32, P, P, P, P, P, P, P]
+                                         i32, u64, i32, P, P, P, P, P, P, P, f32]
         _lib.orc_ray_samples.restype = i32
         _lib.orc_render_grad.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, P, i64, i32,
-                                         dbl, i32, u64, P, P, P, P]
+                                         dbl, i32, u64, P, P, P, P, f32]
         _lib.orc_adam.argtypes = [P, P, P, P, i64, i32, dbl, dbl, dbl, dbl]
         _lib.orc_adam.restype = None
         _lib.orc_splitmix64.argtypes = [u64]
@@ -87,7 +87,8 @@ def _c(a, dt):
 
 
 class Tree:
-    """An exported node table: rows of (code, depth, lo[3], hi[3], axis, plane, slot, 0)."""
+    """An exported node table: rows of (code, depth, lo[3], hi[3], axis, plane, leaf slot,
+    node slot)."""
 
     def __init__(self, rows, mass, grid_n):
         self.rows = rows
@@ -130,8 +131,9 @@ def _sel(ray_idx, R):
     return ri, len(ri)
 
 
-def trace(tree: Tree, o, d, ray_idx=None, cap=None):
-    """Leaf intervals per ray: (t0[n][cap], t1[n][cap], slot[n][cap], m[n])."""
+def trace(tree: Tree, o, d, ray_idx=None, cap=None, footprint=0.0):
+    """Leaf intervals per ray: (t0[n][cap], t1[n][cap], slot[n][cap], m[n]); with footprint > 0
+    the intervals of hierarchical sampling, keyed by node slot."""
     o = _c(o, np.float32); d = _c(d, np.float32)
     R = o.shape[1]
     ri, n = _sel(ray_idx, R)
@@ -139,19 +141,19 @@ def trace(tree: Tree, o, d, ray_idx=None, cap=None):
     t0 = np.zeros((n, cap)); t1 = np.zeros((n, cap))
     slot = np.full((n, cap), -1, np.int32); m = np.zeros(n, np.int32)
     rc = lib().orc_trace_rays(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(o), _p(d), R, _p(ri), n,
-                              cap, _p(t0), _p(t1), _p(slot), _p(m))
+                              cap, _p(t0), _p(t1), _p(slot), _p(m), float(footprint))
     if rc != 0:
         raise ValueError("orc_trace_rays failed")
     return t0, t1, slot, m
 
 
-def robust(tree: Tree, o, d, ray_idx=None, min_len=1e-5, eps=1e-6):
+def robust(tree: Tree, o, d, ray_idx=None, min_len=1e-5, eps=1e-6, footprint=0.0):
     o = _c(o, np.float32); d = _c(d, np.float32)
     R = o.shape[1]
     ri, n = _sel(ray_idx, R)
     out = np.zeros(n, np.int32)
     lib().orc_robust(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(o), _p(d), R, _p(ri), n,
-                     min_len, eps, _p(out))
+                     min_len, eps, _p(out), float(footprint))
     return out.astype(bool)
 
 
@@ -166,8 +168,9 @@ def mlp_eval(params_leaf, n_hidden, hidden, x, dirs, return_features=False):
 
 
 def render(tree: Tree, params, n_hidden, hidden, o, d, s_max, eps=1e-4, ray_idx=None,
-           jitter=False, seed=0, threads=None):
-    """Per-ray (rgb[n][3], depth[n], opacity[n], n_samples[n], flags[n]) in float64."""
+           jitter=False, seed=0, threads=None, footprint=0.0):
+    """Per-ray (rgb[n][3], depth[n], opacity[n], n_samples[n], flags[n]) in float64.  With
+    footprint > 0: hierarchical sampling, params holding one set per node (by node slot)."""
     params = _c(params, np.float32)
     o = _c(o, np.float32); d = _c(d, np.float32)
     R = o.shape[1]
@@ -177,13 +180,14 @@ def render(tree: Tree, params, n_hidden, hidden, o, d, s_max, eps=1e-4, ray_idx=
     threads = threads or min(16, os.cpu_count() or 1)
     rc = lib().orc_render(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(params), params.shape[0],
                           n_hidden, hidden, _p(o), _p(d), R, _p(ri), n, s_max, eps, int(jitter),
-                          seed, _p(rgb), _p(depth), _p(opac), _p(ns), _p(flags), threads)
+                          seed, _p(rgb), _p(depth), _p(opac), _p(ns), _p(flags), threads, float(footprint))
     if rc != 0:
         raise ValueError("orc_render failed")
     return rgb, depth, opac, ns, flags
 
 
-def ray_samples(tree: Tree, params, n_hidden, hidden, o, d, r, s_max, eps=1e-4, jitter=False, seed=0):
+def ray_samples(tree: Tree, params, n_hidden, hidden, o, d, r, s_max, eps=1e-4, jitter=False, seed=0,
+                footprint=0.0):
     """Front-to-back per-sample record of ray r as a dict of arrays."""
     params = _c(params, np.float32)
     o = _c(o, np.float32); d = _c(d, np.float32)
@@ -193,7 +197,7 @@ def ray_samples(tree: Tree, params, n_hidden, hidden, o, d, r, s_max, eps=1e-4, 
     ns = lib().orc_ray_samples(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(params), params.shape[0],
                                n_hidden, hidden, _p(o), _p(d), o.shape[1], int(r), s_max, eps,
                                int(jitter), seed, cap, _p(slot), _p(t), _p(de), _p(sg), _p(rgb),
-                               _p(w), _p(ray))
+                               _p(w), _p(ray), float(footprint))
     if ns < 0:
         raise ValueError("orc_ray_samples failed")
     return dict(slot=slot[:ns], t=t[:ns], delta=de[:ns], sigma=sg[:ns], rgb=rgb[:ns], w=w[:ns],
@@ -202,7 +206,7 @@ def ray_samples(tree: Tree, params, n_hidden, hidden, o, d, r, s_max, eps=1e-4, 
 
 
 def render_grad(tree: Tree, params, n_hidden, hidden, o, d, s_max, g_rgb, g_depth=None,
-                g_opac=None, eps=1e-4, ray_idx=None, jitter=False, seed=0):
+                g_opac=None, eps=1e-4, ray_idx=None, jitter=False, seed=0, footprint=0.0):
     """dL/dparams [L][P] (float64) for upstream gradients of the rendered outputs."""
     params = _c(params, np.float32)
     o = _c(o, np.float32); d = _c(d, np.float32)
@@ -214,7 +218,7 @@ def render_grad(tree: Tree, params, n_hidden, hidden, o, d, s_max, g_rgb, g_dept
     grad = np.zeros(params.shape, np.float64)
     rc = lib().orc_render_grad(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(params), params.shape[0],
                                n_hidden, hidden, _p(o), _p(d), R, _p(ri), n, s_max, eps, int(jitter),
-                               seed, _p(g_rgb), _p(gd), _p(ga), _p(grad))
+                               seed, _p(g_rgb), _p(gd), _p(ga), _p(grad), float(footprint))
     if rc != 0:
         raise ValueError("orc_render_grad failed")
     return grad

@@ -60,6 +60,7 @@ typedef struct {
   int axis, plane;    /* split (inner nodes); plane is a cell index */
   int child[2];
   int slot;           /* leaf rank in left-first depth-first order */
+  int nslot;          /* rank among all nodes in left-first depth-first preorder */
   uint64_t mass;
   int leaf;
 } onode;
@@ -89,8 +90,9 @@ static int splittable(const onode* nd, int max_depth) {
   return nd->depth < max_depth && nd->hi[a] - nd->lo[a] >= 2;
 }
 
-static int slot_counter;
+static int slot_counter, nslot_counter;
 static void assign_slots(onode* nodes, int i) {
+  nodes[i].nslot = nslot_counter++;   /* preorder: the node before its subtrees */
   if (nodes[i].leaf) { nodes[i].slot = slot_counter++; return; }
   assign_slots(nodes, nodes[i].child[0]);
   assign_slots(nodes, nodes[i].child[1]);
@@ -103,7 +105,8 @@ static int cmp_code(const void* a, const void* b) {
 }
 
 /* Builds the tree and exports it as rows of 12 int32, sorted by node code:
- *   code, depth, lo[3], hi[3], axis (-1 leaf), plane (-1 leaf), slot (-1 inner), 0
+ *   code, depth, lo[3], hi[3], axis (-1 leaf), plane (-1 leaf), slot (-1 inner), node slot
+ * (preorder rank among all nodes: the MLP index of a node under hierarchical sampling)
  * plus the integer mass of each node.  Returns 0, or -1 on bad arguments / capacity. */
 int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int split, int cap,
                    int32_t* rows, uint64_t* mass_out, int* n_nodes_out, int* n_leaves_out) {
@@ -176,6 +179,7 @@ int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int 
   free(q);
   if (nn > cap) { free(nodes); return -1; }
   slot_counter = 0;
+  nslot_counter = 0;
   for (int i = 0; i < nn; ++i) nodes[i].slot = -1;
   assign_slots(nodes, 0);
   int* order = (int*)malloc(sizeof(int) * nn);
@@ -190,7 +194,7 @@ int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int 
     row[8] = nd->leaf ? -1 : nd->axis;
     row[9] = nd->leaf ? -1 : nd->plane;
     row[10] = nd->leaf ? nd->slot : -1;
-    row[11] = 0;
+    row[11] = nd->nslot;
     if (mass_out) mass_out[k] = nd->mass;
   }
   free(order);
@@ -209,6 +213,8 @@ typedef struct {
   int* left;
   int* right;
   int root;
+  float footprint;    /* hierarchical sampling (HCheck) when > 0 */
+  float* t_stop;      /* per node: longest side / footprint, in float32 */
 } otree;
 
 static int find_code(const int32_t* rows, int nn, uint32_t code) {
@@ -222,14 +228,31 @@ static int find_code(const int32_t* rows, int nn, uint32_t code) {
   return -1;
 }
 
+/* Hierarchical sampling (Section 3.5, HCheck), read as a level-of-detail test: a node whose
+   longest side s is small next to the spacing of samples at the distance where the ray
+   enters it is not refined.  With the caller's footprint f (sample spacing per unit
+   distance), the descent continues into the children iff the entry parameter t satisfies
+   t <= s / f; both sides of the test in float32 (the quotient rounded once). */
+static int otree_init_hcheck(otree* T, const int32_t* rows, int nn, int grid_n, float footprint);
+
 static int otree_init(otree* T, const int32_t* rows, int nn, int grid_n) {
+  return otree_init_hcheck(T, rows, nn, grid_n, 0.0f);
+}
+
+static int otree_init_hcheck(otree* T, const int32_t* rows, int nn, int grid_n, float footprint) {
   T->nn = nn; T->rows = rows; T->grid_n = grid_n; T->n_leaves = 0;
+  T->footprint = footprint;
   T->left = (int*)malloc(sizeof(int) * nn);
   T->right = (int*)malloc(sizeof(int) * nn);
+  T->t_stop = (float*)malloc(sizeof(float) * nn);
   T->root = find_code(rows, nn, 1u);
   if (T->root < 0) return -1;
   for (int i = 0; i < nn; ++i) {
     const int32_t* r = rows + (int64_t)i * NODE_COLS;
+    int ext = 0;
+    for (int a = 0; a < 3; ++a) if (r[5 + a] - r[2 + a] > ext) ext = r[5 + a] - r[2 + a];
+    float side = (float)ext / (float)grid_n;
+    T->t_stop[i] = footprint > 0.0f ? side / footprint : INFINITY;
     if (r[8] < 0) { T->left[i] = T->right[i] = -1; T->n_leaves++; continue; }
     T->left[i] = find_code(rows, nn, 2u * (uint32_t)r[0]);
     T->right[i] = find_code(rows, nn, 2u * (uint32_t)r[0] + 1u);
@@ -238,7 +261,7 @@ static int otree_init(otree* T, const int32_t* rows, int nn, int grid_n) {
   return 0;
 }
 
-static void otree_free(otree* T) { free(T->left); free(T->right); }
+static void otree_free(otree* T) { free(T->left); free(T->right); free(T->t_stop); }
 
 /* ------------------------------------------------------------------------- */
 /* Traversal (Algorithm 1, Traverse)                                          */
@@ -248,10 +271,13 @@ typedef struct { double t0, t1; int slot; } oiv;
 typedef struct { oiv* iv; int m, cap; } ivlist;
 
 static void descend(const otree* T, int node, const double o[3], const double d[3],
-                    double t0, double t1, ivlist* L) {
+                    double t0, double t1, ivlist* L, int hcheck) {
   const int32_t* r = T->rows + (int64_t)node * NODE_COLS;
-  if (r[8] < 0) {
-    if (t1 > t0 && L->m < L->cap) { L->iv[L->m].t0 = t0; L->iv[L->m].t1 = t1; L->iv[L->m].slot = r[10]; }
+  /* a leaf, or an inner node where HCheck stops the descent: the node takes the segment
+     (keyed by its leaf slot, or by its preorder node slot under hierarchical sampling) */
+  if (r[8] < 0 || (hcheck && (float)t0 > T->t_stop[node])) {
+    int slot = hcheck ? r[11] : r[10];
+    if (t1 > t0 && L->m < L->cap) { L->iv[L->m].t0 = t0; L->iv[L->m].t1 = t1; L->iv[L->m].slot = slot; }
     if (t1 > t0) L->m++;
     return;
   }
@@ -260,19 +286,20 @@ static void descend(const otree* T, int node, const double o[3], const double d[
   if (d[a] == 0.0) {
     /* parallel to the plane: the whole segment lies on o's side (a point on the plane
        belongs to the upper cell, matching half-open cells [lo, hi)) */
-    descend(T, o[a] >= s ? T->right[node] : T->left[node], o, d, t0, t1, L);
+    descend(T, o[a] >= s ? T->right[node] : T->left[node], o, d, t0, t1, L, hcheck);
     return;
   }
   double ts = (s - o[a]) / d[a];
   int before = d[a] > 0.0 ? T->left[node] : T->right[node];
   int after = d[a] > 0.0 ? T->right[node] : T->left[node];
-  if (ts >= t1) descend(T, before, o, d, t0, t1, L);
-  else if (ts <= t0) descend(T, after, o, d, t0, t1, L);
-  else { descend(T, before, o, d, t0, ts, L); descend(T, after, o, d, ts, t1, L); }
+  if (ts >= t1) descend(T, before, o, d, t0, t1, L, hcheck);
+  else if (ts <= t0) descend(T, after, o, d, t0, t1, L, hcheck);
+  else { descend(T, before, o, d, t0, ts, L, hcheck); descend(T, after, o, d, ts, t1, L, hcheck); }
 }
 
-/* Root box [0,1]^3 slab test, then front-to-back descent; returns the interval count. */
-static int trace_ray(const otree* T, const double o[3], const double d[3], ivlist* L) {
+/* Root box [0,1]^3 slab test, then front-to-back descent; returns the interval count.
+   hcheck: stop the descent by HCheck (the tree's footprint must be > 0). */
+static int trace_ray_mode(const otree* T, const double o[3], const double d[3], ivlist* L, int hcheck) {
   L->m = 0;
   double tin = 0.0, tout = INFINITY;
   for (int a = 0; a < 3; ++a) {
@@ -286,8 +313,19 @@ static int trace_ray(const otree* T, const double o[3], const double d[3], ivlis
     if (tb < tout) tout = tb;
   }
   if (!(tin < tout)) return 0;
-  descend(T, T->root, o, d, tin, tout, L);
+  descend(T, T->root, o, d, tin, tout, L, hcheck);
   return L->m;
+}
+
+/* The intervals a render samples: HCheck's when the tree has a footprint, else the leaves'. */
+static int trace_ray(const otree* T, const double o[3], const double d[3], ivlist* L) {
+  return trace_ray_mode(T, o, d, L, T->footprint > 0.0f);
+}
+
+/* The ray's leaf-interval count, which sets the samples per interval in either mode. */
+static int leaf_count(const otree* T, const double o[3], const double d[3]) {
+  ivlist L = {NULL, 0, 0};
+  return trace_ray_mode(T, o, d, &L, 0);
 }
 
 static void load_ray(const float* o, const float* d, int64_t R, int64_t r, double oo[3], double dd[3]) {
@@ -296,9 +334,9 @@ static void load_ray(const float* o, const float* d, int64_t R, int64_t r, doubl
 
 int orc_trace_rays(const int32_t* rows, int nn, int grid_n, const float* o, const float* d,
                    int64_t R, const int64_t* ray_idx, int64_t n_sel, int cap,
-                   double* t0, double* t1, int32_t* slot, int32_t* m_out) {
+                   double* t0, double* t1, int32_t* slot, int32_t* m_out, float footprint) {
   otree T;
-  if (otree_init(&T, rows, nn, grid_n)) { otree_free(&T); return -1; }
+  if (otree_init_hcheck(&T, rows, nn, grid_n, footprint)) { otree_free(&T); return -1; }
   oiv* buf = (oiv*)malloc(sizeof(oiv) * (T.n_leaves + 1));
   for (int64_t s = 0; s < n_sel; ++s) {
     int64_t r = ray_idx ? ray_idx[s] : s;
@@ -320,9 +358,9 @@ int orc_trace_rays(const int32_t* rows, int nn, int grid_n, const float* o, cons
    unchanged when o moves by +-eps along each axis.  Node ids are compared only there. */
 int orc_robust(const int32_t* rows, int nn, int grid_n, const float* o, const float* d,
                int64_t R, const int64_t* ray_idx, int64_t n_sel, double min_len, double eps,
-               int32_t* robust) {
+               int32_t* robust, float footprint) {
   otree T;
-  if (otree_init(&T, rows, nn, grid_n)) { otree_free(&T); return -1; }
+  if (otree_init_hcheck(&T, rows, nn, grid_n, footprint)) { otree_free(&T); return -1; }
   int cap = T.n_leaves + 1;
   oiv* a = (oiv*)malloc(sizeof(oiv) * cap);
   oiv* b = (oiv*)malloc(sizeof(oiv) * cap);
@@ -369,16 +407,20 @@ static double stratum_offset(int jitter, uint64_t seed, int64_t r, int k) {
   return (double)(h >> 40) * (1.0 / 16777216.0);
 }
 
-/* Equal count per interval: n = max(1, floor(S_max/m)); when m > S_max only the first
-   S_max intervals receive one sample each. */
+/* Equal count per interval: n = max(1, floor(S_max/m)) for a ray crossing m leaves; when
+   m > S_max only the first S_max intervals receive one sample each.  Under hierarchical
+   sampling the ray has m' <= m intervals and each still gets the leaf share n (a node
+   that stops the descent is sampled like one leaf interval). */
 static int samples_per_interval(int m, int s_max) { return m <= s_max ? s_max / m : 1; }
 
 typedef struct { int slot; double t, delta; } osample;
 
-static int make_samples(const oiv* iv, int m, int s_max, int jitter, uint64_t seed, int64_t r,
+/* m: the ray's intervals in iv; m_leaf: its leaf-interval count (m_leaf = m without
+   hierarchical sampling). */
+static int make_samples(const oiv* iv, int m, int m_leaf, int s_max, int jitter, uint64_t seed, int64_t r,
                         osample* out) {
   if (m == 0) return 0;
-  int n = samples_per_interval(m, s_max);
+  int n = samples_per_interval(m_leaf, s_max);
   int meff = m <= s_max ? m : s_max;
   int c = 0;
   for (int k = 0; k < meff; ++k) {
@@ -503,7 +545,8 @@ static void render_ray(const octx* C, int64_t r, oiv* ivbuf, osample* sbuf, oray
   load_ray(C->o, C->d, C->R, r, oo, dd);
   ivlist L = {ivbuf, 0, C->T->n_leaves + 1};
   int m = trace_ray(C->T, oo, dd, &L);
-  int ns = make_samples(ivbuf, m, C->s_max, C->jitter, C->seed, r, sbuf);
+  int m_leaf = C->T->footprint > 0.0f ? leaf_count(C->T, oo, dd) : m;
+  int ns = make_samples(ivbuf, m, m_leaf, C->s_max, C->jitter, C->seed, r, sbuf);
   memset(res, 0, sizeof(*res));
   res->m = m;
   res->n_samples = ns;
@@ -538,11 +581,13 @@ static void render_ray(const octx* C, int64_t r, oiv* ivbuf, osample* sbuf, oray
   res->n_used = used;
 }
 
+/* n_leaves: parameter sets in params, one per leaf (one per node under hierarchical
+   sampling, footprint > 0). */
 static int make_ctx(octx* C, otree* T, olayout* L, double** P, const int32_t* rows, int nn, int grid_n,
-                    const float* params, int n_leaves, int n_hidden, int hidden) {
-  if (otree_init(T, rows, nn, grid_n)) return -1;
+                    const float* params, int n_leaves, int n_hidden, int hidden, float footprint) {
+  if (otree_init_hcheck(T, rows, nn, grid_n, footprint)) return -1;
   if (make_layout(n_hidden, hidden, L)) return -1;
-  if (T->n_leaves != n_leaves) return -1;
+  if ((footprint > 0.0f ? T->nn : T->n_leaves) != n_leaves) return -1;
   *P = (double*)malloc(sizeof(double) * (int64_t)n_leaves * L->P);
   for (int64_t i = 0; i < (int64_t)n_leaves * L->P; ++i) (*P)[i] = (double)params[i];
   C->T = T; C->L = L; C->P = *P;
@@ -554,10 +599,10 @@ int orc_render(const int32_t* rows, int nn, int grid_n, const float* params, int
                int n_hidden, int hidden, const float* o, const float* d, int64_t R,
                const int64_t* ray_idx, int64_t n_sel, int s_max, double eps, int jitter,
                uint64_t seed, double* rgb, double* depth, double* opac, int32_t* n_samples,
-               int32_t* flags, int n_threads) {
+               int32_t* flags, int n_threads, float footprint) {
   if (s_max < 1) return -1;
   otree T; olayout L; double* P = NULL; octx C;
-  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden)) {
+  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden, footprint)) {
     free(P); otree_free(&T); return -1;
   }
   C.o = o; C.d = d; C.R = R; C.s_max = s_max; C.eps = eps; C.jitter = jitter; C.seed = seed;
@@ -591,9 +636,9 @@ int orc_ray_samples(const int32_t* rows, int nn, int grid_n, const float* params
                     int n_hidden, int hidden, const float* o, const float* d, int64_t R,
                     int64_t r, int s_max, double eps, int jitter, uint64_t seed, int cap,
                     int32_t* slot, double* t, double* delta, double* sigma, double* rgb3,
-                    double* w, double* ray_out /* rgb3, depth, opac, flags, n_used */) {
+                    double* w, double* ray_out /* rgb3, depth, opac, flags, n_used */, float footprint) {
   otree T; olayout L; double* P = NULL; octx C;
-  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden)) {
+  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden, footprint)) {
     free(P); otree_free(&T); return -1;
   }
   C.o = o; C.d = d; C.R = R; C.s_max = s_max; C.eps = eps; C.jitter = jitter; C.seed = seed;
@@ -633,9 +678,9 @@ int orc_render_grad(const int32_t* rows, int nn, int grid_n, const float* params
                     int n_hidden, int hidden, const float* o, const float* d, int64_t R,
                     const int64_t* ray_idx, int64_t n_sel, int s_max, double eps, int jitter,
                     uint64_t seed, const double* g_rgb, const double* g_depth,
-                    const double* g_opac, double* grad) {
+                    const double* g_opac, double* grad, float footprint) {
   otree T; olayout L; double* P = NULL; octx C;
-  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden)) {
+  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden, footprint)) {
     free(P); otree_free(&T); return -1;
   }
   C.o = o; C.d = d; C.R = R; C.s_max = s_max; C.eps = eps; C.jitter = jitter; C.seed = seed;
@@ -654,7 +699,8 @@ int orc_render_grad(const int32_t* rows, int nn, int grid_n, const float* params
     load_ray(o, d, R, r, oo, dd);
     ivlist IL = {ivbuf, 0, T.n_leaves + 1};
     int m = trace_ray(&T, oo, dd, &IL);
-    int ns = make_samples(ivbuf, m, s_max, jitter, seed, r, sbuf);
+    int m_leaf = T.footprint > 0.0f ? leaf_count(&T, oo, dd) : m;
+    int ns = make_samples(ivbuf, m, m_leaf, s_max, jitter, seed, r, sbuf);
     /* forward, keeping activations */
     double S = 0.0, Cc[3] = {0, 0, 0}, D = 0.0, A = 0.0;
     int J = ns;
@@ -901,7 +947,7 @@ int orc_render_proposal(const int32_t* rows, int nn, int grid_n, const float* pa
                         int32_t* plan_sel, double* mass, int n_threads) {
   if (s_max < 1 || cap < 1) return -1;
   otree T; olayout L; double* P = NULL; octx C;
-  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden)) {
+  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden, 0.0f)) {
     free(P); otree_free(&T); return -1;
   }
   double* PP = (double*)malloc(sizeof(double) * PROP_P);
@@ -919,7 +965,7 @@ int orc_render_proposal(const int32_t* rows, int nn, int grid_n, const float* pa
       load_ray(o, d, R, r, oo, dd);
       ivlist IL = {ivbuf, 0, T.n_leaves + 1};
       int m = trace_ray(&T, oo, dd, &IL);
-      int ns = make_samples(ivbuf, m, s_max, 0, 0, r, sbuf);
+      int ns = make_samples(ivbuf, m, m, s_max, 0, 0, r, sbuf);
       oplan pl;
       plan_ray(&T, PP, oo, dd, ivbuf, m, s_max, mass_thresh, cap, &pl, sel, p);
       int use = pl.n_sel < 0 ? ns : pl.n_sel;
@@ -995,7 +1041,7 @@ int64_t orc_prop_targets(const int32_t* rows, int nn, int grid_n, const float* p
                          int hidden, const float* o, const float* d, int64_t R, const int64_t* ray_idx,
                          int64_t n_sel, int s_max, int64_t cap, double* alpha) {
   otree T; olayout L; double* P = NULL; octx C;
-  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden)) {
+  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden, 0.0f)) {
     free(P); otree_free(&T); return -1;
   }
   oiv* ivbuf = (oiv*)malloc(sizeof(oiv) * (T.n_leaves + 1));
@@ -1007,7 +1053,7 @@ int64_t orc_prop_targets(const int32_t* rows, int nn, int grid_n, const float* p
     load_ray(o, d, R, r, oo, dd);
     ivlist IL = {ivbuf, 0, T.n_leaves + 1};
     int m = trace_ray(&T, oo, dd, &IL);
-    make_samples(ivbuf, m, s_max, 0, 0, r, sbuf);
+    make_samples(ivbuf, m, m, s_max, 0, 0, r, sbuf);
     int n = m == 0 ? 0 : samples_per_interval(m, s_max);
     int meff = m <= s_max ? m : s_max;
     for (int k = 0; k < meff; ++k, ++c) {

@@ -84,7 +84,8 @@ class amnerf_proposal(C.Structure):
 
 class amnerf_render_params(C.Structure):
     _fields_ = [("s_max", C.c_int32), ("ert_eps", C.c_float), ("flags", C.c_uint32),
-                ("jitter_seed", C.c_uint64), ("proposal", C.POINTER(amnerf_proposal))]
+                ("jitter_seed", C.c_uint64), ("proposal", C.POINTER(amnerf_proposal)),
+                ("hcheck_footprint", C.c_float)]
 
 
 class amnerf_render_out(C.Structure):
@@ -261,10 +262,10 @@ def amnerf_mlp_pack(ctx, n_hidden: int, hidden: int, dtype: int, n_leaves: int, 
 
 def amnerf_render(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, s_max: int, rgb_dev, depth_dev=None,
                   opacity_dev=None, weights_dev=None, ert_eps: float = 1e-4, jitter: bool = False,
-                  seed: int = 0, stream=None, proposal: "amnerf_proposal" = None):
+                  seed: int = 0, stream=None, proposal: "amnerf_proposal" = None, hcheck_footprint: float = 0.0):
     rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]) if o_dev is not None else 0)
     prm = amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed,
-                               C.pointer(proposal) if proposal is not None else None)
+                               C.pointer(proposal) if proposal is not None else None, hcheck_footprint)
     out = amnerf_render_out(_ptr(rgb_dev), _ptr(depth_dev), _ptr(opacity_dev), _ptr(weights_dev))
     _check(_lib.amnerf_render(ctx, tree, C.byref(mlp), C.byref(rays), C.byref(prm), C.byref(out),
                               _stream(stream)))
@@ -325,9 +326,10 @@ def amnerf_error_stats(ctx, x_dev, ref_dev, sel_dev=None, stream=None):
 
 def amnerf_train_step(ctx, tree, train: amnerf_mlp_train, o_dev, d_dev, target_dev, loss_dev, s_max, step,
                       lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, ert_eps=1e-4, jitter=False, seed=0,
-                      grad_only=False, stream=None):
+                      grad_only=False, stream=None, hcheck_footprint=0.0):
     rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]))
-    prm = amnerf_train_params(amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed, None),
+    prm = amnerf_train_params(amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed, None,
+                                                   hcheck_footprint),
                               amnerf_adam_params(lr, beta1, beta2, eps, step),
                               AMNERF_GRAD_ONLY if grad_only else 0)
     _check(_lib.amnerf_train_step(ctx, tree, C.byref(train), C.byref(rays), _ptr(target_dev), C.byref(prm),
@@ -420,7 +422,7 @@ class Mlp:
 
 
 def render(ctx: Context, tree: Tree, mlp: Mlp, o_dev, d_dev, s_max, ert_eps=1e-4, jitter=False, seed=0,
-           weights=False, stream=None):
+           weights=False, stream=None, hcheck_footprint=0.0):
     """Allocates the outputs and renders; returns dict of device tensors."""
     import torch
     R = int(o_dev.shape[1])
@@ -431,21 +433,21 @@ def render(ctx: Context, tree: Tree, mlp: Mlp, o_dev, d_dev, s_max, ert_eps=1e-4
     if weights:
         out["weights"] = torch.zeros(R * s_max, dtype=torch.float32, device=dev)
     amnerf_render(ctx.h, tree.h, mlp.desc, o_dev, d_dev, s_max, out["rgb"], out["depth"], out["opacity"],
-                  out.get("weights"), ert_eps, jitter, seed, stream)
+                  out.get("weights"), ert_eps, jitter, seed, stream, hcheck_footprint=hcheck_footprint)
     return out
 
 
 class Trainer:
     """Float32 masters, gradient and Adam moments of a leaf-MLP set, plus its bf16 packed block."""
 
-    def __init__(self, ctx: Context, tree: Tree, master_dev, n_hidden, hidden):
+    def __init__(self, ctx: Context, tree: Tree, master_dev, n_hidden, hidden, n_sets=None):
         import torch
         self.ctx, self.tree = ctx, tree
         self.master = master_dev.contiguous()
         self.grad = torch.zeros_like(self.master)
         self.m = torch.zeros_like(self.master)
         self.v = torch.zeros_like(self.master)
-        L = tree.n_leaves
+        L = tree.n_leaves if n_sets is None else n_sets   # n_nodes for hierarchical sampling
         nbytes = amnerf_mlp_packed_bytes(n_hidden, hidden, AMNERF_BF16, L)
         self.packed = torch.empty(nbytes, dtype=torch.uint8, device=self.master.device)
         amnerf_mlp_pack(ctx.h, n_hidden, hidden, AMNERF_BF16, L, self.master, self.packed)

@@ -102,6 +102,7 @@ struct amnerf_tree {
   std::vector<uint64_t> mass;
   DevNode* dev_nodes = nullptr;
   float* dev_leafbox = nullptr;   // per leaf slot: 2*centre-1 (3), size (3), in [0,1] units
+  DevNodeAhs* dev_ahs = nullptr;  // per device-table node: longest side, preorder node slot
 };
 
 // ---------------------------------------------------------------------------------------
@@ -260,6 +261,7 @@ struct HNode {
   int axis = -1, plane = -1;
   int left = -1;     // index of the lower child; the upper child follows it
   int slot = -1;
+  int nslot = -1;    // rank among all nodes in left-first depth-first preorder
   uint64_t mass = 0;
 };
 
@@ -395,12 +397,13 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
     if (splittable(nodes[li])) pq.push({prio(nodes[li]), nodes[li].code, li});
     if (splittable(nodes[li + 1])) pq.push({prio(nodes[li + 1]), nodes[li + 1].code, li + 1});
   }
-  // slots: left-first depth-first order
-  int next_slot = 0, max_depth = 0;
+  // slots: left-first depth-first order (leaves among leaves; every node among all nodes)
+  int next_slot = 0, next_nslot = 0, max_depth = 0;
   std::vector<int> stack = {0};
   while (!stack.empty()) {
     int i = stack.back();
     stack.pop_back();
+    nodes[i].nslot = next_nslot++;
     if (nodes[i].left < 0) {
       nodes[i].slot = next_slot++;
       max_depth = std::max(max_depth, nodes[i].depth);
@@ -429,11 +432,12 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
     r[8] = nd.left < 0 ? -1 : nd.axis;
     r[9] = nd.left < 0 ? -1 : nd.plane;
     r[10] = nd.slot;
-    r[11] = 0;
+    r[11] = nd.nslot;
     t->mass[k] = nd.mass;
   }
   // device table: breadth-first, siblings adjacent
   std::vector<DevNode> dev(nodes.size());
+  std::vector<DevNodeAhs> ahs(nodes.size());
   std::vector<int> bfs = {0};
   std::vector<int> at(nodes.size(), -1);
   at[0] = 0;
@@ -441,6 +445,10 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
   for (size_t q = 0; q < bfs.size(); ++q) {
     int i = bfs[q];
     DevNode& dn = dev[at[i]];
+    int ext = 0;
+    for (int a = 0; a < 3; ++a) ext = std::max(ext, nodes[i].hi[a] - nodes[i].lo[a]);
+    ahs[at[i]].size = (float)ext / (float)n;   // exact: a small integer over a power of two
+    ahs[at[i]].slot = (uint32_t)nodes[i].nslot;
     if (nodes[i].left < 0) {
       dn.plane = 0.f;
       dn.info = -(nodes[i].slot + 1);
@@ -468,9 +476,12 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
   if (e == hipSuccess) e = hipMemcpy(t->dev_nodes, dev.data(), sizeof(DevNode) * dev.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc((void**)&t->dev_leafbox, sizeof(float) * box.size());
   if (e == hipSuccess) e = hipMemcpy(t->dev_leafbox, box.data(), sizeof(float) * box.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&t->dev_ahs, sizeof(DevNodeAhs) * ahs.size());
+  if (e == hipSuccess) e = hipMemcpy(t->dev_ahs, ahs.data(), sizeof(DevNodeAhs) * ahs.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     if (t->dev_nodes) (void)hipFree(t->dev_nodes);
     if (t->dev_leafbox) (void)hipFree(t->dev_leafbox);
+    if (t->dev_ahs) (void)hipFree(t->dev_ahs);
     delete t;
     return fail(AMNERF_EDEVICE, "amnerf_build_tree: upload: %s", hipGetErrorString(e));
   }
@@ -501,6 +512,7 @@ extern "C" int amnerf_tree_destroy(amnerf_tree* t) {
     (void)hipDeviceSynchronize();
     (void)hipFree(t->dev_nodes);
     if (t->dev_leafbox) (void)hipFree(t->dev_leafbox);
+    if (t->dev_ahs) (void)hipFree(t->dev_ahs);
   }
   delete t;
   return AMNERF_OK;
@@ -653,8 +665,20 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   MlpGeom g;
   int rc = check_geom(&mlp->shape, mlp->dtype, &g, "amnerf_render");
   if (rc) return rc;
-  if (mlp->n_leaves != tree->n_leaves)
-    return fail(AMNERF_EINVAL, "amnerf_render: MLP has %d leaves, tree has %d", mlp->n_leaves, tree->n_leaves);
+  if (!(p->hcheck_footprint >= 0.f) || !std::isfinite(p->hcheck_footprint))
+    return fail(AMNERF_EINVAL, "amnerf_render: hcheck_footprint must be finite and >= 0");
+  const bool ahs = p->hcheck_footprint > 0.f;
+  const int n_nodes = (int)tree->mass.size();
+  // MLP parameter sets: one per leaf, or one per node under hierarchical sampling
+  const int n_sets = ahs ? n_nodes : tree->n_leaves;
+  if (ahs && n_sets > AMNERF_MAX_LEAVES)
+    return fail(AMNERF_ECAPACITY, "amnerf_render: hierarchical sampling needs %d node MLPs (at most %d)", n_sets,
+                AMNERF_MAX_LEAVES);
+  if (mlp->n_leaves != n_sets)
+    return fail(AMNERF_EINVAL, "amnerf_render: MLP has %d parameter sets, the render needs %d (one per %s)",
+                mlp->n_leaves, n_sets, ahs ? "node" : "leaf");
+  if (ahs && p->proposal)
+    return fail(AMNERF_EINVAL, "amnerf_render: proposal sampling runs on leaf intervals (no hierarchical sampling)");
   if (!mlp->packed_dev) return fail(AMNERF_EINVAL, "amnerf_render: packed parameters are NULL");
   if (rays->n_rays < 0) return fail(AMNERF_EINVAL, "amnerf_render: n_rays < 0");
   if (rays->n_rays > 0 && (!rays->o_dev || !rays->d_dev)) return fail(AMNERF_EINVAL, "amnerf_render: ray arrays are NULL");
@@ -668,9 +692,11 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const int64_t R = rays->n_rays;
-  const uint32_t L = (uint32_t)tree->n_leaves;
+  const uint32_t L = (uint32_t)n_sets;
   const int jitter = (p->flags & AMNERF_JITTER) ? 1 : 0;
-  const uint64_t iv_per_ray = std::min<uint64_t>((uint64_t)p->s_max, L);
+  // a ray has at most one interval per leaf, and hierarchical sampling only merges them
+  const uint64_t iv_per_ray = std::min<uint64_t>((uint64_t)p->s_max, (uint64_t)tree->n_leaves);
+  const DevNodeAhs* ahs_tab = ahs ? tree->dev_ahs : nullptr;
   uint64_t chunk = std::max<uint64_t>(1, kChunkSamples / (uint64_t)p->s_max);
   if (R > 0 && (uint64_t)R < chunk) chunk = (uint64_t)R;
   const uint64_t niv_max = chunk * iv_per_ray, ns_max = chunk * (uint64_t)p->s_max;
@@ -693,9 +719,9 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
     }
     auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev->ev[k], st) : hipSuccess; };
     HIP_TRY(mark(0));
-    HIP_TRY(launch_trav_count(tree->dev_nodes, (uint32_t)tree->mass.size(), tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, p->s_max, w.cnt_iv, w.cnt_smp, st));
+    HIP_TRY(launch_trav_count(tree->dev_nodes, ahs_tab, p->hcheck_footprint, (uint32_t)n_nodes, tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, p->s_max, w.cnt_iv, w.cnt_smp, st));
     HIP_TRY(launch_scan_u32_pair(w.cnt_iv, w.iv_off, w.cnt_smp, w.smp_off, nr, w.scan_tmp, st));
-    HIP_TRY(launch_trav_emit(tree->dev_nodes, (uint32_t)tree->mass.size(), tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
+    HIP_TRY(launch_trav_emit(tree->dev_nodes, ahs_tab, p->hcheck_footprint, (uint32_t)n_nodes, tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
                              w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, st));
     HIP_TRY(mark(1));
     const IvSet plain = {w.iv_off, w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, w.iv_off + nr};
@@ -870,7 +896,10 @@ int backward_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* ml
   if (ctx->last_chunks != 1) return fail(AMNERF_ESTATE, "amnerf_render_backward: the last render ran in %lld chunks",
                                          (long long)ctx->last_chunks);
   if (!grad || (rays->n_rays > 0 && !g_rgb)) return fail(AMNERF_EINVAL, "amnerf_render_backward: null gradient pointer");
-  const uint64_t L = (uint64_t)tree->n_leaves;
+  if (mlp->n_leaves != (int)ctx->last_leaves)
+    return fail(AMNERF_EINVAL, "amnerf_render_backward: MLP has %d parameter sets, the last render used %u",
+                mlp->n_leaves, ctx->last_leaves);
+  const uint64_t L = (uint64_t)ctx->last_leaves;   // parameter sets of that render
   const uint64_t P = (uint64_t)amnerf_mlp_param_count(&mlp->shape);
   const uint64_t ns = ctx->last_ns_max, R = (uint64_t)rays->n_rays;
   const uint64_t tiles = ns / kMlpTileRows + L;
@@ -949,7 +978,7 @@ extern "C" int amnerf_train_step(amnerf_ctx* ctx, const amnerf_tree* tree, amner
   // outputs of the forward pass live in the second arena: size it before rendering
   BwdWork w;
   {
-    const uint64_t L = (uint64_t)tree->n_leaves;
+    const uint64_t L = (uint64_t)std::max(1, m->n_leaves);
     const uint64_t P = (uint64_t)amnerf_mlp_param_count(&m->shape);
     uint64_t chunk = std::max<uint64_t>(1, kChunkSamples / (uint64_t)std::max(1, p->render.s_max));
     if (R > chunk) return fail(AMNERF_ECAPACITY, "amnerf_train_step: %llu rays exceed one pass (%llu)",

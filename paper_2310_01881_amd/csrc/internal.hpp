@@ -16,6 +16,13 @@ struct DevNode {
   int32_t info;
 };
 
+// Per node, for hierarchical sampling: the longest side of its box in [0,1] units and its
+// rank among all nodes in left-first depth-first preorder (its MLP slot).
+struct DevNodeAhs {
+  float size;
+  uint32_t slot;
+};
+
 // Per-chunk totals produced on the device (the host never waits for them mid-render).
 struct ChunkCounts {
   uint32_t n_iv;        // intervals that carry samples (this chunk)
@@ -36,11 +43,12 @@ constexpr int kScanItems = 2048;        // elements per scan block (256 threads 
 // ---- traversal (Algorithm 1: Traverse) -------------------------------------------------
 // Pass 1: per ray, the number of leaf intervals that receive samples (min(m, s_max)) and
 // the number of samples.  Pass 2: the intervals themselves, ray-major, at iv_off.
-hipError_t launch_trav_count(const DevNode* nodes, uint32_t n_nodes, int depth, const float* o, const float* d,
-                             int64_t ray_stride, int64_t r0, uint32_t nr, int s_max,
+// `ahs` NULL: leaf intervals; else hierarchical sampling with the given footprint.
+hipError_t launch_trav_count(const DevNode* nodes, const DevNodeAhs* ahs, float footprint, uint32_t n_nodes, int depth,
+                             const float* o, const float* d, int64_t ray_stride, int64_t r0, uint32_t nr, int s_max,
                              uint32_t* cnt_iv, uint32_t* cnt_smp, hipStream_t st);
-hipError_t launch_trav_emit(const DevNode* nodes, uint32_t n_nodes, int depth, const float* o, const float* d,
-                            int64_t ray_stride, int64_t r0, uint32_t nr,
+hipError_t launch_trav_emit(const DevNode* nodes, const DevNodeAhs* ahs, float footprint, uint32_t n_nodes, int depth,
+                            const float* o, const float* d, int64_t ray_stride, int64_t r0, uint32_t nr,
                             const uint32_t* cnt_iv, const uint32_t* cnt_smp,
                             const uint32_t* iv_off, const uint32_t* smp_off, float* iv_t0,
                             float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray, uint32_t* iv_base,

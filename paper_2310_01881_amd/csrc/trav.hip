@@ -51,15 +51,39 @@ constexpr int kLdsNodes = 2048;  // node tables up to this size are staged in LD
 
 __device__ __forceinline__ float axis_val(const float v[3], int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); }
 
+// Hierarchical sampling (HCheck): the descent stops at an inner node when the ray enters
+// it farther than the node's stopping distance t_stop = size / footprint (size: the node's
+// longest side; footprint: the caller's sample footprint per unit distance), and the node's
+// own MLP then takes the ray's whole segment in it.  Both the decision (float32 entry
+// parameter against float32 t_stop) and t_stop (one correctly rounded float32 division)
+// are fixed to the bit.  Two views of the per-node data: staged in LDS as (t_stop, slot)
+// pairs, or read from memory with t_stop formed on the fly.
+struct AhsNone {
+  __device__ float tstop(int) const { return __builtin_inff(); }
+  __device__ uint32_t slot(int) const { return 0u; }
+};
+struct AhsLds {
+  const float2* p;
+  __device__ float tstop(int i) const { return p[i].x; }
+  __device__ uint32_t slot(int i) const { return __builtin_bit_cast(uint32_t, p[i].y); }
+};
+struct AhsMem {
+  const DevNodeAhs* p;
+  float footprint;
+  __device__ float tstop(int i) const { return __fdiv_rn(p[i].size, footprint); }
+  __device__ uint32_t slot(int i) const { return p[i].slot; }
+};
+
 // Traverses one ray.  EMIT = false: returns the interval count, stopping once it exceeds
-// cap.  EMIT = true: writes the first `cap` intervals through the output pointers.
+// cap.  EMIT = true: writes the first `cap` intervals through the output pointers.  AHS:
+// stop the descent by HCheck, and key intervals by the node's preorder slot.
 __device__ __forceinline__ uint32_t push_word(int node, float lo) {
   return (uint32_t)node | ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)lo) << 16);
 }
 __device__ __forceinline__ float word_lo(uint32_t w) { return (float)__builtin_bit_cast(__bf16, (uint16_t)(w >> 16)); }
 
-template <bool EMIT, typename NodePtr, typename Put>
-__device__ int traverse(NodePtr nodes, const float o[3], const float dir[3], int cap, uint32_t n_per,
+template <bool EMIT, bool AHS, typename NodePtr, typename Ahs, typename Put>
+__device__ int traverse(NodePtr nodes, const Ahs ahs, const float o[3], const float dir[3], int cap, uint32_t n_per,
                         uint32_t* st_word, float* st_hi, Put put) {
   // root box [0,1]^3
   DF tin = {0.f, 0.f}, tout = {__builtin_inff(), 0.f};
@@ -83,6 +107,7 @@ __device__ int traverse(NodePtr nodes, const float o[3], const float dir[3], int
   while (true) {
     int info = nodes[node].info;
     while (info >= 0) {
+      if (AHS && t0.hi > ahs.tstop(node)) break;
       int a = info & 3;
       int left = info >> 2;
       float s = nodes[node].plane;
@@ -107,12 +132,14 @@ __device__ int traverse(NodePtr nodes, const float o[3], const float dir[3], int
       }
       info = nodes[node].info;
     }
-    // leaf interval [t0, t1], t1 > t0 by construction
+    // interval [t0, t1] of a leaf (or, with AHS, of a node HCheck stopped at), t1 > t0 by
+    // construction
     if (EMIT) {
       if (m < cap) {
         float dh = t1.hi - t0.hi;
         float dt = dh + (t1.lo - t0.lo);
-        put(m, t0.hi, dt, (uint32_t)(-(info + 1)) | (n_per << 16));
+        const uint32_t slot = AHS ? ahs.slot(node) : (uint32_t)(-(info + 1));
+        put(m, t0.hi, dt, slot | (n_per << 16));
       }
     }
     ++m;
@@ -126,23 +153,35 @@ __device__ int traverse(NodePtr nodes, const float o[3], const float dir[3], int
   return m;
 }
 
-// The block's copy of the node table (LDS = true) or the table in memory, and the stack.
+// The block's copy of the node table (LDS = true) or the table in memory, the per-node
+// hierarchical-sampling data (staged with the table when AHS), and the stack.
 struct TravLds {
   const DevNode* nodes;
+  const float2* ahs;
   uint32_t* st_word;
   float* st_hi;
 };
 
-template <bool LDS>
-__device__ __forceinline__ TravLds stage(const DevNode* __restrict__ nodes, uint32_t n_nodes, int stack_n,
-                                         uint8_t* dyn) {
+template <bool LDS, bool AHS>
+__device__ __forceinline__ TravLds stage(const DevNode* __restrict__ nodes, const DevNodeAhs* __restrict__ ahs,
+                                         float footprint, uint32_t n_nodes, int stack_n, uint8_t* dyn) {
   TravLds t;
   uint8_t* p = dyn;
+  t.ahs = nullptr;
   if (LDS) {
     DevNode* s = reinterpret_cast<DevNode*>(p);
     for (uint32_t i = threadIdx.x; i < n_nodes; i += kBlock) s[i] = nodes[i];
     p += sizeof(DevNode) * n_nodes;
     t.nodes = s;
+    if (AHS) {
+      float2* a = reinterpret_cast<float2*>(p);
+      for (uint32_t i = threadIdx.x; i < n_nodes; i += kBlock) {
+        const DevNodeAhs v = ahs[i];
+        a[i] = make_float2(__fdiv_rn(v.size, footprint), __builtin_bit_cast(float, v.slot));
+      }
+      p += sizeof(float2) * n_nodes;
+      t.ahs = a;
+    }
   } else {
     t.nodes = nodes;
   }
@@ -152,19 +191,33 @@ __device__ __forceinline__ TravLds stage(const DevNode* __restrict__ nodes, uint
   return t;
 }
 
-__host__ __device__ constexpr uint32_t trav_lds_bytes(bool lds, uint32_t n_nodes, int stack_n) {
-  return (lds ? (uint32_t)sizeof(DevNode) * n_nodes : 0u) + 8u * (uint32_t)stack_n * kBlock;
+__host__ __device__ constexpr uint32_t trav_lds_bytes(bool lds, bool ahs, uint32_t n_nodes, int stack_n) {
+  return (lds ? (uint32_t)(sizeof(DevNode) + (ahs ? sizeof(float2) : 0u)) * n_nodes : 0u) +
+         8u * (uint32_t)stack_n * kBlock;
 }
 
-template <bool LDS>
-__global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict__ nodes, uint32_t n_nodes,
+// Runs `f` with the hierarchical-sampling view that matches the staging.
+template <bool LDS, bool AHS, typename F>
+__device__ __forceinline__ int with_ahs(const TravLds& tl, const DevNodeAhs* ahs, float footprint, F f) {
+  if constexpr (!AHS) return f(AhsNone{});
+  else if constexpr (LDS) return f(AhsLds{tl.ahs});
+  else return f(AhsMem{ahs, footprint});
+}
+
+// Counts.  Samples per interval follow the ray's leaf-interval count m (s_max / m, or 1
+// when m > s_max); with AHS the intervals are those of the HCheck traversal, so a node that
+// stops the descent gets one interval's share however many leaves it covers.
+template <bool LDS, bool AHS>
+__global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict__ nodes,
+                                                       const DevNodeAhs* __restrict__ ahs, float footprint,
+                                                       uint32_t n_nodes,
                                                        int stack_n, const float* __restrict__ o,
                                                        const float* __restrict__ d,
                                                        int64_t stride, int64_t r0, uint32_t nr,
                                                        int s_max, uint32_t* __restrict__ cnt_iv,
                                                        uint32_t* __restrict__ cnt_smp) {
   extern __shared__ __align__(16) uint8_t dyn[];
-  const TravLds tl = stage<LDS>(nodes, n_nodes, stack_n, dyn);
+  const TravLds tl = stage<LDS, AHS>(nodes, ahs, footprint, n_nodes, stack_n, dyn);
   uint32_t r = blockIdx.x * kBlock + threadIdx.x;
   bool live = r < nr;
   float oo[3] = {0.f, 0.f, 0.f}, dd[3] = {0.f, 0.f, 1.f};
@@ -175,12 +228,19 @@ __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict
       dd[a] = d[a * stride + r0 + r];
     }
   }
-  int m = 0;
+  int m = 0, mi = 0;
   // skip the descent for a wave whose rays are all out of range
-  if (__ballot(live) != 0 && live)
-    m = traverse<false>(tl.nodes, oo, dd, s_max, 0, tl.st_word, tl.st_hi, [](int, float, float, uint32_t) {});
+  if (__ballot(live) != 0 && live) {
+    auto none = [](int, float, float, uint32_t) {};
+    m = traverse<false, false>(tl.nodes, AhsNone{}, oo, dd, s_max, 0, tl.st_word, tl.st_hi, none);
+    mi = m;
+    if (AHS && m > 0)
+      mi = with_ahs<LDS, AHS>(tl, ahs, footprint, [&](auto av) {
+        return traverse<false, AHS>(tl.nodes, av, oo, dd, s_max, 0, tl.st_word, tl.st_hi, none);
+      });
+  }
   if (live) {
-    uint32_t meff = m <= s_max ? (uint32_t)m : (uint32_t)s_max;
+    uint32_t meff = mi <= s_max ? (uint32_t)mi : (uint32_t)s_max;
     uint32_t nper = m == 0 ? 0u : (m <= s_max ? (uint32_t)(s_max / m) : 1u);
     cnt_iv[r] = meff;
     cnt_smp[r] = meff * nper;
@@ -192,8 +252,10 @@ __global__ __launch_bounds__(kBlock) void k_trav_count(const DevNode* __restrict
 // of that range (entries past it go straight to memory), and the block then writes the
 // staged entries out with consecutive threads on consecutive entries, so every cache line
 // is written whole at once instead of piecewise by lanes that finish at different times.
-template <bool LDS>
-__global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict__ nodes, uint32_t n_nodes,
+template <bool LDS, bool AHS>
+__global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict__ nodes,
+                                                      const DevNodeAhs* __restrict__ ahs, float footprint,
+                                                      uint32_t n_nodes,
                                                       int stack_n, uint32_t stage_n, const float* __restrict__ o,
                                                       const float* __restrict__ d, int64_t stride,
                                                       int64_t r0, uint32_t nr,
@@ -207,8 +269,8 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
                                                       uint32_t* __restrict__ iv_ray,
                                                       uint32_t* __restrict__ iv_base) {
   extern __shared__ __align__(16) uint8_t dyn[];
-  const TravLds tl = stage<LDS>(nodes, n_nodes, stack_n, dyn);
-  uint8_t* sp = dyn + trav_lds_bytes(LDS, n_nodes, stack_n);
+  const TravLds tl = stage<LDS, AHS>(nodes, ahs, footprint, n_nodes, stack_n, dyn);
+  uint8_t* sp = dyn + trav_lds_bytes(LDS, AHS, n_nodes, stack_n);
   float* s_t0 = reinterpret_cast<float*>(sp);
   float* s_dt = s_t0 + stage_n;
   uint32_t* s_key = reinterpret_cast<uint32_t*>(s_dt + stage_n);
@@ -229,17 +291,19 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
     const uint32_t nper = cnt_smp[r] / meff;
     const uint32_t pos0 = iv_off[r] - b0;
     const uint32_t base = smp_off[r];
-    traverse<true>(tl.nodes, oo, dd, (int)meff, nper, tl.st_word, tl.st_hi,
-                   [&](int m, float t0, float dt, uint32_t key) {
-                     const uint32_t q = pos0 + (uint32_t)m;
-                     const uint32_t smp = base + (uint32_t)m * nper;
-                     if (q < stage_n) {
-                       s_t0[q] = t0; s_dt[q] = dt; s_key[q] = key; s_ray[q] = r; s_base[q] = smp;
-                     } else {
-                       iv_t0[b0 + q] = t0; iv_dt[b0 + q] = dt; iv_key[b0 + q] = key; iv_ray[b0 + q] = r;
-                       iv_base[b0 + q] = smp;
-                     }
-                   });
+    auto put = [&](int m, float t0, float dt, uint32_t key) {
+      const uint32_t q = pos0 + (uint32_t)m;
+      const uint32_t smp = base + (uint32_t)m * nper;
+      if (q < stage_n) {
+        s_t0[q] = t0; s_dt[q] = dt; s_key[q] = key; s_ray[q] = r; s_base[q] = smp;
+      } else {
+        iv_t0[b0 + q] = t0; iv_dt[b0 + q] = dt; iv_key[b0 + q] = key; iv_ray[b0 + q] = r;
+        iv_base[b0 + q] = smp;
+      }
+    };
+    with_ahs<LDS, AHS>(tl, ahs, footprint, [&](auto av) {
+      return traverse<true, AHS>(tl.nodes, av, oo, dd, (int)meff, nper, tl.st_word, tl.st_hi, put);
+    });
   }
   __syncthreads();
   const uint32_t n = b1 - b0 < stage_n ? b1 - b0 : stage_n;
@@ -258,58 +322,86 @@ static hipError_t allow_lds(const void* kern) {
   return hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
 }
 
+template <bool AHS>
+static hipError_t trav_setup_one() {
+  hipError_t e = allow_lds((const void*)k_trav_count<true, AHS>);
+  if (e == hipSuccess) e = allow_lds((const void*)k_trav_count<false, AHS>);
+  if (e == hipSuccess) e = allow_lds((const void*)k_trav_emit<true, AHS>);
+  if (e == hipSuccess) e = allow_lds((const void*)k_trav_emit<false, AHS>);
+  return e;
+}
+
 static hipError_t trav_setup() {
   static bool done = false;
   if (done) return hipSuccess;
-  hipError_t e = allow_lds((const void*)k_trav_count<true>);
-  if (e == hipSuccess) e = allow_lds((const void*)k_trav_count<false>);
-  if (e == hipSuccess) e = allow_lds((const void*)k_trav_emit<true>);
-  if (e == hipSuccess) e = allow_lds((const void*)k_trav_emit<false>);
+  hipError_t e = trav_setup_one<false>();
+  if (e == hipSuccess) e = trav_setup_one<true>();
   if (e == hipSuccess) done = true;
   return e;
 }
 
-hipError_t launch_trav_count(const DevNode* nodes, uint32_t n_nodes, int depth, const float* o, const float* d,
-                             int64_t ray_stride, int64_t r0, uint32_t nr, int s_max,
+template <bool LDS, bool AHS>
+static void count_launch(uint32_t grid, uint32_t bytes, hipStream_t st, const DevNode* nodes, const DevNodeAhs* ahs,
+                         float footprint, uint32_t n_nodes, int stack_n, const float* o, const float* d,
+                         int64_t ray_stride, int64_t r0, uint32_t nr, int s_max, uint32_t* cnt_iv, uint32_t* cnt_smp) {
+  hipLaunchKernelGGL((k_trav_count<LDS, AHS>), dim3(grid), dim3(kBlock), bytes, st, nodes, ahs, footprint, n_nodes,
+                     stack_n, o, d, ray_stride, r0, nr, s_max, cnt_iv, cnt_smp);
+}
+
+hipError_t launch_trav_count(const DevNode* nodes, const DevNodeAhs* ahs, float footprint, uint32_t n_nodes, int depth,
+                             const float* o, const float* d, int64_t ray_stride, int64_t r0, uint32_t nr, int s_max,
                              uint32_t* cnt_iv, uint32_t* cnt_smp, hipStream_t st) {
   if (nr == 0) return hipSuccess;
   hipError_t e = trav_setup();
   if (e != hipSuccess) return e;
   const int stack_n = depth + 1;
   const uint32_t grid = (nr + kBlock - 1) / kBlock;
-  if (n_nodes <= (uint32_t)kLdsNodes)
-    hipLaunchKernelGGL(k_trav_count<true>, dim3(grid), dim3(kBlock), trav_lds_bytes(true, n_nodes, stack_n), st, nodes,
-                       n_nodes, stack_n, o, d, ray_stride, r0, nr, s_max, cnt_iv, cnt_smp);
-  else
-    hipLaunchKernelGGL(k_trav_count<false>, dim3(grid), dim3(kBlock), trav_lds_bytes(false, n_nodes, stack_n), st,
-                       nodes, n_nodes, stack_n, o, d, ray_stride, r0, nr, s_max, cnt_iv, cnt_smp);
+  const bool lds = n_nodes <= (uint32_t)kLdsNodes, hs = ahs != nullptr;
+  const uint32_t bytes = trav_lds_bytes(lds, hs, n_nodes, stack_n);
+  auto go = [&](auto fn) { fn(grid, bytes, st, nodes, ahs, footprint, n_nodes, stack_n, o, d, ray_stride, r0, nr, s_max,
+                              cnt_iv, cnt_smp); };
+  if (lds && hs) go(count_launch<true, true>);
+  else if (lds) go(count_launch<true, false>);
+  else if (hs) go(count_launch<false, true>);
+  else go(count_launch<false, false>);
   return hipGetLastError();
 }
 
-hipError_t launch_trav_emit(const DevNode* nodes, uint32_t n_nodes, int depth, const float* o, const float* d,
-                            int64_t ray_stride, int64_t r0, uint32_t nr, const uint32_t* cnt_iv,
-                            const uint32_t* cnt_smp, const uint32_t* iv_off, const uint32_t* smp_off,
-                            float* iv_t0, float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray,
+template <bool LDS, bool AHS>
+static void emit_launch(uint32_t grid, uint32_t bytes, hipStream_t st, const DevNode* nodes, const DevNodeAhs* ahs,
+                        float footprint, uint32_t n_nodes, int stack_n, uint32_t stage_n, const float* o,
+                        const float* d, int64_t ray_stride, int64_t r0, uint32_t nr, const uint32_t* cnt_iv,
+                        const uint32_t* cnt_smp, const uint32_t* iv_off, const uint32_t* smp_off, float* iv_t0,
+                        float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray, uint32_t* iv_base) {
+  hipLaunchKernelGGL((k_trav_emit<LDS, AHS>), dim3(grid), dim3(kBlock), bytes, st, nodes, ahs, footprint, n_nodes,
+                     stack_n, stage_n, o, d, ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt,
+                     iv_key, iv_ray, iv_base);
+}
+
+hipError_t launch_trav_emit(const DevNode* nodes, const DevNodeAhs* ahs, float footprint, uint32_t n_nodes, int depth,
+                            const float* o, const float* d, int64_t ray_stride, int64_t r0, uint32_t nr,
+                            const uint32_t* cnt_iv, const uint32_t* cnt_smp, const uint32_t* iv_off,
+                            const uint32_t* smp_off, float* iv_t0, float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray,
                             uint32_t* iv_base, hipStream_t st) {
   if (nr == 0) return hipSuccess;
   hipError_t e = trav_setup();
   if (e != hipSuccess) return e;
   const int stack_n = depth + 1;
   const uint32_t grid = (nr + kBlock - 1) / kBlock;
-  const bool lds = n_nodes <= (uint32_t)kLdsNodes;
+  const bool lds = n_nodes <= (uint32_t)kLdsNodes, hs = ahs != nullptr;
   // staging sized so that two blocks still fit in a CU's 160 KiB of LDS (the traversal
   // needs the occupancy), at most 2048 entries of 20 bytes
-  const uint32_t fixed = trav_lds_bytes(lds, n_nodes, stack_n);
+  const uint32_t fixed = trav_lds_bytes(lds, hs, n_nodes, stack_n);
   const uint32_t budget = 80u * 1024u;
   uint32_t stage_n = fixed + 20u * 256u <= budget ? (budget - fixed) / 20u : 256u;
   stage_n = std::min<uint32_t>(stage_n, 2048u) & ~63u;
   const uint32_t bytes = fixed + 20u * stage_n;
-  if (lds)
-    hipLaunchKernelGGL(k_trav_emit<true>, dim3(grid), dim3(kBlock), bytes, st, nodes, n_nodes, stack_n, stage_n, o, d,
-                       ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base);
-  else
-    hipLaunchKernelGGL(k_trav_emit<false>, dim3(grid), dim3(kBlock), bytes, st, nodes, n_nodes, stack_n, stage_n, o,
-                       d, ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base);
+  auto go = [&](auto fn) { fn(grid, bytes, st, nodes, ahs, footprint, n_nodes, stack_n, stage_n, o, d, ray_stride, r0,
+                              nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base); };
+  if (lds && hs) go(emit_launch<true, true>);
+  else if (lds) go(emit_launch<true, false>);
+  else if (hs) go(emit_launch<false, true>);
+  else go(emit_launch<false, false>);
   return hipGetLastError();
 }
 

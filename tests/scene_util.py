@@ -13,13 +13,23 @@ import synth
 
 
 class Scene:
-    def __init__(self, cfg: synth.SceneConfig, grid=None, split=0):
+    """footprint > 0: renders use hierarchical sampling, so every node gets an MLP (indexed by
+    its preorder node slot, its sigma bias from the mean density over its box)."""
+
+    def __init__(self, cfg: synth.SceneConfig, grid=None, split=0, footprint=0.0):
         self.cfg = cfg
         self.split = split
+        self.footprint = footprint
         self.grid = synth.make_grid(cfg) if grid is None else grid
         self.otree = oracle.build_tree(self.grid, cfg.grid_n, cfg.max_depth, cfg.max_leaves, split)
-        dens = synth.leaf_mean_density(self.grid, cfg.grid_n, self.otree.leaf_boxes())
-        self.W = synth.make_weights(self.otree.n_leaves, cfg.n_hidden, cfg.hidden, cfg.seed_weights, dens)
+        if footprint > 0:
+            rows = self.otree.rows
+            boxes = rows[np.argsort(rows[:, 11])][:, 2:8].copy()
+        else:
+            boxes = self.otree.leaf_boxes()
+        self.n_sets = len(boxes)
+        dens = synth.leaf_mean_density(self.grid, cfg.grid_n, boxes)
+        self.W = synth.make_weights(self.n_sets, cfg.n_hidden, cfg.hidden, cfg.seed_weights, dens)
 
     def camera_rays(self, i=0, n=1, width=None, height=None):
         cams = synth.make_cameras(i + n, self.cfg.seed_cameras, width or self.cfg.width,
@@ -36,7 +46,7 @@ def gpu_setup(scene: Scene, dtype, device="cuda:0"):
     assert np.array_equal(tree.rows, scene.otree.rows)
     assert np.array_equal(tree.mass, scene.otree.mass)
     master = torch.from_numpy(scene.W).to(device)
-    mlp = am.Mlp(ctx, master, scene.cfg.n_hidden, scene.cfg.hidden, dtype, tree.n_leaves)
+    mlp = am.Mlp(ctx, master, scene.cfg.n_hidden, scene.cfg.hidden, dtype, scene.n_sets)
     return ctx, tree, mlp
 
 

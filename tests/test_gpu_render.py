@@ -57,8 +57,10 @@ def fetch_inspect(ctx, R, n_leaves):
 def check_intervals_and_sort(scene, o, d, s_max, ins, rays_to_check, max_nonrobust=0.01):
     """Node ids bit-exact on robust rays; perm and bucket offsets bit-exact everywhere."""
     R = o.shape[1]
-    t0, t1, slot, m = oracle.trace(scene.otree, o, d, ray_idx=rays_to_check)
-    robust = oracle.robust(scene.otree, o, d, ray_idx=rays_to_check)
+    f = getattr(scene, "footprint", 0.0)
+    t0, t1, slot, m = oracle.trace(scene.otree, o, d, ray_idx=rays_to_check, footprint=f)
+    m_leaf = oracle.trace(scene.otree, o, d, ray_idx=rays_to_check)[3] if f > 0 else m
+    robust = oracle.robust(scene.otree, o, d, ray_idx=rays_to_check, footprint=f)
     off = ins["ray_iv_off"].astype(np.int64)
     n_nonrobust = 0
     for q, r in enumerate(rays_to_check):
@@ -72,12 +74,12 @@ def check_intervals_and_sort(scene, o, d, s_max, ins, rays_to_check, max_nonrobu
         np.testing.assert_allclose(ins["iv_t0"][a:b], t0[q, :meff], rtol=0, atol=2e-6)
         np.testing.assert_allclose(ins["iv_dt"][a:b], (t1 - t0)[q, :meff], rtol=1e-6, atol=1e-7)
         if meff:
-            n = s_max // m[q] if m[q] <= s_max else 1
+            n = s_max // m_leaf[q] if m_leaf[q] <= s_max else 1
             assert np.all(ins["iv_n"][a:b] == n)
     assert n_nonrobust <= max(2, max_nonrobust * len(rays_to_check))
     # the sort: ray-major sample keys expanded from intervals, stably sorted
     keys = np.repeat(ins["iv_slot"], ins["iv_n"])
-    counts, offsets, perm = oracle.buckets(keys, scene.otree.n_leaves)
+    counts, offsets, perm = oracle.buckets(keys, scene.n_sets)
     np.testing.assert_array_equal(ins["bucket_off"].view(np.uint32), offsets)
     np.testing.assert_array_equal(ins["perm"], perm)
     smp_off = ins["ray_smp_off"].astype(np.int64)
@@ -89,7 +91,8 @@ def compare_render(scene, out, o, d, s_max, rays_to_check, robust, tol_rgb=TOL_R
                    jitter=False, seed=0, min_ok=0.98):
     cfg = scene.cfg
     rgb, dep, op, ns, flags = oracle.render(scene.otree, scene.W, cfg.n_hidden, cfg.hidden, o, d, s_max,
-                                            eps=cfg.ert_eps, ray_idx=rays_to_check, jitter=jitter, seed=seed)
+                                            eps=cfg.ert_eps, ray_idx=rays_to_check, jitter=jitter, seed=seed,
+                                            footprint=getattr(scene, "footprint", 0.0))
     g_rgb = out["rgb"].cpu().numpy()[rays_to_check]
     g_dep = out["depth"].cpu().numpy()[rays_to_check]
     g_op = out["opacity"].cpu().numpy()[rays_to_check]
@@ -106,7 +109,8 @@ def compare_render(scene, out, o, d, s_max, rays_to_check, robust, tol_rgb=TOL_R
 
 def render_all(scene, ctx, tree, mlp, o, d, s_max, **kw):
     od, dd = to_dev(o), to_dev(d)
-    out = am.render(ctx, tree, mlp, od, dd, s_max, ert_eps=scene.cfg.ert_eps, **kw)
+    out = am.render(ctx, tree, mlp, od, dd, s_max, ert_eps=scene.cfg.ert_eps,
+                    hcheck_footprint=getattr(scene, "footprint", 0.0), **kw)
     torch.cuda.synchronize()
     return out
 
