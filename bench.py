@@ -101,14 +101,17 @@ def large_scene(args, am, torch, np, synth, ctx):
     desc = prop.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
     desc_untrained = untrained.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
 
-    paths = {"fp8": ("fp8", None), "fp8_prop": ("fp8", desc), "bf16": ("bf16", None), "bf16_prop": ("bf16", desc),
-             "fp8_untrained_prop": ("fp8", desc_untrained)}
+    # empty-space skipping: occupancy at half the guidance resolution, 1 % of the peak density
+    occ = am.Occupancy(ctx, grid, cfg.grid_n, 2, 0.01)
+    paths = {"fp8": ("fp8", None, None), "fp8_prop": ("fp8", desc, None), "bf16": ("bf16", None, None),
+             "bf16_prop": ("bf16", desc, None), "fp8_untrained_prop": ("fp8", desc_untrained, None),
+             "fp8_ess": ("fp8", None, occ)}
     outs = {k: torch.empty((R, 3), dtype=torch.float32, device=dev) for k in paths}
 
     def render(kind, rgb):
-        mk, pd = paths[kind]
+        mk, pd, oc = paths[kind]
         am.amnerf_render(ctx.h, tree.h, mlps[mk].desc, o_all, d_all, cfg.s_max, rgb, None, None, None, cfg.ert_eps,
-                         proposal=pd)
+                         proposal=pd, occupancy=oc)
 
     res = {}
     am.amnerf_ctx_set_timing(ctx.h, True)
@@ -140,7 +143,7 @@ def large_scene(args, am, torch, np, synth, ctx):
     # each proposal render judged by the plain render with the same leaf weights, every pixel
     # of the 30 cameras (the outputs of the last timed call)
     psnr_prop_vs_plain = {}
-    for kind, ref in (("fp8_prop", "fp8"), ("bf16_prop", "bf16"), ("fp8_untrained_prop", "fp8")):
+    for kind, ref in (("fp8_prop", "fp8"), ("bf16_prop", "bf16"), ("fp8_untrained_prop", "fp8"), ("fp8_ess", "fp8")):
         rep = am.amnerf_error_stats(ctx.h, outs[kind].view(-1), outs[ref].view(-1).double())
         psnr_prop_vs_plain[kind] = rep["psnr"]
     log("large proposal psnr vs plain: %s" % {k: round(v, 2) for k, v in psnr_prop_vs_plain.items()})
@@ -179,7 +182,7 @@ def large_scene(args, am, torch, np, synth, ctx):
                                           eps=cfg.ert_eps, ray_idx=sel, threads=threads)
         sel_dev = torch.from_numpy(sel).to(dev)
         acc = {"rays": int(sel.size), "sample": "seeded 1/64 pixel subset of camera 0"}
-        for kind in ("fp8", "fp8_prop"):
+        for kind in ("fp8", "fp8_prop", "fp8_ess"):
             x = outs[kind][:R1][sel_dev].contiguous().view(-1)
             acc["psnr_%s_vs_oracle_db" % kind] = am.amnerf_error_stats(
                 ctx.h, x, torch.from_numpy(np.ascontiguousarray(rgb_o)).to(dev).view(-1))["psnr"]
@@ -191,6 +194,7 @@ def large_scene(args, am, torch, np, synth, ctx):
                         "%d-leaf KD tree (max depth 12), 4x64 leaf MLPs, <=192 samples/ray, ERT at T<1e-4; "
                         "%d held-out cameras rendered by one call" % (L, n_cams),
             "n_leaves": L, "rays_per_call": R, "cameras_per_call": n_cams, "paths": res,
+            "occupancy": {"cells": occ.g ** 3, "occupied": occ.n_occupied, "block": 2, "thresh": 0.01},
             "psnr_vs_plain_db": psnr_prop_vs_plain, "bucket_sizes": spread, "accuracy": acc,
             "proposal_training": {"steps": args.large_prop_steps, "rays_per_step": args.prop_batch, "cameras": 200,
                                   "seconds": t_prop, "loss_first_last": [losses[0], losses[-1]]}}

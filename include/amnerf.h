@@ -62,6 +62,7 @@ extern "C" {
 
 typedef struct amnerf_ctx amnerf_ctx;
 typedef struct amnerf_tree amnerf_tree;
+typedef struct amnerf_occ amnerf_occ;
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* amnerf_last_error(void);
@@ -133,6 +134,30 @@ int amnerf_tree_export(const amnerf_tree* tree, int32_t* rows_host, uint64_t* ma
 
 /* Frees the tree (host and device copies).  NULL is accepted. */
 int amnerf_tree_destroy(amnerf_tree* tree);
+
+/* ---- occupancy grid for empty-space skipping (Section 4.1: the framework's density grid
+ *      also serves empty-space detection) ---------------------------------------------- */
+/* Builds a bit grid of G^3 cells, G = n / block, from the guidance grid: densities are
+ * quantised as for the tree (q = floor(g / max(g) * 2^24 + 1/2)); a cell is occupied iff the
+ * largest q over its block^3 guidance cells is >= floor(thresh * 2^24 + 1/2) and at least 1.
+ *   grid_host: host float32[n^3] as for amnerf_build_tree (NaN/inf: AMNERF_EINVAL).
+ *   n:         a power of two, 1 .. AMNERF_MAX_GRID;  block: a power of two dividing n.
+ *   thresh:    in [0, 1].
+ * A render given the grid drops every sample whose position falls in an empty cell
+ * (cell index floor(x * G) per axis, clamped to [0, G-1]) before the sort: its density is
+ * taken as 0, so the MLPs never see it.  This changes the result wherever the MLPs have
+ * density in empty cells.  Synchronous on the host, then uploads the bits. */
+int amnerf_build_occupancy(amnerf_ctx* ctx, const float* grid_host, int32_t n, int32_t block, float thresh,
+                           amnerf_occ** out);
+
+/* G, and the number of occupied cells. */
+int amnerf_occupancy_info_get(const amnerf_occ* occ, int32_t* g_out, int64_t* n_occupied_out);
+
+/* Copies the cells into host uint8[G^3] (0 or 1), cell (i,j,k) at i + G*(j + G*k). */
+int amnerf_occupancy_export(const amnerf_occ* occ, uint8_t* cells_host);
+
+/* Frees the grid (host and device copies).  NULL is accepted. */
+int amnerf_occupancy_destroy(amnerf_occ* occ);
 
 /* ---- per-leaf MLPs (Section 3.1, Section 3.2) ----------------------------------------- */
 /* Every leaf holds the same MLP shape (the paper keeps one MLP size for all nodes):
@@ -222,6 +247,11 @@ typedef struct {
                              interval's share.  Not combined with a proposal (AMNERF_EINVAL).
                              The footprint is a sample spacing per unit distance, e.g.
                              kappa times the pixel angle */
+  const amnerf_occ* occupancy; /* NULL, or empty-space skipping: samples in empty cells are
+                             dropped before the sort (centred strata only: AMNERF_JITTER
+                             is rejected; not combined with a proposal).  Kept samples keep
+                             their positions and segment lengths, so the render is the
+                             plain quadrature with the dropped samples' densities set to 0 */
 } amnerf_render_params;
 
 typedef struct {

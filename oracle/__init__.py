@@ -26,6 +26,7 @@ NODE_COLS = 12
 FLAG_ERT_AMBIGUOUS = 1
 FLAG_ERT_FIRED = 2
 FLAG_CLIPPED = 4
+FLAG_OCC_AMBIGUOUS = 8
 
 
 def build(force: bool = False) -> str:
@@ -54,7 +55,8 @@ def lib():
         _lib.orc_robust.argtypes = [P, i32, i32, P, P, i64, P, i64, dbl, dbl, P, f32]
         _lib.orc_mlp_eval.argtypes = [P, i32, i32, P, P, i64, P, P]
         _lib.orc_render.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, P, i64, i32, dbl,
-                                    i32, u64, P, P, P, P, P, i32, f32]
+                                    i32, u64, P, P, P, P, P, i32, f32, P, i32]
+        _lib.orc_occupancy.argtypes = [P, i32, i32, dbl, P]
         _lib.orc_ray_samples.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, i64, i32, dbl,
                                          i32, u64, i32, P, P, P, P, P, P, P, f32]
         _lib.orc_ray_samples.restype = i32
@@ -167,10 +169,22 @@ def mlp_eval(params_leaf, n_hidden, hidden, x, dirs, return_features=False):
     return (out, feat) if return_features else out
 
 
+def occupancy(grid, n, block, thresh):
+    """Occupancy cells uint8[G^3] (G = n / block) for empty-space skipping."""
+    grid = _c(grid, np.float32)
+    G = n // block
+    out = np.zeros(G ** 3, np.uint8)
+    if lib().orc_occupancy(_p(grid), n, block, float(thresh), _p(out)) != G:
+        raise ValueError("orc_occupancy failed")
+    return out
+
+
 def render(tree: Tree, params, n_hidden, hidden, o, d, s_max, eps=1e-4, ray_idx=None,
-           jitter=False, seed=0, threads=None, footprint=0.0):
+           jitter=False, seed=0, threads=None, footprint=0.0, occupancy=None):
     """Per-ray (rgb[n][3], depth[n], opacity[n], n_samples[n], flags[n]) in float64.  With
-    footprint > 0: hierarchical sampling, params holding one set per node (by node slot)."""
+    footprint > 0: hierarchical sampling, params holding one set per node (by node slot).  With
+    occupancy cells (uint8[G^3]): samples in empty cells are dropped, and n_samples counts the
+    kept ones."""
     params = _c(params, np.float32)
     o = _c(o, np.float32); d = _c(d, np.float32)
     R = o.shape[1]
@@ -178,9 +192,16 @@ def render(tree: Tree, params, n_hidden, hidden, o, d, s_max, eps=1e-4, ray_idx=
     rgb = np.zeros((n, 3)); depth = np.zeros(n); opac = np.zeros(n)
     ns = np.zeros(n, np.int32); flags = np.zeros(n, np.int32)
     threads = threads or min(16, os.cpu_count() or 1)
+    occ, occ_g = None, 0
+    if occupancy is not None:
+        occ = _c(occupancy, np.uint8)
+        occ_g = round(occ.size ** (1 / 3))
+        if occ_g ** 3 != occ.size:
+            raise ValueError("occupancy must hold G^3 cells")
     rc = lib().orc_render(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(params), params.shape[0],
                           n_hidden, hidden, _p(o), _p(d), R, _p(ri), n, s_max, eps, int(jitter),
-                          seed, _p(rgb), _p(depth), _p(opac), _p(ns), _p(flags), threads, float(footprint))
+                          seed, _p(rgb), _p(depth), _p(opac), _p(ns), _p(flags), threads, float(footprint),
+                          _p(occ), occ_g)
     if rc != 0:
         raise ValueError("orc_render failed")
     return rgb, depth, opac, ns, flags

@@ -205,6 +205,37 @@ int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int 
 }
 
 /* ------------------------------------------------------------------------- */
+/* Occupancy grid (Section 4.1: the density grid also detects empty space)    */
+/* ------------------------------------------------------------------------- */
+/* Cell (i,j,k) of the G^3 grid, G = n / block, covers guidance cells [b i, b i + b) x ...;
+   it is occupied iff its largest quantised density reaches q_thr = max(1, floor(thresh 2^24
+   + 1/2)).  out: uint8[G^3], cell (i,j,k) at i + G (j + G k).  Returns G or -1. */
+int orc_occupancy(const float* grid, int n, int block, double thresh, uint8_t* out) {
+  if (!grid || !out || n < 1 || block < 1 || n % block != 0 || !(thresh >= 0.0 && thresh <= 1.0)) return -1;
+  int64_t ncell = (int64_t)n * n * n;
+  uint32_t* q = (uint32_t*)malloc(sizeof(uint32_t) * ncell);
+  if (!q) return -1;
+  quantise(grid, ncell, q);
+  double t = floor(ldexp(thresh, 24) + 0.5);
+  uint32_t q_thr = t < 1.0 ? 1u : (uint32_t)t;
+  int G = n / block;
+  for (int k = 0; k < G; ++k)
+    for (int j = 0; j < G; ++j)
+      for (int i = 0; i < G; ++i) {
+        uint32_t mx = 0;
+        for (int c = 0; c < block; ++c)
+          for (int b = 0; b < block; ++b)
+            for (int a = 0; a < block; ++a) {
+              uint32_t v = q[(int64_t)(block * i + a) + (int64_t)n * ((int64_t)(block * j + b) + (int64_t)n * (block * k + c))];
+              if (v > mx) mx = v;
+            }
+        out[(int64_t)i + (int64_t)G * ((int64_t)j + (int64_t)G * k)] = mx >= q_thr;
+      }
+  free(q);
+  return G;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Tree view over an exported node table                                      */
 /* ------------------------------------------------------------------------- */
 typedef struct {
@@ -520,6 +551,7 @@ int orc_mlp_eval(const float* params_leaf, int n_hidden, int hidden, const doubl
 #define FLAG_ERT_AMBIGUOUS 1
 #define FLAG_ERT_FIRED 2
 #define FLAG_CLIPPED 4
+#define FLAG_OCC_AMBIGUOUS 8
 
 typedef struct {
   const otree* T;
@@ -531,6 +563,8 @@ typedef struct {
   double eps;
   int jitter;
   uint64_t seed;
+  const uint8_t* occ;   /* empty-space skipping: G^3 occupancy cells, or NULL */
+  int occ_g;
 } octx;
 
 /* Per-ray result plus optional per-sample record. */
@@ -538,6 +572,29 @@ typedef struct {
   double rgb[3], depth, opac;
   int n_samples, n_used, flags, m;
 } oray;
+
+/* Occupancy of the cell holding x: floor(x G) per axis, clamped to [0, G-1]. */
+static int occ_at(const octx* C, const double x[3]) {
+  int c[3];
+  for (int a = 0; a < 3; ++a) {
+    double f = floor(x[a] * (double)C->occ_g);
+    c[a] = f < 0.0 ? 0 : (f > (double)(C->occ_g - 1) ? C->occ_g - 1 : (int)f);
+  }
+  return C->occ[(int64_t)c[0] + (int64_t)C->occ_g * ((int64_t)c[1] + (int64_t)C->occ_g * c[2])] != 0;
+}
+
+/* A sample whose occupancy changes when it moves by 2e-6 along an axis: a float32 position
+   may land on the other side of the cell boundary. */
+static int occ_ambiguous(const octx* C, const double x[3]) {
+  int v = occ_at(C, x);
+  for (int a = 0; a < 3; ++a)
+    for (int sg = -1; sg <= 1; sg += 2) {
+      double y[3] = {x[0], x[1], x[2]};
+      y[a] += sg * 2e-6;
+      if (occ_at(C, y) != v) return 1;
+    }
+  return 0;
+}
 
 static void render_ray(const octx* C, int64_t r, oiv* ivbuf, osample* sbuf, oray* res,
                        double* s_sigma, double* s_rgb, double* s_w) {
@@ -551,11 +608,30 @@ static void render_ray(const octx* C, int64_t r, oiv* ivbuf, osample* sbuf, oray
   res->m = m;
   res->n_samples = ns;
   if (m > C->s_max) res->flags |= FLAG_CLIPPED;
+  if (C->occ) {
+    /* empty-space skipping: a sample in an empty cell is dropped (density 0); the count
+       reported is that of the kept samples */
+    int kept = 0;
+    for (int j = 0; j < ns; ++j) {
+      double x[3];
+      for (int a = 0; a < 3; ++a) x[a] = oo[a] + sbuf[j].t * dd[a];
+      kept += occ_at(C, x);
+      if (occ_ambiguous(C, x)) res->flags |= FLAG_OCC_AMBIGUOUS;
+    }
+    res->n_samples = kept;
+  }
   double S = 0.0;
   int used = 0;
   for (int j = 0; j < ns; ++j) {
     double x[3];
     for (int a = 0; a < 3; ++a) x[a] = oo[a] + sbuf[j].t * dd[a];
+    if (C->occ && !occ_at(C, x)) {
+      if (s_sigma) s_sigma[j] = 0.0;
+      if (s_rgb) for (int c = 0; c < 3; ++c) s_rgb[3 * j + c] = 0.0;
+      if (s_w) s_w[j] = 0.0;
+      used = j + 1;
+      continue;
+    }
     double u[IN_DIM], out[OUT_DIM];
     features(x, dd, u);
     mlp_forward(C->L, C->P + (int64_t)sbuf[j].slot * C->L->P, u, out, NULL);
@@ -591,6 +667,7 @@ static int make_ctx(octx* C, otree* T, olayout* L, double** P, const int32_t* ro
   *P = (double*)malloc(sizeof(double) * (int64_t)n_leaves * L->P);
   for (int64_t i = 0; i < (int64_t)n_leaves * L->P; ++i) (*P)[i] = (double)params[i];
   C->T = T; C->L = L; C->P = *P;
+  C->occ = NULL; C->occ_g = 0;
   return 0;
 }
 
@@ -599,13 +676,14 @@ int orc_render(const int32_t* rows, int nn, int grid_n, const float* params, int
                int n_hidden, int hidden, const float* o, const float* d, int64_t R,
                const int64_t* ray_idx, int64_t n_sel, int s_max, double eps, int jitter,
                uint64_t seed, double* rgb, double* depth, double* opac, int32_t* n_samples,
-               int32_t* flags, int n_threads, float footprint) {
-  if (s_max < 1) return -1;
+               int32_t* flags, int n_threads, float footprint, const uint8_t* occ, int occ_g) {
+  if (s_max < 1 || (occ && occ_g < 1)) return -1;
   otree T; olayout L; double* P = NULL; octx C;
   if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden, footprint)) {
     free(P); otree_free(&T); return -1;
   }
   C.o = o; C.d = d; C.R = R; C.s_max = s_max; C.eps = eps; C.jitter = jitter; C.seed = seed;
+  C.occ = occ; C.occ_g = occ_g;
   int cap_iv = T.n_leaves + 1;
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
   {
@@ -642,6 +720,7 @@ int orc_ray_samples(const int32_t* rows, int nn, int grid_n, const float* params
     free(P); otree_free(&T); return -1;
   }
   C.o = o; C.d = d; C.R = R; C.s_max = s_max; C.eps = eps; C.jitter = jitter; C.seed = seed;
+  C.occ = NULL; C.occ_g = 0;
   oiv* ivbuf = (oiv*)malloc(sizeof(oiv) * (T.n_leaves + 1));
   osample* sbuf = (osample*)malloc(sizeof(osample) * (s_max + 1));
   double* sg = (double*)malloc(sizeof(double) * (s_max + 1));

@@ -38,6 +38,7 @@ AMNERF_MAX_SAMPLES = 255
 EXPORTS = [
     "amnerf_last_error", "amnerf_version", "amnerf_ctx_create", "amnerf_ctx_destroy",
     "amnerf_build_tree", "amnerf_tree_info_get", "amnerf_tree_export", "amnerf_tree_destroy",
+    "amnerf_build_occupancy", "amnerf_occupancy_info_get", "amnerf_occupancy_export", "amnerf_occupancy_destroy",
     "amnerf_mlp_param_count", "amnerf_mlp_packed_bytes", "amnerf_mlp_pack", "amnerf_render",
     "amnerf_render_stats_get", "amnerf_render_inspect", "amnerf_ctx_set_timing",
     "amnerf_timing_collect", "amnerf_render_backward", "amnerf_adam_step", "amnerf_train_step",
@@ -85,7 +86,7 @@ class amnerf_proposal(C.Structure):
 class amnerf_render_params(C.Structure):
     _fields_ = [("s_max", C.c_int32), ("ert_eps", C.c_float), ("flags", C.c_uint32),
                 ("jitter_seed", C.c_uint64), ("proposal", C.POINTER(amnerf_proposal)),
-                ("hcheck_footprint", C.c_float)]
+                ("hcheck_footprint", C.c_float), ("occupancy", C.c_void_p)]
 
 
 class amnerf_render_out(C.Structure):
@@ -145,6 +146,10 @@ def _load():
     lib.amnerf_tree_info_get.argtypes = [P, C.POINTER(amnerf_tree_info)]
     lib.amnerf_tree_export.argtypes = [P, P, P]
     lib.amnerf_tree_destroy.argtypes = [P]
+    lib.amnerf_build_occupancy.argtypes = [P, P, C.c_int32, C.c_int32, C.c_float, C.POINTER(P)]
+    lib.amnerf_occupancy_info_get.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+    lib.amnerf_occupancy_export.argtypes = [P, P]
+    lib.amnerf_occupancy_destroy.argtypes = [P]
     lib.amnerf_mlp_param_count.argtypes = [C.POINTER(amnerf_mlp_shape)]
     lib.amnerf_mlp_param_count.restype = C.c_int64
     lib.amnerf_mlp_packed_bytes.argtypes = [C.POINTER(amnerf_mlp_shape), C.c_int32, C.c_int32,
@@ -241,6 +246,32 @@ def amnerf_tree_destroy(tree):
     _check(_lib.amnerf_tree_destroy(tree))
 
 
+def amnerf_build_occupancy(ctx, grid: np.ndarray, n: int, block: int, thresh: float):
+    g = np.ascontiguousarray(grid, dtype=np.float32)
+    if g.size != n ** 3:
+        raise ValueError("grid has %d cells, expected %d" % (g.size, n ** 3))
+    h = C.c_void_p()
+    _check(_lib.amnerf_build_occupancy(ctx, g.ctypes.data_as(C.c_void_p), n, block, thresh, C.byref(h)))
+    return h
+
+
+def amnerf_occupancy_info_get(occ):
+    g, n = C.c_int32(), C.c_int64()
+    _check(_lib.amnerf_occupancy_info_get(occ, C.byref(g), C.byref(n)))
+    return int(g.value), int(n.value)
+
+
+def amnerf_occupancy_export(occ) -> np.ndarray:
+    g, _ = amnerf_occupancy_info_get(occ)
+    cells = np.zeros(g ** 3, np.uint8)
+    _check(_lib.amnerf_occupancy_export(occ, cells.ctypes.data_as(C.c_void_p)))
+    return cells
+
+
+def amnerf_occupancy_destroy(occ):
+    _check(_lib.amnerf_occupancy_destroy(occ))
+
+
 def amnerf_mlp_param_count(n_hidden: int, hidden: int) -> int:
     s = amnerf_mlp_shape(n_hidden, hidden)
     return int(_lib.amnerf_mlp_param_count(C.byref(s)))
@@ -262,10 +293,12 @@ def amnerf_mlp_pack(ctx, n_hidden: int, hidden: int, dtype: int, n_leaves: int, 
 
 def amnerf_render(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, s_max: int, rgb_dev, depth_dev=None,
                   opacity_dev=None, weights_dev=None, ert_eps: float = 1e-4, jitter: bool = False,
-                  seed: int = 0, stream=None, proposal: "amnerf_proposal" = None, hcheck_footprint: float = 0.0):
+                  seed: int = 0, stream=None, proposal: "amnerf_proposal" = None, hcheck_footprint: float = 0.0,
+                  occupancy=None):
     rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]) if o_dev is not None else 0)
     prm = amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed,
-                               C.pointer(proposal) if proposal is not None else None, hcheck_footprint)
+                               C.pointer(proposal) if proposal is not None else None, hcheck_footprint,
+                               _handle(occupancy))
     out = amnerf_render_out(_ptr(rgb_dev), _ptr(depth_dev), _ptr(opacity_dev), _ptr(weights_dev))
     _check(_lib.amnerf_render(ctx, tree, C.byref(mlp), C.byref(rays), C.byref(prm), C.byref(out),
                               _stream(stream)))
@@ -380,6 +413,36 @@ class Context:
             pass
 
 
+class Occupancy:
+    """Occupancy bit grid for empty-space skipping (G = n / block cells per side)."""
+
+    def __init__(self, ctx: Context, grid, n, block, thresh):
+        self.ctx = ctx
+        self.h = amnerf_build_occupancy(ctx.h, grid, n, block, thresh)
+        self.g, self.n_occupied = amnerf_occupancy_info_get(self.h)
+
+    def cells(self):
+        return amnerf_occupancy_export(self.h)
+
+    def close(self):
+        if self.h is not None:
+            amnerf_occupancy_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _handle(x):
+    """A raw handle, or the handle of a wrapper object (Occupancy), or None."""
+    if x is None:
+        return None
+    return x.h if hasattr(x, "h") else x
+
+
 class Tree:
     def __init__(self, ctx: Context, grid, n, max_depth, max_leaves, split=0):
         self.ctx = ctx
@@ -422,7 +485,7 @@ class Mlp:
 
 
 def render(ctx: Context, tree: Tree, mlp: Mlp, o_dev, d_dev, s_max, ert_eps=1e-4, jitter=False, seed=0,
-           weights=False, stream=None, hcheck_footprint=0.0):
+           weights=False, stream=None, hcheck_footprint=0.0, occupancy=None):
     """Allocates the outputs and renders; returns dict of device tensors."""
     import torch
     R = int(o_dev.shape[1])
@@ -433,7 +496,8 @@ def render(ctx: Context, tree: Tree, mlp: Mlp, o_dev, d_dev, s_max, ert_eps=1e-4
     if weights:
         out["weights"] = torch.zeros(R * s_max, dtype=torch.float32, device=dev)
     amnerf_render(ctx.h, tree.h, mlp.desc, o_dev, d_dev, s_max, out["rgb"], out["depth"], out["opacity"],
-                  out.get("weights"), ert_eps, jitter, seed, stream, hcheck_footprint=hcheck_footprint)
+                  out.get("weights"), ert_eps, jitter, seed, stream, hcheck_footprint=hcheck_footprint,
+                  occupancy=occupancy)
     return out
 
 

@@ -71,6 +71,7 @@ struct amnerf_ctx {
   int64_t last_rays = 0;
   int64_t last_chunks = 0;
   uint32_t last_leaves = 0;
+  bool last_ess = false;          // the last render skipped empty space
   uint64_t last_niv_max = 0, last_ns_max = 0;
   // workspace views of the last chunk: the intervals the samples came from (plain or
   // planned by the proposal) and the sorted sample arrays
@@ -103,6 +104,14 @@ struct amnerf_tree {
   DevNode* dev_nodes = nullptr;
   float* dev_leafbox = nullptr;   // per leaf slot: 2*centre-1 (3), size (3), in [0,1] units
   DevNodeAhs* dev_ahs = nullptr;  // per device-table node: longest side, preorder node slot
+};
+
+struct amnerf_occ {
+  int device = 0;
+  int g = 0;                      // cells per side
+  int64_t n_occupied = 0;
+  std::vector<uint8_t> cells;     // G^3, 0 or 1
+  uint32_t* dev_bits = nullptr;   // G^3 bits, cell c at word c / 32, bit c % 32
 };
 
 // ---------------------------------------------------------------------------------------
@@ -519,6 +528,87 @@ extern "C" int amnerf_tree_destroy(amnerf_tree* t) {
 }
 
 // ---------------------------------------------------------------------------------------
+// occupancy grid
+// ---------------------------------------------------------------------------------------
+extern "C" int amnerf_build_occupancy(amnerf_ctx* ctx, const float* grid, int32_t n, int32_t block, float thresh,
+                                      amnerf_occ** out) {
+  if (!ctx || !grid || !out) return fail(AMNERF_EINVAL, "amnerf_build_occupancy: null argument");
+  *out = nullptr;
+  if (n < 1 || n > AMNERF_MAX_GRID || (n & (n - 1)) != 0)
+    return fail(AMNERF_EINVAL, "amnerf_build_occupancy: grid side %d must be a power of two <= %d", n, AMNERF_MAX_GRID);
+  if (block < 1 || (block & (block - 1)) != 0 || block > n)
+    return fail(AMNERF_EINVAL, "amnerf_build_occupancy: block %d must be a power of two dividing %d", block, n);
+  if (!(thresh >= 0.f && thresh <= 1.f)) return fail(AMNERF_EINVAL, "amnerf_build_occupancy: thresh must be in [0, 1]");
+  const size_t ncell = (size_t)n * n * n;
+  double gmax = 0.0;
+  for (size_t i = 0; i < ncell; ++i) {
+    float g = grid[i];
+    if (!std::isfinite(g)) return fail(AMNERF_EINVAL, "amnerf_build_occupancy: grid[%zu] is not finite", i);
+    if ((double)g > gmax) gmax = g;
+  }
+  const uint64_t q_thr = std::max<uint64_t>(1ull, (uint64_t)std::floor(std::ldexp((double)thresh, 24) + 0.5));
+  const int G = n / block;
+  amnerf_occ* o = new (std::nothrow) amnerf_occ();
+  if (!o) return fail(AMNERF_ENOMEM, "amnerf_build_occupancy: host allocation");
+  o->device = ctx->device;
+  o->g = G;
+  std::vector<uint32_t> bits;
+  try {
+    o->cells.assign((size_t)G * G * G, 0);
+    bits.assign(((size_t)G * G * G + 31) / 32, 0u);
+  } catch (...) {
+    delete o;
+    return fail(AMNERF_ENOMEM, "amnerf_build_occupancy: host allocation");
+  }
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        const double g = grid[(size_t)i + (size_t)n * ((size_t)j + (size_t)n * k)];
+        const uint64_t q = (gmax > 0.0 && g > 0.0) ? (uint64_t)std::floor(std::ldexp(g / gmax, 24) + 0.5) : 0ull;
+        if (q >= q_thr) o->cells[(size_t)(i / block) + (size_t)G * ((size_t)(j / block) + (size_t)G * (k / block))] = 1;
+      }
+  for (size_t c = 0; c < o->cells.size(); ++c)
+    if (o->cells[c]) {
+      bits[c >> 5] |= 1u << (c & 31);
+      ++o->n_occupied;
+    }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&o->dev_bits, sizeof(uint32_t) * bits.size());
+  if (e == hipSuccess) e = hipMemcpy(o->dev_bits, bits.data(), sizeof(uint32_t) * bits.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (o->dev_bits) (void)hipFree(o->dev_bits);
+    delete o;
+    return fail(AMNERF_EDEVICE, "amnerf_build_occupancy: upload: %s", hipGetErrorString(e));
+  }
+  *out = o;
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_occupancy_info_get(const amnerf_occ* o, int32_t* g, int64_t* n_occupied) {
+  if (!o) return fail(AMNERF_EINVAL, "amnerf_occupancy_info_get: null argument");
+  if (g) *g = o->g;
+  if (n_occupied) *n_occupied = o->n_occupied;
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_occupancy_export(const amnerf_occ* o, uint8_t* cells) {
+  if (!o || !cells) return fail(AMNERF_EINVAL, "amnerf_occupancy_export: null argument");
+  std::memcpy(cells, o->cells.data(), o->cells.size());
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_occupancy_destroy(amnerf_occ* o) {
+  if (!o) return AMNERF_OK;
+  if (o->dev_bits) {
+    (void)hipSetDevice(o->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(o->dev_bits);
+  }
+  delete o;
+  return AMNERF_OK;
+}
+
+// ---------------------------------------------------------------------------------------
 // MLP parameters
 // ---------------------------------------------------------------------------------------
 extern "C" int64_t amnerf_mlp_param_count(const amnerf_mlp_shape* s) {
@@ -679,6 +769,12 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
                 mlp->n_leaves, n_sets, ahs ? "node" : "leaf");
   if (ahs && p->proposal)
     return fail(AMNERF_EINVAL, "amnerf_render: proposal sampling runs on leaf intervals (no hierarchical sampling)");
+  const amnerf_occ* occ = p->occupancy;
+  if (occ && p->proposal)
+    return fail(AMNERF_EINVAL, "amnerf_render: empty-space skipping is not combined with a proposal");
+  if (occ && (p->flags & AMNERF_JITTER))
+    return fail(AMNERF_EINVAL, "amnerf_render: empty-space skipping uses centred strata (no jitter)");
+  if (occ && occ->device != ctx->device) return fail(AMNERF_EINVAL, "amnerf_render: occupancy grid lives on another device");
   if (!mlp->packed_dev) return fail(AMNERF_EINVAL, "amnerf_render: packed parameters are NULL");
   if (rays->n_rays < 0) return fail(AMNERF_EINVAL, "amnerf_render: n_rays < 0");
   if (rays->n_rays > 0 && (!rays->o_dev || !rays->d_dev)) return fail(AMNERF_EINVAL, "amnerf_render: ray arrays are NULL");
@@ -752,6 +848,27 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
       spu = spp;
       mat = pw.mat; mat_scan = pw.mat_scan; sidx = pw.sidx; sn = pw.sn; ssb = pw.ssb; scan_tmp = pw.scan_tmp;
       niv_use_max = niv_plan;
+    } else if (occ) {
+      // empty-space skipping: the kept samples of each ray as runs of consecutive slots
+      // (within an interval of n slots at most ceil(n/2) runs, so a ray has at most
+      // (s_max + m) / 2 of them); buffers sized from the plain interval count
+      HIP_TRY(hipMemcpyAsync(&ctx->counts_host->n_iv, w.iv_off + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      const uint64_t niv_plain = ctx->counts_host->n_iv;
+      const uint64_t niv_plan = (niv_plain + (uint64_t)nr * (uint64_t)p->s_max) / 2 + nr;
+      SortPlan spp = make_sort_plan(niv_plan, L);
+      PropWork pw;
+      rc = ensure_arena3(ctx, carve_prop(nullptr, nr, 1, niv_plan, spp, pw));
+      if (rc) return rc;
+      carve_prop((char*)ctx->arena3, nr, 1, niv_plan, spp, pw);
+      HIP_TRY(launch_occ_select(nr, plain, rays->o_dev, rays->d_dev, R, r0, occ->dev_bits, occ->g, pw.runs, pw.nsel,
+                                pw.mask, st));
+      HIP_TRY(launch_scan_u32_pair(pw.runs, pw.pv_off, pw.nsel, pw.ps_off, nr, pw.scan_tmp, st));
+      HIP_TRY(launch_prop_emit(nr, plain, pw.mask, pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, st));
+      use = {pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, pw.pv_off + nr};
+      spu = spp;
+      mat = pw.mat; mat_scan = pw.mat_scan; sidx = pw.sidx; sn = pw.sn; ssb = pw.ssb; scan_tmp = pw.scan_tmp;
+      niv_use_max = niv_plan;
     }
     HIP_TRY(launch_chunk_begin(ctx->counts, use.n_iv_dev, spu.seg, L, st));
     HIP_TRY(mark(2));
@@ -791,6 +908,8 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   ctx->last_dtype = mlp->dtype;
   ctx->last_params = *p;
   ctx->last_params.proposal = nullptr;
+  ctx->last_params.occupancy = nullptr;
+  ctx->last_ess = occ != nullptr;
   ctx->last_o = rays->o_dev;
   return AMNERF_OK;
 }
@@ -896,6 +1015,8 @@ int backward_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* ml
   if (ctx->last_chunks != 1) return fail(AMNERF_ESTATE, "amnerf_render_backward: the last render ran in %lld chunks",
                                          (long long)ctx->last_chunks);
   if (!grad || (rays->n_rays > 0 && !g_rgb)) return fail(AMNERF_EINVAL, "amnerf_render_backward: null gradient pointer");
+  if (ctx->last_ess)
+    return fail(AMNERF_ESTATE, "amnerf_render_backward: the last render skipped empty space (not differentiated)");
   if (mlp->n_leaves != (int)ctx->last_leaves)
     return fail(AMNERF_EINVAL, "amnerf_render_backward: MLP has %d parameter sets, the last render used %u",
                 mlp->n_leaves, ctx->last_leaves);

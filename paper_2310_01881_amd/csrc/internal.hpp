@@ -176,6 +176,12 @@ hipError_t launch_prop_select(uint32_t nr, const IvSet& iv, const float* wts, co
                               int cap, int s_max,
                               uint32_t* runs, uint32_t* nsel, uint64_t* mask, float* mass, ChunkCounts* counts,
                               hipStream_t st);
+// Empty-space skipping: per ray, the mask of plain slots whose centred sample lies in an
+// occupied cell of the G^3 bit grid, with its run and kept-slot counts (emitted by
+// launch_prop_emit).
+hipError_t launch_occ_select(uint32_t nr, const IvSet& iv, const float* o, const float* d, int64_t stride, int64_t r0,
+                             const uint32_t* bits, int g, uint32_t* runs, uint32_t* nsel, uint64_t* mask,
+                             hipStream_t st);
 hipError_t launch_prop_emit(uint32_t nr, const IvSet& iv, const uint64_t* mask, const uint32_t* pv_off,
                             const uint32_t* ps_off, float* pt0, float* pdt, uint32_t* pkey, uint32_t* pray,
                             uint32_t* pbase, hipStream_t st);
