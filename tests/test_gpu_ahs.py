@@ -140,3 +140,35 @@ def test_hcheck_argument_checks():
     with pytest.raises(am.AmnerfError) as e:
         am.amnerf_render(ctx.h, tree.h, mlp.desc, od, dd, 64, rgb, proposal=desc, hcheck_footprint=0.5)
     assert e.value.code == am.AMNERF_EINVAL and "proposal" in am.amnerf_last_error()
+
+
+def test_hcheck_with_jitter():
+    """Jittered strata under hierarchical sampling: the offset of interval k of a ray is the
+    same counter-based hash, k counting the ray's HCheck intervals."""
+    scene = Scene(synth.C1, footprint=0.5)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = scene.camera_rays()
+    R = o.shape[1]
+    out = render_all(scene, ctx, tree, mlp, o, d, cfg.s_max, jitter=True, seed=1234)
+    rays = np.arange(R)
+    robust = oracle.robust(scene.otree, o, d, footprint=scene.footprint)
+    e = compare_render(scene, out, o, d, cfg.s_max, rays, robust, jitter=True, seed=1234)
+    print("c1 hcheck jitter: max err rgb/opacity/depth", e, flush=True)
+
+
+def test_hcheck_node_count_capacity():
+    """A 4096-leaf tree has 8191 nodes, more MLP sets than a render supports: ECAPACITY."""
+    cfg = synth.scaled(synth.C2, grid_n=64, max_depth=12, max_leaves=4096, n_hidden=2, hidden=32,
+                       width=8, height=8, s_max=32)
+    g = synth.make_grid(cfg)
+    ctx = am.Context(0)
+    tree = am.Tree(ctx, g, cfg.grid_n, cfg.max_depth, cfg.max_leaves)
+    assert tree.info.n_nodes > 4096
+    W = synth.make_weights(4096, 2, 32, 1)
+    mlp = am.Mlp(ctx, torch.from_numpy(W).to("cuda:0"), 2, 32, am.AMNERF_F32, 4096)
+    o, d = synth.camera_rays(synth.make_cameras(1, 3, 8, 8)[0])
+    rgb = torch.empty((o.shape[1], 3), device="cuda:0")
+    with pytest.raises(am.AmnerfError) as e:
+        am.amnerf_render(ctx.h, tree.h, mlp.desc, to_dev(o), to_dev(d), 32, rgb, hcheck_footprint=0.1)
+    assert e.value.code == am.AMNERF_ECAPACITY

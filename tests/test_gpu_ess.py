@@ -121,3 +121,31 @@ def test_argument_checks():
     for args in ((3, 0.01), (2, -0.1), (2, 1.5), (64, 0.01)):
         with pytest.raises(am.AmnerfError):
             am.Occupancy(ctx, scene.grid, cfg.grid_n, *args)
+
+
+def test_c3_camera_in_two_passes_fp32():
+    """Camera 0 of the large scene whole (2 073 600 rays, two passes at S_max 192) with empty
+    space skipped; 1 500 rays of both passes against the oracle."""
+    scene = Scene(synth.C3)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    occ_cells = oracle.occupancy(scene.grid, cfg.grid_n, 2, 0.01)
+    o, d = scene.camera_rays()
+    R = o.shape[1]
+    out = am.render(ctx, tree, mlp, to_dev(o), to_dev(d), cfg.s_max, ert_eps=cfg.ert_eps,
+                    occupancy=am.Occupancy(ctx, scene.grid, cfg.grid_n, 2, 0.01))
+    torch.cuda.synchronize()
+    st = am.amnerf_render_stats_get(ctx.h)
+    assert st["n_chunks"] == 2 and st["n_nonfinite"] == 0
+    rays = np.sort(np.random.default_rng(33).choice(R, 1500, replace=False))
+    chunk = (1 << 28) // cfg.s_max
+    assert rays.min() < chunk <= rays.max()
+    rgb, dep, op, ns, flags = oracle.render(scene.otree, scene.W, cfg.n_hidden, cfg.hidden, o, d, cfg.s_max,
+                                            eps=cfg.ert_eps, ray_idx=rays, occupancy=occ_cells)
+    robust = oracle.robust(scene.otree, o, d, ray_idx=rays)
+    ok = robust & ((flags & (oracle.FLAG_OCC_AMBIGUOUS | oracle.FLAG_ERT_AMBIGUOUS)) == 0)
+    assert ok.mean() > 0.95
+    e = np.abs(out["rgb"].cpu().numpy()[rays] - rgb)[ok].max()
+    print("c3 ess two passes: kept %d of %d samples; max rgb err %.3e on %d rays" % (
+        st["n_samples"], st["n_plain_samples"], e, ok.sum()), flush=True)
+    assert e <= TOL_RGB
