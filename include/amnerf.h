@@ -251,7 +251,9 @@ typedef struct {
                              dropped before the sort (centred strata only: AMNERF_JITTER
                              is rejected; not combined with a proposal).  Kept samples keep
                              their positions and segment lengths, so the render is the
-                             plain quadrature with the dropped samples' densities set to 0 */
+                             plain quadrature with the dropped samples' densities set to 0.
+                             Not differentiated: amnerf_render_backward (and so
+                             amnerf_train_step) after such a render returns AMNERF_ESTATE */
 } amnerf_render_params;
 
 typedef struct {
