@@ -38,32 +38,46 @@ __global__ __launch_bounds__(kThreads) void k_occ_select(uint32_t nr, IvSet iv, 
     dd[a] = d[a * stride + r0 + r];
   }
   const float G = (float)g, gmax = (float)(g - 1);
-  uint32_t s = 0, kept = 0, nrun = 0, q = 0;
+  uint32_t kept = 0, nrun = 0, s = 0, q = 0;
   uint64_t cur = 0ull;
+  bool prev = false;
+  // interval by interval; inside an interval the slots go in groups of 8 whose occupancy
+  // words are loaded together (slots past the interval's end re-read its last slot and
+  // are masked off)
+  constexpr uint32_t kGroup = 8;
   for (uint32_t k = 0; k < meff; ++k) {
     const float t0 = iv.t0[i0 + k];
     const float delta = iv.dt[i0 + k] / (float)n;
-    bool prev = false;
-    for (uint32_t j = 0; j < n; ++j) {
-      const float t = sample_t(t0, delta, j, 0.5f);
-      uint32_t c[3];
+    for (uint32_t j0 = 0; j0 < n; j0 += kGroup) {
+      uint32_t word[kGroup], sh[kGroup];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const float x = fmaf(t, dd[a], oo[a]);
-        c[a] = (uint32_t)fminf(fmaxf(floorf(x * G), 0.f), gmax);   // NaN -> 0
+      for (uint32_t e = 0; e < kGroup; ++e) {
+        const uint32_t j = j0 + e < n ? j0 + e : n - 1u;
+        const float t = sample_t(t0, delta, j, 0.5f);
+        uint32_t c[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float x = fmaf(t, dd[a], oo[a]);
+          c[a] = (uint32_t)fminf(fmaxf(floorf(x * G), 0.f), gmax);   // NaN -> 0
+        }
+        const uint32_t idx = c[0] + (uint32_t)g * (c[1] + (uint32_t)g * c[2]);
+        word[e] = bits[idx >> 5];
+        sh[e] = idx & 31u;
       }
-      const uint32_t idx = c[0] + (uint32_t)g * (c[1] + (uint32_t)g * c[2]);
-      const bool occ = (bits[idx >> 5] >> (idx & 31u)) & 1u;
-      if (occ) {
-        cur |= 1ull << (s & 63u);
-        ++kept;
-        if (!prev) ++nrun;
-      }
-      prev = occ;
-      ++s;
-      if ((s & 63u) == 0u) {
-        mw[q++] = cur;
-        cur = 0ull;
+#pragma unroll
+      for (uint32_t e = 0; e < kGroup; ++e) {
+        if (j0 + e >= n) break;
+        const bool occ = (word[e] >> sh[e]) & 1u;
+        cur |= (uint64_t)occ << (s & 63u);
+        kept += occ;
+        // a kept slot starts a run unless its left neighbour in the same interval is kept
+        nrun += occ && (j0 + e == 0u || !prev);
+        prev = occ;
+        ++s;
+        if ((s & 63u) == 0u) {
+          mw[q++] = cur;
+          cur = 0ull;
+        }
       }
     }
   }

@@ -713,62 +713,90 @@ __global__ __launch_bounds__(kThreads, QM == 2 ? 8 : (QM == 3 ? 7 : 1)) void k_p
 // ---- emission of the planned intervals: one lane per ray -------------------------------
 // The lane walks its ray's slot mask run by run: trailing zeros skip slots that are not
 // kept, trailing ones give the run's length, cut at the interval's end.  A run that is a
-// whole interval keeps its endpoints exactly.
+// whole interval keeps its endpoints exactly.  The block's rays are consecutive, so their
+// planned intervals fill one contiguous output range: the first `stage_n` entries of it are
+// put in LDS and written out by consecutive threads (whole cache lines), the rest go
+// straight to memory.
+constexpr uint32_t kEmitStage = 3072;   // 20 B each: 60 KiB of LDS
+
 __global__ __launch_bounds__(kThreads) void k_prop_emit(uint32_t nr, IvSet iv, const uint64_t* __restrict__ mask,
                                                         const uint32_t* __restrict__ pv_off,
                                                         const uint32_t* __restrict__ ps_off,
                                                         float* __restrict__ pt0, float* __restrict__ pdt,
                                                         uint32_t* __restrict__ pkey, uint32_t* __restrict__ pray,
                                                         uint32_t* __restrict__ pbase) {
-  const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
-  if (r >= nr) return;
-  const uint32_t i0 = iv.iv_off[r], meff = iv.iv_off[r + 1] - i0;
-  if (meff == 0) return;
-  const uint32_t ns = iv.smp_off[r + 1] - iv.smp_off[r];
-  const uint32_t n = ns / meff;
-  const uint32_t m32 = n > 1u ? 0xFFFFFFFFu / n + 1u : 0u;   // floor(x / n) = umulhi(x, m32), x < 2^16
-  uint32_t out = pv_off[r], smp = ps_off[r];
-  const uint64_t w[4] = {mask[4 * (uint64_t)r], mask[4 * (uint64_t)r + 1], mask[4 * (uint64_t)r + 2],
-                         mask[4 * (uint64_t)r + 3]};
-  auto word = [&](uint32_t q) { return q == 0 ? w[0] : (q == 1 ? w[1] : (q == 2 ? w[2] : w[3])); };
-  uint32_t s = 0;
-  while (s < ns) {
-    // next kept slot at or after s
-    const uint64_t x = word(s >> 6) >> (s & 63u);
-    if (x == 0ull) {
-      s = (s | 63u) + 1u;
-      continue;
+  extern __shared__ __align__(16) uint8_t dyn[];
+  float* s_t0 = reinterpret_cast<float*>(dyn);
+  float* s_dt = s_t0 + kEmitStage;
+  uint32_t* s_key = reinterpret_cast<uint32_t*>(s_dt + kEmitStage);
+  uint32_t* s_ray = s_key + kEmitStage;
+  uint32_t* s_base = s_ray + kEmitStage;
+  const uint32_t rb = blockIdx.x * kThreads;                     // first ray of the block
+  const uint32_t re = rb + kThreads < nr ? rb + kThreads : nr;   // one past its last ray
+  const uint32_t b0 = pv_off[rb], b1 = pv_off[re];               // the block's output range
+  const uint32_t r = rb + threadIdx.x;
+  const uint32_t i0 = r < nr ? iv.iv_off[r] : 0u, meff = r < nr ? iv.iv_off[r + 1] - i0 : 0u;
+  if (meff != 0) {
+    const uint32_t ns = iv.smp_off[r + 1] - iv.smp_off[r];
+    const uint32_t n = ns / meff;
+    const uint32_t m32 = n > 1u ? 0xFFFFFFFFu / n + 1u : 0u;   // floor(x / n) = umulhi(x, m32), x < 2^16
+    uint32_t out = pv_off[r], smp = ps_off[r];
+    const uint64_t w[4] = {mask[4 * (uint64_t)r], mask[4 * (uint64_t)r + 1], mask[4 * (uint64_t)r + 2],
+                           mask[4 * (uint64_t)r + 3]};
+    auto word = [&](uint32_t q) { return q == 0 ? w[0] : (q == 1 ? w[1] : (q == 2 ? w[2] : w[3])); };
+    uint32_t s = 0;
+    while (s < ns) {
+      // next kept slot at or after s
+      const uint64_t x = word(s >> 6) >> (s & 63u);
+      if (x == 0ull) {
+        s = (s | 63u) + 1u;
+        continue;
+      }
+      s += (uint32_t)__builtin_ctzll(x);
+      if (s >= ns) break;
+      const uint32_t k = n > 1u ? __umulhi(s, m32) : s;
+      const uint32_t j0 = s - k * n;
+      // consecutive kept slots from s, word by word, cut at the interval's end
+      uint32_t len = 0, pos = s;
+      while (pos < ns) {
+        const uint32_t b = pos & 63u;
+        const uint64_t y = ~(word(pos >> 6) >> b);
+        const uint32_t c = y ? (uint32_t)__builtin_ctzll(y) : 64u - b;
+        len += c;
+        pos += c;
+        if (c < 64u - b) break;
+      }
+      len = min(len, min(n - j0, ns - s));
+      const uint32_t i = i0 + k;
+      const float delta = iv.dt[i] / (float)n;
+      float t0o, dto;
+      if (j0 == 0 && len == n) {          // the whole interval: keep it exactly
+        t0o = iv.t0[i];
+        dto = iv.dt[i];
+      } else {
+        t0o = fmaf((float)j0, delta, iv.t0[i]);
+        dto = (float)len * delta;
+      }
+      const uint32_t key = key_slot(iv.key[i]) | (len << 16);
+      const uint32_t q = out - b0;
+      if (q < kEmitStage) {
+        s_t0[q] = t0o; s_dt[q] = dto; s_key[q] = key; s_ray[q] = r; s_base[q] = smp;
+      } else {
+        pt0[out] = t0o; pdt[out] = dto; pkey[out] = key; pray[out] = r; pbase[out] = smp;
+      }
+      ++out;
+      smp += len;
+      s += len;
     }
-    s += (uint32_t)__builtin_ctzll(x);
-    if (s >= ns) break;
-    const uint32_t k = n > 1u ? __umulhi(s, m32) : s;
-    const uint32_t j0 = s - k * n;
-    // consecutive kept slots from s, word by word, cut at the interval's end
-    uint32_t len = 0, pos = s;
-    while (pos < ns) {
-      const uint32_t b = pos & 63u;
-      const uint64_t y = ~(word(pos >> 6) >> b);
-      const uint32_t c = y ? (uint32_t)__builtin_ctzll(y) : 64u - b;
-      len += c;
-      pos += c;
-      if (c < 64u - b) break;
-    }
-    len = min(len, min(n - j0, ns - s));
-    const uint32_t i = i0 + k;
-    const float delta = iv.dt[i] / (float)n;
-    if (j0 == 0 && len == n) {          // the whole interval: keep it exactly
-      pt0[out] = iv.t0[i];
-      pdt[out] = iv.dt[i];
-    } else {
-      pt0[out] = fmaf((float)j0, delta, iv.t0[i]);
-      pdt[out] = (float)len * delta;
-    }
-    pkey[out] = key_slot(iv.key[i]) | (len << 16);
-    pray[out] = r;
-    pbase[out] = smp;
-    ++out;
-    smp += len;
-    s += len;
+  }
+  __syncthreads();
+  const uint32_t n_st = b1 - b0 < kEmitStage ? b1 - b0 : kEmitStage;
+  for (uint32_t q = threadIdx.x; q < n_st; q += kThreads) {
+    pt0[b0 + q] = s_t0[q];
+    pdt[b0 + q] = s_dt[q];
+    pkey[b0 + q] = s_key[q];
+    pray[b0 + q] = s_ray[q];
+    pbase[b0 + q] = s_base[q];
   }
 }
 
@@ -1139,8 +1167,8 @@ hipError_t launch_prop_emit(uint32_t nr, const IvSet& iv, const uint64_t* mask, 
                             const uint32_t* ps_off, float* pt0, float* pdt, uint32_t* pkey, uint32_t* pray,
                             uint32_t* pbase, hipStream_t st) {
   if (nr == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prop_emit, dim3((nr + kThreads - 1) / kThreads), dim3(kThreads), 0, st, nr, iv, mask, pv_off,
-                     ps_off, pt0, pdt, pkey, pray, pbase);
+  hipLaunchKernelGGL(k_prop_emit, dim3((nr + kThreads - 1) / kThreads), dim3(kThreads), 20u * kEmitStage, st, nr, iv,
+                     mask, pv_off, ps_off, pt0, pdt, pkey, pray, pbase);
   return hipGetLastError();
 }
 
