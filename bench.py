@@ -223,8 +223,8 @@ def main():
                     help="frames in flight for the throughput line: contexts on streams of their own")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(rays shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (rays would shard "
+              "across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
