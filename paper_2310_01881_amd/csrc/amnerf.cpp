@@ -92,6 +92,17 @@ struct amnerf_ctx {
   // error report: block partials and totals (device), totals (pinned host)
   double* err_dev = nullptr;
   double* err_host = nullptr;
+  // second lane of a render that runs in several chunks: a stream (default priority), the
+  // fork and join events, and its own chunk workspace, proposal arena and counters
+  struct {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    void* arena3 = nullptr;
+    size_t arena3_bytes = 0;
+    ChunkCounts* counts = nullptr;
+  } lane;
 };
 
 struct amnerf_tree {
@@ -156,6 +167,12 @@ extern "C" int amnerf_ctx_destroy(amnerf_ctx* ctx) {
   if (ctx->counts_host) (void)hipHostFree(ctx->counts_host);
   if (ctx->err_dev) (void)hipFree(ctx->err_dev);
   if (ctx->err_host) (void)hipHostFree(ctx->err_host);
+  if (ctx->lane.arena) (void)hipFree(ctx->lane.arena);
+  if (ctx->lane.arena3) (void)hipFree(ctx->lane.arena3);
+  if (ctx->lane.counts) (void)hipFree(ctx->lane.counts);
+  if (ctx->lane.fork) (void)hipEventDestroy(ctx->lane.fork);
+  if (ctx->lane.join) (void)hipEventDestroy(ctx->lane.join);
+  if (ctx->lane.stream) (void)hipStreamDestroy(ctx->lane.stream);
   delete ctx;
   return AMNERF_OK;
 }
@@ -239,6 +256,42 @@ static int ensure_arena3(amnerf_ctx* ctx, size_t bytes) {
   if (e != hipSuccess) return fail(AMNERF_ENOMEM, "workspace hipMalloc(%zu): %s", grow, hipGetErrorString(e));
   ctx->arena3_bytes = grow;
   return AMNERF_OK;
+}
+
+// Grows a lane buffer to `bytes` (plus `extra` of slack), within the context's cap.
+static int grow_lane_buffer(amnerf_ctx* ctx, void** buf, size_t* have, size_t bytes, size_t extra) {
+  if (bytes <= *have) return AMNERF_OK;
+  const size_t others = ctx->arena_bytes + ctx->arena2_bytes + ctx->arena3_bytes + ctx->lane.arena_bytes +
+                        ctx->lane.arena3_bytes - *have;
+  if (ctx->cap && bytes + others > ctx->cap)
+    return fail(AMNERF_ENOMEM, "workspace needs %zu more bytes, cap is %zu", bytes, ctx->cap);
+  HIP_TRY(hipDeviceSynchronize());
+  if (*buf) HIP_TRY(hipFree(*buf));
+  *buf = nullptr;
+  *have = 0;
+  const size_t grow = bytes + extra;
+  hipError_t e = hipMalloc(buf, grow);
+  if (e != hipSuccess) return fail(AMNERF_ENOMEM, "workspace hipMalloc(%zu): %s", grow, hipGetErrorString(e));
+  *have = grow;
+  return AMNERF_OK;
+}
+
+// The second lane's stream, events, counters and chunk workspace (`need` bytes).
+static int lane_prepare(amnerf_ctx* ctx, size_t need) {
+  if (!ctx->lane.stream) {
+    HIP_TRY(hipStreamCreateWithFlags(&ctx->lane.stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&ctx->lane.fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ctx->lane.join, hipEventDisableTiming));
+    HIP_TRY(hipMalloc((void**)&ctx->lane.counts, sizeof(ChunkCounts)));
+  }
+  return grow_lane_buffer(ctx, &ctx->lane.arena, &ctx->lane.arena_bytes, need, need / 8);
+}
+
+// The proposal arena of the main context (lane 0) or of the second lane.
+static int ensure_arena3(amnerf_ctx* ctx, size_t bytes);
+static int ensure_arena3_for(amnerf_ctx* ctx, bool second, size_t bytes) {
+  if (!second) return ensure_arena3(ctx, bytes);
+  return grow_lane_buffer(ctx, &ctx->lane.arena3, &ctx->lane.arena3_bytes, bytes, bytes / 4);
 }
 
 static int ensure_arena(amnerf_ctx* ctx, size_t bytes) {
@@ -797,28 +850,50 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   if (R > 0 && (uint64_t)R < chunk) chunk = (uint64_t)R;
   const uint64_t niv_max = chunk * iv_per_ray, ns_max = chunk * (uint64_t)p->s_max;
   SortPlan sp = make_sort_plan(niv_max, L);
-  Work w;
-  size_t need = carve(nullptr, chunk, niv_max, ns_max, sp, w);
+  Work w0, w1;
+  size_t need = carve(nullptr, chunk, niv_max, ns_max, sp, w0);
   rc = ensure_arena(ctx, need);
   if (rc) return rc;
-  carve((char*)ctx->arena, chunk, niv_max, ns_max, sp, w);
+  carve((char*)ctx->arena, chunk, niv_max, ns_max, sp, w0);
+  // More than one chunk (and no per-sample weights, whose offsets need the chunks in
+  // order): odd chunks run on a second lane -- its own stream, workspace and counters --
+  // so one chunk's latency-bound stages overlap the other's matrix-core stage.  The lane
+  // waits for the caller's stream on entry and the caller's stream waits for the lane on
+  // exit, so the call stays asynchronous on `stream`.
+  const bool pipe = (uint64_t)R > chunk && !out->weights_dev;
+  if (pipe) {
+    rc = lane_prepare(ctx, need);
+    if (rc) return rc;
+    carve((char*)ctx->lane.arena, chunk, niv_max, ns_max, sp, w1);
+  }
   HIP_TRY(launch_counts_reset(ctx->counts, st));
+  if (pipe) {
+    HIP_TRY(launch_counts_reset(ctx->lane.counts, st));
+    HIP_TRY(hipEventRecord(ctx->lane.fork, st));
+    HIP_TRY(hipStreamWaitEvent(ctx->lane.stream, ctx->lane.fork, 0));
+  }
   int64_t n_chunks = 0;
   IvSet use = {};
-  uint32_t *mat = w.mat, *mat_scan = w.mat_scan, *sidx = w.sidx, *sn = w.sn, *ssb = w.ssb, *scan_tmp = w.scan_tmp;
+  Work* wl = &w0;   // the last chunk's workspace
+  uint32_t *mat = w0.mat, *mat_scan = w0.mat_scan, *sidx = w0.sidx, *sn = w0.sn, *ssb = w0.ssb, *scan_tmp = w0.scan_tmp;
   for (int64_t r0 = 0; r0 < R; r0 += (int64_t)chunk, ++n_chunks) {
     const uint32_t nr = (uint32_t)std::min<int64_t>((int64_t)chunk, R - r0);
+    const bool second = pipe && (n_chunks & 1);
+    const hipStream_t cs = second ? ctx->lane.stream : st;
+    ChunkCounts* const cc = second ? ctx->lane.counts : ctx->counts;
+    Work& w = second ? w1 : w0;
+    wl = &w;
     EvSet* ev = nullptr;
     if (ctx->timing) {
       rc = next_set(ctx, &ev);
       if (rc) return rc;
     }
-    auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev->ev[k], st) : hipSuccess; };
+    auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev->ev[k], cs) : hipSuccess; };
     HIP_TRY(mark(0));
-    HIP_TRY(launch_trav_count(tree->dev_nodes, ahs_tab, p->hcheck_footprint, (uint32_t)n_nodes, tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, p->s_max, w.cnt_iv, w.cnt_smp, st));
-    HIP_TRY(launch_scan_u32_pair(w.cnt_iv, w.iv_off, w.cnt_smp, w.smp_off, nr, w.scan_tmp, st));
+    HIP_TRY(launch_trav_count(tree->dev_nodes, ahs_tab, p->hcheck_footprint, (uint32_t)n_nodes, tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, p->s_max, w.cnt_iv, w.cnt_smp, cs));
+    HIP_TRY(launch_scan_u32_pair(w.cnt_iv, w.iv_off, w.cnt_smp, w.smp_off, nr, w.scan_tmp, cs));
     HIP_TRY(launch_trav_emit(tree->dev_nodes, ahs_tab, p->hcheck_footprint, (uint32_t)n_nodes, tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
-                             w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, st));
+                             w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, cs));
     HIP_TRY(mark(1));
     const IvSet plain = {w.iv_off, w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, w.iv_off + nr};
     use = plain;
@@ -828,22 +903,22 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
     if (p->proposal) {
       // the proposal buffers are sized from the plain interval count: wait for it once
       uint32_t niv_plain = 0;
-      HIP_TRY(hipMemcpyAsync(&ctx->counts_host->n_iv, w.iv_off + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(hipMemcpyAsync(&ctx->counts_host->n_iv, w.iv_off + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, cs));
+      HIP_TRY(hipStreamSynchronize(cs));
       niv_plain = ctx->counts_host->n_iv;
       const amnerf_proposal* q = p->proposal;
       const uint64_t niv_plan = (uint64_t)niv_plain + (uint64_t)nr * (uint64_t)std::min(q->cap, p->s_max);
       SortPlan spp = make_sort_plan(niv_plan, L);
       PropWork pw;
-      rc = ensure_arena3(ctx, carve_prop(nullptr, nr, niv_plain, niv_plan, spp, pw));
+      rc = ensure_arena3_for(ctx, second, carve_prop(nullptr, nr, niv_plain, niv_plan, spp, pw));
       if (rc) return rc;
-      carve_prop((char*)ctx->arena3, nr, niv_plain, niv_plan, spp, pw);
+      carve_prop((char*)(second ? ctx->lane.arena3 : ctx->arena3), nr, niv_plain, niv_plan, spp, pw);
       HIP_TRY(launch_prop_fwd(q->dtype, q->packed_dev, plain, rays->o_dev, rays->d_dev, R, r0, tree->dev_leafbox,
-                              p->s_max, niv_plain, true, pw.wts, pw.tot, st));
+                              p->s_max, niv_plain, true, pw.wts, pw.tot, cs));
       HIP_TRY(launch_prop_select(nr, plain, pw.wts, pw.tot, q->mass_thresh, q->cap, p->s_max, pw.runs, pw.nsel, pw.mask, nullptr,
-                                 ctx->counts, st));
-      HIP_TRY(launch_scan_u32_pair(pw.runs, pw.pv_off, pw.nsel, pw.ps_off, nr, pw.scan_tmp, st));
-      HIP_TRY(launch_prop_emit(nr, plain, pw.mask, pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, st));
+                                 cc, cs));
+      HIP_TRY(launch_scan_u32_pair(pw.runs, pw.pv_off, pw.nsel, pw.ps_off, nr, pw.scan_tmp, cs));
+      HIP_TRY(launch_prop_emit(nr, plain, pw.mask, pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, cs));
       use = {pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, pw.pv_off + nr};
       spu = spp;
       mat = pw.mat; mat_scan = pw.mat_scan; sidx = pw.sidx; sn = pw.sn; ssb = pw.ssb; scan_tmp = pw.scan_tmp;
@@ -852,42 +927,47 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
       // empty-space skipping: the kept samples of each ray as runs of consecutive slots
       // (within an interval of n slots at most ceil(n/2) runs, so a ray has at most
       // (s_max + m) / 2 of them); buffers sized from the plain interval count
-      HIP_TRY(hipMemcpyAsync(&ctx->counts_host->n_iv, w.iv_off + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(hipMemcpyAsync(&ctx->counts_host->n_iv, w.iv_off + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, cs));
+      HIP_TRY(hipStreamSynchronize(cs));
       const uint64_t niv_plain = ctx->counts_host->n_iv;
       const uint64_t niv_plan = (niv_plain + (uint64_t)nr * (uint64_t)p->s_max) / 2 + nr;
       SortPlan spp = make_sort_plan(niv_plan, L);
       PropWork pw;
-      rc = ensure_arena3(ctx, carve_prop(nullptr, nr, 1, niv_plan, spp, pw));
+      rc = ensure_arena3_for(ctx, second, carve_prop(nullptr, nr, 1, niv_plan, spp, pw));
       if (rc) return rc;
-      carve_prop((char*)ctx->arena3, nr, 1, niv_plan, spp, pw);
+      carve_prop((char*)(second ? ctx->lane.arena3 : ctx->arena3), nr, 1, niv_plan, spp, pw);
       HIP_TRY(launch_occ_select(nr, plain, rays->o_dev, rays->d_dev, R, r0, occ->dev_bits, occ->g, pw.runs, pw.nsel,
-                                pw.mask, st));
-      HIP_TRY(launch_scan_u32_pair(pw.runs, pw.pv_off, pw.nsel, pw.ps_off, nr, pw.scan_tmp, st));
-      HIP_TRY(launch_prop_emit(nr, plain, pw.mask, pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, st));
+                                pw.mask, cs));
+      HIP_TRY(launch_scan_u32_pair(pw.runs, pw.pv_off, pw.nsel, pw.ps_off, nr, pw.scan_tmp, cs));
+      HIP_TRY(launch_prop_emit(nr, plain, pw.mask, pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, cs));
       use = {pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, pw.pv_off + nr};
       spu = spp;
       mat = pw.mat; mat_scan = pw.mat_scan; sidx = pw.sidx; sn = pw.sn; ssb = pw.ssb; scan_tmp = pw.scan_tmp;
       niv_use_max = niv_plan;
     }
-    HIP_TRY(launch_chunk_begin(ctx->counts, use.n_iv_dev, spu.seg, L, st));
+    HIP_TRY(launch_chunk_begin(cc, use.n_iv_dev, spu.seg, L, cs));
     HIP_TRY(mark(2));
-    HIP_TRY(launch_sort_hist(spu, use.key, use.n_iv_dev, mat, st));
-    HIP_TRY(launch_scan_u32(mat, mat_scan, (uint64_t)L * spu.nseg_max, &ctx->counts->mat_n, scan_tmp, st));
-    HIP_TRY(launch_sort_scatter(spu, use.key, use.n_iv_dev, mat_scan, sidx, sn, st));
-    HIP_TRY(launch_scan_u32(sn, ssb, niv_use_max, use.n_iv_dev, scan_tmp, st));
-    HIP_TRY(launch_bucket_tiles(spu, mat_scan, ssb, w.bucket_off, w.tile_off, ctx->counts, st));
+    HIP_TRY(launch_sort_hist(spu, use.key, use.n_iv_dev, mat, cs));
+    HIP_TRY(launch_scan_u32(mat, mat_scan, (uint64_t)L * spu.nseg_max, &cc->mat_n, scan_tmp, cs));
+    HIP_TRY(launch_sort_scatter(spu, use.key, use.n_iv_dev, mat_scan, sidx, sn, cs));
+    HIP_TRY(launch_scan_u32(sn, ssb, niv_use_max, use.n_iv_dev, scan_tmp, cs));
+    HIP_TRY(launch_bucket_tiles(spu, mat_scan, ssb, w.bucket_off, w.tile_off, cc, cs));
     HIP_TRY(mark(3));
-    HIP_TRY(launch_expand(sidx, ssb, use, r0, jitter, p->jitter_seed, w.srec_ray, w.srec_t, w.perm, st));
+    HIP_TRY(launch_expand(sidx, ssb, use, r0, jitter, p->jitter_seed, w.srec_ray, w.srec_t, w.perm, cs));
     HIP_TRY(mark(4));
-    HIP_TRY(launch_mlp(g, mlp->packed_dev, L, w.bucket_off, w.tile_off, ctx->counts, w.srec_ray, w.srec_t, w.perm,
-                       rays->o_dev, rays->d_dev, R, r0, w.smp_out, st));
+    HIP_TRY(launch_mlp(g, mlp->packed_dev, L, w.bucket_off, w.tile_off, cc, w.srec_ray, w.srec_t, w.perm,
+                       rays->o_dev, rays->d_dev, R, r0, w.smp_out, cs));
     HIP_TRY(mark(5));
     HIP_TRY(launch_composite(nr, use, w.smp_out, r0, jitter, p->jitter_seed, p->ert_eps, out->rgb_dev, out->depth_dev,
-                             out->opacity_dev, out->weights_dev, ctx->counts, st));
+                             out->opacity_dev, out->weights_dev, cc, cs));
     HIP_TRY(mark(6));
     if (ev) ev->pending = true;
-    HIP_TRY(launch_chunk_finish(ctx->counts, use.smp_off + nr, use.n_iv_dev, w.smp_off + nr, st));
+    HIP_TRY(launch_chunk_finish(cc, use.smp_off + nr, use.n_iv_dev, w.smp_off + nr, cs));
+  }
+  if (pipe) {
+    HIP_TRY(hipEventRecord(ctx->lane.join, ctx->lane.stream));
+    HIP_TRY(hipStreamWaitEvent(st, ctx->lane.join, 0));
+    HIP_TRY(launch_counts_merge(ctx->counts, ctx->lane.counts, st));
   }
   ctx->last_stream = st;
   ctx->have_render = true;
@@ -897,12 +977,12 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   ctx->last_niv_max = niv_max;
   ctx->last_ns_max = ns_max;
   ctx->use = use;
-  ctx->bucket_off = w.bucket_off;
-  ctx->perm = w.perm;
-  ctx->smp_out = w.smp_out;
-  ctx->tile_off = w.tile_off;
-  ctx->srec_ray = w.srec_ray;
-  ctx->srec_t = w.srec_t;
+  ctx->bucket_off = wl->bucket_off;
+  ctx->perm = wl->perm;
+  ctx->smp_out = wl->smp_out;
+  ctx->tile_off = wl->tile_off;
+  ctx->srec_ray = wl->srec_ray;
+  ctx->srec_t = wl->srec_t;
   ctx->last_tree = tree;
   ctx->last_packed = mlp->packed_dev;
   ctx->last_dtype = mlp->dtype;

@@ -193,6 +193,16 @@ __global__ void k_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total, uin
   counts->mat_n = n_leaves * ((n + seg - 1) / seg);
 }
 
+// Adds the second lane's running totals into the first lane's counters.
+__global__ void k_counts_merge(ChunkCounts* a, const ChunkCounts* b) {
+  if (threadIdx.x != 0) return;
+  a->smp_global += b->smp_global;
+  a->iv_global += b->iv_global;
+  a->nonfinite += b->nonfinite;
+  a->fallback += b->fallback;
+  a->plain_smp += b->plain_smp;
+}
+
 __global__ void k_counts_reset(ChunkCounts* counts) {
   if (threadIdx.x != 0) return;
   ChunkCounts z = {};
@@ -217,6 +227,11 @@ hipError_t launch_chunk_finish(ChunkCounts* counts, const uint32_t* smp_off_tota
                                hipStream_t st) {
   hipLaunchKernelGGL(k_chunk_finish, dim3(1), dim3(64), 0, st, counts, smp_off_total, iv_off_total,
                      plain_smp_total);
+  return hipGetLastError();
+}
+
+hipError_t launch_counts_merge(ChunkCounts* a, const ChunkCounts* b, hipStream_t st) {
+  hipLaunchKernelGGL(k_counts_merge, dim3(1), dim3(64), 0, st, a, b);
   return hipGetLastError();
 }
 

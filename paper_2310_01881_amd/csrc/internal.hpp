@@ -191,6 +191,7 @@ hipError_t launch_prop_train(const void* packed, const IvSet& iv, const float* o
                              float* loss_part, float* grad, float* loss, hipStream_t st);
 
 // ---- small helpers ----------------------------------------------------------------------
+hipError_t launch_counts_merge(ChunkCounts* a, const ChunkCounts* b, hipStream_t st);
 hipError_t launch_counts_reset(ChunkCounts* counts, hipStream_t st);
 hipError_t launch_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total, uint32_t seg, uint32_t n_leaves,
                               hipStream_t st);

@@ -320,3 +320,31 @@ def test_axis_parallel_and_inside_rays():
     print("axis-parallel rays: %d, robust %d, samples %d" % (R, robust.sum(), st["n_samples"]))
     assert st["n_samples"] > 0
     compare_render(scene, out, o, d, 64, rays, robust, min_ok=0.9)
+
+
+def test_multi_chunk_call_equals_chunk_by_chunk_calls():
+    """A call over 2.6 M rays at S_max 255 runs in three passes (odd passes on the second
+    lane); its outputs and sample count are bit-identical to three calls on the same slices."""
+    scene = Scene(synth.C1)
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = scene.camera_rays()
+    reps = 640
+    od = to_dev(o).repeat(1, reps).contiguous()
+    dd = to_dev(d).repeat(1, reps).contiguous()
+    R = od.shape[1]
+    chunk = (1 << 28) // 255
+    assert 2 * chunk < R < 3 * chunk
+    print("multi-chunk: rays", R, flush=True)
+    whole = am.render(ctx, tree, mlp, od, dd, 255, ert_eps=scene.cfg.ert_eps)
+    torch.cuda.synchronize()
+    st = am.amnerf_render_stats_get(ctx.h)
+    assert st["n_chunks"] == 3 and st["n_nonfinite"] == 0
+    n_samples = 0
+    for r0 in range(0, R, chunk):
+        part = am.render(ctx, tree, mlp, od[:, r0:r0 + chunk].contiguous(), dd[:, r0:r0 + chunk].contiguous(), 255,
+                         ert_eps=scene.cfg.ert_eps)
+        torch.cuda.synchronize()
+        n_samples += am.amnerf_render_stats_get(ctx.h)["n_samples"]
+        for k in ("rgb", "depth", "opacity"):
+            assert torch.equal(whole[k][r0:r0 + chunk], part[k]), (k, r0)
+    assert st["n_samples"] == n_samples
