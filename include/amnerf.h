@@ -275,8 +275,12 @@ typedef struct {
  * bucket, and per ray tau_j = sigma_j delta_j, T_j = exp(-sum_{i<j} tau_i),
  * w_j = T_j (1 - exp(-tau_j)), rgb = sum w_j c_j, depth = sum w_j t_j,
  * opacity = sum w_j, stopping after the first j with T_{j+1} < ert_eps.
- * Asynchronous on `stream`.  Rays are processed in chunks when the sample budget of
- * one pass would exceed the context's chunk limit. */
+ * Asynchronous on `stream`.  Rays are processed in chunks of at most 2^28 / s_max rays.
+ * With several chunks (and weights_dev NULL), odd chunks run on a second stream owned by
+ * the context, with a workspace of its own: that stream first waits for `stream`, and
+ * `stream` waits for it before the call returns, so the call stays ordered on `stream`
+ * and its outputs equal those of chunk-by-chunk calls.  Calls on one context must not
+ * overlap (the workspaces are reused). */
 int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
                   const amnerf_rays* rays, const amnerf_render_params* params,
                   amnerf_render_out* out, void* stream);
