@@ -279,10 +279,25 @@ static int grow_lane_buffer(amnerf_ctx* ctx, void** buf, size_t* have, size_t by
 // The second lane's stream, events, counters and chunk workspace (`need` bytes).
 static int lane_prepare(amnerf_ctx* ctx, size_t need) {
   if (!ctx->lane.stream) {
-    HIP_TRY(hipStreamCreateWithFlags(&ctx->lane.stream, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&ctx->lane.fork, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&ctx->lane.join, hipEventDisableTiming));
-    HIP_TRY(hipMalloc((void**)&ctx->lane.counts, sizeof(ChunkCounts)));
+    // all four or none: a failure leaves the context without a second lane
+    hipStream_t s = nullptr;
+    hipEvent_t f = nullptr, j = nullptr;
+    ChunkCounts* c = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&f, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc((void**)&c, sizeof(ChunkCounts));
+    if (e != hipSuccess) {
+      if (c) (void)hipFree(c);
+      if (j) (void)hipEventDestroy(j);
+      if (f) (void)hipEventDestroy(f);
+      if (s) (void)hipStreamDestroy(s);
+      return fail(AMNERF_EDEVICE, "second render lane: %s", hipGetErrorString(e));
+    }
+    ctx->lane.stream = s;
+    ctx->lane.fork = f;
+    ctx->lane.join = j;
+    ctx->lane.counts = c;
   }
   return grow_lane_buffer(ctx, &ctx->lane.arena, &ctx->lane.arena_bytes, need, need / 8);
 }
