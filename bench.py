@@ -531,6 +531,13 @@ def main():
         cpu = {"value": float(ns.sum()) / t_cpu, "unit": "samples/s", "cores": threads, "kind": "oracle",
                "sample": "%d random rays of held-out camera 0 (%.1f%% of one 800x800 frame, %d samples), "
                          "float64 plain render, %.1f s" % (n_sample, 100.0 * n_sample / R, int(ns.sum()), t_cpu)}
+        # the same oracle on one host thread, over the first sixteenth of that sample
+        sel1 = sel[:max(1, n_sample // 16)]
+        t0 = time.perf_counter()
+        ns1 = oracle.render(otree, W, cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max, eps=cfg.ert_eps, ray_idx=sel1,
+                            threads=1)[3]
+        t1c = time.perf_counter() - t0
+        cpu["one_thread"] = {"value": float(ns1.sum()) / t1c, "rays": int(sel1.size), "seconds": t1c}
         # float64 error report on the GPU over the sampled rays
         sel_dev = torch.from_numpy(sel).to(dev)
         ref_dev = torch.from_numpy(np.ascontiguousarray(rgb, dtype=np.float64)).to(dev).view(-1)
