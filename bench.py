@@ -531,8 +531,8 @@ def main():
         cpu = {"value": float(ns.sum()) / t_cpu, "unit": "samples/s", "cores": threads, "kind": "oracle",
                "sample": "%d random rays of held-out camera 0 (%.1f%% of one 800x800 frame, %d samples), "
                          "float64 plain render, %.1f s" % (n_sample, 100.0 * n_sample / R, int(ns.sum()), t_cpu)}
-        # the same oracle on one host thread, over the first sixteenth of that sample
-        sel1 = sel[:max(1, n_sample // 16)]
+        # the same oracle on one host thread, over every sixteenth ray of that sample
+        sel1 = sel[::16]
         t0 = time.perf_counter()
         ns1 = oracle.render(otree, W, cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max, eps=cfg.ert_eps, ray_idx=sel1,
                             threads=1)[3]
