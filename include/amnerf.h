@@ -305,9 +305,12 @@ int amnerf_render_stats_get(amnerf_ctx* ctx, amnerf_render_stats* out);
  *   ray_smp_off  uint32[n_rays+1]   first sample of each ray (ray-major), and the total
  *   iv_t0        float32[n_intervals]  interval start t
  *   iv_dt        float32[n_intervals]  interval length
- *   iv_slot      uint32[n_intervals]   leaf slot (the node id samples are sorted by)
+ *   iv_slot      uint32[n_intervals]   leaf slot (the node id samples are sorted by); the
+ *                                      node's preorder slot under hierarchical sampling
  *   iv_n         uint32[n_intervals]   samples in the interval
- *   bucket_off   uint32[n_leaves+1]    first sorted sample of each leaf bucket, and total
+ *   bucket_off   uint32[n_sets+1]      first sorted sample of each bucket, and the total
+ *                                      (n_sets = the MLP's parameter sets: leaves, or nodes
+ *                                      under hierarchical sampling)
  *   perm         uint32[n_samples]     ray-major index of the sample at each sorted
  *                                      position (the stable sort of samples by slot)
  *   sample_out   float32[n_samples][4] MLP output pre-activations (sigma^, r^, g^, b^) in
