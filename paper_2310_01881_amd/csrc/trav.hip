@@ -301,9 +301,13 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
         iv_base[b0 + q] = smp;
       }
     };
-    with_ahs<LDS, AHS>(tl, ahs, footprint, [&](auto av) {
+    const int got = with_ahs<LDS, AHS>(tl, ahs, footprint, [&](auto av) {
       return traverse<true, AHS>(tl.nodes, av, oo, dd, (int)meff, nper, tl.st_word, tl.st_hi, put);
     });
+    // The count pass walks the same way, so `got` equals meff.  Should a walk ever end
+    // early, the rest of the ray's range still gets well-formed entries (zero length,
+    // slot 0): later stages then never read an unwritten key.
+    for (uint32_t q = (uint32_t)got; q < meff; ++q) put((int)q, 0.f, 0.f, nper << 16);
   }
   __syncthreads();
   const uint32_t n = b1 - b0 < stage_n ? b1 - b0 : stage_n;
