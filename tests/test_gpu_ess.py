@@ -149,3 +149,23 @@ def test_c3_camera_in_two_passes_fp32():
     print("c3 ess two passes: kept %d of %d samples; max rgb err %.3e on %d rays" % (
         st["n_samples"], st["n_plain_samples"], e, ok.sum()), flush=True)
     assert e <= TOL_RGB
+
+
+def test_backward_after_skipping_is_rejected():
+    scene = Scene(synth.C1)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_BF16)
+    occ = am.Occupancy(ctx, scene.grid, cfg.grid_n, 2, 0.01)
+    o, d = scene.camera_rays()
+    od, dd = to_dev(o), to_dev(d)
+    am.render(ctx, tree, mlp, od, dd, cfg.s_max, occupancy=occ)
+    g = torch.zeros((o.shape[1], 3), dtype=torch.float32, device="cuda:0")
+    grad = torch.zeros_like(mlp.master)
+    with pytest.raises(am.AmnerfError) as e:
+        am.amnerf_render_backward(ctx.h, tree.h, mlp.desc, od, dd, g, grad)
+    assert e.value.code == am.AMNERF_ESTATE and "empty space" in am.amnerf_last_error()
+    # a plain render on the same context is differentiable again
+    am.render(ctx, tree, mlp, od, dd, cfg.s_max)
+    am.amnerf_render_backward(ctx.h, tree.h, mlp.desc, od, dd, g, grad)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(grad) == 0          # zero upstream gradient

@@ -219,3 +219,31 @@ def test_gradient_matches_central_differences_with_hcheck():
         Wm = W.copy(); Wm[s, i] = np.float32(base - h)
         fd = (loss(Wp) - loss(Wm)) / (float(Wp[s, i]) - float(Wm[s, i]))
         assert abs(grad[s, i] - fd) <= 1e-6 * max(1.0, abs(fd)), (s, i, grad[s, i], fd)
+
+
+@pytest.mark.parametrize("footprint,expected", [
+    (0.5, [(1.0, 1.25, 2), (1.25, 2.0, 5)]),     # t_stop = 2 for every inner node: leaves only
+    (0.9, [(1.0, 1.25, 2), (1.25, 2.0, 4)]),     # t_stop = 1.111: node 3 (entered at 1.25) stops
+    (1.5, [(1.0, 2.0, 0)]),                      # t_stop = 0.667: the root (entered at 1) stops
+])
+def test_hand_derived_4cube(footprint, expected):
+    """The hand-derived 4-leaf tree of the golden fixture (root split at x = 1/4, node 2
+    at y = 1/4, node 3 at y = 3/4; every inner node's longest side is 1, so t_stop = 1/f),
+    preorder slots root 0, node 2 -> 1, node 4 -> 2, node 5 -> 3, node 3 -> 4, node 6 -> 5,
+    node 7 -> 6, and a ray along +x at y = 0.1 entering at t = 1 and crossing x = 1/4 at
+    t = 1.25.  It crosses two leaves (4 and 6), so S_max = 8 gives 4 samples per interval."""
+    g = np.zeros((4, 4, 4), np.float32)
+    g[0, 0, 0] = 1.0
+    g[3, 3, 3] = 0.5
+    tree = oracle.build_tree(g.reshape(-1), 4, 2, 4)
+    assert {int(r[0]): int(r[11]) for r in tree.rows} == {1: 0, 2: 1, 4: 2, 5: 3, 3: 4, 6: 5, 7: 6}
+    o = np.array([[-1.0], [0.1], [0.5]], np.float32)
+    d = np.array([[1.0], [0.0], [0.0]], np.float32)
+    t0, t1, slot, m = oracle.trace(tree, o, d, footprint=footprint)
+    assert m[0] == len(expected)
+    for k, (e0, e1, es) in enumerate(expected):
+        assert (t0[0, k], t1[0, k], slot[0, k]) == (e0, e1, es)
+    W = synth.make_weights(tree.n_nodes, N_HIDDEN, HIDDEN, 6)
+    rec = oracle.ray_samples(tree, W, N_HIDDEN, HIDDEN, o, d, 0, 8, eps=0.0, footprint=footprint)
+    exp_t = [e0 + (j + 0.5) / 4 * (e1 - e0) for e0, e1, _ in expected for j in range(4)]
+    np.testing.assert_allclose(rec["t"], exp_t, rtol=0, atol=1e-15)
