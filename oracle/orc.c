@@ -19,6 +19,13 @@
  *     the NeRF quadrature), Section 4.1 (early termination).
  *   - analytic gradient of that quadrature and of the MLPs, and Adam (training step;
  *     not in the paper, so it follows the standard definitions).
+ *   - regular subdivision (middle planes, breadth first) for the ablation against it
+ *     ............................................................... Section 4.2, table
+ *   - hierarchical sampling: HCheck stops the descent at inner nodes, whose own MLPs
+ *     take their segments ........................................... Section 3.5, Algorithm 1
+ *   - occupancy grid and empty-space skipping ..................... Section 4.1
+ *   - the learned proposal (not in the paper): features, network, slot selection,
+ *     targets and loss, following the stated reading step by step.
  *
  * Everything is double precision; float inputs are promoted exactly.  No blocking,
  * sorting, batching or fusion: every ray is processed on its own, sample by sample.
