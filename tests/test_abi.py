@@ -43,3 +43,16 @@ def test_fp8_block_size():
         per = ((nh * H + 16) * 4 + 15) // 16 * 16 + 64 + 32 * H + (nh - 1) * H * H + 16 * H
         assert am.amnerf_mlp_packed_bytes(nh, H, am.AMNERF_FP8, 512) == per * 512
     assert am.amnerf_mlp_packed_bytes(4, 64, am.AMNERF_FP8, 1) < am.amnerf_mlp_packed_bytes(4, 64, am.AMNERF_BF16, 1) // 2
+
+
+def test_no_device_fails_loudly():
+    """Without a GPU the library reports an error: there is no CPU fallback."""
+    import pytest
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    try:
+        am.Context(0)
+        raise AssertionError("a context was created without a device")
+    except am.AmnerfError as e:
+        assert e.code == am.AMNERF_EDEVICE and am.amnerf_last_error()
