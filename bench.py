@@ -7,19 +7,24 @@ path: traversal -> (learned proposal) -> per-leaf samples -> sort by leaf -> gro
 -> compositing.  Rays of 8 held-out cameras are resident in HBM before the timed region;
 step k renders camera k mod 8.  Five paths are timed: plain float32, plain bfloat16,
 bfloat16 with the learned proposal (bfloat16 inference, <= 48 samples per ray, fallback
-below 0.99 predicted mass), and float8 (e4m3) leaf weights without and with the proposal.  The proposal is first trained (untimed) by the library's own
-kernels on plain-render targets from 200 seeded training cameras.  Each path is timed one
-frame at a time (with per-stage event timing), then with --inflight frames in flight (one
-library context per stream, frame k on stream k mod N; every frame is still rendered in
-full, and the last frame of each stream is checked bit-identical to the same camera
-rendered alone).  `value` is the proposal path's samples/s (samples evaluated by the leaf
-MLPs) with frames in flight, and `ms_per_step` its ms/frame.  The oracle (float64, CPU) renders a bounded random subset of camera 0's rays:
-that gives the CPU baseline and the PSNR of each GPU path against the oracle.
+below 0.99 predicted mass), and float8 (e4m3) leaf weights without and with the proposal.
+The proposal is first trained (untimed) by the library's own kernels on plain-render
+targets from 200 seeded training cameras.  Each path is timed one frame at a time (with
+per-stage event timing), then with --inflight frames in flight (one library context per
+stream, frame k on stream k mod N; every frame is still rendered in full, and the last
+frame of each stream is checked bit-identical to the same camera rendered alone).
+`value` is the proposal path's samples/s (samples evaluated by the leaf MLPs) with frames
+in flight, and `ms_per_step` its ms/frame.  The oracle (float64, CPU) renders a bounded
+random subset of camera 0's rays: that gives the CPU baseline and the PSNR of each GPU
+path against the oracle.  The same scene is also rendered with a regular-subdivision
+tree (the ablation without the adaptive split) and with hierarchical sampling at three
+footprints, and a training step is timed.
 
 A second, larger workload follows in the same run and is reported under `large_scene`
 (skip it with --no-large): 1920x1080 frames of a 256^3-grid scene with a 100:1 blob-density
 skew, a 4096-leaf tree, float8 (and bfloat16) leaf weights and S_max 192; one call renders
-30 held-out cameras, with and without a proposal trained on 200 other cameras.
+30 held-out cameras, with and without a proposal trained on 200 other cameras, and with
+empty space skipped by an occupancy grid.
 """
 from __future__ import annotations
 
