@@ -224,6 +224,8 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 1920x1080 4096-leaf scene")
     ap.add_argument("--large-calls", type=int, default=3, help="timed 30-camera calls of the large scene")
     ap.add_argument("--large-prop-steps", type=int, default=6000, help="proposal training steps, large scene")
+    ap.add_argument("--ablation-steps", type=int, default=400,
+                    help="training steps per student of the ablation's quality comparison (0: skip)")
     ap.add_argument("--inflight", type=int, default=2,
                     help="frames in flight for the throughput line: contexts on streams of their own")
     args = ap.parse_args()
@@ -424,6 +426,55 @@ def main():
             ablation["adaptive_samples_per_frame"]))
         rtree.close()
         del rmlp
+
+    # ---- the ablation's quality side: a finer field (a 4096-leaf adaptive tree on the same
+    #      grid, random 4x64 leaf MLPs following the density) is the teacher; 64-leaf students
+    #      on the adaptive and on the regular tree are fitted to its renders by the library's
+    #      training step (same rays, seeds, steps and learning rate), then rendered on a
+    #      held-out camera against the teacher ----
+    if ablation is not None and args.ablation_steps > 0:
+        t0 = time.perf_counter()
+        ttree = am.Tree(ctx, grid, cfg.grid_n, cfg.max_depth, 4096)
+        tdens = synth.leaf_mean_density(grid, cfg.grid_n, ttree.leaf_boxes())
+        tW = synth.make_weights(ttree.n_leaves, cfg.n_hidden, cfg.hidden, cfg.seed_weights + 50, tdens)
+        tmlp = am.Mlp(ctx, torch.from_numpy(tW).to(dev), cfg.n_hidden, cfg.hidden, am.AMNERF_F32, ttree.n_leaves)
+        B = 65536
+        tcams = synth.make_cameras(100, cfg.seed_batches + 7, cfg.width, cfg.height)
+        po, pd = synth.random_pixel_rays(tcams, 8 * B, cfg.seed_batches + 8)
+        po, pd = torch.from_numpy(po).to(dev), torch.from_numpy(pd).to(dev)
+        ptgt = torch.empty((8 * B, 3), device=dev)
+        am.amnerf_render(ctx.h, ttree.h, tmlp.desc, po, pd, cfg.s_max, ptgt, None, None, None, cfg.ert_eps)
+        o0, d0 = rays[0]
+        ref = torch.empty((R, 3), device=dev)
+        am.amnerf_render(ctx.h, ttree.h, tmlp.desc, o0, d0, cfg.s_max, ref, None, None, None, cfg.ert_eps)
+        batches = [(po[:, i * B:(i + 1) * B].contiguous(), pd[:, i * B:(i + 1) * B].contiguous(),
+                    ptgt[i * B:(i + 1) * B].contiguous()) for i in range(8)]
+        quality = {"teacher": "4096-leaf adaptive tree, random 4x64 leaf MLPs (density-following sigma biases)",
+                   "students": "64 leaves, 4x64 bf16 leaf MLPs, %d Adam steps of %d rays (lr 1e-3) on teacher renders "
+                               "from 100 cameras; PSNR of camera 0 against the teacher" % (args.ablation_steps, B)}
+        for name, split in (("adaptive", am.AMNERF_SPLIT_MEDIAN), ("regular", am.AMNERF_SPLIT_MIDDLE)):
+            stree = am.Tree(ctx, grid, cfg.grid_n, cfg.max_depth, 64, split)
+            sdens = synth.leaf_mean_density(grid, cfg.grid_n, stree.leaf_boxes())
+            sW = synth.make_weights(stree.n_leaves, cfg.n_hidden, cfg.hidden, cfg.seed_student, sdens)
+            tr = am.Trainer(ctx, stree, torch.from_numpy(sW).to(dev), cfg.n_hidden, cfg.hidden)
+            first = float(tr.step(*batches[0], cfg.s_max, lr=1e-3).item())
+            for it in range(1, args.ablation_steps):
+                tr.step(*batches[it % 8], cfg.s_max, lr=1e-3)
+            last = float(tr.loss.item())
+            img = torch.empty((R, 3), device=dev)
+            am.amnerf_render(ctx.h, stree.h, tr.mlp, o0, d0, cfg.s_max, img, None, None, None, cfg.ert_eps)
+            ns = am.amnerf_render_stats_get(ctx.h)["n_samples"]
+            rep = am.amnerf_error_stats(ctx.h, img.view(-1), ref.view(-1).double())
+            quality[name] = {"psnr_vs_teacher_db": rep["psnr"], "loss_first_last": [first, last],
+                             "samples_per_frame": ns}
+            log("ablation quality, %s tree: %.2f dB against the teacher after %d steps (loss %.3e -> %.3e)" % (
+                name, rep["psnr"], args.ablation_steps, first, last))
+            del tr
+            stree.close()
+        quality["seconds"] = time.perf_counter() - t0
+        ablation["quality"] = quality
+        del tmlp, batches, po, pd, ptgt
+        ttree.close()
 
     # ---- hierarchical sampling (HCheck): every node gets an MLP, plain bf16 render, same
     #      cameras; the footprint (sample spacing per unit distance) is a free parameter ----
