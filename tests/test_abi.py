@@ -56,3 +56,34 @@ def test_no_device_fails_loudly():
         raise AssertionError("a context was created without a device")
     except am.AmnerfError as e:
         assert e.code == am.AMNERF_EDEVICE and am.amnerf_last_error()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every C struct the binding mirrors has the header's size and field offsets (a C
+    program compiled against include/amnerf.h prints them)."""
+    import shutil
+    import subprocess
+    import pytest
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {name: getattr(am, name) for name in dir(am)
+               if name.startswith("amnerf_") and isinstance(getattr(am, name), type)
+               and issubclass(getattr(am, name), ctypes.Structure)}
+    assert len(structs) >= 14
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "amnerf.h"', 'int main(void) {']
+    for name, st in structs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in st._fields_:
+            lines.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                                check=True).stdout.splitlines())
+    for name, st in structs.items():
+        assert int(got[name + " size"]) == ctypes.sizeof(st), name
+        for f, _ in st._fields_:
+            assert int(got["%s.%s" % (name, f)]) == getattr(st, f).offset, (name, f)
