@@ -275,7 +275,9 @@ typedef struct {
  * bucket, and per ray tau_j = sigma_j delta_j, T_j = exp(-sum_{i<j} tau_i),
  * w_j = T_j (1 - exp(-tau_j)), rgb = sum w_j c_j, depth = sum w_j t_j,
  * opacity = sum w_j, stopping after the first j with T_{j+1} < ert_eps.
- * Asynchronous on `stream`.  Rays are processed in chunks of at most 2^28 / s_max rays.
+ * Asynchronous on `stream`, except that with a proposal or an occupancy grid each pass
+ * waits on the host for its plain interval count (to size the planned intervals).  Rays
+ * are processed in chunks of at most 2^28 / s_max rays.
  * With several chunks (and weights_dev NULL), odd chunks run on a second stream owned by
  * the context, with a workspace of its own: that stream first waits for `stream`, and
  * `stream` waits for it before the call returns, so the call stays ordered on `stream`
