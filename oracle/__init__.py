@@ -69,7 +69,7 @@ def lib():
         _lib.orc_stratum_offset.argtypes = [i32, u64, i64, i32]
         _lib.orc_stratum_offset.restype = dbl
         _lib.orc_render_proposal.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, P, i64, P, i64, i32, dbl,
-                                             dbl, i32, P, P, P, P, P, P, P, i32]
+                                             dbl, i32, P, P, P, P, P, P, P, i32, P]
         _lib.orc_prop_eval.argtypes = [P, i32, i32, P, P, P, i64, P, i64, i32, i64, P, P]
         _lib.orc_prop_eval.restype = i64
         _lib.orc_prop_targets.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, P, i64, i32, i64, P]
@@ -279,8 +279,9 @@ def prop_param_count():
 
 
 def render_proposal(tree: Tree, params, n_hidden, hidden, prop, o, d, s_max, eps=1e-4, mass_thresh=0.99,
-                    cap=48, ray_idx=None, threads=None):
-    """Per ray: rgb, depth, opacity, samples used, plan size (-1 = fallback), plan slots [n][cap], M^."""
+                    cap=48, ray_idx=None, threads=None, tau=None):
+    """Per ray: rgb, depth, opacity, samples used, plan size (-1 = fallback), plan slots [n][cap], M^.
+    tau: for a single ray, given bin thicknesses [intervals][32] in place of the network's."""
     params = _c(params, np.float32)
     prop = _c(prop, np.float32)
     o = _c(o, np.float32); d = _c(d, np.float32)
@@ -293,7 +294,7 @@ def render_proposal(tree: Tree, params, n_hidden, hidden, prop, o, d, s_max, eps
     rc = lib().orc_render_proposal(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(params), params.shape[0],
                                    n_hidden, hidden, _p(prop), _p(o), _p(d), R, _p(ri), n, s_max, eps,
                                    mass_thresh, cap, _p(rgb), _p(depth), _p(opac), _p(ns), _p(pn), _p(psel),
-                                   _p(mass), threads)
+                                   _p(mass), threads, _p(None if tau is None else _c(tau, np.float64)))
     if rc != 0:
         raise ValueError("orc_render_proposal failed")
     return rgb, depth, opac, ns, pn, psel, mass

@@ -971,8 +971,11 @@ static void order_desc(const double* p, int n, int* order) {
    largest p (ties: earlier slot) whose sum reaches mass_thresh * M^, if M^ >= mass_thresh and
    that set has at most cap slots; otherwise fallback.  sel[] receives the chosen plain slot
    indices in increasing order. */
+/* tau_in: when not NULL, the bins' optical thicknesses of the ray's intervals ([meff][32])
+   are taken from it instead of the network (for pins with known thicknesses). */
 static void plan_ray(const otree* T, const double* PP, const double o[3], const double d[3], const oiv* iv,
-                     int m, int s_max, double mass_thresh, int cap, oplan* pl, int* sel, double* p_out) {
+                     int m, int s_max, double mass_thresh, int cap, oplan* pl, int* sel, double* p_out,
+                     const double* tau_in) {
   pl->n_sel = -1;
   pl->mass = 0.0;
   pl->n_plain = 0;
@@ -987,8 +990,12 @@ static void plan_ray(const otree* T, const double* PP, const double o[3], const 
     int node = -1;
     for (int i = 0; i < T->nn; ++i) if (T->rows[(int64_t)i * NODE_COLS + 10] == iv[k].slot) { node = i; break; }
     double f[PROP_IN], tau[PROP_BINS];
-    prop_features(o, d, iv[k].t0, iv[k].t1, k, s_max, T->rows + (int64_t)node * NODE_COLS, T->grid_n, f);
-    prop_forward(PP, f, tau, NULL);
+    if (tau_in) {
+      for (int b = 0; b < PROP_BINS; ++b) tau[b] = tau_in[k * PROP_BINS + b];
+    } else {
+      prop_features(o, d, iv[k].t0, iv[k].t1, k, s_max, T->rows + (int64_t)node * NODE_COLS, T->grid_n, f);
+      prop_forward(PP, f, tau, NULL);
+    }
     for (int b = 0; b < PROP_BINS; ++b) {
       double w = exp(-S) * (-expm1(-tau[b]));
       S += tau[b];
@@ -1030,8 +1037,9 @@ int orc_render_proposal(const int32_t* rows, int nn, int grid_n, const float* pa
                         int hidden, const float* prop_params, const float* o, const float* d, int64_t R,
                         const int64_t* ray_idx, int64_t n_sel, int s_max, double eps, double mass_thresh, int cap,
                         double* rgb, double* depth, double* opac, int32_t* n_samples, int32_t* plan_n,
-                        int32_t* plan_sel, double* mass, int n_threads) {
-  if (s_max < 1 || cap < 1) return -1;
+                        int32_t* plan_sel, double* mass, int n_threads, const double* tau_in) {
+  /* tau_in (given bin thicknesses instead of the network's) serves a single ray */
+  if (s_max < 1 || cap < 1 || (tau_in && n_sel != 1)) return -1;
   otree T; olayout L; double* P = NULL; octx C;
   if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden, 0.0f)) {
     free(P); otree_free(&T); return -1;
@@ -1053,7 +1061,7 @@ int orc_render_proposal(const int32_t* rows, int nn, int grid_n, const float* pa
       int m = trace_ray(&T, oo, dd, &IL);
       int ns = make_samples(ivbuf, m, m, s_max, 0, 0, r, sbuf);
       oplan pl;
-      plan_ray(&T, PP, oo, dd, ivbuf, m, s_max, mass_thresh, cap, &pl, sel, p);
+      plan_ray(&T, PP, oo, dd, ivbuf, m, s_max, mass_thresh, cap, &pl, sel, p, tau_in);
       int use = pl.n_sel < 0 ? ns : pl.n_sel;
       double Sacc = 0.0, cr[3] = {0, 0, 0}, dep = 0.0, op = 0.0;
       for (int q = 0; q < use; ++q) {

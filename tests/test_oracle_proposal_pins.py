@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 import synth
+from test_oracle_pins import constant_field
 
 
 def scene():
@@ -175,3 +176,35 @@ def test_plan_invariants_and_all_fallback(s_max):
     np.testing.assert_array_equal(rgb2, rgb0)
     np.testing.assert_array_equal(dep2, dep0)
     np.testing.assert_array_equal(ns2, ns0)
+
+
+@pytest.mark.parametrize("sigma0,thresh", [(5.0, 0.9), (3.0, 0.95), (8.0, 0.99)])
+def test_exact_histogram_selects_the_front_slots(sigma0, thresh):
+    """A proposal that predicts the true bin thicknesses of a constant-density ray: one leaf,
+    a ray along z with chord 1 and S_max = 32, so each of the 32 slots is one bin, bin b
+    has thickness sigma0 / 32 and weight exp(-sigma0 b / 32) (1 - exp(-sigma0 / 32)),
+    decreasing along the ray.  The plan keeps the first c slots, c the least count with
+    1 - exp(-sigma0 c / 32) >= thresh (1 - exp(-sigma0)); the planned render is the plain
+    quadrature over them, so its opacity is 1 - exp(-sigma0 c / 32) and it differs from the
+    plain render by exactly the skipped weight."""
+    g = np.ones(8 ** 3, np.float32)
+    tree = oracle.build_tree(g, 8, 0, 1)
+    W, sig = constant_field(1, 2, 32, sigma0, [0.4, -0.2, 1.0])
+    s0 = float(sig[0])
+    c0 = 1 / (1 + np.exp(-np.array([0.4, -0.2, 1.0], np.float32).astype(np.float64)))
+    o = np.array([[0.37], [0.61], [-1.0]], np.float32)
+    d = np.array([[0.0], [0.0], [1.0]], np.float32)
+    tau = np.full((1, 32), s0 / 32)
+    prop = np.zeros(oracle.prop_param_count(), np.float32)
+    rgb, dep, op, ns, pn, psel, mass = oracle.render_proposal(tree, W, 2, 32, prop, o, d, 32, eps=0.0,
+                                                              mass_thresh=thresh, cap=32, tau=tau)
+    M = -math.expm1(-s0)
+    assert abs(mass[0] - M) < 1e-14
+    c = math.ceil(-32 / s0 * math.log(1 - thresh * M) - 1e-12)
+    assert pn[0] == c and ns[0] == c
+    assert list(psel[0, :c]) == list(range(c))
+    op_c = -math.expm1(-s0 * c / 32)
+    assert abs(op[0] - op_c) < 1e-14
+    np.testing.assert_allclose(rgb[0], c0 * op_c, rtol=0, atol=1e-14)
+    _, _, op_plain, _, _ = oracle.render(tree, W, 2, 32, o, d, 32, eps=0.0)
+    assert abs((op_plain[0] - op[0]) - (math.exp(-s0 * c / 32) - math.exp(-s0))) < 1e-14
