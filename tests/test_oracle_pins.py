@@ -475,3 +475,30 @@ def test_middle_split_is_regular_subdivision(n, max_depth, max_leaves):
         assert np.all(depths == k)
         assert np.all(ext.max(axis=1) <= side) and np.all(ext.min(axis=1) >= side // 2)
         assert np.all(np.prod(ext, axis=1) == n ** 3 // max_leaves)
+
+
+def test_middle_split_hand_derived():
+    """4^3 grid, regular subdivision: the root's sides tie, so x is cut at cell 2; then the
+    depth-1 leaves in code order (2 before 3), each 2x4x4 cells, are cut along y at cell 2.
+    Rows: code, depth, lo, hi, axis, plane, leaf slot, node slot."""
+    g = np.random.default_rng(9).uniform(0, 1, 4 ** 3).astype(np.float32)   # ignored by the split
+    rows4 = [
+        (1, 0, 0, 0, 0, 4, 4, 4, 0, 2, -1, 0),
+        (2, 1, 0, 0, 0, 2, 4, 4, 1, 2, -1, 1),
+        (3, 1, 2, 0, 0, 4, 4, 4, 1, 2, -1, 4),
+        (4, 2, 0, 0, 0, 2, 2, 4, -1, -1, 0, 2),
+        (5, 2, 0, 2, 0, 2, 4, 4, -1, -1, 1, 3),
+        (6, 2, 2, 0, 0, 4, 2, 4, -1, -1, 2, 5),
+        (7, 2, 2, 2, 0, 4, 4, 4, -1, -1, 3, 6),
+    ]
+    t = oracle.build_tree(g, 4, 2, 4, split=1)
+    np.testing.assert_array_equal(t.rows, np.array(rows4, np.int32))
+    rows3 = [
+        (1, 0, 0, 0, 0, 4, 4, 4, 0, 2, -1, 0),
+        (2, 1, 0, 0, 0, 2, 4, 4, 1, 2, -1, 1),
+        (3, 1, 2, 0, 0, 4, 4, 4, -1, -1, 2, 4),
+        (4, 2, 0, 0, 0, 2, 2, 4, -1, -1, 0, 2),
+        (5, 2, 0, 2, 0, 2, 4, 4, -1, -1, 1, 3),
+    ]
+    t = oracle.build_tree(g, 4, 2, 3, split=1)
+    np.testing.assert_array_equal(t.rows, np.array(rows3, np.int32))
