@@ -24,7 +24,7 @@ A second, larger workload follows in the same run and is reported under `large_s
 (skip it with --no-large): 1920x1080 frames of a 256^3-grid scene with a 100:1 blob-density
 skew, a 4096-leaf tree, float8 (and bfloat16) leaf weights and S_max 192; one call renders
 30 held-out cameras, with and without a proposal trained on 200 other cameras, and with
-empty space skipped by an occupancy grid.
+empty space skipped by an occupancy grid (--large-paths picks a subset of these paths).
 """
 from __future__ import annotations
 
@@ -52,6 +52,9 @@ def cpu_threads():
     except AttributeError:
         n = os.cpu_count() or 1
     return max(1, min(16, n))
+
+
+LARGE_PATHS = ("fp8", "fp8_prop", "bf16", "bf16_prop", "fp8_untrained_prop", "fp8_ess")
 
 
 def large_scene(args, am, torch, np, synth, ctx):
@@ -84,36 +87,44 @@ def large_scene(args, am, torch, np, synth, ctx):
         d_all[:, i * R1:(i + 1) * R1] = torch.from_numpy(d).to(dev)
     log("large scene %s: %d leaves, %d rays per call, set-up %.1f s" % (cfg.name, L, R, time.perf_counter() - t0))
 
-    # proposal trained on 200 other cameras (untimed)
-    t0 = time.perf_counter()
-    prop = am.Proposal(ctx, torch.from_numpy(synth.make_prop_weights(cfg.seed_proposal)).to(dev))
-    untrained = am.Proposal(ctx, torch.from_numpy(synth.make_prop_weights(cfg.seed_proposal)).to(dev))
-    untrained.repack()
-    train_cams = synth.make_cameras(200, cfg.seed_batches, cfg.width, cfg.height)
-    pool_o, pool_d = synth.random_pixel_rays(train_cams, 2_000_000, cfg.seed_batches + 1)
-    pool_o, pool_d = torch.from_numpy(pool_o).to(dev), torch.from_numpy(pool_d).to(dev)
-    gen = torch.Generator(device=dev).manual_seed(cfg.seed_batches + 2)
-    losses = []
-    for it in range(args.large_prop_steps):
-        lr = 3e-3 if it < 0.7 * args.large_prop_steps else 1e-3
-        idx = torch.randint(0, pool_o.shape[1], (args.prop_batch,), device=dev, generator=gen)
-        loss = prop.train_step(tree, mlps["f32"].desc, pool_o[:, idx].contiguous(), pool_d[:, idx].contiguous(),
-                               cfg.s_max, lr=lr)
-        if it % 1000 == 0 or it == args.large_prop_steps - 1:
-            losses.append(float(loss.item()))
-    prop.repack()
-    torch.cuda.synchronize()
-    t_prop = time.perf_counter() - t0
-    del pool_o, pool_d
-    log("large proposal: %d steps in %.1f s, loss %s" % (args.large_prop_steps, t_prop, ["%.2e" % v for v in losses]))
-    desc = prop.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
-    desc_untrained = untrained.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
+    wanted = [k for k in LARGE_PATHS if k in args.large_paths.split(",")]
+    prop_training = None
+    desc = desc_untrained = None
+    if any(k.endswith("_prop") for k in wanted):
+        # proposal trained on 200 other cameras (untimed)
+        t0 = time.perf_counter()
+        prop = am.Proposal(ctx, torch.from_numpy(synth.make_prop_weights(cfg.seed_proposal)).to(dev))
+        untrained = am.Proposal(ctx, torch.from_numpy(synth.make_prop_weights(cfg.seed_proposal)).to(dev))
+        untrained.repack()
+        train_cams = synth.make_cameras(200, cfg.seed_batches, cfg.width, cfg.height)
+        pool_o, pool_d = synth.random_pixel_rays(train_cams, 2_000_000, cfg.seed_batches + 1)
+        pool_o, pool_d = torch.from_numpy(pool_o).to(dev), torch.from_numpy(pool_d).to(dev)
+        gen = torch.Generator(device=dev).manual_seed(cfg.seed_batches + 2)
+        losses = []
+        for it in range(args.large_prop_steps):
+            lr = 3e-3 if it < 0.7 * args.large_prop_steps else 1e-3
+            idx = torch.randint(0, pool_o.shape[1], (args.prop_batch,), device=dev, generator=gen)
+            loss = prop.train_step(tree, mlps["f32"].desc, pool_o[:, idx].contiguous(),
+                                   pool_d[:, idx].contiguous(), cfg.s_max, lr=lr)
+            if it % 1000 == 0 or it == args.large_prop_steps - 1:
+                losses.append(float(loss.item()))
+        prop.repack()
+        torch.cuda.synchronize()
+        t_prop = time.perf_counter() - t0
+        del pool_o, pool_d
+        log("large proposal: %d steps in %.1f s, loss %s" % (args.large_prop_steps, t_prop,
+                                                              ["%.2e" % v for v in losses]))
+        desc = prop.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
+        desc_untrained = untrained.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
+        prop_training = {"steps": args.large_prop_steps, "rays_per_step": args.prop_batch, "cameras": 200,
+                         "seconds": t_prop, "loss_first_last": [losses[0], losses[-1]] if losses else None}
 
     # empty-space skipping: occupancy at half the guidance resolution, 1 % of the peak density
     occ = am.Occupancy(ctx, grid, cfg.grid_n, 2, 0.01)
     paths = {"fp8": ("fp8", None, None), "fp8_prop": ("fp8", desc, None), "bf16": ("bf16", None, None),
              "bf16_prop": ("bf16", desc, None), "fp8_untrained_prop": ("fp8", desc_untrained, None),
              "fp8_ess": ("fp8", None, occ)}
+    paths = {k: paths[k] for k in wanted}
     outs = {k: torch.empty((R, 3), dtype=torch.float32, device=dev) for k in paths}
 
     def render(kind, rgb):
@@ -152,30 +163,36 @@ def large_scene(args, am, torch, np, synth, ctx):
     # of the 30 cameras (the outputs of the last timed call)
     psnr_prop_vs_plain = {}
     for kind, ref in (("fp8_prop", "fp8"), ("bf16_prop", "bf16"), ("fp8_untrained_prop", "fp8"), ("fp8_ess", "fp8")):
+        if kind not in outs or ref not in outs:
+            continue
         rep = am.amnerf_error_stats(ctx.h, outs[kind].view(-1), outs[ref].view(-1).double())
         psnr_prop_vs_plain[kind] = rep["psnr"]
     log("large proposal psnr vs plain: %s" % {k: round(v, 2) for k, v in psnr_prop_vs_plain.items()})
 
-    # bucket sizes of one single-chunk pass: the first 2^20 rays of camera 0
-    n_sub = 1 << 20
-    o_sub, d_sub = o_all[:, :n_sub].contiguous(), d_all[:, :n_sub].contiguous()
-    sub_rgb = torch.empty((n_sub, 3), dtype=torch.float32, device=dev)
-    am.amnerf_render(ctx.h, tree.h, mlps["fp8"].desc, o_sub, d_sub, cfg.s_max, sub_rgb, None, None, None, cfg.ert_eps)
-    st = am.amnerf_render_stats_get(ctx.h)
-    ns = st["n_samples"]
-    bo = torch.empty(L + 1, dtype=torch.int32, device=dev)
-    am.amnerf_render_inspect(ctx.h, bucket_off=bo)
-    sizes = np.diff(bo.cpu().numpy().astype(np.int64))
-    nz = sizes[sizes > 0]
-    spread = {"rays": n_sub, "samples": int(ns), "leaves_nonempty": int(nz.size),
-              "min": int(nz.min()), "p1": float(np.percentile(nz, 1)), "median": float(np.median(nz)),
-              "p99": float(np.percentile(nz, 99)), "max": int(nz.max()),
-              "max_over_min_nonempty": float(nz.max() / nz.min()),
-              "p99_over_p1": float(np.percentile(nz, 99) / max(np.percentile(nz, 1), 1))}
-    log("large bucket sizes: %s" % spread)
+    # bucket sizes of one single-chunk pass (plain e4m3): the first 2^20 rays of camera 0
+    spread = None
+    if "fp8" in outs:
+        n_sub = 1 << 20
+        o_sub, d_sub = o_all[:, :n_sub].contiguous(), d_all[:, :n_sub].contiguous()
+        sub_rgb = torch.empty((n_sub, 3), dtype=torch.float32, device=dev)
+        am.amnerf_render(ctx.h, tree.h, mlps["fp8"].desc, o_sub, d_sub, cfg.s_max, sub_rgb, None, None, None,
+                         cfg.ert_eps)
+        st = am.amnerf_render_stats_get(ctx.h)
+        ns = st["n_samples"]
+        bo = torch.empty(L + 1, dtype=torch.int32, device=dev)
+        am.amnerf_render_inspect(ctx.h, bucket_off=bo)
+        sizes = np.diff(bo.cpu().numpy().astype(np.int64))
+        nz = sizes[sizes > 0]
+        spread = {"rays": n_sub, "samples": int(ns), "leaves_nonempty": int(nz.size),
+                  "min": int(nz.min()), "p1": float(np.percentile(nz, 1)), "median": float(np.median(nz)),
+                  "p99": float(np.percentile(nz, 99)), "max": int(nz.max()),
+                  "max_over_min_nonempty": float(nz.max() / nz.min()),
+                  "p99_over_p1": float(np.percentile(nz, 99) / max(np.percentile(nz, 1), 1))}
+        log("large bucket sizes: %s" % spread)
 
     acc = None
-    if not args.no_cpu:
+    acc_kinds = [k for k in ("fp8", "fp8_prop", "fp8_ess") if k in outs]
+    if not args.no_cpu and acc_kinds:
         import oracle
         from oracle import fp8 as ofp8
         otree = oracle.build_tree(grid, cfg.grid_n, cfg.max_depth, cfg.max_leaves)
@@ -190,7 +207,7 @@ def large_scene(args, am, torch, np, synth, ctx):
                                           eps=cfg.ert_eps, ray_idx=sel, threads=threads)
         sel_dev = torch.from_numpy(sel).to(dev)
         acc = {"rays": int(sel.size), "sample": "seeded 1/64 pixel subset of camera 0"}
-        for kind in ("fp8", "fp8_prop", "fp8_ess"):
+        for kind in acc_kinds:
             x = outs[kind][:R1][sel_dev].contiguous().view(-1)
             acc["psnr_%s_vs_oracle_db" % kind] = am.amnerf_error_stats(
                 ctx.h, x, torch.from_numpy(np.ascontiguousarray(rgb_o)).to(dev).view(-1))["psnr"]
@@ -204,8 +221,7 @@ def large_scene(args, am, torch, np, synth, ctx):
             "n_leaves": L, "rays_per_call": R, "cameras_per_call": n_cams, "paths": res,
             "occupancy": {"cells": occ.g ** 3, "occupied": occ.n_occupied, "block": 2, "thresh": 0.01},
             "psnr_vs_plain_db": psnr_prop_vs_plain, "bucket_sizes": spread, "accuracy": acc,
-            "proposal_training": {"steps": args.large_prop_steps, "rays_per_step": args.prop_batch, "cameras": 200,
-                                  "seconds": t_prop, "loss_first_last": [losses[0], losses[-1]]}}
+            "proposal_training": prop_training}
 
 
 def main():
@@ -224,6 +240,9 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 1920x1080 4096-leaf scene")
     ap.add_argument("--large-calls", type=int, default=3, help="timed 30-camera calls of the large scene")
     ap.add_argument("--large-prop-steps", type=int, default=6000, help="proposal training steps, large scene")
+    ap.add_argument("--large-paths", default=",".join(LARGE_PATHS),
+                    help="comma-separated render paths of the large scene (each PSNR comparison needs its "
+                         "plain reference path too)")
     ap.add_argument("--ablation-steps", type=int, default=400,
                     help="training steps per student of the ablation's quality comparison (0: skip)")
     ap.add_argument("--inflight", type=int, default=2,
@@ -233,6 +252,9 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path (rays would shard "
               "across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
+    bad = set(args.large_paths.split(",")) - set(LARGE_PATHS)
+    if bad:
+        ap.error("unknown --large-paths entries %s (known: %s)" % (sorted(bad), ",".join(LARGE_PATHS)))
 
     import numpy as np
     import torch

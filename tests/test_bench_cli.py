@@ -1,5 +1,5 @@
-"""bench.py's command line on the CPU: more than one GPU is refused with a message, before
-any device work."""
+"""bench.py's command line on the CPU: more than one GPU, or an unknown render path of the
+large scene, is refused with a message before any device work."""
 import os
 import subprocess
 import sys
@@ -12,4 +12,12 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+    assert p.stdout == ""
+
+
+def test_unknown_large_path_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--large-paths", "fp8,fp16_ess"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "fp16_ess" in p.stderr
     assert p.stdout == ""
