@@ -1,6 +1,7 @@
 """Empty-space skipping on the GPU: the occupancy grid bit-exact against the oracle's, per-ray
 kept-sample counts exact and renders within the float32 bars against the oracle run with the
-same grid, an all-occupied grid bit-identical to the plain render, and argument checks."""
+same grid, an all-occupied grid bit-identical to the plain render, an all-empty one black,
+and argument checks."""
 from __future__ import annotations
 
 import numpy as np
@@ -100,6 +101,23 @@ def test_all_occupied_is_bit_identical_to_plain():
     torch.cuda.synchronize()
     for k in ("rgb", "depth", "opacity"):
         assert torch.equal(plain[k], ess[k]), k
+
+
+def test_all_empty_renders_black():
+    """An occupancy grid with no occupied cell (a zero guidance grid) drops every sample: the
+    plain intervals are still traversed, nothing reaches the MLP and every output is 0."""
+    scene = Scene(synth.C1)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    empty = am.Occupancy(ctx, np.zeros(cfg.grid_n ** 3, np.float32), cfg.grid_n, 2, 0.0)
+    assert empty.n_occupied == 0
+    o, d = scene.camera_rays()
+    out = am.render(ctx, tree, mlp, to_dev(o), to_dev(d), cfg.s_max, ert_eps=cfg.ert_eps, occupancy=empty)
+    torch.cuda.synchronize()
+    st = am.amnerf_render_stats_get(ctx.h)
+    assert st["n_samples"] == 0 and st["n_plain_samples"] > 0 and st["n_nonfinite"] == 0
+    for k in ("rgb", "depth", "opacity"):
+        assert torch.count_nonzero(out[k]) == 0, k
 
 
 def test_argument_checks():
