@@ -1,6 +1,7 @@
 """Hierarchical sampling (Section 3.5, HCheck) on the GPU: intervals keyed by node slot,
-samples, sort and renders against the oracle run with the same footprint; the backward
-through node MLPs against the oracle's gradient; argument checks."""
+samples, sort and renders against the oracle run with the same footprint; the two limits of
+the footprint (the root stops every ray; no node stops any); the backward through node MLPs
+against the oracle's gradient; argument checks."""
 from __future__ import annotations
 
 import numpy as np
@@ -172,3 +173,52 @@ def test_hcheck_node_count_capacity():
     with pytest.raises(am.AmnerfError) as e:
         am.amnerf_render(ctx.h, tree.h, mlp.desc, to_dev(o), to_dev(d), 32, rgb, hcheck_footprint=0.1)
     assert e.value.code == am.AMNERF_ECAPACITY
+
+
+def test_hcheck_root_only_fp32():
+    """A footprint so large that the root stops every ray (the cameras are outside the box, so
+    every ray enters it at t > 0): one interval per hit ray, keyed by the root's slot 0, every
+    sample in the root's bucket; renders against the oracle."""
+    scene = Scene(synth.C1, footprint=1e30)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = scene.camera_rays()
+    R = o.shape[1]
+    out = render_all(scene, ctx, tree, mlp, o, d, cfg.s_max)
+    st, ins = fetch_inspect(ctx, R, scene.n_sets)
+    assert st["n_nonfinite"] == 0
+    m = np.diff(ins["ray_iv_off"].astype(np.int64))
+    assert m.max() == 1 and st["n_intervals"] == np.count_nonzero(m) > 0
+    assert np.all(ins["iv_slot"] == 0)
+    assert ins["bucket_off"][1] == st["n_samples"] and np.all(ins["bucket_off"][1:] == st["n_samples"])
+    rays = np.arange(R)
+    robust = check_intervals_and_sort(scene, o, d, cfg.s_max, ins, rays)
+    e = compare_render(scene, out, o, d, cfg.s_max, rays, robust)
+    print("root only: %d intervals, %d samples, max err rgb/opacity/depth %s" % (
+        st["n_intervals"], st["n_samples"], e), flush=True)
+
+
+def test_hcheck_tiny_footprint_is_the_leaf_render():
+    """A footprint so small that no node stops the descent: the intervals are the leaf
+    intervals keyed by the leaves' node slots with the plain sample counts, so the render with
+    node MLPs equals, bit for bit, the plain render whose leaf MLPs are those leaves' node
+    MLPs."""
+    scene = Scene(synth.C1, footprint=1e-30)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = scene.camera_rays()
+    od, dd = to_dev(o), to_dev(d)
+    hs = am.render(ctx, tree, mlp, od, dd, cfg.s_max, ert_eps=cfg.ert_eps, hcheck_footprint=scene.footprint)
+    torch.cuda.synchronize()
+    n_hs = am.amnerf_render_stats_get(ctx.h)["n_samples"]
+    rows = scene.otree.rows
+    leaves = rows[rows[:, 10] >= 0]
+    l2n = np.empty(tree.n_leaves, np.int64)
+    l2n[leaves[:, 10]] = leaves[:, 11]
+    leaf_w = torch.from_numpy(np.ascontiguousarray(scene.W[l2n])).to("cuda:0")
+    leaf_mlp = am.Mlp(ctx, leaf_w, cfg.n_hidden, cfg.hidden, am.AMNERF_F32, tree.n_leaves)
+    plain = am.render(ctx, tree, leaf_mlp, od, dd, cfg.s_max, ert_eps=cfg.ert_eps)
+    torch.cuda.synchronize()
+    assert am.amnerf_render_stats_get(ctx.h)["n_samples"] == n_hs > 0
+    for k in ("rgb", "depth", "opacity"):
+        assert torch.equal(hs[k], plain[k]), k
