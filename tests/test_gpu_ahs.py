@@ -52,6 +52,12 @@ def test_c1_hcheck_full_frame_fp32():
     run_and_check(Scene(synth.C1, footprint=0.5), None, "c1 hcheck")
 
 
+def test_c1_hcheck_on_the_regular_tree_fp32():
+    """Hierarchical sampling over the regular-subdivision tree: its node slots, stopping
+    distances and node MLPs, small frame in full."""
+    run_and_check(Scene(synth.C1, split=1, footprint=0.5), None, "c1 hcheck regular tree")
+
+
 @pytest.mark.parametrize("footprint", [0.1, 0.25])
 def test_c2_hcheck_sampled_fp32(footprint):
     run_and_check(Scene(synth.C2, footprint=footprint),

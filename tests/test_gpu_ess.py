@@ -75,6 +75,15 @@ def test_c1_full_frame_fp32(footprint):
     ess_check(scene, occ_cells, (2, 0.01), o, d, np.arange(o.shape[1]), cfg.s_max, "c1 ess f=%g" % footprint)
 
 
+def test_c1_regular_tree_fp32():
+    """Empty-space skipping under the regular-subdivision tree, small frame in full."""
+    scene = Scene(synth.C1, split=1)
+    cfg = scene.cfg
+    occ_cells = oracle.occupancy(scene.grid, cfg.grid_n, 2, 0.01)
+    o, d = scene.camera_rays()
+    ess_check(scene, occ_cells, (2, 0.01), o, d, np.arange(o.shape[1]), cfg.s_max, "c1 ess regular tree")
+
+
 def test_c3_subset_fp32():
     """200 000 random pixels of the large scene's camera 0 (S_max 192), occupancy at half the
     guidance resolution, 1 % threshold; 1 500 rays compared."""
