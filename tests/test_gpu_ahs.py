@@ -228,3 +228,35 @@ def test_hcheck_tiny_footprint_is_the_leaf_render():
     assert am.amnerf_render_stats_get(ctx.h)["n_samples"] == n_hs > 0
     for k in ("rgb", "depth", "opacity"):
         assert torch.equal(hs[k], plain[k]), k
+
+
+@pytest.mark.parametrize("dtype", [am.AMNERF_BF16, am.AMNERF_FP8])
+def test_c2_hcheck_reduced_precision_error_report(dtype):
+    """Node MLPs packed in bf16 or e4m3 under HCheck (f = 0.25, the 800x800 frame), 1 500 rays,
+    with the plain leaf render's bars: bf16 above 35 dB against the float64 oracle on the
+    float32 node weights; e4m3 above 45 dB against the oracle on the dequantised weights, and
+    within 1 dB of that oracle's own distance to the float32-weight render."""
+    scene = Scene(synth.C2, footprint=0.25)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, dtype)
+    o, d = scene.camera_rays()
+    out = render_all(scene, ctx, tree, mlp, o, d, cfg.s_max)
+    assert am.amnerf_render_stats_get(ctx.h)["n_nonfinite"] == 0
+    rays = np.sort(np.random.default_rng(4).choice(o.shape[1], 1500, replace=False))
+
+    def ref(W):
+        return oracle.render(scene.otree, W, cfg.n_hidden, cfg.hidden, o, d, cfg.s_max, eps=cfg.ert_eps,
+                             ray_idx=rays, footprint=scene.footprint)[0]
+
+    g = out["rgb"].cpu().numpy()[rays]
+    rgb = ref(scene.W)
+    p_full = oracle.psnr(g, rgb)
+    if dtype == am.AMNERF_BF16:
+        print("c2 hcheck bf16: psnr vs oracle %.2f dB, max abs %.3e" % (p_full, np.abs(g - rgb).max()), flush=True)
+        assert p_full > 35.0
+    else:
+        rgb8 = ref(fp8.quantise(scene.W, cfg.n_hidden, cfg.hidden)[2].astype(np.float32))
+        p_q, p_oq = oracle.psnr(g, rgb8), oracle.psnr(rgb8, rgb)
+        print("c2 hcheck e4m3: psnr vs oracle(dequantised) %.2f dB, vs oracle(float32) %.2f dB; oracle "
+              "dequantised vs float32 %.2f dB" % (p_q, p_full, p_oq), flush=True)
+        assert p_q > 45.0 and p_full > p_oq - 1.0
