@@ -196,3 +196,40 @@ def test_backward_after_skipping_is_rejected():
     am.amnerf_render_backward(ctx.h, tree.h, mlp.desc, od, dd, g, grad)
     torch.cuda.synchronize()
     assert torch.count_nonzero(grad) == 0          # zero upstream gradient
+
+
+@pytest.mark.parametrize("dtype", [am.AMNERF_BF16, am.AMNERF_FP8])
+def test_c2_reduced_precision_error_report(dtype):
+    """Leaf MLPs packed in bf16 or e4m3 with empty space skipped (the 800x800 frame, occupancy
+    at half the guidance resolution, 1 % threshold), 1 500 rays against the oracle run with the
+    same grid, with the plain render's bars: bf16 above 35 dB against the float32 weights;
+    e4m3 above 45 dB against the dequantised weights, and within 1 dB of that oracle's own
+    distance to the float32-weight render."""
+    from oracle import fp8
+    scene = Scene(synth.C2)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, dtype)
+    occ_cells = oracle.occupancy(scene.grid, cfg.grid_n, 2, 0.01)
+    o, d = scene.camera_rays()
+    out = am.render(ctx, tree, mlp, to_dev(o), to_dev(d), cfg.s_max, ert_eps=cfg.ert_eps,
+                    occupancy=am.Occupancy(ctx, scene.grid, cfg.grid_n, 2, 0.01))
+    torch.cuda.synchronize()
+    assert am.amnerf_render_stats_get(ctx.h)["n_nonfinite"] == 0
+    rays = np.sort(np.random.default_rng(5).choice(o.shape[1], 1500, replace=False))
+
+    def ref(W):
+        return oracle.render(scene.otree, W, cfg.n_hidden, cfg.hidden, o, d, cfg.s_max, eps=cfg.ert_eps,
+                             ray_idx=rays, occupancy=occ_cells)[0]
+
+    g = out["rgb"].cpu().numpy()[rays]
+    rgb = ref(scene.W)
+    p_full = oracle.psnr(g, rgb)
+    if dtype == am.AMNERF_BF16:
+        print("c2 ess bf16: psnr vs oracle %.2f dB, max abs %.3e" % (p_full, np.abs(g - rgb).max()), flush=True)
+        assert p_full > 35.0
+    else:
+        rgb8 = ref(fp8.quantise(scene.W, cfg.n_hidden, cfg.hidden)[2].astype(np.float32))
+        p_q, p_oq = oracle.psnr(g, rgb8), oracle.psnr(rgb8, rgb)
+        print("c2 ess e4m3: psnr vs oracle(dequantised) %.2f dB, vs oracle(float32) %.2f dB; oracle "
+              "dequantised vs float32 %.2f dB" % (p_q, p_full, p_oq), flush=True)
+        assert p_q > 45.0 and p_full > p_oq - 1.0
