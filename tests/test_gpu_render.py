@@ -348,3 +348,37 @@ def test_multi_chunk_call_equals_chunk_by_chunk_calls():
         for k in ("rgb", "depth", "opacity"):
             assert torch.equal(whole[k][r0:r0 + chunk], part[k]), (k, r0)
     assert st["n_samples"] == n_samples
+
+
+@pytest.mark.parametrize("mode", ["hcheck", "ess"])
+def test_multi_chunk_call_with_options_equals_chunk_by_chunk_calls(mode):
+    """The same three-pass call with hierarchical sampling (f = 0.5, node MLPs) or with empty
+    space skipped (occupancy at half the guidance resolution, 1 % threshold): outputs and
+    sample count bit-identical to three calls on the same slices."""
+    scene = Scene(synth.C1, footprint=0.5 if mode == "hcheck" else 0.0)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    if mode == "hcheck":
+        kw = {"hcheck_footprint": scene.footprint}
+    else:
+        kw = {"occupancy": am.Occupancy(ctx, scene.grid, cfg.grid_n, 2, 0.01)}
+    o, d = scene.camera_rays()
+    od = to_dev(o).repeat(1, 640).contiguous()
+    dd = to_dev(d).repeat(1, 640).contiguous()
+    R = od.shape[1]
+    chunk = (1 << 28) // 255
+    assert 2 * chunk < R < 3 * chunk
+    print("multi-chunk %s: rays %d" % (mode, R), flush=True)
+    whole = am.render(ctx, tree, mlp, od, dd, 255, ert_eps=cfg.ert_eps, **kw)
+    torch.cuda.synchronize()
+    st = am.amnerf_render_stats_get(ctx.h)
+    assert st["n_chunks"] == 3 and st["n_nonfinite"] == 0
+    n_samples = 0
+    for r0 in range(0, R, chunk):
+        part = am.render(ctx, tree, mlp, od[:, r0:r0 + chunk].contiguous(), dd[:, r0:r0 + chunk].contiguous(), 255,
+                         ert_eps=cfg.ert_eps, **kw)
+        torch.cuda.synchronize()
+        n_samples += am.amnerf_render_stats_get(ctx.h)["n_samples"]
+        for k in ("rgb", "depth", "opacity"):
+            assert torch.equal(whole[k][r0:r0 + chunk], part[k]), (k, r0)
+    assert st["n_samples"] == n_samples
