@@ -1,0 +1,48 @@
+"""Frames in flight: two library contexts, each on its own stream (default priority), render
+camera frames back to back with no host synchronisation between them; every output is
+bit-identical to the same camera rendered alone.  Plain, with hierarchical sampling and with
+empty space skipped (the tree, the MLP and the occupancy grid are shared, read only)."""
+from __future__ import annotations
+
+import pytest
+
+import synth
+from scene_util import Scene, gpu_setup, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2310_01881_amd as am  # noqa: E402
+
+
+@pytest.mark.parametrize("mode", ["plain", "hcheck", "ess"])
+def test_two_contexts_on_two_streams(mode):
+    scene = Scene(synth.C1, footprint=0.5 if mode == "hcheck" else 0.0)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_BF16)
+    ctx2 = am.Context(0)
+    kw = {}
+    if mode == "hcheck":
+        kw["hcheck_footprint"] = scene.footprint
+    elif mode == "ess":
+        kw["occupancy"] = am.Occupancy(ctx, scene.grid, cfg.grid_n, 2, 0.01)
+    n_cams = 4
+    rays = [tuple(to_dev(a) for a in scene.camera_rays(i)) for i in range(n_cams)]
+    alone = [am.render(ctx, tree, mlp, o, d, cfg.s_max, ert_eps=cfg.ert_eps, **kw) for o, d in rays]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    streams[1].wait_stream(streams[0])
+    ctxs = [ctx, ctx2]
+    frames = []
+    for k in range(4 * n_cams):
+        q = k % 2
+        o, d = rays[k % n_cams]
+        frames.append(am.render(ctxs[q], tree, mlp, o, d, cfg.s_max, ert_eps=cfg.ert_eps, stream=streams[q], **kw))
+    torch.cuda.synchronize()
+    for k, out in enumerate(frames):
+        for name in ("rgb", "depth", "opacity"):
+            assert torch.equal(out[name], alone[k % n_cams][name]), (mode, k, name)
+    print("%s: %d frames on two streams bit-identical to the frames alone" % (mode, len(frames)), flush=True)
