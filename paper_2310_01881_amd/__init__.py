@@ -485,7 +485,7 @@ class Mlp:
 
 
 def render(ctx: Context, tree: Tree, mlp: Mlp, o_dev, d_dev, s_max, ert_eps=1e-4, jitter=False, seed=0,
-           weights=False, stream=None, hcheck_footprint=0.0, occupancy=None):
+           weights=False, stream=None, hcheck_footprint=0.0, occupancy=None, proposal=None):
     """Allocates the outputs and renders; returns dict of device tensors."""
     import torch
     R = int(o_dev.shape[1])
@@ -496,8 +496,8 @@ def render(ctx: Context, tree: Tree, mlp: Mlp, o_dev, d_dev, s_max, ert_eps=1e-4
     if weights:
         out["weights"] = torch.zeros(R * s_max, dtype=torch.float32, device=dev)
     amnerf_render(ctx.h, tree.h, mlp.desc, o_dev, d_dev, s_max, out["rgb"], out["depth"], out["opacity"],
-                  out.get("weights"), ert_eps, jitter, seed, stream, hcheck_footprint=hcheck_footprint,
-                  occupancy=occupancy)
+                  out.get("weights"), ert_eps, jitter, seed, stream, proposal=proposal,
+                  hcheck_footprint=hcheck_footprint, occupancy=occupancy)
     return out
 
 

@@ -1,7 +1,8 @@
 """Frames in flight: two library contexts, each on its own stream (default priority), render
 camera frames back to back with no host synchronisation between them; every output is
-bit-identical to the same camera rendered alone.  Plain, with hierarchical sampling and with
-empty space skipped (the tree, the MLP and the occupancy grid are shared, read only)."""
+bit-identical to the same camera rendered alone.  Plain, with hierarchical sampling, with
+empty space skipped and with a (untrained) proposal (the tree, the MLP, the occupancy grid and
+the proposal are shared, read only)."""
 from __future__ import annotations
 
 import pytest
@@ -18,7 +19,7 @@ if not torch.cuda.is_available():
 import paper_2310_01881_amd as am  # noqa: E402
 
 
-@pytest.mark.parametrize("mode", ["plain", "hcheck", "ess"])
+@pytest.mark.parametrize("mode", ["plain", "hcheck", "ess", "proposal"])
 def test_two_contexts_on_two_streams(mode):
     scene = Scene(synth.C1, footprint=0.5 if mode == "hcheck" else 0.0)
     cfg = scene.cfg
@@ -29,6 +30,9 @@ def test_two_contexts_on_two_streams(mode):
         kw["hcheck_footprint"] = scene.footprint
     elif mode == "ess":
         kw["occupancy"] = am.Occupancy(ctx, scene.grid, cfg.grid_n, 2, 0.01)
+    elif mode == "proposal":
+        prop = am.Proposal(ctx, torch.from_numpy(synth.make_prop_weights(1)).to("cuda:0"))
+        kw["proposal"] = prop.descriptor(am.AMNERF_BF16, 0.99, 48)
     n_cams = 4
     rays = [tuple(to_dev(a) for a in scene.camera_rays(i)) for i in range(n_cams)]
     alone = [am.render(ctx, tree, mlp, o, d, cfg.s_max, ert_eps=cfg.ert_eps, **kw) for o, d in rays]
