@@ -1,5 +1,6 @@
 """The regular-subdivision tree of the ablation without the adaptive split on the GPU: the
-library's tree bit-exact against the oracle's, and renders through it against the oracle."""
+library's tree bit-exact against the oracle's, and renders through it (float32 and bf16 leaf
+MLPs) against the oracle."""
 from __future__ import annotations
 
 import numpy as np
@@ -50,6 +51,26 @@ def test_c2_middle_split_sampled_fp32():
     robust = check_intervals_and_sort(scene, o, d, scene.cfg.s_max, ins, rays)
     e = compare_render(scene, out, o, d, scene.cfg.s_max, rays, robust)
     print("c2 middle split max err rgb/opacity/depth", e, flush=True)
+
+
+def test_c2_middle_split_bf16_error_report():
+    """The path the ablation times (bf16 leaf MLPs on the regular tree): 1 500 rays of the
+    800x800 frame against the float64 oracle on the float32 weights, with the plain adaptive
+    render's 35 dB bar."""
+    import oracle
+    scene = Scene(synth.C2, split=am.AMNERF_SPLIT_MIDDLE)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_BF16)
+    o, d = scene.camera_rays()
+    out = render_all(scene, ctx, tree, mlp, o, d, cfg.s_max)
+    assert am.amnerf_render_stats_get(ctx.h)["n_nonfinite"] == 0
+    rays = np.sort(np.random.default_rng(13).choice(o.shape[1], 1500, replace=False))
+    rgb = oracle.render(scene.otree, scene.W, cfg.n_hidden, cfg.hidden, o, d, cfg.s_max, eps=cfg.ert_eps,
+                        ray_idx=rays)[0]
+    g = out["rgb"].cpu().numpy()[rays]
+    psnr = oracle.psnr(g, rgb)
+    print("c2 middle split bf16: psnr vs oracle %.2f dB, max abs %.3e" % (psnr, np.abs(g - rgb).max()), flush=True)
+    assert psnr > 35.0
 
 
 def test_split_mode_is_validated():
