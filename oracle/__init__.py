@@ -77,6 +77,10 @@ def lib():
         _lib.orc_prop_loss_grad.argtypes = [P, P, P, i64, P]
         _lib.orc_prop_loss_grad.restype = dbl
         _lib.orc_prop_param_count.restype = i32
+        _lib.orc_composite.argtypes = [i32, P, P, P, dbl, P, P]
+        _lib.orc_composite.restype = i32
+        _lib.orc_composite_grad.argtypes = [i32, P, P, P, dbl, P, P]
+        _lib.orc_composite_grad.restype = i32
     return _lib
 
 
@@ -243,6 +247,32 @@ def render_grad(tree: Tree, params, n_hidden, hidden, o, d, s_max, g_rgb, g_dept
     if rc != 0:
         raise ValueError("orc_render_grad failed")
     return grad
+
+
+def composite(z, t, delta, eps=1e-4):
+    """One ray's quadrature from its samples' output pre-activations z[ns][4]
+    (sigma^, r^, g^, b^), positions t[ns] and segment lengths delta[ns]:
+    ((rgb[3], depth, opacity), weights[ns], samples composited)."""
+    z = _c(z, np.float64).reshape(-1, 4)
+    ns = len(z)
+    t = _c(t, np.float64); delta = _c(delta, np.float64)
+    assert t.shape == (ns,) and delta.shape == (ns,)
+    out = np.zeros(5); w = np.zeros(max(ns, 1))
+    used = lib().orc_composite(ns, _p(z), _p(t), _p(delta), float(eps), _p(out), _p(w))
+    return out, w[:ns], int(used)
+
+
+def composite_grad(z, t, delta, g, eps=1e-4):
+    """dL/dz[ns][4] for L = g . (rgb[3], depth, opacity) of composite(); (dz, samples
+    composited)."""
+    z = _c(z, np.float64).reshape(-1, 4)
+    ns = len(z)
+    t = _c(t, np.float64); delta = _c(delta, np.float64)
+    g = _c(g, np.float64)
+    assert g.shape == (5,)
+    dz = np.zeros((max(ns, 1), 4))
+    J = lib().orc_composite_grad(ns, _p(z), _p(t), _p(delta), float(eps), _p(g), _p(dz))
+    return dz[:ns], int(J)
 
 
 def adam(p, m, v, g, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

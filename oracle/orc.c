@@ -660,7 +660,12 @@ static void render_ray(const octx* C, int64_t r, oiv* ivbuf, osample* sbuf, oray
       if (Tn < C->eps) { res->flags |= FLAG_ERT_FIRED; break; }
     }
   }
-  if (s_w) for (int j = used; j < ns; ++j) s_w[j] = 0.0;
+  /* samples after the stop are not evaluated: record them as zero */
+  for (int j = used; j < ns; ++j) {
+    if (s_w) s_w[j] = 0.0;
+    if (s_sigma) s_sigma[j] = 0.0;
+    if (s_rgb) for (int c = 0; c < 3; ++c) s_rgb[3 * j + c] = 0.0;
+  }
   res->n_used = used;
 }
 
@@ -854,6 +859,80 @@ int orc_render_grad(const int32_t* rows, int nn, int grid_n, const float* params
   free(ivbuf); free(sbuf); free(acts); free(outs); free(Tj); free(wj); free(P);
   otree_free(&T);
   return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Compositing of one ray from its samples' MLP outputs, and its gradient      */
+/* ------------------------------------------------------------------------- */
+/* The quadrature of Section 3.1 (the NeRF volume-rendering sum) over one ray, given per
+   sample the output pre-activations z = (sigma^, r^, g^, b^), the position t and the
+   segment length delta: sigma = softplus(sigma^), c = logistic(r^, g^, b^),
+   tau_j = sigma_j delta_j, T_j = exp(-sum_{i<j} tau_i), w_j = T_j (1 - exp(-tau_j));
+   rgb = sum w_j c_j, depth = sum w_j t_j, opacity = sum w_j, stopping after the first j
+   with T_{j+1} < eps (Section 4.1 early termination; eps = 0: never).
+   out[5] = (rgb, depth, opacity); w (optional) receives every sample's weight (0 after
+   the stop).  Returns the number of samples composited (stop index + 1, or ns). */
+int orc_composite(int ns, const double* z, const double* t, const double* delta, double eps, double* out,
+                  double* w) {
+  double S = 0.0;
+  int used = 0;
+  for (int c = 0; c < 5; ++c) out[c] = 0.0;
+  if (w) for (int j = 0; j < ns; ++j) w[j] = 0.0;
+  for (int j = 0; j < ns; ++j) {
+    double sigma = softplus(z[4 * j]);
+    double tau = sigma * delta[j];
+    double wj = exp(-S) * (-expm1(-tau));
+    for (int c = 0; c < 3; ++c) out[c] += wj * sigmoid(z[4 * j + 1 + c]);
+    out[3] += wj * t[j];
+    out[4] += wj;
+    if (w) w[j] = wj;
+    S += tau;
+    used = j + 1;
+    if (eps > 0.0 && exp(-S) < eps) break;
+  }
+  return used;
+}
+
+/* Gradient of L = g . (rgb, depth, opacity) of orc_composite with respect to every z:
+   dz[ns][4].  With J samples composited, for j < J
+     dL/dc_j = g_rgb w_j,
+     dL/dtau_j = sum_c g_c (T_{j+1} c_j - sum_{J > i > j} w_i c_i)
+               + g_depth (T_{j+1} t_j - sum_{J > i > j} w_i t_i) + g_opac (T_{j+1} - sum_{J > i > j} w_i)
+   (moving tau_j scales the transmittance of every later sample by e^{-d tau_j} and the
+   weight of sample j by its derivative), then dsigma^ = dtau delta logistic(sigma^) and
+   dc^ = dc c (1 - c).  The stop index is held fixed (the loss is the truncated sum).
+   Samples at or after J get 0.  Returns J. */
+int orc_composite_grad(int ns, const double* z, const double* t, const double* delta, double eps,
+                       const double g[5], double* dz) {
+  double* w = (double*)malloc(sizeof(double) * (ns > 0 ? ns : 1));
+  double* Tn = (double*)malloc(sizeof(double) * (ns > 0 ? ns : 1));
+  double out[5];
+  int J = orc_composite(ns, z, t, delta, eps, out, w);
+  double S = 0.0;
+  for (int j = 0; j < J; ++j) {
+    S += softplus(z[4 * j]) * delta[j];
+    Tn[j] = exp(-S);
+  }
+  /* suffix sums over i > j of w_i c_i, w_i t_i, w_i */
+  double suf[5] = {0, 0, 0, 0, 0};
+  for (int j = ns - 1; j >= 0; --j) {
+    double* d = dz + 4 * j;
+    if (j >= J) { d[0] = d[1] = d[2] = d[3] = 0.0; continue; }
+    double c[3];
+    for (int k = 0; k < 3; ++k) c[k] = sigmoid(z[4 * j + 1 + k]);
+    double dtau = 0.0;
+    for (int k = 0; k < 3; ++k) dtau += g[k] * (Tn[j] * c[k] - suf[k]);
+    dtau += g[3] * (Tn[j] * t[j] - suf[3]);
+    dtau += g[4] * (Tn[j] - suf[4]);
+    d[0] = dtau * delta[j] * sigmoid(z[4 * j]);
+    for (int k = 0; k < 3; ++k) d[1 + k] = g[k] * w[j] * c[k] * (1.0 - c[k]);
+    for (int k = 0; k < 3; ++k) suf[k] += w[j] * c[k];
+    suf[3] += w[j] * t[j];
+    suf[4] += w[j];
+  }
+  free(w);
+  free(Tn);
+  return J;
 }
 
 /* ------------------------------------------------------------------------- */
