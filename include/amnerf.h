@@ -296,6 +296,12 @@ typedef struct {
   int64_t n_nonfinite;    /* rays whose rgb, depth or opacity is not finite */
   int64_t n_fallback;     /* rays rendered with every plain slot under a proposal */
   int64_t n_plain_samples;/* samples the plain sampler would have taken */
+  int64_t n_unreached;    /* interval entries the traversal's emission pass did not reach and
+                             filled with zero-length entries (0 unless its two passes disagree;
+                             such entries add samples of zero weight to leaf 0's bucket) */
+  int64_t n_composited;   /* samples composited before early termination (the stop sample
+                             included); n_samples - n_composited were evaluated by the MLPs
+                             but lie past the termination point */
 } amnerf_render_stats;
 
 /* Waits for the last render's stream and reports its totals. */
@@ -317,7 +323,9 @@ int amnerf_render_stats_get(amnerf_ctx* ctx, amnerf_render_stats* out);
  *                                      position (the stable sort of samples by slot)
  *   sample_out   float32[n_samples][4] MLP output pre-activations (sigma^, r^, g^, b^) in
  *                                      ray-major order: sigma = softplus(sigma^),
- *                                      rgb = logistic(r^, g^, b^) */
+ *                                      rgb = logistic(r^, g^, b^)
+ *   ray_used     uint32[n_rays]        samples of each ray composited before early
+ *                                      termination (the stop sample included) */
 typedef struct {
   uint32_t* ray_iv_off;
   uint32_t* ray_smp_off;
@@ -328,6 +336,7 @@ typedef struct {
   uint32_t* bucket_off;
   uint32_t* perm;
   float* sample_out;
+  uint32_t* ray_used;
 } amnerf_inspect;
 
 int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* out, void* stream);
@@ -355,22 +364,29 @@ int amnerf_timing_collect(amnerf_ctx* ctx, double* stage_ms_host, int64_t* n_pas
 
 /* Gradient of a scalar loss L with respect to every leaf parameter, given dL/d(outputs) of
  * the rays of the most recent amnerf_render on this context.  That render must have used
- * the same tree, MLP (dtype AMNERF_BF16), rays and params and run as a single chunk; its
- * intermediate arrays are reused, and per-sample activations are recomputed (none are kept
- * from the forward pass).  Backward through the quadrature: dL/dc_j = w_j g,
- * dL/dtau_j = T_{j+1} c_j g - g . sum_{i>j} w_i c_i (likewise for depth with t_j and for
- * opacity with 1), zero after the early-termination sample; then softplus' = logistic,
- * logistic' = c (1 - c), and the chain rule through the ReLU MLP (bfloat16 operands,
- * float32 accumulation).
+ * the same tree, MLP (dtype AMNERF_BF16 or AMNERF_F32), rays and params and run as a single
+ * chunk (else AMNERF_ESTATE); its intermediate arrays are reused, and per-sample
+ * activations are recomputed (none are kept from the forward pass).  Backward through the
+ * quadrature: dL/dc_j = w_j g, dL/dtau_j = T_{j+1} c_j g - g . sum_{i>j} w_i c_i (likewise
+ * for depth with t_j and for opacity with 1), zero after the early-termination sample,
+ * which is the one the forward pass stopped at (recorded per ray by the render, never
+ * decided again); then softplus' = logistic, logistic' = c (1 - c), and the chain rule
+ * through the ReLU MLP (operands in the MLP's dtype, float32 accumulation).
  *   g_rgb_dev     device float32[n_rays][3]
  *   g_depth_dev   device float32[n_rays] or NULL (zero)
  *   g_opacity_dev device float32[n_rays] or NULL (zero)
  *   grad_dev      device float32[n_leaves][P], overwritten (master parameter layout)
- * Supported shapes: n_hidden 2 or 4, hidden 32 or 64. */
+ * Supported shapes: n_hidden 1 .. 4, hidden 32 or 64. */
 int amnerf_render_backward(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
                            const amnerf_rays* rays, const float* g_rgb_dev,
                            const float* g_depth_dev, const float* g_opacity_dev,
                            float* grad_dev, void* stream);
+
+/* Copies the per-sample gradient of the last amnerf_render_backward with respect to the
+ * MLP output pre-activations, dL/d(sigma^, r^, g^, b^), into the caller's device
+ * float32[n_samples][4] (ray-major sample order, as amnerf_render_inspect's sample_out), on
+ * `stream`.  AMNERF_ESTATE if no backward pass of the last render is available. */
+int amnerf_render_backward_inspect(amnerf_ctx* ctx, float* sample_grad_dev, void* stream);
 
 typedef struct {
   float lr, beta1, beta2, eps;  /* Adam (Kingma & Ba) with bias correction */

@@ -43,7 +43,7 @@ EXPORTS = [
     "amnerf_render_stats_get", "amnerf_render_inspect", "amnerf_ctx_set_timing",
     "amnerf_timing_collect", "amnerf_render_backward", "amnerf_adam_step", "amnerf_train_step",
     "amnerf_prop_param_count", "amnerf_prop_packed_bytes", "amnerf_prop_pack", "amnerf_propose",
-    "amnerf_error_stats",
+    "amnerf_error_stats", "amnerf_render_backward_inspect",
 ]
 AMNERF_PROPOSE_INFER = 0
 AMNERF_PROPOSE_TRAIN = 1
@@ -97,13 +97,15 @@ class amnerf_render_out(C.Structure):
 class amnerf_render_stats(C.Structure):
     _fields_ = [("n_rays", C.c_int64), ("n_intervals", C.c_int64), ("n_samples", C.c_int64),
                 ("n_tiles", C.c_int64), ("n_chunks", C.c_int64), ("n_nonfinite", C.c_int64),
-                ("n_fallback", C.c_int64), ("n_plain_samples", C.c_int64)]
+                ("n_fallback", C.c_int64), ("n_plain_samples", C.c_int64), ("n_unreached", C.c_int64),
+                ("n_composited", C.c_int64)]
 
 
 class amnerf_inspect(C.Structure):
     _fields_ = [("ray_iv_off", C.c_void_p), ("ray_smp_off", C.c_void_p), ("iv_t0", C.c_void_p),
                 ("iv_dt", C.c_void_p), ("iv_slot", C.c_void_p), ("iv_n", C.c_void_p),
-                ("bucket_off", C.c_void_p), ("perm", C.c_void_p), ("sample_out", C.c_void_p)]
+                ("bucket_off", C.c_void_p), ("perm", C.c_void_p), ("sample_out", C.c_void_p),
+                ("ray_used", C.c_void_p)]
 
 
 class amnerf_adam_params(C.Structure):
@@ -162,6 +164,7 @@ def _load():
     lib.amnerf_ctx_set_timing.argtypes = [P, C.c_int]
     lib.amnerf_timing_collect.argtypes = [P, P, C.POINTER(C.c_int64)]
     lib.amnerf_render_backward.argtypes = [P, P, C.POINTER(amnerf_mlp), C.POINTER(amnerf_rays), P, P, P, P, P]
+    lib.amnerf_render_backward_inspect.argtypes = [P, P, P]
     lib.amnerf_adam_step.argtypes = [P, C.c_int64, P, P, P, P, C.POINTER(amnerf_adam_params), P]
     lib.amnerf_error_stats.argtypes = [P, P, P, P, C.c_int64, C.POINTER(C.c_double * 4), P]
     lib.amnerf_train_step.argtypes = [P, P, C.POINTER(amnerf_mlp_train), C.POINTER(amnerf_rays), P,
@@ -335,6 +338,10 @@ def amnerf_render_backward(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, g_rgb_dev, 
                                        _stream(stream)))
 
 
+def amnerf_render_backward_inspect(ctx, sample_grad_dev, stream=None):
+    _check(_lib.amnerf_render_backward_inspect(ctx, _ptr(sample_grad_dev), _stream(stream)))
+
+
 def amnerf_adam_step(ctx, param_dev, m_dev, v_dev, grad_dev, step, lr=1e-3, beta1=0.9, beta2=0.999,
                      eps=1e-8, stream=None):
     prm = amnerf_adam_params(lr, beta1, beta2, eps, step)
@@ -486,18 +493,32 @@ class Mlp:
 
 def render(ctx: Context, tree: Tree, mlp: Mlp, o_dev, d_dev, s_max, ert_eps=1e-4, jitter=False, seed=0,
            weights=False, stream=None, hcheck_footprint=0.0, occupancy=None, proposal=None):
-    """Allocates the outputs and renders; returns dict of device tensors."""
+    """Allocates the outputs and renders on `stream` (default: the current stream); returns
+    dict of device tensors.  The outputs are allocated and cleared on `stream` itself, which
+    first waits for the current stream (where the inputs were produced), and they are
+    recorded as used by it, so the caching allocator never hands their memory to other work
+    while the render may still write them."""
     import torch
     R = int(o_dev.shape[1])
     dev = o_dev.device
-    out = {"rgb": torch.empty((R, 3), dtype=torch.float32, device=dev),
-           "depth": torch.empty(R, dtype=torch.float32, device=dev),
-           "opacity": torch.empty(R, dtype=torch.float32, device=dev)}
-    if weights:
-        out["weights"] = torch.zeros(R * s_max, dtype=torch.float32, device=dev)
+    cur = torch.cuda.current_stream(dev)
+    st = cur if stream is None else stream
+    if st != cur:
+        st.wait_stream(cur)
+    with torch.cuda.stream(st):
+        out = {"rgb": torch.empty((R, 3), dtype=torch.float32, device=dev),
+               "depth": torch.empty(R, dtype=torch.float32, device=dev),
+               "opacity": torch.empty(R, dtype=torch.float32, device=dev)}
+        if weights:
+            out["weights"] = torch.zeros(R * s_max, dtype=torch.float32, device=dev)
     amnerf_render(ctx.h, tree.h, mlp.desc, o_dev, d_dev, s_max, out["rgb"], out["depth"], out["opacity"],
-                  out.get("weights"), ert_eps, jitter, seed, stream, proposal=proposal,
+                  out.get("weights"), ert_eps, jitter, seed, st, proposal=proposal,
                   hcheck_footprint=hcheck_footprint, occupancy=occupancy)
+    if st != cur:
+        for t in out.values():
+            t.record_stream(st)
+        for t in (o_dev, d_dev):
+            t.record_stream(st)
     return out
 
 
@@ -534,35 +555,47 @@ def _render_fn():
     import torch
 
     class RenderFn(torch.autograd.Function):
-        """rgb, depth, opacity = RenderFn.apply(master, ctx, tree, o, d, s_max, ert_eps, n_hidden, hidden).
+        """rgb, depth, opacity = RenderFn.apply(master, ctx, tree, o, d, s_max, ert_eps, n_hidden, hidden
+        [, dtype]).
 
-        Forward packs the float32 master parameters to bfloat16 and renders; backward
-        returns dL/dmaster from the library's hand-written backward pass."""
+        Forward packs the float32 master parameters (to bfloat16 by default, or float32 with
+        dtype=AMNERF_F32) and renders; backward returns dL/dmaster from the library's
+        hand-written backward pass.  The library differentiates the last render of its
+        context; if another render ran on the context in between, backward renders the same
+        inputs again first (the per-sample activations are recomputed anyway)."""
 
         @staticmethod
-        def forward(fctx, master, ctx, tree, o_dev, d_dev, s_max, ert_eps, n_hidden, hidden):
+        def forward(fctx, master, ctx, tree, o_dev, d_dev, s_max, ert_eps, n_hidden, hidden, dtype=AMNERF_BF16):
             L = tree.n_leaves
-            nbytes = amnerf_mlp_packed_bytes(n_hidden, hidden, AMNERF_BF16, L)
+            nbytes = amnerf_mlp_packed_bytes(n_hidden, hidden, dtype, L)
             packed = torch.empty(nbytes, dtype=torch.uint8, device=master.device)
             master_c = master.detach().contiguous()
-            amnerf_mlp_pack(ctx.h, n_hidden, hidden, AMNERF_BF16, L, master_c, packed)
-            desc = amnerf_mlp(amnerf_mlp_shape(n_hidden, hidden), AMNERF_BF16, L, C.c_void_p(packed.data_ptr()))
+            amnerf_mlp_pack(ctx.h, n_hidden, hidden, dtype, L, master_c, packed)
+            desc = amnerf_mlp(amnerf_mlp_shape(n_hidden, hidden), dtype, L, C.c_void_p(packed.data_ptr()))
             R = int(o_dev.shape[1])
             rgb = torch.empty((R, 3), dtype=torch.float32, device=master.device)
             depth = torch.empty(R, dtype=torch.float32, device=master.device)
             opac = torch.empty(R, dtype=torch.float32, device=master.device)
             amnerf_render(ctx.h, tree.h, desc, o_dev, d_dev, s_max, rgb, depth, opac, None, ert_eps)
-            fctx.keep = (ctx, tree, desc, packed, o_dev, d_dev, master_c)
+            fctx.keep = (ctx, tree, desc, packed, o_dev, d_dev, master_c, s_max, ert_eps)
             return rgb, depth, opac
 
         @staticmethod
         def backward(fctx, g_rgb, g_depth, g_opac):
-            ctx, tree, desc, packed, o_dev, d_dev, master_c = fctx.keep
+            ctx, tree, desc, packed, o_dev, d_dev, master_c, s_max, ert_eps = fctx.keep
             grad = torch.empty_like(master_c)
-            amnerf_render_backward(ctx.h, tree.h, desc, o_dev, d_dev, g_rgb.contiguous(), grad,
-                                   None if g_depth is None else g_depth.contiguous(),
-                                   None if g_opac is None else g_opac.contiguous())
-            return grad, None, None, None, None, None, None, None, None
+            args = (g_rgb.contiguous(), grad, None if g_depth is None else g_depth.contiguous(),
+                    None if g_opac is None else g_opac.contiguous())
+            try:
+                amnerf_render_backward(ctx.h, tree.h, desc, o_dev, d_dev, *args)
+            except AmnerfError as e:
+                if e.code != AMNERF_ESTATE:
+                    raise
+                R = int(o_dev.shape[1])
+                scratch = torch.empty((R, 3), dtype=torch.float32, device=master_c.device)
+                amnerf_render(ctx.h, tree.h, desc, o_dev, d_dev, s_max, scratch, None, None, None, ert_eps)
+                amnerf_render_backward(ctx.h, tree.h, desc, o_dev, d_dev, *args)
+            return grad, None, None, None, None, None, None, None, None, None
 
     return RenderFn
 

@@ -78,6 +78,11 @@ struct amnerf_ctx {
   IvSet use = {};
   uint32_t *bucket_off = nullptr, *perm = nullptr, *tile_off = nullptr, *srec_ray = nullptr;
   float *smp_out = nullptr, *srec_t = nullptr;
+  uint32_t* ray_used = nullptr;   // samples composited per ray (the early-termination count)
+  bool last_uses_arena3 = false;  // the last render's intervals live in the third arena
+  // last backward: per-sample pre-activation gradients (second arena), for inspection
+  bool have_backward = false;
+  const float* last_gpre = nullptr;
   // third arena: proposal stage buffers, sized from the measured interval count
   void* arena3 = nullptr;
   size_t arena3_bytes = 0;
@@ -234,6 +239,7 @@ static int ensure_arena2(amnerf_ctx* ctx, size_t bytes) {
   if (ctx->cap && bytes + ctx->arena_bytes > ctx->cap)
     return fail(AMNERF_ENOMEM, "workspace needs %zu more bytes, cap is %zu", bytes, ctx->cap);
   HIP_TRY(hipDeviceSynchronize());
+  ctx->have_backward = false;
   if (ctx->arena2) HIP_TRY(hipFree(ctx->arena2));
   ctx->arena2 = nullptr;
   ctx->arena2_bytes = 0;
@@ -248,6 +254,7 @@ static int ensure_arena3(amnerf_ctx* ctx, size_t bytes) {
   if (ctx->cap && bytes + ctx->arena_bytes + ctx->arena2_bytes > ctx->cap)
     return fail(AMNERF_ENOMEM, "workspace needs %zu more bytes, cap is %zu", bytes, ctx->cap);
   HIP_TRY(hipDeviceSynchronize());
+  if (ctx->last_uses_arena3) ctx->have_render = false;
   if (ctx->arena3) HIP_TRY(hipFree(ctx->arena3));
   ctx->arena3 = nullptr;
   ctx->arena3_bytes = 0;
@@ -266,6 +273,7 @@ static int grow_lane_buffer(amnerf_ctx* ctx, void** buf, size_t* have, size_t by
   if (ctx->cap && bytes + others > ctx->cap)
     return fail(AMNERF_ENOMEM, "workspace needs %zu more bytes, cap is %zu", bytes, ctx->cap);
   HIP_TRY(hipDeviceSynchronize());
+  ctx->have_render = false;   // a lane buffer may hold the last render's arrays
   if (*buf) HIP_TRY(hipFree(*buf));
   *buf = nullptr;
   *have = 0;
@@ -741,6 +749,7 @@ struct Work {
   uint32_t *mat, *mat_scan, *sidx, *sn, *ssb, *bucket_off, *tile_off;
   uint32_t *srec_ray, *perm;
   float *srec_t, *smp_out;
+  uint32_t* ray_used;
 };
 
 size_t carve(char* base, uint64_t nr, uint64_t niv, uint64_t ns, const SortPlan& sp, Work& w) {
@@ -767,6 +776,7 @@ size_t carve(char* base, uint64_t nr, uint64_t niv, uint64_t ns, const SortPlan&
   w.srec_t = c.take<float>(ns);
   w.perm = c.take<uint32_t>(ns);
   w.smp_out = c.take<float>(4 * ns);
+  w.ray_used = c.take<uint32_t>(nr);
   return c.off + 256;
 }
 
@@ -857,6 +867,10 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   hipStream_t st = (hipStream_t)stream;
   const int64_t R = rays->n_rays;
   const uint32_t L = (uint32_t)n_sets;
+  // the workspaces are about to be overwritten: the previous render can no longer be
+  // inspected or differentiated, whether or not this one completes
+  ctx->have_render = false;
+  ctx->have_backward = false;
   const int jitter = (p->flags & AMNERF_JITTER) ? 1 : 0;
   // a ray has at most one interval per leaf, and hierarchical sampling only merges them
   const uint64_t iv_per_ray = std::min<uint64_t>((uint64_t)p->s_max, (uint64_t)tree->n_leaves);
@@ -908,7 +922,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
     HIP_TRY(launch_trav_count(tree->dev_nodes, ahs_tab, p->hcheck_footprint, (uint32_t)n_nodes, tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, p->s_max, w.cnt_iv, w.cnt_smp, cs));
     HIP_TRY(launch_scan_u32_pair(w.cnt_iv, w.iv_off, w.cnt_smp, w.smp_off, nr, w.scan_tmp, cs));
     HIP_TRY(launch_trav_emit(tree->dev_nodes, ahs_tab, p->hcheck_footprint, (uint32_t)n_nodes, tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
-                             w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, cs));
+                             w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, cc, cs));
     HIP_TRY(mark(1));
     const IvSet plain = {w.iv_off, w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, w.iv_off + nr};
     use = plain;
@@ -974,7 +988,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
                        rays->o_dev, rays->d_dev, R, r0, w.smp_out, cs));
     HIP_TRY(mark(5));
     HIP_TRY(launch_composite(nr, use, w.smp_out, r0, jitter, p->jitter_seed, p->ert_eps, out->rgb_dev, out->depth_dev,
-                             out->opacity_dev, out->weights_dev, cc, cs));
+                             out->opacity_dev, out->weights_dev, w.ray_used, cc, cs));
     HIP_TRY(mark(6));
     if (ev) ev->pending = true;
     HIP_TRY(launch_chunk_finish(cc, use.smp_off + nr, use.n_iv_dev, w.smp_off + nr, cs));
@@ -998,6 +1012,8 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   ctx->tile_off = wl->tile_off;
   ctx->srec_ray = wl->srec_ray;
   ctx->srec_t = wl->srec_t;
+  ctx->ray_used = wl->ray_used;
+  ctx->last_uses_arena3 = p->proposal != nullptr || occ != nullptr;
   ctx->last_tree = tree;
   ctx->last_packed = mlp->packed_dev;
   ctx->last_dtype = mlp->dtype;
@@ -1030,6 +1046,8 @@ extern "C" int amnerf_render_stats_get(amnerf_ctx* ctx, amnerf_render_stats* out
   out->n_nonfinite = (int64_t)c.nonfinite;
   out->n_fallback = (int64_t)c.fallback;
   out->n_plain_samples = (int64_t)c.plain_smp;
+  out->n_unreached = (int64_t)c.unreached;
+  out->n_composited = (int64_t)c.composited;
   return AMNERF_OK;
 }
 
@@ -1054,6 +1072,7 @@ extern "C" int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* o, v
   HIP_TRY(cp(o->bucket_off, ctx->bucket_off, 4 * (L + 1)));
   HIP_TRY(cp(o->perm, ctx->perm, 4 * ns));
   HIP_TRY(cp(o->sample_out, ctx->smp_out, 16 * ns));
+  HIP_TRY(cp(o->ray_used, ctx->ray_used, 4 * nr));
   if (o->iv_slot || o->iv_n) {
     // split the packed keys on the host (inspection only)
     std::vector<uint32_t> keys(niv);
@@ -1101,9 +1120,11 @@ int backward_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* ml
   MlpGeom g;
   int rc = check_geom(&mlp->shape, mlp->dtype, &g, "amnerf_render_backward");
   if (rc) return rc;
-  if (mlp->dtype != AMNERF_BF16) return fail(AMNERF_EINVAL, "amnerf_render_backward: the backward pass runs in bfloat16");
+  if (mlp->dtype != AMNERF_BF16 && mlp->dtype != AMNERF_F32)
+    return fail(AMNERF_EINVAL, "amnerf_render_backward: the backward pass runs in bfloat16 or float32 (dtype %d)",
+                mlp->dtype);
   if (!mlp_bwd_supported(mlp->shape.n_hidden, mlp->shape.hidden))
-    return fail(AMNERF_EINVAL, "amnerf_render_backward: n_hidden must be 2 or 4 (got %d)", mlp->shape.n_hidden);
+    return fail(AMNERF_EINVAL, "amnerf_render_backward: n_hidden must be 1 .. 4 (got %d)", mlp->shape.n_hidden);
   if (!ctx->have_render || ctx->last_tree != tree || ctx->last_packed != mlp->packed_dev ||
       ctx->last_dtype != mlp->dtype || ctx->last_rays != rays->n_rays || ctx->last_o != rays->o_dev)
     return fail(AMNERF_ESTATE, "amnerf_render_backward: the last render on this context used other inputs");
@@ -1129,12 +1150,14 @@ int backward_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* ml
   const amnerf_render_params& p = ctx->last_params;
   const int jitter = (p.flags & AMNERF_JITTER) ? 1 : 0;
   const uint32_t nr = (uint32_t)R;
-  HIP_TRY(launch_comp_bwd(nr, ctx->use, ctx->smp_out, 0, jitter, p.jitter_seed, p.ert_eps, g_rgb, g_depth, g_opac,
-                          w.gpre, st));
+  HIP_TRY(launch_comp_bwd(nr, ctx->use, ctx->smp_out, 0, jitter, p.jitter_seed, ctx->ray_used, g_rgb, g_depth,
+                          g_opac, w.gpre, st));
   HIP_TRY(launch_seg_offsets(ctx->tile_off, (uint32_t)L, w.seg_off, st));
   HIP_TRY(launch_mlp_bwd(g, mlp->packed_dev, (uint32_t)L, ctx->bucket_off, ctx->tile_off, w.seg_off, ctx->srec_ray,
                          ctx->srec_t, ctx->perm, rays->o_dev, rays->d_dev, rays->n_rays, 0, w.gpre, w.part, st));
   HIP_TRY(launch_grad_reduce(w.part, w.seg_off, (uint32_t)L, (uint32_t)P, grad, st));
+  ctx->have_backward = true;
+  ctx->last_gpre = w.gpre;
   return AMNERF_OK;
 }
 
@@ -1146,6 +1169,17 @@ extern "C" int amnerf_render_backward(amnerf_ctx* ctx, const amnerf_tree* tree, 
   if (!ctx || !tree || !mlp || !rays) return fail(AMNERF_EINVAL, "amnerf_render_backward: null argument");
   HIP_TRY(hipSetDevice(ctx->device));
   return backward_impl(ctx, tree, mlp, rays, g_rgb, g_depth, g_opac, grad, (hipStream_t)stream, nullptr);
+}
+
+extern "C" int amnerf_render_backward_inspect(amnerf_ctx* ctx, float* sample_grad_dev, void* stream) {
+  if (!ctx || !sample_grad_dev) return fail(AMNERF_EINVAL, "amnerf_render_backward_inspect: null argument");
+  if (!ctx->have_backward || !ctx->have_render)
+    return fail(AMNERF_ESTATE, "amnerf_render_backward_inspect: no backward pass of the last render");
+  int rc = read_counts(ctx);
+  if (rc) return rc;
+  const uint64_t ns = ctx->counts_host->n_smp;
+  if (ns) HIP_TRY(hipMemcpyAsync(sample_grad_dev, ctx->last_gpre, 16 * ns, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return AMNERF_OK;
 }
 
 extern "C" int amnerf_error_stats(amnerf_ctx* ctx, const float* x, const double* ref, const uint8_t* sel, int64_t n,
@@ -1267,6 +1301,9 @@ extern "C" int amnerf_propose(amnerf_ctx* ctx, const amnerf_tree* tree, const am
   if (p->mode == AMNERF_PROPOSE_INFER && (!p->infer_packed_dev || !p->tau_dev ||
                                           (p->infer_dtype != AMNERF_F32 && p->infer_dtype != AMNERF_BF16)))
     return fail(AMNERF_EINVAL, "amnerf_propose: bad inference arguments");
+  if (p->s_max < 1 || p->s_max > AMNERF_MAX_SAMPLES)
+    return fail(AMNERF_EINVAL, "amnerf_propose: s_max %d out of [1, %d]", p->s_max, AMNERF_MAX_SAMPLES);
+  if (rays->n_rays < 0) return fail(AMNERF_EINVAL, "amnerf_propose: n_rays < 0");
   const uint64_t R = (uint64_t)rays->n_rays;
   if (R * (uint64_t)std::max(1, p->s_max) > kChunkSamples)
     return fail(AMNERF_ECAPACITY, "amnerf_propose: %llu rays x %d samples exceed one pass", (unsigned long long)R, p->s_max);

@@ -5,6 +5,8 @@
 // Per ray: tau_j = sigma_j delta_j, S_j = sum_{i<j} tau_i accumulated in float32 with
 // compensation (log-space transmittance), T_j = exp(-S_j), w_j = T_j * (1 - exp(-tau_j))
 // via expm1, stop after the first j with T_{j+1} < eps.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "devcommon.hpp"
 
@@ -90,7 +92,8 @@ constexpr uint32_t kStage = 256;   // intervals of a ray searched in LDS (more: 
 __global__ __launch_bounds__(kThreads) void k_composite(
     uint32_t nr, IvSet iv, const float* __restrict__ smp_out, int64_t r0, int jitter,
     uint64_t seed, float eps, float* __restrict__ rgb, float* __restrict__ depth,
-    float* __restrict__ opac, float* __restrict__ weights, ChunkCounts* __restrict__ counts) {
+    float* __restrict__ opac, float* __restrict__ weights, uint32_t* __restrict__ ray_used,
+    ChunkCounts* __restrict__ counts) {
   __shared__ uint32_t sbase[kThreads / 64][kStage];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t r = blockIdx.x * (kThreads / 64) + wave;
@@ -108,6 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_composite(
   }
   const uint64_t wbase = counts->smp_global + s0;
   float cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f, acc = 0.f;
+  uint32_t used = ns;   // samples composited: up to and including the stop sample
   if (ns > 0) {
     DF carry = {0.f, 0.f};
     bool done = false;
@@ -150,6 +154,7 @@ __global__ __launch_bounds__(kThreads) void k_composite(
         const int first = __ffsll((unsigned long long)stops) - 1;
         if (lane > first) w = 0.f;
         done = true;
+        used = base + (uint32_t)first + 1u;
       }
       cr = fmaf(w, sig_c[0], cr);
       cg = fmaf(w, sig_c[1], cg);
@@ -167,6 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_composite(
     acc = wave_sum(acc);
   }
   if (lane == 0) {
+    ray_used[r] = used;
     rgb[3 * (uint64_t)(r0 + r) + 0] = cr;
     rgb[3 * (uint64_t)(r0 + r) + 1] = cg;
     rgb[3 * (uint64_t)(r0 + r) + 2] = cb;
@@ -174,6 +180,24 @@ __global__ __launch_bounds__(kThreads) void k_composite(
     if (opac) opac[r0 + r] = acc;
     if (!isfinite(cr) || !isfinite(cg) || !isfinite(cb) || !isfinite(dep) || !isfinite(acc))
       atomicAdd(reinterpret_cast<unsigned long long*>(&counts->nonfinite), 1ull);
+  }
+}
+
+// counts->composited += sum of ray_used[0, nr): block sums in a fixed order, one integer
+// atomic per block.
+__global__ __launch_bounds__(kThreads) void k_sum_used(uint32_t nr, const uint32_t* __restrict__ ray_used,
+                                                       ChunkCounts* __restrict__ counts) {
+  __shared__ uint32_t sh[kThreads / 64];
+  uint32_t s = 0;
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < nr; i += gridDim.x * kThreads) s += ray_used[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < kThreads / 64; ++w) t += sh[w];
+    if (t) atomicAdd(reinterpret_cast<unsigned long long*>(&counts->composited), (unsigned long long)t);
   }
 }
 
@@ -201,6 +225,8 @@ __global__ void k_counts_merge(ChunkCounts* a, const ChunkCounts* b) {
   a->nonfinite += b->nonfinite;
   a->fallback += b->fallback;
   a->plain_smp += b->plain_smp;
+  a->unreached += b->unreached;
+  a->composited += b->composited;
 }
 
 __global__ void k_counts_reset(ChunkCounts* counts) {
@@ -213,12 +239,15 @@ __global__ void k_counts_reset(ChunkCounts* counts) {
 
 hipError_t launch_composite(uint32_t nr, const IvSet& iv, const float* smp_out, int64_t r0,
                             int jitter, uint64_t seed, float ert_eps, float* rgb, float* depth,
-                            float* opac, float* weights, ChunkCounts* counts, hipStream_t st) {
+                            float* opac, float* weights, uint32_t* ray_used, ChunkCounts* counts,
+                            hipStream_t st) {
   if (nr == 0) return hipSuccess;
   const uint32_t rays_per_block = kThreads / 64;
   uint32_t grid = (nr + rays_per_block - 1) / rays_per_block;
   hipLaunchKernelGGL(k_composite, dim3(grid), dim3(kThreads), 0, st, nr, iv, smp_out, r0, jitter, seed,
-                     ert_eps, rgb, depth, opac, weights, counts);
+                     ert_eps, rgb, depth, opac, weights, ray_used, counts);
+  const uint32_t sgrid = std::min<uint32_t>(256u, (nr + 4 * kThreads - 1) / (4 * kThreads));
+  hipLaunchKernelGGL(k_sum_used, dim3(sgrid), dim3(kThreads), 0, st, nr, ray_used, counts);
   return hipGetLastError();
 }
 

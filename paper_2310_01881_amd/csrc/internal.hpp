@@ -34,6 +34,9 @@ struct ChunkCounts {
   uint64_t nonfinite;   // rays with a non-finite output (accumulated over chunks)
   uint64_t fallback;    // rays that fell back to plain sampling under a proposal
   uint64_t plain_smp;   // samples of the plain sampler (before any proposal)
+  uint64_t unreached;   // interval entries the emission walk did not reach (filled with
+                        // zero-length slot-0 entries; 0 unless the two traversal passes disagree)
+  uint64_t composited;  // samples composited before early termination (accumulated)
 };
 
 constexpr int kMlpTileRows = 256;       // rows of one MLP work tile (4 waves x 64)
@@ -52,7 +55,7 @@ hipError_t launch_trav_emit(const DevNode* nodes, const DevNodeAhs* ahs, float f
                             const uint32_t* cnt_iv, const uint32_t* cnt_smp,
                             const uint32_t* iv_off, const uint32_t* smp_off, float* iv_t0,
                             float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray, uint32_t* iv_base,
-                            hipStream_t st);
+                            ChunkCounts* counts, hipStream_t st);
 
 // Intervals of one chunk, ray-major: per ray the interval range [iv_off[r], iv_off[r+1]) and
 // sample range [smp_off[r], smp_off[r+1]); per interval t0, length dt, key (slot | n << 16),
@@ -132,6 +135,10 @@ hipError_t launch_error_stats(const float* x, const double* ref, const uint8_t* 
 // current device: the register/wave limit from the runtime, the LDS limit from the
 // device's LDS size per compute unit.
 hipError_t resident_blocks(const void* kern, int threads, uint32_t lds, int* per_cu);
+// Grid of a persistent launch of `kern` on the current device: compute units x resident
+// blocks at `lds` bytes of dynamic LDS (allowing up to 160 KiB of it first).  Cached per
+// (kernel, device, lds); safe to call from several host threads.
+hipError_t persistent_grid(const void* kern, int threads, uint32_t lds, int* grid);
 
 hipError_t launch_mlp_pack(const MlpGeom& g, int n_leaves, const float* master, void* packed,
                            hipStream_t st);
@@ -142,14 +149,19 @@ hipError_t launch_mlp(const MlpGeom& g, const void* packed, uint32_t n_leaves,
                       int64_t r0, float* out, hipStream_t st);
 
 // ---- compositing (Section 3.1 -> NeRF quadrature, early ray termination) ---------------
+// ray_used[r] receives the number of samples of ray r that were composited (the stop
+// sample included), and counts->composited their sum.
 hipError_t launch_composite(uint32_t nr, const IvSet& iv, const float* smp_out, int64_t r0,
                             int jitter, uint64_t seed, float ert_eps, float* rgb, float* depth,
-                            float* opac, float* weights, ChunkCounts* counts, hipStream_t st);
+                            float* opac, float* weights, uint32_t* ray_used, ChunkCounts* counts,
+                            hipStream_t st);
 
 // ---- training ----------------------------------------------------------------------------
 bool mlp_bwd_supported(int n_hidden, int hidden);
+// Backward of the quadrature; ray_used[r] = samples of ray r the forward composited (the
+// samples after them get zero gradient).
 hipError_t launch_comp_bwd(uint32_t nr, const IvSet& iv, const float* smp_out, int64_t r0, int jitter,
-                           uint64_t seed, float eps, const float* g_rgb, const float* g_depth,
+                           uint64_t seed, const uint32_t* ray_used, const float* g_rgb, const float* g_depth,
                            const float* g_opac, float* gpre, hipStream_t st);
 hipError_t launch_seg_offsets(const uint32_t* tile_off, uint32_t n_leaves, uint32_t* seg_off, hipStream_t st);
 hipError_t launch_mlp_bwd(const MlpGeom& g, const void* packed, uint32_t n_leaves, const uint32_t* bucket_off,

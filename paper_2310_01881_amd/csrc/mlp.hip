@@ -19,6 +19,9 @@
 //   FP8  : the BF16 kernel; the leaf's e4m3 weights are widened to bf16 (times the layer's
 //          scale) while they are staged into LDS, so the block in memory is half the size.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "internal.hpp"
 #include "devcommon.hpp"
@@ -491,28 +494,42 @@ hipError_t launch_typed(const Layout& L, const void* packed, uint32_t n_leaves, 
                         const uint32_t* tile_off, const ChunkCounts* counts, const uint32_t* srec_ray,
                         const float* srec_t, const uint32_t* perm, const float* o, const float* d,
                         int64_t stride, int64_t r0, float* out, hipStream_t st) {
-  static int grid = 0;
-  static uint32_t grid_bytes = 0;
   auto kern = k_mlp<H, BF16, FP8>;
-  if (grid == 0 || grid_bytes != L.bytes) {
-    if (L.bytes > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.bytes);
-      if (e != hipSuccess) return e;
-    }
-    int dev = 0, ncu = 0, per = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = resident_blocks((const void*)kern, kThreads, L.bytes, &per);
-    if (e != hipSuccess) return e;
-    grid = ncu * per;
-    grid_bytes = L.bytes;
-  }
+  int grid = 0;
+  hipError_t e = persistent_grid((const void*)kern, kThreads, L.bytes, &grid);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), L.bytes, st, L, (const uint8_t*)packed, n_leaves,
                      bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d, stride, r0, out);
   return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t persistent_grid(const void* kern, int threads, uint32_t lds, int* grid) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, int, uint32_t>, int> cache;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const auto key = std::make_tuple(kern, dev, lds);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      *grid = it->second;
+      return hipSuccess;
+    }
+  }
+  int ncu = 0, per = 0;
+  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = resident_blocks(kern, threads, lds, &per);
+  if (e != hipSuccess) return e;
+  *grid = ncu * per;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = *grid;
+  return hipSuccess;
+}
 
 hipError_t resident_blocks(const void* kern, int threads, uint32_t lds, int* per_cu) {
   int dev = 0, lds_cu = 0, per_regs = 0;

@@ -283,6 +283,231 @@ __global__ __launch_bounds__(kThreads) void k_mlp_bwd(
   }
 }
 
+// ---- float32 operands: v_mfma_f32_16x16x4_f32.  An MFMA takes A[m][k] from lane
+// (k, m) and B[k][n] from lane (k, n) (one float each) and leaves C rows 4g..4g+3 of column
+// n in lane (g, n).  The same work split as the bfloat16 kernel (segments of one leaf's
+// tiles, partial gradients per segment), with 64-row sub-tiles of 16 rows per wave; the
+// leaf's float32 forward block (the layout k_mlp reads) is staged in LDS and serves both
+// the forward recomputation and, read transposed, dH = W^T dZ.
+constexpr int kSub32 = 64;                 // rows of a float32 sub-tile (4 waves x 16)
+constexpr int kRowF = kSub32 + 4;          // staged feature row (floats) + padding
+
+// W_l[row][col] of a hidden or output layer inside the float32 forward block: unit
+// (l, row / 16, col / 16), lane ((col % 16) / 4) * 16 + row % 16, element col % 4.
+__device__ __forceinline__ float w_at(const Layout& L, const uint8_t* units, int l, int row, int col) {
+  const int u = L.unit_index(l, row >> 4, col >> 4);
+  return *reinterpret_cast<const float*>(units + u * kUnitBytes + ((((col & 15) >> 2) << 4) + (row & 15)) * 16 +
+                                         (col & 3) * 4);
+}
+
+template <int H, int NH>
+__global__ __launch_bounds__(kThreads) void k_mlp_bwd_f32(
+    Layout L, const uint8_t* __restrict__ packed, uint32_t n_leaves, const uint32_t* __restrict__ bucket_off,
+    const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ seg_off,
+    const uint32_t* __restrict__ srec_ray, const float* __restrict__ srec_t, const uint32_t* __restrict__ perm,
+    const float* __restrict__ o, const float* __restrict__ d, int64_t stride, int64_t r0,
+    const float* __restrict__ gpre, float* __restrict__ part, int P) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  constexpr int RB = H / 16;
+  const float* bias = reinterpret_cast<const float*>(lds);
+  const uint8_t* units = lds + L.bias_bytes;
+  float* sZ = reinterpret_cast<float*>(lds + L.bytes);   // [H][kRowF]: dZ_l, feature-major
+  float* sH = sZ + H * kRowF;                            // [H][kRowF]: layer input, feature-major
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, m = lane & 15;
+  const uint32_t n_seg = seg_off[n_leaves];
+  int cur = -1;
+  for (uint32_t seg = blockIdx.x; seg < n_seg; seg += gridDim.x) {
+    uint32_t lo = 0, hi = n_leaves;
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (seg_off[mid] <= seg) lo = mid; else hi = mid;
+    }
+    const uint32_t b = lo;
+    const uint32_t t_first = tile_off[b] + (seg - seg_off[b]) * kSegTiles;
+    const uint32_t t_last = t_first + kSegTiles < tile_off[b + 1] ? t_first + kSegTiles : tile_off[b + 1];
+    if ((int)b != cur) {
+      __syncthreads();
+      const f32x4* src = reinterpret_cast<const f32x4*>(packed + (uint64_t)b * L.bytes);
+      for (uint32_t i = tid; i < L.bytes / 16; i += kThreads) reinterpret_cast<f32x4*>(lds)[i] = src[i];
+      __syncthreads();
+      cur = (int)b;
+    }
+    f32x4 accW[NH + 1][4];
+    f32x4 accB[NH + 1];
+#pragma unroll
+    for (int l = 0; l <= NH; ++l) {
+      accB[l] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) accW[l][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    constexpr int kSubPerTile = kMlpTileRows / kSub32;
+    for (uint32_t sub = kSubPerTile * t_first; sub < kSubPerTile * t_last; ++sub) {
+      const uint32_t row_end = bucket_off[b + 1];
+      const uint32_t row = bucket_off[b] + (sub - kSubPerTile * tile_off[b]) * kSub32 + wave * 16 + m;
+      const bool valid = row < row_end;
+      // ---- this lane's sample (column m of the wave's block): inputs as in the forward ----
+      uint32_t ray = 0, dst = 0;
+      float ts = 0.f;
+      if (valid) {
+        ray = srec_ray[row];
+        ts = srec_t[row];
+        dst = perm[row];
+      }
+      const int64_t ri = r0 + ray;
+      const float ox = o[ri], oy = o[stride + ri], oz = o[2 * stride + ri];
+      const float dx = d[ri], dy = d[stride + ri], dz_ = d[2 * stride + ri];
+      const float px = 2.f * fmaf(ts, dx, ox) - 1.f;
+      const float py = 2.f * fmaf(ts, dy, oy) - 1.f;
+      const float pz = 2.f * fmaf(ts, dz_, oz) - 1.f;
+      float feat[8];
+      {
+        const float sc = (float)(1 << g);
+        feat[0] = sinpif(px * sc); feat[1] = sinpif(py * sc); feat[2] = sinpif(pz * sc);
+        feat[3] = cospif(px * sc); feat[4] = cospif(py * sc); feat[5] = cospif(pz * sc);
+        feat[6] = g == 0 ? px : (g == 1 ? pz : (g == 2 ? dy : 0.f));
+        feat[7] = g == 0 ? py : (g == 1 ? dx : (g == 2 ? dz_ : 0.f));
+      }
+      // ---- forward recompute: Hs[l] = ReLU output of layer l (accumulator layout) ----
+      f32x4 Hs[NH][RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        f32x4 z = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
+#pragma unroll
+        for (int ku = 0; ku < 2; ++ku) {
+          const f32x4 A = *reinterpret_cast<const f32x4*>(units + L.unit_index(0, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) z = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], feat[4 * ku + e], z, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Hs[0][rb][i] = fmaxf(z[i], 0.f);
+      }
+#pragma unroll
+      for (int l = 1; l < NH; ++l) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          f32x4 z = *reinterpret_cast<const f32x4*>(bias + l * H + 16 * rb + 4 * g);
+#pragma unroll
+          for (int ku = 0; ku < RB; ++ku) {
+            const f32x4 A = *reinterpret_cast<const f32x4*>(units + L.unit_index(l, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) z = __builtin_amdgcn_mfma_f32_16x16x4f32(A[e], Hs[l - 1][ku][e], z, 0, 0, 0);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Hs[l][rb][i] = fmaxf(z[i], 0.f);
+        }
+      }
+      // ---- backward from the output layer: lanes of group 0 hold dL/d(sigma^, r^, g^, b^) ----
+      f32x4 dz[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) dz[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (g == 0 && valid) dz[0] = *reinterpret_cast<const f32x4*>(gpre + 4 * (uint64_t)dst);
+#pragma unroll
+      for (int l = NH; l >= 0; --l) {
+        const int rbo = l == NH ? 1 : RB;          // row blocks of this layer's outputs
+        const int cbi = l == 0 ? 2 : RB;           // 16-column blocks of its inputs
+        const int n_items = rbo * cbi;
+        const int per = (n_items + 3) / 4;
+        __syncthreads();
+        const int col = wave * 16 + m;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (rb >= rbo) break;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sZ[(16 * rb + 4 * g + i) * kRowF + col] = dz[rb][i];
+        }
+        if (l == 0) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) sH[(8 * g + i) * kRowF + col] = feat[i];
+        } else {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sH[(16 * rb + 4 * g + i) * kRowF + col] = Hs[l - 1][rb][i];
+        }
+        __syncthreads();
+        // dW_l += dZ_l X_l^T and db_l += dZ_l 1 over the sub-tile's 64 samples (K = samples)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int item = wave * per + q;
+          if (q >= per || item >= n_items) break;
+          const int rb = item / cbi, ci = item % cbi;
+#pragma unroll 4
+          for (int kk = 0; kk < kSub32 / 4; ++kk) {
+            const float a = sZ[(16 * rb + m) * kRowF + 4 * kk + g];
+            const float bb = sH[(16 * ci + m) * kRowF + 4 * kk + g];
+            accW[l][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, accW[l][q], 0, 0, 0);
+            if (ci == 0) accB[l] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, 1.f, accB[l], 0, 0, 0);
+          }
+        }
+        if (l == 0) break;
+        // dH = W_l^T dZ_l (rows: the layer's inputs; K: its outputs), then the ReLU mask
+        f32x4 dh[RB];
+#pragma unroll
+        for (int rbi = 0; rbi < RB; ++rbi) {
+          dh[rbi] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int ku = 0; ku < RB; ++ku) {
+            if (ku >= rbo) break;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float a = w_at(L, units, l, 16 * ku + 4 * g + e, 16 * rbi + m);
+              dh[rbi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, dz[ku][e], dh[rbi], 0, 0, 0);
+            }
+          }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) dz[rb][i] = Hs[l - 1][rb][i] > 0.f ? dh[rb][i] : 0.f;
+      }
+    }
+
+    // ---- this segment's partial gradient, master layout ----
+    float* dstp = part + (uint64_t)seg * P;
+#pragma unroll
+    for (int l = 0; l <= NH; ++l) {
+      const int rbo = l == NH ? 1 : RB;
+      const int cbi = l == 0 ? 2 : RB;
+      const int n_items = rbo * cbi;
+      const int per = (n_items + 3) / 4;
+      int din, dout, off_w, off_b;
+      master_offsets(NH, H, l, din, dout, off_w, off_b);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int item = wave * per + q;
+        if (q >= per || item >= n_items) break;
+        const int rb = item / cbi, ci = item % cbi;
+        const int c = 16 * ci + m;
+        const int colm = l == 0 ? first_layer_col(c >> 3, c & 7) : c;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int out = 16 * rb + 4 * g + i;
+          if (out < dout && colm >= 0) dstp[off_w + out * din + colm] = accW[l][q][i];
+          if (ci == 0 && m == 0 && out < dout) dstp[off_b + out] = accB[l][i];
+        }
+      }
+    }
+  }
+}
+
+template <int H, int NH>
+hipError_t launch_bwd_f32_typed(const Layout& L, const void* packed, uint32_t n_leaves,
+                                const uint32_t* bucket_off, const uint32_t* tile_off,
+                                const uint32_t* seg_off, const uint32_t* srec_ray, const float* srec_t,
+                                const uint32_t* perm, const float* o, const float* d, int64_t stride,
+                                int64_t r0, const float* gpre, float* part, hipStream_t st) {
+  auto kern = k_mlp_bwd_f32<H, NH>;
+  const uint32_t lds = L.bytes + 2u * H * kRowF * 4u;
+  int grid = 0;
+  hipError_t e = persistent_grid((const void*)kern, kThreads, lds, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, L, (const uint8_t*)packed, n_leaves,
+                     bucket_off, tile_off, seg_off, srec_ray, srec_t, perm, o, d, stride, r0, gpre, part,
+                     master_param_count(NH, H));
+  return hipGetLastError();
+}
+
 template <int H, int NH>
 hipError_t launch_bwd_typed(const Layout& L, const void* packed, uint32_t n_leaves,
                             const uint32_t* bucket_off, const uint32_t* tile_off,
@@ -291,17 +516,9 @@ hipError_t launch_bwd_typed(const Layout& L, const void* packed, uint32_t n_leav
                             int64_t r0, const float* gpre, float* part, hipStream_t st) {
   auto kern = k_mlp_bwd<H, NH>;
   const uint32_t lds = L.bytes + L.bwd_bytes + 2u * H * kRowBytes;
-  static int grid = 0;
-  if (grid == 0) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    int dev = 0, ncu = 0, per = 0;
-    e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = resident_blocks((const void*)kern, kThreads, lds, &per);
-    if (e != hipSuccess) return e;
-    grid = ncu * per;
-  }
+  int grid = 0;
+  hipError_t e = persistent_grid((const void*)kern, kThreads, lds, &grid);
+  if (e != hipSuccess) return e;
   const uint8_t* pf = (const uint8_t*)packed;
   const uint8_t* pb = pf + (uint64_t)n_leaves * L.bytes;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, L, pf, pb, n_leaves, bucket_off, tile_off,
@@ -313,7 +530,7 @@ hipError_t launch_bwd_typed(const Layout& L, const void* packed, uint32_t n_leav
 }  // namespace
 
 bool mlp_bwd_supported(int n_hidden, int hidden) {
-  return (n_hidden == 2 || n_hidden == 4) && (hidden == 32 || hidden == 64);
+  return n_hidden >= 1 && n_hidden <= 4 && (hidden == 32 || hidden == 64);
 }
 
 hipError_t launch_mlp_bwd(const MlpGeom& g, const void* packed, uint32_t n_leaves,
@@ -321,15 +538,23 @@ hipError_t launch_mlp_bwd(const MlpGeom& g, const void* packed, uint32_t n_leave
                           const uint32_t* srec_ray, const float* srec_t, const uint32_t* perm,
                           const float* o, const float* d, int64_t ray_stride, int64_t r0,
                           const float* gpre, float* part, hipStream_t st) {
-  Layout L = make_layout(g.n_hidden, g.hidden, AMNERF_BF16);
-#define AMN_BWD(HH, NN)                                                                          \
-  if (g.hidden == HH && g.n_hidden == NN)                                                        \
-    return launch_bwd_typed<HH, NN>(L, packed, n_leaves, bucket_off, tile_off, seg_off, srec_ray, \
-                                    srec_t, perm, o, d, ray_stride, r0, gpre, part, st);
+  Layout L = make_layout(g.n_hidden, g.hidden, g.dtype);
+#define AMN_BWD(HH, NN)                                                                                \
+  if (g.hidden == HH && g.n_hidden == NN) {                                                            \
+    if (g.dtype == AMNERF_F32)                                                                         \
+      return launch_bwd_f32_typed<HH, NN>(L, packed, n_leaves, bucket_off, tile_off, seg_off, srec_ray, \
+                                          srec_t, perm, o, d, ray_stride, r0, gpre, part, st);        \
+    return launch_bwd_typed<HH, NN>(L, packed, n_leaves, bucket_off, tile_off, seg_off, srec_ray,       \
+                                    srec_t, perm, o, d, ray_stride, r0, gpre, part, st);              \
+  }
   AMN_BWD(64, 4)
+  AMN_BWD(64, 3)
   AMN_BWD(64, 2)
+  AMN_BWD(64, 1)
   AMN_BWD(32, 4)
+  AMN_BWD(32, 3)
   AMN_BWD(32, 2)
+  AMN_BWD(32, 1)
 #undef AMN_BWD
   return hipErrorInvalidValue;
 }

@@ -1182,12 +1182,8 @@ hipError_t launch_prop_train(const void* packed, const IvSet& iv, const float* o
                              float* loss_part, float* grad, float* loss, hipStream_t st) {
   const uint32_t nb = prop_train_blocks();
   const uint32_t lds = kF32Bytes + 2u * kH * kTrRow;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_prop_train, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  hipError_t e = hipFuncSetAttribute((const void*)k_prop_train, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_prop_train, dim3(nb), dim3(kThreads), lds, st, (const uint8_t*)packed, iv, o, d, stride, r0,
                      leafbox, s_max, alpha, part, loss_part);
   hipLaunchKernelGGL(k_prop_reduce, dim3(36), dim3(kThreads), 0, st, part, nb, loss_part, 0u, grad, loss, iv.n_iv_dev);

@@ -58,8 +58,10 @@ __device__ __forceinline__ float suffix_excl(float v, int lane) {
   return x - v;
 }
 
-// Backward of the quadrature, one wave per ray.  Pass 1 recomputes the forward scan to find
-// the early-termination sample J and the transmittance carried into each 64-sample step.
+// Backward of the quadrature, one wave per ray.  The forward's count of composited samples
+// U = ray_used[r] fixes the early-termination sample J = U - 1 (the backward never decides
+// termination again, so it differentiates exactly the sum the forward computed).  Pass 1
+// recomputes the transmittance carried into each 64-sample step up to J.
 // Pass 2 walks the steps in reverse: with T_{j+1} = exp(-S_{j+1}) and the suffix sums
 // sum_{i>j} w_i c_i (and of w_i t_i, w_i) from a reverse scan,
 //   dL/dtau_j = g . (T_{j+1} c_j - sum_{i>j} w_i c_i) + g_D (T_{j+1} t_j - sum_{i>j} w_i t_i)
@@ -67,8 +69,8 @@ __device__ __forceinline__ float suffix_excl(float v, int lane) {
 // dL/dsigma^_j = dL/dtau_j delta_j logistic(sigma^_j), dL/dc^_j = g w_j c_j (1 - c_j).
 __global__ __launch_bounds__(kThreads) void k_comp_bwd(
     uint32_t nr, IvSet iv, const float* __restrict__ smp_out, int64_t r0, int jitter,
-    uint64_t seed, float eps, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
-    const float* __restrict__ g_opac, float* __restrict__ gpre) {
+    uint64_t seed, const uint32_t* __restrict__ ray_used, const float* __restrict__ g_rgb,
+    const float* __restrict__ g_depth, const float* __restrict__ g_opac, float* __restrict__ gpre) {
   const int lane = threadIdx.x & 63;
   const uint32_t r = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (r >= nr) return;
@@ -90,32 +92,27 @@ __global__ __launch_bounds__(kThreads) void k_comp_bwd(
     t = sample_t(iv.t0[i], delta, jj, u);
     tau = softplusf(z.x) * delta;
   };
-  // pass 1: forward scan, termination sample
+  // pass 1: forward scan of the steps up to the termination sample
+  const uint32_t U = ray_used[r] < ns ? ray_used[r] : ns;
+  const uint32_t J = U > 0 ? U - 1 : 0;
+  const uint32_t steps = (U + 63) / 64;
   DF carry = {0.f, 0.f};
-  uint32_t J = ns - 1;
-  uint32_t steps = 0;
-  for (uint32_t base = 0; base < ns; base += 64) {
-    carry_at[steps++] = carry;
-    const uint32_t j = base + lane;
+  for (uint32_t st = 0; st < steps; ++st) {
+    carry_at[st] = carry;
+    const uint32_t j = st * 64u + lane;
     float tau = 0.f, delta, t;
     float4 z;
     if (j < ns) sample(j, tau, delta, t, z);
     DF S, Sn;
     tau_scan(tau, carry, lane, S, Sn);
-    const bool stop = j < ns && eps > 0.f && df_exp_neg(Sn) < eps;
-    const uint64_t stops = __ballot(stop);
     carry = {__shfl(Sn.hi, 63, 64), __shfl(Sn.lo, 63, 64)};
-    if (stops) {
-      J = base + (uint32_t)(__ffsll((unsigned long long)stops) - 1);
-      break;
-    }
   }
   // pass 2: reverse over steps
   float sufR = 0.f, sufG = 0.f, sufB = 0.f, sufD = 0.f, sufA = 0.f;
   for (int st = (int)steps - 1; st >= 0; --st) {
     const uint32_t base = (uint32_t)st * 64u;
     const uint32_t j = base + lane;
-    const bool valid = j <= J;
+    const bool valid = j <= J && U > 0;
     float tau = 0.f, delta = 0.f, t = 0.f;
     float4 z = {0.f, 0.f, 0.f, 0.f};
     if (j < ns) sample(j, tau, delta, t, z);
@@ -251,12 +248,12 @@ __global__ __launch_bounds__(kThreads) void k_adam(int64_t n, float* __restrict_
 }  // namespace
 
 hipError_t launch_comp_bwd(uint32_t nr, const IvSet& iv, const float* smp_out, int64_t r0, int jitter,
-                           uint64_t seed, float eps, const float* g_rgb, const float* g_depth,
+                           uint64_t seed, const uint32_t* ray_used, const float* g_rgb, const float* g_depth,
                            const float* g_opac, float* gpre, hipStream_t st) {
   if (nr == 0) return hipSuccess;
   const uint32_t rays_per_block = kThreads / 64;
   hipLaunchKernelGGL(k_comp_bwd, dim3((nr + rays_per_block - 1) / rays_per_block), dim3(kThreads), 0, st, nr,
-                     iv, smp_out, r0, jitter, seed, eps, g_rgb, g_depth, g_opac, gpre);
+                     iv, smp_out, r0, jitter, seed, ray_used, g_rgb, g_depth, g_opac, gpre);
   return hipGetLastError();
 }
 

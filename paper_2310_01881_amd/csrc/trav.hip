@@ -9,6 +9,8 @@
 // quadrature) keep float32 relative accuracy even far along the ray.
 #include <algorithm>
 
+#include <atomic>
+
 #include "internal.hpp"
 #include "devcommon.hpp"
 
@@ -267,7 +269,8 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
                                                       float* __restrict__ iv_dt,
                                                       uint32_t* __restrict__ iv_key,
                                                       uint32_t* __restrict__ iv_ray,
-                                                      uint32_t* __restrict__ iv_base) {
+                                                      uint32_t* __restrict__ iv_base,
+                                                      ChunkCounts* __restrict__ counts) {
   extern __shared__ __align__(16) uint8_t dyn[];
   const TravLds tl = stage<LDS, AHS>(nodes, ahs, footprint, n_nodes, stack_n, dyn);
   uint8_t* sp = dyn + trav_lds_bytes(LDS, AHS, n_nodes, stack_n);
@@ -306,8 +309,12 @@ __global__ __launch_bounds__(kBlock) void k_trav_emit(const DevNode* __restrict_
     });
     // The count pass walks the same way, so `got` equals meff.  Should a walk ever end
     // early, the rest of the ray's range still gets well-formed entries (zero length,
-    // slot 0): later stages then never read an unwritten key.
-    for (uint32_t q = (uint32_t)got; q < meff; ++q) put((int)q, 0.f, 0.f, nper << 16);
+    // slot 0), so later stages never read an unwritten key, and the filled entries are
+    // counted (reported by the render statistics; every test requires 0).
+    if ((uint32_t)got < meff) {
+      for (uint32_t q = (uint32_t)got; q < meff; ++q) put((int)q, 0.f, 0.f, nper << 16);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&counts->unreached), (unsigned long long)(meff - (uint32_t)got));
+    }
   }
   __syncthreads();
   const uint32_t n = b1 - b0 < stage_n ? b1 - b0 : stage_n;
@@ -335,12 +342,17 @@ static hipError_t trav_setup_one() {
   return e;
 }
 
+// Once per device (the attribute is set on the current device).
 static hipError_t trav_setup() {
-  static bool done = false;
-  if (done) return hipSuccess;
-  hipError_t e = trav_setup_one<false>();
+  static std::atomic<uint64_t> done{0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = dev < 64 ? 1ull << dev : 0ull;
+  if (bit && (done.load() & bit)) return hipSuccess;
+  e = trav_setup_one<false>();
   if (e == hipSuccess) e = trav_setup_one<true>();
-  if (e == hipSuccess) done = true;
+  if (e == hipSuccess) done.fetch_or(bit);
   return e;
 }
 
@@ -376,17 +388,17 @@ static void emit_launch(uint32_t grid, uint32_t bytes, hipStream_t st, const Dev
                         float footprint, uint32_t n_nodes, int stack_n, uint32_t stage_n, const float* o,
                         const float* d, int64_t ray_stride, int64_t r0, uint32_t nr, const uint32_t* cnt_iv,
                         const uint32_t* cnt_smp, const uint32_t* iv_off, const uint32_t* smp_off, float* iv_t0,
-                        float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray, uint32_t* iv_base) {
+                        float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray, uint32_t* iv_base, ChunkCounts* counts) {
   hipLaunchKernelGGL((k_trav_emit<LDS, AHS>), dim3(grid), dim3(kBlock), bytes, st, nodes, ahs, footprint, n_nodes,
                      stack_n, stage_n, o, d, ray_stride, r0, nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt,
-                     iv_key, iv_ray, iv_base);
+                     iv_key, iv_ray, iv_base, counts);
 }
 
 hipError_t launch_trav_emit(const DevNode* nodes, const DevNodeAhs* ahs, float footprint, uint32_t n_nodes, int depth,
                             const float* o, const float* d, int64_t ray_stride, int64_t r0, uint32_t nr,
                             const uint32_t* cnt_iv, const uint32_t* cnt_smp, const uint32_t* iv_off,
                             const uint32_t* smp_off, float* iv_t0, float* iv_dt, uint32_t* iv_key, uint32_t* iv_ray,
-                            uint32_t* iv_base, hipStream_t st) {
+                            uint32_t* iv_base, ChunkCounts* counts, hipStream_t st) {
   if (nr == 0) return hipSuccess;
   hipError_t e = trav_setup();
   if (e != hipSuccess) return e;
@@ -401,7 +413,7 @@ hipError_t launch_trav_emit(const DevNode* nodes, const DevNodeAhs* ahs, float f
   stage_n = std::min<uint32_t>(stage_n, 2048u) & ~63u;
   const uint32_t bytes = fixed + 20u * stage_n;
   auto go = [&](auto fn) { fn(grid, bytes, st, nodes, ahs, footprint, n_nodes, stack_n, stage_n, o, d, ray_stride, r0,
-                              nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base); };
+                              nr, cnt_iv, cnt_smp, iv_off, smp_off, iv_t0, iv_dt, iv_key, iv_ray, iv_base, counts); };
   if (lds && hs) go(emit_launch<true, true>);
   else if (lds) go(emit_launch<true, false>);
   else if (hs) go(emit_launch<false, true>);

@@ -122,6 +122,35 @@ def test_hcheck_backward_matches_oracle_gradient():
     assert np.all(g_gpu[~hit] == 0)
 
 
+def test_hcheck_backward_f32_matches_oracle_gradient():
+    """float32 node MLPs: the whole gradient, inner-node MLPs included, within 1e-4 relative
+    L2 of the oracle's analytic gradient (pinned by central differences under hierarchical
+    sampling with early termination on)."""
+    cfg = synth.scaled(synth.C2, grid_n=64, max_leaves=64, max_depth=12)
+    scene = Scene(cfg, footprint=0.25)
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = synth.camera_rays(synth.make_cameras(1, cfg.seed_cameras, 16, 16)[0])
+    R = o.shape[1]
+    rng = np.random.default_rng(8)
+    g_rgb = (rng.standard_normal((R, 3)) / R).astype(np.float32)
+    od, dd = to_dev(o), to_dev(d)
+    rgb = torch.empty((R, 3), device="cuda:0")
+    am.amnerf_render(ctx.h, tree.h, mlp.desc, od, dd, cfg.s_max, rgb, None, None, None, 1e-4,
+                     hcheck_footprint=scene.footprint)
+    grad = torch.empty_like(mlp.master)
+    am.amnerf_render_backward(ctx.h, tree.h, mlp.desc, od, dd, to_dev(g_rgb), grad)
+    torch.cuda.synchronize()
+    am.amnerf_render_stats_get(ctx.h)
+    g_gpu = grad.cpu().numpy().astype(np.float64)
+    g_ref = oracle.render_grad(scene.otree, scene.W, cfg.n_hidden, cfg.hidden, o, d, cfg.s_max,
+                               g_rgb.astype(np.float64), eps=1e-4, footprint=scene.footprint)
+    e = float(np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref))
+    print("hcheck f32 backward: relative L2 %.3e" % e, flush=True)
+    inner = scene.otree.rows[scene.otree.rows[:, 8] >= 0][:, 11]
+    assert np.linalg.norm(g_ref[inner]) > 0
+    assert np.isfinite(g_gpu).all() and e <= 1e-4
+
+
 def test_hcheck_argument_checks():
     scene = Scene(synth.C1, footprint=0.5)
     ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)

@@ -68,6 +68,7 @@ def render_vs_oracle(scene, rays_sel, seed_label):
     print(seed_label, "rays", R, flush=True)
     out = am.render(ctx, tree, mlp, to_dev(o), to_dev(d), cfg.s_max, ert_eps=cfg.ert_eps)
     torch.cuda.synchronize()
+    am.amnerf_render_stats_get(ctx.h)
     _, _, deq = fp8.quantise(scene.W, cfg.n_hidden, cfg.hidden)
     rays = np.arange(R) if rays_sel is None else rays_sel(R)
     rgb8, dep8, op8, _, _ = oracle.render(scene.otree, deq.astype(np.float32), cfg.n_hidden, cfg.hidden, o, d,

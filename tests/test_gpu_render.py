@@ -36,6 +36,7 @@ def inspect(ctx, R):
         "iv_n": torch.empty(max(niv, 1), dtype=torch.int32, device=dev),
         "perm": torch.empty(max(ns, 1), dtype=torch.int32, device=dev),
         "sample_out": torch.empty((max(ns, 1), 4), dtype=torch.float32, device=dev),
+        "ray_used": torch.empty(max(R, 1), dtype=torch.int32, device=dev),
     }
     return st, b
 
@@ -51,6 +52,7 @@ def fetch_inspect(ctx, R, n_leaves):
         out[k] = out[k][:niv]
     out["perm"] = out["perm"][:ns].view(np.uint32)
     out["sample_out"] = out["sample_out"][:ns]
+    out["ray_used"] = out["ray_used"][:R]
     return st, out
 
 
@@ -112,6 +114,7 @@ def render_all(scene, ctx, tree, mlp, o, d, s_max, **kw):
     out = am.render(ctx, tree, mlp, od, dd, s_max, ert_eps=scene.cfg.ert_eps,
                     hcheck_footprint=getattr(scene, "footprint", 0.0), **kw)
     torch.cuda.synchronize()
+    am.amnerf_render_stats_get(ctx.h)    # checks that no interval entry was left unreached
     return out
 
 

@@ -46,6 +46,8 @@ def test_two_contexts_on_two_streams(mode):
         o, d = rays[k % n_cams]
         frames.append(am.render(ctxs[q], tree, mlp, o, d, cfg.s_max, ert_eps=cfg.ert_eps, stream=streams[q], **kw))
     torch.cuda.synchronize()
+    for c in ctxs:
+        am.amnerf_render_stats_get(c.h)
     for k, out in enumerate(frames):
         for name in ("rgb", "depth", "opacity"):
             assert torch.equal(out[name], alone[k % n_cams][name]), (mode, k, name)

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from scene_util import Scene, to_dev
+from scene_util import Scene, gpu_setup, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -17,12 +17,25 @@ if not torch.cuda.is_available():
 
 import paper_2310_01881_amd as am  # noqa: E402
 
-# bfloat16 operands (weights, activations, gradients at the MFMA inputs) against a float64
-# reference: relative L2 error of the whole gradient vector.
-TOL_REL_L2 = 2e-2
+# float32 operands against the float64 oracle: relative L2 error of the whole gradient
+# vector (sample positions, features and sums carry float32 rounding, ~1e-6 relative).
+TOL_F32_REL_L2 = 1e-4
+# bfloat16 operands against the oracle run on the same bf16-rounded weights.  What remains
+# is the bf16 rounding of the activations (and of the gradients at the MFMA inputs), which
+# moves a few ReLU pre-activations across zero: each such sample switches a unit's whole
+# backward contribution, so with random-sign upstream gradients (the gradient itself a
+# random-sign sum over samples) the relative L2 error grows like the square root of the
+# switched fraction: about 2% here (see the design notes).  Upstream gradients of a
+# squared-error loss against a teacher sum coherently, and there the bar is 1e-2.
+TOL_BF16_RANDOM = 3e-2
+TOL_BF16_MSE = 1e-2
+# per-sample compositing backward (float32) against the oracle's, per ray and column:
+# |gpu - ref| <= 1e-5 * max over the ray's samples of |ref| (+ a 1e-9 floor)
+TOL_COMP = 1e-5
 
 
 def setup(scene):
+    """Context, tree and a bf16 trainer over the scene's weights."""
     ctx = am.Context(0)
     tree = am.Tree(ctx, scene.grid, scene.cfg.grid_n, scene.cfg.max_depth, scene.cfg.max_leaves)
     assert np.array_equal(tree.rows, scene.otree.rows)
@@ -31,50 +44,175 @@ def setup(scene):
     return ctx, tree, tr
 
 
-def gpu_grad(scene, ctx, tree, tr, o, d, s_max, eps, g_rgb, g_dep, g_op):
+def gpu_grad(scene, ctx, tree, mlp, master, o, d, s_max, eps, g_rgb, g_dep, g_op, sample_grad=False):
     od, dd = to_dev(o), to_dev(d)
     R = o.shape[1]
     rgb = torch.empty((R, 3), device="cuda:0")
-    am.amnerf_render(ctx.h, tree.h, tr.mlp, od, dd, s_max, rgb, None, None, None, eps)
-    grad = torch.empty_like(tr.master)
-    am.amnerf_render_backward(ctx.h, tree.h, tr.mlp, od, dd, to_dev(g_rgb.astype(np.float32)), grad,
+    am.amnerf_render(ctx.h, tree.h, mlp, od, dd, s_max, rgb, None, None, None, eps)
+    grad = torch.empty_like(master)
+    am.amnerf_render_backward(ctx.h, tree.h, mlp, od, dd, to_dev(g_rgb.astype(np.float32)), grad,
                               to_dev(g_dep.astype(np.float32)), to_dev(g_op.astype(np.float32)))
     torch.cuda.synchronize()
-    return grad.cpu().numpy().astype(np.float64)
+    st = am.amnerf_render_stats_get(ctx.h)
+    g = grad.cpu().numpy().astype(np.float64)
+    if not sample_grad:
+        return g
+    ns = st["n_samples"]
+    gs = torch.empty((max(ns, 1), 4), device="cuda:0")
+    smp_off = torch.empty(R + 1, dtype=torch.int32, device="cuda:0")
+    used = torch.empty(R, dtype=torch.int32, device="cuda:0")
+    am.amnerf_render_backward_inspect(ctx.h, gs)
+    am.amnerf_render_inspect(ctx.h, ray_smp_off=smp_off, ray_used=used)
+    torch.cuda.synchronize()
+    return g, gs.cpu().numpy()[:ns].astype(np.float64), smp_off.cpu().numpy().astype(np.int64), used.cpu().numpy()
 
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
+def bf16_round(W):
+    return torch.from_numpy(W).to(torch.bfloat16).to(torch.float32).numpy()
+
+
+C2_SMALL = synth.scaled(synth.C2, grid_n=64, max_leaves=64, max_depth=12)
+
+
+def random_upstream(R, seed=7):
+    """dL/d(rgb, depth, opacity) per ray with random signs."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((R, 3)) / R, rng.standard_normal(R) * 0.1 / R, rng.standard_normal(R) * 0.1 / R
+
+
+def mse_upstream(scene, W, o, d, s_max, eps):
+    """dL/drgb = 2 (rgb - target) / (3 R) of a squared-error loss, with rgb the oracle's render
+    with weights W and a target 0.05 brighter in red and 0.05 darker in blue: the residuals'
+    signs agree over the image, as they do in training."""
+    cfg = scene.cfg
+    rgb, _, _, _, _ = oracle.render(scene.otree, W, cfg.n_hidden, cfg.hidden, o, d, s_max, eps=eps)
+    R = o.shape[1]
+    target = rgb + np.array([0.05, 0.0, -0.05])
+    return 2.0 * (rgb - target) / (3 * R), np.zeros(R), np.zeros(R)
+
+
 @pytest.mark.parametrize("cfg,eps", [
     (synth.C1, 0.0),
     (synth.C1, 1e-4),
-    (synth.scaled(synth.C2, grid_n=64, max_leaves=64, max_depth=12), 1e-4),
+    (C2_SMALL, 1e-4),
 ])
-def test_backward_matches_oracle_gradient(cfg, eps):
-    """256 rays (a 16x16 camera) through an 8-leaf (2x32) or 64-leaf (4x64) scene."""
+def test_backward_f32_matches_oracle_gradient(cfg, eps):
+    """float32 forward and backward: the whole gradient within 1e-4 relative L2 of the
+    oracle's analytic gradient (itself pinned by central differences, with early termination
+    on and off).  256 rays (a 16x16 camera) through an 8-leaf (2x32) or 64-leaf (4x64) scene."""
+    scene = Scene(cfg)
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    o, d = synth.camera_rays(synth.make_cameras(1, cfg.seed_cameras, 16, 16)[0])
+    R = o.shape[1]
+    g_rgb, g_dep, g_op = random_upstream(R)
+    g_gpu = gpu_grad(scene, ctx, tree, mlp.desc, mlp.master, o, d, cfg.s_max, eps, g_rgb, g_dep, g_op)
+    f64 = lambda a: a.astype(np.float32).astype(np.float64)
+    g_ref = oracle.render_grad(scene.otree, scene.W, cfg.n_hidden, cfg.hidden, o, d, cfg.s_max,
+                               f64(g_rgb), f64(g_dep), f64(g_op), eps=eps)
+    e = rel_l2(g_gpu, g_ref)
+    print("f32 backward %s eps=%g: relative L2 error %.3e, |g| %.3e" % (cfg.name, eps, e, np.linalg.norm(g_ref)))
+    assert np.isfinite(g_gpu).all()
+    assert e <= TOL_F32_REL_L2
+    hit = np.abs(g_ref).sum(axis=1) > 0
+    assert np.all(g_gpu[~hit] == 0)
+
+
+@pytest.mark.parametrize("cfg,eps,kind", [
+    (synth.C1, 0.0, "random"),
+    (synth.C1, 1e-4, "random"),
+    (C2_SMALL, 1e-4, "random"),
+    (synth.C1, 1e-4, "mse"),
+    (C2_SMALL, 1e-4, "mse"),
+])
+def test_backward_bf16_matches_oracle_on_bf16_weights(cfg, eps, kind):
+    """bfloat16 forward and backward against the oracle run on the bf16-rounded weights."""
     scene = Scene(cfg)
     ctx, tree, tr = setup(scene)
     o, d = synth.camera_rays(synth.make_cameras(1, cfg.seed_cameras, 16, 16)[0])
     R = o.shape[1]
-    rng = np.random.default_rng(7)
-    g_rgb = rng.standard_normal((R, 3)) / R
-    g_dep = rng.standard_normal(R) * 0.1 / R
-    g_op = rng.standard_normal(R) * 0.1 / R
-    s_max = cfg.s_max
-    g_gpu = gpu_grad(scene, ctx, tree, tr, o, d, s_max, eps, g_rgb, g_dep, g_op)
-    g_ref = oracle.render_grad(scene.otree, scene.W, cfg.n_hidden, cfg.hidden, o, d, s_max,
-                               g_rgb.astype(np.float32).astype(np.float64),
-                               g_dep.astype(np.float32).astype(np.float64),
-                               g_op.astype(np.float32).astype(np.float64), eps=eps)
+    Wb = bf16_round(scene.W)
+    if kind == "random":
+        g_rgb, g_dep, g_op = random_upstream(R)
+    else:
+        g_rgb, g_dep, g_op = mse_upstream(scene, Wb, o, d, cfg.s_max, eps)
+    g_gpu = gpu_grad(scene, ctx, tree, tr.mlp, tr.master, o, d, cfg.s_max, eps, g_rgb, g_dep, g_op)
+    f64 = lambda a: a.astype(np.float32).astype(np.float64)
+    g_ref = oracle.render_grad(scene.otree, Wb, cfg.n_hidden, cfg.hidden, o, d, cfg.s_max, f64(g_rgb), f64(g_dep),
+                               f64(g_op), eps=eps)
     e = rel_l2(g_gpu, g_ref)
-    print("backward %s eps=%g: relative L2 error %.3e, |g| %.3e" % (cfg.name, eps, e, np.linalg.norm(g_ref)))
+    print("bf16 backward %s eps=%g %s: relative L2 error %.3e against the oracle on bf16 weights"
+          % (cfg.name, eps, kind, e))
     assert np.isfinite(g_gpu).all()
-    assert e <= TOL_REL_L2
-    # leaves that no sample reached have exactly zero gradient
+    assert e <= (TOL_BF16_RANDOM if kind == "random" else TOL_BF16_MSE)
     hit = np.abs(g_ref).sum(axis=1) > 0
     assert np.all(g_gpu[~hit] == 0)
+
+
+def inv_softplus(s):
+    return np.where(s > 30, s, np.log(np.expm1(np.maximum(s, 1e-300))))
+
+
+def logit(c):
+    return np.log(c) - np.log1p(-c)
+
+
+@pytest.mark.parametrize("cfg,eps,dtype", [
+    (synth.C1, 1e-4, am.AMNERF_F32),
+    (synth.C1, 0.0, am.AMNERF_F32),
+    (C2_SMALL, 1e-4, am.AMNERF_F32),
+    (C2_SMALL, 1e-4, am.AMNERF_BF16),
+])
+def test_composite_backward_per_sample_matches_oracle(cfg, eps, dtype):
+    """The compositing backward sample by sample: the GPU's dL/d(sigma^, r^, g^, b^) against
+    the oracle's per-ray compositing gradient, evaluated on the oracle's own per-sample record
+    (positions, segment lengths and MLP outputs from the seeded inputs).  The float32 leaf
+    MLPs agree with the oracle's to ~1e-6, so each element agrees to 1e-5 of the ray's
+    largest; the forward's stop index (recorded per ray) equals the oracle's on every ray
+    whose stop is not within 1e-4 of the threshold.  With bf16 leaf MLPs the outputs move by
+    ~1e-2, so only the stop index and the zero gradient after it are compared."""
+    scene = Scene(cfg)
+    ctx, tree, mlp = gpu_setup(scene, dtype)
+    o, d = synth.camera_rays(synth.make_cameras(1, cfg.seed_cameras, 24, 24)[0])
+    R = o.shape[1]
+    rng = np.random.default_rng(3)
+    g_rgb, g_dep, g_op = rng.standard_normal((R, 3)), rng.standard_normal(R) * 0.1, rng.standard_normal(R) * 0.1
+    g, gs, smp_off, used = gpu_grad(scene, ctx, tree, mlp.desc, mlp.master, o, d, cfg.s_max, eps,
+                                    g_rgb, g_dep, g_op, sample_grad=True)
+    robust = oracle.robust(scene.otree, o, d)
+    n_cmp = n_stop = worst = 0
+    for r in range(R):
+        rec = oracle.ray_samples(scene.otree, scene.W, cfg.n_hidden, cfg.hidden, o, d, r, cfg.s_max, eps=eps)
+        a, b = smp_off[r], smp_off[r + 1]
+        ns = len(rec["t"])
+        assert np.all(gs[a + used[r]:b] == 0)       # nothing after the forward's stop
+        n_stop += used[r] < b - a
+        if dtype != am.AMNERF_F32 or not robust[r] or rec["flags"] & oracle.FLAG_ERT_AMBIGUOUS:
+            continue
+        assert b - a == ns, (r, b - a, ns)
+        assert used[r] == rec["n_used"], (r, used[r], rec["n_used"])
+        J = rec["n_used"]
+        if ns == 0:
+            continue
+        z = np.zeros((ns, 4))
+        z[:J] = np.column_stack([inv_softplus(rec["sigma"][:J]), logit(rec["rgb"][:J])])
+        gv = np.array([*g_rgb[r], g_dep[r], g_op[r]], np.float32).astype(np.float64)
+        ref, Jr = oracle.composite_grad(z, rec["t"], rec["delta"], gv, eps=eps)
+        assert Jr == J
+        scale = np.abs(ref).max(axis=0)
+        err = np.abs(gs[a:b] - ref)
+        assert np.all(err <= TOL_COMP * scale + 1e-9), (r, (err / (scale + 1e-30)).max())
+        worst = max(worst, float((err / (scale + 1e-9)).max()))
+        n_cmp += 1
+    print("per-sample compositing backward %s eps=%g dtype %d: %d rays compared, %d stopped early, worst %.2e"
+          % (cfg.name, eps, dtype, n_cmp, n_stop, worst))
+    if eps > 0:
+        assert n_stop > 0
+    if dtype == am.AMNERF_F32:
+        assert n_cmp > 0.9 * (smp_off[1:] > smp_off[:-1]).sum()
 
 
 def test_backward_is_deterministic():
@@ -84,8 +222,8 @@ def test_backward_is_deterministic():
     R = o.shape[1]
     g = np.full((R, 3), 1.0 / R)
     z = np.zeros(R)
-    a = gpu_grad(scene, ctx, tree, tr, o, d, 64, 1e-4, g, z, z)
-    b = gpu_grad(scene, ctx, tree, tr, o, d, 64, 1e-4, g, z, z)
+    a = gpu_grad(scene, ctx, tree, tr.mlp, tr.master, o, d, 64, 1e-4, g, z, z)
+    b = gpu_grad(scene, ctx, tree, tr.mlp, tr.master, o, d, 64, 1e-4, g, z, z)
     assert np.array_equal(a, b)
 
 
