@@ -42,6 +42,9 @@ FLOP_PER_SAMPLE_4x64 = 2 * (30 * 64 + 3 * 64 * 64 + 64 * 4)   # 28 928, unpadded
 PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
 
 
+HEADLINE_PSNR_DB = 45.0   # the headline path's quality bar against the oracle
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -686,6 +689,11 @@ def main():
         "hierarchical_sampling": hier,
     }
     print(json.dumps(line), flush=True)
+    head_psnr = psnr.get("bf16_prop")
+    if head_psnr is not None and not head_psnr >= HEADLINE_PSNR_DB:
+        print("bench.py: the headline path is at %.2f dB against the oracle, below the %.0f dB it is quoted at"
+              % (head_psnr, HEADLINE_PSNR_DB), file=sys.stderr, flush=True)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -325,7 +325,12 @@ int amnerf_render_stats_get(amnerf_ctx* ctx, amnerf_render_stats* out);
  *                                      ray-major order: sigma = softplus(sigma^),
  *                                      rgb = logistic(r^, g^, b^)
  *   ray_used     uint32[n_rays]        samples of each ray composited before early
- *                                      termination (the stop sample included) */
+ *                                      termination (the stop sample included)
+ *   slot_mask    uint64[n_rays][4]     proposal or empty-space renders only (else
+ *                                      AMNERF_ESTATE): bit s % 64 of word s / 64 is set when
+ *                                      plain slot s of the ray (its plain samples numbered
+ *                                      front to back) is kept; all bits for a ray that fell
+ *                                      back; unspecified for rays with no interval */
 typedef struct {
   uint32_t* ray_iv_off;
   uint32_t* ray_smp_off;
@@ -337,6 +342,7 @@ typedef struct {
   uint32_t* perm;
   float* sample_out;
   uint32_t* ray_used;
+  uint64_t* slot_mask;
 } amnerf_inspect;
 
 int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* out, void* stream);

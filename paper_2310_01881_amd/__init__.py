@@ -105,7 +105,7 @@ class amnerf_inspect(C.Structure):
     _fields_ = [("ray_iv_off", C.c_void_p), ("ray_smp_off", C.c_void_p), ("iv_t0", C.c_void_p),
                 ("iv_dt", C.c_void_p), ("iv_slot", C.c_void_p), ("iv_n", C.c_void_p),
                 ("bucket_off", C.c_void_p), ("perm", C.c_void_p), ("sample_out", C.c_void_p),
-                ("ray_used", C.c_void_p)]
+                ("ray_used", C.c_void_p), ("slot_mask", C.c_void_p)]
 
 
 class amnerf_adam_params(C.Structure):

@@ -80,6 +80,7 @@ struct amnerf_ctx {
   float *smp_out = nullptr, *srec_t = nullptr;
   uint32_t* ray_used = nullptr;   // samples composited per ray (the early-termination count)
   bool last_uses_arena3 = false;  // the last render's intervals live in the third arena
+  const uint64_t* last_mask = nullptr;   // kept plain slots per ray (proposal or empty-space renders)
   // last backward: per-sample pre-activation gradients (second arena), for inspection
   bool have_backward = false;
   const float* last_gpre = nullptr;
@@ -903,6 +904,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   }
   int64_t n_chunks = 0;
   IvSet use = {};
+  const uint64_t* sel_mask = nullptr;   // the last chunk's kept-slot mask, if it selected slots
   Work* wl = &w0;   // the last chunk's workspace
   uint32_t *mat = w0.mat, *mat_scan = w0.mat_scan, *sidx = w0.sidx, *sn = w0.sn, *ssb = w0.ssb, *scan_tmp = w0.scan_tmp;
   for (int64_t r0 = 0; r0 < R; r0 += (int64_t)chunk, ++n_chunks) {
@@ -949,6 +951,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
       HIP_TRY(launch_scan_u32_pair(pw.runs, pw.pv_off, pw.nsel, pw.ps_off, nr, pw.scan_tmp, cs));
       HIP_TRY(launch_prop_emit(nr, plain, pw.mask, pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, cs));
       use = {pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, pw.pv_off + nr};
+      sel_mask = pw.mask;
       spu = spp;
       mat = pw.mat; mat_scan = pw.mat_scan; sidx = pw.sidx; sn = pw.sn; ssb = pw.ssb; scan_tmp = pw.scan_tmp;
       niv_use_max = niv_plan;
@@ -970,6 +973,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
       HIP_TRY(launch_scan_u32_pair(pw.runs, pw.pv_off, pw.nsel, pw.ps_off, nr, pw.scan_tmp, cs));
       HIP_TRY(launch_prop_emit(nr, plain, pw.mask, pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, cs));
       use = {pw.pv_off, pw.ps_off, pw.pt0, pw.pdt, pw.pkey, pw.pray, pw.pbase, pw.pv_off + nr};
+      sel_mask = pw.mask;
       spu = spp;
       mat = pw.mat; mat_scan = pw.mat_scan; sidx = pw.sidx; sn = pw.sn; ssb = pw.ssb; scan_tmp = pw.scan_tmp;
       niv_use_max = niv_plan;
@@ -1022,6 +1026,7 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   ctx->last_params.occupancy = nullptr;
   ctx->last_ess = occ != nullptr;
   ctx->last_o = rays->o_dev;
+  ctx->last_mask = sel_mask;
   return AMNERF_OK;
 }
 
@@ -1073,6 +1078,11 @@ extern "C" int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* o, v
   HIP_TRY(cp(o->perm, ctx->perm, 4 * ns));
   HIP_TRY(cp(o->sample_out, ctx->smp_out, 16 * ns));
   HIP_TRY(cp(o->ray_used, ctx->ray_used, 4 * nr));
+  if (o->slot_mask) {
+    if (!ctx->last_mask)
+      return fail(AMNERF_ESTATE, "amnerf_render_inspect: slot_mask needs a proposal or empty-space render");
+    HIP_TRY(cp(o->slot_mask, ctx->last_mask, 32 * nr));
+  }
   if (o->iv_slot || o->iv_n) {
     // split the packed keys on the host (inspection only)
     std::vector<uint32_t> keys(niv);

@@ -282,10 +282,10 @@ def test_c2_hcheck_reduced_precision_error_report(dtype):
     p_full = oracle.psnr(g, rgb)
     if dtype == am.AMNERF_BF16:
         print("c2 hcheck bf16: psnr vs oracle %.2f dB, max abs %.3e" % (p_full, np.abs(g - rgb).max()), flush=True)
-        assert p_full > 35.0
+        assert p_full > 59.0 and np.abs(g - rgb).max() < 1e-2   # measured 64.1 dB, 3.7e-3
     else:
         rgb8 = ref(fp8.quantise(scene.W, cfg.n_hidden, cfg.hidden)[2].astype(np.float32))
         p_q, p_oq = oracle.psnr(g, rgb8), oracle.psnr(rgb8, rgb)
         print("c2 hcheck e4m3: psnr vs oracle(dequantised) %.2f dB, vs oracle(float32) %.2f dB; oracle "
               "dequantised vs float32 %.2f dB" % (p_q, p_full, p_oq), flush=True)
-        assert p_q > 45.0 and p_full > p_oq - 1.0
+        assert p_q > 59.0 and np.abs(g - rgb8).max() < 1e-2 and p_full > p_oq - 1.0   # measured 64.7 dB

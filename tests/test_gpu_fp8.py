@@ -82,6 +82,7 @@ def render_vs_oracle(scene, rays_sel, seed_label):
     print("%s: psnr vs oracle(dequantised) %.2f dB, vs oracle(float32 weights) %.2f dB; "
           "oracle dequantised vs float32 weights %.2f dB; max abs vs dequantised %.3e"
           % (seed_label, p_q, p_full, p_oracle_q, np.abs(g - rgb8).max()), flush=True)
+    assert np.abs(g - rgb8).max() < 1e-2     # measured 2.0e-3 (small frame), 2.8e-3 (800x800)
     return p_q, p_full, p_oracle_q
 
 
@@ -90,14 +91,14 @@ def test_c1_fp8_full_frame():
     # against its own weights the float8 render carries only the bfloat16 rounding of weights
     # and activations; against the float32 weights its error is the quantisation's own (the
     # oracle with dequantised weights is as far off), plus no more than 1 dB
-    assert p_q > 45.0
+    assert p_q > 63.0   # measured 68.6 dB
     assert p_full > p_oq - 1.0
 
 
 def test_c2_fp8_sampled():
     p_q, p_full, p_oq = render_vs_oracle(
         Scene(synth.C2), lambda R: np.sort(np.random.default_rng(4).choice(R, 1500, replace=False)), "c2 fp8")
-    assert p_q > 45.0
+    assert p_q > 60.0   # measured 65.0 dB
     assert p_full > p_oq - 1.0
 
 

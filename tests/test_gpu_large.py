@@ -80,7 +80,7 @@ def test_c3_fp8_full_camera_in_two_passes(scene):
     p_q, p_full, p_oq = oracle.psnr(g, rgb_q), oracle.psnr(g, rgb), oracle.psnr(rgb_q, rgb)
     print("c3 fp8: psnr vs oracle(dequantised) %.2f dB, vs oracle(float32 weights) %.2f dB, "
           "quantisation alone %.2f dB" % (p_q, p_full, p_oq), flush=True)
-    assert p_q > 45.0
+    assert p_q > 63.0 and np.abs(g - rgb_q).max() < 1e-2   # measured 68.7 dB
     assert p_full > p_oq - 1.0
 
 
@@ -119,4 +119,4 @@ def test_c3_thirty_cameras_in_one_call(scene):
     p_q = oracle.psnr(g, rgb_q)
     print("c3 30 cameras fp8: psnr vs oracle(dequantised) %.2f dB on %d rays of %d cameras" % (
         p_q, pick.size, len(np.unique(pick // R1))), flush=True)
-    assert p_q > 45.0
+    assert p_q > 65.0 and np.abs(g - rgb_q).max() < 1e-2   # measured 70.3 dB

@@ -16,10 +16,10 @@ if not torch.cuda.is_available():
 
 import paper_2310_01881_amd as am  # noqa: E402
 
-# Tolerances (float32 path vs float64 oracle): rgb and opacity 1e-5 absolute; depth is a
-# weighted sum of t ~ 1.5..3.5, so its float32 rounding scales with t: 4e-5 absolute.
+# Tolerances (float32 path vs float64 oracle): rgb, opacity and depth 1e-5 absolute (depth
+# sums w t with t up to ~3.5; measured errors are below 1e-6).
 TOL_RGB = 1e-5
-TOL_DEPTH = 4e-5
+TOL_DEPTH = 1e-5
 
 
 def inspect(ctx, R):
@@ -251,7 +251,7 @@ def test_c2_bf16_error_report():
     g = out["rgb"].cpu().numpy()[rays]
     psnr = oracle.psnr(g, rgb)
     print("c2 bf16 psnr vs oracle %.2f dB, max abs %.3e" % (psnr, np.abs(g - rgb).max()))
-    assert psnr > 35.0
+    assert psnr > 59.0 and np.abs(g - rgb).max() < 1e-2   # measured 64.4 dB, 4.6e-3
 
 
 @pytest.mark.parametrize("n_hidden,hidden", [(1, 32), (3, 64), (5, 32), (8, 64)])
@@ -289,7 +289,7 @@ def test_mlp_shapes(n_hidden, hidden):
         out = render_all(scene, ctx, tree, m2, o, d, cfg.s_max)
         psnr = oracle.psnr(out["rgb"].cpu().numpy()[rays], want)
         print("  dtype %d: psnr %.2f dB" % (dtype, psnr), flush=True)
-        assert psnr > 50.0   # measured 62-69 dB
+        assert psnr > 57.0   # measured 62.6-68.7 dB
 
 
 def test_axis_parallel_and_inside_rays():

@@ -30,8 +30,13 @@ TOL_F32_REL_L2 = 1e-4
 TOL_BF16_RANDOM = 3e-2
 TOL_BF16_MSE = 1e-2
 # per-sample compositing backward (float32) against the oracle's, per ray and column:
-# |gpu - ref| <= 1e-5 * max over the ray's samples of |ref| (+ a 1e-9 floor)
+# |gpu - ref| <= 1e-5 * max over the ray's samples of |ref|.  dL/dsigma^_j = delta_j
+# logistic(sigma^_j) dL/dtau_j sums O(1) terms (T_{j+1} c_j against the suffix sums, each
+# weighted by the upstream gradient), so its float32 rounding is a few ulps of
+# G = sum_c |g_c| + |g_depth| t_j + |g_opacity| times delta_j, whatever the result's size:
+# that column also gets 1e-6 delta_j G (about 16 float32 ulps).
 TOL_COMP = 1e-5
+TOL_COMP_TAU_ULPS = 1e-6
 
 
 def setup(scene):
@@ -203,11 +208,15 @@ def test_composite_backward_per_sample_matches_oracle(cfg, eps, dtype):
         ref, Jr = oracle.composite_grad(z, rec["t"], rec["delta"], gv, eps=eps)
         assert Jr == J
         scale = np.abs(ref).max(axis=0)
+        G = np.abs(gv[:3]).sum() + abs(gv[3]) * rec["t"] + abs(gv[4])
+        bar = np.repeat((TOL_COMP * scale)[None, :], ns, axis=0)
+        bar[:, 0] += TOL_COMP_TAU_ULPS * rec["delta"] * G
         err = np.abs(gs[a:b] - ref)
-        assert np.all(err <= TOL_COMP * scale + 1e-9), (r, (err / (scale + 1e-30)).max())
-        worst = max(worst, float((err / (scale + 1e-9)).max()))
+        assert np.all(err <= bar + 1e-12), (r, (err / bar).max())
+        worst = max(worst, float((err / bar).max()))
         n_cmp += 1
-    print("per-sample compositing backward %s eps=%g dtype %d: %d rays compared, %d stopped early, worst %.2e"
+    print("per-sample compositing backward %s eps=%g dtype %d: %d rays compared, %d stopped early, worst "
+          "error / bar %.2e"
           % (cfg.name, eps, dtype, n_cmp, n_stop, worst))
     if eps > 0:
         assert n_stop > 0
