@@ -287,6 +287,26 @@ int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* ml
                   const amnerf_rays* rays, const amnerf_render_params* params,
                   amnerf_render_out* out, void* stream);
 
+/* Allocation-free render, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): amnerf_render with
+ * the same arguments and results (bit-identical), whose workspace is a static array of
+ * amnerf_render_static_capacity() bytes (64 MiB) on each GPU, set up when the first context
+ * on that GPU is created and held until the process ends; the call itself allocates nothing
+ * and never waits on the host.  The whole call must fit one pass and that workspace: about
+ * 20 + 40 * min(s_max, n_leaves) + 28 * s_max bytes per ray (7 500 rays at s_max 128 with
+ * 512 leaves); larger calls fail with AMNERF_ECAPACITY and the bytes they need, before any
+ * work is enqueued.  No proposal or occupancy grid (AMNERF_EINVAL: their buffers are sized
+ * from a count measured on the host).  Every call on a GPU shares that GPU's array and
+ * overwrites it, so calls that overlap on one GPU race: a caller with several streams or
+ * contexts on one GPU must order them.  The render's intermediate arrays cannot be
+ * inspected or differentiated afterwards (AMNERF_ESTATE); its statistics can be read. */
+int amnerf_render_static(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
+                         const amnerf_rays* rays, const amnerf_render_params* params,
+                         amnerf_render_out* out, void* stream);
+
+/* Bytes of the static workspace of amnerf_render_static on each GPU. */
+size_t amnerf_render_static_capacity(void);
+
 typedef struct {
   int64_t n_rays;
   int64_t n_intervals;    /* leaf intervals that received samples */

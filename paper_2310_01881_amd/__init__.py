@@ -43,7 +43,8 @@ EXPORTS = [
     "amnerf_render_stats_get", "amnerf_render_inspect", "amnerf_ctx_set_timing",
     "amnerf_timing_collect", "amnerf_render_backward", "amnerf_adam_step", "amnerf_train_step",
     "amnerf_prop_param_count", "amnerf_prop_packed_bytes", "amnerf_prop_pack", "amnerf_propose",
-    "amnerf_error_stats", "amnerf_render_backward_inspect",
+    "amnerf_error_stats", "amnerf_render_backward_inspect", "amnerf_render_static",
+    "amnerf_render_static_capacity",
 ]
 AMNERF_PROPOSE_INFER = 0
 AMNERF_PROPOSE_TRAIN = 1
@@ -159,6 +160,8 @@ def _load():
     lib.amnerf_mlp_pack.argtypes = [P, C.POINTER(amnerf_mlp_shape), C.c_int32, C.c_int32, P, P, P]
     lib.amnerf_render.argtypes = [P, P, C.POINTER(amnerf_mlp), C.POINTER(amnerf_rays),
                                   C.POINTER(amnerf_render_params), C.POINTER(amnerf_render_out), P]
+    lib.amnerf_render_static.argtypes = lib.amnerf_render.argtypes
+    lib.amnerf_render_static_capacity.restype = C.c_size_t
     lib.amnerf_render_stats_get.argtypes = [P, C.POINTER(amnerf_render_stats)]
     lib.amnerf_render_inspect.argtypes = [P, C.POINTER(amnerf_inspect), P]
     lib.amnerf_ctx_set_timing.argtypes = [P, C.c_int]
@@ -305,6 +308,20 @@ def amnerf_render(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, s_max: int, rgb_dev,
     out = amnerf_render_out(_ptr(rgb_dev), _ptr(depth_dev), _ptr(opacity_dev), _ptr(weights_dev))
     _check(_lib.amnerf_render(ctx, tree, C.byref(mlp), C.byref(rays), C.byref(prm), C.byref(out),
                               _stream(stream)))
+
+
+def amnerf_render_static(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, s_max: int, rgb_dev, depth_dev=None,
+                         opacity_dev=None, weights_dev=None, ert_eps: float = 1e-4, jitter: bool = False,
+                         seed: int = 0, stream=None, hcheck_footprint: float = 0.0):
+    rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]) if o_dev is not None else 0)
+    prm = amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed, None, hcheck_footprint, None)
+    out = amnerf_render_out(_ptr(rgb_dev), _ptr(depth_dev), _ptr(opacity_dev), _ptr(weights_dev))
+    _check(_lib.amnerf_render_static(ctx, tree, C.byref(mlp), C.byref(rays), C.byref(prm), C.byref(out),
+                                     _stream(stream)))
+
+
+def amnerf_render_static_capacity() -> int:
+    return int(_lib.amnerf_render_static_capacity())
 
 
 def amnerf_render_stats_get(ctx) -> dict:

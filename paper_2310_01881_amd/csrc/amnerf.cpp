@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <queue>
 #include <string>
@@ -39,6 +40,40 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr uint64_t kChunkSamples = 1ull << 28;   // worst-case samples of one render pass
 
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// static workspace of the allocation-free render (amnerf_render_static)
+// ---------------------------------------------------------------------------------------
+// One array per GPU the library runs on, held until the process ends.  In host code the
+// array's name is only a stand-in: its device address on each device is taken once, at
+// context creation with that device current, and only that address is ever used.
+static constexpr size_t kStaticBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current); once per device.
+int static_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return AMNERF_OK;   // static renders unavailable there
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_ptr[device]) return AMNERF_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(AMNERF_EDEVICE, "static workspace address on device %d: %s", device, hipGetErrorString(e));
+  g_static_ptr[device] = ptr;
+  return AMNERF_OK;
+}
+
+void* static_workspace(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  return g_static_ptr[device];
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
@@ -80,6 +115,7 @@ struct amnerf_ctx {
   float *smp_out = nullptr, *srec_t = nullptr;
   uint32_t* ray_used = nullptr;   // samples composited per ray (the early-termination count)
   bool last_uses_arena3 = false;  // the last render's intervals live in the third arena
+  bool last_static = false;       // the last render ran in the device's static workspace
   const uint64_t* last_mask = nullptr;   // kept plain slots per ray (proposal or empty-space renders)
   // last backward: per-sample pre-activation gradients (second arena), for inspection
   bool have_backward = false;
@@ -148,6 +184,11 @@ extern "C" int amnerf_ctx_create(int device, size_t workspace_cap, amnerf_ctx** 
   if (!c) return fail(AMNERF_ENOMEM, "amnerf_ctx_create: host allocation");
   c->device = device;
   c->cap = workspace_cap;
+  int rc = static_setup(device);
+  if (rc) {
+    delete c;
+    return rc;
+  }
   hipError_t e = hipMalloc((void**)&c->counts, sizeof(ChunkCounts));
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->counts_host, sizeof(ChunkCounts), hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -827,9 +868,13 @@ static int check_proposal(const amnerf_render_params* p) {
   return AMNERF_OK;
 }
 
-extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
-                             const amnerf_rays* rays, const amnerf_render_params* p,
-                             amnerf_render_out* out, void* stream) {
+// The render pipeline.  static_ws == nullptr: the workspace is the context's arenas, grown
+// on demand.  Otherwise it is the static_bytes of static_ws (the allocation-free entry
+// point): the call must then fit one pass and that workspace, and runs no proposal or
+// empty-space selection (their buffers are sized on the host from a measured count).
+static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
+                       const amnerf_rays* rays, const amnerf_render_params* p,
+                       amnerf_render_out* out, void* stream, char* static_ws, size_t static_bytes) {
   if (!ctx || !tree || !mlp || !rays || !p || !out) return fail(AMNERF_EINVAL, "amnerf_render: null argument");
   MlpGeom g;
   int rc = check_geom(&mlp->shape, mlp->dtype, &g, "amnerf_render");
@@ -882,15 +927,25 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   SortPlan sp = make_sort_plan(niv_max, L);
   Work w0, w1;
   size_t need = carve(nullptr, chunk, niv_max, ns_max, sp, w0);
-  rc = ensure_arena(ctx, need);
-  if (rc) return rc;
-  carve((char*)ctx->arena, chunk, niv_max, ns_max, sp, w0);
+  if (static_ws) {
+    if ((uint64_t)R > chunk)
+      return fail(AMNERF_ECAPACITY, "amnerf_render_static: %lld rays exceed one pass (%llu at s_max %d)",
+                  (long long)R, (unsigned long long)chunk, p->s_max);
+    if (need > static_bytes)
+      return fail(AMNERF_ECAPACITY, "amnerf_render_static: the call needs %zu bytes of workspace, the static "
+                  "workspace holds %zu", need, static_bytes);
+    carve(static_ws, chunk, niv_max, ns_max, sp, w0);
+  } else {
+    rc = ensure_arena(ctx, need);
+    if (rc) return rc;
+    carve((char*)ctx->arena, chunk, niv_max, ns_max, sp, w0);
+  }
   // More than one chunk (and no per-sample weights, whose offsets need the chunks in
   // order): odd chunks run on a second lane -- its own stream, workspace and counters --
   // so one chunk's latency-bound stages overlap the other's matrix-core stage.  The lane
   // waits for the caller's stream on entry and the caller's stream waits for the lane on
   // exit, so the call stays asynchronous on `stream`.
-  const bool pipe = (uint64_t)R > chunk && !out->weights_dev;
+  const bool pipe = (uint64_t)R > chunk && !out->weights_dev && !static_ws;
   if (pipe) {
     rc = lane_prepare(ctx, need);
     if (rc) return rc;
@@ -1026,9 +1081,30 @@ extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amn
   ctx->last_params.occupancy = nullptr;
   ctx->last_ess = occ != nullptr;
   ctx->last_o = rays->o_dev;
+  ctx->last_static = static_ws != nullptr;
   ctx->last_mask = sel_mask;
   return AMNERF_OK;
 }
+
+extern "C" int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
+                             const amnerf_rays* rays, const amnerf_render_params* p,
+                             amnerf_render_out* out, void* stream) {
+  return render_impl(ctx, tree, mlp, rays, p, out, stream, nullptr, 0);
+}
+
+extern "C" int amnerf_render_static(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
+                                    const amnerf_rays* rays, const amnerf_render_params* p,
+                                    amnerf_render_out* out, void* stream) {
+  if (!ctx || !p) return fail(AMNERF_EINVAL, "amnerf_render_static: null argument");
+  if (p->proposal || p->occupancy)
+    return fail(AMNERF_EINVAL, "amnerf_render_static: proposal and empty-space renders size their buffers on the host "
+                "(use amnerf_render)");
+  char* ws = (char*)static_workspace(ctx->device);
+  if (!ws) return fail(AMNERF_ESTATE, "amnerf_render_static: no static workspace on device %d", ctx->device);
+  return render_impl(ctx, tree, mlp, rays, p, out, stream, ws, kStaticBytes);
+}
+
+extern "C" size_t amnerf_render_static_capacity(void) { return kStaticBytes; }
 
 static int read_counts(amnerf_ctx* ctx) {
   HIP_TRY(hipSetDevice(ctx->device));
@@ -1059,6 +1135,8 @@ extern "C" int amnerf_render_stats_get(amnerf_ctx* ctx, amnerf_render_stats* out
 extern "C" int amnerf_render_inspect(amnerf_ctx* ctx, const amnerf_inspect* o, void* stream) {
   if (!ctx || !o) return fail(AMNERF_EINVAL, "amnerf_render_inspect: null argument");
   if (!ctx->have_render) return fail(AMNERF_ESTATE, "amnerf_render_inspect: no render yet");
+  if (ctx->last_static)
+    return fail(AMNERF_ESTATE, "amnerf_render_inspect: the last render ran in the shared static workspace");
   if (ctx->last_chunks != 1) return fail(AMNERF_ESTATE, "amnerf_render_inspect: last render ran in %lld chunks", (long long)ctx->last_chunks);
   int rc = read_counts(ctx);
   if (rc) return rc;
@@ -1140,6 +1218,8 @@ int backward_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* ml
     return fail(AMNERF_ESTATE, "amnerf_render_backward: the last render on this context used other inputs");
   if (ctx->last_chunks != 1) return fail(AMNERF_ESTATE, "amnerf_render_backward: the last render ran in %lld chunks",
                                          (long long)ctx->last_chunks);
+  if (ctx->last_static)
+    return fail(AMNERF_ESTATE, "amnerf_render_backward: the last render ran in the shared static workspace");
   if (!grad || (rays->n_rays > 0 && !g_rgb)) return fail(AMNERF_EINVAL, "amnerf_render_backward: null gradient pointer");
   if (ctx->last_ess)
     return fail(AMNERF_ESTATE, "amnerf_render_backward: the last render skipped empty space (not differentiated)");

@@ -19,9 +19,7 @@
 //   FP8  : the BF16 kernel; the leaf's e4m3 weights are widened to bf16 (times the layer's
 //          scale) while they are staged into LDS, so the block in memory is half the size.
 #include <algorithm>
-#include <map>
 #include <mutex>
-#include <tuple>
 
 #include "internal.hpp"
 #include "devcommon.hpp"
@@ -506,19 +504,27 @@ hipError_t launch_typed(const Layout& L, const void* packed, uint32_t n_leaves, 
 }  // namespace
 
 hipError_t persistent_grid(const void* kern, int threads, uint32_t lds, int* grid) {
+  // a fixed table (no heap allocation on this path); when full, grids are recomputed
+  struct Entry {
+    const void* kern;
+    int dev;
+    uint32_t lds;
+    int grid;
+  };
+  constexpr int kEntries = 128;
   static std::mutex mu;
-  static std::map<std::tuple<const void*, int, uint32_t>, int> cache;
+  static Entry table[kEntries];
+  static int used = 0;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  const auto key = std::make_tuple(kern, dev, lds);
   {
     std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-      *grid = it->second;
-      return hipSuccess;
-    }
+    for (int i = 0; i < used; ++i)
+      if (table[i].kern == kern && table[i].dev == dev && table[i].lds == lds) {
+        *grid = table[i].grid;
+        return hipSuccess;
+      }
   }
   int ncu = 0, per = 0;
   e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -527,7 +533,7 @@ hipError_t persistent_grid(const void* kern, int threads, uint32_t lds, int* gri
   if (e != hipSuccess) return e;
   *grid = ncu * per;
   std::lock_guard<std::mutex> lk(mu);
-  cache[key] = *grid;
+  if (used < kEntries) table[used++] = {kern, dev, lds, *grid};
   return hipSuccess;
 }
 
