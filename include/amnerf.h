@@ -215,6 +215,17 @@ typedef struct {
 
 /* ---- render (Section 3.5, Algorithm 1; Section 3.1) ----------------------------------- */
 #define AMNERF_JITTER 1u        /* stratified jitter instead of interval-centred samples */
+#define AMNERF_ERT_ROUNDS 2u    /* early termination in rounds (Section 4.1): the leaf MLPs
+                                   evaluate each ray's samples 64 at a time, front to back,
+                                   window k of every ray in round k, and a ray that terminated
+                                   in an earlier window has no samples evaluated after it.  The
+                                   outputs are bit-identical to a single-pass render (which
+                                   evaluates every sample and composites up to the stop); only
+                                   the evaluated sample count (stats n_samples) drops.  Needs
+                                   about 24 more bytes of workspace per worst-case sample; with
+                                   s_max <= 64 there is one window and the flag changes nothing.
+                                   The stage timing then counts the rounds' selection and all
+                                   but the last round's compositing as MLP time */
 
 /* Learned proposal used by a render (see amnerf_propose below). */
 typedef struct {
@@ -260,10 +271,10 @@ typedef struct {
   float* rgb_dev;         /* device float32[n_rays][3] (background 0) */
   float* depth_dev;       /* device float32[n_rays]: sum of w_j t_j; may be NULL */
   float* opacity_dev;     /* device float32[n_rays]: sum of w_j; may be NULL */
-  float* weights_dev;     /* device float32[n_samples] per-sample weights in ray-major
-                             sample order, or NULL; its size is only known after the
-                             render (amnerf_render_stats_get), so a caller passes a buffer
-                             of n_rays * s_max floats */
+  float* weights_dev;     /* device float32[n_placed_samples] per-sample weights in
+                             ray-major sample order, or NULL; its size is only known after
+                             the render (amnerf_render_stats_get), so a caller passes a
+                             buffer of n_rays * s_max floats */
 } amnerf_render_out;
 
 /* Renders `rays`.  Per ray r: m intervals (t0_k, t1_k, leaf_k) of the leaves the ray
@@ -310,7 +321,8 @@ size_t amnerf_render_static_capacity(void);
 typedef struct {
   int64_t n_rays;
   int64_t n_intervals;    /* leaf intervals that received samples */
-  int64_t n_samples;      /* samples evaluated by the MLPs */
+  int64_t n_samples;      /* samples evaluated by the MLPs (fewer than the samples placed
+                             when AMNERF_ERT_ROUNDS skipped samples past termination) */
   int64_t n_tiles;        /* MLP work tiles of the last chunk */
   int64_t n_chunks;
   int64_t n_nonfinite;    /* rays whose rgb, depth or opacity is not finite */
@@ -322,6 +334,9 @@ typedef struct {
   int64_t n_composited;   /* samples composited before early termination (the stop sample
                              included); n_samples - n_composited were evaluated by the MLPs
                              but lie past the termination point */
+  int64_t n_placed_samples; /* samples placed along the rays (the length of the per-sample
+                             arrays: weights_dev, inspect's perm and sample_out); equals
+                             n_samples unless AMNERF_ERT_ROUNDS skipped some */
 } amnerf_render_stats;
 
 /* Waits for the last render's stream and reports its totals. */

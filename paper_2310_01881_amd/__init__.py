@@ -29,6 +29,7 @@ AMNERF_FP8 = 2
 AMNERF_SPLIT_MEDIAN = 0
 AMNERF_SPLIT_MIDDLE = 1
 AMNERF_JITTER = 1
+AMNERF_ERT_ROUNDS = 2
 AMNERF_MAX_GRID = 512
 AMNERF_MAX_DEPTH = 16
 AMNERF_MAX_LEAVES = 4096
@@ -99,7 +100,7 @@ class amnerf_render_stats(C.Structure):
     _fields_ = [("n_rays", C.c_int64), ("n_intervals", C.c_int64), ("n_samples", C.c_int64),
                 ("n_tiles", C.c_int64), ("n_chunks", C.c_int64), ("n_nonfinite", C.c_int64),
                 ("n_fallback", C.c_int64), ("n_plain_samples", C.c_int64), ("n_unreached", C.c_int64),
-                ("n_composited", C.c_int64)]
+                ("n_composited", C.c_int64), ("n_placed_samples", C.c_int64)]
 
 
 class amnerf_inspect(C.Structure):

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libamnerf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["amnerf.cpp", "trav.hip", "scan.hip", "sort.hip", "mlp.hip", "mlp_bwd.hip", "comp.hip", "train.hip",
-           "prop.hip", "err.hip", "ess.hip"]
+           "prop.hip", "err.hip", "ess.hip", "ert.hip"]
 # Packed fp32 arithmetic is disabled for all device code.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

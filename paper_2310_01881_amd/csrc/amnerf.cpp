@@ -792,9 +792,14 @@ struct Work {
   uint32_t *srec_ray, *perm;
   float *srec_t, *smp_out;
   uint32_t* ray_used;
+  // early termination in rounds: selection flags and their scan, compacted sample records,
+  // the compacted buckets' offsets, and each ray's state between windows
+  uint32_t *r_flags, *r_pos, *r_tmp, *c_ray, *c_perm, *c_boff, *c_toff;
+  float* c_t;
+  CompCarry* carry;
 };
 
-size_t carve(char* base, uint64_t nr, uint64_t niv, uint64_t ns, const SortPlan& sp, Work& w) {
+size_t carve(char* base, uint64_t nr, uint64_t niv, uint64_t ns, const SortPlan& sp, Work& w, bool rounds) {
   Carve c{base};
   uint64_t scan_n = std::max<uint64_t>({nr, niv, (uint64_t)sp.n_leaves * sp.nseg_max});
   w.cnt_iv = c.take<uint32_t>(nr);
@@ -819,6 +824,16 @@ size_t carve(char* base, uint64_t nr, uint64_t niv, uint64_t ns, const SortPlan&
   w.perm = c.take<uint32_t>(ns);
   w.smp_out = c.take<float>(4 * ns);
   w.ray_used = c.take<uint32_t>(nr);
+  const uint64_t nsr = rounds ? ns : 0, nrr = rounds ? nr : 0, lr = rounds ? sp.n_leaves + 1 : 0;
+  w.r_flags = c.take<uint32_t>(nsr + 1);
+  w.r_pos = c.take<uint32_t>(nsr + 1);
+  w.r_tmp = c.take<uint32_t>(rounds ? scan_tmp_words(ns) : 0);
+  w.c_ray = c.take<uint32_t>(nsr);
+  w.c_t = c.take<float>(nsr);
+  w.c_perm = c.take<uint32_t>(nsr);
+  w.c_boff = c.take<uint32_t>(lr);
+  w.c_toff = c.take<uint32_t>(lr);
+  w.carry = c.take<CompCarry>(nrr);
   return c.off + 256;
 }
 
@@ -926,7 +941,9 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
   const uint64_t niv_max = chunk * iv_per_ray, ns_max = chunk * (uint64_t)p->s_max;
   SortPlan sp = make_sort_plan(niv_max, L);
   Work w0, w1;
-  size_t need = carve(nullptr, chunk, niv_max, ns_max, sp, w0);
+  // early termination in rounds of 64-sample windows (a single window needs no rounds)
+  const bool rounds = (p->flags & AMNERF_ERT_ROUNDS) && p->s_max > 64;
+  size_t need = carve(nullptr, chunk, niv_max, ns_max, sp, w0, rounds);
   if (static_ws) {
     if ((uint64_t)R > chunk)
       return fail(AMNERF_ECAPACITY, "amnerf_render_static: %lld rays exceed one pass (%llu at s_max %d)",
@@ -934,11 +951,11 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
     if (need > static_bytes)
       return fail(AMNERF_ECAPACITY, "amnerf_render_static: the call needs %zu bytes of workspace, the static "
                   "workspace holds %zu", need, static_bytes);
-    carve(static_ws, chunk, niv_max, ns_max, sp, w0);
+    carve(static_ws, chunk, niv_max, ns_max, sp, w0, rounds);
   } else {
     rc = ensure_arena(ctx, need);
     if (rc) return rc;
-    carve((char*)ctx->arena, chunk, niv_max, ns_max, sp, w0);
+    carve((char*)ctx->arena, chunk, niv_max, ns_max, sp, w0, rounds);
   }
   // More than one chunk (and no per-sample weights, whose offsets need the chunks in
   // order): odd chunks run on a second lane -- its own stream, workspace and counters --
@@ -949,7 +966,7 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
   if (pipe) {
     rc = lane_prepare(ctx, need);
     if (rc) return rc;
-    carve((char*)ctx->lane.arena, chunk, niv_max, ns_max, sp, w1);
+    carve((char*)ctx->lane.arena, chunk, niv_max, ns_max, sp, w1, rounds);
   }
   HIP_TRY(launch_counts_reset(ctx->counts, st));
   if (pipe) {
@@ -1043,14 +1060,35 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
     HIP_TRY(mark(3));
     HIP_TRY(launch_expand(sidx, ssb, use, r0, jitter, p->jitter_seed, w.srec_ray, w.srec_t, w.perm, cs));
     HIP_TRY(mark(4));
-    HIP_TRY(launch_mlp(g, mlp->packed_dev, L, w.bucket_off, w.tile_off, cc, w.srec_ray, w.srec_t, w.perm,
-                       rays->o_dev, rays->d_dev, R, r0, w.smp_out, cs));
-    HIP_TRY(mark(5));
-    HIP_TRY(launch_composite(nr, use, w.smp_out, r0, jitter, p->jitter_seed, p->ert_eps, out->rgb_dev, out->depth_dev,
-                             out->opacity_dev, out->weights_dev, w.ray_used, cc, cs));
+    if (!rounds) {
+      HIP_TRY(launch_mlp(g, mlp->packed_dev, L, w.bucket_off, w.tile_off, cc, w.srec_ray, w.srec_t, w.perm,
+                         rays->o_dev, rays->d_dev, R, r0, w.smp_out, cs));
+      HIP_TRY(mark(5));
+      HIP_TRY(launch_composite(nr, use, w.smp_out, r0, jitter, p->jitter_seed, p->ert_eps, out->rgb_dev,
+                               out->depth_dev, out->opacity_dev, out->weights_dev, w.ray_used, cc, cs));
+    } else {
+      // round k: the samples of window k of the rays still marching, compacted in sorted
+      // order, through the leaf MLPs, then composited from the state of the earlier windows
+      // (the stage timing counts every round but the last one's compositing as MLP work)
+      const uint32_t n_rounds = (uint32_t)(p->s_max + 63) / 64;
+      for (uint32_t k = 0; k < n_rounds; ++k) {
+        HIP_TRY(launch_round_flags(w.perm, w.srec_ray, use.smp_off, w.carry, cc, k, (uint32_t)ns_max, w.r_flags, cs));
+        HIP_TRY(launch_scan_u32(w.r_flags, w.r_pos, ns_max, &cc->n_smp, w.r_tmp, cs));
+        HIP_TRY(launch_round_compact(w.r_flags, w.r_pos, w.srec_ray, w.srec_t, w.perm, cc, (uint32_t)ns_max, w.c_ray,
+                                     w.c_t, w.c_perm, cs));
+        HIP_TRY(launch_round_tiles(w.bucket_off, w.r_pos, L, w.c_boff, w.c_toff, cc, cs));
+        HIP_TRY(launch_mlp(g, mlp->packed_dev, L, w.c_boff, w.c_toff, cc, w.c_ray, w.c_t, w.c_perm, rays->o_dev,
+                           rays->d_dev, R, r0, w.smp_out, cs));
+        if (k + 1 == n_rounds) HIP_TRY(mark(5));
+        HIP_TRY(launch_composite_round(nr, use, w.smp_out, r0, jitter, p->jitter_seed, p->ert_eps, out->rgb_dev,
+                                       out->depth_dev, out->opacity_dev, out->weights_dev, w.ray_used, cc, w.carry,
+                                       k, cs));
+      }
+      HIP_TRY(launch_sum_used(nr, w.ray_used, cc, cs));
+    }
     HIP_TRY(mark(6));
     if (ev) ev->pending = true;
-    HIP_TRY(launch_chunk_finish(cc, use.smp_off + nr, use.n_iv_dev, w.smp_off + nr, cs));
+    HIP_TRY(launch_chunk_finish(cc, use.smp_off + nr, use.n_iv_dev, w.smp_off + nr, rounds ? 1 : 0, cs));
   }
   if (pipe) {
     HIP_TRY(hipEventRecord(ctx->lane.join, ctx->lane.stream));
@@ -1121,7 +1159,7 @@ extern "C" int amnerf_render_stats_get(amnerf_ctx* ctx, amnerf_render_stats* out
   const ChunkCounts& c = *ctx->counts_host;
   out->n_rays = ctx->last_rays;
   out->n_intervals = (int64_t)c.iv_global;
-  out->n_samples = (int64_t)c.smp_global;
+  out->n_samples = (int64_t)c.evaluated;
   out->n_tiles = c.n_tiles;
   out->n_chunks = ctx->last_chunks;
   out->n_nonfinite = (int64_t)c.nonfinite;
@@ -1129,6 +1167,7 @@ extern "C" int amnerf_render_stats_get(amnerf_ctx* ctx, amnerf_render_stats* out
   out->n_plain_samples = (int64_t)c.plain_smp;
   out->n_unreached = (int64_t)c.unreached;
   out->n_composited = (int64_t)c.composited;
+  out->n_placed_samples = (int64_t)c.smp_global;
   return AMNERF_OK;
 }
 

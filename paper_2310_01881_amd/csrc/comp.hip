@@ -85,21 +85,43 @@ __device__ __forceinline__ float wave_sum(float v) { return lane_value(wave_scan
 // Early termination: the first lane whose T_{j+1} < eps keeps its sample and later lanes
 // (and steps) contribute nothing.  T_j is the neighbouring lane's T_{j+1} (the exclusive
 // sum of lane j is the inclusive sum of lane j - 1), so one exponential per sample serves
-// both.  Lane j finds its interval by binary search over the intervals' first-sample
-// indices.
+// both.  Each step's weighted sums are reduced across the wave and added to the ray's
+// running totals, so the state carried from one step to the next is a handful of scalars.
+// Lane j finds its interval by binary search over the intervals' first-sample indices.
+//
+// ROUND: one 64-sample window (step `round`) of every ray that is still marching, the state
+// of the earlier windows read from and written back to `carry`; a ray's outputs are written
+// when it terminates or its last window is done.  The arithmetic of each step is the same
+// as in the single pass, so a render in rounds is bit-identical to one in a single pass.
 constexpr uint32_t kStage = 256;   // intervals of a ray searched in LDS (more: in memory)
+constexpr uint32_t kDone = 0x80000000u;
 
+template <bool ROUND>
 __global__ __launch_bounds__(kThreads) void k_composite(
     uint32_t nr, IvSet iv, const float* __restrict__ smp_out, int64_t r0, int jitter,
     uint64_t seed, float eps, float* __restrict__ rgb, float* __restrict__ depth,
     float* __restrict__ opac, float* __restrict__ weights, uint32_t* __restrict__ ray_used,
-    ChunkCounts* __restrict__ counts) {
+    ChunkCounts* __restrict__ counts, CompCarry* __restrict__ carry_st, uint32_t round) {
   __shared__ uint32_t sbase[kThreads / 64][kStage];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t r = blockIdx.x * (kThreads / 64) + wave;
   if (r >= nr) return;
   const uint32_t i0 = iv.iv_off[r], i1 = iv.iv_off[r + 1];
   const uint32_t s0 = iv.smp_off[r], ns = iv.smp_off[r + 1] - s0;
+  uint32_t sb = 0, se = ns;                    // this launch's samples of the ray
+  DF S = {0.f, 0.f};                           // sum of tau before sample sb
+  float tot[5] = {0.f, 0.f, 0.f, 0.f, 0.f};    // rgb, depth, opacity so far
+  if (ROUND) {
+    sb = 64u * round;
+    if (sb >= ns && !(ns == 0 && round == 0)) return;   // finished in an earlier window
+    if (round > 0) {
+      const CompCarry c = carry_st[r];
+      if (c.state & kDone) return;
+      S = {c.s_hi, c.s_lo};
+      tot[0] = c.cr; tot[1] = c.cg; tot[2] = c.cb; tot[3] = c.dep; tot[4] = c.acc;
+    }
+    se = sb + 64u < ns ? sb + 64u : ns;
+  }
   // the ray's interval start samples (relative to s0), searched in LDS
   const uint32_t m = i1 - i0;
   const bool staged = m <= kStage;
@@ -110,75 +132,76 @@ __global__ __launch_bounds__(kThreads) void k_composite(
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   const uint64_t wbase = counts->smp_global + s0;
-  float cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f, acc = 0.f;
   uint32_t used = ns;   // samples composited: up to and including the stop sample
-  if (ns > 0) {
-    DF carry = {0.f, 0.f};
-    bool done = false;
-    for (uint32_t base = 0; base < ns; base += 64) {
-      const uint32_t j = base + lane;
-      const bool valid = !done && j < ns;
-      float tau = 0.f, sig_c[3] = {0.f, 0.f, 0.f}, t = 0.f;
-      if (valid) {
-        uint32_t i;
-        if (staged) {
-          uint32_t lo = 0, hi = m;
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (sbase[wave][mid] <= j) lo = mid; else hi = mid;
-          }
-          i = i0 + lo;
-        } else {
-          i = find_interval(iv.base, i0, i1, s0 + j);
+  bool done = false;
+  uint32_t next = sb;   // first sample after the last step processed
+  for (uint32_t base = sb; base < se; base += 64) {
+    next = base + 64u;
+    const uint32_t j = base + lane;
+    const bool valid = !done && j < ns;
+    float tau = 0.f, sig_c[3] = {0.f, 0.f, 0.f}, t = 0.f;
+    if (valid) {
+      uint32_t i;
+      if (staged) {
+        uint32_t lo = 0, hi = m;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (sbase[wave][mid] <= j) lo = mid; else hi = mid;
         }
-        const uint32_t jj = s0 + j - iv.base[i];
-        const float4 z = *reinterpret_cast<const float4*>(smp_out + 4 * (uint64_t)(s0 + j));
-        const float delta = iv.dt[i] / (float)key_n(iv.key[i]);
-        const float u = stratum_u(jitter, seed, (uint64_t)(r0 + r), i - i0);
-        t = sample_t(iv.t0[i], delta, jj, u);
-        tau = softplusf(z.x) * delta;       // sigma = softplus, rgb = logistic
-        sig_c[0] = logisticf(z.y);
-        sig_c[1] = logisticf(z.z);
-        sig_c[2] = logisticf(z.w);
+        i = i0 + lo;
+      } else {
+        i = find_interval(iv.base, i0, i1, s0 + j);
       }
-      // inclusive compensated scan of tau across the wave; exclusive = shifted by one lane
-      const DF inc = df_scan_incl({tau, 0.f});
-      const DF Sn = df_add(carry, inc);
-      const float Tn = df_exp_neg(Sn);                        // T_{j+1}
-      const float Tsh = dpp_or_zero<0x138, 0xF>(Tn);          // wave_shr:1: lane j - 1's T_j
-      const float T = lane == 0 ? df_exp_neg(carry) : Tsh;
-      float w = valid ? T * one_minus_exp_neg(tau) : 0.f;
-      const bool stop = valid && eps > 0.f && Tn < eps;
-      const uint64_t stops = __ballot(stop);
-      if (stops) {
-        const int first = __ffsll((unsigned long long)stops) - 1;
-        if (lane > first) w = 0.f;
-        done = true;
-        used = base + (uint32_t)first + 1u;
-      }
-      cr = fmaf(w, sig_c[0], cr);
-      cg = fmaf(w, sig_c[1], cg);
-      cb = fmaf(w, sig_c[2], cb);
-      dep = fmaf(w, t, dep);
-      acc += w;
-      if (weights && j < ns) weights[wbase + j] = w;
-      carry = {lane_value(Sn.hi, 63), lane_value(Sn.lo, 63)};
-      if (done && !weights) break;
+      const uint32_t jj = s0 + j - iv.base[i];
+      const float4 z = *reinterpret_cast<const float4*>(smp_out + 4 * (uint64_t)(s0 + j));
+      const float delta = iv.dt[i] / (float)key_n(iv.key[i]);
+      const float u = stratum_u(jitter, seed, (uint64_t)(r0 + r), i - i0);
+      t = sample_t(iv.t0[i], delta, jj, u);
+      tau = softplusf(z.x) * delta;       // sigma = softplus, rgb = logistic
+      sig_c[0] = logisticf(z.y);
+      sig_c[1] = logisticf(z.z);
+      sig_c[2] = logisticf(z.w);
     }
-    cr = wave_sum(cr);
-    cg = wave_sum(cg);
-    cb = wave_sum(cb);
-    dep = wave_sum(dep);
-    acc = wave_sum(acc);
+    // inclusive compensated scan of tau across the wave; exclusive = shifted by one lane
+    const DF inc = df_scan_incl({tau, 0.f});
+    const DF Sn = df_add(S, inc);
+    const float Tn = df_exp_neg(Sn);                        // T_{j+1}
+    const float Tsh = dpp_or_zero<0x138, 0xF>(Tn);          // wave_shr:1: lane j - 1's T_j
+    const float T = lane == 0 ? df_exp_neg(S) : Tsh;
+    float w = valid ? T * one_minus_exp_neg(tau) : 0.f;
+    const bool stop = valid && eps > 0.f && Tn < eps;
+    const uint64_t stops = __ballot(stop);
+    if (stops) {
+      const int first = __ffsll((unsigned long long)stops) - 1;
+      if (lane > first) w = 0.f;
+      done = true;
+      used = base + (uint32_t)first + 1u;
+    }
+    tot[0] += wave_sum(w * sig_c[0]);
+    tot[1] += wave_sum(w * sig_c[1]);
+    tot[2] += wave_sum(w * sig_c[2]);
+    tot[3] += wave_sum(w * t);
+    tot[4] += wave_sum(w);
+    if (weights && j < ns) weights[wbase + j] = w;
+    S = {lane_value(Sn.hi, 63), lane_value(Sn.lo, 63)};
+    if (done) break;
+  }
+  // a ray that stopped has weight 0 on every later sample
+  if (weights && done)
+    for (uint32_t j = next + lane; j < ns; j += 64) weights[wbase + j] = 0.f;
+  if (ROUND && !done && se < ns) {
+    if (lane == 0) carry_st[r] = {S.hi, S.lo, tot[0], tot[1], tot[2], tot[3], tot[4], 0u};
+    return;
   }
   if (lane == 0) {
+    if (ROUND) carry_st[r].state = kDone;
     ray_used[r] = used;
-    rgb[3 * (uint64_t)(r0 + r) + 0] = cr;
-    rgb[3 * (uint64_t)(r0 + r) + 1] = cg;
-    rgb[3 * (uint64_t)(r0 + r) + 2] = cb;
-    if (depth) depth[r0 + r] = dep;
-    if (opac) opac[r0 + r] = acc;
-    if (!isfinite(cr) || !isfinite(cg) || !isfinite(cb) || !isfinite(dep) || !isfinite(acc))
+    rgb[3 * (uint64_t)(r0 + r) + 0] = tot[0];
+    rgb[3 * (uint64_t)(r0 + r) + 1] = tot[1];
+    rgb[3 * (uint64_t)(r0 + r) + 2] = tot[2];
+    if (depth) depth[r0 + r] = tot[3];
+    if (opac) opac[r0 + r] = tot[4];
+    if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(tot[2]) || !isfinite(tot[3]) || !isfinite(tot[4]))
       atomicAdd(reinterpret_cast<unsigned long long*>(&counts->nonfinite), 1ull);
   }
 }
@@ -203,8 +226,9 @@ __global__ __launch_bounds__(kThreads) void k_sum_used(uint32_t nr, const uint32
 
 // Records the chunk's totals for the host and advances the global sample base.
 __global__ void k_chunk_finish(ChunkCounts* counts, const uint32_t* smp_total, const uint32_t* iv_total,
-                               const uint32_t* plain_total) {
+                               const uint32_t* plain_total, int rounds) {
   if (threadIdx.x != 0) return;
+  if (!rounds) counts->evaluated += *smp_total;   // (in rounds: added by each round's selection)
   counts->smp_global += *smp_total;
   counts->iv_global += *iv_total;
   counts->plain_smp += *plain_total;
@@ -227,6 +251,7 @@ __global__ void k_counts_merge(ChunkCounts* a, const ChunkCounts* b) {
   a->plain_smp += b->plain_smp;
   a->unreached += b->unreached;
   a->composited += b->composited;
+  a->evaluated += b->evaluated;
 }
 
 __global__ void k_counts_reset(ChunkCounts* counts) {
@@ -244,18 +269,35 @@ hipError_t launch_composite(uint32_t nr, const IvSet& iv, const float* smp_out, 
   if (nr == 0) return hipSuccess;
   const uint32_t rays_per_block = kThreads / 64;
   uint32_t grid = (nr + rays_per_block - 1) / rays_per_block;
-  hipLaunchKernelGGL(k_composite, dim3(grid), dim3(kThreads), 0, st, nr, iv, smp_out, r0, jitter, seed,
-                     ert_eps, rgb, depth, opac, weights, ray_used, counts);
+  hipLaunchKernelGGL(k_composite<false>, dim3(grid), dim3(kThreads), 0, st, nr, iv, smp_out, r0, jitter, seed,
+                     ert_eps, rgb, depth, opac, weights, ray_used, counts, nullptr, 0u);
+  return launch_sum_used(nr, ray_used, counts, st);
+}
+
+hipError_t launch_composite_round(uint32_t nr, const IvSet& iv, const float* smp_out, int64_t r0, int jitter,
+                                  uint64_t seed, float ert_eps, float* rgb, float* depth, float* opac,
+                                  float* weights, uint32_t* ray_used, ChunkCounts* counts, CompCarry* carry,
+                                  uint32_t round, hipStream_t st) {
+  if (nr == 0) return hipSuccess;
+  const uint32_t rays_per_block = kThreads / 64;
+  uint32_t grid = (nr + rays_per_block - 1) / rays_per_block;
+  hipLaunchKernelGGL(k_composite<true>, dim3(grid), dim3(kThreads), 0, st, nr, iv, smp_out, r0, jitter, seed,
+                     ert_eps, rgb, depth, opac, weights, ray_used, counts, carry, round);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_used(uint32_t nr, const uint32_t* ray_used, ChunkCounts* counts, hipStream_t st) {
+  if (nr == 0) return hipSuccess;
   const uint32_t sgrid = std::min<uint32_t>(256u, (nr + 4 * kThreads - 1) / (4 * kThreads));
   hipLaunchKernelGGL(k_sum_used, dim3(sgrid), dim3(kThreads), 0, st, nr, ray_used, counts);
   return hipGetLastError();
 }
 
 hipError_t launch_chunk_finish(ChunkCounts* counts, const uint32_t* smp_off_total,
-                               const uint32_t* iv_off_total, const uint32_t* plain_smp_total,
+                               const uint32_t* iv_off_total, const uint32_t* plain_smp_total, int rounds,
                                hipStream_t st) {
   hipLaunchKernelGGL(k_chunk_finish, dim3(1), dim3(64), 0, st, counts, smp_off_total, iv_off_total,
-                     plain_smp_total);
+                     plain_smp_total, rounds);
   return hipGetLastError();
 }
 

@@ -37,6 +37,14 @@ struct ChunkCounts {
   uint64_t unreached;   // interval entries the emission walk did not reach (filled with
                         // zero-length slot-0 entries; 0 unless the two traversal passes disagree)
   uint64_t composited;  // samples composited before early termination (accumulated)
+  uint64_t evaluated;   // samples the leaf MLPs evaluated (accumulated)
+};
+
+// State of a ray between the windows of a render in rounds: the compensated sum of tau so
+// far, rgb, depth and opacity so far, and kDone once the ray's outputs are written.
+struct CompCarry {
+  float s_hi, s_lo, cr, cg, cb, dep, acc;
+  uint32_t state;
 };
 
 constexpr int kMlpTileRows = 256;       // rows of one MLP work tile (4 waves x 64)
@@ -155,6 +163,29 @@ hipError_t launch_composite(uint32_t nr, const IvSet& iv, const float* smp_out, 
                             int jitter, uint64_t seed, float ert_eps, float* rgb, float* depth,
                             float* opac, float* weights, uint32_t* ray_used, ChunkCounts* counts,
                             hipStream_t st);
+// One 64-sample window (`round`) of every ray still marching, continuing from `carry`;
+// ray_used and the outputs are written as rays finish.  counts->composited is added by
+// launch_sum_used once every round has run.
+hipError_t launch_composite_round(uint32_t nr, const IvSet& iv, const float* smp_out, int64_t r0, int jitter,
+                                  uint64_t seed, float ert_eps, float* rgb, float* depth, float* opac,
+                                  float* weights, uint32_t* ray_used, ChunkCounts* counts, CompCarry* carry,
+                                  uint32_t round, hipStream_t st);
+hipError_t launch_sum_used(uint32_t nr, const uint32_t* ray_used, ChunkCounts* counts, hipStream_t st);
+
+// ---- early termination in rounds (Section 4.1) -------------------------------------------
+// Round k selects, in sorted order, the samples of window k (sample index 64k .. 64k + 63 of
+// their ray) of the rays still marching (carry state not done; every ray in round 0):
+// flags[p] = 1 for each, then (after an exclusive scan into pos) their sample records are
+// compacted and each leaf's bucket and tile offsets recomputed over the compacted list
+// (counts->n_tiles, counts->evaluated).
+hipError_t launch_round_flags(const uint32_t* perm, const uint32_t* srec_ray, const uint32_t* smp_off,
+                              const CompCarry* carry, const ChunkCounts* counts, uint32_t round, uint32_t ns_cap,
+                              uint32_t* flags, hipStream_t st);
+hipError_t launch_round_compact(const uint32_t* flags, const uint32_t* pos, const uint32_t* srec_ray,
+                                const float* srec_t, const uint32_t* perm, const ChunkCounts* counts,
+                                uint32_t ns_cap, uint32_t* c_ray, float* c_t, uint32_t* c_perm, hipStream_t st);
+hipError_t launch_round_tiles(const uint32_t* bucket_off, const uint32_t* pos, uint32_t n_leaves,
+                              uint32_t* c_bucket_off, uint32_t* c_tile_off, ChunkCounts* counts, hipStream_t st);
 
 // ---- training ----------------------------------------------------------------------------
 bool mlp_bwd_supported(int n_hidden, int hidden);
@@ -208,7 +239,7 @@ hipError_t launch_counts_reset(ChunkCounts* counts, hipStream_t st);
 hipError_t launch_chunk_begin(ChunkCounts* counts, const uint32_t* iv_total, uint32_t seg, uint32_t n_leaves,
                               hipStream_t st);
 hipError_t launch_chunk_finish(ChunkCounts* counts, const uint32_t* smp_off_total,
-                               const uint32_t* iv_off_total, const uint32_t* plain_smp_total,
+                               const uint32_t* iv_off_total, const uint32_t* plain_smp_total, int rounds,
                                hipStream_t st);
 
 }  // namespace amn

@@ -24,7 +24,7 @@ TOL_DEPTH = 1e-5
 
 def inspect(ctx, R):
     st = am.amnerf_render_stats_get(ctx.h)
-    niv, ns = st["n_intervals"], st["n_samples"]
+    niv, ns = st["n_intervals"], st["n_placed_samples"]
     L = None
     dev = "cuda:0"
     b = {
@@ -47,7 +47,7 @@ def fetch_inspect(ctx, R, n_leaves):
     am.amnerf_render_inspect(ctx.h, **b)
     torch.cuda.synchronize()
     out = {k: v.cpu().numpy() for k, v in b.items()}
-    niv, ns = st["n_intervals"], st["n_samples"]
+    niv, ns = st["n_intervals"], st["n_placed_samples"]
     for k in ("iv_t0", "iv_dt", "iv_slot", "iv_n"):
         out[k] = out[k][:niv]
     out["perm"] = out["perm"][:ns].view(np.uint32)

@@ -62,7 +62,7 @@ def gpu_grad(scene, ctx, tree, mlp, master, o, d, s_max, eps, g_rgb, g_dep, g_op
     g = grad.cpu().numpy().astype(np.float64)
     if not sample_grad:
         return g
-    ns = st["n_samples"]
+    ns = st["n_placed_samples"]
     gs = torch.empty((max(ns, 1), 4), device="cuda:0")
     smp_off = torch.empty(R + 1, dtype=torch.int32, device="cuda:0")
     used = torch.empty(R, dtype=torch.int32, device="cuda:0")
