@@ -5,26 +5,31 @@ One step renders one 800x800 frame (640 000 rays) of the seeded 128^3-grid scene
 512-leaf KD tree and 4x64 per-leaf MLPs, at most 128 samples per ray, through the whole
 path: traversal -> (learned proposal) -> per-leaf samples -> sort by leaf -> grouped MLP
 -> compositing.  Rays of 8 held-out cameras are resident in HBM before the timed region;
-step k renders camera k mod 8.  Five paths are timed: plain float32, plain bfloat16,
+step k renders camera k mod 8.  Seven paths are timed: plain float32, plain bfloat16,
 bfloat16 with the learned proposal (bfloat16 inference, <= 48 samples per ray, fallback
-below 0.99 predicted mass), and float8 (e4m3) leaf weights without and with the proposal.
-The proposal is first trained (untimed) by the library's own kernels on plain-render
-targets from 200 seeded training cameras.  Each path is timed one frame at a time (with
+below 0.99 predicted mass), float8 (e4m3) leaf weights without and with the proposal, and
+plain float32 and bfloat16 with early termination in 64-sample rounds (terminated rays
+drop out before the leaf MLPs).  The proposal is first trained (untimed) by the library's
+own kernels on plain-render targets from 200 seeded training cameras.  Each path is timed
+one frame at a time (an event after every frame; the median frame is reported, with
 per-stage event timing), then with --inflight frames in flight (one library context per
-stream, frame k on stream k mod N; every frame is still rendered in full, and the last
-frame of each stream is checked bit-identical to the same camera rendered alone).
-`value` is the proposal path's samples/s (samples evaluated by the leaf MLPs) with frames
-in flight, and `ms_per_step` its ms/frame.  The oracle (float64, CPU) renders a bounded
-random subset of camera 0's rays: that gives the CPU baseline and the PSNR of each GPU
-path against the oracle.  The same scene is also rendered with a regular-subdivision
-tree (the ablation without the adaptive split) and with hierarchical sampling at three
-footprints, and a training step is timed.
+stream, frame k on stream k mod N; --windows windows of --steps frames, the median window
+reported; every frame is still rendered in full, and the last frame of each stream is
+checked bit-identical to the same camera rendered alone).  `value` is the proposal path's
+samples/s (samples evaluated by the leaf MLPs) with frames in flight, and `ms_per_step`
+its ms/frame.  The oracle (float64, CPU, on every host core the process is given)
+renders a bounded random subset of camera 0's rays: that gives the CPU baseline and the
+PSNR of each GPU path against the oracle.  The same scene is also rendered with a
+regular-subdivision tree (the ablation without the adaptive split) and with hierarchical
+sampling at three footprints, and a training step is timed (median step, per-stage
+events, the MLP backward's roofline, and the oracle's training step as its CPU baseline).
 
 A second, larger workload follows in the same run and is reported under `large_scene`
 (skip it with --no-large): 1920x1080 frames of a 256^3-grid scene with a 100:1 blob-density
 skew, a 4096-leaf tree, float8 (and bfloat16) leaf weights and S_max 192; one call renders
-30 held-out cameras, with and without a proposal trained on 200 other cameras, and with
-empty space skipped by an occupancy grid (--large-paths picks a subset of these paths).
+30 held-out cameras without a proposal (and with empty space skipped by an occupancy
+grid), and one call renders 50 held-out cameras (the same first 30, then 20 more) with a
+proposal trained on 200 other cameras (--large-paths picks a subset of these paths).
 """
 from __future__ import annotations
 
@@ -39,22 +44,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_SAMPLE_4x64 = 2 * (30 * 64 + 3 * 64 * 64 + 64 * 4)   # 28 928, unpadded
+# backward per sample: the forward again (activations are recomputed, not stored), the input
+# gradients of layers 1..4 (layer 0's input needs none) and every weight gradient
+FLOP_PER_SAMPLE_BWD_4x64 = FLOP_PER_SAMPLE_4x64 + 2 * (3 * 64 * 64 + 64 * 4) + FLOP_PER_SAMPLE_4x64   # 82 944
 PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
 
 
 HEADLINE_PSNR_DB = 45.0   # the headline path's quality bar against the oracle
+PROPOSAL_TEST_CAMERAS = 50   # held-out cameras of the large scene's proposal renders
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def cpu_threads():
+def host_cpus():
+    """Host cores this process may run on (what nproc prints)."""
     try:
-        n = len(os.sched_getaffinity(0))
+        return len(os.sched_getaffinity(0))
     except AttributeError:
-        n = os.cpu_count() or 1
-    return max(1, min(16, n))
+        return os.cpu_count() or 1
+
+
+def cpu_threads():
+    """Threads for the oracle: every host core of the process, unless OMP_NUM_THREADS gives the
+    process a smaller CPU share (then that share)."""
+    n = host_cpus()
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def median(xs):
+    xs = sorted(xs)
+    k = len(xs)
+    return 0.5 * (xs[(k - 1) // 2] + xs[k // 2])
 
 
 LARGE_PATHS = ("fp8", "fp8_prop", "bf16", "bf16_prop", "fp8_untrained_prop", "fp8_ess")
@@ -78,21 +103,27 @@ def large_scene(args, am, torch, np, synth, ctx):
     master = torch.from_numpy(W).to(dev)
     mlps = {k: am.Mlp(ctx, master, cfg.n_hidden, cfg.hidden, dt, L)
             for k, dt in (("fp8", am.AMNERF_FP8), ("bf16", am.AMNERF_BF16), ("f32", am.AMNERF_F32))}
+    # 50 held-out cameras: the proposal paths render all of them in one call; the paths
+    # without a proposal render the first 30 (the same seeds) in one call
     n_cams = cfg.n_cameras
-    cams = synth.make_cameras(n_cams, cfg.seed_cameras, cfg.width, cfg.height)
+    n_prop_cams = PROPOSAL_TEST_CAMERAS
+    cams = synth.make_cameras(n_prop_cams, cfg.seed_cameras, cfg.width, cfg.height)
     R1 = cfg.width * cfg.height
     R = R1 * n_cams
-    o_all = torch.empty((3, R), dtype=torch.float32, device=dev)
-    d_all = torch.empty((3, R), dtype=torch.float32, device=dev)
+    R50 = R1 * n_prop_cams
+    o50 = torch.empty((3, R50), dtype=torch.float32, device=dev)
+    d50 = torch.empty((3, R50), dtype=torch.float32, device=dev)
     for i, c in enumerate(cams):
         o, d = synth.camera_rays(c)
-        o_all[:, i * R1:(i + 1) * R1] = torch.from_numpy(o).to(dev)
-        d_all[:, i * R1:(i + 1) * R1] = torch.from_numpy(d).to(dev)
-    log("large scene %s: %d leaves, %d rays per call, set-up %.1f s" % (cfg.name, L, R, time.perf_counter() - t0))
+        o50[:, i * R1:(i + 1) * R1] = torch.from_numpy(o).to(dev)
+        d50[:, i * R1:(i + 1) * R1] = torch.from_numpy(d).to(dev)
+    o_all, d_all = o50[:, :R].contiguous(), d50[:, :R].contiguous()
+    log("large scene %s: %d leaves, %d rays per call (%d with a proposal), set-up %.1f s" % (
+        cfg.name, L, R, R50, time.perf_counter() - t0))
 
     wanted = [k for k in LARGE_PATHS if k in args.large_paths.split(",")]
     prop_training = None
-    desc = desc_untrained = None
+    prop = desc = desc_untrained = None
     if any(k.endswith("_prop") for k in wanted):
         # proposal trained on 200 other cameras (untimed)
         t0 = time.perf_counter()
@@ -128,48 +159,74 @@ def large_scene(args, am, torch, np, synth, ctx):
              "bf16_prop": ("bf16", desc, None), "fp8_untrained_prop": ("fp8", desc_untrained, None),
              "fp8_ess": ("fp8", None, occ)}
     paths = {k: paths[k] for k in wanted}
-    outs = {k: torch.empty((R, 3), dtype=torch.float32, device=dev) for k in paths}
 
-    def render(kind, rgb):
+    def cams_of(kind):
+        return n_prop_cams if kind.endswith("_prop") else n_cams
+    outs = {k: torch.empty((R1 * cams_of(k), 3), dtype=torch.float32, device=dev) for k in paths}
+
+    def render(kind, rgb, n_c=None):
         mk, pd, oc = paths[kind]
-        am.amnerf_render(ctx.h, tree.h, mlps[mk].desc, o_all, d_all, cfg.s_max, rgb, None, None, None, cfg.ert_eps,
+        o, d = (o50, d50) if (n_c or cams_of(kind)) == n_prop_cams else (o_all, d_all)
+        am.amnerf_render(ctx.h, tree.h, mlps[mk].desc, o, d, cfg.s_max, rgb, None, None, None, cfg.ert_eps,
                          proposal=pd, occupancy=oc)
 
     res = {}
     am.amnerf_ctx_set_timing(ctx.h, True)
     for kind in paths:
         rgb = outs[kind]
+        nc = cams_of(kind)
         render(kind, rgb)                                    # warm-up, and the sample counts
         st = am.amnerf_render_stats_get(ctx.h)
         am.amnerf_timing_collect(ctx.h)
         calls = args.large_calls if kind != "fp8_untrained_prop" else 1
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(calls):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(calls + 1)]
+        evs[0].record()
+        for c in range(calls):
             render(kind, rgb)
+            evs[c + 1].record()
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / calls
+        dt = 1e-3 * median([evs[c].elapsed_time(evs[c + 1]) for c in range(calls)])
         stage_ms, npass = am.amnerf_timing_collect(ctx.h)
         mlp_ms = stage_ms["mlp"] / calls
-        res[kind] = {"ms_per_frame": 1e3 * dt / n_cams, "ms_per_call": 1e3 * dt,
-                     "samples_per_s": st["n_samples"] / dt, "samples_per_frame": st["n_samples"] / n_cams,
-                     "samples_per_ray": st["n_samples"] / R, "fallback_fraction": st["n_fallback"] / R,
+        Rk = R1 * nc
+        tf = FLOP_PER_SAMPLE_4x64 * st["n_samples"] / (mlp_ms * 1e-3) / 1e12
+        res[kind] = {"ms_per_frame": 1e3 * dt / nc, "ms_per_call": 1e3 * dt, "cameras_per_call": nc,
+                     "samples_per_s": st["n_samples"] / dt, "samples_per_frame": st["n_samples"] / nc,
+                     "composited_samples_per_frame": st["n_composited"] / nc,
+                     "samples_per_ray": st["n_samples"] / Rk, "fallback_fraction": st["n_fallback"] / Rk,
                      "chunks_per_call": st["n_chunks"],
-                     "stage_ms_per_frame": {k: v / calls / n_cams for k, v in stage_ms.items()},
-                     "mlp_tflops": FLOP_PER_SAMPLE_4x64 * st["n_samples"] / (mlp_ms * 1e-3) / 1e12}
-        log("large %s: %.3f ms/frame, %.3e samples/s, %.1f samples/ray, fallback %.3f, stages %s" % (
-            kind, res[kind]["ms_per_frame"], res[kind]["samples_per_s"], res[kind]["samples_per_ray"],
-            res[kind]["fallback_fraction"], {k: round(v, 4) for k, v in res[kind]["stage_ms_per_frame"].items()}))
+                     "stage_ms_per_frame": {k: v / calls / nc for k, v in stage_ms.items()},
+                     "mlp_tflops": tf,
+                     "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                                  "frac": tf / PEAK_TFLOPS["bf16"], "traffic": None, "kernel": "k_mlp<64,bf16>"
+                                  + (" (e4m3 weights widened on chip)" if paths[kind][0] == "fp8" else ""),
+                                  "kernel_ms_per_call": mlp_ms}}
+        log("large %s: %.3f ms/frame (%d cameras per call, median of %d calls), %.3e samples/s, %.1f samples/ray, "
+            "fallback %.3f, MLP %.3f of peak, stages %s" % (
+                kind, res[kind]["ms_per_frame"], nc, calls, res[kind]["samples_per_s"], res[kind]["samples_per_ray"],
+                res[kind]["fallback_fraction"], tf / PEAK_TFLOPS["bf16"],
+                {k: round(v, 4) for k, v in res[kind]["stage_ms_per_frame"].items()}))
     am.amnerf_ctx_set_timing(ctx.h, False)
 
     # each proposal render judged by the plain render with the same leaf weights, every pixel
-    # of the 30 cameras (the outputs of the last timed call)
+    # of its cameras (the outputs of the last timed call; the plain render of the 50 cameras
+    # is made for this, untimed)
     psnr_prop_vs_plain = {}
+    plain50 = {}
     for kind, ref in (("fp8_prop", "fp8"), ("bf16_prop", "bf16"), ("fp8_untrained_prop", "fp8"), ("fp8_ess", "fp8")):
-        if kind not in outs or ref not in outs:
+        if kind not in outs or ref not in paths:
             continue
-        rep = am.amnerf_error_stats(ctx.h, outs[kind].view(-1), outs[ref].view(-1).double())
+        if cams_of(kind) == n_prop_cams:
+            if ref not in plain50:
+                plain50[ref] = torch.empty((R50, 3), dtype=torch.float32, device=dev)
+                render(ref, plain50[ref], n_prop_cams)
+            ref_rgb = plain50[ref]
+        else:
+            ref_rgb = outs[ref]
+        rep = am.amnerf_error_stats(ctx.h, outs[kind].view(-1), ref_rgb.view(-1).double())
         psnr_prop_vs_plain[kind] = rep["psnr"]
+    del plain50
     log("large proposal psnr vs plain: %s" % {k: round(v, 2) for k, v in psnr_prop_vs_plain.items()})
 
     # bucket sizes of one single-chunk pass (plain e4m3): the first 2^20 rays of camera 0
@@ -203,8 +260,14 @@ def large_scene(args, am, torch, np, synth, ctx):
         o0, d0 = synth.camera_rays(cams[0])
         sel = np.sort(np.random.default_rng(64).choice(R1, R1 // 64, replace=False))
         threads = cpu_threads()
+        t0 = time.perf_counter()
         rgb_o, _, _, ns_o, _ = oracle.render(otree, W, cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max, eps=cfg.ert_eps,
                                              ray_idx=sel, threads=threads)
+        t_o = time.perf_counter() - t0
+        cpu_plain = {"value": float(ns_o.sum()) / t_o, "unit": "samples/s", "cores": threads, "kind": "oracle",
+                     "host_cpus": host_cpus(),
+                     "sample": "seeded 1/64 pixel subset of camera 0 (%d rays, %d samples), float64 plain render, "
+                               "%.1f s" % (sel.size, int(ns_o.sum()), t_o)}
         _, _, deq = ofp8.quantise(W, cfg.n_hidden, cfg.hidden)
         rgb_q, _, _, _, _ = oracle.render(otree, deq.astype(np.float32), cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max,
                                           eps=cfg.ert_eps, ray_idx=sel, threads=threads)
@@ -217,11 +280,40 @@ def large_scene(args, am, torch, np, synth, ctx):
             acc["psnr_%s_vs_oracle_fp8_weights_db" % kind] = am.amnerf_error_stats(
                 ctx.h, x, torch.from_numpy(np.ascontiguousarray(rgb_q)).to(dev).view(-1))["psnr"]
         log("large accuracy: %s" % acc)
+        if "fp8" in res:
+            res["fp8"]["cpu_baseline"] = cpu_plain
+        if "fp8_prop" in res:
+            # the proposal render on the oracle (float64 proposal network, selection and leaf
+            # MLPs), over a bounded random subset of camera 0
+            pm = prop.master.cpu().numpy()
+            prng = np.random.default_rng(6464)
+
+            def oracle_prop(idx):
+                return oracle.render_proposal(otree, W, cfg.n_hidden, cfg.hidden, pm, o0, d0, cfg.s_max,
+                                              eps=cfg.ert_eps, mass_thresh=0.99, cap=48, ray_idx=idx,
+                                              threads=threads)[3]
+            idx = np.sort(prng.choice(R1, 4000, replace=False))
+            t0 = time.perf_counter()
+            oracle_prop(idx)
+            per_ray = (time.perf_counter() - t0) / idx.size
+            n_p = int(min(R1, max(4000, 0.5 * args.cpu_seconds / max(per_ray, 1e-9))))
+            idx = np.sort(prng.choice(R1, n_p, replace=False))
+            t0 = time.perf_counter()
+            ns_p = oracle_prop(idx)
+            t_p = time.perf_counter() - t0
+            res["fp8_prop"]["cpu_baseline"] = {
+                "value": float(ns_p.sum()) / t_p, "unit": "samples/s", "cores": threads, "kind": "oracle",
+                "host_cpus": host_cpus(),
+                "sample": "%d random rays of held-out camera 0 (%d samples), float64 proposal render (float32 "
+                          "leaf weights), %.1f s" % (n_p, int(ns_p.sum()), t_p)}
+            log("large oracle: plain %.3e, proposal %.3e samples/s on %d threads" % (
+                cpu_plain["value"], res["fp8_prop"]["cpu_baseline"]["value"], threads))
 
     return {"workload": "1920x1080 frames, 256^3 guidance grid (2000 anisotropic blobs, 100:1 density skew), "
                         "%d-leaf KD tree (max depth 12), 4x64 leaf MLPs, <=192 samples/ray, ERT at T<1e-4; "
-                        "%d held-out cameras rendered by one call" % (L, n_cams),
-            "n_leaves": L, "rays_per_call": R, "cameras_per_call": n_cams, "paths": res,
+                        "%d held-out cameras rendered by one call (%d with the proposal)" % (L, n_cams, n_prop_cams),
+            "n_leaves": L, "rays_per_call": R, "cameras_per_call": n_cams,
+            "proposal_rays_per_call": R50, "proposal_cameras_per_call": n_prop_cams, "paths": res,
             "occupancy": {"cells": occ.g ** 3, "occupied": occ.n_occupied, "block": 2, "thresh": 0.01},
             "psnr_vs_plain_db": psnr_prop_vs_plain, "bucket_sizes": spread, "accuracy": acc,
             "proposal_training": prop_training}
@@ -237,7 +329,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-steps", type=int, default=20, help="timed training steps (0: skip)")
-    ap.add_argument("--paths", default="f32,bf16,bf16_prop,fp8,fp8_prop",
+    ap.add_argument("--paths", default="f32,bf16,bf16_prop,fp8,fp8_prop,f32_rounds,bf16_rounds",
                     help="comma-separated render paths to time (the headline bf16_prop is always timed)")
     ap.add_argument("--train-batch", type=int, default=262144)
     ap.add_argument("--no-large", action="store_true", help="skip the 1920x1080 4096-leaf scene")
@@ -250,6 +342,8 @@ def main():
                     help="training steps per student of the ablation's quality comparison (0: skip)")
     ap.add_argument("--inflight", type=int, default=2,
                     help="frames in flight for the throughput line: contexts on streams of their own")
+    ap.add_argument("--windows", type=int, default=5,
+                    help="timed windows of --steps frames with frames in flight (the median is reported)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (rays would shard "
@@ -308,8 +402,10 @@ def main():
                                                              ["%.2e" % v for v in losses]))
     desc = prop.descriptor(am.AMNERF_BF16, mass_thresh=0.99, cap=48)
 
-    all_paths = {"f32": ("f32", None), "bf16": ("bf16", None), "bf16_prop": ("bf16", desc),
-                 "fp8": ("fp8", None), "fp8_prop": ("fp8", desc)}
+    # (leaf weights, proposal, early termination in 64-sample rounds)
+    all_paths = {"f32": ("f32", None, False), "bf16": ("bf16", None, False), "bf16_prop": ("bf16", desc, False),
+                 "fp8": ("fp8", None, False), "fp8_prop": ("fp8", desc, False),
+                 "f32_rounds": ("f32", None, True), "bf16_rounds": ("bf16", None, True)}
     wanted = set(args.paths.split(",")) | {"bf16_prop"}
     paths = {k: v for k, v in all_paths.items() if k in wanted}
     outs = {k: {"rgb": torch.empty((R, 3), device=dev), "depth": torch.empty(R, device=dev),
@@ -318,24 +414,29 @@ def main():
     def render(kind, cam):
         o, d = rays[cam]
         ob = outs[kind]
-        mk, pd = paths[kind]
+        mk, pd, rounds = paths[kind]
         am.amnerf_render(ctx.h, tree.h, mlps[mk].desc, o, d, cfg.s_max, ob["rgb"], ob["depth"], ob["opacity"],
-                         None, cfg.ert_eps, proposal=pd)
+                         None, cfg.ert_eps, proposal=pd, ert_rounds=rounds)
 
-    # samples per camera (untimed)
+    # samples per camera (untimed): evaluated by the leaf MLPs, and composited (in front of
+    # each ray's termination)
     samples = {k: [] for k in paths}
+    composited = {k: [] for k in paths}
     fallback, plain = [], []
     for kind in paths:
         for cam in range(n_cams):
             render(kind, cam)
             st = am.amnerf_render_stats_get(ctx.h)
             samples[kind].append(st["n_samples"])
+            composited[kind].append(st["n_composited"])
             if kind == "bf16_prop":
                 fallback.append(st["n_fallback"])
                 plain.append(st["n_plain_samples"])
     torch.cuda.synchronize()
     log("samples per frame: plain %s, proposal %s, fallback rays %s" % (plain, samples["bf16_prop"], fallback))
 
+    # one frame at a time: an event after every frame on the render stream, the median frame
+    # (GPU time between consecutive events) reported
     results = {}
     am.amnerf_ctx_set_timing(ctx.h, True)
     for kind in paths:
@@ -343,26 +444,34 @@ def main():
             render(kind, w % n_cams)
         torch.cuda.synchronize()
         am.amnerf_timing_collect(ctx.h)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         t0 = time.perf_counter()
+        evs[0].record()
         for k in range(args.steps):
             render(kind, k % n_cams)
+            evs[k + 1].record()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        frame_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
         stage_ms, npass = am.amnerf_timing_collect(ctx.h)
-        n_s = sum(samples[kind][k % n_cams] for k in range(args.steps))
+        n_s = sum(samples[kind][k % n_cams] for k in range(args.steps)) / args.steps
+        n_c = sum(composited[kind][k % n_cams] for k in range(args.steps)) / args.steps
         mlp_ms = stage_ms["mlp"] / max(npass, 1)
-        flops = FLOP_PER_SAMPLE_4x64 * n_s / args.steps
+        med = median(frame_ms)
         results[kind] = {
-            "ms_per_frame": 1e3 * dt / args.steps,
-            "samples_per_s": n_s / dt,
-            "samples_per_frame": n_s / args.steps,
+            "ms_per_frame": med,
+            "ms_per_frame_mean": 1e3 * dt / args.steps,
+            "ms_per_frame_min_max": [min(frame_ms), max(frame_ms)],
+            "samples_per_s": n_s / (med * 1e-3),
+            "samples_per_frame": n_s,
+            "composited_samples_per_frame": n_c,
             "stage_ms_per_frame": {k: v / max(npass, 1) for k, v in stage_ms.items()},
             "mlp_ms": mlp_ms,
-            "mlp_tflops": flops / (mlp_ms * 1e-3) / 1e12,
+            "mlp_tflops": FLOP_PER_SAMPLE_4x64 * n_s / (mlp_ms * 1e-3) / 1e12,
         }
-        log("%s: %.3f ms/frame, %.3e samples/s, stages %s" % (
-            kind, results[kind]["ms_per_frame"], results[kind]["samples_per_s"],
-            {k: round(v, 4) for k, v in results[kind]["stage_ms_per_frame"].items()}))
+        log("%s: %.3f ms/frame (median of %d), %.3e samples/s, %.0f evaluated / %.0f composited samples, "
+            "stages %s" % (kind, med, args.steps, results[kind]["samples_per_s"], n_s, n_c,
+                           {k: round(v, 4) for k, v in results[kind]["stage_ms_per_frame"].items()}))
     am.amnerf_ctx_set_timing(ctx.h, False)
 
     # ---- frames in flight: one context per stream (the contexts share the tree and the
@@ -380,19 +489,23 @@ def main():
         def prender(kind, cam, q):
             o, d = rays[cam]
             ob = iouts[q]
-            mk, pd = paths[kind]
+            mk, pd, rounds = paths[kind]
             am.amnerf_render(ctxs[q].h, tree.h, mlps[mk].desc, o, d, cfg.s_max, ob["rgb"], ob["depth"],
-                             ob["opacity"], None, cfg.ert_eps, proposal=pd, stream=streams[q])
-        inflight = {"frames_in_flight": N, "paths": {}}
+                             ob["opacity"], None, cfg.ert_eps, proposal=pd, stream=streams[q], ert_rounds=rounds)
+        inflight = {"frames_in_flight": N, "windows": args.windows, "paths": {}}
         for kind in paths:
             for w in range(args.warmup):
                 prender(kind, w % n_cams, w % N)
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(args.steps):
-                prender(kind, k % n_cams, k % N)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
+            # --windows timed windows of --steps frames each; the median window is reported
+            wins = []
+            for _ in range(args.windows):
+                t0 = time.perf_counter()
+                for k in range(args.steps):
+                    prender(kind, k % n_cams, k % N)
+                torch.cuda.synchronize()
+                wins.append(time.perf_counter() - t0)
+            dt = median(wins)
             n_s = sum(samples[kind][k % n_cams] for k in range(args.steps))
             # the last frame of each stream equals the same camera rendered alone
             same = True
@@ -402,6 +515,7 @@ def main():
                 torch.cuda.synchronize()
                 same = same and all(torch.equal(iouts[q][c], outs[kind][c]) for c in ("rgb", "depth", "opacity"))
             inflight["paths"][kind] = {"ms_per_frame": 1e3 * dt / args.steps, "samples_per_s": n_s / dt,
+                                       "window_ms_per_frame": [1e3 * x / args.steps for x in wins],
                                        "identical_to_single_stream": bool(same)}
             log("%s, %d frames in flight: %.3f ms/frame, %.3e samples/s, outputs identical: %s" % (
                 kind, N, 1e3 * dt / args.steps, n_s / dt, same))
@@ -542,7 +656,7 @@ def main():
 
     # ---- training step on the same scene (teacher-student, bf16 forward, float32 gradients,
     #      Adam), timed apart from the frame ----
-    train = None
+    train = train_host = None
     if args.train_steps > 0:
         B = args.train_batch
         tcams = synth.make_cameras(100, cfg.seed_batches + 3, cfg.width, cfg.height)
@@ -559,25 +673,46 @@ def main():
             ob, db_, tb = batches[it % 4]
             tlosses.append(float(trainer.step(ob, db_, tb, cfg.s_max, lr=1e-3).item()))
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        am.amnerf_ctx_set_timing(ctx.h, True)
+        am.amnerf_timing_collect(ctx.h)
+        am.amnerf_timing_collect_backward(ctx.h)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.train_steps + 1)]
+        evs[0].record()
         for it in range(args.train_steps):
             ob, db_, tb = batches[it % 4]
             trainer.step(ob, db_, tb, cfg.s_max, lr=1e-3)
-        e1.record()
+            evs[it + 1].record()
         torch.cuda.synchronize()
-        t_ms = e0.elapsed_time(e1) / args.train_steps
+        step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.train_steps)]
+        fwd_ms, nf = am.amnerf_timing_collect(ctx.h)
+        bwd_ms, nb = am.amnerf_timing_collect_backward(ctx.h)
+        am.amnerf_ctx_set_timing(ctx.h, False)
+        t_ms = median(step_ms)
         for it in range(4):
             ob, db_, tb = batches[it]
             tlosses.append(float(trainer.step(ob, db_, tb, cfg.s_max, lr=1e-3).item()))
             tsamples += am.amnerf_render_stats_get(ctx.h)["n_samples"]
-        train = {"ms_per_step": t_ms, "rays_per_step": B, "samples_per_step": tsamples / 4,
-                 "samples_per_s": tsamples / 4 / (t_ms * 1e-3), "steps": args.train_steps,
+        spp = tsamples / 4
+        stages = {"forward_" + k: v / max(nf, 1) for k, v in fwd_ms.items()}
+        stages.update({k: v / max(nb, 1) for k, v in bwd_ms.items()})
+        bwd_tf = FLOP_PER_SAMPLE_BWD_4x64 * spp / (stages["mlp_bwd"] * 1e-3) / 1e12
+        train = {"ms_per_step": t_ms, "ms_per_step_mean": sum(step_ms) / len(step_ms),
+                 "rays_per_step": B, "samples_per_step": spp,
+                 "samples_per_s": spp / (t_ms * 1e-3), "steps": args.train_steps,
                  "loss_first_last": [tlosses[0], tlosses[-1]],
+                 "stage_ms_per_step": stages,
+                 "tflops_per_step": (FLOP_PER_SAMPLE_4x64 + FLOP_PER_SAMPLE_BWD_4x64) * spp / (t_ms * 1e-3) / 1e12,
+                 "roofline": {"bound": "mfma", "achieved": bwd_tf, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                              "frac": bwd_tf / PEAK_TFLOPS["bf16"], "traffic": None,
+                              "kernel": "k_mlp_bwd<64, 4>", "kernel_ms": stages["mlp_bwd"],
+                              "flop_per_sample": FLOP_PER_SAMPLE_BWD_4x64},
                  "workload": "teacher = the scene's leaf MLPs (float32 renders as targets), student re-seeded; "
                              "%d-ray batches drawn from 100 cameras at 800x800" % B}
-        log("train: %.3f ms/step, %.3e samples/s, loss %.3e -> %.3e" % (
-            t_ms, train["samples_per_s"], tlosses[0], tlosses[-1]))
+        log("train: %.3f ms/step (median of %d), %.3e samples/s, loss %.3e -> %.3e, stages %s" % (
+            t_ms, args.train_steps, train["samples_per_s"], tlosses[0], tlosses[-1],
+            {k: round(v, 4) for k, v in stages.items()}))
+        train_host = (trainer.master.cpu().numpy(), batches[0][0].cpu().numpy(), batches[0][1].cpu().numpy(),
+                      batches[0][2].cpu().numpy())
 
     # outputs of camera 0 for the accuracy report
     imgs = {}
@@ -626,9 +761,38 @@ def main():
             rep = am.amnerf_error_stats(ctx.h, imgs[kind][sel_dev].contiguous().view(-1), ref_dev)
             psnr[kind] = rep["psnr"]
             max_abs[kind] = rep["max_abs"]
-        log("oracle: %.3e samples/s on %d threads; psnr %s; max |rgb - oracle| %s" % (
-            cpu["value"], threads, {k: round(v, 2) for k, v in psnr.items()},
+        cpu["host_cpus"] = host_cpus()
+        log("oracle: %.3e samples/s on %d threads (%d host cores); psnr %s; max |rgb - oracle| %s" % (
+            cpu["value"], threads, cpu["host_cpus"], {k: round(v, 2) for k, v in psnr.items()},
             {k: float("%.3g" % v) for k, v in max_abs.items()}))
+        if train_host is not None:
+            # the training step on the oracle: float64 forward render, the MSE gradient of its
+            # colours, and the float64 parameter gradient (one host thread: the oracle's
+            # gradient is single-threaded), over a bounded random subset of the first batch
+            Ws_h, tob, tdb, ttb = train_host
+            trng = np.random.default_rng(4321)
+
+            def oracle_step(idx):
+                rgb_s, _, _, ns_s, _ = oracle.render(otree, Ws_h, cfg.n_hidden, cfg.hidden, tob, tdb, cfg.s_max,
+                                                     eps=cfg.ert_eps, ray_idx=idx, threads=1)
+                g = 2.0 * (rgb_s - ttb[idx]) / (3.0 * tob.shape[1])
+                oracle.render_grad(otree, Ws_h, cfg.n_hidden, cfg.hidden, tob, tdb, cfg.s_max, g,
+                                   eps=cfg.ert_eps, ray_idx=idx)
+                return int(ns_s.sum())
+            idx = np.sort(trng.choice(tob.shape[1], 128, replace=False))
+            t0 = time.perf_counter()
+            oracle_step(idx)
+            per_ray = (time.perf_counter() - t0) / idx.size
+            n_t = int(min(tob.shape[1], max(128, 0.5 * args.cpu_seconds / max(per_ray, 1e-9))))
+            idx = np.sort(trng.choice(tob.shape[1], n_t, replace=False))
+            t0 = time.perf_counter()
+            ns_t = oracle_step(idx)
+            t_t = time.perf_counter() - t0
+            train["cpu_baseline"] = {
+                "value": ns_t / t_t, "unit": "samples/s", "cores": 1, "kind": "oracle", "host_cpus": host_cpus(),
+                "sample": "%d random rays of the first %d-ray training batch (%d samples): float64 forward "
+                          "render, MSE gradient, float64 parameter gradient; %.1f s" % (n_t, tob.shape[1], ns_t, t_t)}
+            log("oracle training step: %.3e samples/s on one thread" % (ns_t / t_t))
 
     large = None
     if not args.no_large:
@@ -681,6 +845,8 @@ def main():
         "psnr_vs_oracle_db": psnr,
         "max_abs_rgb_vs_oracle": max_abs,
         "speedup_vs_plain_fp32": tput["f32"]["ms_per_frame"] / tput["bf16_prop"]["ms_per_frame"] if "f32" in tput else None,
+        "speedup_vs_plain_fp32_in_rounds": (tput["f32_rounds"]["ms_per_frame"] / tput["bf16_prop"]["ms_per_frame"]
+                                            if "f32_rounds" in tput else None),
         "training": train,
         "paths": results,
         "frames_in_flight": inflight,

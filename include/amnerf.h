@@ -400,6 +400,18 @@ int amnerf_ctx_set_timing(amnerf_ctx* ctx, int enable);
  * render passes (chunks) timed; then restarts the sums. */
 int amnerf_timing_collect(amnerf_ctx* ctx, double* stage_ms_host, int64_t* n_passes);
 
+/* Backward stages, timed the same way (events on the backward's stream) when timing is on. */
+#define AMNERF_BWD_STAGE_COMPOSITE 0  /* loss gradient (training step) and compositing backward */
+#define AMNERF_BWD_STAGE_MLP 1        /* per-leaf MLP backward: segment offsets and k_mlp_bwd */
+#define AMNERF_BWD_STAGE_REDUCE 2     /* reduction of the per-segment weight gradients */
+#define AMNERF_BWD_STAGE_ADAM 3       /* Adam and the repack of the bfloat16 weights (training step) */
+#define AMNERF_N_BWD_STAGES 4
+
+/* As amnerf_timing_collect, for the backward passes (amnerf_render_backward and the backward
+ * of amnerf_train_step; a backward alone has no Adam stage, timed as 0): the summed GPU time
+ * per backward stage (host double[AMNERF_N_BWD_STAGES]) and the number of passes timed. */
+int amnerf_timing_collect_backward(amnerf_ctx* ctx, double* stage_ms_host, int64_t* n_passes);
+
 /* ---- training (not in the paper, which distils its leaf MLPs offline: differentiable
  *      rendering so the leaf MLPs can be fitted to images) --------------------------------- */
 

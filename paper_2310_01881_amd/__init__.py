@@ -42,7 +42,7 @@ EXPORTS = [
     "amnerf_build_occupancy", "amnerf_occupancy_info_get", "amnerf_occupancy_export", "amnerf_occupancy_destroy",
     "amnerf_mlp_param_count", "amnerf_mlp_packed_bytes", "amnerf_mlp_pack", "amnerf_render",
     "amnerf_render_stats_get", "amnerf_render_inspect", "amnerf_ctx_set_timing",
-    "amnerf_timing_collect", "amnerf_render_backward", "amnerf_adam_step", "amnerf_train_step",
+    "amnerf_timing_collect", "amnerf_timing_collect_backward", "amnerf_render_backward", "amnerf_adam_step", "amnerf_train_step",
     "amnerf_prop_param_count", "amnerf_prop_packed_bytes", "amnerf_prop_pack", "amnerf_propose",
     "amnerf_error_stats", "amnerf_render_backward_inspect", "amnerf_render_static",
     "amnerf_render_static_capacity",
@@ -51,6 +51,7 @@ AMNERF_PROPOSE_INFER = 0
 AMNERF_PROPOSE_TRAIN = 1
 AMNERF_GRAD_ONLY = 1
 STAGES = ["traverse", "proposal", "sort", "expand", "mlp", "composite"]
+BWD_STAGES = ["comp_bwd", "mlp_bwd", "grad_reduce", "adam"]
 
 
 class AmnerfError(RuntimeError):
@@ -167,6 +168,7 @@ def _load():
     lib.amnerf_render_inspect.argtypes = [P, C.POINTER(amnerf_inspect), P]
     lib.amnerf_ctx_set_timing.argtypes = [P, C.c_int]
     lib.amnerf_timing_collect.argtypes = [P, P, C.POINTER(C.c_int64)]
+    lib.amnerf_timing_collect_backward.argtypes = [P, P, C.POINTER(C.c_int64)]
     lib.amnerf_render_backward.argtypes = [P, P, C.POINTER(amnerf_mlp), C.POINTER(amnerf_rays), P, P, P, P, P]
     lib.amnerf_render_backward_inspect.argtypes = [P, P, P]
     lib.amnerf_adam_step.argtypes = [P, C.c_int64, P, P, P, P, C.POINTER(amnerf_adam_params), P]
@@ -301,9 +303,10 @@ def amnerf_mlp_pack(ctx, n_hidden: int, hidden: int, dtype: int, n_leaves: int, 
 def amnerf_render(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, s_max: int, rgb_dev, depth_dev=None,
                   opacity_dev=None, weights_dev=None, ert_eps: float = 1e-4, jitter: bool = False,
                   seed: int = 0, stream=None, proposal: "amnerf_proposal" = None, hcheck_footprint: float = 0.0,
-                  occupancy=None):
+                  occupancy=None, ert_rounds: bool = False):
     rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]) if o_dev is not None else 0)
-    prm = amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed,
+    flags = (AMNERF_JITTER if jitter else 0) | (AMNERF_ERT_ROUNDS if ert_rounds else 0)
+    prm = amnerf_render_params(s_max, ert_eps, flags, seed,
                                C.pointer(proposal) if proposal is not None else None, hcheck_footprint,
                                _handle(occupancy))
     out = amnerf_render_out(_ptr(rgb_dev), _ptr(depth_dev), _ptr(opacity_dev), _ptr(weights_dev))
@@ -313,9 +316,10 @@ def amnerf_render(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, s_max: int, rgb_dev,
 
 def amnerf_render_static(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, s_max: int, rgb_dev, depth_dev=None,
                          opacity_dev=None, weights_dev=None, ert_eps: float = 1e-4, jitter: bool = False,
-                         seed: int = 0, stream=None, hcheck_footprint: float = 0.0):
+                         seed: int = 0, stream=None, hcheck_footprint: float = 0.0, ert_rounds: bool = False):
     rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]) if o_dev is not None else 0)
-    prm = amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed, None, hcheck_footprint, None)
+    flags = (AMNERF_JITTER if jitter else 0) | (AMNERF_ERT_ROUNDS if ert_rounds else 0)
+    prm = amnerf_render_params(s_max, ert_eps, flags, seed, None, hcheck_footprint, None)
     out = amnerf_render_out(_ptr(rgb_dev), _ptr(depth_dev), _ptr(opacity_dev), _ptr(weights_dev))
     _check(_lib.amnerf_render_static(ctx, tree, C.byref(mlp), C.byref(rays), C.byref(prm), C.byref(out),
                                      _stream(stream)))
@@ -346,6 +350,14 @@ def amnerf_timing_collect(ctx):
     n = C.c_int64()
     _check(_lib.amnerf_timing_collect(ctx, ms.ctypes.data_as(C.c_void_p), C.byref(n)))
     return dict(zip(STAGES, ms.tolist())), int(n.value)
+
+
+def amnerf_timing_collect_backward(ctx):
+    """(dict backward stage -> summed ms, number of timed backward passes)."""
+    ms = np.zeros(len(BWD_STAGES), np.float64)
+    n = C.c_int64()
+    _check(_lib.amnerf_timing_collect_backward(ctx, ms.ctypes.data_as(C.c_void_p), C.byref(n)))
+    return dict(zip(BWD_STAGES, ms.tolist())), int(n.value)
 
 
 def amnerf_render_backward(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, g_rgb_dev, grad_dev, g_depth_dev=None,

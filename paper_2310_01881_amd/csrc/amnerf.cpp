@@ -86,6 +86,11 @@ struct EvSet {
   hipEvent_t ev[kStages + 1] = {};
   bool pending = false;
 };
+constexpr int kBwdStages = AMNERF_N_BWD_STAGES;
+struct BwdEvSet {
+  hipEvent_t ev[kBwdStages + 1] = {};
+  bool pending = false;
+};
 }  // namespace
 
 struct amnerf_ctx {
@@ -95,6 +100,10 @@ struct amnerf_ctx {
   int ring_next = 0;
   double stage_ms[kStages] = {};
   int64_t timed_passes = 0;
+  std::vector<BwdEvSet> bring;   // the same for backward passes
+  int bring_next = 0;
+  double bwd_ms[kBwdStages] = {};
+  int64_t bwd_passes = 0;
   size_t cap = 0;
   void* arena = nullptr;
   size_t arena_bytes = 0;
@@ -207,6 +216,9 @@ extern "C" int amnerf_ctx_destroy(amnerf_ctx* ctx) {
   for (EvSet& s : ctx->ring)
     for (hipEvent_t e : s.ev)
       if (e) (void)hipEventDestroy(e);
+  for (BwdEvSet& s : ctx->bring)
+    for (hipEvent_t e : s.ev)
+      if (e) (void)hipEventDestroy(e);
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->arena2) (void)hipFree(ctx->arena2);
   if (ctx->arena3) (void)hipFree(ctx->arena3);
@@ -245,6 +257,9 @@ extern "C" int amnerf_ctx_set_timing(amnerf_ctx* ctx, int enable) {
     ctx->ring.resize(kRing);
     for (EvSet& s : ctx->ring)
       for (hipEvent_t& e : s.ev) HIP_TRY(hipEventCreate(&e));
+    ctx->bring.resize(kRing);
+    for (BwdEvSet& s : ctx->bring)
+      for (hipEvent_t& e : s.ev) HIP_TRY(hipEventCreate(&e));
   }
   ctx->timing = enable != 0;
   return AMNERF_OK;
@@ -273,6 +288,44 @@ static int next_set(amnerf_ctx* ctx, EvSet** out) {
   int rc = drain_set(ctx, s);
   if (rc) return rc;
   *out = &s;
+  return AMNERF_OK;
+}
+
+static int drain_bwd_set(amnerf_ctx* ctx, BwdEvSet& s) {
+  if (!s.pending) return AMNERF_OK;
+  HIP_TRY(hipEventSynchronize(s.ev[kBwdStages]));
+  for (int k = 0; k < kBwdStages; ++k) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, s.ev[k], s.ev[k + 1]));
+    ctx->bwd_ms[k] += ms;
+  }
+  ctx->bwd_passes += 1;
+  s.pending = false;
+  return AMNERF_OK;
+}
+
+static int next_bwd_set(amnerf_ctx* ctx, BwdEvSet** out) {
+  BwdEvSet& s = ctx->bring[ctx->bring_next];
+  ctx->bring_next = (ctx->bring_next + 1) % kRing;
+  int rc = drain_bwd_set(ctx, s);
+  if (rc) return rc;
+  *out = &s;
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_timing_collect_backward(amnerf_ctx* ctx, double* stage_ms, int64_t* n_passes) {
+  if (!ctx || !stage_ms) return fail(AMNERF_EINVAL, "amnerf_timing_collect_backward: null argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  for (BwdEvSet& s : ctx->bring) {
+    int rc = drain_bwd_set(ctx, s);
+    if (rc) return rc;
+  }
+  for (int k = 0; k < kBwdStages; ++k) {
+    stage_ms[k] = ctx->bwd_ms[k];
+    ctx->bwd_ms[k] = 0.0;
+  }
+  if (n_passes) *n_passes = ctx->bwd_passes;
+  ctx->bwd_passes = 0;
   return AMNERF_OK;
 }
 
@@ -1241,9 +1294,12 @@ size_t carve_bwd(char* base, uint64_t ns, uint64_t L, uint64_t nseg, uint64_t P,
   return c.off + 256;
 }
 
+// in_step: called by a training step, whose backward stage events (stage 0 already marked)
+// are ev, null when timing is off; a backward pass alone takes an event set of its own when
+// timing is on.
 int backward_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp, const amnerf_rays* rays,
                   const float* g_rgb, const float* g_depth, const float* g_opac, float* grad, hipStream_t st,
-                  BwdWork* w_out) {
+                  BwdWork* w_out, bool in_step, BwdEvSet* ev) {
   MlpGeom g;
   int rc = check_geom(&mlp->shape, mlp->dtype, &g, "amnerf_render_backward");
   if (rc) return rc;
@@ -1279,12 +1335,26 @@ int backward_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* ml
   const amnerf_render_params& p = ctx->last_params;
   const int jitter = (p.flags & AMNERF_JITTER) ? 1 : 0;
   const uint32_t nr = (uint32_t)R;
+  const bool alone = !in_step;
+  if (alone && ctx->timing) {
+    rc = next_bwd_set(ctx, &ev);
+    if (rc) return rc;
+  }
+  auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev->ev[k], st) : hipSuccess; };
+  if (alone) HIP_TRY(mark(AMNERF_BWD_STAGE_COMPOSITE));
   HIP_TRY(launch_comp_bwd(nr, ctx->use, ctx->smp_out, 0, jitter, p.jitter_seed, ctx->ray_used, g_rgb, g_depth,
                           g_opac, w.gpre, st));
+  HIP_TRY(mark(AMNERF_BWD_STAGE_MLP));
   HIP_TRY(launch_seg_offsets(ctx->tile_off, (uint32_t)L, w.seg_off, st));
   HIP_TRY(launch_mlp_bwd(g, mlp->packed_dev, (uint32_t)L, ctx->bucket_off, ctx->tile_off, w.seg_off, ctx->srec_ray,
                          ctx->srec_t, ctx->perm, rays->o_dev, rays->d_dev, rays->n_rays, 0, w.gpre, w.part, st));
+  HIP_TRY(mark(AMNERF_BWD_STAGE_REDUCE));
   HIP_TRY(launch_grad_reduce(w.part, w.seg_off, (uint32_t)L, (uint32_t)P, grad, st));
+  HIP_TRY(mark(AMNERF_BWD_STAGE_ADAM));
+  if (alone && ev) {
+    HIP_TRY(mark(kBwdStages));
+    ev->pending = true;
+  }
   ctx->have_backward = true;
   ctx->last_gpre = w.gpre;
   return AMNERF_OK;
@@ -1297,7 +1367,7 @@ extern "C" int amnerf_render_backward(amnerf_ctx* ctx, const amnerf_tree* tree, 
                                       const float* g_opac, float* grad, void* stream) {
   if (!ctx || !tree || !mlp || !rays) return fail(AMNERF_EINVAL, "amnerf_render_backward: null argument");
   HIP_TRY(hipSetDevice(ctx->device));
-  return backward_impl(ctx, tree, mlp, rays, g_rgb, g_depth, g_opac, grad, (hipStream_t)stream, nullptr);
+  return backward_impl(ctx, tree, mlp, rays, g_rgb, g_depth, g_opac, grad, (hipStream_t)stream, nullptr, false, nullptr);
 }
 
 extern "C" int amnerf_render_backward_inspect(amnerf_ctx* ctx, float* sample_grad_dev, void* stream) {
@@ -1371,8 +1441,14 @@ extern "C" int amnerf_train_step(amnerf_ctx* ctx, const amnerf_tree* tree, amner
   amnerf_render_out out = {w.rgb, nullptr, nullptr, nullptr};
   int rc = amnerf_render(ctx, tree, &mlp, rays, &p->render, &out, stream);
   if (rc) return rc;
+  BwdEvSet* ev = nullptr;
+  if (ctx->timing) {
+    rc = next_bwd_set(ctx, &ev);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(ev->ev[AMNERF_BWD_STAGE_COMPOSITE], st));
+  }
   HIP_TRY(launch_loss_grad((uint32_t)R, w.rgb, target, w.g_rgb, w.loss_partial, loss, st));
-  rc = backward_impl(ctx, tree, &mlp, rays, w.g_rgb, nullptr, nullptr, m->grad_dev, st, nullptr);
+  rc = backward_impl(ctx, tree, &mlp, rays, w.g_rgb, nullptr, nullptr, m->grad_dev, st, nullptr, true, ev);
   if (rc) return rc;
   if (!(p->flags & AMNERF_GRAD_ONLY)) {
     const int64_t n = (int64_t)m->n_leaves * amnerf_mlp_param_count(&m->shape);
@@ -1380,6 +1456,10 @@ extern "C" int amnerf_train_step(amnerf_ctx* ctx, const amnerf_tree* tree, amner
     if (rc) return rc;
     rc = amnerf_mlp_pack(ctx, &m->shape, AMNERF_BF16, m->n_leaves, m->master_dev, m->packed_dev, stream);
     if (rc) return rc;
+  }
+  if (ev) {
+    HIP_TRY(hipEventRecord(ev->ev[kBwdStages], st));
+    ev->pending = true;
   }
   return AMNERF_OK;
 }
