@@ -51,6 +51,7 @@ def lib():
         P = C.c_void_p
         i32, i64, dbl, u64, f32 = C.c_int32, C.c_int64, C.c_double, C.c_uint64, C.c_float
         _lib.orc_build_tree.argtypes = [P, i32, i32, i32, i32, i32, P, P, P, P]
+        _lib.orc_build_tree_codes.argtypes = [P, i32, i32, P, i32, P, P, P, P]
         _lib.orc_trace_rays.argtypes = [P, i32, i32, P, P, i64, P, i64, i32, P, P, P, P, f32]
         _lib.orc_robust.argtypes = [P, i32, i32, P, P, i64, P, i64, dbl, dbl, P, f32]
         _lib.orc_mlp_eval.argtypes = [P, i32, i32, P, P, i64, P, P]
@@ -128,6 +129,24 @@ def build_tree(grid, n, max_depth, max_leaves, split=0) -> Tree:
         raise ValueError("orc_build_tree failed")
     k = int(nn[0])
     return Tree(rows[:k].copy(), mass[:k].copy(), n)
+
+
+def build_tree_codes(grid, n, codes) -> Tree:
+    """The tree whose inner nodes are exactly `codes` (binary node codes, root 1, children 2c
+    and 2c + 1), each split at its density median; a code must name a splittable leaf of the
+    tree its smaller codes give."""
+    grid = _c(grid, np.float32)
+    codes = np.ascontiguousarray(np.asarray(codes, np.uint32).reshape(-1))
+    cap = 2 * codes.size + 1
+    rows = np.zeros((cap, NODE_COLS), np.int32)
+    mass = np.zeros(cap, np.uint64)
+    nn = np.zeros(1, np.int32)
+    nl = np.zeros(1, np.int32)
+    rc = lib().orc_build_tree_codes(_p(grid), n, codes.size, _p(codes) if codes.size else None, cap, _p(rows),
+                                    _p(mass), _p(nn), _p(nl))
+    if rc != 0:
+        raise ValueError("orc_build_tree_codes failed (a code is not a splittable leaf)")
+    return Tree(rows[:int(nn[0])].copy(), mass[:int(nn[0])].copy(), n)
 
 
 def _sel(ray_idx, R):

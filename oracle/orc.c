@@ -111,80 +111,45 @@ static int cmp_code(const void* a, const void* b) {
   return ca < cb ? -1 : (ca > cb ? 1 : 0);
 }
 
-/* Builds the tree and exports it as rows of 12 int32, sorted by node code:
- *   code, depth, lo[3], hi[3], axis (-1 leaf), plane (-1 leaf), slot (-1 inner), node slot
- * (preorder rank among all nodes: the MLP index of a node under hierarchical sampling)
- * plus the integer mass of each node.  Returns 0, or -1 on bad arguments / capacity. */
-int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int split, int cap,
-                   int32_t* rows, uint64_t* mass_out, int* n_nodes_out, int* n_leaves_out) {
-  if (!grid || n < 1 || max_depth < 0 || max_depth > 30 || max_leaves < 1 || !rows) return -1;
-  if (split != 0 && split != 1) return -1;
-  int64_t ncell = (int64_t)n * n * n;
-  uint32_t* q = (uint32_t*)malloc(sizeof(uint32_t) * ncell);
-  if (!q) return -1;
-  quantise(grid, ncell, q);
-  int maxn = 2 * max_leaves;
-  onode* nodes = (onode*)calloc(maxn, sizeof(onode));
-  uint64_t* slab = (uint64_t*)malloc(sizeof(uint64_t) * n);
-  int nn = 1, nleaves = 1;
-  onode* r = &nodes[0];
-  for (int a = 0; a < 3; ++a) { r->lo[a] = 0; r->hi[a] = n; }
-  r->code = 1; r->depth = 0; r->leaf = 1; r->axis = -1; r->plane = -1;
-  r->child[0] = r->child[1] = -1;
-  r->mass = 0;
-  for (int64_t i = 0; i < ncell; ++i) r->mass += q[i];
-
-  while (nleaves < max_leaves) {
-    /* median split (split = 0): best-first, the splittable leaf of largest mass; middle
-       split (split = 1): breadth-first, the splittable leaf of smallest depth; ties to the
-       smallest code */
-    int best = -1;
-    for (int i = 0; i < nn; ++i) {
-      if (!nodes[i].leaf || !splittable(&nodes[i], max_depth)) continue;
-      int better;
-      if (best < 0) better = 1;
-      else if (split == 0) better = nodes[i].mass > nodes[best].mass ||
-                                    (nodes[i].mass == nodes[best].mass && nodes[i].code < nodes[best].code);
-      else better = nodes[i].depth < nodes[best].depth ||
-                    (nodes[i].depth == nodes[best].depth && nodes[i].code < nodes[best].code);
-      if (better) best = i;
+/* Splits leaf `best` on its longest axis: at the weighted median plane (split = 0: the
+ * smallest plane whose lower side holds at least half of the node's mass, the last plane
+ * if none does, the middle plane for a massless node) or at the middle plane (split = 1).
+ * The children are appended at nodes[*nn] and nodes[*nn + 1]. */
+static void split_leaf(onode* nodes, int* nn, int best, const uint32_t* q, int n, int split, uint64_t* slab) {
+  onode* p = &nodes[best];
+  int a = longest_axis(p);
+  int lo = p->lo[a], hi = p->hi[a];
+  for (int c = lo; c < hi; ++c) slab[c - lo] = mass_of_slab(q, n, p->lo, p->hi, a, c);
+  int plane;
+  if (split == 1 || p->mass == 0) {
+    plane = (lo + hi) / 2;
+  } else {
+    /* weighted median: smallest plane whose lower side holds at least half the mass */
+    plane = hi - 1;
+    uint64_t acc = 0;
+    for (int c = lo + 1; c <= hi - 1; ++c) {
+      acc += slab[c - 1 - lo];
+      if (2 * acc >= p->mass) { plane = c; break; }
     }
-    if (best < 0) break;
-    onode* p = &nodes[best];
-    int a = longest_axis(p);
-    int lo = p->lo[a], hi = p->hi[a];
-    for (int c = lo; c < hi; ++c) slab[c - lo] = mass_of_slab(q, n, p->lo, p->hi, a, c);
-    int plane;
-    if (split == 1 || p->mass == 0) {
-      plane = (lo + hi) / 2;
-    } else {
-      /* weighted median: smallest plane whose lower side holds at least half the mass */
-      plane = hi - 1;
-      uint64_t acc = 0;
-      for (int c = lo + 1; c <= hi - 1; ++c) {
-        acc += slab[c - 1 - lo];
-        if (2 * acc >= p->mass) { plane = c; break; }
-      }
-    }
-    uint64_t left_mass = 0;
-    for (int c = lo; c < plane; ++c) left_mass += slab[c - lo];
-    for (int side = 0; side < 2; ++side) {
-      onode* ch = &nodes[nn];
-      *ch = *p;
-      ch->code = 2u * p->code + (uint32_t)side;
-      ch->depth = p->depth + 1;
-      ch->leaf = 1; ch->axis = -1; ch->plane = -1; ch->child[0] = ch->child[1] = -1;
-      if (side == 0) { ch->hi[a] = plane; ch->mass = left_mass; }
-      else { ch->lo[a] = plane; ch->mass = p->mass - left_mass; }
-      p->child[side] = nn;
-      ++nn;
-    }
-    p->leaf = 0; p->axis = a; p->plane = plane;
-    ++nleaves;
   }
-  free(slab);
-  free(q);
-  if (nn > cap) { free(nodes); return -1; }
+  uint64_t left_mass = 0;
+  for (int c = lo; c < plane; ++c) left_mass += slab[c - lo];
+  for (int side = 0; side < 2; ++side) {
+    onode* ch = &nodes[*nn];
+    *ch = *p;
+    ch->code = 2u * p->code + (uint32_t)side;
+    ch->depth = p->depth + 1;
+    ch->leaf = 1; ch->axis = -1; ch->plane = -1; ch->child[0] = ch->child[1] = -1;
+    if (side == 0) { ch->hi[a] = plane; ch->mass = left_mass; }
+    else { ch->lo[a] = plane; ch->mass = p->mass - left_mass; }
+    p->child[side] = *nn;
+    ++*nn;
+  }
+  p->leaf = 0; p->axis = a; p->plane = plane;
+}
+
+/* Slots, then the rows (sorted by code) and masses of the first nn nodes. */
+static void export_rows(onode* nodes, int nn, int32_t* rows, uint64_t* mass_out) {
   slot_counter = 0;
   nslot_counter = 0;
   for (int i = 0; i < nn; ++i) nodes[i].slot = -1;
@@ -205,10 +170,104 @@ int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int 
     if (mass_out) mass_out[k] = nd->mass;
   }
   free(order);
+}
+
+static void init_root(onode* r, int n, const uint32_t* q, int64_t ncell) {
+  for (int a = 0; a < 3; ++a) { r->lo[a] = 0; r->hi[a] = n; }
+  r->code = 1; r->depth = 0; r->leaf = 1; r->axis = -1; r->plane = -1;
+  r->child[0] = r->child[1] = -1;
+  r->mass = 0;
+  for (int64_t i = 0; i < ncell; ++i) r->mass += q[i];
+}
+
+/* Builds the tree and exports it as rows of 12 int32, sorted by node code:
+ *   code, depth, lo[3], hi[3], axis (-1 leaf), plane (-1 leaf), slot (-1 inner), node slot
+ * (preorder rank among all nodes: the MLP index of a node under hierarchical sampling)
+ * plus the integer mass of each node.  Returns 0, or -1 on bad arguments / capacity. */
+int orc_build_tree(const float* grid, int n, int max_depth, int max_leaves, int split, int cap,
+                   int32_t* rows, uint64_t* mass_out, int* n_nodes_out, int* n_leaves_out) {
+  if (!grid || n < 1 || max_depth < 0 || max_depth > 30 || max_leaves < 1 || !rows) return -1;
+  if (split != 0 && split != 1) return -1;
+  int64_t ncell = (int64_t)n * n * n;
+  uint32_t* q = (uint32_t*)malloc(sizeof(uint32_t) * ncell);
+  if (!q) return -1;
+  quantise(grid, ncell, q);
+  int maxn = 2 * max_leaves;
+  onode* nodes = (onode*)calloc(maxn, sizeof(onode));
+  uint64_t* slab = (uint64_t*)malloc(sizeof(uint64_t) * n);
+  int nn = 1, nleaves = 1;
+  init_root(&nodes[0], n, q, ncell);
+
+  while (nleaves < max_leaves) {
+    /* median split (split = 0): best-first, the splittable leaf of largest mass; middle
+       split (split = 1): breadth-first, the splittable leaf of smallest depth; ties to the
+       smallest code */
+    int best = -1;
+    for (int i = 0; i < nn; ++i) {
+      if (!nodes[i].leaf || !splittable(&nodes[i], max_depth)) continue;
+      int better;
+      if (best < 0) better = 1;
+      else if (split == 0) better = nodes[i].mass > nodes[best].mass ||
+                                    (nodes[i].mass == nodes[best].mass && nodes[i].code < nodes[best].code);
+      else better = nodes[i].depth < nodes[best].depth ||
+                    (nodes[i].depth == nodes[best].depth && nodes[i].code < nodes[best].code);
+      if (better) best = i;
+    }
+    if (best < 0) break;
+    split_leaf(nodes, &nn, best, q, n, split, slab);
+    ++nleaves;
+  }
+  free(slab);
+  free(q);
+  if (nn > cap) { free(nodes); return -1; }
+  export_rows(nodes, nn, rows, mass_out);
   free(nodes);
   *n_nodes_out = nn;
   *n_leaves_out = nleaves;
   return 0;
+}
+
+/* The tree whose inner nodes are exactly the given node codes (each split at the density
+ * median as above): the codes are taken in increasing order, and each must name a leaf of
+ * the tree built so far (so a node's parent comes first) whose longest side is at least 2
+ * cells.  This is how BuildKDTree's recursion is driven by an outside stopping rule
+ * (Section 3.4, TestLeaf).  Rows and masses as orc_build_tree.  Returns 0, or -1 on bad
+ * arguments, a code that is not a splittable leaf, or capacity. */
+int orc_build_tree_codes(const float* grid, int n, int n_split, const uint32_t* codes, int cap,
+                         int32_t* rows, uint64_t* mass_out, int* n_nodes_out, int* n_leaves_out) {
+  if (!grid || n < 1 || n_split < 0 || (n_split > 0 && !codes) || !rows) return -1;
+  int nn_need = 2 * n_split + 1;
+  if (nn_need > cap) return -1;
+  int64_t ncell = (int64_t)n * n * n;
+  uint32_t* q = (uint32_t*)malloc(sizeof(uint32_t) * ncell);
+  onode* nodes = (onode*)calloc(nn_need, sizeof(onode));
+  uint64_t* slab = (uint64_t*)malloc(sizeof(uint64_t) * n);
+  uint32_t* sorted = (uint32_t*)malloc(sizeof(uint32_t) * (n_split > 0 ? n_split : 1));
+  if (!q || !nodes || !slab || !sorted) { free(q); free(nodes); free(slab); free(sorted); return -1; }
+  quantise(grid, ncell, q);
+  for (int i = 0; i < n_split; ++i) sorted[i] = codes[i];
+  /* insertion sort: the lists are short */
+  for (int i = 1; i < n_split; ++i)
+    for (int j = i; j > 0 && sorted[j - 1] > sorted[j]; --j) { uint32_t t = sorted[j]; sorted[j] = sorted[j - 1]; sorted[j - 1] = t; }
+  int nn = 1, rc = 0;
+  init_root(&nodes[0], n, q, ncell);
+  for (int s = 0; s < n_split && rc == 0; ++s) {
+    int at = -1;
+    for (int i = 0; i < nn; ++i)
+      if (nodes[i].code == sorted[s]) at = i;
+    if (at < 0 || !nodes[at].leaf || !splittable(&nodes[at], 30)) { rc = -1; break; }
+    split_leaf(nodes, &nn, at, q, n, 0, slab);
+  }
+  free(slab);
+  free(q);
+  free(sorted);
+  if (rc == 0) {
+    export_rows(nodes, nn, rows, mass_out);
+    *n_nodes_out = nn;
+    *n_leaves_out = n_split + 1;
+  }
+  free(nodes);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------- */
