@@ -132,6 +132,14 @@ int amnerf_tree_info_get(const amnerf_tree* tree, amnerf_tree_info* out);
  *   mass_host: host uint64[n_nodes] integer masses, or NULL. */
 int amnerf_tree_export(const amnerf_tree* tree, int32_t* rows_host, uint64_t* mass_host);
 
+/* The tree whose inner nodes are exactly the given node codes (binary: root 1, children 2c
+ * (lower) and 2c + 1 (upper)), each split at the density median as above: the codes are
+ * taken in increasing order, and each must name a leaf of the tree built so far whose
+ * longest side is >= 2 cells (AMNERF_EINVAL otherwise).  The recursion of BuildKDTree
+ * (Section 3.4) driven by a stopping rule made outside the library. */
+int amnerf_build_tree_codes(amnerf_ctx* ctx, const float* grid_host, int32_t n, const uint32_t* codes_host,
+                            int32_t n_codes, amnerf_tree** out);
+
 /* Frees the tree (host and device copies).  NULL is accepted. */
 int amnerf_tree_destroy(amnerf_tree* tree);
 
@@ -462,20 +470,68 @@ typedef struct {
 } amnerf_mlp_train;
 
 #define AMNERF_GRAD_ONLY 1u   /* compute loss and gradient, skip the Adam update */
+#define AMNERF_TRAIN_F32 2u   /* float32 render and backward; packed_dev holds an AMNERF_F32 block */
 
 typedef struct {
   amnerf_render_params render;
   amnerf_adam_params adam;
-  uint32_t flags;           /* AMNERF_GRAD_ONLY */
+  uint32_t flags;           /* AMNERF_GRAD_ONLY, AMNERF_TRAIN_F32 */
 } amnerf_train_params;
 
-/* One training step on a batch of rays: bfloat16 render, loss
+/* One training step on a batch of rays: bfloat16 render (float32 with AMNERF_TRAIN_F32), loss
  * L = mean over rays and channels of (rgb - target)^2, backward, Adam on the float32
- * masters, and re-packing of the bfloat16 block.  target_rgb_dev: device float32
+ * masters, and re-packing of the bfloat16 (float32) block.  target_rgb_dev: device float32
  * [n_rays][3]; loss_dev: device float32[1] receives L. */
 int amnerf_train_step(amnerf_ctx* ctx, const amnerf_tree* tree, amnerf_mlp_train* m,
                       const amnerf_rays* rays, const float* target_rgb_dev,
                       const amnerf_train_params* p, float* loss_dev, void* stream);
+
+/* ---- distillation-driven subdivision (Section 3.4: BuildKDTree with the TestLeaf rule) ----
+ * The recursion of BuildKDTree (node, then its lower subtree, then its upper subtree), each
+ * split at the density median as amnerf_build_tree does, with the stopping rule of
+ * Section 3.4: to test a node, the tree built so far with that node split is distilled for
+ * n_max iterations (every leaf MLP starting from init_dev; step s = 1..n_max is
+ * amnerf_train_step on batch (s - 1) mod n_batches with Adam step s, lr, beta1 0.9,
+ * beta2 0.999, eps 1e-8, fresh moments), and its PSNR on the evaluation rays
+ * (10 log10(1 / mean squared error over the colour channels) against eval_target_dev) is
+ * compared with that of the tree built so far (distilled the same way).  The split is kept
+ * iff PSNR_split - PSNR >= gain_thresh * PSNR (the paper's example threshold: 1 %);
+ * otherwise the node is a leaf.  A node is tested only when its depth < max_depth, its
+ * longest side >= 2 cells and the tree has fewer than max_leaves leaves.  Build-time only:
+ * synchronous, allocates its own device buffers (4 float32 arrays of max_leaves * P, the
+ * packed block, the evaluation colours) and frees them before returning. */
+#define AMNERF_TESTLEAF_F32 1u   /* distil in float32 (render and backward); default bfloat16 */
+
+typedef struct {
+  amnerf_mlp_shape student;        /* node MLP shape (the paper: width 32, depth 4); its
+                                      backward needs n_hidden 1 .. 4, hidden 32 or 64 */
+  const float* init_dev;           /* device float32[P]: the initial parameters of every leaf */
+  int32_t n_max;                   /* distillation steps per trial tree, >= 0 */
+  float gain_thresh;               /* relative PSNR gain a split must reach */
+  float lr;                        /* Adam step size */
+  int32_t n_batches;               /* >= 1 when n_max > 0 */
+  const amnerf_rays* batches;      /* host array [n_batches] of device ray sets (one pass each) */
+  const float* const* targets;     /* host array [n_batches] of device float32[rays][3] colours */
+  amnerf_rays eval;                /* held-out device rays, >= 1 */
+  const double* eval_target_dev;   /* device float64[eval rays][3] colours */
+  amnerf_render_params render;     /* s_max, ert_eps, flags; no proposal, occupancy or footprint */
+  uint32_t flags;                  /* AMNERF_TESTLEAF_F32 */
+} amnerf_testleaf_params;
+
+typedef struct {
+  uint32_t code;                   /* node tested */
+  int32_t depth;
+  int32_t leaves_of_trial;         /* leaves of the tree with the node split */
+  int32_t kept;                    /* 1: split kept */
+  double psnr_current;             /* PSNR of the tree built so far */
+  double psnr_split;               /* PSNR of the tree with the node split */
+} amnerf_testleaf_record;
+
+/* Builds the tree; log_host[0 .. min(*n_log, log_cap)) receives one record per test, in the
+ * order made (*n_log counts every test).  The tree is on ctx's device. */
+int amnerf_build_tree_distilled(amnerf_ctx* ctx, const float* grid_host, int32_t n, int32_t max_depth,
+                                int32_t max_leaves, const amnerf_testleaf_params* params, amnerf_tree** out,
+                                amnerf_testleaf_record* log_host, int32_t log_cap, int32_t* n_log);
 
 /* ---- learned proposal (not in the paper; it cites sample-predicting networks as prior
  *      art).  A 43 -> 64 -> 64 -> 32 ReLU MLP maps features of a (ray, leaf interval) --

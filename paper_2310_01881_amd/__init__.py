@@ -29,6 +29,8 @@ AMNERF_FP8 = 2
 AMNERF_SPLIT_MEDIAN = 0
 AMNERF_SPLIT_MIDDLE = 1
 AMNERF_JITTER = 1
+AMNERF_TRAIN_F32 = 2
+AMNERF_TESTLEAF_F32 = 1
 AMNERF_ERT_ROUNDS = 2
 AMNERF_MAX_GRID = 512
 AMNERF_MAX_DEPTH = 16
@@ -42,7 +44,8 @@ EXPORTS = [
     "amnerf_build_occupancy", "amnerf_occupancy_info_get", "amnerf_occupancy_export", "amnerf_occupancy_destroy",
     "amnerf_mlp_param_count", "amnerf_mlp_packed_bytes", "amnerf_mlp_pack", "amnerf_render",
     "amnerf_render_stats_get", "amnerf_render_inspect", "amnerf_ctx_set_timing",
-    "amnerf_timing_collect", "amnerf_timing_collect_backward", "amnerf_render_backward", "amnerf_adam_step", "amnerf_train_step",
+    "amnerf_timing_collect", "amnerf_timing_collect_backward", "amnerf_render_backward",
+    "amnerf_build_tree_codes", "amnerf_build_tree_distilled", "amnerf_adam_step", "amnerf_train_step",
     "amnerf_prop_param_count", "amnerf_prop_packed_bytes", "amnerf_prop_pack", "amnerf_propose",
     "amnerf_error_stats", "amnerf_render_backward_inspect", "amnerf_render_static",
     "amnerf_render_static_capacity",
@@ -126,6 +129,18 @@ class amnerf_train_params(C.Structure):
     _fields_ = [("render", amnerf_render_params), ("adam", amnerf_adam_params), ("flags", C.c_uint32)]
 
 
+class amnerf_testleaf_params(C.Structure):
+    _fields_ = [("student", amnerf_mlp_shape), ("init_dev", C.c_void_p), ("n_max", C.c_int32),
+                ("gain_thresh", C.c_float), ("lr", C.c_float), ("n_batches", C.c_int32),
+                ("batches", C.POINTER(amnerf_rays)), ("targets", C.POINTER(C.c_void_p)), ("eval", amnerf_rays),
+                ("eval_target_dev", C.c_void_p), ("render", amnerf_render_params), ("flags", C.c_uint32)]
+
+
+class amnerf_testleaf_record(C.Structure):
+    _fields_ = [("code", C.c_uint32), ("depth", C.c_int32), ("leaves_of_trial", C.c_int32), ("kept", C.c_int32),
+                ("psnr_current", C.c_double), ("psnr_split", C.c_double)]
+
+
 class amnerf_propose_params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("s_max", C.c_int32), ("infer_dtype", C.c_int32),
                 ("infer_packed_dev", C.c_void_p), ("tau_dev", C.c_void_p), ("tau_cap", C.c_int64),
@@ -148,6 +163,11 @@ def _load():
     lib.amnerf_ctx_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(P)]
     lib.amnerf_ctx_destroy.argtypes = [P]
     lib.amnerf_build_tree.argtypes = [P, P, C.c_int32, C.POINTER(amnerf_tree_params), C.POINTER(P)]
+    lib.amnerf_build_tree_codes.argtypes = [P, P, C.c_int32, P, C.c_int32, C.POINTER(P)]
+    lib.amnerf_build_tree_distilled.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32,
+                                                C.POINTER(amnerf_testleaf_params), C.POINTER(P),
+                                                C.POINTER(amnerf_testleaf_record), C.c_int32,
+                                                C.POINTER(C.c_int32)]
     lib.amnerf_tree_info_get.argtypes = [P, C.POINTER(amnerf_tree_info)]
     lib.amnerf_tree_export.argtypes = [P, P, P]
     lib.amnerf_tree_destroy.argtypes = [P]
@@ -235,6 +255,43 @@ def amnerf_build_tree(ctx, grid: np.ndarray, n: int, max_depth: int, max_leaves:
     prm = amnerf_tree_params(max_depth, max_leaves, split)
     _check(_lib.amnerf_build_tree(ctx, g.ctypes.data_as(C.c_void_p), n, C.byref(prm), C.byref(h)))
     return h
+
+
+def amnerf_build_tree_codes(ctx, grid: np.ndarray, n: int, codes):
+    g = np.ascontiguousarray(grid, dtype=np.float32)
+    if g.size != n ** 3:
+        raise ValueError("grid has %d cells, expected %d" % (g.size, n ** 3))
+    c = np.ascontiguousarray(np.asarray(codes, np.uint32).reshape(-1))
+    h = C.c_void_p()
+    _check(_lib.amnerf_build_tree_codes(ctx, g.ctypes.data_as(C.c_void_p), n,
+                                        c.ctypes.data_as(C.c_void_p) if c.size else None, int(c.size), C.byref(h)))
+    return h
+
+
+def amnerf_build_tree_distilled(ctx, grid: np.ndarray, n: int, max_depth: int, max_leaves: int, n_hidden: int,
+                                hidden: int, init_dev, n_max: int, gain_thresh: float, lr: float, batches,
+                                eval_rays, eval_target_dev, s_max: int, ert_eps: float = 1e-4, f32: bool = False,
+                                log_cap: int = 4096):
+    """(tree handle, list of test records as dicts).  batches: [(o_dev, d_dev, target_dev)];
+    eval_rays: (o_dev, d_dev); eval_target_dev: float64 [rays][3]."""
+    g = np.ascontiguousarray(grid, dtype=np.float32)
+    if g.size != n ** 3:
+        raise ValueError("grid has %d cells, expected %d" % (g.size, n ** 3))
+    nb = len(batches)
+    rays = (amnerf_rays * max(nb, 1))(*[amnerf_rays(_ptr(o), _ptr(d), int(o.shape[1])) for o, d, _ in batches])
+    tgts = (C.c_void_p * max(nb, 1))(*[_ptr(t) for _, _, t in batches])
+    eo, ed = eval_rays
+    prm = amnerf_testleaf_params(amnerf_mlp_shape(n_hidden, hidden), _ptr(init_dev), n_max, gain_thresh, lr, nb,
+                                 rays, tgts, amnerf_rays(_ptr(eo), _ptr(ed), int(eo.shape[1])), _ptr(eval_target_dev),
+                                 amnerf_render_params(s_max, ert_eps, 0, 0, None, 0.0, None),
+                                 AMNERF_TESTLEAF_F32 if f32 else 0)
+    log = (amnerf_testleaf_record * log_cap)()
+    nlog = C.c_int32()
+    h = C.c_void_p()
+    _check(_lib.amnerf_build_tree_distilled(ctx, g.ctypes.data_as(C.c_void_p), n, max_depth, max_leaves,
+                                            C.byref(prm), C.byref(h), log, log_cap, C.byref(nlog)))
+    recs = [{k: getattr(log[i], k) for k, _ in amnerf_testleaf_record._fields_} for i in range(min(nlog.value, log_cap))]
+    return h, recs
 
 
 def amnerf_tree_info_get(tree) -> amnerf_tree_info:
@@ -396,12 +453,12 @@ def amnerf_error_stats(ctx, x_dev, ref_dev, sel_dev=None, stream=None):
 
 def amnerf_train_step(ctx, tree, train: amnerf_mlp_train, o_dev, d_dev, target_dev, loss_dev, s_max, step,
                       lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, ert_eps=1e-4, jitter=False, seed=0,
-                      grad_only=False, stream=None, hcheck_footprint=0.0):
+                      grad_only=False, stream=None, hcheck_footprint=0.0, f32=False):
     rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]))
     prm = amnerf_train_params(amnerf_render_params(s_max, ert_eps, AMNERF_JITTER if jitter else 0, seed, None,
                                                    hcheck_footprint),
                               amnerf_adam_params(lr, beta1, beta2, eps, step),
-                              AMNERF_GRAD_ONLY if grad_only else 0)
+                              (AMNERF_GRAD_ONLY if grad_only else 0) | (AMNERF_TRAIN_F32 if f32 else 0))
     _check(_lib.amnerf_train_step(ctx, tree, C.byref(train), C.byref(rays), _ptr(target_dev), C.byref(prm),
                                   _ptr(loss_dev), _stream(stream)))
 
@@ -481,11 +538,16 @@ def _handle(x):
 
 
 class Tree:
-    def __init__(self, ctx: Context, grid, n, max_depth, max_leaves, split=0):
+    def __init__(self, ctx: Context, grid, n, max_depth, max_leaves, split=0, handle=None):
         self.ctx = ctx
-        self.h = amnerf_build_tree(ctx.h, grid, n, max_depth, max_leaves, split)
+        self.h = handle if handle is not None else amnerf_build_tree(ctx.h, grid, n, max_depth, max_leaves, split)
         self.info = amnerf_tree_info_get(self.h)
         self.rows, self.mass = amnerf_tree_export(self.h)
+
+    @classmethod
+    def from_codes(cls, ctx: Context, grid, n, codes):
+        """The tree whose inner nodes are exactly the given node codes."""
+        return cls(ctx, None, n, 0, 0, handle=amnerf_build_tree_codes(ctx.h, grid, n, codes))
 
     @property
     def n_leaves(self):
@@ -555,21 +617,23 @@ def render(ctx: Context, tree: Tree, mlp: Mlp, o_dev, d_dev, s_max, ert_eps=1e-4
 class Trainer:
     """Float32 masters, gradient and Adam moments of a leaf-MLP set, plus its bf16 packed block."""
 
-    def __init__(self, ctx: Context, tree: Tree, master_dev, n_hidden, hidden, n_sets=None):
+    def __init__(self, ctx: Context, tree: Tree, master_dev, n_hidden, hidden, n_sets=None, f32=False):
         import torch
         self.ctx, self.tree = ctx, tree
+        self.f32 = f32
+        dt = AMNERF_F32 if f32 else AMNERF_BF16
         self.master = master_dev.contiguous()
         self.grad = torch.zeros_like(self.master)
         self.m = torch.zeros_like(self.master)
         self.v = torch.zeros_like(self.master)
         L = tree.n_leaves if n_sets is None else n_sets   # n_nodes for hierarchical sampling
-        nbytes = amnerf_mlp_packed_bytes(n_hidden, hidden, AMNERF_BF16, L)
+        nbytes = amnerf_mlp_packed_bytes(n_hidden, hidden, dt, L)
         self.packed = torch.empty(nbytes, dtype=torch.uint8, device=self.master.device)
-        amnerf_mlp_pack(ctx.h, n_hidden, hidden, AMNERF_BF16, L, self.master, self.packed)
+        amnerf_mlp_pack(ctx.h, n_hidden, hidden, dt, L, self.master, self.packed)
         self.desc = amnerf_mlp_train(amnerf_mlp_shape(n_hidden, hidden), L, C.c_void_p(self.master.data_ptr()),
                                      C.c_void_p(self.grad.data_ptr()), C.c_void_p(self.m.data_ptr()),
                                      C.c_void_p(self.v.data_ptr()), C.c_void_p(self.packed.data_ptr()))
-        self.mlp = amnerf_mlp(amnerf_mlp_shape(n_hidden, hidden), AMNERF_BF16, L, C.c_void_p(self.packed.data_ptr()))
+        self.mlp = amnerf_mlp(amnerf_mlp_shape(n_hidden, hidden), dt, L, C.c_void_p(self.packed.data_ptr()))
         self.loss = torch.zeros(1, dtype=torch.float32, device=self.master.device)
         self.step_no = 0
 
@@ -577,7 +641,7 @@ class Trainer:
         if not grad_only:
             self.step_no += 1
         amnerf_train_step(self.ctx.h, self.tree.h, self.desc, o_dev, d_dev, target_dev, self.loss, s_max,
-                          max(self.step_no, 1), lr=lr, grad_only=grad_only, **kw)
+                          max(self.step_no, 1), lr=lr, grad_only=grad_only, f32=self.f32, **kw)
         return self.loss
 
 

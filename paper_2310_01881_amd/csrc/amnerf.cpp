@@ -479,105 +479,113 @@ struct CandLess {
 
 }  // namespace
 
-extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
-                                 const amnerf_tree_params* p, amnerf_tree** out) {
-  if (!ctx || !grid || !p || !out) return fail(AMNERF_EINVAL, "amnerf_build_tree: null argument");
-  *out = nullptr;
+namespace {
+
+// Quantised grid (summed-volume table) and the growing node list of one tree build.
+struct TreeBuild {
+  int n = 0;
+  Svt S;
+  std::vector<HNode> nodes;
+  int leaves = 1;
+};
+
+int tree_build_begin(const float* grid, int32_t n, TreeBuild& B, const char* who) {
   if (n < 1 || n > 512 || (n & (n - 1)) != 0)
-    return fail(AMNERF_EINVAL, "amnerf_build_tree: grid side %d must be a power of two <= 512", n);
-  if (p->max_depth < 0 || p->max_depth > AMNERF_MAX_DEPTH)
-    return fail(AMNERF_EINVAL, "amnerf_build_tree: max_depth %d out of [0, %d]", p->max_depth, AMNERF_MAX_DEPTH);
-  if (p->split != AMNERF_SPLIT_MEDIAN && p->split != AMNERF_SPLIT_MIDDLE)
-    return fail(AMNERF_EINVAL, "amnerf_build_tree: bad split mode %d", p->split);
-  if (p->max_leaves < 1 || p->max_leaves > AMNERF_MAX_LEAVES)
-    return fail(AMNERF_EINVAL, "amnerf_build_tree: max_leaves %d out of [1, %d]", p->max_leaves, AMNERF_MAX_LEAVES);
+    return fail(AMNERF_EINVAL, "%s: grid side %d must be a power of two <= 512", who, n);
   const size_t ncell = (size_t)n * n * n;
   double gmax = 0.0;
   for (size_t i = 0; i < ncell; ++i) {
     float g = grid[i];
-    if (!std::isfinite(g)) return fail(AMNERF_EINVAL, "amnerf_build_tree: grid[%zu] is not finite", i);
+    if (!std::isfinite(g)) return fail(AMNERF_EINVAL, "%s: grid[%zu] is not finite", who, i);
     if ((double)g > gmax) gmax = g;
   }
-  Svt S;
-  S.n = n;
+  B.n = n;
+  B.S.n = n;
   try {
-    S.v.assign((size_t)(n + 1) * (n + 1) * (n + 1), 0ull);
+    B.S.v.assign((size_t)(n + 1) * (n + 1) * (n + 1), 0ull);
   } catch (...) {
-    return fail(AMNERF_ENOMEM, "amnerf_build_tree: summed-volume table");
+    return fail(AMNERF_ENOMEM, "%s: summed-volume table", who);
   }
   const size_t N1 = n + 1;
+  std::vector<uint64_t>& V = B.S.v;
   for (int k = 0; k < n; ++k)
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i) {
         double g = grid[(size_t)i + (size_t)n * ((size_t)j + (size_t)n * k)];
         uint64_t q = (gmax > 0.0 && g > 0.0) ? (uint64_t)std::floor(std::ldexp(g / gmax, 24) + 0.5) : 0ull;
         size_t o = ((size_t)(k + 1) * N1 + (j + 1)) * N1 + (i + 1);
-        S.v[o] = q + S.v[o - 1] + S.v[o - N1] + S.v[o - N1 * N1] - S.v[o - 1 - N1] - S.v[o - 1 - N1 * N1] -
-                 S.v[o - N1 - N1 * N1] + S.v[o - 1 - N1 - N1 * N1];
+        V[o] = q + V[o - 1] + V[o - N1] + V[o - N1 * N1] - V[o - 1 - N1] - V[o - 1 - N1 * N1] -
+               V[o - N1 - N1 * N1] + V[o - 1 - N1 - N1 * N1];
       }
-
-  std::vector<HNode> nodes;
-  nodes.reserve(2 * (size_t)p->max_leaves);
+  B.nodes.clear();
   HNode root;
   for (int a = 0; a < 3; ++a) { root.lo[a] = 0; root.hi[a] = n; }
   root.code = 1;
   root.depth = 0;
-  root.mass = S.box(root.lo, root.hi);
-  nodes.push_back(root);
-  auto splittable = [&](const HNode& nd) {
-    int a = longest_axis(nd);
-    return nd.depth < p->max_depth && nd.hi[a] - nd.lo[a] >= 2;
+  root.mass = B.S.box(root.lo, root.hi);
+  B.nodes.push_back(root);
+  B.leaves = 1;
+  return AMNERF_OK;
+}
+
+bool longest_side_splittable(const HNode& nd) {
+  int a = longest_axis(nd);
+  return nd.hi[a] - nd.lo[a] >= 2;
+}
+
+// Splits leaf idx on its longest side: at the first cell plane whose lower side holds at
+// least half of the node's mass (the last plane if none; the middle plane for a massless
+// node), or at the middle plane.  Returns the index of the lower child (the upper follows).
+int tree_split(TreeBuild& B, int idx, bool middle) {
+  HNode nd = B.nodes[idx];
+  const int a = longest_axis(nd);
+  const int lo = nd.lo[a], hi = nd.hi[a];
+  int plane;
+  auto lower_mass = [&](int pl) {
+    int h2[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
+    h2[a] = pl;
+    return B.S.box(nd.lo, h2);
   };
-  const bool middle = p->split == AMNERF_SPLIT_MIDDLE;
-  auto prio = [&](const HNode& nd) { return middle ? (uint64_t)(64 - nd.depth) : nd.mass; };
-  std::priority_queue<Cand, std::vector<Cand>, CandLess> pq;
-  if (splittable(nodes[0])) pq.push({prio(nodes[0]), 1u, 0});
-  int leaves = 1;
-  while (leaves < p->max_leaves && !pq.empty()) {
-    Cand c = pq.top();
-    pq.pop();
-    HNode nd = nodes[c.idx];
-    const int a = longest_axis(nd);
-    const int lo = nd.lo[a], hi = nd.hi[a];
-    int plane;
-    auto lower_mass = [&](int pl) {
-      int h2[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
-      h2[a] = pl;
-      return S.box(nd.lo, h2);
-    };
-    if (middle || nd.mass == 0) {
-      plane = (lo + hi) / 2;
-    } else {
-      // smallest plane in [lo+1, hi-1] with 2 * lower mass >= node mass (binary search on
-      // the monotone lower mass); the last plane when none qualifies
-      int L = lo + 1, R = hi - 1, ans = hi - 1;
-      while (L <= R) {
-        int mid = (L + R) / 2;
-        if (2 * lower_mass(mid) >= nd.mass) { ans = mid; R = mid - 1; }
-        else L = mid + 1;
-      }
-      plane = ans;
+  if (middle || nd.mass == 0) {
+    plane = (lo + hi) / 2;
+  } else {
+    // smallest plane in [lo+1, hi-1] with 2 * lower mass >= node mass (binary search on
+    // the monotone lower mass); the last plane when none qualifies
+    int L = lo + 1, R = hi - 1, ans = hi - 1;
+    while (L <= R) {
+      int mid = (L + R) / 2;
+      if (2 * lower_mass(mid) >= nd.mass) { ans = mid; R = mid - 1; }
+      else L = mid + 1;
     }
-    HNode lc = nd, rc = nd;
-    lc.hi[a] = plane;
-    rc.lo[a] = plane;
-    lc.code = 2 * nd.code;
-    rc.code = 2 * nd.code + 1;
-    lc.depth = rc.depth = nd.depth + 1;
-    lc.axis = rc.axis = lc.plane = rc.plane = lc.left = rc.left = -1;
-    lc.mass = S.box(lc.lo, lc.hi);
-    rc.mass = nd.mass - lc.mass;
-    int li = (int)nodes.size();
-    nodes[c.idx].axis = a;
-    nodes[c.idx].plane = plane;
-    nodes[c.idx].left = li;
-    nodes.push_back(lc);
-    nodes.push_back(rc);
-    ++leaves;
-    if (splittable(nodes[li])) pq.push({prio(nodes[li]), nodes[li].code, li});
-    if (splittable(nodes[li + 1])) pq.push({prio(nodes[li + 1]), nodes[li + 1].code, li + 1});
+    plane = ans;
   }
-  // slots: left-first depth-first order (leaves among leaves; every node among all nodes)
+  HNode lc = nd, rc = nd;
+  lc.hi[a] = plane;
+  rc.lo[a] = plane;
+  lc.code = 2 * nd.code;
+  rc.code = 2 * nd.code + 1;
+  lc.depth = rc.depth = nd.depth + 1;
+  lc.axis = rc.axis = lc.plane = rc.plane = lc.left = rc.left = -1;
+  lc.mass = B.S.box(lc.lo, lc.hi);
+  rc.mass = nd.mass - lc.mass;
+  int li = (int)B.nodes.size();
+  B.nodes[idx].axis = a;
+  B.nodes[idx].plane = plane;
+  B.nodes[idx].left = li;
+  B.nodes.push_back(lc);
+  B.nodes.push_back(rc);
+  ++B.leaves;
+  return li;
+}
+
+// Slots, the exported rows and the device tables of the nodes built; uploads them.
+int tree_build_finish(amnerf_ctx* ctx, TreeBuild& B, amnerf_tree** out, const char* who) {
+  std::vector<HNode>& nodes = B.nodes;
+  const int n = B.n;
+  const int leaves = B.leaves;
+  // slots: left-first depth-first order (leaves among leaves; every node among all nodes);
+  // a node split since an earlier finish loses its leaf slot
+  for (HNode& nd : nodes) nd.slot = -1;
   int next_slot = 0, next_nslot = 0, max_depth = 0;
   std::vector<int> stack = {0};
   while (!stack.empty()) {
@@ -593,7 +601,7 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
     }
   }
   amnerf_tree* t = new (std::nothrow) amnerf_tree();
-  if (!t) return fail(AMNERF_ENOMEM, "amnerf_build_tree: host allocation");
+  if (!t) return fail(AMNERF_ENOMEM, "%s: host allocation", who);
   t->device = ctx->device;
   t->grid_n = n;
   t->n_leaves = leaves;
@@ -611,7 +619,7 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
     for (int a = 0; a < 3; ++a) { r[2 + a] = nd.lo[a]; r[5 + a] = nd.hi[a]; }
     r[8] = nd.left < 0 ? -1 : nd.axis;
     r[9] = nd.left < 0 ? -1 : nd.plane;
-    r[10] = nd.slot;
+    r[10] = nd.left < 0 ? nd.slot : -1;
     r[11] = nd.nslot;
     t->mass[k] = nd.mass;
   }
@@ -663,10 +671,70 @@ extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
     if (t->dev_leafbox) (void)hipFree(t->dev_leafbox);
     if (t->dev_ahs) (void)hipFree(t->dev_ahs);
     delete t;
-    return fail(AMNERF_EDEVICE, "amnerf_build_tree: upload: %s", hipGetErrorString(e));
+    return fail(AMNERF_EDEVICE, "%s: upload: %s", who, hipGetErrorString(e));
   }
   *out = t;
   return AMNERF_OK;
+}
+
+// Index of the node with the given code, or -1.
+int find_code(const TreeBuild& B, uint32_t code) {
+  for (size_t i = 0; i < B.nodes.size(); ++i)
+    if (B.nodes[i].code == code) return (int)i;
+  return -1;
+}
+
+}  // namespace
+
+extern "C" int amnerf_build_tree(amnerf_ctx* ctx, const float* grid, int32_t n,
+                                 const amnerf_tree_params* p, amnerf_tree** out) {
+  if (!ctx || !grid || !p || !out) return fail(AMNERF_EINVAL, "amnerf_build_tree: null argument");
+  *out = nullptr;
+  if (p->max_depth < 0 || p->max_depth > AMNERF_MAX_DEPTH)
+    return fail(AMNERF_EINVAL, "amnerf_build_tree: max_depth %d out of [0, %d]", p->max_depth, AMNERF_MAX_DEPTH);
+  if (p->split != AMNERF_SPLIT_MEDIAN && p->split != AMNERF_SPLIT_MIDDLE)
+    return fail(AMNERF_EINVAL, "amnerf_build_tree: bad split mode %d", p->split);
+  if (p->max_leaves < 1 || p->max_leaves > AMNERF_MAX_LEAVES)
+    return fail(AMNERF_EINVAL, "amnerf_build_tree: max_leaves %d out of [1, %d]", p->max_leaves, AMNERF_MAX_LEAVES);
+  TreeBuild B;
+  int rc = tree_build_begin(grid, n, B, "amnerf_build_tree");
+  if (rc) return rc;
+  B.nodes.reserve(2 * (size_t)p->max_leaves);
+  auto splittable = [&](const HNode& nd) { return nd.depth < p->max_depth && longest_side_splittable(nd); };
+  const bool middle = p->split == AMNERF_SPLIT_MIDDLE;
+  auto prio = [&](const HNode& nd) { return middle ? (uint64_t)(64 - nd.depth) : nd.mass; };
+  std::priority_queue<Cand, std::vector<Cand>, CandLess> pq;
+  if (splittable(B.nodes[0])) pq.push({prio(B.nodes[0]), 1u, 0});
+  while (B.leaves < p->max_leaves && !pq.empty()) {
+    Cand c = pq.top();
+    pq.pop();
+    const int li = tree_split(B, c.idx, middle);
+    if (splittable(B.nodes[li])) pq.push({prio(B.nodes[li]), B.nodes[li].code, li});
+    if (splittable(B.nodes[li + 1])) pq.push({prio(B.nodes[li + 1]), B.nodes[li + 1].code, li + 1});
+  }
+  return tree_build_finish(ctx, B, out, "amnerf_build_tree");
+}
+
+extern "C" int amnerf_build_tree_codes(amnerf_ctx* ctx, const float* grid, int32_t n, const uint32_t* codes,
+                                       int32_t n_codes, amnerf_tree** out) {
+  if (!ctx || !grid || !out || n_codes < 0 || (n_codes > 0 && !codes))
+    return fail(AMNERF_EINVAL, "amnerf_build_tree_codes: bad argument");
+  *out = nullptr;
+  if (n_codes + 1 > AMNERF_MAX_LEAVES)
+    return fail(AMNERF_EINVAL, "amnerf_build_tree_codes: %d splits exceed %d leaves", n_codes, AMNERF_MAX_LEAVES);
+  TreeBuild B;
+  int rc = tree_build_begin(grid, n, B, "amnerf_build_tree_codes");
+  if (rc) return rc;
+  std::vector<uint32_t> sorted(codes, codes + n_codes);
+  std::sort(sorted.begin(), sorted.end());
+  for (uint32_t code : sorted) {
+    const int at = find_code(B, code);
+    if (at < 0 || B.nodes[at].left >= 0 || !longest_side_splittable(B.nodes[at]) ||
+        B.nodes[at].depth >= AMNERF_MAX_DEPTH)
+      return fail(AMNERF_EINVAL, "amnerf_build_tree_codes: code %u is not a splittable leaf", code);
+    tree_split(B, at, false);
+  }
+  return tree_build_finish(ctx, B, out, "amnerf_build_tree_codes");
 }
 
 extern "C" int amnerf_tree_info_get(const amnerf_tree* t, amnerf_tree_info* out) {
@@ -1418,9 +1486,10 @@ extern "C" int amnerf_train_step(amnerf_ctx* ctx, const amnerf_tree* tree, amner
     return fail(AMNERF_EINVAL, "amnerf_train_step: null parameter buffer");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
+  const int32_t dtype = (p->flags & AMNERF_TRAIN_F32) ? AMNERF_F32 : AMNERF_BF16;
   amnerf_mlp mlp;
   mlp.shape = m->shape;
-  mlp.dtype = AMNERF_BF16;
+  mlp.dtype = dtype;
   mlp.n_leaves = m->n_leaves;
   mlp.packed_dev = m->packed_dev;
   const uint64_t R = (uint64_t)rays->n_rays;
@@ -1454,13 +1523,189 @@ extern "C" int amnerf_train_step(amnerf_ctx* ctx, const amnerf_tree* tree, amner
     const int64_t n = (int64_t)m->n_leaves * amnerf_mlp_param_count(&m->shape);
     rc = amnerf_adam_step(ctx, n, m->master_dev, m->m_dev, m->v_dev, m->grad_dev, &p->adam, stream);
     if (rc) return rc;
-    rc = amnerf_mlp_pack(ctx, &m->shape, AMNERF_BF16, m->n_leaves, m->master_dev, m->packed_dev, stream);
+    rc = amnerf_mlp_pack(ctx, &m->shape, dtype, m->n_leaves, m->master_dev, m->packed_dev, stream);
     if (rc) return rc;
   }
   if (ev) {
     HIP_TRY(hipEventRecord(ev->ev[kBwdStages], st));
     ev->pending = true;
   }
+  return AMNERF_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// distillation-driven subdivision (Section 3.4, TestLeaf)
+// ---------------------------------------------------------------------------------------
+namespace {
+
+struct Distiller {
+  amnerf_ctx* ctx = nullptr;
+  const amnerf_testleaf_params* p = nullptr;
+  int32_t dtype = AMNERF_BF16;
+  int64_t P = 0;
+  float *master = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr, *loss = nullptr, *rgb = nullptr;
+  void* packed = nullptr;
+  ~Distiller() {
+    for (void* q : {(void*)master, (void*)grad, (void*)m, (void*)v, (void*)loss, (void*)rgb, packed})
+      if (q) (void)hipFree(q);
+  }
+};
+
+// PSNR of the evaluation rays after n_max distillation steps of one parameter set per leaf of
+// `tree`, every set starting from the same initial parameters.
+int distil_psnr(Distiller& D, const amnerf_tree* tree, double* psnr) {
+  const amnerf_testleaf_params* p = D.p;
+  const int32_t L = tree->n_leaves;
+  const size_t bytes = (size_t)D.P * 4;
+  const hipStream_t st = nullptr;
+  // tile the initial set over the leaves by doubling copies
+  HIP_TRY(hipMemcpyAsync(D.master, p->init_dev, bytes, hipMemcpyDeviceToDevice, st));
+  for (int32_t have = 1; have < L;) {
+    const int32_t k = std::min(have, L - have);
+    HIP_TRY(hipMemcpyAsync(D.master + (size_t)have * D.P, D.master, bytes * k, hipMemcpyDeviceToDevice, st));
+    have += k;
+  }
+  HIP_TRY(hipMemsetAsync(D.m, 0, bytes * L, st));
+  HIP_TRY(hipMemsetAsync(D.v, 0, bytes * L, st));
+  int rc = amnerf_mlp_pack(D.ctx, &p->student, D.dtype, L, D.master, D.packed, st);
+  if (rc) return rc;
+  amnerf_mlp_train mt;
+  mt.shape = p->student;
+  mt.n_leaves = L;
+  mt.master_dev = D.master;
+  mt.grad_dev = D.grad;
+  mt.m_dev = D.m;
+  mt.v_dev = D.v;
+  mt.packed_dev = D.packed;
+  for (int32_t s = 1; s <= p->n_max; ++s) {
+    amnerf_train_params tp;
+    tp.render = p->render;
+    tp.adam.lr = p->lr;
+    tp.adam.beta1 = 0.9f;
+    tp.adam.beta2 = 0.999f;
+    tp.adam.eps = 1e-8f;
+    tp.adam.step = s;
+    tp.flags = D.dtype == AMNERF_F32 ? AMNERF_TRAIN_F32 : 0u;
+    const int32_t b = (s - 1) % p->n_batches;
+    rc = amnerf_train_step(D.ctx, tree, &mt, &p->batches[b], p->targets[b], &tp, D.loss, st);
+    if (rc) return rc;
+  }
+  amnerf_mlp mlp;
+  mlp.shape = p->student;
+  mlp.dtype = D.dtype;
+  mlp.n_leaves = L;
+  mlp.packed_dev = D.packed;
+  amnerf_render_out ro = {D.rgb, nullptr, nullptr, nullptr};
+  rc = amnerf_render(D.ctx, tree, &mlp, &p->eval, &p->render, &ro, st);
+  if (rc) return rc;
+  double e[4];
+  rc = amnerf_error_stats(D.ctx, D.rgb, p->eval_target_dev, nullptr, 3 * (int64_t)p->eval.n_rays, e, st);
+  if (rc) return rc;
+  *psnr = e[1] > 0.0 ? 10.0 * std::log10(e[2] / e[1]) : INFINITY;
+  return AMNERF_OK;
+}
+
+}  // namespace
+
+extern "C" int amnerf_build_tree_distilled(amnerf_ctx* ctx, const float* grid, int32_t n, int32_t max_depth,
+                                           int32_t max_leaves, const amnerf_testleaf_params* p, amnerf_tree** out,
+                                           amnerf_testleaf_record* log, int32_t log_cap, int32_t* n_log) {
+  const char* who = "amnerf_build_tree_distilled";
+  if (!ctx || !grid || !p || !out || log_cap < 0 || (log_cap > 0 && !log))
+    return fail(AMNERF_EINVAL, "%s: null argument", who);
+  *out = nullptr;
+  if (n_log) *n_log = 0;
+  if (max_depth < 0 || max_depth > AMNERF_MAX_DEPTH || max_leaves < 1 || max_leaves > AMNERF_MAX_LEAVES)
+    return fail(AMNERF_EINVAL, "%s: max_depth %d / max_leaves %d out of range", who, max_depth, max_leaves);
+  const int64_t P = amnerf_mlp_param_count(&p->student);
+  if (P <= 0) return fail(AMNERF_EINVAL, "%s: bad student shape", who);
+  if (!mlp_bwd_supported(p->student.n_hidden, p->student.hidden))
+    return fail(AMNERF_EINVAL, "%s: the student's backward needs n_hidden 1 .. 4 and hidden 32 or 64", who);
+  if (!p->init_dev || p->n_max < 0 || (p->n_max > 0 && (p->n_batches < 1 || !p->batches || !p->targets)) ||
+      !(p->lr >= 0.f) || !std::isfinite(p->gain_thresh) || p->eval.n_rays < 1 || !p->eval_target_dev)
+    return fail(AMNERF_EINVAL, "%s: bad distillation parameters", who);
+  if (p->render.proposal || p->render.occupancy || p->render.hcheck_footprint != 0.f)
+    return fail(AMNERF_EINVAL, "%s: distillation renders take no proposal, occupancy or footprint", who);
+  for (int32_t b = 0; b < (p->n_max > 0 ? p->n_batches : 0); ++b)
+    if (!p->targets[b] || p->batches[b].n_rays < 1)
+      return fail(AMNERF_EINVAL, "%s: batch %d is empty or has no targets", who, b);
+  HIP_TRY(hipSetDevice(ctx->device));
+  Distiller D;
+  D.ctx = ctx;
+  D.p = p;
+  D.dtype = (p->flags & AMNERF_TESTLEAF_F32) ? AMNERF_F32 : AMNERF_BF16;
+  D.P = P;
+  size_t packed_bytes = 0;
+  int rc = amnerf_mlp_packed_bytes(&p->student, D.dtype, max_leaves, &packed_bytes);
+  if (rc) return rc;
+  const size_t pb = (size_t)P * 4 * max_leaves;
+  HIP_TRY(hipMalloc((void**)&D.master, pb));
+  HIP_TRY(hipMalloc((void**)&D.grad, pb));
+  HIP_TRY(hipMalloc((void**)&D.m, pb));
+  HIP_TRY(hipMalloc((void**)&D.v, pb));
+  HIP_TRY(hipMalloc((void**)&D.loss, 4));
+  HIP_TRY(hipMalloc((void**)&D.rgb, 12 * (size_t)p->eval.n_rays));
+  HIP_TRY(hipMalloc(&D.packed, packed_bytes));
+
+  TreeBuild B;
+  rc = tree_build_begin(grid, n, B, who);
+  if (rc) return rc;
+  amnerf_tree* current = nullptr;
+  rc = tree_build_finish(ctx, B, &current, who);
+  if (rc) return rc;
+  double psnr_cur = 0.0;
+  rc = distil_psnr(D, current, &psnr_cur);
+  int32_t logged = 0;
+  // BuildKDTree: the node, then its lower subtree, then its upper subtree (explicit stack)
+  std::vector<uint32_t> todo = {1u};
+  while (rc == AMNERF_OK && !todo.empty()) {
+    const uint32_t code = todo.back();
+    todo.pop_back();
+    const int at = find_code(B, code);
+    const HNode nd = B.nodes[at];
+    if (nd.depth >= max_depth || !longest_side_splittable(nd) || B.leaves >= max_leaves) continue;
+    const std::vector<HNode> saved = B.nodes;
+    const int saved_leaves = B.leaves;
+    tree_split(B, at, false);
+    amnerf_tree* trial = nullptr;
+    rc = tree_build_finish(ctx, B, &trial, who);
+    if (rc) break;
+    double psnr_t = 0.0;
+    rc = distil_psnr(D, trial, &psnr_t);
+    if (rc) {
+      amnerf_tree_destroy(trial);
+      break;
+    }
+    const bool kept = psnr_t - psnr_cur >= (double)p->gain_thresh * psnr_cur;
+    if (logged < log_cap) {
+      amnerf_testleaf_record& r = log[logged];
+      r.code = code;
+      r.depth = nd.depth;
+      r.leaves_of_trial = B.leaves;
+      r.kept = kept ? 1 : 0;
+      r.psnr_current = psnr_cur;
+      r.psnr_split = psnr_t;
+    }
+    ++logged;
+    if (!kept) {
+      amnerf_tree_destroy(trial);
+      B.nodes = saved;
+      B.leaves = saved_leaves;
+      continue;
+    }
+    amnerf_tree_destroy(current);
+    current = trial;
+    psnr_cur = psnr_t;
+    todo.push_back(2 * code + 1);
+    todo.push_back(2 * code);
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  if (rc) {
+    amnerf_tree_destroy(current);
+    return rc;
+  }
+  if (n_log) *n_log = logged;
+  *out = current;
   return AMNERF_OK;
 }
 
