@@ -2,12 +2,12 @@
 // accumulation), the differentiable counterpart of the grouped forward in mlp.hip.
 //
 // Work item: a segment of at most kSegTiles consecutive 256-row tiles of one leaf, each
-// processed as two 128-row sub-tiles.  Every wave (32 rows) recomputes its forward
-// activations (none are stored
-// between the forward and backward passes) and keeps each layer's bfloat16 input in
-// registers in B-operand order.  Then, from the output layer down:
+// processed by a block of 16 waves (4 per SIMD: one block fills a compute unit), 16 rows per
+// wave.  Every wave recomputes its forward activations (none are stored between the forward
+// and backward passes) and keeps each layer's bfloat16 input in registers in B-operand
+// order.  Then, from the output layer down:
 //   * dZ_l (gradient at layer l's pre-activation) and the layer's input H_{l-1} are staged
-//     feature-major in LDS ([feature][128 samples], rows padded by 16 bytes), and the four
+//     feature-major in LDS ([feature][256 samples], rows padded by 16 bytes), and the
 //     waves accumulate dW_l = sum_samples dZ_l H_{l-1}^T on MFMA with K = samples (and
 //     db_l = sum_samples dZ_l against a ones operand);
 //   * dH_{l-1} = W_l^T dZ_l runs on MFMA in registers (transposed weights packed in the
@@ -22,10 +22,15 @@
 namespace amn {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kNCB = 2;                          // 16-sample column blocks per wave
-constexpr int kTileRows = kMlpTileRows;          // 256-row tiles of the forward pass ...
-constexpr int kSubRows = 4 * 16 * kNCB;          // ... processed as 128-row sub-tiles
+constexpr int kThreads = 256;                    // the float32 kernel's block
+constexpr int kWavesB = 16;                      // waves of a bfloat16 block (4 per SIMD)
+constexpr int kThreadsB = 64 * kWavesB;
+constexpr int kNCB = 1;                          // 16-sample column blocks per wave
+constexpr int kTileRows = kMlpTileRows;          // 256-row tiles of the forward pass, each
+constexpr int kSubRows = kWavesB * 16 * kNCB;    // processed as one sub-tile of 16 rows per wave
+constexpr int kSubPerTile = kTileRows / kSubRows;
+constexpr int kItemsB = (16 + kWavesB - 1) / kWavesB;   // dW items per wave and layer, at most
+static_assert(kTileRows % kSubRows == 0, "sub-tiles must divide a tile");
 constexpr int kRowBytes = kSubRows * 2 + 16;     // staged feature row (bf16) + padding
 
 __device__ __forceinline__ void stage(uint8_t* base, int row, int col, __bf16 v) {
@@ -39,7 +44,7 @@ __device__ __forceinline__ bool pos_bf16(__bf16 v) {
 }
 
 template <int H, int NH>
-__global__ __launch_bounds__(kThreads) void k_mlp_bwd(
+__global__ __launch_bounds__(kThreadsB) void k_mlp_bwd(
     Layout L, const uint8_t* __restrict__ packed_fwd, const uint8_t* __restrict__ packed_bwd,
     uint32_t n_leaves, const uint32_t* __restrict__ bucket_off,
     const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ seg_off,
@@ -75,23 +80,23 @@ __global__ __launch_bounds__(kThreads) void k_mlp_bwd(
     if ((int)b != cur) {
       __syncthreads();
       const f32x4* s1 = reinterpret_cast<const f32x4*>(packed_fwd + (uint64_t)b * L.bytes);
-      for (uint32_t i = tid; i < L.bytes / 16; i += kThreads) reinterpret_cast<f32x4*>(w_fwd)[i] = s1[i];
+      for (uint32_t i = tid; i < L.bytes / 16; i += kThreadsB) reinterpret_cast<f32x4*>(w_fwd)[i] = s1[i];
       const f32x4* s2 = reinterpret_cast<const f32x4*>(packed_bwd + (uint64_t)b * L.bwd_bytes);
-      for (uint32_t i = tid; i < L.bwd_bytes / 16; i += kThreads) reinterpret_cast<f32x4*>(w_bwd)[i] = s2[i];
+      for (uint32_t i = tid; i < L.bwd_bytes / 16; i += kThreadsB) reinterpret_cast<f32x4*>(w_bwd)[i] = s2[i];
       __syncthreads();
       cur = (int)b;
     }
-    f32x4 accW[NH + 1][4];
+    f32x4 accW[NH + 1][kItemsB];
     f32x4 accB[NH + 1];
 #pragma unroll
     for (int l = 0; l <= NH; ++l) {
       accB[l] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) accW[l][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int q = 0; q < kItemsB; ++q) accW[l][q] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
 
-    for (uint32_t sub = 2 * t_first; sub < 2 * t_last; ++sub) {
-      const uint32_t row0 = bucket_off[b] + (sub - 2 * tile_off[b]) * kSubRows + wave * (16 * kNCB);
+    for (uint32_t sub = kSubPerTile * t_first; sub < kSubPerTile * t_last; ++sub) {
+      const uint32_t row0 = bucket_off[b] + (sub - kSubPerTile * tile_off[b]) * kSubRows + wave * (16 * kNCB);
       const uint32_t row_end = bucket_off[b + 1];
       // ---- forward recompute: layer inputs in B-operand order ----
       bf16x8 X0[kNCB];
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_bwd(
         const int rbo = l == NH ? 1 : RB;          // row blocks of this layer's outputs
         const int cbi = l == 0 ? 2 : RB;           // 16-column blocks of its inputs
         const int n_items = rbo * cbi;
-        const int per = (n_items + 3) / 4;
+        const int per = (n_items + kWavesB - 1) / kWavesB;
         // stage dZ_l and the layer input, feature-major
         __syncthreads();
 #pragma unroll
@@ -202,9 +207,9 @@ __global__ __launch_bounds__(kThreads) void k_mlp_bwd(
           }
         }
         __syncthreads();
-        // dW_l += dZ_l H^T, db_l += dZ_l 1 over the sub-tile's 128 samples
+        // dW_l += dZ_l H^T, db_l += dZ_l 1 over the sub-tile's samples
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kItemsB; ++q) {
           const int item = wave * per + q;
           if (q >= per || item >= n_items) break;
           const int rb = item / cbi, ci = item % cbi;
@@ -262,11 +267,11 @@ __global__ __launch_bounds__(kThreads) void k_mlp_bwd(
       const int rbo = l == NH ? 1 : RB;
       const int cbi = l == 0 ? 2 : RB;
       const int n_items = rbo * cbi;
-      const int per = (n_items + 3) / 4;
+      const int per = (n_items + kWavesB - 1) / kWavesB;
       int din, dout, off_w, off_b;
       master_offsets(NH, H, l, din, dout, off_w, off_b);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < kItemsB; ++q) {
         const int item = wave * per + q;
         if (q >= per || item >= n_items) break;
         const int rb = item / cbi, ci = item % cbi;
@@ -517,11 +522,11 @@ hipError_t launch_bwd_typed(const Layout& L, const void* packed, uint32_t n_leav
   auto kern = k_mlp_bwd<H, NH>;
   const uint32_t lds = L.bytes + L.bwd_bytes + 2u * H * kRowBytes;
   int grid = 0;
-  hipError_t e = persistent_grid((const void*)kern, kThreads, lds, &grid);
+  hipError_t e = persistent_grid((const void*)kern, kThreadsB, lds, &grid);
   if (e != hipSuccess) return e;
   const uint8_t* pf = (const uint8_t*)packed;
   const uint8_t* pb = pf + (uint64_t)n_leaves * L.bytes;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, L, pf, pb, n_leaves, bucket_off, tile_off,
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreadsB), lds, st, L, pf, pb, n_leaves, bucket_off, tile_off,
                      seg_off, srec_ray, srec_t, perm, o, d, stride, r0, gpre, part,
                      master_param_count(NH, H));
   return hipGetLastError();
