@@ -192,6 +192,119 @@ __device__ __forceinline__ void item_features(const IvSet& iv, uint32_t i, const
 }
 
 // ---- inference: tau^[item][32] --------------------------------------------------------
+// Pieces of the bfloat16 network.
+// The first layer's B operand of one column block: lane (g, m) evaluates its own 16
+// inputs of item m (see bf16_in_feature).
+__device__ __forceinline__ void prop_bf16_inputs(const float oo[3], const float dd[3], float t0, float t1,
+                                                 const float box[3], uint32_t k, int s_max, int g, bf16x8 X[2]) {
+  const float tt = g == 2 ? t0 : t1;
+  const float half_f = (g & 1) ? 1.f : 0.5f;   // revolutions per unit of v
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float q = (oo[a] - 0.5f) * 0.5f;
+    const float v = g < 2 ? q : dd[a];
+    const float x = 2.f * fmaf(tt, dd[a], oo[a]) - 1.f;
+    X[0][a] = (__bf16)__builtin_amdgcn_sinf(half_f * v);
+    X[0][3 + a] = (__bf16)__builtin_amdgcn_cosf(half_f * v);
+    X[1][a] = (__bf16)(g == 0 ? q : (g == 1 ? dd[a] : x));
+    X[1][3 + a] = (__bf16)(g < 2 ? box[a] : 0.f);
+  }
+  X[0][6] = (__bf16)(g == 0 ? (float)k / (float)s_max : 0.f);
+  X[0][7] = (__bf16)0.f;
+  X[1][6] = (__bf16)0.f;
+  X[1][7] = (__bf16)0.f;
+}
+
+// The three layers on MFMA for NCB column blocks: acc[cb][rb] holds the 32 output
+// pre-activations (rb = 0, 1) of the items of column block cb.
+template <int NCB>
+__device__ __forceinline__ void prop_bf16_net(const uint8_t* units, const float* bias, int g, int lane,
+                                              const bf16x8 X[NCB][2], f32x4 acc[NCB][4]) {
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
+#pragma unroll
+    for (int ku = 0; ku < 2; ++ku) {
+      const bf16x8 A = *reinterpret_cast<const bf16x8*>(units + bf16_unit(0, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, X[cb][ku], ku == 0 ? bv : acc[cb][rb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int layer = 1; layer <= 2; ++layer) {
+    bf16x8 Bv[NCB][2];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int ku = 0; ku < 2; ++ku) {
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = acc[cb][2 * ku + e / 4][e % 4];
+        Bv[cb][ku] = relu_bf16x8(v);
+      }
+    const int nrb = layer == 1 ? 4 : 2;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      if (rb >= nrb) break;
+      const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + layer * kH + 16 * rb + 4 * g);
+#pragma unroll
+      for (int ku = 0; ku < 2; ++ku) {
+        const bf16x8 A = *reinterpret_cast<const bf16x8*>(units + bf16_unit(layer, rb, ku) * kUnitBytes + lane * 16);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv[cb][ku], ku == 0 ? bv : acc[cb][rb], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// Output of one column: v = the 32 bin thicknesses (rows 16 rb + 4 g + e), or with cum set
+// the bins' local composited weights w_b = exp(-P_(b-1)) (1 - exp(-tau_b)), P_b = tau_0 +
+// ... + tau_b, and the interval's total P_31 (valid in lane group 3).  Lane group g holds
+// bins 4g..4g+3 and 16+4g..16+4g+3 of its column, so the offsets of its two runs are sums
+// over the lower groups, gathered 16 and 32 lanes down the wave; within a run the
+// transmittance steps by exp(-tau_b).
+template <bool BF16>
+__device__ __forceinline__ float prop_outputs(const f32x4 acc[4], int cum, int g, int m, f32x4 v[2]) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[rb][e] = BF16 ? softplus_fast(acc[rb][e]) : softplusf(acc[rb][e]);
+  float total = 0.f;
+  if (cum) {
+    float run[2], off[2], last[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      float x = v[rb][0] + v[rb][1];
+      x += v[rb][2];
+      x += v[rb][3];
+      last[rb] = x;                      // this lane's run total
+      float y = __shfl_up(x, 16, 64);
+      x += g >= 1 ? y : 0.f;
+      y = __shfl_up(x, 32, 64);
+      x += g >= 2 ? y : 0.f;
+      run[rb] = x;                       // inclusive over groups 0..g
+      off[rb] = x - last[rb];
+    }
+    const float tot0 = __shfl(run[0], 48 + m, 64);
+    const float start[2] = {off[0], tot0 + off[1]};
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      float T = exp_neg(start[rb]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float tb = v[rb][e];
+        const float eb = exp_neg(tb);
+        v[rb][e] = T * one_minus_exp_neg(tb, eb);
+        T *= eb;
+      }
+    }
+    total = last[1] + (tot0 + off[1]);   // P_31 in lane group 3
+  }
+  return total;
+}
+
 template <bool BF16>
 __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict__ packed, IvSet iv,
                                                        const float* __restrict__ o, const float* __restrict__ d,
@@ -254,66 +367,8 @@ __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict
       }
       if ((tile + gridDim.x) * kTile < n_items) load_records(tile + gridDim.x);
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        const uint32_t k = c_k[cb];
-        const float* oo = c_o[cb];
-        const float* dd = c_d[cb];
-        const float t0 = c_t0[cb], t1 = c_t1[cb];
-        const float* box = c_box[cb];
-        const float tt = g == 2 ? t0 : t1;
-        const float half_f = (g & 1) ? 1.f : 0.5f;   // revolutions per unit of v
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const float q = (oo[a] - 0.5f) * 0.5f;
-          const float v = g < 2 ? q : dd[a];
-          const float x = 2.f * fmaf(tt, dd[a], oo[a]) - 1.f;
-          X[cb][0][a] = (__bf16)__builtin_amdgcn_sinf(half_f * v);
-          X[cb][0][3 + a] = (__bf16)__builtin_amdgcn_cosf(half_f * v);
-          X[cb][1][a] = (__bf16)(g == 0 ? q : (g == 1 ? dd[a] : x));
-          X[cb][1][3 + a] = (__bf16)(g < 2 ? box[a] : 0.f);
-        }
-        X[cb][0][6] = (__bf16)(g == 0 ? (float)k / (float)s_max : 0.f);
-        X[cb][0][7] = (__bf16)0.f;
-        X[cb][1][6] = (__bf16)0.f;
-        X[cb][1][7] = (__bf16)0.f;
-      }
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + 16 * rb + 4 * g);
-#pragma unroll
-        for (int ku = 0; ku < 2; ++ku) {
-          const bf16x8 A = *reinterpret_cast<const bf16x8*>(units + bf16_unit(0, rb, ku) * kUnitBytes + lane * 16);
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb)
-            acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, X[cb][ku], ku == 0 ? bv : acc[cb][rb], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int layer = 1; layer <= 2; ++layer) {
-        bf16x8 Bv[NCB][2];
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-          for (int ku = 0; ku < 2; ++ku) {
-            float v[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = acc[cb][2 * ku + e / 4][e % 4];
-            Bv[cb][ku] = relu_bf16x8(v);
-          }
-        const int nrb = layer == 1 ? 4 : 2;
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-          if (rb >= nrb) break;
-          const f32x4 bv = *reinterpret_cast<const f32x4*>(bias + layer * kH + 16 * rb + 4 * g);
-#pragma unroll
-          for (int ku = 0; ku < 2; ++ku) {
-            const bf16x8 A = *reinterpret_cast<const bf16x8*>(units + bf16_unit(layer, rb, ku) * kUnitBytes + lane * 16);
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb)
-              acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv[cb][ku], ku == 0 ? bv : acc[cb][rb], 0, 0, 0);
-          }
-        }
-      }
+      for (int cb = 0; cb < NCB; ++cb) prop_bf16_inputs(c_o[cb], c_d[cb], c_t0[cb], c_t1[cb], c_box[cb], c_k[cb], s_max, g, X[cb]);
+      prop_bf16_net<NCB>(units, bias, g, lane, X, acc);
     } else {
       float X[NCB][12];
 #pragma unroll
@@ -372,51 +427,13 @@ __global__ __launch_bounds__(kThreads) void k_prop_fwd(const uint8_t* __restrict
             if (rb < nrb) acc[cb][rb] = nacc[cb][rb];
       }
     }
-    // outputs: rows 16 rb + 4 g + e of the 32 bins.  With cum set (rendering), the bins'
-    // local composited weights are stored instead, w_b = exp(-P_(b-1)) (1 - exp(-tau_b)) with
-    // P_b = tau_0 + ... + tau_b, and the interval's total P_31 goes to tot.  Lane group g
-    // holds bins 4g..4g+3 and 16+4g..16+4g+3 of its column, so the offsets of its two runs
-    // are sums over the lower groups, gathered 16 and 32 lanes down the wave; within a run
-    // the transmittance steps by exp(-tau_b).
+    // outputs: rows 16 rb + 4 g + e of the 32 bins (with cum set, for rendering: the bins'
+    // local composited weights, and the interval's total to tot)
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
       const uint32_t it = base + cb * 16 + m;
       f32x4 v[2];
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[rb][e] = BF16 ? softplus_fast(acc[cb][rb][e]) : softplusf(acc[cb][rb][e]);
-      float total = 0.f;
-      if (cum) {
-        float run[2], off[2], last[2];
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-          float x = v[rb][0] + v[rb][1];
-          x += v[rb][2];
-          x += v[rb][3];
-          last[rb] = x;                      // this lane's run total
-          float y = __shfl_up(x, 16, 64);
-          x += g >= 1 ? y : 0.f;
-          y = __shfl_up(x, 32, 64);
-          x += g >= 2 ? y : 0.f;
-          run[rb] = x;                       // inclusive over groups 0..g
-          off[rb] = x - last[rb];
-        }
-        const float tot0 = __shfl(run[0], 48 + m, 64);
-        const float start[2] = {off[0], tot0 + off[1]};
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-          float T = exp_neg(start[rb]);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float tb = v[rb][e];
-            const float eb = exp_neg(tb);
-            v[rb][e] = T * one_minus_exp_neg(tb, eb);
-            T *= eb;
-          }
-        }
-        total = last[1] + (tot0 + off[1]);   // P_31 in lane group 3
-      }
+      const float total = prop_outputs<BF16>(acc[cb], cum, g, m, v);
       if (it >= n_items) continue;
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
@@ -542,6 +559,155 @@ __device__ __forceinline__ uint32_t count_sorted(const float p[4], uint32_t ns, 
   return count;
 }
 
+// Selection of one ray (one wave): bins of interval i0 + k at wts[(i0 + k) * 32 ..], its
+// total at tot[i0 + k] (global memory, or the fused kernel's LDS copy); sb: the wave's
+// kMaxSlots floats of LDS.  Writes runs[r], nsel[r], mask[4 r ..] (and mass_out[r]);
+// returns true when the ray falls back.  prefetch() is called once every load of the ray
+// has been issued.
+template <int QM, class Prefetch>
+__device__ __forceinline__ bool select_ray(uint32_t r, uint32_t i0, uint32_t meff, uint32_t ns,
+                                           const float* __restrict__ wts, const float* __restrict__ tot,
+                                           float* __restrict__ sb, float mass_thresh, int cap, int lane,
+                                           uint32_t* __restrict__ runs, uint32_t* __restrict__ nsel,
+                                           uint64_t* __restrict__ mask, float* __restrict__ mass_out,
+                                           Prefetch&& prefetch) {
+  if (meff == 0) {
+    if (lane == 0) { runs[r] = 0; nsel[r] = 0; if (mass_out) mass_out[r] = 0.f; }
+    if (lane < 4) mask[4 * (uint64_t)r + lane] = 0ull;
+    prefetch();
+    return false;
+  }
+  const uint32_t n = ns / meff;
+  // floor(x / n) = umulhi(x, m) with m = ceil(2^32 / n) for x < 2^16 and n >= 2 (the
+  // error x (m - 2^32/n) / 2^32 stays below 1/n, so it never carries into the integer part)
+  const uint32_t m32 = n > 1u ? 0xFFFFFFFFu / n + 1u : 0u;
+  auto div_n = [&](uint32_t x) { return n > 1u ? __umulhi(x, m32) : x; };
+  const uint32_t nq = (ns + 63u) / 64u;
+  // Every load of the ray is issued before the first wait: the bin weights each slot
+  // covers (its first and last bin and up to kMid whole bins between them), then the
+  // interval totals, then (prefetch) the next ray's offsets.
+  // The slot geometry is kept packed: interval k (8 bits), slot j in it (8 bits), first and
+  // last bin (5 bits each).
+  constexpr int kMid = QM == 2 ? 3 : 4;
+  float wlo[QM], whi[QM], wmid[QM][kMid];
+  uint32_t geo[QM];
+#pragma unroll
+  for (int q = 0; q < QM; ++q) {
+    wlo[q] = 0.f; whi[q] = 0.f; geo[q] = 0u;
+#pragma unroll
+    for (int t = 0; t < kMid; ++t) wmid[q][t] = 0.f;
+    if ((uint32_t)q >= nq) continue;
+    const uint32_t s = (uint32_t)lane + 64u * q;
+    const uint32_t sk = div_n(s);
+    const uint32_t j = s - sk * n;
+    const uint32_t blo = div_n(32u * j);
+    const uint32_t bhi = div_n(32u * (j + 1) + n - 1) - 1u;
+    geo[q] = (sk & 255u) | ((j & 255u) << 8) | (blo << 16) | ((bhi & 31u) << 24);
+    if (s >= ns) continue;
+    const float* row = wts + (uint64_t)(i0 + sk) * kBins;
+    wlo[q] = row[blo];
+    whi[q] = row[bhi];
+#pragma unroll
+    for (int t = 0; t < kMid; ++t)
+      if (blo + 1u + (uint32_t)t < bhi) wmid[q][t] = row[blo + 1u + t];
+  }
+  float tk0 = (uint32_t)lane < meff ? tot[i0 + lane] : 0.f;
+  prefetch();
+  // transmittance at the entry of each interval, exp(-S_k)
+  float carry = 0.f;
+  for (uint32_t k0 = 0; k0 < meff; k0 += 64) {
+    const uint32_t k = k0 + (uint32_t)lane;
+    const float tk = k0 == 0 ? tk0 : (k < meff ? tot[i0 + k] : 0.f);
+    const float inc = wave_scan_incl(tk);
+    if (k < meff) sb[k] = exp_neg(carry + (inc - tk));
+    carry += lane_value(inc, 63);
+  }
+  const float M = -expm1f(-carry);
+  if (mass_out && lane == 0) mass_out[r] = M;
+  bool fallback = !(M >= mass_thresh);
+  uint32_t count = 0;
+  uint64_t sel[4] = {0ull, 0ull, 0ull, 0ull};
+  uint64_t first[4] = {0ull, 0ull, 0ull, 0ull};   // slots that start an interval
+  if (!fallback) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const float inv_n = 1.f / (float)n;
+    float p[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+      if ((uint32_t)q >= nq) break;
+      const uint32_t s = (uint32_t)lane + 64u * q;
+      const uint32_t sk = geo[q] & 255u, j = (geo[q] >> 8) & 255u;
+      first[q] = __ballot(j == 0u);
+      if (s >= ns) continue;
+      const uint32_t blo = (geo[q] >> 16) & 31u, bhi = geo[q] >> 24;
+      const float u0 = (float)(32u * j) * inv_n, u1 = (float)(32u * (j + 1)) * inv_n;
+      float v;
+      if (bhi == blo) {
+        v = 32.f * inv_n * wlo[q];
+      } else {
+        v = ((float)(blo + 1) - u0) * wlo[q];
+#pragma unroll
+        for (int t = 0; t < kMid; ++t) v += wmid[q][t];
+        const float* row = wts + (uint64_t)(i0 + sk) * kBins;
+        for (uint32_t b = blo + 1u + kMid; b < bhi; ++b) v += row[b];   // slots wider than kMid + 1 bins
+        v += (u1 - (float)bhi) * whi[q];
+      }
+      p[q] = sb[sk] * v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const float target = mass_thresh * M;
+    bool reached = true;
+    float wcut = 0.f;
+    if constexpr (QM == 2) count = count_sorted<2>(p, ns, target, lane, &reached, &wcut);
+    else if constexpr (QM == 3) count = nq <= 2 ? count_sorted<2>(p, ns, target, lane, &reached, &wcut)
+                                                : count_sorted<4>(p, ns, target, lane, &reached, &wcut);
+    else count = nq <= 2 ? count_sorted<2>(p, ns, target, lane, &reached, &wcut)
+                         : count_sorted<4>(p, ns, target, lane, &reached, &wcut);
+    if (count > (uint32_t)cap || count == 0 || !reached) {
+      fallback = true;
+    } else {
+      // above the cut, then the earliest slots equal to it
+      uint32_t n_gt = 0;
+      uint64_t eqm[4];
+#pragma unroll
+      for (int q = 0; q < QM; ++q) {
+        const bool valid = (uint32_t)lane + 64u * q < ns;
+        sel[q] = __ballot(valid && p[q] > wcut);
+        eqm[q] = __ballot(valid && p[q] == wcut);
+        n_gt += (uint32_t)__popcll(sel[q]);
+      }
+      uint32_t need = count - n_gt;
+#pragma unroll
+      for (int q = 0; q < QM; ++q) {
+        uint64_t e = eqm[q];
+        while (need && e) {
+          const uint64_t low = e & (~e + 1ull);
+          sel[q] |= low;
+          e ^= low;
+          --need;
+        }
+      }
+    }
+  }
+  if (fallback) {
+    if (lane == 0) { runs[r] = meff; nsel[r] = ns; }
+    if (lane < 4) mask[4 * (uint64_t)r + lane] = ~0ull;
+    return true;
+  }
+  // runs: a kept slot starts a run unless the previous slot is kept in the same interval
+  uint32_t nruns = 0;
+#pragma unroll
+  for (int q = 0; q < QM; ++q) {
+    const uint64_t prev_kept = (sel[q] << 1) | (q > 0 ? sel[q - 1] >> 63 : 0ull);
+    nruns += (uint32_t)__popcll(sel[q] & ~(prev_kept & ~first[q]));
+  }
+  if (lane == 0) { runs[r] = nruns; nsel[r] = count; }
+  if (lane < 4) mask[4 * (uint64_t)r + lane] = sel[lane];
+  return false;
+}
+
 // QM: registers of 64 slots a ray may need (2 when S_max <= 128, 3 up to 192, else 4);
 // fewer live registers keep more waves resident.
 template <int QM>
@@ -566,140 +732,11 @@ __global__ __launch_bounds__(kThreads, QM == 2 ? 8 : (QM == 3 ? 7 : 1)) void k_p
     const uint32_t i0 = nx_i0, meff = nx_i1 - nx_i0;
     const uint32_t ns = nx_s1 - nx_s0;
     const uint32_t rn = r + step;
-    if (meff == 0) {
-      if (lane == 0) { runs[r] = 0; nsel[r] = 0; if (mass_out) mass_out[r] = 0.f; }
+    auto prefetch = [&]() {
       if (rn < nr) { nx_i0 = iv.iv_off[rn]; nx_i1 = iv.iv_off[rn + 1]; nx_s0 = iv.smp_off[rn]; nx_s1 = iv.smp_off[rn + 1]; }
-      continue;
-    }
-    const uint32_t n = ns / meff;
-    // floor(x / n) = umulhi(x, m) with m = ceil(2^32 / n) for x < 2^16 and n >= 2 (the
-    // error x (m - 2^32/n) / 2^32 stays below 1/n, so it never carries into the integer part)
-    const uint32_t m32 = n > 1u ? 0xFFFFFFFFu / n + 1u : 0u;
-    auto div_n = [&](uint32_t x) { return n > 1u ? __umulhi(x, m32) : x; };
-    const uint32_t nq = (ns + 63u) / 64u;
-    // Every load of the ray is issued before the first wait: the bin weights each slot
-    // covers (its first and last bin and up to kMid whole bins between them), then the
-    // interval totals, then the next ray's offsets.
-    // The slot geometry is kept packed: interval k (8 bits), slot j in it (8 bits), first and
-    // last bin (5 bits each).
-    constexpr int kMid = QM == 2 ? 3 : 4;
-    float wlo[QM], whi[QM], wmid[QM][kMid];
-    uint32_t geo[QM];
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-      wlo[q] = 0.f; whi[q] = 0.f; geo[q] = 0u;
-#pragma unroll
-      for (int t = 0; t < kMid; ++t) wmid[q][t] = 0.f;
-      if ((uint32_t)q >= nq) continue;
-      const uint32_t s = (uint32_t)lane + 64u * q;
-      const uint32_t sk = div_n(s);
-      const uint32_t j = s - sk * n;
-      const uint32_t blo = div_n(32u * j);
-      const uint32_t bhi = div_n(32u * (j + 1) + n - 1) - 1u;
-      geo[q] = (sk & 255u) | ((j & 255u) << 8) | (blo << 16) | ((bhi & 31u) << 24);
-      if (s >= ns) continue;
-      const float* row = wts + (uint64_t)(i0 + sk) * kBins;
-      wlo[q] = row[blo];
-      whi[q] = row[bhi];
-#pragma unroll
-      for (int t = 0; t < kMid; ++t)
-        if (blo + 1u + (uint32_t)t < bhi) wmid[q][t] = row[blo + 1u + t];
-    }
-    float tk0 = (uint32_t)lane < meff ? tot[i0 + lane] : 0.f;
-    if (rn < nr) { nx_i0 = iv.iv_off[rn]; nx_i1 = iv.iv_off[rn + 1]; nx_s0 = iv.smp_off[rn]; nx_s1 = iv.smp_off[rn + 1]; }
-    // transmittance at the entry of each interval, exp(-S_k)
-    float carry = 0.f;
-    for (uint32_t k0 = 0; k0 < meff; k0 += 64) {
-      const uint32_t k = k0 + (uint32_t)lane;
-      const float tk = k0 == 0 ? tk0 : (k < meff ? tot[i0 + k] : 0.f);
-      const float inc = wave_scan_incl(tk);
-      if (k < meff) sbuf[wave][k] = exp_neg(carry + (inc - tk));
-      carry += lane_value(inc, 63);
-    }
-    const float M = -expm1f(-carry);
-    if (mass_out && lane == 0) mass_out[r] = M;
-    bool fallback = !(M >= mass_thresh);
-    uint32_t count = 0;
-    uint64_t sel[4] = {0ull, 0ull, 0ull, 0ull};
-    uint64_t first[4] = {0ull, 0ull, 0ull, 0ull};   // slots that start an interval
-    if (!fallback) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      const float inv_n = 1.f / (float)n;
-      float p[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int q = 0; q < QM; ++q) {
-        if ((uint32_t)q >= nq) break;
-        const uint32_t s = (uint32_t)lane + 64u * q;
-        const uint32_t sk = geo[q] & 255u, j = (geo[q] >> 8) & 255u;
-        first[q] = __ballot(j == 0u);
-        if (s >= ns) continue;
-        const uint32_t blo = (geo[q] >> 16) & 31u, bhi = geo[q] >> 24;
-        const float u0 = (float)(32u * j) * inv_n, u1 = (float)(32u * (j + 1)) * inv_n;
-        float v;
-        if (bhi == blo) {
-          v = 32.f * inv_n * wlo[q];
-        } else {
-          v = ((float)(blo + 1) - u0) * wlo[q];
-#pragma unroll
-          for (int t = 0; t < kMid; ++t) v += wmid[q][t];
-          const float* row = wts + (uint64_t)(i0 + sk) * kBins;
-          for (uint32_t b = blo + 1u + kMid; b < bhi; ++b) v += row[b];   // slots wider than kMid + 1 bins
-          v += (u1 - (float)bhi) * whi[q];
-        }
-        p[q] = sbuf[wave][sk] * v;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      const float target = mass_thresh * M;
-      bool reached = true;
-      float wcut = 0.f;
-      if constexpr (QM == 2) count = count_sorted<2>(p, ns, target, lane, &reached, &wcut);
-      else if constexpr (QM == 3) count = nq <= 2 ? count_sorted<2>(p, ns, target, lane, &reached, &wcut)
-                                                  : count_sorted<4>(p, ns, target, lane, &reached, &wcut);
-      else count = nq <= 2 ? count_sorted<2>(p, ns, target, lane, &reached, &wcut)
-                           : count_sorted<4>(p, ns, target, lane, &reached, &wcut);
-      if (count > (uint32_t)cap || count == 0 || !reached) {
-        fallback = true;
-      } else {
-        // above the cut, then the earliest slots equal to it
-        uint32_t n_gt = 0;
-        uint64_t eqm[4];
-#pragma unroll
-        for (int q = 0; q < QM; ++q) {
-          const bool valid = (uint32_t)lane + 64u * q < ns;
-          sel[q] = __ballot(valid && p[q] > wcut);
-          eqm[q] = __ballot(valid && p[q] == wcut);
-          n_gt += (uint32_t)__popcll(sel[q]);
-        }
-        uint32_t need = count - n_gt;
-#pragma unroll
-        for (int q = 0; q < QM; ++q) {
-          uint64_t e = eqm[q];
-          while (need && e) {
-            const uint64_t low = e & (~e + 1ull);
-            sel[q] |= low;
-            e ^= low;
-            --need;
-          }
-        }
-      }
-    }
-    if (fallback) {
-      if (lane == 0) { runs[r] = meff; nsel[r] = ns; }
-      if (lane < 4) mask[4 * (uint64_t)r + lane] = ~0ull;
-      ++n_fb;
-      continue;
-    }
-    // runs: a kept slot starts a run unless the previous slot is kept in the same interval
-    uint32_t nruns = 0;
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-      const uint64_t prev_kept = (sel[q] << 1) | (q > 0 ? sel[q - 1] >> 63 : 0ull);
-      nruns += (uint32_t)__popcll(sel[q] & ~(prev_kept & ~first[q]));
-    }
-    if (lane == 0) { runs[r] = nruns; nsel[r] = count; }
-    if (lane < 4) mask[4 * (uint64_t)r + lane] = sel[lane];
+    };
+    n_fb += select_ray<QM>(r, i0, meff, ns, wts, tot, sbuf[wave], mass_thresh, cap, lane, runs, nsel, mask, mass_out,
+                           prefetch) ? 1u : 0u;
   }
   if (lane == 0) fb_lds[wave] = n_fb;
   __syncthreads();
