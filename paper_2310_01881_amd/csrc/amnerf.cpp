@@ -90,6 +90,7 @@ constexpr int kBwdStages = AMNERF_N_BWD_STAGES;
 struct BwdEvSet {
   hipEvent_t ev[kBwdStages + 1] = {};
   bool pending = false;
+  bool no_adam = false;   // a backward pass alone: its last event ends the reduction stage
 };
 }  // namespace
 
@@ -293,8 +294,9 @@ static int next_set(amnerf_ctx* ctx, EvSet** out) {
 
 static int drain_bwd_set(amnerf_ctx* ctx, BwdEvSet& s) {
   if (!s.pending) return AMNERF_OK;
-  HIP_TRY(hipEventSynchronize(s.ev[kBwdStages]));
-  for (int k = 0; k < kBwdStages; ++k) {
+  const int last = s.no_adam ? AMNERF_BWD_STAGE_ADAM : kBwdStages;
+  HIP_TRY(hipEventSynchronize(s.ev[last]));
+  for (int k = 0; k < last; ++k) {
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, s.ev[k], s.ev[k + 1]));
     ctx->bwd_ms[k] += ms;
@@ -1420,7 +1422,7 @@ int backward_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* ml
   HIP_TRY(launch_grad_reduce(w.part, w.seg_off, (uint32_t)L, (uint32_t)P, grad, st));
   HIP_TRY(mark(AMNERF_BWD_STAGE_ADAM));
   if (alone && ev) {
-    HIP_TRY(mark(kBwdStages));
+    ev->no_adam = true;
     ev->pending = true;
   }
   ctx->have_backward = true;
@@ -1528,6 +1530,7 @@ extern "C" int amnerf_train_step(amnerf_ctx* ctx, const amnerf_tree* tree, amner
   }
   if (ev) {
     HIP_TRY(hipEventRecord(ev->ev[kBwdStages], st));
+    ev->no_adam = false;
     ev->pending = true;
   }
   return AMNERF_OK;

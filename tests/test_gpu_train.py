@@ -295,3 +295,37 @@ def test_training_reduces_loss_teacher_student():
     print("teacher-student loss: first %.4e, last %.4e" % (losses[0], losses[-1]))
     assert np.isfinite(losses).all()
     assert np.mean(losses[-5:]) < 0.5 * np.mean(losses[:5])
+
+
+def test_backward_stage_timing():
+    """With timing on, every backward pass records its stages: a training step all four (the
+    Adam stage includes the repack), a backward pass alone no Adam; the forward stages of
+    the step's render are timed as usual."""
+    scene = Scene(synth.C1)
+    ctx, tree, tr = setup(scene)
+    o, d = synth.camera_rays(synth.make_cameras(1, 301, 24, 24)[0])
+    od, dd = to_dev(o), to_dev(d)
+    R = o.shape[1]
+    target = to_dev(np.random.default_rng(1).uniform(0, 1, (R, 3)).astype(np.float32))
+    am.amnerf_ctx_set_timing(ctx.h, True)
+    am.amnerf_timing_collect(ctx.h)
+    am.amnerf_timing_collect_backward(ctx.h)
+    for _ in range(3):
+        tr.step(od, dd, target, 64, lr=1e-3)
+    torch.cuda.synchronize()
+    bwd, nb = am.amnerf_timing_collect_backward(ctx.h)
+    fwd, nf = am.amnerf_timing_collect(ctx.h)
+    assert nb == 3 and nf == 3
+    assert all(v > 0 for v in bwd.values()), bwd
+    assert fwd["mlp"] > 0 and fwd["composite"] > 0
+    # a backward pass alone: no Adam stage
+    am.amnerf_render(ctx.h, tree.h, tr.mlp, od, dd, 64, torch.empty((R, 3), device="cuda:0"), None, None, None, 1e-4)
+    grad = torch.empty_like(tr.master)
+    am.amnerf_render_backward(ctx.h, tree.h, tr.mlp, od, dd, to_dev(np.full((R, 3), 1.0, np.float32)), grad)
+    torch.cuda.synchronize()
+    bwd, nb = am.amnerf_timing_collect_backward(ctx.h)
+    assert nb == 1 and bwd["adam"] == 0.0 and bwd["mlp_bwd"] > 0 and bwd["comp_bwd"] > 0
+    am.amnerf_ctx_set_timing(ctx.h, False)
+    tr.step(od, dd, target, 64, lr=1e-3)
+    torch.cuda.synchronize()
+    assert am.amnerf_timing_collect_backward(ctx.h)[1] == 0
