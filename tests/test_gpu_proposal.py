@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from scene_util import Scene, to_dev
+from scene_util import Scene, gpu_setup, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -175,3 +175,40 @@ def test_training_reduces_samples_and_keeps_quality():
     assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:10])
     assert pr[3]["n_samples"] < 0.8 * plain[3]["n_samples"]
     assert psnr >= 40.0   # measured 44.2 dB
+
+
+def test_failed_call_after_freed_workspace_leaves_no_inspectable_render():
+    """A proposal render keeps its plan in the context's third workspace.  A later call that
+    regrows that workspace and then fails (here: amnerf_propose whose scene MLP has the wrong
+    number of leaves) must leave no render to inspect or differentiate: AMNERF_ESTATE, not a
+    copy out of freed memory.  A call that fails its argument checks first changes nothing."""
+    scene = Scene(synth.C1)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    prop = am.Proposal(ctx, torch.from_numpy(synth.make_prop_weights(1)).to("cuda:0"))
+    o, d = (to_dev(a) for a in scene.camera_rays(0))
+    R = o.shape[1]
+    am.render(ctx, tree, mlp, o, d, cfg.s_max, proposal=prop.descriptor(am.AMNERF_F32, 0.5, 48))
+    used = torch.empty(R, dtype=torch.int32, device="cuda:0")
+    mask = torch.empty((R, 4), dtype=torch.int64, device="cuda:0")
+    am.amnerf_render_inspect(ctx.h, ray_used=used, slot_mask=mask)
+    torch.cuda.synchronize()
+    # bad s_max: rejected before any workspace is touched; the render stays inspectable
+    with pytest.raises(am.AmnerfError) as e:
+        prop.infer(tree, mlp.desc, o, d, 0)
+    assert e.value.code == am.AMNERF_EINVAL
+    am.amnerf_render_inspect(ctx.h, ray_used=used)
+    # many rays regrow the third workspace, then the scene MLP is refused
+    big = [to_dev(a) for a in scene.camera_rays(1, width=400, height=400)]
+    wrong = am.Mlp(ctx, torch.from_numpy(synth.make_weights(1, cfg.n_hidden, cfg.hidden, 1)).to("cuda:0"),
+                   cfg.n_hidden, cfg.hidden, am.AMNERF_F32, 1)
+    with pytest.raises(am.AmnerfError) as e:
+        prop.infer(tree, wrong.desc, big[0], big[1], cfg.s_max)
+    assert e.value.code == am.AMNERF_EINVAL
+    with pytest.raises(am.AmnerfError) as e:
+        am.amnerf_render_inspect(ctx.h, ray_used=used)
+    assert e.value.code == am.AMNERF_ESTATE
+    grad = torch.empty_like(mlp.master)
+    with pytest.raises(am.AmnerfError) as e:
+        am.amnerf_render_backward(ctx.h, tree.h, mlp.desc, o, d, torch.zeros((R, 3), device="cuda:0"), grad)
+    assert e.value.code == am.AMNERF_ESTATE

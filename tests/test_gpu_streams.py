@@ -52,3 +52,23 @@ def test_two_contexts_on_two_streams(mode):
         for name in ("rgb", "depth", "opacity"):
             assert torch.equal(out[name], alone[k % n_cams][name]), (mode, k, name)
     print("%s: %d frames on two streams bit-identical to the frames alone" % (mode, len(frames)), flush=True)
+
+
+def test_weights_on_a_side_stream():
+    """render() on a stream other than the current one: the per-sample weights are cleared
+    on that stream before the render writes them, so every frame's weights equal the weights
+    of the same frame rendered on the current stream."""
+    scene = Scene(synth.C1)
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_F32)
+    rays = [tuple(to_dev(a) for a in scene.camera_rays(i)) for i in range(3)]
+    alone = [am.render(ctx, tree, mlp, o, d, cfg.s_max, ert_eps=cfg.ert_eps, weights=True) for o, d in rays]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    ctx2 = am.Context(0)
+    outs = [am.render(ctx2, tree, mlp, o, d, cfg.s_max, ert_eps=cfg.ert_eps, weights=True, stream=side)
+            for o, d in rays for _ in range(2)]
+    torch.cuda.synchronize()
+    for k, out in enumerate(outs):
+        for name in ("rgb", "depth", "opacity", "weights"):
+            assert torch.equal(out[name], alone[k // 2][name]), (k, name)
