@@ -55,6 +55,12 @@ def lib():
         _lib.orc_trace_rays.argtypes = [P, i32, i32, P, P, i64, P, i64, i32, P, P, P, P, f32]
         _lib.orc_robust.argtypes = [P, i32, i32, P, P, i64, P, i64, dbl, dbl, P, f32]
         _lib.orc_mlp_eval.argtypes = [P, i32, i32, P, P, i64, P, P]
+        _lib.orc_mlp_eval_q8.argtypes = [P, i32, i32, P, P, i64, P, P]
+        _lib.orc_render_q8.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, P, i64, i32, dbl, P,
+                                       P, P, P, i32]
+        _lib.orc_act_max.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, P, i64, i32, P, i32]
+        _lib.orc_e4m3_round.argtypes = [dbl]
+        _lib.orc_e4m3_round.restype = dbl
         _lib.orc_render.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, P, i64, i32, dbl,
                                     i32, u64, P, P, P, P, P, i32, f32, P, i32]
         _lib.orc_occupancy.argtypes = [P, i32, i32, dbl, P]
@@ -192,6 +198,23 @@ def mlp_eval(params_leaf, n_hidden, hidden, x, dirs, return_features=False):
     return (out, feat) if return_features else out
 
 
+def mlp_eval_q8(params_leaf, n_hidden, hidden, x, dirs, act_exp):
+    """mlp_eval with float8 hidden activations: act_exp[n_hidden] exponents of the leaf."""
+    p = _c(params_leaf, np.float32)
+    x = _c(x, np.float64); dirs = _c(dirs, np.float64)
+    k = _c(act_exp, np.int32)
+    assert k.shape == (n_hidden,)
+    out = np.zeros((len(x), 4))
+    if lib().orc_mlp_eval_q8(_p(p), n_hidden, hidden, _p(x), _p(dirs), len(x), _p(k), _p(out)) != 0:
+        raise ValueError("orc_mlp_eval_q8 failed")
+    return out
+
+
+def e4m3_round(x):
+    """Nearest e4m3 value of x in [0, 448] (448 for x >= 448), ties to even."""
+    return lib().orc_e4m3_round(float(x))
+
+
 def occupancy(grid, n, block, thresh):
     """Occupancy cells uint8[G^3] (G = n / block) for empty-space skipping."""
     grid = _c(grid, np.float32)
@@ -228,6 +251,40 @@ def render(tree: Tree, params, n_hidden, hidden, o, d, s_max, eps=1e-4, ray_idx=
     if rc != 0:
         raise ValueError("orc_render failed")
     return rgb, depth, opac, ns, flags
+
+
+def render_q8(tree: Tree, params, n_hidden, hidden, o, d, s_max, act_exp, eps=1e-4, ray_idx=None,
+              threads=None):
+    """render() of leaf samples with float8 hidden activations (exponents act_exp[L][n_hidden]):
+    (rgb[n][3], depth[n], opacity[n])."""
+    params = _c(params, np.float32)
+    o = _c(o, np.float32); d = _c(d, np.float32)
+    k = _c(act_exp, np.int32)
+    assert k.shape == (params.shape[0], n_hidden)
+    R = o.shape[1]
+    ri, n = _sel(ray_idx, R)
+    rgb = np.zeros((n, 3)); depth = np.zeros(n); opac = np.zeros(n)
+    threads = threads or min(16, os.cpu_count() or 1)
+    if lib().orc_render_q8(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(params), params.shape[0], n_hidden,
+                           hidden, _p(o), _p(d), R, _p(ri), n, s_max, eps, _p(k), _p(rgb), _p(depth), _p(opac),
+                           threads) != 0:
+        raise ValueError("orc_render_q8 failed")
+    return rgb, depth, opac
+
+
+def act_max(tree: Tree, params, n_hidden, hidden, o, d, s_max, ray_idx=None, threads=None):
+    """Calibration maxima [L][n_hidden]: the largest ReLU output of each leaf's hidden layers
+    over every sample placed on the selected rays (float64, no early termination)."""
+    params = _c(params, np.float32)
+    o = _c(o, np.float32); d = _c(d, np.float32)
+    R = o.shape[1]
+    ri, n = _sel(ray_idx, R)
+    out = np.zeros((params.shape[0], n_hidden))
+    threads = threads or min(16, os.cpu_count() or 1)
+    if lib().orc_act_max(_p(tree.rows), tree.n_nodes, tree.grid_n, _p(params), params.shape[0], n_hidden, hidden,
+                         _p(o), _p(d), R, _p(ri), n, s_max, _p(out), threads) != 0:
+        raise ValueError("orc_act_max failed")
+    return out
 
 
 def ray_samples(tree: Tree, params, n_hidden, hidden, o, d, r, s_max, eps=1e-4, jitter=False, seed=0,

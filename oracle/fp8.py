@@ -14,6 +14,18 @@ module states that storage from its definitions, independently of the HIP path:
 
 The encoder looks the value up in the table of all finite codes (``decode`` of 0..126)
 rather than by exponent arithmetic, so it shares no steps with the device encoder.
+
+The float8 matrix-core variant (``quantise_mma``) also rounds the hidden activations, so
+both operands of every hidden and output layer are e4m3, and all its scales are powers of
+two (an exact rescaling, applied by the matrix instruction's block scales):
+
+* a weight layer l >= 1 gets the exponent e = the smallest integer with max |W| <= 448 * 2^e
+  (0 for an all-zero layer) and the codes e4m3(W / 2^e); the first layer's weights are
+  bfloat16 (round to nearest even), its inputs being the bfloat16 positional encoding;
+  biases stay float32;
+* hidden layer j's ReLU outputs a get the exponent k = the smallest integer with
+  1.25 * m <= 448 * 2^k, m the calibration maximum of that leaf and layer (0 when m = 0),
+  and are held as 2^k * e4m3(min(a / 2^k, 448)) (the oracle's C forward applies this).
 """
 from __future__ import annotations
 
@@ -79,3 +91,53 @@ def quantise(W: np.ndarray, n_hidden: int, hidden: int):
         codes.append(q)
         deq[:, ow:ow + din * dout] = decode(q) * s[:, None].astype(np.float64)
     return scales, codes, deq
+
+
+def bf16_round(x) -> np.ndarray:
+    """float32 values rounded to the nearest bfloat16 (ties to even), as float32; finite inputs."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def pow2_exponent(m, limit: float) -> np.ndarray:
+    """Smallest integer e with m <= limit * 2^e, elementwise for m > 0; 0 where m == 0."""
+    m = np.asarray(m, dtype=np.float64)
+    out = np.zeros(m.shape, np.int32)
+    for idx in zip(*np.nonzero(m > 0)):
+        v = float(m[idx])
+        e = int(np.ceil(np.log2(v / limit)))
+        while v > limit * 2.0 ** e:          # exact comparisons settle the logarithm's rounding
+            e += 1
+        while v <= limit * 2.0 ** (e - 1):
+            e -= 1
+        out[idx] = e
+    return out
+
+
+def act_exponents(act_max) -> np.ndarray:
+    """Activation exponents [L][n_hidden] from float32 calibration maxima: 1.25 m <= 448 * 2^k."""
+    m = np.asarray(act_max, dtype=np.float32).astype(np.float64)
+    return pow2_exponent(1.25 * m, MAX)
+
+
+def quantise_mma(W: np.ndarray, n_hidden: int, hidden: int, act_max):
+    """The float8 matrix-core model of the leaf MLPs: (weight exponents int32[L][n_hidden] of
+    layers 1..n_hidden, activation exponents int32[L][n_hidden], dequantised parameters
+    float32[L][P] -- every value exact in float32 -- for the oracle's forward with float8
+    activations)."""
+    W = np.asarray(W, dtype=np.float32)
+    L = W.shape[0]
+    sl = layer_slices(n_hidden, hidden)
+    deq = W.copy()
+    ow, din, dout, _ = sl[0]
+    deq[:, ow:ow + din * dout] = bf16_round(W[:, ow:ow + din * dout])
+    w_exp = np.zeros((L, n_hidden), np.int32)
+    for li in range(1, n_hidden + 1):
+        ow, din, dout, _ = sl[li]
+        w = W[:, ow:ow + din * dout].astype(np.float64)
+        e = pow2_exponent(np.abs(w).max(axis=1), MAX)
+        w_exp[:, li - 1] = e
+        scaled = w * np.exp2(-e.astype(np.float64))[:, None]          # exact
+        deq[:, ow:ow + din * dout] = (decode(encode(scaled)) * np.exp2(e.astype(np.float64))[:, None]).astype(np.float32)
+    return w_exp, act_exponents(act_max), deq

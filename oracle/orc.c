@@ -26,6 +26,11 @@
  *   - occupancy grid and empty-space skipping ..................... Section 4.1
  *   - the learned proposal (not in the paper): features, network, slot selection,
  *     targets and loss, following the stated reading step by step.
+ *   - float8 activations (not in the paper; the large workload's float8 matrix-core
+ *     path): every hidden activation rounded to the nearest e4m3 value times a power-of-two
+ *     scale 2^k per leaf and layer, saturating at 448 * 2^k; and the calibration maxima
+ *     those scales come from (the largest ReLU output per leaf and hidden layer over the
+ *     samples of a render).
  *
  * Everything is double precision; float inputs are promoted exactly.  No blocking,
  * sorting, batching or fusion: every ray is processed on its own, sample by sample.
@@ -34,6 +39,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NODE_COLS 12
 #define IN_DIM 30
@@ -570,10 +578,27 @@ static void features(const double x[3], const double dir[3], double u[IN_DIM]) {
 static double softplus(double z) { return (z > 0 ? z : 0.0) + log1p(exp(-fabs(z))); }
 static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 
+/* Nearest OCP e4m3 value of x in [0, 448] (3 mantissa bits; normal values from 2^-6,
+   subnormal steps of 2^-9; largest finite value 448), ties to even; x >= 448 gives 448. */
+static double e4m3_round(double x) {
+  if (x >= 448.0) return 448.0;
+  if (x < ldexp(1.0, -6)) return ldexp(nearbyint(ldexp(x, 9)), -9);
+  int e;
+  frexp(x, &e);                      /* x in [2^(e-1), 2^e): the step is 2^(e-4) */
+  return ldexp(nearbyint(ldexp(x, 4 - e)), e - 4);
+}
+
+double orc_e4m3_round(double x) { return e4m3_round(x); }
+
+/* A ReLU output a >= 0 held as float8 with scale 2^k: 2^k * e4m3(min(a / 2^k, 448)). */
+static double act_round(double a, int k) { return ldexp(e4m3_round(ldexp(a, -k)), k); }
+
 /* Forward of one leaf MLP.  acts (optional) receives the input features followed by the
-   pre-activation of every layer (widths din[0], dout[0], ..., dout[last]). */
+   pre-activation of every layer (widths din[0], dout[0], ..., dout[last]).  aexp (optional,
+   one exponent per hidden layer): each hidden layer's ReLU outputs are rounded by act_round
+   with that layer's exponent before the next layer reads them. */
 static void mlp_forward(const olayout* L, const double* P, const double u[IN_DIM], double out[OUT_DIM],
-                        double* acts) {
+                        double* acts, const int32_t* aexp) {
   double a[MAX_HIDDEN], z[MAX_HIDDEN];
   int w = IN_DIM;
   for (int i = 0; i < IN_DIM; ++i) a[i] = u[i];
@@ -589,14 +614,18 @@ static void mlp_forward(const olayout* L, const double* P, const double u[IN_DIM
     }
     if (rec) { memcpy(rec, z, sizeof(double) * L->dout[l]); rec += L->dout[l]; }
     w = L->dout[l];
-    if (l < L->n_lin - 1) for (int o = 0; o < w; ++o) a[o] = z[o] > 0.0 ? z[o] : 0.0;
+    if (l < L->n_lin - 1)
+      for (int o = 0; o < w; ++o) {
+        a[o] = z[o] > 0.0 ? z[o] : 0.0;
+        if (aexp) a[o] = act_round(a[o], aexp[l]);
+      }
   }
   out[0] = softplus(z[0]);
   for (int c = 1; c < OUT_DIM; ++c) out[c] = sigmoid(z[c]);
 }
 
-int orc_mlp_eval(const float* params_leaf, int n_hidden, int hidden, const double* x,
-                 const double* dir, int64_t n, double* out, double* feat) {
+static int mlp_eval(const float* params_leaf, int n_hidden, int hidden, const double* x,
+                    const double* dir, int64_t n, double* out, double* feat, const int32_t* aexp) {
   olayout L;
   if (make_layout(n_hidden, hidden, &L)) return -1;
   double* P = (double*)malloc(sizeof(double) * L.P);
@@ -605,10 +634,22 @@ int orc_mlp_eval(const float* params_leaf, int n_hidden, int hidden, const doubl
     double u[IN_DIM];
     features(x + 3 * s, dir + 3 * s, u);
     if (feat) memcpy(feat + IN_DIM * s, u, sizeof(u));
-    mlp_forward(&L, P, u, out + OUT_DIM * s, NULL);
+    mlp_forward(&L, P, u, out + OUT_DIM * s, NULL, aexp);
   }
   free(P);
   return 0;
+}
+
+int orc_mlp_eval(const float* params_leaf, int n_hidden, int hidden, const double* x,
+                 const double* dir, int64_t n, double* out, double* feat) {
+  return mlp_eval(params_leaf, n_hidden, hidden, x, dir, n, out, feat, NULL);
+}
+
+/* As orc_mlp_eval, with float8 hidden activations: act_exp[n_hidden] (the leaf's exponents). */
+int orc_mlp_eval_q8(const float* params_leaf, int n_hidden, int hidden, const double* x,
+                    const double* dir, int64_t n, const int32_t* act_exp, double* out) {
+  if (!act_exp) return -1;
+  return mlp_eval(params_leaf, n_hidden, hidden, x, dir, n, out, NULL, act_exp);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -631,6 +672,7 @@ typedef struct {
   uint64_t seed;
   const uint8_t* occ;   /* empty-space skipping: G^3 occupancy cells, or NULL */
   int occ_g;
+  const int32_t* aexp;  /* float8 activations: [n_leaves][n_hidden] exponents, or NULL */
 } octx;
 
 /* Per-ray result plus optional per-sample record. */
@@ -700,7 +742,8 @@ static void render_ray(const octx* C, int64_t r, oiv* ivbuf, osample* sbuf, oray
     }
     double u[IN_DIM], out[OUT_DIM];
     features(x, dd, u);
-    mlp_forward(C->L, C->P + (int64_t)sbuf[j].slot * C->L->P, u, out, NULL);
+    mlp_forward(C->L, C->P + (int64_t)sbuf[j].slot * C->L->P, u, out, NULL,
+                C->aexp ? C->aexp + (int64_t)sbuf[j].slot * (C->L->n_lin - 1) : NULL);
     double tau = out[0] * sbuf[j].delta;
     double T = exp(-S);
     double alpha = -expm1(-tau);
@@ -739,15 +782,17 @@ static int make_ctx(octx* C, otree* T, olayout* L, double** P, const int32_t* ro
   for (int64_t i = 0; i < (int64_t)n_leaves * L->P; ++i) (*P)[i] = (double)params[i];
   C->T = T; C->L = L; C->P = *P;
   C->occ = NULL; C->occ_g = 0;
+  C->aexp = NULL;
   return 0;
 }
 
-/* Renders the selected rays (all rays when ray_idx is NULL). */
-int orc_render(const int32_t* rows, int nn, int grid_n, const float* params, int n_leaves,
-               int n_hidden, int hidden, const float* o, const float* d, int64_t R,
-               const int64_t* ray_idx, int64_t n_sel, int s_max, double eps, int jitter,
-               uint64_t seed, double* rgb, double* depth, double* opac, int32_t* n_samples,
-               int32_t* flags, int n_threads, float footprint, const uint8_t* occ, int occ_g) {
+/* Renders the selected rays (all rays when ray_idx is NULL); aexp: see octx. */
+static int render_impl(const int32_t* rows, int nn, int grid_n, const float* params, int n_leaves,
+                       int n_hidden, int hidden, const float* o, const float* d, int64_t R,
+                       const int64_t* ray_idx, int64_t n_sel, int s_max, double eps, int jitter,
+                       uint64_t seed, double* rgb, double* depth, double* opac, int32_t* n_samples,
+                       int32_t* flags, int n_threads, float footprint, const uint8_t* occ, int occ_g,
+                       const int32_t* aexp) {
   if (s_max < 1 || (occ && occ_g < 1)) return -1;
   otree T; olayout L; double* P = NULL; octx C;
   if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden, footprint)) {
@@ -755,6 +800,7 @@ int orc_render(const int32_t* rows, int nn, int grid_n, const float* params, int
   }
   C.o = o; C.d = d; C.R = R; C.s_max = s_max; C.eps = eps; C.jitter = jitter; C.seed = seed;
   C.occ = occ; C.occ_g = occ_g;
+  C.aexp = aexp;
   int cap_iv = T.n_leaves + 1;
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
   {
@@ -774,6 +820,88 @@ int orc_render(const int32_t* rows, int nn, int grid_n, const float* params, int
     free(ivbuf);
     free(sbuf);
   }
+  free(P);
+  otree_free(&T);
+  return 0;
+}
+
+int orc_render(const int32_t* rows, int nn, int grid_n, const float* params, int n_leaves,
+               int n_hidden, int hidden, const float* o, const float* d, int64_t R,
+               const int64_t* ray_idx, int64_t n_sel, int s_max, double eps, int jitter,
+               uint64_t seed, double* rgb, double* depth, double* opac, int32_t* n_samples,
+               int32_t* flags, int n_threads, float footprint, const uint8_t* occ, int occ_g) {
+  return render_impl(rows, nn, grid_n, params, n_leaves, n_hidden, hidden, o, d, R, ray_idx, n_sel, s_max,
+                     eps, jitter, seed, rgb, depth, opac, n_samples, flags, n_threads, footprint, occ, occ_g,
+                     NULL);
+}
+
+/* Leaf samples only (no hierarchical sampling, no skipping), float8 hidden activations with
+   the exponents act_exp[n_leaves][n_hidden]. */
+int orc_render_q8(const int32_t* rows, int nn, int grid_n, const float* params, int n_leaves,
+                  int n_hidden, int hidden, const float* o, const float* d, int64_t R,
+                  const int64_t* ray_idx, int64_t n_sel, int s_max, double eps, const int32_t* act_exp,
+                  double* rgb, double* depth, double* opac, int n_threads) {
+  if (!act_exp) return -1;
+  return render_impl(rows, nn, grid_n, params, n_leaves, n_hidden, hidden, o, d, R, ray_idx, n_sel, s_max,
+                     eps, 0, 0, rgb, depth, opac, NULL, NULL, n_threads, 0.0f, NULL, 0, act_exp);
+}
+
+/* Calibration maxima: out[n_leaves][n_hidden] = the largest ReLU output of each hidden layer
+   of each leaf over every sample placed on the selected rays (all of a ray's samples, with
+   no early termination; float64 weights as given), 0 where a leaf has no sample. */
+int orc_act_max(const int32_t* rows, int nn, int grid_n, const float* params, int n_leaves,
+                int n_hidden, int hidden, const float* o, const float* d, int64_t R,
+                const int64_t* ray_idx, int64_t n_sel, int s_max, double* out, int n_threads) {
+  if (s_max < 1) return -1;
+  otree T; olayout L; double* P = NULL; octx C;
+  if (make_ctx(&C, &T, &L, &P, rows, nn, grid_n, params, n_leaves, n_hidden, hidden, 0.0f)) {
+    free(P); otree_free(&T); return -1;
+  }
+  const int nt = n_threads > 0 ? n_threads : 1;
+  const int64_t nmax = (int64_t)n_leaves * n_hidden;
+  double* part = (double*)calloc((size_t)(nt * nmax), sizeof(double));
+  int act_w = IN_DIM;
+  for (int l = 0; l < L.n_lin; ++l) act_w += L.dout[l];
+#pragma omp parallel num_threads(nt)
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    double* mx = part + (int64_t)tid * nmax;
+    oiv* ivbuf = (oiv*)malloc(sizeof(oiv) * (T.n_leaves + 1));
+    osample* sbuf = (osample*)malloc(sizeof(osample) * (s_max + 1));
+    double* acts = (double*)malloc(sizeof(double) * act_w);
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t s = 0; s < n_sel; ++s) {
+      int64_t r = ray_idx ? ray_idx[s] : s;
+      double oo[3], dd[3];
+      load_ray(o, d, R, r, oo, dd);
+      ivlist IL = {ivbuf, 0, T.n_leaves + 1};
+      int m = trace_ray(&T, oo, dd, &IL);
+      int ns = make_samples(ivbuf, m, m, s_max, 0, 0, r, sbuf);
+      for (int j = 0; j < ns; ++j) {
+        double x[3], u[IN_DIM], res[OUT_DIM];
+        for (int a = 0; a < 3; ++a) x[a] = oo[a] + sbuf[j].t * dd[a];
+        features(x, dd, u);
+        mlp_forward(&L, P + (int64_t)sbuf[j].slot * L.P, u, res, acts, NULL);
+        const double* z = acts + IN_DIM;
+        for (int l = 0; l < n_hidden; ++l) {
+          double* cell = mx + (int64_t)sbuf[j].slot * n_hidden + l;
+          for (int k = 0; k < L.dout[l]; ++k)
+            if (z[k] > *cell) *cell = z[k];
+          z += L.dout[l];
+        }
+      }
+    }
+    free(ivbuf); free(sbuf); free(acts);
+  }
+  for (int64_t i = 0; i < nmax; ++i) {
+    double v = 0.0;
+    for (int t = 0; t < nt; ++t) if (part[(int64_t)t * nmax + i] > v) v = part[(int64_t)t * nmax + i];
+    out[i] = v;
+  }
+  free(part);
   free(P);
   otree_free(&T);
   return 0;
@@ -859,7 +987,7 @@ int orc_render_grad(const int32_t* rows, int nn, int grid_n, const float* params
       double x[3], u[IN_DIM];
       for (int a = 0; a < 3; ++a) x[a] = oo[a] + sbuf[j].t * dd[a];
       features(x, dd, u);
-      mlp_forward(&L, P + (int64_t)sbuf[j].slot * L.P, u, outs + OUT_DIM * j, acts + (int64_t)act_w * j);
+      mlp_forward(&L, P + (int64_t)sbuf[j].slot * L.P, u, outs + OUT_DIM * j, acts + (int64_t)act_w * j, NULL);
       double tau = outs[OUT_DIM * j] * sbuf[j].delta;
       double Tcur = exp(-S);
       double w = Tcur * (-expm1(-tau));
@@ -1207,7 +1335,7 @@ int orc_render_proposal(const int32_t* rows, int nn, int grid_n, const float* pa
         double x[3], u[IN_DIM], out[OUT_DIM];
         for (int a = 0; a < 3; ++a) x[a] = oo[a] + sbuf[j].t * dd[a];
         features(x, dd, u);
-        mlp_forward(&L, P + (int64_t)sbuf[j].slot * L.P, u, out, NULL);
+        mlp_forward(&L, P + (int64_t)sbuf[j].slot * L.P, u, out, NULL, NULL);
         double tau = out[0] * sbuf[j].delta;
         double w = exp(-Sacc) * (-expm1(-tau));
         for (int c = 0; c < 3; ++c) cr[c] += w * out[1 + c];
@@ -1297,7 +1425,7 @@ int64_t orc_prop_targets(const int32_t* rows, int nn, int grid_n, const float* p
         double x[3], u[IN_DIM], out[OUT_DIM];
         for (int a = 0; a < 3; ++a) x[a] = oo[a] + sm->t * dd[a];
         features(x, dd, u);
-        mlp_forward(&L, P + (int64_t)sm->slot * L.P, u, out, NULL);
+        mlp_forward(&L, P + (int64_t)sm->slot * L.P, u, out, NULL, NULL);
         for (int b = 0; b < PROP_BINS; ++b)
           tb[b] += out[0] * len * overlap((double)j / n, (double)(j + 1) / n, (double)b / PROP_BINS,
                                           (double)(b + 1) / PROP_BINS);
