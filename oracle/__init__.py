@@ -61,6 +61,8 @@ def lib():
         _lib.orc_act_max.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, P, i64, i32, P, i32]
         _lib.orc_e4m3_round.argtypes = [dbl]
         _lib.orc_e4m3_round.restype = dbl
+        _lib.orc_bf16_round.argtypes = [dbl]
+        _lib.orc_bf16_round.restype = dbl
         _lib.orc_render.argtypes = [P, i32, i32, P, i32, i32, i32, P, P, i64, P, i64, i32, dbl,
                                     i32, u64, P, P, P, P, P, i32, f32, P, i32]
         _lib.orc_occupancy.argtypes = [P, i32, i32, dbl, P]
@@ -199,7 +201,8 @@ def mlp_eval(params_leaf, n_hidden, hidden, x, dirs, return_features=False):
 
 
 def mlp_eval_q8(params_leaf, n_hidden, hidden, x, dirs, act_exp):
-    """mlp_eval with float8 hidden activations: act_exp[n_hidden] exponents of the leaf."""
+    """mlp_eval in the float8 model: bfloat16 input features, float8 hidden activations with
+    the leaf's exponents act_exp[n_hidden]."""
     p = _c(params_leaf, np.float32)
     x = _c(x, np.float64); dirs = _c(dirs, np.float64)
     k = _c(act_exp, np.int32)
@@ -213,6 +216,11 @@ def mlp_eval_q8(params_leaf, n_hidden, hidden, x, dirs, act_exp):
 def e4m3_round(x):
     """Nearest e4m3 value of x in [0, 448] (448 for x >= 448), ties to even."""
     return lib().orc_e4m3_round(float(x))
+
+
+def bf16_round(x):
+    """Nearest bfloat16 value of x, ties to even."""
+    return lib().orc_bf16_round(float(x))
 
 
 def occupancy(grid, n, block, thresh):

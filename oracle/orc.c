@@ -27,8 +27,9 @@
  *   - the learned proposal (not in the paper): features, network, slot selection,
  *     targets and loss, following the stated reading step by step.
  *   - float8 activations (not in the paper; the large workload's float8 matrix-core
- *     path): every hidden activation rounded to the nearest e4m3 value times a power-of-two
- *     scale 2^k per leaf and layer, saturating at 448 * 2^k; and the calibration maxima
+ *     path): the input features rounded to bfloat16 and every hidden activation rounded to
+ *     the nearest e4m3 value times a power-of-two scale 2^k per leaf and layer, saturating
+ *     at 448 * 2^k; and the calibration maxima
  *     those scales come from (the largest ReLU output per leaf and hidden layer over the
  *     samples of a render).
  *
@@ -590,18 +591,29 @@ static double e4m3_round(double x) {
 
 double orc_e4m3_round(double x) { return e4m3_round(x); }
 
+/* Nearest bfloat16 value of x (8 significant bits), ties to even. */
+static double bf16_round(double x) {
+  if (x == 0.0 || !isfinite(x)) return x;
+  int e;
+  frexp(x, &e);                      /* |x| in [2^(e-1), 2^e): the step is 2^(e-8) */
+  return ldexp(nearbyint(ldexp(x, 8 - e)), e - 8);
+}
+
+double orc_bf16_round(double x) { return bf16_round(x); }
+
 /* A ReLU output a >= 0 held as float8 with scale 2^k: 2^k * e4m3(min(a / 2^k, 448)). */
 static double act_round(double a, int k) { return ldexp(e4m3_round(ldexp(a, -k)), k); }
 
 /* Forward of one leaf MLP.  acts (optional) receives the input features followed by the
    pre-activation of every layer (widths din[0], dout[0], ..., dout[last]).  aexp (optional,
-   one exponent per hidden layer): each hidden layer's ReLU outputs are rounded by act_round
-   with that layer's exponent before the next layer reads them. */
+   one exponent per hidden layer): the float8 model -- the input features are rounded to
+   bfloat16 (the first layer's operands), and each hidden layer's ReLU outputs are rounded by
+   act_round with that layer's exponent before the next layer reads them. */
 static void mlp_forward(const olayout* L, const double* P, const double u[IN_DIM], double out[OUT_DIM],
                         double* acts, const int32_t* aexp) {
   double a[MAX_HIDDEN], z[MAX_HIDDEN];
   int w = IN_DIM;
-  for (int i = 0; i < IN_DIM; ++i) a[i] = u[i];
+  for (int i = 0; i < IN_DIM; ++i) a[i] = aexp ? bf16_round(u[i]) : u[i];
   double* rec = acts;
   if (rec) { memcpy(rec, u, sizeof(double) * IN_DIM); rec += IN_DIM; }
   for (int l = 0; l < L->n_lin; ++l) {

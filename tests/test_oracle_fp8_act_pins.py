@@ -23,6 +23,15 @@ def test_c_rounding_matches_the_table_quantiser():
     assert np.array_equal(got, want)
 
 
+def test_c_bf16_rounding_matches_the_bit_rounding():
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.standard_normal(3000) * np.exp(rng.uniform(-20, 20, 3000)),
+                        [1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8), 0.0, 3.0e38]])
+    x = x.astype(np.float32)
+    got = np.array([oracle.bf16_round(float(v)) for v in x])
+    assert np.array_equal(got, fp8.bf16_round(x).astype(np.float64))
+
+
 def test_exponent_rules_hand_worked():
     # activations: 1.25 m <= 448 * 2^k; 358.4 in float32 is just below 448 / 1.25, and
     # 1.25 * 0.7 (float32 0.7 is just below it) is 0.875 = 448 * 2^-9
@@ -86,6 +95,21 @@ def test_rounding_and_saturation_closed_form():
     p2 = _one_leaf(1, H, [(W0, [-3.0, 1e-4]), (Wo, np.zeros(4))])
     got = oracle.mlp_eval_q8(p2, 1, H, x, dr, [0])[0]
     assert np.allclose(got, heads(np.zeros(4)), rtol=1e-15)
+
+
+def test_first_layer_inputs_are_bfloat16():
+    """p_x = 2x - 1 just below an e4m3 midpoint (0.59375) rounds to the midpoint in bfloat16,
+    which then goes to the even e4m3 neighbour 0.625; unrounded it would give 0.5625."""
+    H = 2
+    W0 = np.zeros((H, 30)); W0[0, 0] = 1.0
+    Wo = np.zeros((4, H)); Wo[1, 0] = 1.0
+    p = _one_leaf(1, H, [(W0, np.zeros(H)), (Wo, np.zeros(4))])
+    px = 0.59375 - 2.0 ** -11
+    x = np.array([[(px + 1.0) / 2.0, 0.5, 0.5]]); dr = np.array([[0.0, 0.0, 1.0]])
+    assert 2.0 * x[0, 0] - 1.0 == px
+    got = oracle.mlp_eval_q8(p, 1, H, x, dr, [0])[0, 1]
+    assert got == 1.0 / (1.0 + np.exp(-0.625))
+    assert oracle.mlp_eval(p, 1, H, x, dr)[0, 1] == 1.0 / (1.0 + np.exp(-px))
 
 
 def _two_leaf_scene():
