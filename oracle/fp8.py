@@ -24,8 +24,10 @@ two (an exact rescaling, applied by the matrix instruction's block scales):
   bfloat16 (round to nearest even), its inputs being the bfloat16 positional encoding;
   biases stay float32;
 * hidden layer j's ReLU outputs a get the exponent k = the smallest integer with
-  1.25 * m <= 448 * 2^k, m the calibration maximum of that leaf and layer (0 when m = 0),
-  and are held as 2^k * e4m3(min(a / 2^k, 448)) (the oracle's C forward applies this).
+  1.25 * m <= 256 * 2^k, m the calibration maximum of that leaf and layer (0 when m = 0),
+  and are held as 2^k * e4m3(min(a / 2^k, 256)) (the oracle's C forward applies this):
+  saturation at 256, the largest power of two e4m3 holds, lets the kernel apply ReLU and
+  saturation as one clamp to [0, 1] before a conversion that scales by 2^8.
 """
 from __future__ import annotations
 
@@ -115,10 +117,13 @@ def pow2_exponent(m, limit: float) -> np.ndarray:
     return out
 
 
+ACT_SAT = 256.0   # float8 activations saturate at ACT_SAT * 2^k
+
+
 def act_exponents(act_max) -> np.ndarray:
-    """Activation exponents [L][n_hidden] from float32 calibration maxima: 1.25 m <= 448 * 2^k."""
+    """Activation exponents [L][n_hidden] from float32 calibration maxima: 1.25 m <= 256 * 2^k."""
     m = np.asarray(act_max, dtype=np.float32).astype(np.float64)
-    return pow2_exponent(1.25 * m, MAX)
+    return pow2_exponent(1.25 * m, ACT_SAT)
 
 
 def quantise_mma(W: np.ndarray, n_hidden: int, hidden: int, act_max):

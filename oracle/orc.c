@@ -29,7 +29,7 @@
  *   - float8 activations (not in the paper; the large workload's float8 matrix-core
  *     path): the input features rounded to bfloat16 and every hidden activation rounded to
  *     the nearest e4m3 value times a power-of-two scale 2^k per leaf and layer, saturating
- *     at 448 * 2^k; and the calibration maxima
+ *     at 256 * 2^k; and the calibration maxima
  *     those scales come from (the largest ReLU output per leaf and hidden layer over the
  *     samples of a render).
  *
@@ -601,8 +601,12 @@ static double bf16_round(double x) {
 
 double orc_bf16_round(double x) { return bf16_round(x); }
 
-/* A ReLU output a >= 0 held as float8 with scale 2^k: 2^k * e4m3(min(a / 2^k, 448)). */
-static double act_round(double a, int k) { return ldexp(e4m3_round(ldexp(a, -k)), k); }
+/* A ReLU output a >= 0 held as float8 with scale 2^k, saturating at 256 * 2^k (the largest
+   power of two e4m3 holds): 2^k * e4m3(min(a / 2^k, 256)). */
+static double act_round(double a, int k) {
+  const double x = ldexp(a, -k);
+  return ldexp(e4m3_round(x < 256.0 ? x : 256.0), k);
+}
 
 /* Forward of one leaf MLP.  acts (optional) receives the input features followed by the
    pre-activation of every layer (widths din[0], dout[0], ..., dout[last]).  aexp (optional,

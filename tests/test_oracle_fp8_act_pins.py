@@ -33,9 +33,10 @@ def test_c_bf16_rounding_matches_the_bit_rounding():
 
 
 def test_exponent_rules_hand_worked():
-    # activations: 1.25 m <= 448 * 2^k; 358.4 in float32 is just below 448 / 1.25, and
-    # 1.25 * 0.7 (float32 0.7 is just below it) is 0.875 = 448 * 2^-9
-    assert fp8.act_exponents([358.4, 358.40002, 0.0, 1.0, 0.7, 1000.0]).tolist() == [0, 1, 0, -8, -9, 2]
+    # activations: 1.25 m <= 256 * 2^k; 204.8 in float32 is just above 256 / 1.25 (and the
+    # float32 below it just under), 1.25 * 0.8 (float32 0.8 is just above 0.8) is just above
+    # 1 = 256 * 2^-8, and 1.25 * 0.375 = 0.46875 lies in (256 * 2^-10, 256 * 2^-9]
+    assert fp8.act_exponents([204.79999, 204.8, 0.0, 0.8, 0.375, 1000.0]).tolist() == [0, 1, 0, -7, -9, 3]
     # weights: max |W| <= 448 * 2^e
     assert fp8.pow2_exponent([448.0, 448.5, 0.7, 0.0, 0.875], 448.0).tolist() == [0, 1, -9, 0, -9]
 
@@ -81,15 +82,15 @@ def test_rounding_and_saturation_closed_form():
         sp = np.log1p(np.exp(z[0]))
         return np.array([sp] + [1.0 / (1.0 + np.exp(-v)) for v in z[1:]])
 
-    # k = 0: 17 is a tie between 16 and 18 -> 16 (even code); 1000 saturates at 448
+    # k = 0: 17 is a tie between 16 and 18 -> 16 (even code); 1000 saturates at 256
     got = oracle.mlp_eval_q8(p, 1, H, x, dr, [0])[0]
-    assert np.allclose(got, heads(np.array([16 / 64, 448 / 1024, -16 / 64 + 448 / 1024, 0.0])), rtol=1e-15)
+    assert np.allclose(got, heads(np.array([16 / 64, 256 / 1024, -16 / 64 + 256 / 1024, 0.0])), rtol=1e-15)
     # k = 2: 17/4 = 4.25 -> 4 (tie, even) -> 16; 1000/4 = 250 -> 256 -> 1024
     got = oracle.mlp_eval_q8(p, 1, H, x, dr, [2])[0]
     assert np.allclose(got, heads(np.array([16 / 64, 1.0, -16 / 64 + 1.0, 0.0])), rtol=1e-15)
-    # k = -12: 17 * 2^12 and 1000 * 2^12 saturate at 448 * 2^-12
+    # k = -12: 17 * 2^12 and 1000 * 2^12 saturate at 256 * 2^-12
     got = oracle.mlp_eval_q8(p, 1, H, x, dr, [-12])[0]
-    s = 448 * 2.0 ** -12
+    s = 256 * 2.0 ** -12
     assert np.allclose(got, heads(np.array([s / 64, s / 1024, -s / 64 + s / 1024, 0.0])), rtol=1e-15)
     # negative pre-activations are zero before rounding; tiny ones underflow to zero
     p2 = _one_leaf(1, H, [(W0, [-3.0, 1e-4]), (Wo, np.zeros(4))])
