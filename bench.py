@@ -47,7 +47,7 @@ FLOP_PER_SAMPLE_4x64 = 2 * (30 * 64 + 3 * 64 * 64 + 64 * 4)   # 28 928, unpadded
 # backward per sample: the forward again (activations are recomputed, not stored), the input
 # gradients of layers 1..4 (layer 0's input needs none) and every weight gradient
 FLOP_PER_SAMPLE_BWD_4x64 = FLOP_PER_SAMPLE_4x64 + 2 * (3 * 64 * 64 + 64 * 4) + FLOP_PER_SAMPLE_4x64   # 82 944
-PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
+PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
 
 
 HEADLINE_PSNR_DB = 45.0   # the headline path's quality bar against the oracle
@@ -82,7 +82,7 @@ def median(xs):
     return 0.5 * (xs[(k - 1) // 2] + xs[k // 2])
 
 
-LARGE_PATHS = ("fp8", "fp8_prop", "bf16", "bf16_prop", "fp8_untrained_prop", "fp8_ess")
+LARGE_PATHS = ("fp8", "fp8_prop", "bf16", "bf16_prop", "fp8_untrained_prop", "fp8_ess", "fp8act", "fp8act_prop")
 
 
 def large_scene(args, am, torch, np, synth, ctx):
@@ -103,6 +103,27 @@ def large_scene(args, am, torch, np, synth, ctx):
     master = torch.from_numpy(W).to(dev)
     mlps = {k: am.Mlp(ctx, master, cfg.n_hidden, cfg.hidden, dt, L)
             for k, dt in (("fp8", am.AMNERF_FP8), ("bf16", am.AMNERF_BF16), ("f32", am.AMNERF_F32))}
+    wanted = [k for k in LARGE_PATHS if k in args.large_paths.split(",")]
+    calibration = None
+    act_max = None
+    if any(k.startswith("fp8act") for k in wanted):
+        # float8 activations on the matrix cores: activation exponents from the calibration
+        # maxima of a bfloat16 render of 2^20 random pixels of 20 other cameras (untimed)
+        t0 = time.perf_counter()
+        cal_cams = synth.make_cameras(20, cfg.seed_batches + 3, cfg.width, cfg.height)
+        co, cd = synth.random_pixel_rays(cal_cams, 1 << 20, cfg.seed_batches + 4)
+        co, cd = torch.from_numpy(co).to(dev), torch.from_numpy(cd).to(dev)
+        cal_rgb = torch.empty((co.shape[1], 3), dtype=torch.float32, device=dev)
+        am.amnerf_render(ctx.h, tree.h, mlps["bf16"].desc, co, cd, cfg.s_max, cal_rgb, None, None, None, cfg.ert_eps)
+        act_max = torch.zeros((L, cfg.n_hidden), dtype=torch.float32, device=dev)
+        am.amnerf_mlp_calibrate(ctx.h, cfg.n_hidden, L, master, co, cd, act_max)
+        mlps["fp8act"] = am.Mlp(ctx, master, cfg.n_hidden, cfg.hidden, am.AMNERF_FP8_ACT, L, act_max_dev=act_max)
+        torch.cuda.synchronize()
+        unseen = int((act_max.max(dim=1).values == 0).sum())
+        del co, cd, cal_rgb
+        calibration = {"rays": 1 << 20, "cameras": 20, "seconds": time.perf_counter() - t0,
+                       "leaves_without_samples": unseen}
+        log("large calibration: %s" % calibration)
     # 50 held-out cameras: the proposal paths render all of them in one call; the paths
     # without a proposal render the first 30 (the same seeds) in one call
     n_cams = cfg.n_cameras
@@ -121,7 +142,6 @@ def large_scene(args, am, torch, np, synth, ctx):
     log("large scene %s: %d leaves, %d rays per call (%d with a proposal), set-up %.1f s" % (
         cfg.name, L, R, R50, time.perf_counter() - t0))
 
-    wanted = [k for k in LARGE_PATHS if k in args.large_paths.split(",")]
     prop_training = None
     prop = desc = desc_untrained = None
     if any(k.endswith("_prop") for k in wanted):
@@ -157,7 +177,7 @@ def large_scene(args, am, torch, np, synth, ctx):
     occ = am.Occupancy(ctx, grid, cfg.grid_n, 2, 0.01)
     paths = {"fp8": ("fp8", None, None), "fp8_prop": ("fp8", desc, None), "bf16": ("bf16", None, None),
              "bf16_prop": ("bf16", desc, None), "fp8_untrained_prop": ("fp8", desc_untrained, None),
-             "fp8_ess": ("fp8", None, occ)}
+             "fp8_ess": ("fp8", None, occ), "fp8act": ("fp8act", None, None), "fp8act_prop": ("fp8act", desc, None)}
     paths = {k: paths[k] for k in wanted}
 
     def cams_of(kind):
@@ -191,6 +211,10 @@ def large_scene(args, am, torch, np, synth, ctx):
         mlp_ms = stage_ms["mlp"] / calls
         Rk = R1 * nc
         tf = FLOP_PER_SAMPLE_4x64 * st["n_samples"] / (mlp_ms * 1e-3) / 1e12
+        act8 = paths[kind][0] == "fp8act"
+        peak = PEAK_TFLOPS["fp8" if act8 else "bf16"]
+        kname = ("k_mlp8<4> (e4m3 weights and activations; first layer bf16)" if act8 else "k_mlp<64,bf16>"
+                 + (" (e4m3 weights widened on chip)" if paths[kind][0] == "fp8" else ""))
         res[kind] = {"ms_per_frame": 1e3 * dt / nc, "ms_per_call": 1e3 * dt, "cameras_per_call": nc,
                      "samples_per_s": st["n_samples"] / dt, "samples_per_frame": st["n_samples"] / nc,
                      "composited_samples_per_frame": st["n_composited"] / nc,
@@ -198,14 +222,12 @@ def large_scene(args, am, torch, np, synth, ctx):
                      "chunks_per_call": st["n_chunks"],
                      "stage_ms_per_frame": {k: v / calls / nc for k, v in stage_ms.items()},
                      "mlp_tflops": tf,
-                     "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
-                                  "frac": tf / PEAK_TFLOPS["bf16"], "traffic": None, "kernel": "k_mlp<64,bf16>"
-                                  + (" (e4m3 weights widened on chip)" if paths[kind][0] == "fp8" else ""),
-                                  "kernel_ms_per_call": mlp_ms}}
+                     "roofline": {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
+                                  "frac": tf / peak, "traffic": None, "kernel": kname, "kernel_ms_per_call": mlp_ms}}
         log("large %s: %.3f ms/frame (%d cameras per call, median of %d calls), %.3e samples/s, %.1f samples/ray, "
             "fallback %.3f, MLP %.3f of peak, stages %s" % (
                 kind, res[kind]["ms_per_frame"], nc, calls, res[kind]["samples_per_s"], res[kind]["samples_per_ray"],
-                res[kind]["fallback_fraction"], tf / PEAK_TFLOPS["bf16"],
+                res[kind]["fallback_fraction"], tf / peak,
                 {k: round(v, 4) for k, v in res[kind]["stage_ms_per_frame"].items()}))
     am.amnerf_ctx_set_timing(ctx.h, False)
 
@@ -214,7 +236,8 @@ def large_scene(args, am, torch, np, synth, ctx):
     # is made for this, untimed)
     psnr_prop_vs_plain = {}
     plain50 = {}
-    for kind, ref in (("fp8_prop", "fp8"), ("bf16_prop", "bf16"), ("fp8_untrained_prop", "fp8"), ("fp8_ess", "fp8")):
+    for kind, ref in (("fp8_prop", "fp8"), ("bf16_prop", "bf16"), ("fp8_untrained_prop", "fp8"), ("fp8_ess", "fp8"),
+                      ("fp8act_prop", "fp8act")):
         if kind not in outs or ref not in paths:
             continue
         if cams_of(kind) == n_prop_cams:
@@ -251,7 +274,7 @@ def large_scene(args, am, torch, np, synth, ctx):
         log("large bucket sizes: %s" % spread)
 
     acc = None
-    acc_kinds = [k for k in ("fp8", "fp8_prop", "fp8_ess") if k in outs]
+    acc_kinds = [k for k in ("fp8", "fp8_prop", "fp8_ess", "fp8act", "fp8act_prop") if k in outs]
     if not args.no_cpu and acc_kinds:
         import oracle
         from oracle import fp8 as ofp8
@@ -271,14 +294,28 @@ def large_scene(args, am, torch, np, synth, ctx):
         _, _, deq = ofp8.quantise(W, cfg.n_hidden, cfg.hidden)
         rgb_q, _, _, _, _ = oracle.render(otree, deq.astype(np.float32), cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max,
                                           eps=cfg.ert_eps, ray_idx=sel, threads=threads)
+        rgb_qa = rgb_q8 = None
+        if act_max is not None:
+            # the float8 matrix-core model: its own (power-of-two) weight quantisation, with
+            # float64 activations, and with float8 activations on the same exponents
+            _, k_act, deq_a = ofp8.quantise_mma(W, cfg.n_hidden, cfg.hidden, act_max.cpu().numpy())
+            rgb_qa, _, _, _, _ = oracle.render(otree, deq_a, cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max,
+                                               eps=cfg.ert_eps, ray_idx=sel, threads=threads)
+            rgb_q8, _, _ = oracle.render_q8(otree, deq_a, cfg.n_hidden, cfg.hidden, o0, d0, cfg.s_max, k_act,
+                                            eps=cfg.ert_eps, ray_idx=sel, threads=threads)
         sel_dev = torch.from_numpy(sel).to(dev)
         acc = {"rays": int(sel.size), "sample": "seeded 1/64 pixel subset of camera 0"}
+
+        def psnr_vs(x, ref):
+            return am.amnerf_error_stats(ctx.h, x, torch.from_numpy(np.ascontiguousarray(ref)).to(dev).view(-1))["psnr"]
         for kind in acc_kinds:
             x = outs[kind][:R1][sel_dev].contiguous().view(-1)
-            acc["psnr_%s_vs_oracle_db" % kind] = am.amnerf_error_stats(
-                ctx.h, x, torch.from_numpy(np.ascontiguousarray(rgb_o)).to(dev).view(-1))["psnr"]
-            acc["psnr_%s_vs_oracle_fp8_weights_db" % kind] = am.amnerf_error_stats(
-                ctx.h, x, torch.from_numpy(np.ascontiguousarray(rgb_q)).to(dev).view(-1))["psnr"]
+            acc["psnr_%s_vs_oracle_db" % kind] = psnr_vs(x, rgb_o)
+            if kind.startswith("fp8act"):
+                acc["psnr_%s_vs_oracle_fp8_weights_db" % kind] = psnr_vs(x, rgb_qa)
+                acc["psnr_%s_vs_oracle_fp8_model_db" % kind] = psnr_vs(x, rgb_q8)
+            else:
+                acc["psnr_%s_vs_oracle_fp8_weights_db" % kind] = psnr_vs(x, rgb_q)
         log("large accuracy: %s" % acc)
         if "fp8" in res:
             res["fp8"]["cpu_baseline"] = cpu_plain
@@ -316,7 +353,7 @@ def large_scene(args, am, torch, np, synth, ctx):
             "proposal_rays_per_call": R50, "proposal_cameras_per_call": n_prop_cams, "paths": res,
             "occupancy": {"cells": occ.g ** 3, "occupied": occ.n_occupied, "block": 2, "thresh": 0.01},
             "psnr_vs_plain_db": psnr_prop_vs_plain, "bucket_sizes": spread, "accuracy": acc,
-            "proposal_training": prop_training}
+            "proposal_training": prop_training, "fp8act_calibration": calibration}
 
 
 def main():

@@ -53,6 +53,15 @@ extern "C" {
                                  (max |W| / 448), widened to bfloat16 when a leaf's block is
                                  staged on chip; bfloat16 activations, float32 accumulate.
                                  Render only (no backward). */
+#define AMNERF_FP8_ACT 3      /* float8 e4m3 weights AND activations on the float8 matrix cores
+                                 (hidden 64, n_hidden 1 .. 4): the first layer in bfloat16
+                                 (inputs and weights); the hidden and output layers take e4m3
+                                 weight codes W / 2^e (e the smallest exponent with
+                                 max |W| <= 448 * 2^e, per leaf and layer) and e4m3 activation
+                                 codes a / 2^k (per leaf and hidden layer, see
+                                 amnerf_mlp_pack_fp8_act; values above 256 * 2^k saturate);
+                                 float32 accumulate, float32 biases (carried as a bfloat16 high
+                                 and low part, about 16 significant bits).  Render only. */
 
 /* ---- limits -------------------------------------------------------------------------- */
 #define AMNERF_MAX_GRID 512   /* guidance grid side */
@@ -205,9 +214,31 @@ int amnerf_mlp_packed_bytes(const amnerf_mlp_shape* shape, int32_t dtype, int32_
 int amnerf_mlp_pack(amnerf_ctx* ctx, const amnerf_mlp_shape* shape, int32_t dtype,
                     int32_t n_leaves, const float* master_dev, void* packed_dev, void* stream);
 
+/* Packs device master parameters float32[n_leaves][P] as an AMNERF_FP8_ACT block (shape:
+ * hidden 64, n_hidden 1 .. 4) with the activation exponents derived from calibration maxima:
+ * k[leaf][j] = the smallest integer with 1.25 * act_max[leaf][j] <= 256 * 2^k (evaluated
+ * exactly; 0 where the maximum is 0), so hidden layer j's ReLU outputs a are held as
+ * 2^k * e4m3(min(a / 2^k, 256)) (256: the largest power of two e4m3 holds).  act_max_dev: device float32[n_leaves][n_hidden]
+ * (amnerf_mlp_calibrate), or NULL for every k = 0 (what amnerf_mlp_pack does for this
+ * dtype).  The block is n_leaves equal leaf blocks of amnerf_mlp_packed_bytes / n_leaves
+ * bytes, each: 16 int32 (k[0..3], the weight exponents e of layers 1..4, then the E8M0 block
+ * scale of each float8 layer's weight operand, 127 + e_l + k_(l-1) - k_l - 8 for a hidden
+ * layer and 127 + e_n + k_(n-1) for the output layer, clamped to 0 .. 254, and 4 zeros);
+ * 4096 bytes of layer 0's bfloat16 weights times 2^-(k_0 + 8) (64 rows x 32 inputs: the 30
+ * features and the bias times 2^-(k_0 + 8) as a bfloat16 high and low part); 4096 bytes of
+ * e4m3 codes W / 2^e per hidden layer 1 .. n_hidden - 1 and 2048 bytes for the output layer
+ * (32 rows, of which the first 4 are the outputs and the rest zero), each in fragment order,
+ * in which every weight appears once; then 2 n_hidden - 1 words of 256 bytes holding the
+ * other layers' biases (a hidden layer's over 2^(k_l + 8)) as bfloat16 high and low parts; zero
+ * padding to a multiple of 256 bytes.  Launches on `stream`; AMNERF_EINVAL for a bad shape,
+ * count or NULL pointer, AMNERF_EDEVICE. */
+int amnerf_mlp_pack_fp8_act(amnerf_ctx* ctx, const amnerf_mlp_shape* shape, int32_t n_leaves,
+                            const float* master_dev, const float* act_max_dev, void* packed_dev,
+                            void* stream);
+
 typedef struct {
   amnerf_mlp_shape shape;
-  int32_t dtype;          /* AMNERF_F32, AMNERF_BF16 or AMNERF_FP8 */
+  int32_t dtype;          /* AMNERF_F32, AMNERF_BF16, AMNERF_FP8 or AMNERF_FP8_ACT */
   int32_t n_leaves;       /* parameter sets: the tree's leaf count (its node count for a
                              render with hierarchical sampling) */
   const void* packed_dev; /* device block written by amnerf_mlp_pack with the same
@@ -442,6 +473,18 @@ int amnerf_render_backward(amnerf_ctx* ctx, const amnerf_tree* tree, const amner
                            const amnerf_rays* rays, const float* g_rgb_dev,
                            const float* g_depth_dev, const float* g_opacity_dev,
                            float* grad_dev, void* stream);
+
+/* Calibration for AMNERF_FP8_ACT (not in the paper): over every sample the most recent
+ * amnerf_render on this context evaluated, the float32 forward of the master parameters
+ * master_dev float32[n_leaves][P] (shape: hidden 64, n_hidden 1 .. 4); act_max_dev[leaf][j]
+ * (device float32[n_leaves][n_hidden]) is raised to the largest ReLU output of hidden layer j
+ * of that leaf.  The caller zeroes it before the first call; calls over several renders
+ * accumulate.  That render must have used these rays and n_leaves parameter sets and run as
+ * a single chunk, without AMNERF_ERT_ROUNDS and not in the static workspace (else
+ * AMNERF_ESTATE).  Launches on `stream`. */
+int amnerf_mlp_calibrate(amnerf_ctx* ctx, const amnerf_mlp_shape* shape, int32_t n_leaves,
+                         const float* master_dev, const amnerf_rays* rays, float* act_max_dev,
+                         void* stream);
 
 /* Copies the per-sample gradient of the last amnerf_render_backward with respect to the
  * MLP output pre-activations, dL/d(sigma^, r^, g^, b^), into the caller's device

@@ -26,6 +26,7 @@ AMNERF_ESTATE = -5
 AMNERF_F32 = 0
 AMNERF_BF16 = 1
 AMNERF_FP8 = 2
+AMNERF_FP8_ACT = 3
 AMNERF_SPLIT_MEDIAN = 0
 AMNERF_SPLIT_MIDDLE = 1
 AMNERF_JITTER = 1
@@ -48,7 +49,7 @@ EXPORTS = [
     "amnerf_build_tree_codes", "amnerf_build_tree_distilled", "amnerf_adam_step", "amnerf_train_step",
     "amnerf_prop_param_count", "amnerf_prop_packed_bytes", "amnerf_prop_pack", "amnerf_propose",
     "amnerf_error_stats", "amnerf_render_backward_inspect", "amnerf_render_static",
-    "amnerf_render_static_capacity",
+    "amnerf_render_static_capacity", "amnerf_mlp_pack_fp8_act", "amnerf_mlp_calibrate",
 ]
 AMNERF_PROPOSE_INFER = 0
 AMNERF_PROPOSE_TRAIN = 1
@@ -180,6 +181,8 @@ def _load():
     lib.amnerf_mlp_packed_bytes.argtypes = [C.POINTER(amnerf_mlp_shape), C.c_int32, C.c_int32,
                                             C.POINTER(C.c_size_t)]
     lib.amnerf_mlp_pack.argtypes = [P, C.POINTER(amnerf_mlp_shape), C.c_int32, C.c_int32, P, P, P]
+    lib.amnerf_mlp_pack_fp8_act.argtypes = [P, C.POINTER(amnerf_mlp_shape), C.c_int32, P, P, P, P]
+    lib.amnerf_mlp_calibrate.argtypes = [P, C.POINTER(amnerf_mlp_shape), C.c_int32, P, C.POINTER(amnerf_rays), P, P]
     lib.amnerf_render.argtypes = [P, P, C.POINTER(amnerf_mlp), C.POINTER(amnerf_rays),
                                   C.POINTER(amnerf_render_params), C.POINTER(amnerf_render_out), P]
     lib.amnerf_render_static.argtypes = lib.amnerf_render.argtypes
@@ -355,6 +358,19 @@ def amnerf_mlp_pack(ctx, n_hidden: int, hidden: int, dtype: int, n_leaves: int, 
     s = amnerf_mlp_shape(n_hidden, hidden)
     _check(_lib.amnerf_mlp_pack(ctx, C.byref(s), dtype, n_leaves, _ptr(master_dev), _ptr(packed_dev),
                                 _stream(stream)))
+
+
+def amnerf_mlp_pack_fp8_act(ctx, n_hidden: int, n_leaves: int, master_dev, act_max_dev, packed_dev, stream=None):
+    s = amnerf_mlp_shape(n_hidden, 64)
+    _check(_lib.amnerf_mlp_pack_fp8_act(ctx, C.byref(s), n_leaves, _ptr(master_dev), _ptr(act_max_dev),
+                                        _ptr(packed_dev), _stream(stream)))
+
+
+def amnerf_mlp_calibrate(ctx, n_hidden: int, n_leaves: int, master_dev, o_dev, d_dev, act_max_dev, stream=None):
+    s = amnerf_mlp_shape(n_hidden, 64)
+    rays = amnerf_rays(_ptr(o_dev), _ptr(d_dev), int(o_dev.shape[1]))
+    _check(_lib.amnerf_mlp_calibrate(ctx, C.byref(s), n_leaves, _ptr(master_dev), C.byref(rays), _ptr(act_max_dev),
+                                     _stream(stream)))
 
 
 def amnerf_render(ctx, tree, mlp: amnerf_mlp, o_dev, d_dev, s_max: int, rgb_dev, depth_dev=None,
@@ -572,12 +588,18 @@ class Tree:
 class Mlp:
     """Packed per-leaf parameters on the device (kept alive with the descriptor)."""
 
-    def __init__(self, ctx: Context, master_dev, n_hidden, hidden, dtype, n_leaves, stream=None):
+    def __init__(self, ctx: Context, master_dev, n_hidden, hidden, dtype, n_leaves, stream=None, act_max_dev=None):
+        """act_max_dev: calibration maxima for AMNERF_FP8_ACT (amnerf_mlp_calibrate), else None."""
         import torch
         nbytes = amnerf_mlp_packed_bytes(n_hidden, hidden, dtype, n_leaves)
         self.packed = torch.empty(nbytes, dtype=torch.uint8, device=master_dev.device)
         self.master = master_dev
-        amnerf_mlp_pack(ctx.h, n_hidden, hidden, dtype, n_leaves, master_dev, self.packed, stream)
+        if act_max_dev is not None:
+            if dtype != AMNERF_FP8_ACT or hidden != 64:
+                raise ValueError("calibration maxima are for AMNERF_FP8_ACT (hidden 64) only")
+            amnerf_mlp_pack_fp8_act(ctx.h, n_hidden, n_leaves, master_dev, act_max_dev, self.packed, stream)
+        else:
+            amnerf_mlp_pack(ctx.h, n_hidden, hidden, dtype, n_leaves, master_dev, self.packed, stream)
         self.desc = amnerf_mlp(amnerf_mlp_shape(n_hidden, hidden), dtype, n_leaves,
                                C.c_void_p(self.packed.data_ptr()))
         self.n_hidden, self.hidden, self.dtype, self.n_leaves = n_hidden, hidden, dtype, n_leaves

@@ -17,8 +17,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libamnerf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["amnerf.cpp", "trav.hip", "scan.hip", "sort.hip", "mlp.hip", "mlp_bwd.hip", "comp.hip", "train.hip",
-           "prop.hip", "err.hip", "ess.hip", "ert.hip"]
+SOURCES = ["amnerf.cpp", "trav.hip", "scan.hip", "sort.hip", "mlp.hip", "mlp8.hip", "mlp_bwd.hip", "comp.hip",
+           "train.hip", "prop.hip", "err.hip", "ess.hip", "ert.hip"]
 # Packed fp32 arithmetic is disabled for all device code.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -27,7 +27,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-u
 # accumulators in ordinary VGPRs: in the accumulation registers each result would first be
 # copied out (one v_accvgpr_read per value).
 PER_FILE = {"prop.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
-            "mlp_bwd.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+            "mlp_bwd.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+            "mlp8.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src: str) -> str:

@@ -181,7 +181,7 @@ struct amnerf_occ {
 // misc
 // ---------------------------------------------------------------------------------------
 extern "C" const char* amnerf_last_error(void) { return g_err.c_str(); }
-extern "C" int amnerf_version(void) { return 100; }
+extern "C" int amnerf_version(void) { return 200; }
 
 extern "C" int amnerf_ctx_create(int device, size_t workspace_cap, amnerf_ctx** out) {
   if (!out) return fail(AMNERF_EINVAL, "amnerf_ctx_create: out is NULL");
@@ -890,6 +890,18 @@ extern "C" int amnerf_mlp_pack(amnerf_ctx* ctx, const amnerf_mlp_shape* s, int32
   return AMNERF_OK;
 }
 
+extern "C" int amnerf_mlp_pack_fp8_act(amnerf_ctx* ctx, const amnerf_mlp_shape* s, int32_t n_leaves,
+                                       const float* master, const float* act_max, void* packed, void* stream) {
+  MlpGeom g;
+  int rc = check_geom(s, AMNERF_FP8_ACT, &g, "amnerf_mlp_pack_fp8_act");
+  if (rc) return rc;
+  if (!ctx || !master || !packed || n_leaves < 1 || n_leaves > AMNERF_MAX_LEAVES)
+    return fail(AMNERF_EINVAL, "amnerf_mlp_pack_fp8_act: bad argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(launch_mlp8_pack(s->n_hidden, n_leaves, master, act_max, packed, (hipStream_t)stream));
+  return AMNERF_OK;
+}
+
 // ---------------------------------------------------------------------------------------
 // render
 // ---------------------------------------------------------------------------------------
@@ -1438,6 +1450,28 @@ extern "C" int amnerf_render_backward(amnerf_ctx* ctx, const amnerf_tree* tree, 
   if (!ctx || !tree || !mlp || !rays) return fail(AMNERF_EINVAL, "amnerf_render_backward: null argument");
   HIP_TRY(hipSetDevice(ctx->device));
   return backward_impl(ctx, tree, mlp, rays, g_rgb, g_depth, g_opac, grad, (hipStream_t)stream, nullptr, false, nullptr);
+}
+
+extern "C" int amnerf_mlp_calibrate(amnerf_ctx* ctx, const amnerf_mlp_shape* s, int32_t n_leaves, const float* master,
+                                    const amnerf_rays* rays, float* act_max, void* stream) {
+  MlpGeom g;
+  int rc = check_geom(s, AMNERF_FP8_ACT, &g, "amnerf_mlp_calibrate");
+  if (rc) return rc;
+  if (!ctx || !master || !rays || !act_max || n_leaves < 1)
+    return fail(AMNERF_EINVAL, "amnerf_mlp_calibrate: bad argument");
+  if (!ctx->have_render || ctx->last_rays != rays->n_rays || ctx->last_o != rays->o_dev)
+    return fail(AMNERF_ESTATE, "amnerf_mlp_calibrate: the last render on this context used other rays");
+  if (ctx->last_chunks != 1 || ctx->last_static || (ctx->last_params.flags & AMNERF_ERT_ROUNDS))
+    return fail(AMNERF_ESTATE, "amnerf_mlp_calibrate: the last render ran in several chunks, in rounds or in the "
+                "static workspace");
+  if ((uint32_t)n_leaves != ctx->last_leaves)
+    return fail(AMNERF_EINVAL, "amnerf_mlp_calibrate: %d parameter sets, the last render used %u", n_leaves,
+                ctx->last_leaves);
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(launch_act_max(s->n_hidden, master, (uint32_t)n_leaves, ctx->bucket_off, ctx->tile_off, ctx->counts,
+                         ctx->srec_ray, ctx->srec_t, rays->o_dev, rays->d_dev, rays->n_rays, 0, act_max,
+                         (hipStream_t)stream));
+  return AMNERF_OK;
 }
 
 extern "C" int amnerf_render_backward_inspect(amnerf_ctx* ctx, float* sample_grad_dev, void* stream) {

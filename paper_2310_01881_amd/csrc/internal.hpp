@@ -156,6 +156,24 @@ hipError_t launch_mlp(const MlpGeom& g, const void* packed, uint32_t n_leaves,
                       const uint32_t* perm, const float* o, const float* d, int64_t ray_stride,
                       int64_t r0, float* out, hipStream_t st);
 
+// ---- float8 weights and activations on the float8 matrix cores (hidden width 64,
+// n_hidden 1..4) ----------------------------------------------------------------------------
+size_t mlp8_block_bytes(int n_hidden);
+// act_max: device float32[n_leaves][n_hidden] calibration maxima, or null (every activation
+// exponent 0).
+hipError_t launch_mlp8_pack(int n_hidden, int n_leaves, const float* master, const float* act_max, void* packed,
+                            hipStream_t st);
+hipError_t launch_mlp8(int n_hidden, const void* packed, uint32_t n_leaves, const uint32_t* bucket_off,
+                       const uint32_t* tile_off, const ChunkCounts* counts, const uint32_t* srec_ray,
+                       const float* srec_t, const uint32_t* perm, const float* o, const float* d, int64_t stride,
+                       int64_t r0, float* out, hipStream_t st);
+// Raises act_max[leaf][j] to the largest ReLU output of hidden layer j over the sorted
+// samples (float32 forward of the master parameters).
+hipError_t launch_act_max(int n_hidden, const float* master, uint32_t n_leaves, const uint32_t* bucket_off,
+                          const uint32_t* tile_off, const ChunkCounts* counts, const uint32_t* srec_ray,
+                          const float* srec_t, const float* o, const float* d, int64_t stride, int64_t r0,
+                          float* act_max, hipStream_t st);
+
 // ---- compositing (Section 3.1 -> NeRF quadrature, early ray termination) ---------------
 // ray_used[r] receives the number of samples of ray r that were composited (the stop
 // sample included), and counts->composited their sum.

@@ -552,6 +552,15 @@ hipError_t resident_blocks(const void* kern, int threads, uint32_t lds, int* per
 bool mlp_geom(int n_hidden, int hidden, int dtype, MlpGeom* g) {
   if (n_hidden < 1 || n_hidden > 8) return false;
   if (hidden != 32 && hidden != 64) return false;
+  if (dtype == AMNERF_FP8_ACT) {
+    if (hidden != 64 || n_hidden > 4) return false;
+    g->n_hidden = n_hidden;
+    g->hidden = hidden;
+    g->dtype = dtype;
+    g->node_bytes = mlp8_block_bytes(n_hidden);
+    g->bwd_node_bytes = 0;
+    return true;
+  }
   if (dtype != AMNERF_F32 && dtype != AMNERF_BF16 && dtype != AMNERF_FP8) return false;
   Layout L = make_layout(n_hidden, hidden, dtype);
   if (L.bytes > 160 * 1024) return false;
@@ -565,6 +574,7 @@ bool mlp_geom(int n_hidden, int hidden, int dtype, MlpGeom* g) {
 
 hipError_t launch_mlp_pack(const MlpGeom& g, int n_leaves, const float* master, void* packed,
                            hipStream_t st) {
+  if (g.dtype == AMNERF_FP8_ACT) return launch_mlp8_pack(g.n_hidden, n_leaves, master, nullptr, packed, st);
   Layout L = make_layout(g.n_hidden, g.hidden, g.dtype);
   int P = master_param_count(g.n_hidden, g.hidden);
   if (g.dtype == AMNERF_FP8)
@@ -578,6 +588,9 @@ hipError_t launch_mlp(const MlpGeom& g, const void* packed, uint32_t n_leaves, c
                       const uint32_t* tile_off, const ChunkCounts* counts, const uint32_t* srec_ray,
                       const float* srec_t, const uint32_t* perm, const float* o, const float* d,
                       int64_t ray_stride, int64_t r0, float* out, hipStream_t st) {
+  if (g.dtype == AMNERF_FP8_ACT)
+    return launch_mlp8(g.n_hidden, packed, n_leaves, bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d,
+                       ray_stride, r0, out, st);
   Layout L = make_layout(g.n_hidden, g.hidden, g.dtype);
   if (g.dtype == AMNERF_FP8) {
     if (g.hidden == 64) return launch_typed<64, true, true>(L, packed, n_leaves, bucket_off, tile_off, counts, srec_ray, srec_t, perm, o, d, ray_stride, r0, out, st);

@@ -67,6 +67,7 @@ CASES = {
     "small_bf16_occupancy": dict(cfg=synth.C1, dtype=am.AMNERF_BF16, s_max=128, occupancy=True),
     "small_f32_proposal": dict(cfg=synth.C1, dtype=am.AMNERF_F32, s_max=160, proposal=True, saves=False),
     "c2_bf16_s128": dict(cfg=synth.C2, dtype=am.AMNERF_BF16, s_max=128, rays=120_000),
+    "small_fp8act_s192": dict(cfg=synth.scaled(synth.C1, n_hidden=4, hidden=64), dtype=am.AMNERF_FP8_ACT, s_max=192),
 }
 
 
