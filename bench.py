@@ -29,7 +29,11 @@ A second, larger workload follows in the same run and is reported under `large_s
 skew, a 4096-leaf tree, float8 (and bfloat16) leaf weights and S_max 192; one call renders
 30 held-out cameras without a proposal (and with empty space skipped by an occupancy
 grid), and one call renders 50 held-out cameras (the same first 30, then 20 more) with a
-proposal trained on 200 other cameras (--large-paths picks a subset of these paths).
+proposal trained on 200 other cameras (--large-paths picks a subset of these paths).  The
+`fp8act` paths run float8 weights and activations on the float8 matrix cores, with
+activation exponents from a calibration render of 2^20 pixels of 20 other cameras; they
+are priced at the float8 peak and judged against the oracle's float8 model and against the
+oracle on their own dequantised weights.
 """
 from __future__ import annotations
 
