@@ -381,7 +381,7 @@ def main():
                          "plain reference path too)")
     ap.add_argument("--ablation-steps", type=int, default=400,
                     help="training steps per student of the ablation's quality comparison (0: skip)")
-    ap.add_argument("--inflight", type=int, default=2,
+    ap.add_argument("--inflight", type=int, default=3,
                     help="frames in flight for the throughput line: contexts on streams of their own")
     ap.add_argument("--windows", type=int, default=5,
                     help="timed windows of --steps frames with frames in flight (the median is reported)")
