@@ -248,3 +248,41 @@ def test_unsupported_shapes_rejected():
         with pytest.raises(am.AmnerfError) as e:
             am.amnerf_mlp_packed_bytes(nh, hid, am.AMNERF_FP8_ACT, 4)
         assert e.value.code == am.AMNERF_EINVAL
+
+
+@pytest.mark.parametrize("mode", ["plain", "hcheck", "ess"])
+def test_multi_chunk_call_equals_chunk_by_chunk_calls(mode):
+    """A three-pass call (odd passes on the context's second lane) with float8 activations,
+    plain, with hierarchical sampling (node MLPs) or with empty space skipped: outputs and
+    sample count bit-identical to three calls on the same slices."""
+    cfg = synth.scaled(synth.C1, n_hidden=4, hidden=64)
+    scene = Scene(cfg, footprint=0.5 if mode == "hcheck" else 0.0)
+    ctx = am.Context(0)
+    tree = am.Tree(ctx, scene.grid, cfg.grid_n, cfg.max_depth, cfg.max_leaves, 0)
+    amax = np.exp(np.random.default_rng(9).uniform(0, 3, (scene.n_sets, cfg.n_hidden))).astype(np.float32)
+    mlp = am.Mlp(ctx, to_dev(scene.W), cfg.n_hidden, 64, am.AMNERF_FP8_ACT, scene.n_sets, act_max_dev=to_dev(amax))
+    kw = {}
+    if mode == "hcheck":
+        kw = {"hcheck_footprint": scene.footprint}
+    elif mode == "ess":
+        kw = {"occupancy": am.Occupancy(ctx, scene.grid, cfg.grid_n, 2, 0.01)}
+    o, d = scene.camera_rays()
+    od = to_dev(o).repeat(1, 640).contiguous()
+    dd = to_dev(d).repeat(1, 640).contiguous()
+    R = od.shape[1]
+    chunk = (1 << 28) // 255
+    assert 2 * chunk < R < 3 * chunk
+    print("fp8-act multi-chunk %s: rays %d" % (mode, R), flush=True)
+    whole = am.render(ctx, tree, mlp, od, dd, 255, ert_eps=cfg.ert_eps, **kw)
+    torch.cuda.synchronize()
+    st = am.amnerf_render_stats_get(ctx.h)
+    assert st["n_chunks"] == 3 and st["n_nonfinite"] == 0 and st["n_unreached"] == 0
+    n_samples = 0
+    for r0 in range(0, R, chunk):
+        part = am.render(ctx, tree, mlp, od[:, r0:r0 + chunk].contiguous(), dd[:, r0:r0 + chunk].contiguous(), 255,
+                         ert_eps=cfg.ert_eps, **kw)
+        torch.cuda.synchronize()
+        n_samples += am.amnerf_render_stats_get(ctx.h)["n_samples"]
+        for k in ("rgb", "depth", "opacity"):
+            assert torch.equal(whole[k][r0:r0 + chunk], part[k]), (k, r0)
+    assert st["n_samples"] == n_samples
