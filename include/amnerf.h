@@ -60,8 +60,9 @@ extern "C" {
                                  max |W| <= 448 * 2^e, per leaf and layer) and e4m3 activation
                                  codes a / 2^k (per leaf and hidden layer, see
                                  amnerf_mlp_pack_fp8_act; values above 256 * 2^k saturate);
-                                 float32 accumulate, float32 biases (carried as a bfloat16 high
-                                 and low part, about 16 significant bits).  Render only. */
+                                 float32 accumulate, float32 biases (the output layer's carried
+                                 as a bfloat16 high and low part, about 16 significant bits).
+                                 Render only. */
 
 /* ---- limits -------------------------------------------------------------------------- */
 #define AMNERF_MAX_GRID 512   /* guidance grid side */
@@ -225,11 +226,12 @@ int amnerf_mlp_pack(amnerf_ctx* ctx, const amnerf_mlp_shape* shape, int32_t dtyp
  * scale of each float8 layer's weight operand, 127 + e_l + k_(l-1) - k_l - 8 for a hidden
  * layer and 127 + e_n + k_(n-1) for the output layer, clamped to 0 .. 254, and 4 zeros);
  * 4096 bytes of layer 0's bfloat16 weights times 2^-(k_0 + 8) (64 rows x 32 inputs: the 30
- * features and the bias times 2^-(k_0 + 8) as a bfloat16 high and low part); 4096 bytes of
- * e4m3 codes W / 2^e per hidden layer 1 .. n_hidden - 1 and 2048 bytes for the output layer
- * (32 rows, of which the first 4 are the outputs and the rest zero), each in fragment order,
- * in which every weight appears once; then 2 n_hidden - 1 words of 256 bytes holding the
- * other layers' biases (a hidden layer's over 2^(k_l + 8)) as bfloat16 high and low parts; zero
+ * features and two zero columns); 4096 bytes of e4m3 codes W / 2^e per hidden layer
+ * 1 .. n_hidden - 1 and 2048 bytes for the output layer (32 rows, of which the first 4 are
+ * the outputs and the rest zero), each in fragment order, in which every weight appears
+ * once; n_hidden blocks of 256 bytes holding the biases of layers 0 .. n_hidden - 1 over
+ * 2^(k_l + 8) as float32 (rows in accumulator order); 256 bytes holding the output layer's
+ * biases as bfloat16 high and low parts (one 4-byte word per lane); zero
  * padding to a multiple of 256 bytes.  Launches on `stream`; AMNERF_EINVAL for a bad shape,
  * count or NULL pointer, AMNERF_EDEVICE. */
 int amnerf_mlp_pack_fp8_act(amnerf_ctx* ctx, const amnerf_mlp_shape* shape, int32_t n_leaves,

@@ -12,12 +12,11 @@
 //   * hidden layer j's ReLU outputs a are held as e4m3(min(a / 2^k_j, 256)), k_j from the
 //     calibration maximum m of that leaf and layer (the smallest k with 1.25 m <= 256 * 2^k).
 // Each hidden layer's accumulator comes out already divided by 256 * 2^k of its own
-// activations: layer 0's weights and bias are pre-scaled by 2^-(k_0 + 8), and the weight
-// operand of layer l >= 1 carries the block scale 2^(e_l + k_(l-1) - k_l - 8), its bias
-// b / 2^(k_l + 8) (the output layer: 2^(e_n + k_(n-1)), its bias unscaled).  Conversion to
-// the next layer's operand is then one clamp to [0, 1] per value (ReLU and saturation, a
-// full-rate add with the clamp bit, the add being the bias's) and one packed conversion per
-// two values that multiplies by 2^8 on the way.
+// activations: layer 0's weights are pre-scaled by 2^-(k_0 + 8), and the weight operand of
+// layer l >= 1 carries the block scale 2^(e_l + k_(l-1) - k_l - 8), its bias b / 2^(k_l + 8)
+// (the output layer: 2^(e_n + k_(n-1)), its bias unscaled).  Conversion to the next layer's
+// operand is then one bias add per value that carries the clamp bit (ReLU and saturation
+// at full rate) and one packed conversion per two values that multiplies by 2^8.
 //
 // Data flow inside a wave (64 rows = 2 column blocks of 32 samples): every layer is
 // computed transposed, Y^T = W X^T, weights as the A operand, activations as the B operand.
@@ -28,11 +27,11 @@
 // the same way.  Activations never leave registers.  A block stages its leaf's parameter
 // block (about 20 KB for 4 hidden layers) in LDS when the leaf changes, and every wave reads
 // each weight operand from there as it needs it (32 bytes per lane per 32-row block), which
-// leaves registers for three waves per SIMD.  Biases: layer 0's enter through two extra
-// input slots (constant 1) holding the bias as a bfloat16 high and low part; every other
-// layer's is broadcast over the 32 columns by one bfloat16 MFMA per 32-row block (A = the
-// high and low parts in two K slots, B = ones), then added to a hidden layer's accumulators
-// by the clamping add, or taken as the output layer's accumulator input.
+// leaves registers for three waves per SIMD.  Biases of the layers whose outputs are
+// activations are float32, stored per layer in accumulator order (the 16 rows of each lane
+// half of each row block), read from LDS at the start of the layer and added by the
+// clamping add; the output layer's is broadcast over the 32 columns by one bfloat16 MFMA
+// (A = its high and low parts in two K slots, B = ones) and taken as the accumulator input.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -53,12 +52,12 @@ constexpr int kThreads8 = 256;
 constexpr int kHdrBytes = 64;            // int32 header: k_j [0..3], e_l [4..7], block scale [8..11]
 constexpr int kFrag = 1024;              // 64 lanes x 16 bytes (bfloat16 layer 0)
 constexpr int kFrag8 = 2048;             // 64 lanes x 32 bytes (a float8 weight operand)
-constexpr int kBiasFrag = 256;           // 64 lanes x 4 bytes
-constexpr int kBiasHi = 30, kBiasLo = 31;   // layer-0 input slots holding the constant 1
+constexpr int kBiasBlock = 256;          // one layer's activation biases: float [rb][h][16]
+constexpr int kBiasWord = 256;           // the output bias broadcast operand: 64 lanes x 4 bytes
 
 struct Layout8 {
   int nh;
-  uint32_t off_l0, off_hid, off_out, off_bias, bytes;
+  uint32_t off_l0, off_hid, off_out, off_bias, off_obias, bytes;
 };
 
 __host__ __device__ inline Layout8 make_layout8(int nh) {
@@ -68,16 +67,17 @@ __host__ __device__ inline Layout8 make_layout8(int nh) {
   L.off_hid = L.off_l0 + 4 * kFrag;                       // (rb, s) fragments
   L.off_out = L.off_hid + (uint32_t)(nh - 1) * 2 * kFrag8; // per layer, rb: 32 bytes per lane
   L.off_bias = L.off_out + kFrag8;                        // output: 32 bytes per lane
-  const uint32_t end = L.off_bias + (uint32_t)(2 * nh - 1) * kBiasFrag;
+  L.off_obias = L.off_bias + (uint32_t)nh * kBiasBlock;   // layers 0 .. nh-1: biases in C order
+  const uint32_t end = L.off_obias + kBiasWord;
   L.bytes = (end + 255u) / 256u * 256u;
   return L;
 }
 
 // Input feature in byte/element e of K step s of lane half h (layer 0, bfloat16 B operand):
 // half 0 holds coordinate x at the four frequencies (step 0) and y (step 1), half 1 holds z
-// (step 0) and then p, d and the two bias slots (step 1).  sin / cos pairs alternate.
+// (step 0) and then p, d and two zero slots (-1, step 1).  sin / cos pairs alternate.
 __host__ __device__ inline int l0_feature(int s, int h, int e) {
-  if (s == 1 && h == 1) return e < 3 ? e : (e < 6 ? 27 + (e - 3) : (e == 6 ? kBiasHi : kBiasLo));
+  if (s == 1 && h == 1) return e < 3 ? e : (e < 6 ? 27 + (e - 3) : -1);
   const int coord = h == 0 ? (s == 0 ? 0 : 1) : 2;
   return 3 + 6 * (e / 2) + 3 * (e % 2) + coord;
 }
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kThreads8) void k_mlp8_exps(int nh, int P, const fl
   }
   {
     uint8_t* blk = packed + (uint64_t)leaf * L.bytes;
-    for (uint32_t i = L.off_bias + (uint32_t)(2 * nh - 1) * kBiasFrag + threadIdx.x; i < L.bytes; i += kThreads8) blk[i] = 0;
+    for (uint32_t i = L.off_obias + kBiasWord + threadIdx.x; i < L.bytes; i += kThreads8) blk[i] = 0;
   }
   if (threadIdx.x == 0) {
     int* hdr = reinterpret_cast<int*>(packed + (uint64_t)leaf * L.bytes);
@@ -148,12 +148,13 @@ __global__ __launch_bounds__(kThreads8) void k_mlp8_exps(int nh, int P, const fl
   }
 }
 
-// One thread per (leaf, item): a 16-byte lane fragment of a weight layer or a 4-byte bias
-// lane word.  Reads the exponents k_mlp8_exps wrote.
+// One thread per (leaf, item): a 16-byte lane fragment of a weight layer, one bias of a
+// layer whose outputs are activations, or the output layer's 4-byte bias lane word.  Reads
+// the exponents k_mlp8_exps wrote.
 __global__ void k_mlp8_pack(int nh, int n_leaves, int P, const float* __restrict__ master, uint8_t* __restrict__ packed) {
   const Layout8 L = make_layout8(nh);
   const int frags = 4 + (nh - 1) * 4 + 2;                 // 16-byte lane fragments per leaf
-  const int per_leaf = frags * 64 + (2 * nh - 1) * 64;
+  const int per_leaf = frags * 64 + nh * 64 + 64;
   const uint64_t total = (uint64_t)per_leaf * n_leaves;
   for (uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
        id += (uint64_t)gridDim.x * blockDim.x) {
@@ -169,18 +170,12 @@ __global__ void k_mlp8_pack(int nh, int n_leaves, int P, const float* __restrict
         int din, dout, off_w, off_b;
         master_offsets(nh, 64, 0, din, dout, off_w, off_b);
         const int row = 32 * rb + c, k0 = hdr[0] + 8;
-        const float bs = ldexpf(Wm[off_b + row], -k0);    // exact
-        const uint32_t bhi = bf16_bits(bs);
-        const uint32_t blo = bf16_bits(bs - bf16_value(bhi));
         uint32_t w[4];
         for (int q = 0; q < 4; ++q) {
           uint32_t two = 0;
           for (int t = 0; t < 2; ++t) {
             const int col = l0_feature(s, h, 2 * q + t);
-            uint32_t bits;
-            if (col == kBiasHi) bits = bhi;
-            else if (col == kBiasLo) bits = blo;
-            else bits = bf16_bits(ldexpf(Wm[off_w + row * din + col], -k0));
+            const uint32_t bits = col >= 0 ? bf16_bits(ldexpf(Wm[off_w + row * din + col], -k0)) : 0u;
             two |= bits << (16 * t);
           }
           w[q] = two;
@@ -208,51 +203,53 @@ __global__ void k_mlp8_pack(int nh, int n_leaves, int P, const float* __restrict
         const uint32_t off = layer < nh ? L.off_hid + (uint32_t)((layer - 1) * 2 + rb) * kFrag8 : L.off_out;
         *reinterpret_cast<i32x4*>(blk + off + lane * 32 + half * 16) = i32x4{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
       }
-    } else {                                              // bias word (layer, rb): lanes of half 0
+    } else if (rem < frags * 64 + nh * 64) {            // bias of layer l < nh over 2^(k_l + 8)
       rem -= frags * 64;
-      const int bi = rem / 64, lane = rem % 64, h = lane / 32, c = lane % 32;
-      const int layer = bi < 2 * (nh - 1) ? 1 + bi / 2 : nh;
-      const int rb = layer < nh ? bi % 2 : 0;
+      const int layer = rem / 64, idx = rem % 64;
+      const int rb = idx / 32, h = (idx / 16) % 2, v = idx % 16;
       int din, dout, off_w, off_b;
       master_offsets(nh, 64, layer, din, dout, off_w, off_b);
-      const int row = 32 * rb + c;
+      const int row = 32 * rb + 8 * (v / 4) + 4 * h + (v % 4);   // accumulator register v of half h
+      *reinterpret_cast<float*>(blk + L.off_bias + (uint32_t)layer * kBiasBlock + idx * 4) =
+          ldexpf(Wm[off_b + row], -(hdr[layer] + 8));      // exact
+    } else {                                              // output bias word: lanes of half 0
+      const int lane = rem - frags * 64 - nh * 64, h = lane / 32, c = lane % 32;
+      int din, dout, off_w, off_b;
+      master_offsets(nh, 64, nh, din, dout, off_w, off_b);
       uint32_t word = 0;
-      if (h == 0 && row < dout) {
-        const int kout = layer < nh ? hdr[layer] + 8 : 0;
-        const float bs = ldexpf(Wm[off_b + row], -kout);
+      if (h == 0 && c < dout) {
+        const float bs = Wm[off_b + c];
         const uint32_t bhi = bf16_bits(bs);
         word = bhi | (bf16_bits(bs - bf16_value(bhi)) << 16);
       }
-      *reinterpret_cast<uint32_t*>(blk + L.off_bias + (uint32_t)bi * kBiasFrag + lane * 4) = word;
+      *reinterpret_cast<uint32_t*>(blk + L.off_obias + lane * 4) = word;
     }
   }
 }
 
-// ReLU, saturation and e4m3 conversion of both row blocks of one column block: the next
-// layer's 32-byte B operand (byte 16 rb + 4 j + i = register 4 j + i of row block rb).  The
-// accumulators (plus the broadcast bias, when given) hold activations over 256 * 2^k; they
-// are clamped to [0, 1] -- ReLU and saturation in one instruction, a full-rate add with the
-// clamp bit when there is a bias to add, else a half-rate maximum with it -- and the
+// ReLU, saturation and e4m3 conversion of both column blocks: the next layer's 32-byte B
+// operands (byte 16 rb + 4 j + i = register 4 j + i of row block rb).  The accumulators plus
+// the layer's biases (b[rb][j] = the biases of registers 4 j .. 4 j + 3 of row block rb of
+// this lane half) hold activations over 256 * 2^k; they are clamped to [0, 1] -- ReLU and
+// saturation in the bias add itself, which carries the clamp bit at full rate -- and the
 // conversion divides by the exponent of its scale operand, 2^-8, so the codes are
 // e4m3(min(a / 2^k, 256)).
-template <bool BIAS>
-__device__ __forceinline__ i32x8 to_fp8(const f32x16& a0, const f32x16& a1, const f32x16& b0, const f32x16& b1) {
-  i32x8 r;
+__device__ __forceinline__ void to_fp8(const f32x16 (&a)[2][2], const f32x4 (&b)[2][4], i32x8 (&act)[2]) {
 #pragma unroll
   for (int w = 0; w < 8; ++w) {
-    const f32x16& a = w < 4 ? a0 : a1;
-    const f32x16& b = w < 4 ? b0 : b1;
-    const int v = 4 * (w % 4);
-    float x[4];
+    const int rb = w / 4, j = w % 4;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) x[i] = __builtin_amdgcn_fmed3f(BIAS ? a[v + i] + b[v + i] : a[v + i], 0.f, 1.f);
-    // the first conversion writes the low half of a register whose high half the second
-    // one overwrites, so x0's own register serves (no zeroing move)
-    const s16x2 lo = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(__builtin_bit_cast(s16x2, x[0]), x[0], x[1], 0.00390625f,
-                                                              false);
-    r[w] = __builtin_bit_cast(int, __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(lo, x[2], x[3], 0.00390625f, true));
+    for (int cb = 0; cb < 2; ++cb) {
+      float x[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = __builtin_amdgcn_fmed3f(a[rb][cb][4 * j + i] + b[rb][j][i], 0.f, 1.f);
+      // the first conversion writes the low half of a register whose high half the second
+      // one overwrites, so x0's own register serves (no zeroing move)
+      const s16x2 lo = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(__builtin_bit_cast(s16x2, x[0]), x[0], x[1],
+                                                                0.00390625f, false);
+      act[cb][w] = __builtin_bit_cast(int, __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(lo, x[2], x[3], 0.00390625f, true));
+    }
   }
-  return r;
 }
 
 template <int NH>
@@ -278,8 +275,9 @@ __global__ __launch_bounds__(kThreads8) void k_mlp8(
   uint32_t b = lo;
   int cur = -1;
 
-  // the leaf's bias words and block scales, in registers (the weights are read from LDS)
-  uint32_t Bw[2 * NH - 1];
+  // the output layer's bias word and the block scales, in registers (the weights and the
+  // other biases are read from LDS)
+  uint32_t bwo = 0u;
   int sc[NH];
   // B operand of the bias broadcast: K slots 0 and 1 (lanes of half 0) are 1
   uint32_t ones_u[4] = {h == 0 ? 0x3F803F80u : 0u, 0u, 0u, 0u};
@@ -322,8 +320,7 @@ __global__ __launch_bounds__(kThreads8) void k_mlp8(
       const int* hdr = reinterpret_cast<const int*>(lds);
 #pragma unroll
       for (int l = 0; l < NH; ++l) sc[l] = hdr[8 + l];
-#pragma unroll
-      for (int i = 0; i < 2 * NH - 1; ++i) Bw[i] = *reinterpret_cast<const uint32_t*>(lds + L.off_bias + i * kBiasFrag + lane * 4);
+      bwo = *reinterpret_cast<const uint32_t*>(lds + L.off_obias + lane * 4);
       cur = (int)b;
     }
     const uint32_t row0 = q_row0, row_end = q_end;
@@ -370,13 +367,32 @@ __global__ __launch_bounds__(kThreads8) void k_mlp8(
       if (h) {
         f2[0] = px; f2[1] = py; f2[2] = pz;
         f2[3] = dx; f2[4] = dy; f2[5] = dz;
-        f2[6] = 1.f; f2[7] = 1.f;
+        f2[6] = 0.f; f2[7] = 0.f;
       }
       X[cb][0] = cvt_bf16x8(f1);
       X[cb][1] = cvt_bf16x8(f2);
     }
 
+    // Two compiler liberties are taken away with empty asm statements.  The bias and weight
+    // loads of a layer do not depend on its input, and would all be hoisted to the top of
+    // the tile (the registers of a wave per SIMD); the statement that takes a layer's whole
+    // input ties them to it.  And a value used only by the final masked store would be
+    // computed under that store's lane mask, but the matrix instructions combine lanes:
+    // every lane's operand must be written, so each layer's input and the output are
+    // consumed unconditionally.
+    uint32_t wl = lane * 32u, hb = (uint32_t)h * 64u;
+    f32x4 bias[2][4];
+    auto load_bias = [&](int layer) {
+      const uint8_t* bl = lds + L.off_bias + (uint32_t)layer * kBiasBlock + hb;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bias[rb][j] = *reinterpret_cast<const f32x4*>(bl + rb * 128 + j * 16);
+    };
+
     // ---- layer 0 (bfloat16) ----
+    asm volatile("" : "+v"(hb) : "v"(X[0][0]), "v"(X[1][0]));
+    load_bias(0);
     f32x16 acc[2][2];
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
@@ -391,27 +407,13 @@ __global__ __launch_bounds__(kThreads8) void k_mlp8(
     if (more) gather();
     __builtin_amdgcn_sched_barrier(0);
     i32x8 act[2];
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) act[cb] = to_fp8<false>(acc[0][cb], acc[1][cb], zero16, zero16);
+    to_fp8(acc, bias, act);
 
     // ---- hidden layers (float8) ----
-    // Two compiler liberties are taken away with empty asm statements.  The bias broadcasts
-    // and weight loads of a layer do not depend on its input, and would all be hoisted to the
-    // top of the tile (seven 16-register biases for four hidden layers: the registers of a
-    // second wave per SIMD); the statement that takes a layer's whole input ties them to it.
-    // And a value used only by the final masked store would be computed under that store's
-    // lane mask, but the matrix instructions combine lanes: every lane's operand must be
-    // written, so each layer's input and the output are consumed unconditionally.
-    uint32_t wl = lane * 32u;
 #pragma unroll
     for (int l = 0; l < NH - 1; ++l) {
-      uint32_t bw0 = Bw[2 * l], bw1 = Bw[2 * l + 1];
-      asm volatile("" : "+v"(bw0), "+v"(bw1), "+v"(wl) : "v"(act[0]), "v"(act[1]));
-      // the bias, broadcast over the columns once per row block, is added on the vector
-      // units together with the clamp (the add carries the clamp bit at full rate)
-      const uint32_t bwa[4] = {bw0, 0u, 0u, 0u}, bwb[4] = {bw1, 0u, 0u, 0u};
-      const f32x16 bc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, bwa), ones, zero16, 0, 0, 0);
-      const f32x16 bc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, bwb), ones, zero16, 0, 0, 0);
+      asm volatile("" : "+v"(hb), "+v"(wl) : "v"(act[0]), "v"(act[1]));
+      load_bias(l + 1);
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) {
         const i32x8 w = *reinterpret_cast<const i32x8*>(lds + L.off_hid + (l * 2 + rb) * kFrag8 + wl);
@@ -419,13 +421,14 @@ __global__ __launch_bounds__(kThreads8) void k_mlp8(
         for (int cb = 0; cb < 2; ++cb)
           acc[rb][cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(w, act[cb], zero16, 0, 0, 0, sc[l], 0, 127);
       }
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) act[cb] = to_fp8<true>(acc[0][cb], acc[1][cb], bc0, bc1);
+      to_fp8(acc, bias, act);
     }
 
-    // ---- output layer (float8; rows 0..3 are sigma^, r^, g^, b^) ----
+    // ---- output layer (float8; rows 0..3 are sigma^, r^, g^, b^): the bias, broadcast over
+    // the columns by one bfloat16 MFMA (A = its high and low parts in two K slots, B = ones),
+    // is the accumulator input ----
     {
-      uint32_t bw = Bw[2 * (NH - 1)];
+      uint32_t bw = bwo;
       asm volatile("" : "+v"(bw), "+v"(wl) : "v"(act[0]), "v"(act[1]));
       const uint32_t bwa[4] = {bw, 0u, 0u, 0u};
       const f32x16 bo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, bwa), ones, zero16, 0, 0, 0);

@@ -44,7 +44,7 @@ def block_regions(n_hidden):
         off += 4096
     layers.append((off, 2048))
     off += 2048
-    bias = (off, (2 * n_hidden - 1) * 256)
+    bias = (off, n_hidden * 256 + 256)
     off += bias[1]
     return layers, bias, (off + 255) // 256 * 256
 
