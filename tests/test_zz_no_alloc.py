@@ -33,6 +33,7 @@ C2_SMALL = synth.scaled(synth.C2, grid_n=64, max_leaves=64, max_depth=12)
 @pytest.mark.parametrize("cfg,dtype,sizes,weights", [
     (synth.C1, am.AMNERF_F32, (4096, 1000), True),
     (C2_SMALL, am.AMNERF_BF16, (6000, 2500), False),
+    (C2_SMALL, am.AMNERF_FP8_ACT, (6000, 2500), False),
 ])
 def test_static_render_equals_render(cfg, dtype, sizes, weights):
     scene = Scene(cfg)
