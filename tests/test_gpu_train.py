@@ -157,6 +157,56 @@ def test_backward_bf16_matches_oracle_on_bf16_weights(cfg, eps, kind):
     assert np.all(g_gpu[~hit] == 0)
 
 
+def test_full_batch_backward_on_sampled_rays():
+    """The backward at the training step's full size: a 262 144-ray batch of the 800x800
+    scene (512 leaves, one chunk, the training batches' recipe) with upstream gradients on
+    a seeded subset of its rays only.  The gradient is linear in the upstream gradients and
+    every other ray contributes exact zeros, so it must equal the oracle's over the subset
+    alone: on 4 096 rays (about 8 per leaf) at the squared-error bar against the oracle on the
+    bf16-rounded weights, and, on 256 rays, exactly zero for every leaf none of them crosses.
+    (With about one ray per leaf, 256 rays leave the bf16 rounding of a few ReLU inputs
+    unaveraged: measured 2.3e-2 there.)  Subset rays are robust ones (no split edge within
+    the traversal's rounding), so both sides trace the same leaves."""
+    cfg = synth.C2
+    scene = Scene(cfg)
+    ctx, tree, tr = setup(scene)
+    B = 262144
+    tcams = synth.make_cameras(100, cfg.seed_batches + 3, cfg.width, cfg.height)
+    o, d = synth.random_pixel_rays(tcams, B, cfg.seed_batches + 4)
+    Wb = bf16_round(scene.W)
+    f64 = lambda a: a.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(9)
+    for n_sub in (4096, 256):
+        cand = np.sort(rng.choice(B, n_sub + 64, replace=False))
+        sub = cand[oracle.robust(scene.otree, o[:, cand], d[:, cand])][:n_sub]
+        assert len(sub) == n_sub
+        # a squared-error residual of one sign over the image (red too dark, blue too bright)
+        g_sub = np.tile(2.0 * np.array([-0.05, 0.0, 0.05]) / (3 * n_sub), (n_sub, 1))
+        g_rgb = np.zeros((B, 3))
+        g_rgb[sub] = g_sub
+        print("full-batch backward: %d rays, upstream gradients on %d" % (B, n_sub), flush=True)
+        g_gpu = gpu_grad(scene, ctx, tree, tr.mlp, tr.master, o, d, cfg.s_max, cfg.ert_eps, g_rgb, np.zeros(B),
+                         np.zeros(B))
+        st = am.amnerf_render_stats_get(ctx.h)
+        assert st["n_chunks"] == 1 and st["n_rays"] == B and st["n_unreached"] == 0
+        assert np.isfinite(g_gpu).all()
+        g_ref = oracle.render_grad(scene.otree, Wb, cfg.n_hidden, cfg.hidden, o, d, cfg.s_max, f64(g_sub),
+                                   np.zeros(n_sub), np.zeros(n_sub), eps=cfg.ert_eps, ray_idx=sub)
+        e = rel_l2(g_gpu, g_ref)
+        _, _, slot, m = oracle.trace(scene.otree, o, d, ray_idx=sub)
+        crossed = np.zeros(g_ref.shape[0], bool)
+        for k in range(n_sub):
+            crossed[slot[k, :m[k]]] = True
+        print("full-batch backward, %d rays: relative L2 error %.3e against the oracle on bf16 weights; "
+              "%d of %d leaves crossed" % (n_sub, e, crossed.sum(), len(crossed)), flush=True)
+        if n_sub == 4096:
+            assert e <= TOL_BF16_MSE
+        else:
+            assert e <= TOL_BF16_RANDOM
+            assert crossed.sum() > 100 and (~crossed).sum() > 10
+            assert np.all(g_gpu[~crossed] == 0)
+
+
 def inv_softplus(s):
     return np.where(s > 30, s, np.log(np.expm1(np.maximum(s, 1e-300))))
 
