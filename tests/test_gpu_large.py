@@ -24,6 +24,9 @@ S_MAX = synth.C3.s_max
 # the dequantised weights (measured 82.1 and 54.5 dB)
 PSNR_FP8ACT_VS_Q8 = 76.0
 PSNR_FP8ACT_VS_DEQ = 49.0
+# the proposal launch against the oracle's planned render on the dequantised weights
+# (measured 79.6 dB)
+PSNR_PROP_LAUNCH = 74.0
 
 
 @pytest.fixture(scope="module")
@@ -169,3 +172,51 @@ def test_c3_thirty_cameras_fp8act_in_one_call(scene):
           "%.2f dB on %d rays of %d cameras" % (p_q8, np.abs(g - q8).max(), p_deq, pick.size,
                                                 len(np.unique(pick // R1))), flush=True)
     assert p_q8 > PSNR_FP8ACT_VS_Q8 and p_deq > PSNR_FP8ACT_VS_DEQ
+
+
+def test_c3_fifty_cameras_with_proposal_in_one_call(scene):
+    """The proposal workload's launch: 50 cameras (103.7 M rays) in one call with e4m3 leaf
+    weights and a proposal planning most rays (untrained, mass threshold 0.5, at most 48
+    samples; float32 inference so that plans are comparable with the oracle's float64 ones);
+    1 500 rays sampled across all cameras and passes against the oracle's planned render on
+    the dequantised weights."""
+    cfg = scene.cfg
+    ctx, tree, mlp = gpu_setup(scene, am.AMNERF_FP8)
+    prop_w = synth.make_prop_weights(cfg.seed_proposal)
+    prop = am.Proposal(ctx, torch.from_numpy(prop_w).to("cuda:0"))
+    desc = prop.descriptor(am.AMNERF_F32, mass_thresh=0.5, cap=48)
+    cams = synth.make_cameras(50, cfg.seed_cameras, cfg.width, cfg.height)
+    R1 = cfg.width * cfg.height
+    R = R1 * len(cams)
+    o_all = torch.empty((3, R), dtype=torch.float32, device="cuda:0")
+    d_all = torch.empty((3, R), dtype=torch.float32, device="cuda:0")
+    pick = np.sort(np.random.default_rng(28).choice(R, 1500, replace=False))
+    o_pick = np.zeros((3, pick.size), np.float32)
+    d_pick = np.zeros((3, pick.size), np.float32)
+    for i, c in enumerate(cams):
+        o, d = synth.camera_rays(c)
+        o_all[:, i * R1:(i + 1) * R1] = torch.from_numpy(o).to("cuda:0")
+        d_all[:, i * R1:(i + 1) * R1] = torch.from_numpy(d).to("cuda:0")
+        sel = (pick >= i * R1) & (pick < (i + 1) * R1)
+        o_pick[:, sel] = o[:, pick[sel] - i * R1]
+        d_pick[:, sel] = d[:, pick[sel] - i * R1]
+    print("c3 50 cameras with proposal: rays", R, flush=True)
+    rgb = torch.empty((R, 3), device="cuda:0")
+    am.amnerf_render(ctx.h, tree.h, mlp.desc, o_all, d_all, S_MAX, rgb, None, None, None, cfg.ert_eps,
+                     proposal=desc)
+    torch.cuda.synchronize()
+    st = am.amnerf_render_stats_get(ctx.h)
+    print("c3 50 cameras with proposal stats", st, flush=True)
+    assert st["n_nonfinite"] == 0 and st["n_unreached"] == 0 and st["n_chunks"] > 1
+    assert st["n_samples"] < 0.8 * st["n_plain_samples"]
+    g = rgb[torch.from_numpy(pick).to("cuda:0")].cpu().numpy()
+    _, _, deq = fp8.quantise(scene.W, cfg.n_hidden, cfg.hidden)
+    orgb, _, _, ons, opn, _, omass = oracle.render_proposal(scene.otree, deq.astype(np.float32), cfg.n_hidden,
+                                                            cfg.hidden, prop_w, o_pick, d_pick, S_MAX,
+                                                            eps=cfg.ert_eps, mass_thresh=0.5, cap=48)
+    near = np.abs(omass - 0.5) < 1e-4          # a plan decided within float32 rounding of the cut
+    p = oracle.psnr(g[~near], orgb[~near])
+    print("c3 50 cameras with proposal: %d of %d sampled rays planned, psnr vs oracle(dequantised) %.2f dB "
+          "(max abs %.3e)" % ((opn > 0).sum(), pick.size, p, np.abs(g[~near] - orgb[~near]).max()), flush=True)
+    assert (opn > 0).sum() > 0.3 * pick.size
+    assert p > PSNR_PROP_LAUNCH
