@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kThreads8) void k_mlp8_exps(int nh, int P, const fl
     red[threadIdx.x] = mx;
     __syncthreads();
     for (int w = kThreads8 / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+      if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
       __syncthreads();
     }
     ew[l - 1] = pow2_exponent((double)red[0], 448.0);

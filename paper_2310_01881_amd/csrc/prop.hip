@@ -1125,7 +1125,7 @@ __global__ __launch_bounds__(kThreads) void k_prop_train(const uint8_t* __restri
 
 __global__ __launch_bounds__(kThreads) void k_prop_reduce(const float* __restrict__ part, uint32_t nb,
                                                           const float* __restrict__ loss_part,
-                                                          uint32_t n_items_unused, float* __restrict__ grad,
+                                                          float* __restrict__ grad,
                                                           float* __restrict__ loss, const uint32_t* __restrict__ n_iv) {
   for (uint32_t p = blockIdx.x * kThreads + threadIdx.x; p < (uint32_t)kP; p += gridDim.x * kThreads) {
     float s = 0.f;
@@ -1157,8 +1157,8 @@ int prop_param_count() { return kP; }
 size_t prop_packed_bytes(int dtype) { return dtype == AMNERF_BF16 ? kBf16Bytes : kF32Bytes; }
 uint32_t prop_train_blocks() {
   int n = 0;
-  ncu(&n);
-  return (uint32_t)(n > 0 ? n : 256);
+  if (ncu(&n) != hipSuccess || n <= 0) return 256u;   // the device's compute units, else a fixed count
+  return (uint32_t)n;
 }
 
 hipError_t launch_prop_pack(int dtype, const float* master, void* packed, hipStream_t st) {
@@ -1223,7 +1223,7 @@ hipError_t launch_prop_train(const void* packed, const IvSet& iv, const float* o
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_prop_train, dim3(nb), dim3(kThreads), lds, st, (const uint8_t*)packed, iv, o, d, stride, r0,
                      leafbox, s_max, alpha, part, loss_part);
-  hipLaunchKernelGGL(k_prop_reduce, dim3(36), dim3(kThreads), 0, st, part, nb, loss_part, 0u, grad, loss, iv.n_iv_dev);
+  hipLaunchKernelGGL(k_prop_reduce, dim3(36), dim3(kThreads), 0, st, part, nb, loss_part, grad, loss, iv.n_iv_dev);
   return hipGetLastError();
 }
 

@@ -29,8 +29,7 @@ __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane
 
 __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t* __restrict__ iv_key,
                                                         const uint32_t* __restrict__ n_iv_dev,
-                                                        uint32_t seg, uint32_t nseg_max,
-                                                        uint32_t n_leaves,
+                                                        uint32_t seg, uint32_t n_leaves,
                                                         uint32_t* __restrict__ mat) {
   extern __shared__ uint32_t sh[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -54,8 +53,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint32_t* __restri
 
 __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint32_t* __restrict__ iv_key,
                                                            const uint32_t* __restrict__ n_iv_dev,
-                                                           uint32_t seg, uint32_t nseg_max,
-                                                           uint32_t n_leaves, uint32_t key_bits,
+                                                           uint32_t seg, uint32_t n_leaves,
+                                                           uint32_t key_bits,
                                                            const uint32_t* __restrict__ mat_scan,
                                                            uint32_t* __restrict__ sidx,
                                                            uint32_t* __restrict__ sn) {
@@ -245,8 +244,8 @@ hipError_t launch_sort_hist(const SortPlan& p, const uint32_t* iv_key, const uin
   uint32_t grid = (p.nseg_max + kWaves - 1) / kWaves;
   if (grid > kMaxGrid) grid = kMaxGrid;
   size_t lds = sizeof(uint32_t) * kWaves * p.n_leaves;
-  hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(kThreads), lds, st, iv_key, n_iv_dev, p.seg,
-                     p.nseg_max, p.n_leaves, mat);
+  hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(kThreads), lds, st, iv_key, n_iv_dev, p.seg, p.n_leaves,
+                     mat);
   return hipGetLastError();
 }
 
@@ -256,8 +255,8 @@ hipError_t launch_sort_scatter(const SortPlan& p, const uint32_t* iv_key, const 
   uint32_t grid = (p.nseg_max + kWaves - 1) / kWaves;
   if (grid > kMaxGrid) grid = kMaxGrid;
   size_t lds = sizeof(uint32_t) * kWaves * p.n_leaves;
-  hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kThreads), lds, st, iv_key, n_iv_dev, p.seg,
-                     p.nseg_max, p.n_leaves, p.key_bits, mat_scan, sidx, sn);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kThreads), lds, st, iv_key, n_iv_dev, p.seg, p.n_leaves,
+                     p.key_bits, mat_scan, sidx, sn);
   return hipGetLastError();
 }
 
