@@ -39,6 +39,9 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr uint64_t kChunkSamples = 1ull << 28;   // worst-case samples of one render pass
+// lanes of a render that runs in several chunks: chunk k runs on lane k mod kLanes, lane 0
+// being the caller's stream
+constexpr int kLanes = 4;
 
 }  // namespace
 
@@ -144,9 +147,9 @@ struct amnerf_ctx {
   // error report: block partials and totals (device), totals (pinned host)
   double* err_dev = nullptr;
   double* err_host = nullptr;
-  // second lane of a render that runs in several chunks: a stream (default priority), the
-  // fork and join events, and its own chunk workspace, proposal arena and counters
-  struct {
+  // lanes 1 .. kLanes - 1 of a render that runs in several chunks: each a stream (default
+  // priority), fork and join events, and its own chunk workspace, proposal arena and counters
+  struct Lane {
     hipStream_t stream = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     void* arena = nullptr;
@@ -154,7 +157,7 @@ struct amnerf_ctx {
     void* arena3 = nullptr;
     size_t arena3_bytes = 0;
     ChunkCounts* counts = nullptr;
-  } lane;
+  } lanes[kLanes - 1];
 };
 
 struct amnerf_tree {
@@ -227,12 +230,14 @@ extern "C" int amnerf_ctx_destroy(amnerf_ctx* ctx) {
   if (ctx->counts_host) (void)hipHostFree(ctx->counts_host);
   if (ctx->err_dev) (void)hipFree(ctx->err_dev);
   if (ctx->err_host) (void)hipHostFree(ctx->err_host);
-  if (ctx->lane.arena) (void)hipFree(ctx->lane.arena);
-  if (ctx->lane.arena3) (void)hipFree(ctx->lane.arena3);
-  if (ctx->lane.counts) (void)hipFree(ctx->lane.counts);
-  if (ctx->lane.fork) (void)hipEventDestroy(ctx->lane.fork);
-  if (ctx->lane.join) (void)hipEventDestroy(ctx->lane.join);
-  if (ctx->lane.stream) (void)hipStreamDestroy(ctx->lane.stream);
+  for (auto& ln : ctx->lanes) {
+    if (ln.arena) (void)hipFree(ln.arena);
+    if (ln.arena3) (void)hipFree(ln.arena3);
+    if (ln.counts) (void)hipFree(ln.counts);
+    if (ln.fork) (void)hipEventDestroy(ln.fork);
+    if (ln.join) (void)hipEventDestroy(ln.join);
+    if (ln.stream) (void)hipStreamDestroy(ln.stream);
+  }
   delete ctx;
   return AMNERF_OK;
 }
@@ -365,8 +370,8 @@ static int ensure_arena3(amnerf_ctx* ctx, size_t bytes) {
 // Grows a lane buffer to `bytes` (plus `extra` of slack), within the context's cap.
 static int grow_lane_buffer(amnerf_ctx* ctx, void** buf, size_t* have, size_t bytes, size_t extra) {
   if (bytes <= *have) return AMNERF_OK;
-  const size_t others = ctx->arena_bytes + ctx->arena2_bytes + ctx->arena3_bytes + ctx->lane.arena_bytes +
-                        ctx->lane.arena3_bytes - *have;
+  size_t others = ctx->arena_bytes + ctx->arena2_bytes + ctx->arena3_bytes - *have;
+  for (const auto& ln : ctx->lanes) others += ln.arena_bytes + ln.arena3_bytes;
   if (ctx->cap && bytes + others > ctx->cap)
     return fail(AMNERF_ENOMEM, "workspace needs %zu more bytes, cap is %zu", bytes, ctx->cap);
   HIP_TRY(hipDeviceSynchronize());
@@ -381,10 +386,11 @@ static int grow_lane_buffer(amnerf_ctx* ctx, void** buf, size_t* have, size_t by
   return AMNERF_OK;
 }
 
-// The second lane's stream, events, counters and chunk workspace (`need` bytes).
-static int lane_prepare(amnerf_ctx* ctx, size_t need) {
-  if (!ctx->lane.stream) {
-    // all four or none: a failure leaves the context without a second lane
+// Lane i's (1 .. kLanes - 1) stream, events, counters and chunk workspace (`need` bytes).
+static int lane_prepare(amnerf_ctx* ctx, int i, size_t need) {
+  auto& ln = ctx->lanes[i - 1];
+  if (!ln.stream) {
+    // all four or none: a failure leaves the context without this lane
     hipStream_t s = nullptr;
     hipEvent_t f = nullptr, j = nullptr;
     ChunkCounts* c = nullptr;
@@ -397,21 +403,21 @@ static int lane_prepare(amnerf_ctx* ctx, size_t need) {
       if (j) (void)hipEventDestroy(j);
       if (f) (void)hipEventDestroy(f);
       if (s) (void)hipStreamDestroy(s);
-      return fail(AMNERF_EDEVICE, "second render lane: %s", hipGetErrorString(e));
+      return fail(AMNERF_EDEVICE, "render lane %d: %s", i, hipGetErrorString(e));
     }
-    ctx->lane.stream = s;
-    ctx->lane.fork = f;
-    ctx->lane.join = j;
-    ctx->lane.counts = c;
+    ln.stream = s;
+    ln.fork = f;
+    ln.join = j;
+    ln.counts = c;
   }
-  return grow_lane_buffer(ctx, &ctx->lane.arena, &ctx->lane.arena_bytes, need, need / 8);
+  return grow_lane_buffer(ctx, &ln.arena, &ln.arena_bytes, need, need / 8);
 }
 
-// The proposal arena of the main context (lane 0) or of the second lane.
+// The proposal arena of the main context (lane 0) or of lane i.
 static int ensure_arena3(amnerf_ctx* ctx, size_t bytes);
-static int ensure_arena3_for(amnerf_ctx* ctx, bool second, size_t bytes) {
-  if (!second) return ensure_arena3(ctx, bytes);
-  return grow_lane_buffer(ctx, &ctx->lane.arena3, &ctx->lane.arena3_bytes, bytes, bytes / 4);
+static int ensure_arena3_for(amnerf_ctx* ctx, int i, size_t bytes) {
+  if (i == 0) return ensure_arena3(ctx, bytes);
+  return grow_lane_buffer(ctx, &ctx->lanes[i - 1].arena3, &ctx->lanes[i - 1].arena3_bytes, bytes, bytes / 4);
 }
 
 static int ensure_arena(amnerf_ctx* ctx, size_t bytes) {
@@ -1075,7 +1081,8 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
   if (R > 0 && (uint64_t)R < chunk) chunk = (uint64_t)R;
   const uint64_t niv_max = chunk * iv_per_ray, ns_max = chunk * (uint64_t)p->s_max;
   SortPlan sp = make_sort_plan(niv_max, L);
-  Work w0, w1;
+  Work ws[kLanes];
+  Work& w0 = ws[0];
   // early termination in rounds of 64-sample windows (a single window needs no rounds)
   const bool rounds = (p->flags & AMNERF_ERT_ROUNDS) && p->s_max > 64;
   size_t need = carve(nullptr, chunk, niv_max, ns_max, sp, w0, rounds);
@@ -1093,21 +1100,23 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
     carve((char*)ctx->arena, chunk, niv_max, ns_max, sp, w0, rounds);
   }
   // More than one chunk (and no per-sample weights, whose offsets need the chunks in
-  // order): odd chunks run on a second lane -- its own stream, workspace and counters --
-  // so one chunk's latency-bound stages overlap the other's matrix-core stage.  The lane
-  // waits for the caller's stream on entry and the caller's stream waits for the lane on
-  // exit, so the call stays asynchronous on `stream`.
+  // order): chunk k runs on lane k mod n_lanes -- lanes beyond the caller's stream have their
+  // own stream, workspace and counters -- so one chunk's latency-bound stages overlap
+  // another's matrix-core stage.  The lanes wait for the caller's stream on entry and the
+  // caller's stream waits for them on exit, so the call stays asynchronous on `stream`.
   const bool pipe = (uint64_t)R > chunk && !out->weights_dev && !static_ws;
-  if (pipe) {
-    rc = lane_prepare(ctx, need);
+  const int n_lanes = pipe ? (int)std::min<uint64_t>((uint64_t)kLanes, ((uint64_t)R + chunk - 1) / chunk) : 1;
+  for (int i = 1; i < n_lanes; ++i) {
+    rc = lane_prepare(ctx, i, need);
     if (rc) return rc;
-    carve((char*)ctx->lane.arena, chunk, niv_max, ns_max, sp, w1, rounds);
+    carve((char*)ctx->lanes[i - 1].arena, chunk, niv_max, ns_max, sp, ws[i], rounds);
   }
   HIP_TRY(launch_counts_reset(ctx->counts, st));
-  if (pipe) {
-    HIP_TRY(launch_counts_reset(ctx->lane.counts, st));
-    HIP_TRY(hipEventRecord(ctx->lane.fork, st));
-    HIP_TRY(hipStreamWaitEvent(ctx->lane.stream, ctx->lane.fork, 0));
+  for (int i = 1; i < n_lanes; ++i) {
+    auto& ln = ctx->lanes[i - 1];
+    HIP_TRY(launch_counts_reset(ln.counts, st));
+    HIP_TRY(hipEventRecord(ln.fork, st));
+    HIP_TRY(hipStreamWaitEvent(ln.stream, ln.fork, 0));
   }
   int64_t n_chunks = 0;
   IvSet use = {};
@@ -1116,10 +1125,10 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
   uint32_t *mat = w0.mat, *mat_scan = w0.mat_scan, *sidx = w0.sidx, *sn = w0.sn, *ssb = w0.ssb, *scan_tmp = w0.scan_tmp;
   for (int64_t r0 = 0; r0 < R; r0 += (int64_t)chunk, ++n_chunks) {
     const uint32_t nr = (uint32_t)std::min<int64_t>((int64_t)chunk, R - r0);
-    const bool second = pipe && (n_chunks & 1);
-    const hipStream_t cs = second ? ctx->lane.stream : st;
-    ChunkCounts* const cc = second ? ctx->lane.counts : ctx->counts;
-    Work& w = second ? w1 : w0;
+    const int li = (int)(n_chunks % n_lanes);
+    const hipStream_t cs = li ? ctx->lanes[li - 1].stream : st;
+    ChunkCounts* const cc = li ? ctx->lanes[li - 1].counts : ctx->counts;
+    Work& w = ws[li];
     wl = &w;
     EvSet* ev = nullptr;
     if (ctx->timing) {
@@ -1148,9 +1157,9 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
       const uint64_t niv_plan = (uint64_t)niv_plain + (uint64_t)nr * (uint64_t)std::min(q->cap, p->s_max);
       SortPlan spp = make_sort_plan(niv_plan, L);
       PropWork pw;
-      rc = ensure_arena3_for(ctx, second, carve_prop(nullptr, nr, niv_plain, niv_plan, spp, pw));
+      rc = ensure_arena3_for(ctx, li, carve_prop(nullptr, nr, niv_plain, niv_plan, spp, pw));
       if (rc) return rc;
-      carve_prop((char*)(second ? ctx->lane.arena3 : ctx->arena3), nr, niv_plain, niv_plan, spp, pw);
+      carve_prop((char*)(li ? ctx->lanes[li - 1].arena3 : ctx->arena3), nr, niv_plain, niv_plan, spp, pw);
       HIP_TRY(launch_prop_fwd(q->dtype, q->packed_dev, plain, rays->o_dev, rays->d_dev, R, r0, tree->dev_leafbox,
                               p->s_max, niv_plain, true, pw.wts, pw.tot, cs));
       HIP_TRY(launch_prop_select(nr, plain, pw.wts, pw.tot, q->mass_thresh, q->cap, p->s_max, pw.runs, pw.nsel, pw.mask, nullptr,
@@ -1172,9 +1181,9 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
       const uint64_t niv_plan = (niv_plain + (uint64_t)nr * (uint64_t)p->s_max) / 2 + nr;
       SortPlan spp = make_sort_plan(niv_plan, L);
       PropWork pw;
-      rc = ensure_arena3_for(ctx, second, carve_prop(nullptr, nr, 1, niv_plan, spp, pw));
+      rc = ensure_arena3_for(ctx, li, carve_prop(nullptr, nr, 1, niv_plan, spp, pw));
       if (rc) return rc;
-      carve_prop((char*)(second ? ctx->lane.arena3 : ctx->arena3), nr, 1, niv_plan, spp, pw);
+      carve_prop((char*)(li ? ctx->lanes[li - 1].arena3 : ctx->arena3), nr, 1, niv_plan, spp, pw);
       HIP_TRY(launch_occ_select(nr, plain, rays->o_dev, rays->d_dev, R, r0, occ->dev_bits, occ->g, pw.runs, pw.nsel,
                                 pw.mask, cs));
       HIP_TRY(launch_scan_u32_pair(pw.runs, pw.pv_off, pw.nsel, pw.ps_off, nr, pw.scan_tmp, cs));
@@ -1225,10 +1234,11 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
     if (ev) ev->pending = true;
     HIP_TRY(launch_chunk_finish(cc, use.smp_off + nr, use.n_iv_dev, w.smp_off + nr, rounds ? 1 : 0, cs));
   }
-  if (pipe) {
-    HIP_TRY(hipEventRecord(ctx->lane.join, ctx->lane.stream));
-    HIP_TRY(hipStreamWaitEvent(st, ctx->lane.join, 0));
-    HIP_TRY(launch_counts_merge(ctx->counts, ctx->lane.counts, st));
+  for (int i = 1; i < n_lanes; ++i) {
+    auto& ln = ctx->lanes[i - 1];
+    HIP_TRY(hipEventRecord(ln.join, ln.stream));
+    HIP_TRY(hipStreamWaitEvent(st, ln.join, 0));
+    HIP_TRY(launch_counts_merge(ctx->counts, ln.counts, st));
   }
   ctx->last_stream = st;
   ctx->have_render = true;
