@@ -112,7 +112,7 @@ struct amnerf_ctx {
   void* arena = nullptr;
   size_t arena_bytes = 0;
   ChunkCounts* counts = nullptr;        // device
-  ChunkCounts* counts_host = nullptr;   // pinned
+  ChunkCounts* counts_host = nullptr;   // pinned, one per render lane (the first also for statistics)
   hipStream_t last_stream = nullptr;
   bool have_render = false;
   // last render, for stats and inspection
@@ -203,7 +203,7 @@ extern "C" int amnerf_ctx_create(int device, size_t workspace_cap, amnerf_ctx** 
     return rc;
   }
   hipError_t e = hipMalloc((void**)&c->counts, sizeof(ChunkCounts));
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->counts_host, sizeof(ChunkCounts), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->counts_host, sizeof(ChunkCounts) * kLanes, hipHostMallocDefault);
   if (e != hipSuccess) {
     if (c->counts) (void)hipFree(c->counts);
     delete c;
@@ -1123,17 +1123,27 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
   const uint64_t* sel_mask = nullptr;   // the last chunk's kept-slot mask, if it selected slots
   Work* wl = &w0;   // the last chunk's workspace
   uint32_t *mat = w0.mat, *mat_scan = w0.mat_scan, *sidx = w0.sidx, *sn = w0.sn, *ssb = w0.ssb, *scan_tmp = w0.scan_tmp;
-  for (int64_t r0 = 0; r0 < R; r0 += (int64_t)chunk, ++n_chunks) {
-    const uint32_t nr = (uint32_t)std::min<int64_t>((int64_t)chunk, R - r0);
-    const int li = (int)(n_chunks % n_lanes);
+  // A proposal or an occupancy grid sizes its buffers from the chunk's plain interval count,
+  // which the host reads back.  The chunk loop is therefore split in two phases, and with
+  // more than one lane chunk k's second phase is enqueued after chunk k + 1's first (which
+  // runs on another lane, in another workspace): while the host waits for chunk k's count,
+  // the next chunk's traversal is already queued.
+  const bool wait_count = p->proposal || occ;
+  struct Pending {
+    int64_t r0;
+    uint32_t nr;
+    int li;
+    EvSet* ev;
+  };
+  // phase 1: traversal, and the plain interval count on its way to the host (lane li's slot)
+  auto phase1 = [&](int64_t r0, uint32_t nr, int li, Pending* pd) -> int {
     const hipStream_t cs = li ? ctx->lanes[li - 1].stream : st;
     ChunkCounts* const cc = li ? ctx->lanes[li - 1].counts : ctx->counts;
     Work& w = ws[li];
-    wl = &w;
     EvSet* ev = nullptr;
     if (ctx->timing) {
-      rc = next_set(ctx, &ev);
-      if (rc) return rc;
+      int r = next_set(ctx, &ev);
+      if (r) return r;
     }
     auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev->ev[k], cs) : hipSuccess; };
     HIP_TRY(mark(0));
@@ -1142,17 +1152,31 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
     HIP_TRY(launch_trav_emit(tree->dev_nodes, ahs_tab, p->hcheck_footprint, (uint32_t)n_nodes, tree->depth, rays->o_dev, rays->d_dev, R, r0, nr, w.cnt_iv, w.cnt_smp, w.iv_off,
                              w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, cc, cs));
     HIP_TRY(mark(1));
+    if (wait_count)
+      HIP_TRY(hipMemcpyAsync(&ctx->counts_host[li].n_iv, w.iv_off + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, cs));
+    *pd = {r0, nr, li, ev};
+    return AMNERF_OK;
+  };
+  // phase 2: proposal or occupancy selection, sort, expansion, leaf MLPs, compositing
+  auto phase2 = [&](const Pending& pd) -> int {
+    const int64_t r0 = pd.r0;
+    const uint32_t nr = pd.nr;
+    const int li = pd.li;
+    EvSet* const ev = pd.ev;
+    const hipStream_t cs = li ? ctx->lanes[li - 1].stream : st;
+    ChunkCounts* const cc = li ? ctx->lanes[li - 1].counts : ctx->counts;
+    Work& w = ws[li];
+    wl = &w;
+    int rc = AMNERF_OK;
+    auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev->ev[k], cs) : hipSuccess; };
     const IvSet plain = {w.iv_off, w.smp_off, w.iv_t0, w.iv_dt, w.iv_key, w.iv_ray, w.iv_base, w.iv_off + nr};
     use = plain;
     SortPlan spu = sp;
     mat = w.mat; mat_scan = w.mat_scan; sidx = w.sidx; sn = w.sn; ssb = w.ssb; scan_tmp = w.scan_tmp;
     uint64_t niv_use_max = niv_max;
+    if (wait_count) HIP_TRY(hipStreamSynchronize(cs));   // the chunk's plain interval count has arrived
     if (p->proposal) {
-      // the proposal buffers are sized from the plain interval count: wait for it once
-      uint32_t niv_plain = 0;
-      HIP_TRY(hipMemcpyAsync(&ctx->counts_host->n_iv, w.iv_off + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, cs));
-      HIP_TRY(hipStreamSynchronize(cs));
-      niv_plain = ctx->counts_host->n_iv;
+      const uint32_t niv_plain = ctx->counts_host[li].n_iv;
       const amnerf_proposal* q = p->proposal;
       const uint64_t niv_plan = (uint64_t)niv_plain + (uint64_t)nr * (uint64_t)std::min(q->cap, p->s_max);
       SortPlan spp = make_sort_plan(niv_plan, L);
@@ -1175,9 +1199,7 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
       // empty-space skipping: the kept samples of each ray as runs of consecutive slots
       // (within an interval of n slots at most ceil(n/2) runs, so a ray has at most
       // (s_max + m) / 2 of them); buffers sized from the plain interval count
-      HIP_TRY(hipMemcpyAsync(&ctx->counts_host->n_iv, w.iv_off + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, cs));
-      HIP_TRY(hipStreamSynchronize(cs));
-      const uint64_t niv_plain = ctx->counts_host->n_iv;
+      const uint64_t niv_plain = ctx->counts_host[li].n_iv;
       const uint64_t niv_plan = (niv_plain + (uint64_t)nr * (uint64_t)p->s_max) / 2 + nr;
       SortPlan spp = make_sort_plan(niv_plan, L);
       PropWork pw;
@@ -1233,6 +1255,30 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
     HIP_TRY(mark(6));
     if (ev) ev->pending = true;
     HIP_TRY(launch_chunk_finish(cc, use.smp_off + nr, use.n_iv_dev, w.smp_off + nr, rounds ? 1 : 0, cs));
+    return rc;
+  };
+  Pending prev = {};
+  bool have_prev = false;
+  for (int64_t r0 = 0; r0 < R; r0 += (int64_t)chunk, ++n_chunks) {
+    const uint32_t nr = (uint32_t)std::min<int64_t>((int64_t)chunk, R - r0);
+    Pending cur;
+    rc = phase1(r0, nr, (int)(n_chunks % n_lanes), &cur);
+    if (rc) return rc;
+    if (n_lanes == 1) {   // one workspace: the next chunk's traversal must wait for this chunk
+      rc = phase2(cur);
+      if (rc) return rc;
+      continue;
+    }
+    if (have_prev) {
+      rc = phase2(prev);
+      if (rc) return rc;
+    }
+    prev = cur;
+    have_prev = true;
+  }
+  if (have_prev) {
+    rc = phase2(prev);
+    if (rc) return rc;
   }
   for (int i = 1; i < n_lanes; ++i) {
     auto& ln = ctx->lanes[i - 1];
