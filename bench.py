@@ -98,6 +98,7 @@ def large_scene(args, am, torch, np, synth, ctx):
     of the 30 cameras (the plain renderer judges it)."""
     cfg = synth.C3
     dev = "cuda:0"
+    am.amnerf_ctx_set_render_lanes(ctx.h, args.lanes)
     t0 = time.perf_counter()
     grid = synth.make_grid(cfg)
     tree = am.Tree(ctx, grid, cfg.grid_n, cfg.max_depth, cfg.max_leaves)
@@ -353,7 +354,7 @@ def large_scene(args, am, torch, np, synth, ctx):
     return {"workload": "1920x1080 frames, 256^3 guidance grid (2000 anisotropic blobs, 100:1 density skew), "
                         "%d-leaf KD tree (max depth 12), 4x64 leaf MLPs, <=192 samples/ray, ERT at T<1e-4; "
                         "%d held-out cameras rendered by one call (%d with the proposal)" % (L, n_cams, n_prop_cams),
-            "n_leaves": L, "rays_per_call": R, "cameras_per_call": n_cams,
+            "n_leaves": L, "rays_per_call": R, "cameras_per_call": n_cams, "render_lanes": args.lanes,
             "proposal_rays_per_call": R50, "proposal_cameras_per_call": n_prop_cams, "paths": res,
             "occupancy": {"cells": occ.g ** 3, "occupied": occ.n_occupied, "block": 2, "thresh": 0.01},
             "psnr_vs_plain_db": psnr_prop_vs_plain, "bucket_sizes": spread, "accuracy": acc,
@@ -375,6 +376,8 @@ def main():
     ap.add_argument("--train-batch", type=int, default=262144)
     ap.add_argument("--no-large", action="store_true", help="skip the 1920x1080 4096-leaf scene")
     ap.add_argument("--large-calls", type=int, default=3, help="timed 30-camera calls of the large scene")
+    ap.add_argument("--lanes", type=int, default=4,
+                    help="render lanes of the large scene's multi-chunk calls (chunks in flight at once)")
     ap.add_argument("--large-prop-steps", type=int, default=6000, help="proposal training steps, large scene")
     ap.add_argument("--large-paths", default=",".join(LARGE_PATHS),
                     help="comma-separated render paths of the large scene (each PSNR comparison needs its "

@@ -91,6 +91,15 @@ int amnerf_ctx_create(int device, size_t workspace_cap, amnerf_ctx** out);
 /* Synchronises the device, frees the workspace and the handle.  NULL is accepted. */
 int amnerf_ctx_destroy(amnerf_ctx* ctx);
 
+/* Render lanes of a render that runs in several chunks (see amnerf_render): the number of
+ * chunks in flight at once, 1 .. AMNERF_MAX_RENDER_LANES (the default).  Each lane beyond
+ * the first holds a chunk workspace of its own (about 16 GB when s_max is at most the leaf
+ * count: 2^28 intervals and 2^28 samples), so fewer lanes hold less device memory; results
+ * do not depend on it.
+ * AMNERF_EINVAL outside the range. */
+#define AMNERF_MAX_RENDER_LANES 4
+int amnerf_ctx_set_render_lanes(amnerf_ctx* ctx, int n_lanes);
+
 /* ---- tree (Section 3.4) -------------------------------------------------------------- */
 #define AMNERF_SPLIT_MEDIAN 0  /* density-median subdivision (the method) */
 #define AMNERF_SPLIT_MIDDLE 1  /* regular subdivision, for the ablation without it */
@@ -330,11 +339,14 @@ typedef struct {
  * Asynchronous on `stream`, except that with a proposal or an occupancy grid each pass
  * waits on the host for its plain interval count (to size the planned intervals).  Rays
  * are processed in chunks of at most 2^28 / s_max rays.
- * With several chunks (and weights_dev NULL), odd chunks run on a second stream owned by
- * the context, with a workspace of its own: that stream first waits for `stream`, and
- * `stream` waits for it before the call returns, so the call stays ordered on `stream`
- * and its outputs equal those of chunk-by-chunk calls.  Calls on one context must not
- * overlap (the workspaces are reused). */
+ * With several chunks (and weights_dev NULL), chunk k runs on lane k mod n, n the
+ * context's render lanes (amnerf_ctx_set_render_lanes, 4 by default) or the chunk count if
+ * smaller: lane 0 is `stream`, the others are streams owned by the context, each with a
+ * chunk workspace of its own.  Those streams first wait for `stream`, and `stream` waits
+ * for them before the call returns, so the call stays ordered on `stream` and its outputs
+ * equal those of chunk-by-chunk calls.  With a proposal or an occupancy grid the host waits
+ * for a chunk's count only after the next chunk's traversal is queued.  Calls on one
+ * context must not overlap (the workspaces are reused). */
 int amnerf_render(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_mlp* mlp,
                   const amnerf_rays* rays, const amnerf_render_params* params,
                   amnerf_render_out* out, void* stream);

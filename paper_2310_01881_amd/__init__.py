@@ -37,6 +37,7 @@ AMNERF_MAX_GRID = 512
 AMNERF_MAX_DEPTH = 16
 AMNERF_MAX_LEAVES = 4096
 AMNERF_MAX_SAMPLES = 255
+AMNERF_MAX_RENDER_LANES = 4
 
 # symbols declared in include/amnerf.h
 EXPORTS = [
@@ -44,7 +45,7 @@ EXPORTS = [
     "amnerf_build_tree", "amnerf_tree_info_get", "amnerf_tree_export", "amnerf_tree_destroy",
     "amnerf_build_occupancy", "amnerf_occupancy_info_get", "amnerf_occupancy_export", "amnerf_occupancy_destroy",
     "amnerf_mlp_param_count", "amnerf_mlp_packed_bytes", "amnerf_mlp_pack", "amnerf_render",
-    "amnerf_render_stats_get", "amnerf_render_inspect", "amnerf_ctx_set_timing",
+    "amnerf_render_stats_get", "amnerf_render_inspect", "amnerf_ctx_set_timing", "amnerf_ctx_set_render_lanes",
     "amnerf_timing_collect", "amnerf_timing_collect_backward", "amnerf_render_backward",
     "amnerf_build_tree_codes", "amnerf_build_tree_distilled", "amnerf_adam_step", "amnerf_train_step",
     "amnerf_prop_param_count", "amnerf_prop_packed_bytes", "amnerf_prop_pack", "amnerf_propose",
@@ -190,6 +191,7 @@ def _load():
     lib.amnerf_render_stats_get.argtypes = [P, C.POINTER(amnerf_render_stats)]
     lib.amnerf_render_inspect.argtypes = [P, C.POINTER(amnerf_inspect), P]
     lib.amnerf_ctx_set_timing.argtypes = [P, C.c_int]
+    lib.amnerf_ctx_set_render_lanes.argtypes = [P, C.c_int]
     lib.amnerf_timing_collect.argtypes = [P, P, C.POINTER(C.c_int64)]
     lib.amnerf_timing_collect_backward.argtypes = [P, P, C.POINTER(C.c_int64)]
     lib.amnerf_render_backward.argtypes = [P, P, C.POINTER(amnerf_mlp), C.POINTER(amnerf_rays), P, P, P, P, P]
@@ -415,6 +417,11 @@ def amnerf_render_inspect(ctx, stream=None, **bufs):
 
 def amnerf_ctx_set_timing(ctx, enable: bool):
     _check(_lib.amnerf_ctx_set_timing(ctx, 1 if enable else 0))
+
+
+def amnerf_ctx_set_render_lanes(ctx, n_lanes: int):
+    """Chunks in flight at once in a multi-chunk render (1 .. AMNERF_MAX_RENDER_LANES)."""
+    _check(_lib.amnerf_ctx_set_render_lanes(ctx, int(n_lanes)))
 
 
 def amnerf_timing_collect(ctx):

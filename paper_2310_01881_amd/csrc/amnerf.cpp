@@ -41,7 +41,7 @@ int fail(int code, const char* fmt, ...) {
 constexpr uint64_t kChunkSamples = 1ull << 28;   // worst-case samples of one render pass
 // lanes of a render that runs in several chunks: chunk k runs on lane k mod kLanes, lane 0
 // being the caller's stream
-constexpr int kLanes = 4;
+constexpr int kLanes = AMNERF_MAX_RENDER_LANES;
 
 }  // namespace
 
@@ -113,6 +113,7 @@ struct amnerf_ctx {
   size_t arena_bytes = 0;
   ChunkCounts* counts = nullptr;        // device
   ChunkCounts* counts_host = nullptr;   // pinned, one per render lane (the first also for statistics)
+  int render_lanes = kLanes;          // lanes a multi-chunk render spreads its chunks over
   hipStream_t last_stream = nullptr;
   bool have_render = false;
   // last render, for stats and inspection
@@ -184,7 +185,7 @@ struct amnerf_occ {
 // misc
 // ---------------------------------------------------------------------------------------
 extern "C" const char* amnerf_last_error(void) { return g_err.c_str(); }
-extern "C" int amnerf_version(void) { return 200; }
+extern "C" int amnerf_version(void) { return 201; }
 
 extern "C" int amnerf_ctx_create(int device, size_t workspace_cap, amnerf_ctx** out) {
   if (!out) return fail(AMNERF_EINVAL, "amnerf_ctx_create: out is NULL");
@@ -253,6 +254,14 @@ static int drain_set(amnerf_ctx* ctx, EvSet& s) {
   }
   ctx->timed_passes += 1;
   s.pending = false;
+  return AMNERF_OK;
+}
+
+extern "C" int amnerf_ctx_set_render_lanes(amnerf_ctx* ctx, int n_lanes) {
+  if (!ctx) return fail(AMNERF_EINVAL, "amnerf_ctx_set_render_lanes: ctx is NULL");
+  if (n_lanes < 1 || n_lanes > kLanes)
+    return fail(AMNERF_EINVAL, "amnerf_ctx_set_render_lanes: %d lanes, the range is 1 .. %d", n_lanes, kLanes);
+  ctx->render_lanes = n_lanes;
   return AMNERF_OK;
 }
 
@@ -1105,7 +1114,7 @@ static int render_impl(amnerf_ctx* ctx, const amnerf_tree* tree, const amnerf_ml
   // another's matrix-core stage.  The lanes wait for the caller's stream on entry and the
   // caller's stream waits for them on exit, so the call stays asynchronous on `stream`.
   const bool pipe = (uint64_t)R > chunk && !out->weights_dev && !static_ws;
-  const int n_lanes = pipe ? (int)std::min<uint64_t>((uint64_t)kLanes, ((uint64_t)R + chunk - 1) / chunk) : 1;
+  const int n_lanes = pipe ? (int)std::min<uint64_t>((uint64_t)ctx->render_lanes, ((uint64_t)R + chunk - 1) / chunk) : 1;
   for (int i = 1; i < n_lanes; ++i) {
     rc = lane_prepare(ctx, i, need);
     if (rc) return rc;

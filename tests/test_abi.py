@@ -24,7 +24,7 @@ def test_header_declarations_are_exported():
 
 
 def test_calls_that_need_no_device():
-    assert am.amnerf_version() == 200
+    assert am.amnerf_version() == 201
     assert am.amnerf_mlp_param_count(4, 64) == 14724
     assert am.amnerf_mlp_param_count(2, 32) == 2180
     assert am.amnerf_mlp_param_count(0, 64) == -1
