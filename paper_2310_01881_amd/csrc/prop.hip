@@ -15,6 +15,7 @@
 #include "mlp_layout.hpp"
 
 #include <algorithm>
+#include <atomic>
 
 namespace amn {
 namespace {
@@ -1139,15 +1140,17 @@ __global__ __launch_bounds__(kThreads) void k_prop_reduce(const float* __restric
   }
 }
 
-int g_ncu = 0;
+std::atomic<int> g_ncu{0};   // compute units of the device (queried once; host threads may race to it)
 hipError_t ncu(int* out) {
-  if (g_ncu == 0) {
+  int n = g_ncu.load();
+  if (n == 0) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&g_ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
+    g_ncu.store(n);
   }
-  *out = g_ncu;
+  *out = n;
   return hipSuccess;
 }
 
