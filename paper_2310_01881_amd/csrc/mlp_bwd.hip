@@ -29,15 +29,24 @@ constexpr int kNCB = 1;                          // 16-sample column blocks per 
 constexpr int kTileRows = kMlpTileRows;          // 256-row tiles of the forward pass, each
 constexpr int kSubRows = kWavesB * 16 * kNCB;    // processed as one sub-tile of 16 rows per wave
 constexpr int kSubPerTile = kTileRows / kSubRows;
-constexpr int kItemsB = (16 + kWavesB - 1) / kWavesB;   // dW items per wave and layer, at most
 static_assert(kTileRows % kSubRows == 0, "sub-tiles must divide a tile");
 constexpr int kRowBytes = kSubRows * 2 + 16;     // staged feature row (bf16) + padding
+static_assert(kWavesB == 16, "the weight-gradient ownership below assumes 16 waves");
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Weight-gradient ownership, fixed so that every sum is taken in one order.  Below the
+// output layer, dW_l is cut into 32x32 blocks (rows: outputs; columns: staged inputs), one
+// wave each, accumulated with 32x32x16 MFMAs over the sub-tile's samples: the layers take
+// waves in the order 1, 2, .., NH - 1, 0 (slot li), (H/32)^2 waves apiece.  db_l's 16-row
+// blocks go to 16x16x32 MFMAs against a ones operand on waves 8 + li H/16 + j (mod 16),
+// which never hold a dW block of the same layer, and each hold one layer's.  The output
+// layer (its outputs padded to 16 rows) keeps 16x16 blocks: column block ci on wave ci,
+// its db on wave 0.
+__device__ __forceinline__ constexpr int bwd_slot(int NH, int l) { return l >= 1 ? l - 1 : NH - 1; }
 
 __device__ __forceinline__ void stage(uint8_t* base, int row, int col, __bf16 v) {
   *reinterpret_cast<__bf16*>(base + row * kRowBytes + col * 2) = v;
-}
-__device__ __forceinline__ bf16x8 ld_frag(const uint8_t* base, int row, int col) {
-  return *reinterpret_cast<const bf16x8*>(base + row * kRowBytes + col * 2);
 }
 __device__ __forceinline__ bool pos_bf16(__bf16 v) {
   return __builtin_bit_cast(short, v) > 0;
@@ -65,6 +74,24 @@ __global__ __launch_bounds__(kThreadsB) void k_mlp_bwd(
   bf16x8 ones;
 #pragma unroll
   for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.f;
+  // this wave's blocks (see above) and the byte offsets of its operand fragments in the
+  // staged rows, which are the same for every layer
+  const int h32 = lane >> 5, c32 = lane & 31;
+  int big_l = -1, big_ri = 0, big_cj = 0, bias_l = -1, bias_j = 0;
+#pragma unroll
+  for (int l = 0; l < NH; ++l) {
+    const int li = bwd_slot(NH, l);
+    const int ncol = l == 0 ? 1 : H / 32;
+    const int bi = wave - li * (H / 32) * (H / 32);
+    if (bi >= 0 && bi < (H / 32) * ncol) { big_l = l; big_ri = bi / ncol; big_cj = bi % ncol; }
+    const int bj = (wave - 8 - li * (H / 16)) & 15;
+    if (bj < H / 16) { bias_l = l; bias_j = bj; }
+  }
+  const uint32_t big_a = (uint32_t)(32 * big_ri + c32) * kRowBytes + 16u * h32;   // + 32 bytes per K step
+  const uint32_t big_b = (uint32_t)(32 * big_cj + c32) * kRowBytes + 16u * h32;
+  const uint32_t bias_a = (uint32_t)(16 * bias_j + m) * kRowBytes + 16u * g;      // + 64 bytes per K step
+  const uint32_t out_b = (uint32_t)(16 * (wave & (RB - 1)) + m) * kRowBytes + 16u * g;
+  const uint32_t out_a = (uint32_t)m * kRowBytes + 16u * g;
 
   const uint32_t n_seg = seg_off[n_leaves];
   int cur = -1;
@@ -86,14 +113,12 @@ __global__ __launch_bounds__(kThreadsB) void k_mlp_bwd(
       __syncthreads();
       cur = (int)b;
     }
-    f32x4 accW[NH + 1][kItemsB];
-    f32x4 accB[NH + 1];
+    f32x16 accW32;             // this wave's 32x32 block of some dW_l (l < NH)
 #pragma unroll
-    for (int l = 0; l <= NH; ++l) {
-      accB[l] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int q = 0; q < kItemsB; ++q) accW[l][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int i = 0; i < 16; ++i) accW32[i] = 0.f;
+    f32x4 accB16 = {0.f, 0.f, 0.f, 0.f};   // its 16-row block of some db_l (l < NH)
+    f32x4 accWo = {0.f, 0.f, 0.f, 0.f};    // its 16x16 block of the output layer's dW
+    f32x4 accBo = {0.f, 0.f, 0.f, 0.f};    // the output layer's db (wave 0)
 
     for (uint32_t sub = kSubPerTile * t_first; sub < kSubPerTile * t_last; ++sub) {
       const uint32_t row0 = bucket_off[b] + (sub - kSubPerTile * tile_off[b]) * kSubRows + wave * (16 * kNCB);
@@ -182,9 +207,6 @@ __global__ __launch_bounds__(kThreadsB) void k_mlp_bwd(
 #pragma unroll
       for (int l = NH; l >= 0; --l) {
         const int rbo = l == NH ? 1 : RB;          // row blocks of this layer's outputs
-        const int cbi = l == 0 ? 2 : RB;           // 16-column blocks of its inputs
-        const int n_items = rbo * cbi;
-        const int per = (n_items + kWavesB - 1) / kWavesB;
         // stage dZ_l and the layer input, feature-major
         __syncthreads();
 #pragma unroll
@@ -208,17 +230,33 @@ __global__ __launch_bounds__(kThreadsB) void k_mlp_bwd(
         }
         __syncthreads();
         // dW_l += dZ_l H^T, db_l += dZ_l 1 over the sub-tile's samples
+        if (l == NH) {
+          if (wave < RB) {
 #pragma unroll
-        for (int q = 0; q < kItemsB; ++q) {
-          const int item = wave * per + q;
-          if (q >= per || item >= n_items) break;
-          const int rb = item / cbi, ci = item % cbi;
+            for (int kb = 0; kb < kSubRows / 32; ++kb) {
+              const bf16x8 A = *reinterpret_cast<const bf16x8*>(s_dz + out_a + 64 * kb);
+              const bf16x8 Bm = *reinterpret_cast<const bf16x8*>(s_h + out_b + 64 * kb);
+              accWo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bm, accWo, 0, 0, 0);
+              if (wave == 0) accBo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, ones, accBo, 0, 0, 0);
+            }
+          }
+        } else {
+          // A: lane (h, c) holds dZ row 32 ri + c at samples 16 ks + 8 h ..; B: the input
+          // feature 32 cj + c at the same samples
+          if (big_l == l) {
+#pragma unroll 4
+            for (int ks = 0; ks < kSubRows / 16; ++ks) {
+              const bf16x8 A = *reinterpret_cast<const bf16x8*>(s_dz + big_a + 32 * ks);
+              const bf16x8 Bm = *reinterpret_cast<const bf16x8*>(s_h + big_b + 32 * ks);
+              accW32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bm, accW32, 0, 0, 0);
+            }
+          }
+          if (bias_l == l) {
 #pragma unroll
-          for (int kb = 0; kb < kSubRows / 32; ++kb) {
-            const bf16x8 A = ld_frag(s_dz, 16 * rb + m, kb * 32 + 8 * g);
-            const bf16x8 Bm = ld_frag(s_h, 16 * ci + m, kb * 32 + 8 * g);
-            accW[l][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bm, accW[l][q], 0, 0, 0);
-            if (ci == 0) accB[l] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, ones, accB[l], 0, 0, 0);
+            for (int kb = 0; kb < kSubRows / 32; ++kb) {
+              const bf16x8 A = *reinterpret_cast<const bf16x8*>(s_dz + bias_a + 64 * kb);
+              accB16 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, ones, accB16, 0, 0, 0);
+            }
           }
         }
         if (l == 0) break;
@@ -261,28 +299,39 @@ __global__ __launch_bounds__(kThreadsB) void k_mlp_bwd(
     }
 
     // ---- this segment's partial gradient, master layout ----
+    // (every weight and bias of the leaf is written by exactly one wave)
     float* dst = part + (uint64_t)seg * P;
-#pragma unroll
-    for (int l = 0; l <= NH; ++l) {
-      const int rbo = l == NH ? 1 : RB;
-      const int cbi = l == 0 ? 2 : RB;
-      const int n_items = rbo * cbi;
-      const int per = (n_items + kWavesB - 1) / kWavesB;
+    {
       int din, dout, off_w, off_b;
-      master_offsets(NH, H, l, din, dout, off_w, off_b);
-#pragma unroll
-      for (int q = 0; q < kItemsB; ++q) {
-        const int item = wave * per + q;
-        if (q >= per || item >= n_items) break;
-        const int rb = item / cbi, ci = item % cbi;
-        const int c = 16 * ci + m;
-        const int col = l == 0 ? first_layer_col_bf16(c / 8, c % 8) : c;
+      master_offsets(NH, H, NH, din, dout, off_w, off_b);
+      if (wave < RB) {
+        const int c = 16 * wave + m;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int out = 16 * rb + 4 * g + i;
-          if (out < dout && col >= 0) dst[off_w + out * din + col] = accW[l][q][i];
-          if (ci == 0 && m == 0 && out < dout) dst[off_b + out] = accB[l][i];
+          const int out = 4 * g + i;
+          if (out < dout) dst[off_w + out * din + c] = accWo[i];
+          if (wave == 0 && m == 0 && out < dout) dst[off_b + out] = accBo[i];
         }
+      }
+    }
+    if (big_l >= 0) {
+      int din, dout, off_w, off_b;
+      master_offsets(NH, H, big_l, din, dout, off_w, off_b);
+      const int cc = 32 * big_cj + c32;
+      const int col = big_l == 0 ? first_layer_col_bf16(cc / 8, cc % 8) : cc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int out = 32 * big_ri + 8 * (r / 4) + 4 * h32 + (r % 4);   // accumulator row of register r
+        if (out < dout && col >= 0) dst[off_w + out * din + col] = accW32[r];
+      }
+    }
+    if (bias_l >= 0 && m == 0) {
+      int din, dout, off_w, off_b;
+      master_offsets(NH, H, bias_l, din, dout, off_w, off_b);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int out = 16 * bias_j + 4 * g + i;
+        if (out < dout) dst[off_b + out] = accB16[i];
       }
     }
   }
