@@ -3,6 +3,8 @@
 #include "internal.hpp"
 #include "devcommon.hpp"
 
+#include <algorithm>
+
 #include "../../include/amnerf.h"
 
 namespace amn {
@@ -188,8 +190,19 @@ __global__ __launch_bounds__(kThreads) void k_grad_reduce(const float* __restric
   for (uint64_t id = (uint64_t)blockIdx.x * kThreads + threadIdx.x; id < total;
        id += (uint64_t)gridDim.x * kThreads) {
     const uint32_t b = (uint32_t)(id / P), p = (uint32_t)(id % P);
+    const uint32_t s1 = seg_off[b + 1];
+    const float* q = part + p;
     float s = 0.f;
-    for (uint32_t seg = seg_off[b]; seg < seg_off[b + 1]; ++seg) s += part[(uint64_t)seg * P + p];
+    uint32_t seg = seg_off[b];
+    // eight loads in flight, then their sum in segment order (the order of one at a time)
+    for (; seg + 8 <= s1; seg += 8) {
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = q[(uint64_t)(seg + k) * P];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; seg < s1; ++seg) s += q[(uint64_t)seg * P];
     grad[id] = s;
   }
 }
@@ -264,7 +277,10 @@ hipError_t launch_seg_offsets(const uint32_t* tile_off, uint32_t n_leaves, uint3
 
 hipError_t launch_grad_reduce(const float* part, const uint32_t* seg_off, uint32_t n_leaves, uint32_t P,
                               float* grad, hipStream_t st) {
-  hipLaunchKernelGGL(k_grad_reduce, dim3(2048), dim3(kThreads), 0, st, part, seg_off, n_leaves, P, grad);
+  // one thread per parameter (its loads are what it waits for)
+  const uint64_t total = (uint64_t)n_leaves * P;
+  const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((total + kThreads - 1) / kThreads, 1u << 20));
+  hipLaunchKernelGGL(k_grad_reduce, dim3((uint32_t)blocks), dim3(kThreads), 0, st, part, seg_off, n_leaves, P, grad);
   return hipGetLastError();
 }
 
