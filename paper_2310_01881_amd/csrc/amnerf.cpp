@@ -1433,7 +1433,7 @@ struct BwdWork {
 size_t carve_bwd(char* base, uint64_t ns, uint64_t L, uint64_t nseg, uint64_t P, uint64_t R, BwdWork& w) {
   Carve c{base};
   w.gpre = c.take<float>(4 * ns);
-  w.seg_off = c.take<uint32_t>(L + 1);
+  w.seg_off = c.take<uint32_t>(L + 2);   // segment offsets, total, and the backward's queue
   w.part = c.take<float>(nseg * P);
   w.rgb = c.take<float>(3 * R);
   w.g_rgb = c.take<float>(3 * R);

@@ -212,9 +212,11 @@ bool mlp_bwd_supported(int n_hidden, int hidden);
 hipError_t launch_comp_bwd(uint32_t nr, const IvSet& iv, const float* smp_out, int64_t r0, int jitter,
                            uint64_t seed, const uint32_t* ray_used, const float* g_rgb, const float* g_depth,
                            const float* g_opac, float* gpre, hipStream_t st);
+// seg_off: n_leaves + 2 words; the last is the bfloat16 backward's segment queue, which
+// launch_seg_offsets resets to 0 and launch_mlp_bwd advances.
 hipError_t launch_seg_offsets(const uint32_t* tile_off, uint32_t n_leaves, uint32_t* seg_off, hipStream_t st);
 hipError_t launch_mlp_bwd(const MlpGeom& g, const void* packed, uint32_t n_leaves, const uint32_t* bucket_off,
-                          const uint32_t* tile_off, const uint32_t* seg_off, const uint32_t* srec_ray,
+                          const uint32_t* tile_off, uint32_t* seg_off, const uint32_t* srec_ray,
                           const float* srec_t, const uint32_t* perm, const float* o, const float* d,
                           int64_t ray_stride, int64_t r0, const float* gpre, float* part, hipStream_t st);
 hipError_t launch_grad_reduce(const float* part, const uint32_t* seg_off, uint32_t n_leaves, uint32_t P,

@@ -59,7 +59,8 @@ __global__ __launch_bounds__(kThreadsB) void k_mlp_bwd(
     const uint32_t* __restrict__ tile_off, const uint32_t* __restrict__ seg_off,
     const uint32_t* __restrict__ srec_ray, const float* __restrict__ srec_t,
     const uint32_t* __restrict__ perm, const float* __restrict__ o, const float* __restrict__ d,
-    int64_t stride, int64_t r0, const float* __restrict__ gpre, float* __restrict__ part, int P) {
+    int64_t stride, int64_t r0, const float* __restrict__ gpre, float* __restrict__ part, int P,
+    uint32_t* __restrict__ seg_queue) {
   extern __shared__ __align__(16) uint8_t lds[];
   constexpr int RB = H / 16;
   constexpr int KUh = H / 32;
@@ -67,6 +68,7 @@ __global__ __launch_bounds__(kThreadsB) void k_mlp_bwd(
   uint8_t* w_bwd = lds + L.bytes;
   uint8_t* s_dz = w_bwd + L.bwd_bytes;
   uint8_t* s_h = s_dz + H * kRowBytes;
+  uint32_t& s_seg = *reinterpret_cast<uint32_t*>(s_h + H * kRowBytes);   // the segment taken
   const float* bias = reinterpret_cast<const float*>(w_fwd);
   const uint8_t* units = w_fwd + L.bias_bytes;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -95,7 +97,12 @@ __global__ __launch_bounds__(kThreadsB) void k_mlp_bwd(
 
   const uint32_t n_seg = seg_off[n_leaves];
   int cur = -1;
-  for (uint32_t seg = blockIdx.x; seg < n_seg; seg += gridDim.x) {
+  // segments are taken from a queue (segments differ in length, so a fixed stride over them
+  // leaves blocks unevenly loaded); each writes its own partial slot, so the order is free
+  if (tid == 0) s_seg = atomicAdd(seg_queue, 1u);
+  __syncthreads();
+  uint32_t seg = __builtin_amdgcn_readfirstlane(s_seg);
+  while (seg < n_seg) {
     uint32_t lo = 0, hi = n_leaves;
     while (hi - lo > 1) {
       uint32_t mid = (lo + hi) >> 1;
@@ -334,6 +341,10 @@ __global__ __launch_bounds__(kThreadsB) void k_mlp_bwd(
         if (out < dout) dst[off_b + out] = accB16[i];
       }
     }
+    __syncthreads();   // every wave has read s_seg
+    if (tid == 0) s_seg = atomicAdd(seg_queue, 1u);
+    __syncthreads();
+    seg = __builtin_amdgcn_readfirstlane(s_seg);
   }
 }
 
@@ -565,11 +576,11 @@ hipError_t launch_bwd_f32_typed(const Layout& L, const void* packed, uint32_t n_
 template <int H, int NH>
 hipError_t launch_bwd_typed(const Layout& L, const void* packed, uint32_t n_leaves,
                             const uint32_t* bucket_off, const uint32_t* tile_off,
-                            const uint32_t* seg_off, const uint32_t* srec_ray, const float* srec_t,
+                            uint32_t* seg_off, const uint32_t* srec_ray, const float* srec_t,
                             const uint32_t* perm, const float* o, const float* d, int64_t stride,
                             int64_t r0, const float* gpre, float* part, hipStream_t st) {
   auto kern = k_mlp_bwd<H, NH>;
-  const uint32_t lds = L.bytes + L.bwd_bytes + 2u * H * kRowBytes;
+  const uint32_t lds = L.bytes + L.bwd_bytes + 2u * H * kRowBytes + 16u;   // + the queue word
   int grid = 0;
   hipError_t e = persistent_grid((const void*)kern, kThreadsB, lds, &grid);
   if (e != hipSuccess) return e;
@@ -577,7 +588,7 @@ hipError_t launch_bwd_typed(const Layout& L, const void* packed, uint32_t n_leav
   const uint8_t* pb = pf + (uint64_t)n_leaves * L.bytes;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreadsB), lds, st, L, pf, pb, n_leaves, bucket_off, tile_off,
                      seg_off, srec_ray, srec_t, perm, o, d, stride, r0, gpre, part,
-                     master_param_count(NH, H));
+                     master_param_count(NH, H), seg_off + n_leaves + 1);
   return hipGetLastError();
 }
 
@@ -588,7 +599,7 @@ bool mlp_bwd_supported(int n_hidden, int hidden) {
 }
 
 hipError_t launch_mlp_bwd(const MlpGeom& g, const void* packed, uint32_t n_leaves,
-                          const uint32_t* bucket_off, const uint32_t* tile_off, const uint32_t* seg_off,
+                          const uint32_t* bucket_off, const uint32_t* tile_off, uint32_t* seg_off,
                           const uint32_t* srec_ray, const float* srec_t, const uint32_t* perm,
                           const float* o, const float* d, int64_t ray_stride, int64_t r0,
                           const float* gpre, float* part, hipStream_t st) {

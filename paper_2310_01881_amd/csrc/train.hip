@@ -178,7 +178,10 @@ __global__ __launch_bounds__(1024) void k_seg_offsets(const uint32_t* __restrict
     carry += tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0) seg_off[n_leaves] = carry;
+  if (threadIdx.x == 0) {
+    seg_off[n_leaves] = carry;
+    seg_off[n_leaves + 1] = 0u;   // the backward's segment queue
+  }
 }
 
 // grad[b][p] = sum over the segments of leaf b, in order, of part[seg][p].
